@@ -1,0 +1,381 @@
+"""Pins for the FP64 oracle: brute force, closed forms, identities, invariants.
+
+Every check here compares the oracle with something other than itself
+(plain loops, numpy's kron/matmul/lstsq, closed forms, exact identities or
+monotonicity), so a dropped term, a wrong sign or index, or a transposed
+operand in the oracle fails at least one of them.
+"""
+
+import math
+
+import numpy as np
+import pytest
+
+import oracle as O
+from paper_1806_07985_amd import inputs
+
+TINY_SHAPES = [(3, 4, 5), (2, 3, 4, 5), (2, 2, 3, 2, 3)]
+
+
+def _rand_factors(dims, R, seed):
+    rng = np.random.default_rng(seed)
+    return [rng.random((d, R)) for d in dims]
+
+
+def _rand_tensor(dims, seed, signed=False):
+    rng = np.random.default_rng(seed)
+    X = rng.random(dims)
+    return X - 0.5 if signed else X
+
+
+# --- Khatri-Rao order -------------------------------------------------------
+
+def test_khatri_rao_is_columnwise_kron():
+    rng = np.random.default_rng(0)
+    A, B = rng.random((3, 4)), rng.random((5, 4))
+    K = O.khatri_rao(A, B)
+    for c in range(4):
+        np.testing.assert_allclose(K[:, c], np.kron(A[:, c], B[:, c]), rtol=0, atol=1e-15)
+
+
+# --- MTTKRP -----------------------------------------------------------------
+
+@pytest.mark.parametrize("dims", TINY_SHAPES)
+@pytest.mark.parametrize("signed", [False, True])
+def test_mttkrp_direct_matches_bruteforce(dims, signed):
+    X = _rand_tensor(dims, 1, signed)
+    H = _rand_factors(dims, 3, 2)
+    for n in range(len(dims)):
+        Mb = O.mttkrp_bruteforce(X, H, n)
+        Md = O.mttkrp_direct(X, H, n)
+        assert np.max(np.abs(Mb - Md)) <= 1e-13 * max(1.0, np.max(np.abs(Mb)))
+
+
+def test_mttkrp_direct_chunked_path_matches_bruteforce():
+    dims = (3, 4, 5, 2)
+    X = _rand_tensor(dims, 3)
+    H = _rand_factors(dims, 2, 4)
+    for n in range(4):
+        Mb = O.mttkrp_bruteforce(X, H, n)
+        Mc = O.mttkrp_direct(X, H, n, max_krp_rows=1)
+        np.testing.assert_allclose(Mc, Mb, rtol=1e-13, atol=1e-13)
+
+
+def test_mttkrp_two_way_is_matmul():
+    rng = np.random.default_rng(5)
+    X = rng.random((7, 9))
+    H = [rng.random((7, 4)), rng.random((9, 4))]
+    np.testing.assert_allclose(O.mttkrp_direct(X, H, 0), X @ H[1], rtol=1e-14)
+    np.testing.assert_allclose(O.mttkrp_direct(X, H, 1), X.T @ H[0], rtol=1e-14)
+
+
+def test_mttkrp_rank_one_closed_form():
+    rng = np.random.default_rng(6)
+    a, b, c = rng.random(4), rng.random(5), rng.random(6)
+    X = np.multiply.outer(np.multiply.outer(a, b), c)
+    H = [rng.random((4, 3)), rng.random((5, 3)), rng.random((6, 3))]
+    expect1 = np.outer(a, (b @ H[1]) * (c @ H[2]))
+    expect3 = np.outer(c, (a @ H[0]) * (b @ H[1]))
+    np.testing.assert_allclose(O.mttkrp_direct(X, H, 0), expect1, rtol=1e-13)
+    np.testing.assert_allclose(O.mttkrp_direct(X, H, 2), expect3, rtol=1e-13)
+
+
+# --- dimension tree ----------------------------------------------------------
+
+@pytest.mark.parametrize("dims", [(3, 4, 5), (4, 3, 5, 2), (2, 3, 2, 3, 2), (5, 2)])
+def test_tree_equals_direct_every_mode_every_split(dims):
+    N = len(dims)
+    X = _rand_tensor(dims, 7)
+    for s in range(1, N):
+        H = _rand_factors(dims, 3, 8)
+        tree = O.DimTree(X, s)
+        rng = np.random.default_rng(9)
+        for sweep in range(2):
+            for n in range(N):
+                Mt = tree.mttkrp(H, n)
+                Md = O.mttkrp_direct(X, H, n)
+                assert np.linalg.norm(Mt - Md) <= 1e-12 * np.linalg.norm(Md)
+                H[n] = rng.random(H[n].shape)  # a new factor, as an update would make
+
+
+def test_tree_equals_direct_along_bcd():
+    dims = (6, 5, 4, 3)
+    X, _ = inputs.planted(dims, 3, 0.01, seed=11)
+    H0 = inputs.init_factors(dims, 3, seed=12)
+    for s in (1, 2, 3):
+        a = O.nncp(X, H0, 4, mttkrp="direct")
+        b = O.nncp(X, H0, 4, mttkrp="tree", split=s)
+        for Ha, Hb in zip(a["H"], b["H"]):
+            assert np.linalg.norm(Ha - Hb) <= 1e-11 * np.linalg.norm(Ha)
+        np.testing.assert_allclose(a["fit"], b["fit"], rtol=0, atol=1e-12)
+
+
+def test_subtree_schedule_shape():
+    sch = O.subtree_schedule(5, 2)
+    assert sch[0] == ("pm_left", 0, 1) and sch[1] == ("trail", 0, 1)
+    assert sch[2] == ("lead", 1, 1) and sch[3] == ("leaf", 1, 1)
+    assert sch[4] == ("pm_right", 2, 4) and sch[5] == ("trail", 2, 4)
+    assert sch[-2] == ("lead", 4, 4) and sch[-1] == ("leaf", 4, 4)
+
+
+def test_choose_split():
+    assert O.choose_split((128, 128, 128, 128)) == 2
+    assert O.choose_split((1024, 1344, 33, 9)) == 1
+    assert O.choose_split((60, 50, 40)) == 1
+    assert O.choose_split((7, 9)) == 1
+
+
+# --- Gram / Hadamard ---------------------------------------------------------
+
+def test_gram_hadamard_is_krp_gram():
+    dims = (4, 5, 3, 2)
+    H = _rand_factors(dims, 3, 13)
+    G = [O.gram(h) for h in H]
+    for n in range(4):
+        K = O.krp_for_mode(H, n)
+        np.testing.assert_allclose(O.hadamard_others(G, n), K.T @ K, rtol=1e-13)
+
+
+# --- error / fit identities ----------------------------------------------------
+
+def test_fit_identity_matches_explicit_residual():
+    dims = (5, 4, 3)
+    X = _rand_tensor(dims, 14)
+    H = _rand_factors(dims, 2, 15)
+    lam = np.array([0.7, 1.3])
+    model = O.model_tensor_cp(lam, H)
+    alpha = float(np.sum(X * X))
+    explicit = float(np.sum((X - model) ** 2))
+    for n in range(3):
+        W = H[n] * lam[None, :]
+        M = O.mttkrp_direct(X, H, n)
+        beta = float(np.sum(M * W))
+        assert abs(beta - float(np.sum(X * model))) <= 1e-12 * alpha
+        G = [O.gram(h) for h in H]
+        Ghat = O.gram(W)
+        gamma = float(np.sum(O.hadamard_others(G, n) * Ghat))
+        assert abs(gamma - float(np.sum(model * model))) <= 1e-12 * alpha
+        assert abs((alpha - 2 * beta + gamma) - explicit) <= 1e-12 * alpha
+    f, e = O.fit_from_terms(alpha, float(np.sum(X * model)), float(np.sum(model * model)))
+    assert abs(e - math.sqrt(explicit / alpha)) < 1e-12
+    assert abs(O.relerr_explicit(X, lam, H) - e) < 1e-12
+
+
+def test_fit_clamps_negative_numerator():
+    f, e = O.fit_from_terms(1.0, 1.0, 1.0 - 1e-17)
+    assert e == 0.0 and f == 1.0
+
+
+def test_driver_fit_equals_explicit_error():
+    dims = (6, 5, 4)
+    X, _ = inputs.planted(dims, 3, 0.05, seed=16)
+    H0 = inputs.init_factors(dims, 3, seed=17)
+    for upd in ("hals", "mu"):
+        out = O.nncp(X, H0, 3, update=upd)
+        assert abs(out["eps"][-1] - O.relerr_explicit(X, out["lam"], out["H"])) < 1e-10
+
+
+# --- NLS updates -----------------------------------------------------------------
+
+def _subproblem(seed, I=7, R=4):
+    rng = np.random.default_rng(seed)
+    K = rng.random((30, R))
+    S = K.T @ K
+    A = rng.random((I, 30))
+    M = A @ K
+    return S, M
+
+
+def test_hals_rank_one_closed_form():
+    S = np.array([[2.5]])
+    M = np.array([[1.0], [-3.0], [5.0]])
+    W0 = np.array([[9.0], [9.0], [9.0]])
+    np.testing.assert_allclose(O.hals_update(W0, S, M), np.maximum(M / 2.5, 0), rtol=1e-15)
+
+
+def test_hals_sweep_is_exact_coordinate_minimiser_and_monotone():
+    S, M = _subproblem(18)
+    W = np.random.default_rng(19).random(M.shape)
+    prev = O.nls_objective(W, S, M)
+    for _ in range(20):
+        W = O.hals_update(W, S, M)
+        cur = O.nls_objective(W, S, M)
+        assert cur <= prev + 1e-12 * abs(prev)
+        prev = cur
+    # each column is a 1-D minimiser: perturbing one column cannot help
+    for r in range(W.shape[1]):
+        for d in (1e-4, -1e-4):
+            V = W.copy()
+            V[:, r] = np.maximum(0, V[:, r] + d)
+            assert O.nls_objective(V, S, M) >= O.nls_objective(O.hals_update(W, S, M), S, M) - 1e-9
+
+
+def test_mu_monotone():
+    S, M = _subproblem(20)
+    W = np.random.default_rng(21).random(M.shape) + 0.1
+    prev = O.nls_objective(W, S, M)
+    for _ in range(50):
+        W = O.mu_update(W, S, M)
+        cur = O.nls_objective(W, S, M)
+        assert cur <= prev + 1e-12 * abs(prev)
+        prev = cur
+
+
+@pytest.mark.parametrize("R", [2, 4, 6])
+def test_hals_converges_to_bruteforce_nnls_and_kkt(R):
+    rng = np.random.default_rng(22 + R)
+    K = rng.random((40, R)) + 0.1 * np.eye(40, R)
+    S = K.T @ K
+    M = rng.standard_normal((5, R)) * 3.0  # mixed signs: some constraints active
+    W = np.zeros_like(M)
+    for _ in range(20000):
+        Wn = O.hals_update(W, S, M)
+        if np.max(np.abs(Wn - W)) < 1e-15:
+            W = Wn
+            break
+        W = Wn
+    for i in range(M.shape[0]):
+        h = O.nnls_bruteforce(S, M[i])
+        np.testing.assert_allclose(W[i], h, rtol=0, atol=1e-10 * max(1.0, np.max(np.abs(h))))
+    assert O.kkt_residual(W, S, M) < 1e-10
+
+
+def test_nnls_bruteforce_matches_unconstrained_when_interior():
+    S, M = _subproblem(30, I=1, R=3)
+    h = np.linalg.solve(S, M[0])
+    if np.all(h > 0):
+        np.testing.assert_allclose(O.nnls_bruteforce(S, M[0]), h, rtol=1e-12)
+
+
+def test_nls_objective_is_least_squares_up_to_constant():
+    rng = np.random.default_rng(31)
+    K = rng.random((25, 3))
+    A = rng.random((4, 25))
+    W = rng.random((4, 3))
+    S, M = K.T @ K, A @ K
+    lhs = np.sum((A - W @ K.T) ** 2)
+    rhs = 2 * O.nls_objective(W, S, M) + np.sum(A * A)
+    assert abs(lhs - rhs) < 1e-11 * lhs
+
+
+@pytest.mark.parametrize("upd", ["hals", "mu"])
+def test_noise_free_truth_is_fixed_point(upd):
+    dims = (6, 5, 4)
+    X, truth = inputs.planted(dims, 3, 0.0, seed=32)
+    out = O.nncp(X, truth, 2, update=upd)
+    model = O.model_tensor_cp(out["lam"], out["H"])
+    assert np.max(np.abs(model - X)) < 1e-11 * np.max(X)
+    assert O.relerr_explicit(X, out["lam"], out["H"]) < 1e-10
+    # the identity alpha - 2 beta + gamma cancels: it resolves eps^2 only to ~1e-15
+    assert out["eps"][-1] ** 2 < 1e-14
+
+
+@pytest.mark.parametrize("upd", ["hals", "mu"])
+def test_bcd_objective_monotone(upd):
+    dims = (8, 7, 6)
+    X, _ = inputs.planted(dims, 4, 0.05, seed=33)
+    H0 = inputs.init_factors(dims, 4, seed=34)
+    out = O.nncp(X, H0, 15, update=upd)
+    e = out["eps"]
+    assert all(e[i + 1] <= e[i] + 1e-12 for i in range(len(e) - 1))
+
+
+def test_normalised_driver_equals_unnormalised_algorithm():
+    dims = (5, 6, 4)
+    X, _ = inputs.planted(dims, 3, 0.02, seed=35)
+    H0 = inputs.init_factors(dims, 3, seed=36)
+    for upd in ("hals", "mu"):
+        a = O.nncp(X, H0, 5, update=upd)
+        Hu = O.nncp_unnormalized(X, H0, 5, update=upd)
+        ma = O.model_tensor_cp(a["lam"], a["H"])
+        mu = O.model_tensor_cp(np.ones(3), Hu)
+        assert np.max(np.abs(ma - mu)) < 1e-10 * np.max(np.abs(mu))
+
+
+# --- planted recovery (Section V-A: exact low rank converges to zero error) ----
+
+def _congruence(A, B):
+    """min over components of the product of per-mode column cosines (after matching)."""
+    R = A[0].shape[1]
+    C = np.ones((R, R))
+    for a, b in zip(A, B):
+        an = a / np.linalg.norm(a, axis=0)
+        bn = b / np.linalg.norm(b, axis=0)
+        C = C * (an.T @ bn)
+    import itertools
+    return max(min(C[i, p[i]] for i in range(R)) for p in itertools.permutations(range(R)))
+
+
+def test_planted_recovery_from_perturbed_start():
+    dims = (12, 10, 8)
+    X, truth = inputs.planted(dims, 3, 0.0, seed=37)
+    rng = np.random.default_rng(38)
+    H0 = [t * (1 + 0.01 * rng.standard_normal(t.shape)) for t in truth]
+    out = O.nncp(X, H0, 1500, update="hals")
+    assert O.relerr_explicit(X, out["lam"], out["H"]) < 1e-10
+    assert _congruence(out["H"], truth) > 1 - 1e-8
+
+
+def test_planted_recovery_from_random_start():
+    dims = (12, 10, 8)
+    X, truth = inputs.planted(dims, 3, 0.0, seed=39)
+    H0 = inputs.init_factors(dims, 3, seed=40)
+    out = O.nncp(X, H0, 1500, update="hals")
+    assert O.relerr_explicit(X, out["lam"], out["H"]) < 1e-10
+    assert _congruence(out["H"], truth) > 1 - 1e-8
+
+
+# --- the generator agrees with the oracle's own model evaluation ---------------
+
+def test_generator_model_matches_oracle_model():
+    dims = (4, 3, 5, 2)
+    H = _rand_factors(dims, 3, 41)
+    np.testing.assert_allclose(inputs.model_tensor(H), O.model_tensor_cp(np.ones(3), H), rtol=1e-13)
+
+
+def test_generator_noise_level():
+    dims = (20, 15, 10)
+    Xc = inputs.model_tensor(inputs.uniform_factors(dims, 4, 42))
+    X = inputs.add_noise_clip(Xc, 0.01, seed=43)
+    # clipping can only shrink the perturbation; with a positive tensor none is clipped
+    rel = np.linalg.norm((X - Xc).ravel()) / np.linalg.norm(Xc.ravel())
+    assert abs(rel - 0.01) < 1e-12
+
+
+# --- planted mistakes: the pins above must catch them ------------------------
+
+def test_pins_catch_wrong_krp_order(monkeypatch):
+    dims = (3, 4, 5)
+    X = _rand_tensor(dims, 44)
+    H = _rand_factors(dims, 2, 45)
+    good = O.mttkrp_bruteforce(X, H, 0)
+    monkeypatch.setattr(O.nncp_oracle, "khatri_rao",
+                        lambda A, B: (A[None, :, :] * B[:, None, :]).reshape(-1, A.shape[1]))
+    bad = O.nncp_oracle.mttkrp_direct(X, H, 0)
+    assert np.max(np.abs(bad - good)) > 1e-3
+
+
+def test_pins_catch_hals_without_division(monkeypatch):
+    S = np.array([[2.5]])
+    M = np.array([[1.0]])
+
+    def bad_hals(W, S, M):
+        W = W.copy()
+        for r in range(W.shape[1]):
+            W[:, r] = np.maximum(0, W[:, r] + M[:, r] - W @ S[:, r])
+        return W
+    assert abs(bad_hals(np.array([[9.0]]), S, M)[0, 0] - 0.4) > 1e-3
+    assert abs(O.hals_update(np.array([[9.0]]), S, M)[0, 0] - 0.4) < 1e-15
+
+
+def test_pins_catch_wrong_fit_sign():
+    dims = (5, 4, 3)
+    X = _rand_tensor(dims, 46)
+    H = _rand_factors(dims, 2, 47)
+    lam = np.ones(2)
+    model = O.model_tensor_cp(lam, H)
+    alpha, beta, gamma = float(np.sum(X * X)), float(np.sum(X * model)), float(np.sum(model * model))
+    good = O.fit_from_terms(alpha, beta, gamma)[1]
+    bad = math.sqrt(abs(alpha + 2 * beta + gamma) / alpha)
+    assert abs(good - O.relerr_explicit(X, lam, H)) < 1e-12
+    assert abs(bad - O.relerr_explicit(X, lam, H)) > 1e-3
