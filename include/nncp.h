@@ -1,0 +1,181 @@
+/*
+ * nncp.h -- C ABI of the MI355X (gfx950) nonnegative CP decomposition library.
+ *
+ * The problem (Eq. (1) of Ballard, Hayashi, Kannan, "Parallel Nonnegative CP
+ * Decomposition of Dense Tensors"): given a dense tensor X of shape
+ * I_1 x ... x I_N and a rank R, find nonnegative factor matrices H^(n)
+ * (I_n x R) and weights lambda (R) that minimise
+ * || X - sum_r lambda_r H^(1)(:,r) o ... o H^(N)(:,r) ||.  The method is block
+ * coordinate descent over the factor matrices (Algorithm 1) with the
+ * dimension-tree MTTKRP (Section IV-A), HALS or multiplicative updates
+ * (Section II-B), column normalisation and the relative-error identity of
+ * Section IV-B / the appendix algorithm.
+ *
+ * Conventions shared by every entry point:
+ *  - Tensors are dense and stored with mode 1 fastest (the generalised
+ *    column-major order of Section IV-C): entry (i_1..i_N), 0-based, lives at
+ *    i_1 + I_1*(i_2 + I_2*(i_3 + ...)).
+ *  - Factor matrices are I_n x R, column-major, float32, leading dimension I_n.
+ *  - "device" pointers are HIP device memory on the current device; "host"
+ *    pointers are ordinary CPU memory. The library never frees caller memory.
+ *  - `stream` is a hipStream_t passed as void*; NULL means the null stream.
+ *    Work is enqueued on it; calls that return host results synchronise it.
+ *  - Every function returns an nncp_status (0 = success). No C++ exception
+ *    crosses this boundary. Invalid arguments are rejected before any work is
+ *    enqueued; a HIP runtime failure returns NNCP_EDEVICE.
+ *  - Tensor values are not scanned: nonnegative data is the intended input
+ *    (Eq. (1)), but any finite values are accepted.
+ */
+#ifndef NNCP_H
+#define NNCP_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  NNCP_OK = 0,
+  NNCP_EINVAL = -1,    /* bad argument (shape, rank, pointer, enum, buffer size) */
+  NNCP_ENOMEM = -2,    /* device memory could not be allocated / job exceeds the HBM budget */
+  NNCP_EDEVICE = -3,   /* a HIP runtime call or kernel launch failed */
+  NNCP_EBUSY = -4,     /* serving: job not finished yet */
+  NNCP_ENOTFOUND = -5, /* serving: unknown job id */
+  NNCP_ECANCELED = -6  /* serving: job was cancelled or failed */
+} nncp_status;
+
+typedef enum { NNCP_HALS = 0, NNCP_MU = 1 } nncp_update;
+typedef enum { NNCP_F32 = 0, NNCP_BF16 = 1, NNCP_F16 = 2 } nncp_dtype;
+
+#define NNCP_MAX_MODES 8
+#define NNCP_MAX_RANK 128
+
+/* Options; zero-initialised means: automatic split, record every fit, use a
+ * HIP graph per outer iteration, no early stop. */
+typedef struct nncp_options {
+  int split;          /* root split s (modes 1..s | s+1..N), 1 <= s <= N-1; <= 0: minimise I_L + I_R */
+  int no_record_fit;  /* nonzero: fit[] receives only the final value */
+  int no_graph;       /* nonzero: launch kernels one by one instead of replaying a HIP graph */
+  int phase_timers;   /* nonzero: time each phase with HIP events (implies no_graph) */
+  double tol;         /* > 0: stop when |fit_k - fit_{k-1}| < tol (host check each iteration) */
+  int reserved[8];
+} nncp_options;
+
+/* Human-readable text for a status code (static storage). */
+const char* nncp_strerror(int status);
+
+/* Library version as major*10000 + minor*100 + patch. */
+int nncp_version(void);
+
+/* Bytes of scratch the nncp() driver needs for this problem (>= 256-byte aligned
+ * internally). Returns 0 for invalid arguments. */
+size_t nncp_workspace_bytes(int N, const int64_t* dims, int R, int dtype,
+                            const nncp_options* opt);
+
+/*
+ * nncp: `iters` outer iterations of alternating-update NNCP (Algorithm 1;
+ * normalisation and error as in the appendix algorithm).
+ *
+ *  X          device, the tensor in `dtype` storage (F32, BF16 or F16), I entries.
+ *  dims       host, N extents, N in [2, NNCP_MAX_MODES], each >= 1.
+ *  R          rank, 1 <= R <= NNCP_MAX_RANK.
+ *  update     NNCP_HALS (column-wise HALS sweep) or NNCP_MU (multiplicative).
+ *  H          host array of N device pointers, H[n] is I_n x R float32.
+ *             In: starting factors (any nonnegative scaling). Out: factors with
+ *             unit 2-norm columns (a column that became zero stays zero).
+ *  lambda     host, R doubles. In: weights of the starting model (pass ones for
+ *             fresh factors). Out: the weights lambda of the final model.
+ *  fit        host, `iters` doubles (or 1 if opt->no_record_fit): fit = 1 - eps
+ *             after each outer iteration, eps = ||X - model|| / ||X|| from
+ *             ||X||^2 - 2<X,model> + ||model||^2 accumulated in float64.
+ *  iters_done host, optional: iterations actually run (fewer if tol stopped early).
+ *  workspace  device scratch of ws_bytes >= nncp_workspace_bytes(...), or NULL to
+ *             let the library allocate (and free before returning).
+ * Synchronises `stream` before returning.
+ */
+int nncp(const void* X, int dtype, int N, const int64_t* dims, int R, int iters, int update,
+         float* const* H, double* lambda, double* fit, int* iters_done,
+         void* workspace, size_t ws_bytes, const nncp_options* opt, void* stream);
+
+/* ---- Persistent plan: the same driver, split so a caller can time or resume ---- */
+typedef struct nncp_plan nncp_plan;
+
+/* Validates, lays out the workspace, computes alpha = ||X||^2 (float64), the
+ * starting Gram matrices and lambda (appendix algorithm, initialisation).
+ * X, H, workspace stay owned by the caller and must outlive the plan.
+ * lambda_in: host R doubles or NULL for ones. */
+int nncp_plan_create(nncp_plan** plan, const void* X, int dtype, int N, const int64_t* dims,
+                     int R, int update, float* const* H, const double* lambda_in,
+                     void* workspace, size_t ws_bytes, const nncp_options* opt, void* stream);
+/* Runs `iters` more outer iterations from the current state; fit (host, may be
+ * NULL) receives one value per iteration. Synchronises. */
+int nncp_plan_run(nncp_plan* plan, int iters, double* fit, int* iters_done);
+/* Writes unit-column factors into H (in place) and lambda (host, R). The plan
+ * stays valid: a later run continues from this normalised state. */
+int nncp_plan_finish(nncp_plan* plan, double* lambda);
+/* Milliseconds per phase accumulated by runs with phase_timers set, in the
+ * order pm, mttv, nls, gram, err, total. ms must hold 6 doubles. */
+int nncp_plan_phase_ms(const nncp_plan* plan, double* ms);
+int nncp_plan_destroy(nncp_plan* plan);
+
+/* ---- Steps of the hot path (each is the kernel the driver runs) ---- */
+
+/* Round float32 to bfloat16 / float16 (round to nearest even), n entries, device. */
+int nncp_quantize(const float* src, void* dst, int dtype, int64_t n, void* stream);
+
+/* out_dev[0] = sum x^2 over n entries accumulated in float64 (the ||A||^2 of
+ * the appendix algorithm's initialisation). out_dev: device double. */
+int nncp_norm_sq(const void* X, int dtype, int64_t n, double* out_dev, void* stream);
+
+/*
+ * Partial MTTKRP for a root branch of the dimension tree (Section IV-A, Fig. 2a):
+ * with I_L = I_1*...*I_s and I_R = I_{s+1}*...*I_N, view X as the column-major
+ * I_L x I_R matrix X_[L].
+ *   side 0 (left node {1..s}):   T = X_[L] * (H^(N) (.) ... (.) H^(s+1)),   T is I_L x R
+ *   side 1 (right node {s+1..N}): T = X_[L]^T * (H^(s) (.) ... (.) H^(1)),  T is I_R x R
+ * (.) is the Khatri-Rao product with the lowest mode's row index fastest.
+ * H: host array of N device factor pointers (only the contracted modes are read).
+ * T: device float32, column-major with leading dimension I_L or I_R.
+ */
+int nncp_partial_mttkrp(const void* X, int dtype, int N, const int64_t* dims, int s, int side,
+                        float* const* H, int R, float* T, void* stream);
+
+/*
+ * Multi-TTV (Section IV-A, Fig. 2b) on a tree node {a..b} whose temporary T has
+ * shape I_a x ... x I_b x R (column-major, R slowest). `node_dims` are the
+ * nm = b-a+1 extents.
+ *   kind 0 (leaf {a}):  out(i,r) = sum_j T(i, j, r) K(j, r), K = H^(b) (.) ... (.) H^(a+1);
+ *                       out is I_a x R. Hf[0..nm-2] are the factors of modes a+1..b.
+ *   kind 1 (node {a+1..b}): out(j, r) = sum_i T(i, j, r) H^(a)(i, r); out has shape
+ *                       I_{a+1} x ... x I_b x R. Hf[0] is the factor of mode a.
+ */
+int nncp_mttv(const float* T, int nm, const int64_t* node_dims, int kind, float* const* Hf,
+              int R, float* out, void* stream);
+
+/* Full dimension-tree MTTKRP for mode n (0-based) with the given factors: the root
+ * PM on n's side of split s, then the chain of multi-TTVs down to leaf n. M: device
+ * float32 I_n x R. Uses an internal workspace allocated for the call. */
+int nncp_mttkrp(const void* X, int dtype, int N, const int64_t* dims, int s, int n,
+                float* const* H, int R, float* M, void* stream);
+
+/* G = H^T H (R x R, float64, device) for a device float32 I x R factor. */
+int nncp_gram(const float* H, int64_t I, int R, double* G, void* stream);
+
+/*
+ * One NLS-Update of a factor (Section II-B) followed by column normalisation:
+ *   W = H diag(lambda) (the block's current value in the model [[lambda; H]]),
+ *   HALS: for r = 1..R: W(:,r) = max(0, W(:,r) + (M(:,r) - (W S)(:,r)) / S(r,r));
+ *   MU:   W = W * M / max(W S, 1e-16);
+ *   lambda = column norms of W, H = W diag(1/lambda), G = H^T H.
+ * M, H: device float32 I x R; S: device float64 R x R (symmetric);
+ * lambda: device float64 R (in/out); G: device float64 R x R (out).
+ */
+int nncp_nls_update(const float* M, float* H, int64_t I, int R, const double* S,
+                    double* lambda, int update, double* G, void* stream);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* NNCP_H */

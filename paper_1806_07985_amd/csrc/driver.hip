@@ -1,0 +1,833 @@
+// Host driver of the NNCP hot path and its C ABI (include/nncp.h).
+//
+// One outer iteration (Algorithm 1) is, for n = 1..N:
+//   node op   -- the tree node whose lowest mode is n: the root partial MTTKRP
+//                of n's half (n = 1 or n = s+1) or a leading multi-TTV from the
+//                parent node (Section IV-A; node {a..b} splits into {a} | {a+1..b});
+//   leaf op   -- a trailing multi-TTV to M^(n), unless the node is the leaf;
+//   update    -- HALS or MU on the rows of the factor (Section II-B);
+//   finalize  -- Gram, column norms lambda, the next mode's S, and after mode N
+//                the fit (Section IV-B, appendix algorithm).
+// The whole iteration is captured once into a HIP graph and replayed.
+//
+// During the iteration the factor buffers hold the unnormalised result of each
+// mode's last update, and lam[n] holds its column norms; every consumer scales
+// by 1/lam (Khatri-Rao operands, multi-TTV vectors, normalised Grams), so the
+// arithmetic equals that of the normalised algorithm. nncp_plan_finish writes
+// the normalised factors back.
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <new>
+#include <vector>
+
+#include "nncp_internal.hpp"
+
+using namespace nncpk;
+
+namespace {
+
+#define HIPCHK(x)                          \
+  do {                                     \
+    hipError_t e_ = (x);                   \
+    if (e_ != hipSuccess) return NNCP_EDEVICE; \
+  } while (0)
+
+constexpr int kFitCap = 1024;
+
+inline size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
+
+struct Node {
+  int a = 0, b = 0;
+  float* buf = nullptr;
+  int64_t rows = 0;  // product of I_a..I_b
+};
+
+struct Layout {
+  size_t off_alpha, off_iter, off_counters, off_lam, off_lammodel, off_lamin, off_G, off_S, off_fit,
+      off_finpart, off_pmpart, off_nspart, off_M, off_nodes, total;
+  int ncounters;
+  int64_t nodes_floats[kMaxModes];
+  PmLaunch pmL[2];
+  int fin_chunks, fin_rows;
+  int ns_blocks;
+};
+
+struct Problem {
+  int N = 0, R = 0, dtype = 0, s = 0, update = 0;
+  int64_t dims[kMaxModes] = {};
+  int64_t IL = 0, IR = 0, I = 0;
+};
+
+int validate(const Problem& p) {
+  if (p.N < 2 || p.N > kMaxModes) return NNCP_EINVAL;
+  if (p.R < 1 || p.R > kMaxRank) return NNCP_EINVAL;
+  if (p.dtype != NNCP_F32 && p.dtype != NNCP_BF16 && p.dtype != NNCP_F16) return NNCP_EINVAL;
+  if (p.update != NNCP_HALS && p.update != NNCP_MU) return NNCP_EINVAL;
+  if (p.s < 1 || p.s > p.N - 1) return NNCP_EINVAL;
+  for (int k = 0; k < p.N; ++k)
+    if (p.dims[k] < 1 || p.dims[k] > (int64_t)INT32_MAX) return NNCP_EINVAL;
+  // every matricisation used by the kernels indexes its reduction with 32 bits
+  if (p.IL > (int64_t)UINT32_MAX || p.IR > (int64_t)UINT32_MAX) return NNCP_EINVAL;
+  return NNCP_OK;
+}
+
+int fill_problem(Problem& p, int N, const int64_t* dims, int R, int dtype, int update, int split) {
+  if (!dims || N < 2 || N > kMaxModes) return NNCP_EINVAL;
+  p.N = N;
+  p.R = R;
+  p.dtype = dtype;
+  p.update = update;
+  long double prodL = 1, total = 1;
+  for (int k = 0; k < N; ++k) {
+    p.dims[k] = dims[k];
+    if (dims[k] < 1) return NNCP_EINVAL;
+    total *= (long double)dims[k];
+  }
+  if (total > 9.0e18L) return NNCP_EINVAL;
+  if (split <= 0) {
+    // root split minimising I_L + I_R (smallest tree temporaries)
+    long double best = -1;
+    int bs = 1;
+    for (int s = 1; s < N; ++s) {
+      long double L = 1, Rr = 1;
+      for (int k = 0; k < s; ++k) L *= dims[k];
+      for (int k = s; k < N; ++k) Rr *= dims[k];
+      if (best < 0 || L + Rr < best) {
+        best = L + Rr;
+        bs = s;
+      }
+    }
+    p.s = bs;
+  } else {
+    p.s = split;
+  }
+  if (p.s < 1 || p.s > N - 1) return NNCP_EINVAL;
+  for (int k = 0; k < p.s; ++k) prodL *= dims[k];
+  p.IL = (int64_t)prodL;
+  p.IR = (int64_t)(total / prodL);
+  p.I = (int64_t)total;
+  return validate(p);
+}
+
+int64_t prod_range(const Problem& p, int a, int b) {
+  int64_t r = 1;
+  for (int k = a; k <= b; ++k) r *= p.dims[k];
+  return r;
+}
+
+// subtree end for mode n
+inline int sub_end(const Problem& p, int n) { return n < p.s ? p.s - 1 : p.N - 1; }
+inline int sub_start(const Problem& p, int n) { return n < p.s ? 0 : p.s; }
+
+Layout make_layout(const Problem& p) {
+  Layout L{};
+  const int N = p.N, R = p.R, RR = R * R;
+  size_t o = 0;
+  auto take = [&](size_t bytes) {
+    size_t at = o;
+    o = align256(o + bytes);
+    return at;
+  };
+  L.pmL[0] = pm_plan(0, p.dtype, p.IL, p.IR, R);
+  L.pmL[1] = pm_plan(1, p.dtype, p.IL, p.IR, R);
+  L.fin_chunks = finalize_chunks(1, &L.fin_rows);
+  int maxchunks = 1;
+  for (int k = 0; k < N; ++k) {
+    int rpc;
+    maxchunks = std::max(maxchunks, finalize_chunks(p.dims[k], &rpc));
+  }
+  L.ns_blocks = norm_sq_blocks(p.I);
+  L.ncounters = std::max(L.pmL[0].ncounters, L.pmL[1].ncounters) + 4;
+  L.off_alpha = take(sizeof(double));
+  L.off_iter = take(sizeof(int));
+  L.off_counters = take(sizeof(unsigned) * L.ncounters);
+  L.off_lam = take(sizeof(double) * N * R);
+  L.off_lammodel = take(sizeof(double) * R);
+  L.off_lamin = take(sizeof(double) * R);
+  L.off_G = take(sizeof(double) * N * RR);
+  L.off_S = take(sizeof(double) * N * RR);
+  L.off_fit = take(sizeof(double) * kFitCap);
+  L.off_finpart = take(sizeof(double) * (size_t)maxchunks * (RR + 1));
+  L.off_pmpart = take(sizeof(float) * std::max(L.pmL[0].partial_floats, L.pmL[1].partial_floats));
+  L.off_nspart = take(sizeof(double) * L.ns_blocks);
+  int64_t maxI = 0;
+  for (int k = 0; k < N; ++k) maxI = std::max(maxI, p.dims[k]);
+  L.off_M = take(sizeof(float) * (size_t)maxI * R);
+  L.off_nodes = o;
+  for (int n = 0; n < N; ++n) {
+    const int b = sub_end(p, n);
+    L.nodes_floats[n] = prod_range(p, n, b) * R;
+    take(sizeof(float) * (size_t)L.nodes_floats[n]);
+  }
+  L.total = o + 256;
+  return L;
+}
+
+}  // namespace
+
+// ---------------------------------------------------------------------------
+// Plan
+// ---------------------------------------------------------------------------
+struct nncp_plan {
+  Problem p;
+  Layout L;
+  const void* X = nullptr;
+  float* H[kMaxModes] = {};
+  char* ws = nullptr;
+  bool own_ws = false;
+  hipStream_t user_stream = nullptr;
+  hipStream_t cap_stream = nullptr;
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t gexec = nullptr;
+  bool use_graph = true;
+  bool phase_timers = false;
+  bool record_fit = true;
+  double tol = 0.0;
+  double phase_ms[6] = {};
+  hipEvent_t ev[2] = {nullptr, nullptr};
+
+  template <typename T>
+  T* at(size_t off) const { return (T*)(ws + off); }
+  double* alpha() const { return at<double>(L.off_alpha); }
+  int* iter() const { return at<int>(L.off_iter); }
+  unsigned* counters() const { return at<unsigned>(L.off_counters); }
+  double* lam() const { return at<double>(L.off_lam); }
+  double* lam_model() const { return at<double>(L.off_lammodel); }
+  double* lam_in() const { return at<double>(L.off_lamin); }
+  double* G() const { return at<double>(L.off_G); }
+  double* S() const { return at<double>(L.off_S); }
+  double* fit() const { return at<double>(L.off_fit); }
+  double* finpart() const { return at<double>(L.off_finpart); }
+  float* pmpart() const { return at<float>(L.off_pmpart); }
+  double* nspart() const { return at<double>(L.off_nspart); }
+  float* Mbuf() const { return at<float>(L.off_M); }
+  float* node(int n) const {
+    size_t o = L.off_nodes;
+    for (int k = 0; k < n; ++k) o = align256(o + sizeof(float) * (size_t)L.nodes_floats[k]);
+    return (float*)(ws + o);
+  }
+};
+
+namespace {
+
+KrpDesc krp_for(const nncp_plan* P, int a, int b, bool scaled) {
+  KrpDesc k{};
+  k.nm = b - a + 1;
+  for (int j = 0; j < k.nm; ++j) {
+    k.f[j] = P->H[a + j];
+    k.dim[j] = (int)P->p.dims[a + j];
+    k.mode[j] = a + j;
+  }
+  k.lam = scaled ? P->lam() : nullptr;
+  k.lam_ld = P->p.R;
+  return k;
+}
+
+hipError_t run_pm(const nncp_plan* P, int side, float* T, const void* X, bool scaled, hipStream_t st) {
+  const Problem& p = P->p;
+  const PmLaunch& pl = P->L.pmL[side];
+  for (int c0 = 0; c0 < p.R; c0 += kPmMaxCols) {
+    PmArgs a{};
+    a.X = X;
+    a.IL = p.IL;
+    a.IR = p.IR;
+    a.krp = side == 0 ? krp_for(P, p.s, p.N - 1, scaled) : krp_for(P, 0, p.s - 1, scaled);
+    a.R = std::min(kPmMaxCols, p.R - c0);
+    a.col0 = c0;
+    a.T = T;
+    a.partial = P->pmpart();
+    a.counters = P->counters();
+    a.nsplit = pl.nsplit;
+    a.kchunk = pl.kchunk;
+    PmLaunch l2 = pl;
+    if (a.R != p.R) {
+      l2 = pm_plan(side, p.dtype, p.IL, p.IR, a.R);
+    }
+    a.nsplit = l2.nsplit;
+    a.kchunk = l2.kchunk;
+    hipError_t e = pm_launch(l2, a, st);
+    if (e != hipSuccess) return e;
+  }
+  return hipSuccess;
+}
+
+// Computes M^(n) (node op + leaf op) on stream st; returns the buffer holding it.
+hipError_t mttkrp_mode(const nncp_plan* P, int n, bool scaled, hipStream_t st, const float** Mout,
+                       int phase_ev = 0) {
+  const Problem& p = P->p;
+  const int b = sub_end(p, n), start = sub_start(p, n);
+  float* nodebuf = P->node(n);
+  hipError_t e;
+  if (n == start) {
+    e = run_pm(P, n == 0 ? 0 : 1, nodebuf, P->X, scaled, st);
+  } else {
+    MttvArgs a{};
+    a.T = P->node(n - 1);
+    a.Ia = p.dims[n - 1];
+    a.J = prod_range(p, n, b);
+    a.R = p.R;
+    a.krp = krp_for(P, n - 1, n - 1, scaled);
+    a.out = nodebuf;
+    e = mttv_lead_launch(a, st);
+  }
+  if (e != hipSuccess) return e;
+  if (n == b) {
+    *Mout = nodebuf;
+    return hipSuccess;
+  }
+  MttvArgs a{};
+  a.T = nodebuf;
+  a.Ia = p.dims[n];
+  a.J = prod_range(p, n + 1, b);
+  a.R = p.R;
+  a.krp = krp_for(P, n + 1, b, scaled);
+  a.out = P->Mbuf();
+  e = mttv_trail_launch(a, st);
+  *Mout = P->Mbuf();
+  return e;
+}
+
+hipError_t finalize_mode(const nncp_plan* P, int n, const float* M, int set_model, int next_mode,
+                         int do_fit, hipStream_t st) {
+  const Problem& p = P->p;
+  FinalizeArgs f{};
+  f.W = P->H[n];
+  f.M = M;
+  f.I = p.dims[n];
+  f.R = p.R;
+  f.N = p.N;
+  f.mode = n;
+  f.G = P->G();
+  f.lam = P->lam();
+  f.lam_model = P->lam_model();
+  f.S = P->S();
+  f.next_mode = next_mode;
+  f.set_model = set_model;
+  f.do_fit = do_fit;
+  f.alpha = P->alpha();
+  f.fit_out = P->fit();
+  f.iter_counter = P->iter();
+  f.fit_capacity = kFitCap;
+  f.partial = P->finpart();
+  f.counter = P->counters() + P->L.ncounters - 1;
+  f.nchunks = finalize_chunks(p.dims[n], &f.rows_per_chunk);
+  return finalize_launch(f, st);
+}
+
+enum { PH_PM = 0, PH_MTTV = 1, PH_NLS = 2, PH_GRAM = 3, PH_ERR = 4, PH_TOTAL = 5 };
+
+// Enqueue one outer iteration. With timers, events bracket each phase (no graph).
+hipError_t enqueue_iteration(nncp_plan* P, hipStream_t st, std::vector<std::pair<int, hipEvent_t>>* marks) {
+  const Problem& p = P->p;
+  auto mark = [&](int phase) -> hipError_t {
+    if (!marks) return hipSuccess;
+    hipEvent_t e;
+    hipError_t r = hipEventCreate(&e);
+    if (r != hipSuccess) return r;
+    r = hipEventRecord(e, st);
+    marks->push_back({phase, e});
+    return r;
+  };
+  hipError_t e;
+  for (int n = 0; n < p.N; ++n) {
+    const int b = sub_end(p, n), start = sub_start(p, n);
+    const float* M = nullptr;
+    if ((e = mark(n == start ? PH_PM : PH_MTTV)) != hipSuccess) return e;
+    if (marks && n == start && n != b) {
+      // time the PM and the trailing mTTV separately
+      if ((e = run_pm(P, n == 0 ? 0 : 1, P->node(n), P->X, true, st)) != hipSuccess) return e;
+      if ((e = mark(PH_MTTV)) != hipSuccess) return e;
+      MttvArgs a{};
+      a.T = P->node(n);
+      a.Ia = p.dims[n];
+      a.J = prod_range(p, n + 1, b);
+      a.R = p.R;
+      a.krp = krp_for(P, n + 1, b, true);
+      a.out = P->Mbuf();
+      if ((e = mttv_trail_launch(a, st)) != hipSuccess) return e;
+      M = P->Mbuf();
+    } else {
+      if ((e = mttkrp_mode(P, n, true, st, &M)) != hipSuccess) return e;
+    }
+    if ((e = mark(PH_NLS)) != hipSuccess) return e;
+    UpdateArgs u{};
+    u.M = M;
+    u.W = P->H[n];
+    u.I = p.dims[n];
+    u.R = p.R;
+    u.S = P->S() + (int64_t)n * p.R * p.R;
+    u.lam_model = P->lam_model();
+    u.lam_self = P->lam() + (int64_t)n * p.R;
+    u.update = p.update;
+    if ((e = update_launch(u, st)) != hipSuccess) return e;
+    const bool last = (n == p.N - 1);
+    if ((e = mark(last ? PH_ERR : PH_GRAM)) != hipSuccess) return e;
+    if ((e = finalize_mode(P, n, M, 1, (n + 1) % p.N, last ? 1 : 0, st)) != hipSuccess) return e;
+  }
+  return mark(-1);
+}
+
+int destroy_graph(nncp_plan* P) {
+  if (P->gexec) hipGraphExecDestroy(P->gexec);
+  if (P->graph) hipGraphDestroy(P->graph);
+  P->gexec = nullptr;
+  P->graph = nullptr;
+  return NNCP_OK;
+}
+
+int build_graph(nncp_plan* P) {
+  destroy_graph(P);
+  HIPCHK(hipStreamBeginCapture(P->cap_stream, hipStreamCaptureModeThreadLocal));
+  hipError_t e = enqueue_iteration(P, P->cap_stream, nullptr);
+  hipGraph_t g = nullptr;
+  hipError_t e2 = hipStreamEndCapture(P->cap_stream, &g);
+  if (e != hipSuccess || e2 != hipSuccess) {
+    if (g) hipGraphDestroy(g);
+    return NNCP_EDEVICE;
+  }
+  P->graph = g;
+  HIPCHK(hipGraphInstantiate(&P->gexec, g, nullptr, nullptr, 0));
+  return NNCP_OK;
+}
+
+}  // namespace
+
+// ---------------------------------------------------------------------------
+// C ABI
+// ---------------------------------------------------------------------------
+extern "C" {
+
+const char* nncp_strerror(int s) {
+  switch (s) {
+    case NNCP_OK: return "ok";
+    case NNCP_EINVAL: return "invalid argument";
+    case NNCP_ENOMEM: return "out of device memory or over budget";
+    case NNCP_EDEVICE: return "HIP runtime or kernel launch failure";
+    case NNCP_EBUSY: return "job not finished";
+    case NNCP_ENOTFOUND: return "unknown job";
+    case NNCP_ECANCELED: return "job cancelled or failed";
+    default: return "unknown status";
+  }
+}
+
+int nncp_version(void) { return 100; }
+
+size_t nncp_workspace_bytes(int N, const int64_t* dims, int R, int dtype, const nncp_options* opt) {
+  Problem p;
+  if (fill_problem(p, N, dims, R, dtype, NNCP_HALS, opt ? opt->split : 0) != NNCP_OK) return 0;
+  return make_layout(p).total;
+}
+
+int nncp_plan_create(nncp_plan** out, const void* X, int dtype, int N, const int64_t* dims, int R,
+                     int update, float* const* H, const double* lambda_in, void* workspace,
+                     size_t ws_bytes, const nncp_options* opt, void* stream) {
+  if (!out || !X || !H) return NNCP_EINVAL;
+  *out = nullptr;
+  Problem p;
+  int st = fill_problem(p, N, dims, R, dtype, update, opt ? opt->split : 0);
+  if (st != NNCP_OK) return st;
+  for (int k = 0; k < N; ++k)
+    if (!H[k]) return NNCP_EINVAL;
+  if (dtype != NNCP_F32) return NNCP_EINVAL;  // low-precision PM kernels: see nncp_quantize
+  nncp_plan* P = new (std::nothrow) nncp_plan();
+  if (!P) return NNCP_ENOMEM;
+  P->p = p;
+  P->L = make_layout(p);
+  P->X = X;
+  for (int k = 0; k < N; ++k) P->H[k] = H[k];
+  P->user_stream = (hipStream_t)stream;
+  P->use_graph = !(opt && (opt->no_graph || opt->phase_timers));
+  P->phase_timers = opt && opt->phase_timers;
+  P->record_fit = !(opt && opt->no_record_fit);
+  P->tol = opt ? opt->tol : 0.0;
+  if (workspace) {
+    if (ws_bytes < P->L.total) {
+      delete P;
+      return NNCP_EINVAL;
+    }
+    P->ws = (char*)workspace;
+  } else {
+    void* w = nullptr;
+    if (hipMalloc(&w, P->L.total) != hipSuccess) {
+      delete P;
+      return NNCP_ENOMEM;
+    }
+    P->ws = (char*)w;
+    P->own_ws = true;
+  }
+  if (((uintptr_t)P->ws) % 256 != 0) {
+    // the layout assumes a 256-byte aligned base
+    if (P->own_ws) hipFree(P->ws);
+    delete P;
+    return NNCP_EINVAL;
+  }
+  hipStream_t s = P->user_stream;
+  auto fail = [&](int code) {
+    nncp_plan_destroy(P);
+    return code;
+  };
+  if (hipStreamCreateWithFlags(&P->cap_stream, hipStreamNonBlocking) != hipSuccess) return fail(NNCP_EDEVICE);
+  if (hipEventCreateWithFlags(&P->ev[0], hipEventDisableTiming) != hipSuccess) return fail(NNCP_EDEVICE);
+  if (hipEventCreateWithFlags(&P->ev[1], hipEventDisableTiming) != hipSuccess) return fail(NNCP_EDEVICE);
+  // zero counters, iteration counter
+  if (fill_u32_launch(P->counters(), P->L.ncounters, 0u, s) != hipSuccess) return fail(NNCP_EDEVICE);
+  if (fill_u32_launch((unsigned*)P->iter(), 1, 0u, s) != hipSuccess) return fail(NNCP_EDEVICE);
+  // lambda_in
+  if (lambda_in) {
+    if (hipMemcpyAsync(P->lam_in(), lambda_in, sizeof(double) * R, hipMemcpyHostToDevice, s) != hipSuccess)
+      return fail(NNCP_EDEVICE);
+  } else if (fill_f64_launch(P->lam_in(), R, 1.0, s) != hipSuccess) {
+    return fail(NNCP_EDEVICE);
+  }
+  // alpha = ||X||^2
+  if (norm_sq_launch(X, dtype, p.I, P->alpha(), P->nspart(), P->counters() + P->L.ncounters - 2,
+                     P->L.ns_blocks, s) != hipSuccess)
+    return fail(NNCP_EDEVICE);
+  // starting Grams / norms per mode, then model weights and S^(1)
+  for (int k = 0; k < N; ++k)
+    if (finalize_mode(P, k, nullptr, 0, -1, 0, s) != hipSuccess) return fail(NNCP_EDEVICE);
+  if (init_model_launch(P->lam_in(), P->lam(), P->lam_model(), P->G(), P->S(), N, R, s) != hipSuccess)
+    return fail(NNCP_EDEVICE);
+  if (hipStreamSynchronize(s) != hipSuccess) return fail(NNCP_EDEVICE);
+  *out = P;
+  return NNCP_OK;
+}
+
+int nncp_plan_destroy(nncp_plan* P) {
+  if (!P) return NNCP_EINVAL;
+  destroy_graph(P);
+  if (P->cap_stream) hipStreamDestroy(P->cap_stream);
+  for (auto& e : P->ev)
+    if (e) hipEventDestroy(e);
+  if (P->own_ws && P->ws) hipFree(P->ws);
+  delete P;
+  return NNCP_OK;
+}
+
+int nncp_plan_run(nncp_plan* P, int iters, double* fit, int* iters_done) {
+  if (!P || iters < 0) return NNCP_EINVAL;
+  if (iters_done) *iters_done = 0;
+  if (iters == 0) return NNCP_OK;
+  hipStream_t us = P->user_stream;
+  int done = 0;
+  double prev_fit = NAN;
+  std::vector<double> hfit;
+  while (done < iters) {
+    int chunk = std::min(iters - done, kFitCap);
+    if (P->tol > 0) chunk = 1;
+    if (fill_u32_launch((unsigned*)P->iter(), 1, 0u, us) != hipSuccess) return NNCP_EDEVICE;
+    if (P->use_graph) {
+      if (!P->gexec) {
+        int r = build_graph(P);
+        if (r != NNCP_OK) return r;
+      }
+      HIPCHK(hipEventRecord(P->ev[0], us));
+      HIPCHK(hipStreamWaitEvent(P->cap_stream, P->ev[0], 0));
+      for (int i = 0; i < chunk; ++i) HIPCHK(hipGraphLaunch(P->gexec, P->cap_stream));
+      HIPCHK(hipEventRecord(P->ev[1], P->cap_stream));
+      HIPCHK(hipStreamWaitEvent(us, P->ev[1], 0));
+    } else if (P->phase_timers) {
+      for (int i = 0; i < chunk; ++i) {
+        std::vector<std::pair<int, hipEvent_t>> marks;
+        hipError_t e = enqueue_iteration(P, us, &marks);
+        if (e == hipSuccess) e = hipStreamSynchronize(us);
+        for (size_t j = 0; j + 1 < marks.size(); ++j) {
+          float ms = 0.f;
+          if (e == hipSuccess && hipEventElapsedTime(&ms, marks[j].second, marks[j + 1].second) == hipSuccess &&
+              marks[j].first >= 0)
+            P->phase_ms[marks[j].first] += ms;
+        }
+        if (e == hipSuccess && marks.size() >= 2) {
+          float ms = 0.f;
+          if (hipEventElapsedTime(&ms, marks.front().second, marks.back().second) == hipSuccess)
+            P->phase_ms[PH_TOTAL] += ms;
+        }
+        for (auto& m : marks) hipEventDestroy(m.second);
+        if (e != hipSuccess) return NNCP_EDEVICE;
+      }
+    } else {
+      for (int i = 0; i < chunk; ++i)
+        if (enqueue_iteration(P, us, nullptr) != hipSuccess) return NNCP_EDEVICE;
+    }
+    hfit.resize(chunk);
+    HIPCHK(hipMemcpyAsync(hfit.data(), P->fit(), sizeof(double) * chunk, hipMemcpyDeviceToHost, us));
+    HIPCHK(hipStreamSynchronize(us));
+    if (fit) std::memcpy(fit + done, hfit.data(), sizeof(double) * chunk);
+    done += chunk;
+    if (P->tol > 0) {
+      double f = hfit[chunk - 1];
+      if (!std::isnan(prev_fit) && std::fabs(f - prev_fit) < P->tol) break;
+      prev_fit = f;
+    }
+  }
+  if (iters_done) *iters_done = done;
+  return NNCP_OK;
+}
+
+int nncp_plan_finish(nncp_plan* P, double* lambda) {
+  if (!P || !lambda) return NNCP_EINVAL;
+  hipStream_t s = P->user_stream;
+  const Problem& p = P->p;
+  for (int k = 0; k < p.N; ++k)
+    if (normalize_out_launch(P->H[k], p.dims[k], p.R, P->lam() + (int64_t)k * p.R, s) != hipSuccess)
+      return NNCP_EDEVICE;
+  if (unit_lambda_launch(P->lam(), (int64_t)p.N * p.R, s) != hipSuccess) return NNCP_EDEVICE;
+  HIPCHK(hipMemcpyAsync(lambda, P->lam_model(), sizeof(double) * p.R, hipMemcpyDeviceToHost, s));
+  HIPCHK(hipStreamSynchronize(s));
+  return NNCP_OK;
+}
+
+int nncp_plan_phase_ms(const nncp_plan* P, double* ms) {
+  if (!P || !ms) return NNCP_EINVAL;
+  for (int i = 0; i < 6; ++i) ms[i] = P->phase_ms[i];
+  return NNCP_OK;
+}
+
+int nncp(const void* X, int dtype, int N, const int64_t* dims, int R, int iters, int update,
+         float* const* H, double* lambda, double* fit, int* iters_done, void* workspace,
+         size_t ws_bytes, const nncp_options* opt, void* stream) {
+  if (iters < 0 || !lambda) return NNCP_EINVAL;
+  nncp_plan* P = nullptr;
+  int st = nncp_plan_create(&P, X, dtype, N, dims, R, update, H, lambda, workspace, ws_bytes, opt, stream);
+  if (st != NNCP_OK) return st;
+  std::vector<double> f(iters > 0 ? iters : 1, NAN);
+  int done = 0;
+  st = nncp_plan_run(P, iters, f.data(), &done);
+  if (st == NNCP_OK) st = nncp_plan_finish(P, lambda);
+  if (st == NNCP_OK && fit) {
+    if (opt && opt->no_record_fit) fit[0] = done > 0 ? f[done - 1] : NAN;
+    else std::memcpy(fit, f.data(), sizeof(double) * (size_t)done);
+  }
+  if (iters_done) *iters_done = done;
+  nncp_plan_destroy(P);
+  return st;
+}
+
+// ---- steps ----
+
+int nncp_quantize(const float* src, void* dst, int dtype, int64_t n, void* stream) {
+  if (!src || !dst || n < 0 || (dtype != NNCP_BF16 && dtype != NNCP_F16)) return NNCP_EINVAL;
+  if (n == 0) return NNCP_OK;
+  return quantize_launch(src, dst, dtype, n, (hipStream_t)stream) == hipSuccess ? NNCP_OK : NNCP_EDEVICE;
+}
+
+int nncp_norm_sq(const void* X, int dtype, int64_t n, double* out_dev, void* stream) {
+  if (!X || !out_dev || n < 1 || (dtype < 0 || dtype > 2)) return NNCP_EINVAL;
+  hipStream_t s = (hipStream_t)stream;
+  const int nb = norm_sq_blocks(n);
+  void* scratch = nullptr;
+  if (hipMalloc(&scratch, sizeof(double) * nb + 256) != hipSuccess) return NNCP_ENOMEM;
+  unsigned* ctr = (unsigned*)((char*)scratch + align256(sizeof(double) * nb));
+  int st = NNCP_OK;
+  if (fill_u32_launch(ctr, 1, 0u, s) != hipSuccess ||
+      norm_sq_launch(X, dtype, n, out_dev, (double*)scratch, ctr, nb, s) != hipSuccess ||
+      hipStreamSynchronize(s) != hipSuccess)
+    st = NNCP_EDEVICE;
+  hipFree(scratch);
+  return st;
+}
+
+// A throw-away plan-like context for the step entry points (no lambda scaling).
+struct StepCtx {
+  nncp_plan P;
+  void* mem = nullptr;
+  ~StepCtx() {
+    if (mem) hipFree(mem);
+  }
+};
+
+static int step_ctx(StepCtx& c, const void* X, int dtype, int N, const int64_t* dims, int s, float* const* H,
+                    int R) {
+  int st = fill_problem(c.P.p, N, dims, R, dtype, NNCP_HALS, s);
+  if (st != NNCP_OK) return st;
+  if (dtype != NNCP_F32) return NNCP_EINVAL;
+  c.P.L = make_layout(c.P.p);
+  c.P.X = X;
+  for (int k = 0; k < N; ++k) {
+    if (!H[k]) return NNCP_EINVAL;
+    c.P.H[k] = H[k];
+  }
+  if (hipMalloc(&c.mem, c.P.L.total) != hipSuccess) return NNCP_ENOMEM;
+  c.P.ws = (char*)c.mem;
+  if (fill_u32_launch(c.P.counters(), c.P.L.ncounters, 0u, nullptr) != hipSuccess) return NNCP_EDEVICE;
+  return NNCP_OK;
+}
+
+int nncp_partial_mttkrp(const void* X, int dtype, int N, const int64_t* dims, int s, int side,
+                        float* const* H, int R, float* T, void* stream) {
+  if (!X || !H || !T || (side != 0 && side != 1) || s < 1) return NNCP_EINVAL;
+  StepCtx c;
+  int st = step_ctx(c, X, dtype, N, dims, s, H, R);
+  if (st != NNCP_OK) return st;
+  hipStream_t hs = (hipStream_t)stream;
+  if (hipDeviceSynchronize() != hipSuccess) return NNCP_EDEVICE;
+  if (run_pm(&c.P, side, T, X, false, hs) != hipSuccess) return NNCP_EDEVICE;
+  if (hipStreamSynchronize(hs) != hipSuccess) return NNCP_EDEVICE;
+  return NNCP_OK;
+}
+
+int nncp_mttv(const float* T, int nm, const int64_t* node_dims, int kind, float* const* Hf, int R,
+              float* out, void* stream) {
+  if (!T || !node_dims || !Hf || !out || nm < 2 || nm > kMaxModes || R < 1 || R > kMaxRank ||
+      (kind != 0 && kind != 1))
+    return NNCP_EINVAL;
+  for (int k = 0; k < nm; ++k)
+    if (node_dims[k] < 1 || node_dims[k] > INT32_MAX) return NNCP_EINVAL;
+  MttvArgs a{};
+  a.T = T;
+  a.Ia = node_dims[0];
+  a.J = 1;
+  for (int k = 1; k < nm; ++k) a.J *= node_dims[k];
+  if (a.J > (int64_t)UINT32_MAX) return NNCP_EINVAL;
+  a.R = R;
+  a.out = out;
+  a.krp.lam = nullptr;
+  if (kind == 0) {
+    a.krp.nm = nm - 1;
+    for (int j = 0; j < nm - 1; ++j) {
+      if (!Hf[j]) return NNCP_EINVAL;
+      a.krp.f[j] = Hf[j];
+      a.krp.dim[j] = (int)node_dims[j + 1];
+      a.krp.mode[j] = j;
+    }
+  } else {
+    if (!Hf[0]) return NNCP_EINVAL;
+    a.krp.nm = 1;
+    a.krp.f[0] = Hf[0];
+    a.krp.dim[0] = (int)node_dims[0];
+  }
+  hipStream_t hs = (hipStream_t)stream;
+  hipError_t e = kind == 0 ? mttv_trail_launch(a, hs) : mttv_lead_launch(a, hs);
+  if (e != hipSuccess) return NNCP_EDEVICE;
+  return hipStreamSynchronize(hs) == hipSuccess ? NNCP_OK : NNCP_EDEVICE;
+}
+
+int nncp_mttkrp(const void* X, int dtype, int N, const int64_t* dims, int s, int n, float* const* H, int R,
+                float* M, void* stream) {
+  if (!X || !H || !M || s < 1 || n < 0 || n >= N) return NNCP_EINVAL;
+  StepCtx c;
+  int st = step_ctx(c, X, dtype, N, dims, s, H, R);
+  if (st != NNCP_OK) return st;
+  hipStream_t hs = (hipStream_t)stream;
+  if (hipDeviceSynchronize() != hipSuccess) return NNCP_EDEVICE;
+  // walk the subtree of n from its root branch: nodes {start..b}, {start+1..b}, ... {n..b}
+  const Problem& p = c.P.p;
+  const int start = sub_start(p, n);
+  const float* Mp = nullptr;
+  for (int k = start; k <= n; ++k) {
+    if (k < n) {
+      // only the node is needed on the way down
+      const int b = sub_end(p, k);
+      if (k == start) {
+        if (run_pm(&c.P, k == 0 ? 0 : 1, c.P.node(k), X, false, hs) != hipSuccess) return NNCP_EDEVICE;
+      } else {
+        MttvArgs a{};
+        a.T = c.P.node(k - 1);
+        a.Ia = p.dims[k - 1];
+        a.J = prod_range(p, k, b);
+        a.R = p.R;
+        a.krp = krp_for(&c.P, k - 1, k - 1, false);
+        a.out = c.P.node(k);
+        if (mttv_lead_launch(a, hs) != hipSuccess) return NNCP_EDEVICE;
+      }
+    } else if (mttkrp_mode(&c.P, k, false, hs, &Mp) != hipSuccess) {
+      return NNCP_EDEVICE;
+    }
+  }
+  if (hipMemcpyAsync(M, Mp, sizeof(float) * (size_t)p.dims[n] * R, hipMemcpyDeviceToDevice, hs) != hipSuccess)
+    return NNCP_EDEVICE;
+  return hipStreamSynchronize(hs) == hipSuccess ? NNCP_OK : NNCP_EDEVICE;
+}
+
+int nncp_gram(const float* H, int64_t I, int R, double* G, void* stream) {
+  if (!H || !G || I < 1 || R < 1 || R > kMaxRank) return NNCP_EINVAL;
+  hipStream_t hs = (hipStream_t)stream;
+  int rpc;
+  const int chunks = finalize_chunks(I, &rpc);
+  const size_t RR = (size_t)R * R;
+  size_t bytes = align256(sizeof(double) * chunks * (RR + 1)) + align256(sizeof(double) * RR) +
+                 align256(sizeof(double) * R) * 2 + 256;
+  char* mem = nullptr;
+  if (hipMalloc(&mem, bytes) != hipSuccess) return NNCP_ENOMEM;
+  size_t o = 0;
+  double* part = (double*)(mem + o);
+  o += align256(sizeof(double) * chunks * (RR + 1));
+  double* Gn = (double*)(mem + o);
+  o += align256(sizeof(double) * RR);
+  double* lam = (double*)(mem + o);
+  o += align256(sizeof(double) * R);
+  double* lamm = (double*)(mem + o);
+  o += align256(sizeof(double) * R);
+  unsigned* ctr = (unsigned*)(mem + o);
+  FinalizeArgs f{};
+  f.W = H;
+  f.I = I;
+  f.R = R;
+  f.N = 1;
+  f.mode = 0;
+  f.G = Gn;
+  f.lam = lam;
+  f.lam_model = lamm;
+  f.next_mode = -1;
+  f.gram_raw = G;
+  f.partial = part;
+  f.counter = ctr;
+  f.nchunks = chunks;
+  f.rows_per_chunk = rpc;
+  int st = NNCP_OK;
+  if (fill_u32_launch(ctr, 1, 0u, hs) != hipSuccess || finalize_launch(f, hs) != hipSuccess ||
+      hipStreamSynchronize(hs) != hipSuccess)
+    st = NNCP_EDEVICE;
+  hipFree(mem);
+  return st;
+}
+
+int nncp_nls_update(const float* M, float* H, int64_t I, int R, const double* S, double* lambda, int update,
+                    double* G, void* stream) {
+  if (!M || !H || !S || !lambda || !G || I < 1 || R < 1 || R > kMaxRank ||
+      (update != NNCP_HALS && update != NNCP_MU))
+    return NNCP_EINVAL;
+  hipStream_t hs = (hipStream_t)stream;
+  int rpc;
+  const int chunks = finalize_chunks(I, &rpc);
+  const size_t RR = (size_t)R * R;
+  size_t bytes = align256(sizeof(double) * chunks * (RR + 1)) + align256(sizeof(double) * R) * 2 + 256;
+  char* mem = nullptr;
+  if (hipMalloc(&mem, bytes) != hipSuccess) return NNCP_ENOMEM;
+  double* part = (double*)mem;
+  double* ones = (double*)(mem + align256(sizeof(double) * chunks * (RR + 1)));
+  unsigned* ctr = (unsigned*)((char*)ones + align256(sizeof(double) * R));
+  int st = NNCP_OK;
+  UpdateArgs u{};
+  u.M = M;
+  u.W = H;
+  u.I = I;
+  u.R = R;
+  u.S = S;
+  u.lam_model = lambda;
+  u.lam_self = ones;
+  u.update = update;
+  FinalizeArgs f{};
+  f.W = H;
+  f.I = I;
+  f.R = R;
+  f.N = 1;
+  f.mode = 0;
+  f.G = G;
+  f.lam = lambda;
+  f.lam_model = lambda;
+  f.next_mode = -1;
+  f.partial = part;
+  f.counter = ctr;
+  f.nchunks = chunks;
+  f.rows_per_chunk = rpc;
+  if (fill_f64_launch(ones, R, 1.0, hs) != hipSuccess || fill_u32_launch(ctr, 1, 0u, hs) != hipSuccess ||
+      update_launch(u, hs) != hipSuccess || finalize_launch(f, hs) != hipSuccess ||
+      normalize_out_launch(H, I, R, lambda, hs) != hipSuccess || hipStreamSynchronize(hs) != hipSuccess)
+    st = NNCP_EDEVICE;
+  hipFree(mem);
+  return st;
+}
+
+}  // extern "C"

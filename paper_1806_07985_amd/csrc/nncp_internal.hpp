@@ -1,0 +1,144 @@
+// Internal declarations shared by the HIP kernels and the host driver.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+#include <stddef.h>
+
+#include "nncp.h"
+
+namespace nncpk {
+
+constexpr int kMaxModes = NNCP_MAX_MODES;
+constexpr int kMaxRank = NNCP_MAX_RANK;
+// Rank handled by one partial-MTTKRP launch (four 16-wide MFMA column blocks);
+// larger ranks are processed in column chunks of this size.
+constexpr int kPmMaxCols = 64;
+
+// Khatri-Rao operand description: rows are indexed by a mixed-radix index over
+// `nm` modes, the first listed mode fastest; row q of the operand is the
+// elementwise product of row d_j(q) of each factor (Section II-A).
+//
+// The factors are stored unnormalised during the iteration; `lam` (device, N x R,
+// row stride lam_ld) holds each mode's column norms and every operand column is
+// multiplied by prod_j 1/lam[mode_j][r] (0 where a norm is 0). lam == nullptr
+// means the factors are used as they are.
+struct KrpDesc {
+  const float* f[kMaxModes];   // factor base pointers (column-major, ld = dim)
+  int dim[kMaxModes];
+  int mode[kMaxModes];
+  int nm;
+  const double* lam;
+  int lam_ld;
+};
+
+struct PmArgs {
+  const void* X;
+  int64_t IL, IR;        // X viewed as column-major IL x IR
+  KrpDesc krp;           // contracted modes
+  int R;                 // columns handled by this launch (<= kPmMaxCols)
+  int col0;              // first column (offset into factor columns and colscale)
+  float* T;              // output, column-major, ld = Mtot, columns col0..col0+R-1 -> T + Mtot*r
+  float* partial;        // split-K partials
+  unsigned* counters;    // one per M tile; zero on entry, left zero on exit
+  int nsplit;
+  int64_t kchunk;        // reduction range per split (multiple of the tile depth)
+};
+
+// Plan of one partial-MTTKRP launch (tile shape and split count).
+struct PmLaunch {
+  int side;      // 0 left (m contiguous), 1 right (k contiguous)
+  int dtype;
+  int nb;        // 16-wide column blocks
+  int mtile;     // output rows per work-group
+  int mtiles;
+  int nsplit;
+  int64_t kchunk;
+  size_t partial_floats;
+  int ncounters;
+};
+
+PmLaunch pm_plan(int side, int dtype, int64_t IL, int64_t IR, int R);
+hipError_t pm_launch(const PmLaunch& L, const PmArgs& a, hipStream_t st);
+
+// Multi-TTV kernels ---------------------------------------------------------
+struct MttvArgs {
+  const float* T;       // node temporary: I_a x J x R (column-major)
+  int64_t Ia, J;
+  int R;
+  KrpDesc krp;          // trail: modes a+1..b (first fastest); lead: one mode (a)
+  float* out;
+};
+hipError_t mttv_trail_launch(const MttvArgs& a, hipStream_t st);
+hipError_t mttv_lead_launch(const MttvArgs& a, hipStream_t st);
+
+// Factor update, Gram, lambda, fit -----------------------------------------
+struct UpdateArgs {
+  const float* M;         // I x R MTTKRP result (others normalised)
+  float* W;               // in: stored factor of this mode (scaled by lam_self), out: new W_hat
+  int64_t I;
+  int R;
+  const double* S;        // R x R (device)
+  const double* lam_model;  // current model weights
+  const double* lam_self;   // column norms of W as stored
+  int update;             // NNCP_HALS / NNCP_MU
+};
+hipError_t update_launch(const UpdateArgs& a, hipStream_t st);
+
+struct FinalizeArgs {
+  const float* W;         // I x R new factor (unnormalised)
+  const float* M;         // I x R (for beta) or nullptr
+  int64_t I;
+  int R;
+  int N, mode;
+  double* G;              // N x R x R: normalised Grams (this mode written)
+  double* lam;            // N x R: per-mode column norms (this mode written)
+  double* lam_model;      // R (written when set_model)
+  double* S;              // N x R x R: S^(next) written for next_mode >= 0
+  int next_mode;
+  int set_model;
+  // fit
+  int do_fit;
+  const double* alpha;
+  double* fit_out;        // indexed by *iter_counter
+  int* iter_counter;
+  int fit_capacity;
+  // scratch
+  double* gram_raw;       // optional: W^T W (unnormalised) written here
+  double* partial;        // nchunks x (R*R + 1)
+  unsigned* counter;      // zero on entry, left zero
+  int nchunks;
+  int rows_per_chunk;
+};
+int finalize_chunks(int64_t I, int* rows_per_chunk);
+hipError_t finalize_launch(const FinalizeArgs& a, hipStream_t st);
+
+// lam_model = lam_in * prod_k lam[k]; S[0] = prod_{k != 0} G[k]
+hipError_t init_model_launch(const double* lam_in, double* lam, double* lam_model, const double* G,
+                             double* S, int N, int R, hipStream_t st);
+// H[k] <- H[k] / lam[k] for all columns; lam[k] <- (lam>0 ? 1 : 0); lam_out_dev <- lam_model
+hipError_t normalize_out_launch(float* W, int64_t I, int R, double* lam_self, hipStream_t st);
+
+hipError_t norm_sq_launch(const void* X, int dtype, int64_t n, double* out, double* partial,
+                          unsigned* counter, int nblocks, hipStream_t st);
+int norm_sq_blocks(int64_t n);
+hipError_t quantize_launch(const float* src, void* dst, int dtype, int64_t n, hipStream_t st);
+hipError_t fill_u32_launch(unsigned* p, int64_t n, unsigned v, hipStream_t st);
+hipError_t fill_f64_launch(double* p, int64_t n, double v, hipStream_t st);
+hipError_t copy_f64_launch(double* dst, const double* src, int64_t n, hipStream_t st);
+// lam[k] <- (lam[k] > 0 ? 1 : 0), n entries (after normalize_out)
+hipError_t unit_lambda_launch(double* lam, int64_t n, hipStream_t st);
+
+// Column scale of a Khatri-Rao operand, prod_j 1/lam[mode_j][r] (device code).
+__device__ __forceinline__ double krp_colscale(const KrpDesc& k, int r) {
+  double s = 1.0;
+  if (k.lam) {
+    for (int j = 0; j < k.nm; ++j) {
+      double l = k.lam[(int64_t)k.mode[j] * k.lam_ld + r];
+      s = (l > 0.0) ? s / l : 0.0;
+    }
+  }
+  return s;
+}
+
+}  // namespace nncpk

@@ -1,0 +1,528 @@
+// Bandwidth- and latency-bound kernels of the NNCP iteration:
+//  * multi-TTV (Section IV-A, Figure 2b): R independent matrix-vector products
+//    over the contiguous blocks of a tree-node temporary, FP64 accumulation;
+//  * the NLS-Update of one factor (Section II-B): HALS column sweep or the
+//    multiplicative rule, one lane group per row, FP64 arithmetic;
+//  * Gram matrix, column norms (lambda), the Hadamard product S of the other
+//    modes' Grams, and the relative error from ||X||^2 - 2<X,M> + ||M||^2
+//    (Section IV-B, appendix algorithm), all accumulated in FP64 with a
+//    deterministic two-stage reduction;
+//  * ||X||^2 and FP32 -> BF16/FP16 quantisation of the stored tensor.
+#include "nncp_internal.hpp"
+
+namespace nncpk {
+namespace {
+
+constexpr int NT = 256;
+
+template <typename T>
+__device__ __forceinline__ double to_f64(T v);
+template <>
+__device__ __forceinline__ double to_f64<float>(float v) { return (double)v; }
+template <>
+__device__ __forceinline__ double to_f64<__bf16>(__bf16 v) { return (double)(float)v; }
+template <>
+__device__ __forceinline__ double to_f64<_Float16>(_Float16 v) { return (double)(float)v; }
+
+__device__ __forceinline__ double block_sum(double v, double* sh) {
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+  const int w = threadIdx.x >> 6, l = threadIdx.x & 63;
+  __syncthreads();
+  if (l == 0) sh[w] = v;
+  __syncthreads();
+  double t = 0.0;
+  if (threadIdx.x == 0)
+    for (int i = 0; i < (int)(blockDim.x >> 6); ++i) t += sh[i];
+  return t;  // valid in thread 0
+}
+
+// Returns true in every thread of the last block to arrive (device-scope counter,
+// reset to zero by that block).
+__device__ __forceinline__ bool last_block(unsigned* counter, unsigned total) {
+  __shared__ int s_last;
+  __threadfence();
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    unsigned prev = __hip_atomic_fetch_add(counter, 1u, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT);
+    s_last = (prev == total - 1);
+    if (s_last) __hip_atomic_store(counter, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  }
+  __syncthreads();
+  if (s_last) __threadfence();
+  return s_last;
+}
+
+// --------------------------------------------------------------------------
+// ||X||^2 in FP64
+// --------------------------------------------------------------------------
+template <typename T>
+__global__ __launch_bounds__(NT) void norm_sq_kernel(const T* X, int64_t n, double* out,
+                                                     double* partial, unsigned* counter) {
+  __shared__ double sh[NT / 64];
+  double s = 0.0;
+  const int64_t stride = (int64_t)gridDim.x * NT;
+  for (int64_t i = (int64_t)blockIdx.x * NT + threadIdx.x; i < n; i += stride) {
+    double v = to_f64<T>(X[i]);
+    s += v * v;
+  }
+  double t = block_sum(s, sh);
+  if (threadIdx.x == 0) partial[blockIdx.x] = t;
+  if (!last_block(counter, gridDim.x)) return;
+  double u = 0.0;
+  if (threadIdx.x == 0) {
+    for (unsigned b = 0; b < gridDim.x; ++b) u += partial[b];
+    out[0] = u;
+  }
+}
+
+// --------------------------------------------------------------------------
+// FP32 -> BF16 / FP16 (round to nearest even)
+// --------------------------------------------------------------------------
+template <typename T>
+__global__ __launch_bounds__(NT) void quantize_kernel(const float* src, T* dst, int64_t n) {
+  const int64_t stride = (int64_t)gridDim.x * NT;
+  for (int64_t i = (int64_t)blockIdx.x * NT + threadIdx.x; i < n; i += stride) dst[i] = (T)src[i];
+}
+
+__global__ void fill_u32_kernel(unsigned* p, int64_t n, unsigned v) {
+  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) p[i] = v;
+}
+__global__ void fill_f64_kernel(double* p, int64_t n, double v) {
+  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) p[i] = v;
+}
+__global__ void copy_f64_kernel(double* d, const double* s, int64_t n) {
+  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) d[i] = s[i];
+}
+__global__ void unit_lambda_kernel(double* lam, int64_t n) {
+  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) lam[i] = lam[i] > 0.0 ? 1.0 : 0.0;
+}
+
+// --------------------------------------------------------------------------
+// Multi-TTV, trailing modes: out(i, r) = sum_j T(i, j, r) K(j, r).
+// Block: 64 rows i x 4 interleaved phases of j; K(:, r) formed in LDS chunks.
+// --------------------------------------------------------------------------
+constexpr int TRAIL_KCH = 1024;
+
+__global__ __launch_bounds__(NT) void mttv_trail_kernel(MttvArgs a) {
+  __shared__ double kv[TRAIL_KCH];
+  __shared__ double red[4][64];
+  const int r = blockIdx.y;
+  const int ti = threadIdx.x & 63, ph = threadIdx.x >> 6;
+  const int64_t i = (int64_t)blockIdx.x * 64 + ti;
+  const double scale = krp_colscale(a.krp, r);
+  const float* Tr = a.T + (int64_t)r * a.Ia * a.J;
+  double acc = 0.0;
+  for (int64_t j0 = 0; j0 < a.J; j0 += TRAIL_KCH) {
+    const int cnt = (int)((a.J - j0) < TRAIL_KCH ? (a.J - j0) : TRAIL_KCH);
+    __syncthreads();
+    for (int e = threadIdx.x; e < cnt; e += NT) {
+      uint32_t rem = (uint32_t)(j0 + e);
+      double p = scale;
+      for (int m = 0; m < a.krp.nm; ++m) {
+        uint32_t d = (uint32_t)a.krp.dim[m];
+        uint32_t q = rem / d;
+        p *= (double)a.krp.f[m][(int64_t)(rem - q * d) + (int64_t)a.krp.dim[m] * r];
+        rem = q;
+      }
+      kv[e] = p;
+    }
+    __syncthreads();
+    if (i < a.Ia) {
+      const float* base = Tr + i + a.Ia * j0;
+      int e = ph;
+      for (; e + 12 < cnt; e += 16) {
+        double t0 = base[a.Ia * e], t1 = base[a.Ia * (e + 4)];
+        double t2 = base[a.Ia * (e + 8)], t3 = base[a.Ia * (e + 12)];
+        acc += t0 * kv[e];
+        acc += t1 * kv[e + 4];
+        acc += t2 * kv[e + 8];
+        acc += t3 * kv[e + 12];
+      }
+      for (; e < cnt; e += 4) acc += (double)base[a.Ia * e] * kv[e];
+    }
+  }
+  red[ph][ti] = acc;
+  __syncthreads();
+  if (ph == 0 && i < a.Ia) {
+    double s = red[0][ti] + red[1][ti] + red[2][ti] + red[3][ti];
+    a.out[i + a.Ia * r] = (float)s;
+  }
+}
+
+// --------------------------------------------------------------------------
+// Multi-TTV, leading mode: out(j, r) = sum_i T(i, j, r) H(i, r), one lane group
+// of GS lanes per output (contiguous dot product, shuffle reduction).
+// --------------------------------------------------------------------------
+template <int GS>
+__global__ __launch_bounds__(NT) void mttv_lead_kernel(MttvArgs a) {
+  constexpr int OPB = NT / GS;
+  const int g = threadIdx.x / GS, p = threadIdx.x % GS;
+  const int64_t o = (int64_t)blockIdx.x * OPB + g;  // output index j + J*r
+  const int64_t total = a.J * a.R;
+  double acc = 0.0;
+  int r = 0;
+  if (o < total) {
+    r = (int)(o / a.J);
+    const int64_t j = o - (int64_t)r * a.J;
+    const float* Tc = a.T + a.Ia * (j + a.J * (int64_t)r);
+    const float* Hc = a.krp.f[0] + a.Ia * (int64_t)r;
+    for (int64_t i = p; i < a.Ia; i += GS) acc += (double)Tc[i] * (double)Hc[i];
+  }
+#pragma unroll
+  for (int off = GS / 2; off > 0; off >>= 1) acc += __shfl_xor(acc, off, GS);
+  if (p == 0 && o < total) a.out[o] = (float)(acc * krp_colscale(a.krp, r));
+}
+
+// --------------------------------------------------------------------------
+// NLS update. A group of GS lanes owns one row; lane p holds columns
+// k = p + GS*v (v < VPL) of the warm start w, the MTTKRP row m and the running
+// product g = w S. HALS visits r = 0..R-1 in order (Gauss-Seidel): the owner of
+// column r computes the new value, broadcasts the change d, and every lane
+// updates g += d S(r, :). S lives in LDS (FP64).
+// --------------------------------------------------------------------------
+template <int GS, int VPL>
+__global__ __launch_bounds__(NT) void update_kernel(UpdateArgs a) {
+  extern __shared__ double Sl[];
+  const int R = a.R;
+  for (int e = threadIdx.x; e < R * R; e += NT) Sl[e] = a.S[e];
+  __syncthreads();
+  constexpr int RPB = NT / GS;  // rows per block
+  const int grp = threadIdx.x / GS, p = threadIdx.x % GS;
+  const int64_t row = (int64_t)blockIdx.x * RPB + grp;
+  const bool active = row < a.I;
+  const int64_t rr = active ? row : 0;
+
+  double w[VPL], m[VPL], g[VPL];
+#pragma unroll
+  for (int v = 0; v < VPL; ++v) {
+    const int k = p + GS * v;
+    w[v] = 0.0;
+    m[v] = 0.0;
+    g[v] = 0.0;
+    if (k < R) {
+      const double ls = a.lam_self[k];
+      const double f = ls > 0.0 ? a.lam_model[k] / ls : 0.0;
+      w[v] = (double)a.W[rr + a.I * k] * f;
+      m[v] = (double)a.M[rr + a.I * k];
+    }
+  }
+  // g = w S (with the current w)
+  for (int r = 0; r < R; ++r) {
+    const int owner = r % GS, slot = r / GS;
+    double wr = 0.0;
+#pragma unroll
+    for (int v = 0; v < VPL; ++v)
+      if (v == slot) wr = w[v];
+    wr = __shfl(wr, owner, GS);
+#pragma unroll
+    for (int v = 0; v < VPL; ++v) {
+      const int k = p + GS * v;
+      if (k < R) g[v] += wr * Sl[r * R + k];
+    }
+  }
+  if (a.update == NNCP_HALS) {
+    for (int r = 0; r < R; ++r) {
+      const int owner = r % GS, slot = r / GS;
+      double d = 0.0;
+      if (p == owner) {
+#pragma unroll
+        for (int v = 0; v < VPL; ++v)
+          if (v == slot) {
+            const double srr = Sl[r * R + r];
+            double wn = 0.0;
+            if (srr > 0.0) {
+              wn = w[v] + (m[v] - g[v]) / srr;
+              wn = wn > 0.0 ? wn : 0.0;
+            }
+            d = wn - w[v];
+            w[v] = wn;
+          }
+      }
+      d = __shfl(d, owner, GS);
+#pragma unroll
+      for (int v = 0; v < VPL; ++v) {
+        const int k = p + GS * v;
+        if (k < R) g[v] += d * Sl[r * R + k];
+      }
+    }
+  } else {
+#pragma unroll
+    for (int v = 0; v < VPL; ++v) {
+      const double den = g[v] > 1e-16 ? g[v] : 1e-16;
+      w[v] = w[v] * m[v] / den;
+    }
+  }
+  if (active) {
+#pragma unroll
+    for (int v = 0; v < VPL; ++v) {
+      const int k = p + GS * v;
+      if (k < R) a.W[row + a.I * k] = (float)w[v];
+    }
+  }
+}
+
+// --------------------------------------------------------------------------
+// Finalize one mode after its update: G_hat = W^T W (FP64) over row chunks,
+// then the last block forms lambda = sqrt(diag G_hat), the normalised Gram,
+// optionally the model weights, S for the next mode, and the fit.
+// --------------------------------------------------------------------------
+constexpr int FIN_SUB = 32;  // rows staged in LDS at a time
+
+__global__ __launch_bounds__(NT) void finalize_kernel(FinalizeArgs a) {
+  extern __shared__ double fl[];  // FIN_SUB x R rows, then R*R scratch
+  __shared__ double sh[NT / 64];
+  const int R = a.R, RR = R * R;
+  const int64_t r0 = (int64_t)blockIdx.x * a.rows_per_chunk;
+  int64_t r1 = r0 + a.rows_per_chunk;
+  if (r1 > a.I) r1 = a.I;
+  double* part = a.partial + (size_t)blockIdx.x * (RR + 1);
+
+  // each thread owns entries e = tid, tid + NT, ... of the R x R Gram
+  constexpr int MAXE = (kMaxRank * kMaxRank + NT - 1) / NT;
+  double acc[MAXE];
+#pragma unroll
+  for (int q = 0; q < MAXE; ++q) acc[q] = 0.0;
+  double bsum = 0.0;
+  for (int64_t s0 = r0; s0 < r1; s0 += FIN_SUB) {
+    const int cnt = (int)((r1 - s0) < FIN_SUB ? (r1 - s0) : FIN_SUB);
+    __syncthreads();
+    for (int e = threadIdx.x; e < cnt * R; e += NT) {
+      const int k = e / cnt, rw = e - k * cnt;
+      const double wv = (double)a.W[s0 + rw + a.I * k];
+      fl[rw * R + k] = wv;
+      if (a.do_fit && a.M) bsum += wv * (double)a.M[s0 + rw + a.I * k];
+    }
+    __syncthreads();
+#pragma unroll
+    for (int q = 0; q < MAXE; ++q) {
+      const int e = threadIdx.x + q * NT;
+      if (e < RR) {
+        const int x = e / R, y = e - x * R;
+        double s = 0.0;
+        for (int rw = 0; rw < cnt; ++rw) s += fl[rw * R + x] * fl[rw * R + y];
+        acc[q] += s;
+      }
+    }
+  }
+#pragma unroll
+  for (int q = 0; q < MAXE; ++q) {
+    const int e = threadIdx.x + q * NT;
+    if (e < RR) part[e] = acc[q];
+  }
+  double bt = block_sum(bsum, sh);
+  if (threadIdx.x == 0) part[RR] = bt;
+  if (!last_block(a.counter, gridDim.x)) return;
+
+  // ---- last block: reduce chunks in order ----
+  double* Gh = fl;  // R*R scratch (reuses the row stage)
+  for (int e = threadIdx.x; e < RR + 1; e += NT) {
+    double s = 0.0;
+    for (int c = 0; c < a.nchunks; ++c) s += a.partial[(size_t)c * (RR + 1) + e];
+    Gh[e] = s;
+  }
+  __syncthreads();
+  if (a.gram_raw)
+    for (int e = threadIdx.x; e < RR; e += NT) a.gram_raw[e] = Gh[e];
+  double* lamm = a.lam + (int64_t)a.mode * R;
+  for (int k = threadIdx.x; k < R; k += NT) {
+    const double l = sqrt(Gh[k * R + k]);
+    lamm[k] = l;
+    if (a.set_model) a.lam_model[k] = l;
+  }
+  double* Gm = a.G + (int64_t)a.mode * RR;
+  for (int e = threadIdx.x; e < RR; e += NT) {
+    const int x = e / R, y = e - x * R;
+    const double lx = sqrt(Gh[x * R + x]), ly = sqrt(Gh[y * R + y]);
+    Gm[e] = (lx > 0.0 && ly > 0.0) ? Gh[e] / (lx * ly) : 0.0;
+  }
+  __threadfence_block();
+  __syncthreads();
+  if (a.do_fit) {
+    // gamma = 1^T (S^(mode) * G_hat) 1 ; S^(mode) is the Hadamard of the others.
+    const double* Sm = a.S + (int64_t)a.mode * RR;
+    double gp = 0.0;
+    for (int e = threadIdx.x; e < RR; e += NT) gp += Sm[e] * Gh[e];
+    double gamma = block_sum(gp, sh);
+    if (threadIdx.x == 0) {
+      const double alpha = a.alpha[0];
+      const double beta = Gh[RR];
+      double num = alpha - 2.0 * beta + gamma;
+      num = num > 0.0 ? num : 0.0;
+      const double eps = alpha > 0.0 ? sqrt(num / alpha) : 0.0;
+      const int it = *a.iter_counter;
+      if (it < a.fit_capacity) a.fit_out[it] = 1.0 - eps;
+      *a.iter_counter = it + 1;
+    }
+    __syncthreads();
+  }
+  if (a.next_mode >= 0) {
+    double* Sn = a.S + (int64_t)a.next_mode * RR;
+    for (int e = threadIdx.x; e < RR; e += NT) {
+      double s = 1.0;
+      for (int k = 0; k < a.N; ++k)
+        if (k != a.next_mode) s *= a.G[(int64_t)k * RR + e];
+      Sn[e] = s;
+    }
+  }
+}
+
+__global__ void init_model_kernel(const double* lam_in, const double* lam, double* lam_model,
+                                  const double* G, double* S, int N, int R) {
+  for (int k = threadIdx.x; k < R; k += blockDim.x) {
+    double l = lam_in ? lam_in[k] : 1.0;
+    for (int n = 0; n < N; ++n) l *= lam[(int64_t)n * R + k];
+    lam_model[k] = l;
+  }
+  const int RR = R * R;
+  for (int e = threadIdx.x; e < RR; e += blockDim.x) {
+    double s = 1.0;
+    for (int n = 1; n < N; ++n) s *= G[(int64_t)n * RR + e];
+    S[e] = s;
+  }
+}
+
+__global__ void normalize_out_kernel(float* W, int64_t I, int R, const double* lam) {
+  const int64_t n = I * R;
+  for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < n;
+       e += (int64_t)gridDim.x * blockDim.x) {
+    const int k = (int)(e / I);
+    const double l = lam[k];
+    W[e] = l > 0.0 ? (float)((double)W[e] / l) : 0.f;
+  }
+}
+
+inline unsigned grid_for(int64_t n, int threads, unsigned cap = 65535u * 32u) {
+  int64_t g = (n + threads - 1) / threads;
+  if (g < 1) g = 1;
+  if (g > (int64_t)cap) g = cap;
+  return (unsigned)g;
+}
+
+}  // namespace
+
+int norm_sq_blocks(int64_t n) {
+  int64_t b = (n + NT * 8 - 1) / (NT * 8);
+  if (b < 1) b = 1;
+  if (b > 1024) b = 1024;
+  return (int)b;
+}
+
+hipError_t norm_sq_launch(const void* X, int dtype, int64_t n, double* out, double* partial,
+                          unsigned* counter, int nblocks, hipStream_t st) {
+  dim3 g(nblocks), b(NT);
+  switch (dtype) {
+    case NNCP_F32: hipLaunchKernelGGL(norm_sq_kernel<float>, g, b, 0, st, (const float*)X, n, out, partial, counter); break;
+    case NNCP_BF16: hipLaunchKernelGGL(norm_sq_kernel<__bf16>, g, b, 0, st, (const __bf16*)X, n, out, partial, counter); break;
+    case NNCP_F16: hipLaunchKernelGGL(norm_sq_kernel<_Float16>, g, b, 0, st, (const _Float16*)X, n, out, partial, counter); break;
+    default: return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
+}
+
+hipError_t quantize_launch(const float* src, void* dst, int dtype, int64_t n, hipStream_t st) {
+  dim3 g(grid_for(n, NT * 4, 8192)), b(NT);
+  if (dtype == NNCP_BF16) hipLaunchKernelGGL(quantize_kernel<__bf16>, g, b, 0, st, src, (__bf16*)dst, n);
+  else if (dtype == NNCP_F16) hipLaunchKernelGGL(quantize_kernel<_Float16>, g, b, 0, st, src, (_Float16*)dst, n);
+  else return hipErrorInvalidValue;
+  return hipGetLastError();
+}
+
+hipError_t fill_u32_launch(unsigned* p, int64_t n, unsigned v, hipStream_t st) {
+  if (n <= 0) return hipSuccess;
+  hipLaunchKernelGGL(fill_u32_kernel, dim3(grid_for(n, NT)), dim3(NT), 0, st, p, n, v);
+  return hipGetLastError();
+}
+hipError_t fill_f64_launch(double* p, int64_t n, double v, hipStream_t st) {
+  if (n <= 0) return hipSuccess;
+  hipLaunchKernelGGL(fill_f64_kernel, dim3(grid_for(n, NT)), dim3(NT), 0, st, p, n, v);
+  return hipGetLastError();
+}
+hipError_t copy_f64_launch(double* d, const double* s, int64_t n, hipStream_t st) {
+  if (n <= 0) return hipSuccess;
+  hipLaunchKernelGGL(copy_f64_kernel, dim3(grid_for(n, NT)), dim3(NT), 0, st, d, s, n);
+  return hipGetLastError();
+}
+hipError_t unit_lambda_launch(double* lam, int64_t n, hipStream_t st) {
+  if (n <= 0) return hipSuccess;
+  hipLaunchKernelGGL(unit_lambda_kernel, dim3(grid_for(n, NT)), dim3(NT), 0, st, lam, n);
+  return hipGetLastError();
+}
+
+hipError_t mttv_trail_launch(const MttvArgs& a, hipStream_t st) {
+  if (a.Ia <= 0 || a.R <= 0) return hipSuccess;
+  dim3 g((unsigned)((a.Ia + 63) / 64), a.R), b(NT);
+  hipLaunchKernelGGL(mttv_trail_kernel, g, b, 0, st, a);
+  return hipGetLastError();
+}
+
+hipError_t mttv_lead_launch(const MttvArgs& a, hipStream_t st) {
+  const int64_t outputs = a.J * a.R;
+  if (outputs <= 0) return hipSuccess;
+  int gs = 4;
+  while (gs < 64 && gs < a.Ia) gs <<= 1;
+  const int64_t blocks = (outputs * gs + NT - 1) / NT;
+  dim3 g((unsigned)blocks), b(NT);
+  switch (gs) {
+    case 4: hipLaunchKernelGGL(mttv_lead_kernel<4>, g, b, 0, st, a); break;
+    case 8: hipLaunchKernelGGL(mttv_lead_kernel<8>, g, b, 0, st, a); break;
+    case 16: hipLaunchKernelGGL(mttv_lead_kernel<16>, g, b, 0, st, a); break;
+    case 32: hipLaunchKernelGGL(mttv_lead_kernel<32>, g, b, 0, st, a); break;
+    default: hipLaunchKernelGGL(mttv_lead_kernel<64>, g, b, 0, st, a); break;
+  }
+  return hipGetLastError();
+}
+
+hipError_t update_launch(const UpdateArgs& a, hipStream_t st) {
+  if (a.I <= 0) return hipSuccess;
+  const size_t lds = (size_t)a.R * a.R * sizeof(double);
+  int gs = 16;
+  while (gs < 64 && gs < a.R) gs <<= 1;
+  const int vpl = (a.R + gs - 1) / gs;
+  const int rpb = NT / gs;
+  dim3 g((unsigned)((a.I + rpb - 1) / rpb)), b(NT);
+  if (gs == 16) hipLaunchKernelGGL((update_kernel<16, 1>), g, b, lds, st, a);
+  else if (gs == 32) hipLaunchKernelGGL((update_kernel<32, 1>), g, b, lds, st, a);
+  else if (vpl == 1) hipLaunchKernelGGL((update_kernel<64, 1>), g, b, lds, st, a);
+  else hipLaunchKernelGGL((update_kernel<64, 2>), g, b, lds, st, a);
+  return hipGetLastError();
+}
+
+int finalize_chunks(int64_t I, int* rows_per_chunk) {
+  int64_t chunks = (I + 63) / 64;
+  if (chunks > 16) chunks = 16;
+  if (chunks < 1) chunks = 1;
+  int64_t rpc = (I + chunks - 1) / chunks;
+  if (rpc < 1) rpc = 1;
+  chunks = (I + rpc - 1) / rpc;
+  if (chunks < 1) chunks = 1;
+  *rows_per_chunk = (int)rpc;
+  return (int)chunks;
+}
+
+hipError_t finalize_launch(const FinalizeArgs& a, hipStream_t st) {
+  size_t lds = (size_t)FIN_SUB * a.R * sizeof(double);
+  const size_t need = ((size_t)a.R * a.R + 1) * sizeof(double);
+  if (need > lds) lds = need;
+  hipLaunchKernelGGL(finalize_kernel, dim3(a.nchunks), dim3(NT), lds, st, a);
+  return hipGetLastError();
+}
+
+hipError_t init_model_launch(const double* lam_in, double* lam, double* lam_model, const double* G,
+                             double* S, int N, int R, hipStream_t st) {
+  hipLaunchKernelGGL(init_model_kernel, dim3(1), dim3(NT), 0, st, lam_in, lam, lam_model, G, S, N, R);
+  return hipGetLastError();
+}
+
+hipError_t normalize_out_launch(float* W, int64_t I, int R, double* lam_self, hipStream_t st) {
+  const int64_t n = I * R;
+  if (n <= 0) return hipSuccess;
+  hipLaunchKernelGGL(normalize_out_kernel, dim3(grid_for(n, NT, 4096)), dim3(NT), 0, st, W, I, R,
+                     (const double*)lam_self);
+  return hipGetLastError();
+}
+
+}  // namespace nncpk

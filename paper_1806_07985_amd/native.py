@@ -1,0 +1,328 @@
+"""ctypes binding of the C ABI in include/nncp.h (argument marshalling only).
+
+Every computation runs in the HIP library ``lib/libnncp.so``; this module only
+turns torch device tensors into pointers and sizes. If the library is missing,
+``lib()`` raises: there is no fallback path.
+
+Layout conventions (see include/nncp.h): a tensor of shape (I_1, ..., I_N) is
+passed as a flat device tensor in mode-1-fastest order, and a factor matrix
+I_n x R (column-major) as a contiguous torch tensor of shape (R, I_n).
+"""
+
+from __future__ import annotations
+
+import ctypes
+import os
+from typing import List, Optional, Sequence
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "lib", "libnncp.so")
+
+NNCP_OK = 0
+HALS, MU = 0, 1
+F32, BF16, F16 = 0, 1, 2
+_UPDATE = {"hals": HALS, "mu": MU}
+_DTYPE = {"f32": F32, "bf16": BF16, "f16": F16}
+
+c_i64p = ctypes.POINTER(ctypes.c_int64)
+c_dp = ctypes.POINTER(ctypes.c_double)
+c_vp = ctypes.c_void_p
+
+
+class Options(ctypes.Structure):
+    _fields_ = [("split", ctypes.c_int), ("no_record_fit", ctypes.c_int), ("no_graph", ctypes.c_int),
+                ("phase_timers", ctypes.c_int), ("tol", ctypes.c_double),
+                ("reserved", ctypes.c_int * 8)]
+
+
+class NNCPError(RuntimeError):
+    def __init__(self, status: int, what: str):
+        msg = _lib.nncp_strerror(status).decode() if _lib is not None else str(status)
+        super().__init__(f"{what}: {msg} ({status})")
+        self.status = status
+
+
+_lib = None
+
+
+def _declare(L):
+    L.nncp_strerror.restype = ctypes.c_char_p
+    L.nncp_strerror.argtypes = [ctypes.c_int]
+    L.nncp_version.restype = ctypes.c_int
+    L.nncp_workspace_bytes.restype = ctypes.c_size_t
+    L.nncp_workspace_bytes.argtypes = [ctypes.c_int, c_i64p, ctypes.c_int, ctypes.c_int, ctypes.POINTER(Options)]
+    L.nncp.restype = ctypes.c_int
+    L.nncp.argtypes = [c_vp, ctypes.c_int, ctypes.c_int, c_i64p, ctypes.c_int, ctypes.c_int, ctypes.c_int,
+                       ctypes.POINTER(c_vp), c_dp, c_dp, ctypes.POINTER(ctypes.c_int), c_vp, ctypes.c_size_t,
+                       ctypes.POINTER(Options), c_vp]
+    L.nncp_plan_create.restype = ctypes.c_int
+    L.nncp_plan_create.argtypes = [ctypes.POINTER(c_vp), c_vp, ctypes.c_int, ctypes.c_int, c_i64p, ctypes.c_int,
+                                   ctypes.c_int, ctypes.POINTER(c_vp), c_dp, c_vp, ctypes.c_size_t,
+                                   ctypes.POINTER(Options), c_vp]
+    L.nncp_plan_run.restype = ctypes.c_int
+    L.nncp_plan_run.argtypes = [c_vp, ctypes.c_int, c_dp, ctypes.POINTER(ctypes.c_int)]
+    L.nncp_plan_finish.restype = ctypes.c_int
+    L.nncp_plan_finish.argtypes = [c_vp, c_dp]
+    L.nncp_plan_phase_ms.restype = ctypes.c_int
+    L.nncp_plan_phase_ms.argtypes = [c_vp, c_dp]
+    L.nncp_plan_destroy.restype = ctypes.c_int
+    L.nncp_plan_destroy.argtypes = [c_vp]
+    L.nncp_quantize.restype = ctypes.c_int
+    L.nncp_quantize.argtypes = [c_vp, c_vp, ctypes.c_int, ctypes.c_int64, c_vp]
+    L.nncp_norm_sq.restype = ctypes.c_int
+    L.nncp_norm_sq.argtypes = [c_vp, ctypes.c_int, ctypes.c_int64, c_vp, c_vp]
+    L.nncp_partial_mttkrp.restype = ctypes.c_int
+    L.nncp_partial_mttkrp.argtypes = [c_vp, ctypes.c_int, ctypes.c_int, c_i64p, ctypes.c_int, ctypes.c_int,
+                                      ctypes.POINTER(c_vp), ctypes.c_int, c_vp, c_vp]
+    L.nncp_mttv.restype = ctypes.c_int
+    L.nncp_mttv.argtypes = [c_vp, ctypes.c_int, c_i64p, ctypes.c_int, ctypes.POINTER(c_vp), ctypes.c_int, c_vp,
+                            c_vp]
+    L.nncp_mttkrp.restype = ctypes.c_int
+    L.nncp_mttkrp.argtypes = [c_vp, ctypes.c_int, ctypes.c_int, c_i64p, ctypes.c_int, ctypes.c_int,
+                              ctypes.POINTER(c_vp), ctypes.c_int, c_vp, c_vp]
+    L.nncp_gram.restype = ctypes.c_int
+    L.nncp_gram.argtypes = [c_vp, ctypes.c_int64, ctypes.c_int, c_vp, c_vp]
+    L.nncp_nls_update.restype = ctypes.c_int
+    L.nncp_nls_update.argtypes = [c_vp, c_vp, ctypes.c_int64, ctypes.c_int, c_vp, c_vp, ctypes.c_int, c_vp, c_vp]
+
+
+def lib():
+    """Load the built library (raises if it was not built)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError(f"{LIB_PATH} is missing: build it with __graft_entry__.build() "
+                               "(python -m paper_1806_07985_amd.build)")
+        L = ctypes.CDLL(LIB_PATH)
+        _declare(L)
+        _lib = L
+    return _lib
+
+
+def _check(status: int, what: str):
+    if status != NNCP_OK:
+        raise NNCPError(status, what)
+
+
+# ---------------------------------------------------------------------------
+# marshalling helpers
+# ---------------------------------------------------------------------------
+
+def _ptr(t) -> int:
+    return int(t.data_ptr())
+
+
+def _stream(stream=None) -> int:
+    import torch
+    s = stream if stream is not None else torch.cuda.current_stream()
+    return int(s.cuda_stream)
+
+
+def _dims(dims: Sequence[int]):
+    arr = (ctypes.c_int64 * len(dims))(*[int(d) for d in dims])
+    return arr
+
+
+def _ptr_array(tensors) -> "ctypes.Array":
+    return (c_vp * len(tensors))(*[_ptr(t) for t in tensors])
+
+
+def _dtype_code(t) -> int:
+    import torch
+    m = {torch.float32: F32, torch.bfloat16: BF16, torch.float16: F16}
+    if t.dtype not in m:
+        raise TypeError(f"unsupported tensor dtype {t.dtype}")
+    return m[t.dtype]
+
+
+def _need(t, numel: int, dtype=None, name="tensor"):
+    import torch
+    if not t.is_cuda:
+        raise ValueError(f"{name} must be a device tensor")
+    if not t.is_contiguous():
+        raise ValueError(f"{name} must be contiguous")
+    if t.numel() != numel:
+        raise ValueError(f"{name} has {t.numel()} elements, expected {numel}")
+    if dtype is not None and t.dtype != dtype:
+        raise ValueError(f"{name} must be {dtype}")
+
+
+def tensor_to_device(X: np.ndarray, dtype=None, device="cuda"):
+    """Flat device copy of a numpy tensor in mode-1-fastest order."""
+    import torch
+    flat = np.asarray(X).ravel(order="F")
+    t = torch.from_numpy(np.ascontiguousarray(flat))
+    if dtype is not None:
+        t = t.to(dtype)
+    return t.to(device)
+
+
+def factor_to_device(H: np.ndarray, device="cuda"):
+    """I x R numpy factor -> device float32 (R, I) tensor (column-major I x R)."""
+    import torch
+    return torch.from_numpy(np.ascontiguousarray(np.asarray(H, dtype=np.float32).T)).to(device)
+
+
+def factor_to_host(t) -> np.ndarray:
+    """Device (R, I) factor -> I x R numpy float64."""
+    return t.detach().cpu().numpy().astype(np.float64).T.copy()
+
+
+# ---------------------------------------------------------------------------
+# entry points
+# ---------------------------------------------------------------------------
+
+def version() -> int:
+    return lib().nncp_version()
+
+
+def workspace_bytes(dims, R, dtype="f32", split=0) -> int:
+    o = Options(split=split)
+    return int(lib().nncp_workspace_bytes(len(dims), _dims(dims), R, _DTYPE[dtype], ctypes.byref(o)))
+
+
+def nncp(X, dims, R, iters, H, lam=None, update="hals", split=0, graph=True, record_fit=True,
+         tol=0.0, workspace=None, stream=None):
+    """Run the full driver. H: list of device (R, I_n) float32 tensors, updated in place.
+
+    Returns dict(fit=np.ndarray, lam=np.ndarray, iters_done=int).
+    """
+    import torch
+    L = lib()
+    N = len(dims)
+    I = int(np.prod(dims))
+    _need(X, I, name="X")
+    for n, h in enumerate(H):
+        _need(h, dims[n] * R, torch.float32, name=f"H[{n}]")
+    lam_arr = (ctypes.c_double * R)(*(np.ones(R) if lam is None else np.asarray(lam, dtype=np.float64)))
+    fit = (ctypes.c_double * max(1, iters))()
+    done = ctypes.c_int(0)
+    o = Options(split=split, no_record_fit=0 if record_fit else 1, no_graph=0 if graph else 1, tol=tol)
+    ws_ptr, ws_bytes = (None, 0)
+    if workspace is not None:
+        ws_ptr, ws_bytes = _ptr(workspace), workspace.numel() * workspace.element_size()
+    st = L.nncp(_ptr(X), _dtype_code(X), N, _dims(dims), R, iters, _UPDATE[update], _ptr_array(H),
+                lam_arr, fit, ctypes.byref(done), ws_ptr, ws_bytes, ctypes.byref(o), _stream(stream))
+    _check(st, "nncp")
+    n_fit = done.value if record_fit else 1
+    return dict(fit=np.array(fit[:n_fit]), lam=np.array(lam_arr[:]), iters_done=done.value)
+
+
+class Plan:
+    """Persistent driver state: create once, run repeatedly, finish to normalise."""
+
+    def __init__(self, X, dims, R, H, lam=None, update="hals", split=0, graph=True, phase_timers=False,
+                 workspace=None, stream=None):
+        import torch
+        L = lib()
+        self.dims, self.R, self.H, self.X = list(dims), R, list(H), X
+        I = int(np.prod(dims))
+        _need(X, I, name="X")
+        for n, h in enumerate(H):
+            _need(h, dims[n] * R, torch.float32, name=f"H[{n}]")
+        lam_arr = None
+        if lam is not None:
+            lam_arr = (ctypes.c_double * R)(*np.asarray(lam, dtype=np.float64))
+        o = Options(split=split, no_graph=0 if graph else 1, phase_timers=1 if phase_timers else 0)
+        self._ws = workspace
+        if workspace is None:
+            nbytes = workspace_bytes(dims, R, "f32", split)
+            self._ws = torch.empty(nbytes, dtype=torch.uint8, device=X.device)
+        handle = c_vp()
+        st = L.nncp_plan_create(ctypes.byref(handle), _ptr(X), _dtype_code(X), len(dims), _dims(dims), R,
+                                _UPDATE[update], _ptr_array(H), lam_arr, _ptr(self._ws),
+                                self._ws.numel(), ctypes.byref(o), _stream(stream))
+        _check(st, "nncp_plan_create")
+        self._h = handle
+
+    def run(self, iters: int) -> np.ndarray:
+        fit = (ctypes.c_double * max(1, iters))()
+        done = ctypes.c_int(0)
+        _check(lib().nncp_plan_run(self._h, iters, fit, ctypes.byref(done)), "nncp_plan_run")
+        return np.array(fit[:done.value])
+
+    def finish(self) -> np.ndarray:
+        lam = (ctypes.c_double * self.R)()
+        _check(lib().nncp_plan_finish(self._h, lam), "nncp_plan_finish")
+        return np.array(lam[:])
+
+    def phase_ms(self) -> dict:
+        ms = (ctypes.c_double * 6)()
+        _check(lib().nncp_plan_phase_ms(self._h, ms), "nncp_plan_phase_ms")
+        return dict(zip(["pm", "mttv", "nls", "gram", "err", "total"], list(ms)))
+
+    def close(self):
+        if getattr(self, "_h", None):
+            lib().nncp_plan_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def quantize(src, dtype: str, stream=None):
+    import torch
+    tdt = {"bf16": torch.bfloat16, "f16": torch.float16}[dtype]
+    _need(src, src.numel(), torch.float32, name="src")
+    dst = torch.empty(src.numel(), dtype=tdt, device=src.device)
+    _check(lib().nncp_quantize(_ptr(src), _ptr(dst), _DTYPE[dtype], src.numel(), _stream(stream)), "nncp_quantize")
+    return dst
+
+
+def norm_sq(X, stream=None) -> float:
+    import torch
+    out = torch.zeros(1, dtype=torch.float64, device=X.device)
+    _check(lib().nncp_norm_sq(_ptr(X), _dtype_code(X), X.numel(), _ptr(out), _stream(stream)), "nncp_norm_sq")
+    return float(out.item())
+
+
+def partial_mttkrp(X, dims, s, side, H, R, stream=None):
+    import torch
+    IL = int(np.prod(dims[:s]))
+    IR = int(np.prod(dims[s:]))
+    rows = IL if side == 0 else IR
+    T = torch.empty((R, rows), dtype=torch.float32, device=X.device)
+    _check(lib().nncp_partial_mttkrp(_ptr(X), _dtype_code(X), len(dims), _dims(dims), s, side, _ptr_array(H), R,
+                                     _ptr(T), _stream(stream)), "nncp_partial_mttkrp")
+    return T
+
+
+def mttv(T, node_dims, kind, Hf, R, stream=None):
+    import torch
+    if kind == 0:
+        out = torch.empty((R, node_dims[0]), dtype=torch.float32, device=T.device)
+    else:
+        out = torch.empty((R, int(np.prod(node_dims[1:]))), dtype=torch.float32, device=T.device)
+    _check(lib().nncp_mttv(_ptr(T), len(node_dims), _dims(node_dims), kind, _ptr_array(Hf), R, _ptr(out),
+                           _stream(stream)), "nncp_mttv")
+    return out
+
+
+def mttkrp(X, dims, s, n, H, R, stream=None):
+    import torch
+    M = torch.empty((R, dims[n]), dtype=torch.float32, device=X.device)
+    _check(lib().nncp_mttkrp(_ptr(X), _dtype_code(X), len(dims), _dims(dims), s, n, _ptr_array(H), R, _ptr(M),
+                             _stream(stream)), "nncp_mttkrp")
+    return M
+
+
+def gram(H, I, R, stream=None):
+    import torch
+    G = torch.empty((R, R), dtype=torch.float64, device=H.device)
+    _check(lib().nncp_gram(_ptr(H), I, R, _ptr(G), _stream(stream)), "nncp_gram")
+    return G
+
+
+def nls_update(M, H, I, R, S, lam, update="hals", stream=None):
+    """In place: H <- normalised update; returns (lam, G) as device tensors."""
+    import torch
+    lam_t = lam.clone()
+    G = torch.empty((R, R), dtype=torch.float64, device=H.device)
+    _check(lib().nncp_nls_update(_ptr(M), _ptr(H), I, R, _ptr(S), _ptr(lam_t), _UPDATE[update], _ptr(G),
+                                 _stream(stream)), "nncp_nls_update")
+    return lam_t, G

@@ -1,0 +1,136 @@
+"""End-to-end parity of the GPU NNCP driver with the FP64 oracle.
+
+The tolerance in FP32 mode is 1e-5 relative on every factor (Frobenius norm of
+the difference of the unit-column factors over the norm of the oracle's), on
+lambda and on every recorded fit. The oracle runs on exactly the FP32 tensor
+and FP32 starting factors the GPU receives.
+"""
+
+import numpy as np
+import pytest
+
+import oracle as O
+from paper_1806_07985_amd import inputs
+
+pytestmark = pytest.mark.gpu
+
+TOL = 1e-5
+
+
+def _run_gpu(X32, H0, R, iters, update="hals", split=0, graph=True, lam=None):
+    from paper_1806_07985_amd import native
+    Xd = native.tensor_to_device(X32)
+    Hd = [native.factor_to_device(h) for h in H0]
+    out = native.nncp(Xd, list(X32.shape), R, iters, Hd, lam=lam, update=update, split=split, graph=graph)
+    out["H"] = [native.factor_to_host(h) for h in Hd]
+    return out
+
+
+def _run_oracle(X32, H0, iters, update="hals", lam=None):
+    H32 = [np.asarray(h, dtype=np.float32).astype(np.float64) for h in H0]
+    return O.nncp(X32.astype(np.float64), H32, iters, update=update, lam0=lam)
+
+
+def _compare(g, o, tol=TOL, fits=True):
+    errs = []
+    for Hg, Ho in zip(g["H"], o["H"]):
+        errs.append(np.linalg.norm(Hg - Ho) / np.linalg.norm(Ho))
+    lam_err = np.max(np.abs(g["lam"] - o["lam"]) / np.abs(o["lam"]))
+    fit_err = np.max(np.abs(np.asarray(g["fit"]) - np.asarray(o["fit"])) / np.abs(np.asarray(o["fit"]))) if fits else 0.0
+    print(f"factor errs {['%.2e' % e for e in errs]} lam {lam_err:.2e} fit {fit_err:.2e}", flush=True)
+    assert max(errs) <= tol, errs
+    assert lam_err <= tol, lam_err
+    assert fit_err <= tol, fit_err
+
+
+def test_one_outer_iteration(gpu_lib):
+    dims, R = (30, 24, 20, 12), 6
+    X, _ = inputs.planted(dims, R, 0.01, seed=101, dtype=np.float32)
+    H0 = [h.astype(np.float32) for h in inputs.init_factors(dims, R, seed=102)]
+    for upd in ("hals", "mu"):
+        print(f"case one-step {upd}", flush=True)
+        _compare(_run_gpu(X, H0, R, 1, upd), _run_oracle(X, H0, 1, upd), tol=2e-6)
+
+
+def test_trajectory_3way_60x50x40_rank5(gpu_lib):
+    """60x50x40 planted rank 5 + 1% noise, HALS, 20 iterations, split {1,2}|{3}."""
+    dims, R = (60, 50, 40), 5
+    X64, _ = inputs.planted(dims, R, 0.01, seed=1)
+    X = X64.astype(np.float32)
+    H0 = [h.astype(np.float32) for h in inputs.init_factors(dims, R, seed=2)]
+    ref = _run_oracle(X, H0, 20)
+    for split in (2, 1):
+        print(f"case C1 split={split}", flush=True)
+        _compare(_run_gpu(X, H0, R, 20, split=split), ref)
+
+
+@pytest.mark.parametrize("update", ["hals", "mu"])
+def test_trajectory_4way(gpu_lib, update):
+    dims, R = (20, 18, 16, 14), 8
+    X, _ = inputs.planted(dims, R, 0.01, seed=11, dtype=np.float32)
+    H0 = [h.astype(np.float32) for h in inputs.init_factors(dims, R, seed=12)]
+    ref = _run_oracle(X, H0, 30, update)
+    for split in (2, 1, 3):
+        print(f"case 4way {update} split={split}", flush=True)
+        _compare(_run_gpu(X, H0, R, 30, update, split=split), ref)
+
+
+def test_trajectory_5way_and_2way(gpu_lib):
+    for dims, R in [((8, 7, 6, 5, 4), 4), ((70, 45), 7)]:
+        X, _ = inputs.planted(dims, R, 0.02, seed=21, dtype=np.float32)
+        H0 = [h.astype(np.float32) for h in inputs.init_factors(dims, R, seed=22)]
+        print(f"case dims={dims}", flush=True)
+        _compare(_run_gpu(X, H0, R, 15), _run_oracle(X, H0, 15))
+
+
+def test_graph_replay_is_bitwise_equal_to_eager(gpu_lib):
+    dims, R = (24, 22, 20), 7
+    X, _ = inputs.planted(dims, R, 0.01, seed=31, dtype=np.float32)
+    H0 = [h.astype(np.float32) for h in inputs.init_factors(dims, R, seed=32)]
+    a = _run_gpu(X, H0, R, 12, graph=True)
+    b = _run_gpu(X, H0, R, 12, graph=False)
+    for Ha, Hb in zip(a["H"], b["H"]):
+        assert np.array_equal(Ha, Hb)
+    assert np.array_equal(a["fit"], b["fit"]) and np.array_equal(a["lam"], b["lam"])
+
+
+def test_resume_from_finished_state(gpu_lib):
+    """Running 6 + 6 iterations through finish() equals 12 iterations (to tolerance)."""
+    from paper_1806_07985_amd import native
+    dims, R = (26, 20, 18), 5
+    X, _ = inputs.planted(dims, R, 0.01, seed=41, dtype=np.float32)
+    H0 = [h.astype(np.float32) for h in inputs.init_factors(dims, R, seed=42)]
+    Xd = native.tensor_to_device(X)
+    Hd = [native.factor_to_device(h) for h in H0]
+    plan = native.Plan(Xd, list(dims), R, Hd)
+    f1 = plan.run(6)
+    lam1 = plan.finish()
+    f2 = plan.run(6)
+    lam2 = plan.finish()
+    plan.close()
+    ref = _run_oracle(X, H0, 12)
+    g = dict(H=[native.factor_to_host(h) for h in Hd], lam=lam2, fit=np.concatenate([f1, f2]))
+    _compare(g, ref)
+
+
+def test_zero_column_stays_zero(gpu_lib):
+    dims, R = (15, 12, 10), 4
+    X, _ = inputs.planted(dims, 3, 0.01, seed=51, dtype=np.float32)
+    H0 = [h.astype(np.float32) for h in inputs.init_factors(dims, R, seed=52)]
+    H0[1][:, 2] = 0.0
+    g = _run_gpu(X, H0, R, 5)
+    o = _run_oracle(X, H0, 5)
+    for H in g["H"]:
+        assert np.all(H[:, 2] == 0.0)
+    assert g["lam"][2] == 0.0 and o["lam"][2] == 0.0
+    keep = [0, 1, 3]
+    for Hg, Ho in zip(g["H"], o["H"]):
+        assert np.linalg.norm(Hg[:, keep] - Ho[:, keep]) <= TOL * np.linalg.norm(Ho[:, keep])
+
+
+def test_lambda_input_scales_the_model(gpu_lib):
+    dims, R = (12, 11, 10), 3
+    X, _ = inputs.planted(dims, R, 0.01, seed=61, dtype=np.float32)
+    H0 = [h.astype(np.float32) for h in inputs.init_factors(dims, R, seed=62)]
+    lam = np.array([2.0, 0.5, 3.0])
+    _compare(_run_gpu(X, H0, R, 4, lam=lam), _run_oracle(X, H0, 4, lam=lam))
