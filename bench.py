@@ -1,0 +1,205 @@
+"""Benchmark of the NNCP hot path on one MI355X.
+
+Workload (default): a 4-way 128 x 128 x 128 x 128 FP32 tensor built from
+rank-32 nonnegative U[0,1) factors plus 1% Gaussian noise clipped at zero,
+NNCP rank 32, dimension-tree split {1,2}|{3,4}, HALS, factors started U[0,1).
+This is one processor's share of the paper's 4-way weak-scaling experiment.
+
+A "step" is one outer iteration of the whole hot path (both partial MTTKRPs,
+all multi-TTVs, the FP64 Gram/Hadamard builds, the factor updates and the
+FP64 fit), replayed from a HIP graph; the tensor is resident in HBM before
+timing starts. Prints one JSON line.
+"""
+
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import math
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+FP32_MFMA_PEAK_TFLOPS = 157.3
+
+
+def _pm_sources_digest() -> str:
+    h = hashlib.sha256()
+    for f in ("pm_common.hpp", "pm_kernels.hip", "pm16_kernels.hip", "pm_plan.hip"):
+        p = os.path.join(ROOT, "paper_1806_07985_amd", "csrc", f)
+        if os.path.exists(p):
+            h.update(open(p, "rb").read())
+    return h.hexdigest()[:16]
+
+
+def _traffic_from_profile(workload: str, launch_bytes: float):
+    """HBM bytes per PM launch from the committed rocprofv3 counter summary, if it
+    was taken on the current kernel sources (else None)."""
+    p = os.path.join(ROOT, "profiles", f"pm_traffic_{workload}.json")
+    if not os.path.exists(p):
+        return None
+    try:
+        d = json.load(open(p))
+    except Exception:
+        return None
+    if d.get("pm_sources_digest") != _pm_sources_digest():
+        return None
+    return d.get("hbm_bytes_per_launch")
+
+
+def _algorithmic_bytes(dims, s, R, sx, node_bytes=8):
+    """Algorithmic HBM bytes of the tree MTTKRP per outer iteration.
+
+    Per root partial MTTKRP: the tensor once (I * s_X), the node temporary
+    written once (rows * R * node_bytes), the contracted factors read once.
+    Per multi-TTV edge: the parent node read once and the child written once.
+    """
+    N = len(dims)
+    I = int(np.prod(dims))
+    IL, IR = int(np.prod(dims[:s])), int(np.prod(dims[s:]))
+    pm_left = I * sx + IL * R * node_bytes + 4 * R * sum(dims[s:])
+    pm_right = I * sx + IR * R * node_bytes + 4 * R * sum(dims[:s])
+    mttv = 0
+    for lo, hi in ((0, s - 1), (s, N - 1)):
+        for a in range(lo, hi + 1):
+            node = int(np.prod(dims[a:hi + 1])) * R * node_bytes
+            if a < hi:
+                mttv += node + dims[a] * R * 8            # trailing edge to the leaf
+            if a > lo:
+                mttv += int(np.prod(dims[a - 1:hi + 1])) * R * node_bytes + node  # leading edge
+    return pm_left, pm_right, mttv
+
+
+def _cpu_baseline(X, H0, iters, seconds_cap=40.0):
+    import oracle as O
+    X64 = X.astype(np.float64)
+    alpha = float(np.sum(X64 * X64))
+    t0 = time.perf_counter()
+    done = 0
+    while done < iters:
+        O.nncp(X64, H0, 1, alpha=alpha)
+        done += 1
+        if time.perf_counter() - t0 > seconds_cap:
+            break
+    dt = time.perf_counter() - t0
+    cores = len(os.sched_getaffinity(0))
+    return dict(value=done / dt, unit="iters/s", cores=cores, kind="oracle",
+                sample=f"{done} outer iteration(s) of the FP64 NumPy oracle (direct MTTKRP from an explicit "
+                       f"Khatri-Rao product, HALS) on the full {'x'.join(map(str, X.shape))} tensor, "
+                       f"BLAS threads = {os.environ.get('OPENBLAS_NUM_THREADS', cores)}")
+
+
+def main(argv=None):
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=50)
+    ap.add_argument("--warmup", type=int, default=5)
+    ap.add_argument("--update", default="hals", choices=["hals", "mu"])
+    ap.add_argument("--dims", default="128,128,128,128")
+    ap.add_argument("--rank", type=int, default=32)
+    ap.add_argument("--split", type=int, default=2)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-iters", type=int, default=3)
+    args = ap.parse_args(argv)
+
+    if args.gpus != 1:
+        print(json.dumps({"error": "this build runs on one GPU; multi-GPU sharding is design-only "
+                                   "(see the sharding notes); run with --gpus 1"}))
+        return 2
+
+    import torch
+    from paper_1806_07985_amd import inputs, native
+
+    dims = [int(d) for d in args.dims.split(",")]
+    R, s = args.rank, args.split
+    workload = "x".join(map(str, dims)) + f"_r{R}"
+    X, _ = inputs.planted(dims, R, 0.01, seed=1, dtype=np.float32)
+    H0 = [h.astype(np.float32) for h in inputs.init_factors(dims, R, seed=2)]
+
+    dev = torch.device("cuda:0")
+    Xd = native.tensor_to_device(X, device=dev)
+    Hd = [native.factor_to_device(h, device=dev) for h in H0]
+    torch.cuda.synchronize()
+
+    plan = native.Plan(Xd, dims, R, Hd, update=args.update, split=s)
+    fits = list(plan.run(args.warmup))
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    fits += list(plan.run(args.steps))
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    iters_per_s = args.steps / dt
+
+    # Dominant kernel: the root partial MTTKRPs (left = mode 1's node, right =
+    # mode s+1's node), timed with HIP events on the plan's stream.
+    reps = 20
+    ms_left = plan.time_node(0, reps)
+    ms_right = plan.time_node(s, reps)
+    pm_l, pm_r, mttv_bytes = _algorithmic_bytes(dims, s, R, 4)
+    gbs_left = pm_l / (ms_left * 1e-3) / 1e9
+    gbs_right = pm_r / (ms_right * 1e-3) / 1e9
+    dom = "left" if ms_left >= ms_right else "right"
+    ms_dom = max(ms_left, ms_right)
+    bytes_dom = pm_l if dom == "left" else pm_r
+    achieved = bytes_dom / (ms_dom * 1e-3) / 1e9
+
+    # phase breakdown (events between kernels, no graph)
+    Hp = [native.factor_to_device(h, device=dev) for h in H0]
+    pplan = native.Plan(Xd, dims, R, Hp, update=args.update, split=s, graph=False, phase_timers=True)
+    pplan.run(3)
+    ph = pplan.phase_ms()
+    pplan.close()
+    ph = {k: v / 3 for k, v in ph.items()}
+    mttkrp_ms = ph["pm"] + ph["mttv"]
+    mttkrp_gbs = (pm_l + pm_r + mttv_bytes) / (mttkrp_ms * 1e-3) / 1e9 if mttkrp_ms > 0 else None
+
+    lam = plan.finish()
+    plan.close()
+    I = int(np.prod(dims))
+    flops_pm = 2.0 * I * R
+
+    out = {
+        "metric": "NNCP iters/s + MTTKRP HBM GB/s (FP32 vs BF16 at equal fit); p50/p99 job latency",
+        "value": iters_per_s,
+        "unit": "iters/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": 1e3 * dt / args.steps,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": f"{'x'.join(map(str, dims))} FP32 planted rank {R} + 1% noise, NNCP R={R}, "
+                               f"{args.update.upper()}, tree split {{1..{s}}}|{{{s + 1}..{len(dims)}}}",
+                   "dims": dims, "R": R, "split": s, "update": args.update, "tensor_dtype": "f32"},
+        "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": achieved / HBM_PEAK_GBS,
+                     "traffic": _traffic_from_profile(workload, bytes_dom),
+                     "kernel": f"partial MTTKRP ({dom} root node)",
+                     "bytes_per_launch": bytes_dom, "ms_per_launch": ms_dom,
+                     "mfma_fp32_tflops": flops_pm / (ms_dom * 1e-3) / 1e12,
+                     "mfma_fp32_frac": flops_pm / (ms_dom * 1e-3) / 1e12 / FP32_MFMA_PEAK_TFLOPS},
+        "pm": {"left_ms": ms_left, "right_ms": ms_right, "left_GBs": gbs_left, "right_GBs": gbs_right},
+        "mttkrp_GBs": mttkrp_gbs,
+        "phase_ms_per_iter": ph,
+        "fit_first": fits[0] if fits else None,
+        "fit_last": fits[-1] if fits else None,
+        "lambda_max": float(np.max(lam)),
+    }
+    if not args.no_cpu_baseline:
+        out["cpu_baseline"] = _cpu_baseline(X, [h.astype(np.float64) for h in H0], args.cpu_iters)
+    print(json.dumps(out), flush=True)
+    return 0
+
+
+if __name__ == "__main__":
+    sys.exit(main())

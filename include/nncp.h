@@ -118,6 +118,12 @@ int nncp_plan_finish(nncp_plan* plan, double* lambda);
 /* Milliseconds per phase accumulated by runs with phase_timers set, in the
  * order pm, mttv, nls, gram, err, total. ms must hold 6 doubles. */
 int nncp_plan_phase_ms(const nncp_plan* plan, double* ms);
+/* Re-runs the tree-node kernel of `mode` (the node op computed just before that
+ * mode's update: a root partial MTTKRP for mode 1 and mode s+1, a multi-TTV
+ * otherwise) `reps` times back to back on the plan's stream and returns the
+ * average milliseconds per launch from HIP events. Reads the current factors;
+ * it rewrites only that node's temporary, which the next iteration recomputes. */
+int nncp_plan_time_node(nncp_plan* plan, int mode, int reps, double* ms_avg);
 int nncp_plan_destroy(nncp_plan* plan);
 
 /* ---- Steps of the hot path (each is the kernel the driver runs) ---- */
@@ -137,28 +143,29 @@ int nncp_norm_sq(const void* X, int dtype, int64_t n, double* out_dev, void* str
  *   side 1 (right node {s+1..N}): T = X_[L]^T * (H^(s) (.) ... (.) H^(1)),  T is I_R x R
  * (.) is the Khatri-Rao product with the lowest mode's row index fastest.
  * H: host array of N device factor pointers (only the contracted modes are read).
- * T: device float32, column-major with leading dimension I_L or I_R.
+ * T: device float64, column-major with leading dimension I_L or I_R. Products are
+ * formed on FP32 MFMA and summed in FP64 after every 16 or 32 terms.
  */
 int nncp_partial_mttkrp(const void* X, int dtype, int N, const int64_t* dims, int s, int side,
-                        float* const* H, int R, float* T, void* stream);
+                        float* const* H, int R, double* T, void* stream);
 
 /*
  * Multi-TTV (Section IV-A, Fig. 2b) on a tree node {a..b} whose temporary T has
- * shape I_a x ... x I_b x R (column-major, R slowest). `node_dims` are the
- * nm = b-a+1 extents.
+ * shape I_a x ... x I_b x R (column-major, R slowest, float64). `node_dims` are the
+ * nm = b-a+1 extents. Sums are accumulated in float64; out is float64.
  *   kind 0 (leaf {a}):  out(i,r) = sum_j T(i, j, r) K(j, r), K = H^(b) (.) ... (.) H^(a+1);
  *                       out is I_a x R. Hf[0..nm-2] are the factors of modes a+1..b.
  *   kind 1 (node {a+1..b}): out(j, r) = sum_i T(i, j, r) H^(a)(i, r); out has shape
  *                       I_{a+1} x ... x I_b x R. Hf[0] is the factor of mode a.
  */
-int nncp_mttv(const float* T, int nm, const int64_t* node_dims, int kind, float* const* Hf,
-              int R, float* out, void* stream);
+int nncp_mttv(const double* T, int nm, const int64_t* node_dims, int kind, float* const* Hf,
+              int R, double* out, void* stream);
 
 /* Full dimension-tree MTTKRP for mode n (0-based) with the given factors: the root
  * PM on n's side of split s, then the chain of multi-TTVs down to leaf n. M: device
- * float32 I_n x R. Uses an internal workspace allocated for the call. */
+ * float64 I_n x R. Uses an internal workspace allocated for the call. */
 int nncp_mttkrp(const void* X, int dtype, int N, const int64_t* dims, int s, int n,
-                float* const* H, int R, float* M, void* stream);
+                float* const* H, int R, double* M, void* stream);
 
 /* G = H^T H (R x R, float64, device) for a device float32 I x R factor. */
 int nncp_gram(const float* H, int64_t I, int R, double* G, void* stream);
@@ -169,10 +176,11 @@ int nncp_gram(const float* H, int64_t I, int R, double* G, void* stream);
  *   HALS: for r = 1..R: W(:,r) = max(0, W(:,r) + (M(:,r) - (W S)(:,r)) / S(r,r));
  *   MU:   W = W * M / max(W S, 1e-16);
  *   lambda = column norms of W, H = W diag(1/lambda), G = H^T H.
- * M, H: device float32 I x R; S: device float64 R x R (symmetric);
- * lambda: device float64 R (in/out); G: device float64 R x R (out).
+ * M: device float64 I x R; H: device float32 I x R; S: device float64 R x R
+ * (symmetric); lambda: device float64 R (in/out); G: device float64 R x R (out).
+ * The update arithmetic is float64; H is stored as float32.
  */
-int nncp_nls_update(const float* M, float* H, int64_t I, int R, const double* S,
+int nncp_nls_update(const double* M, float* H, int64_t I, int R, const double* S,
                     double* lambda, int update, double* G, void* stream);
 
 #ifdef __cplusplus

@@ -11,7 +11,7 @@ ROOT = os.path.dirname(PKG)
 CSRC = os.path.join(PKG, "csrc")
 LIB_DIR = os.path.join(PKG, "lib")
 LIB = os.path.join(LIB_DIR, "libnncp.so")
-SOURCES = ["pm_kernels.hip", "pm16_kernels.hip", "small_kernels.hip", "batch_kernels.hip",
+SOURCES = ["pm_plan.hip", "pm_kernels.hip", "pm16_kernels.hip", "small_kernels.hip", "batch_kernels.hip",
            "driver.hip", "batch.hip", "server.cpp"]
 
 HIPCC_FLAGS = [

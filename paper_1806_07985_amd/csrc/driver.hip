@@ -47,7 +47,8 @@ struct Layout {
   size_t off_alpha, off_iter, off_counters, off_lam, off_lammodel, off_lamin, off_G, off_S, off_fit,
       off_finpart, off_pmpart, off_nspart, off_M, off_nodes, total;
   int ncounters;
-  int64_t nodes_floats[kMaxModes];
+  int64_t node_bytes[kMaxModes];
+  int node_f64;  // tree temporaries are FP64 for FP32 tensors, FP32 for 16-bit tensors
   PmLaunch pmL[2];
   int fin_chunks, fin_rows;
   int ns_blocks;
@@ -149,16 +150,17 @@ Layout make_layout(const Problem& p) {
   L.off_S = take(sizeof(double) * N * RR);
   L.off_fit = take(sizeof(double) * kFitCap);
   L.off_finpart = take(sizeof(double) * (size_t)maxchunks * (RR + 1));
-  L.off_pmpart = take(sizeof(float) * std::max(L.pmL[0].partial_floats, L.pmL[1].partial_floats));
+  L.off_pmpart = take(sizeof(double) * std::max(L.pmL[0].partial_doubles, L.pmL[1].partial_doubles));
   L.off_nspart = take(sizeof(double) * L.ns_blocks);
   int64_t maxI = 0;
   for (int k = 0; k < N; ++k) maxI = std::max(maxI, p.dims[k]);
-  L.off_M = take(sizeof(float) * (size_t)maxI * R);
+  L.off_M = take(sizeof(double) * (size_t)maxI * R);
+  L.node_f64 = p.dtype == NNCP_F32 ? 1 : 0;
   L.off_nodes = o;
   for (int n = 0; n < N; ++n) {
     const int b = sub_end(p, n);
-    L.nodes_floats[n] = prod_range(p, n, b) * R;
-    take(sizeof(float) * (size_t)L.nodes_floats[n]);
+    L.node_bytes[n] = prod_range(p, n, b) * R * (L.node_f64 ? 8 : 4);
+    take((size_t)L.node_bytes[n]);
   }
   L.total = o + 256;
   return L;
@@ -199,13 +201,13 @@ struct nncp_plan {
   double* S() const { return at<double>(L.off_S); }
   double* fit() const { return at<double>(L.off_fit); }
   double* finpart() const { return at<double>(L.off_finpart); }
-  float* pmpart() const { return at<float>(L.off_pmpart); }
+  double* pmpart() const { return at<double>(L.off_pmpart); }
   double* nspart() const { return at<double>(L.off_nspart); }
-  float* Mbuf() const { return at<float>(L.off_M); }
-  float* node(int n) const {
+  double* Mbuf() const { return at<double>(L.off_M); }
+  void* node(int n) const {
     size_t o = L.off_nodes;
-    for (int k = 0; k < n; ++k) o = align256(o + sizeof(float) * (size_t)L.nodes_floats[k]);
-    return (float*)(ws + o);
+    for (int k = 0; k < n; ++k) o = align256(o + (size_t)L.node_bytes[k]);
+    return (void*)(ws + o);
   }
 };
 
@@ -224,7 +226,7 @@ KrpDesc krp_for(const nncp_plan* P, int a, int b, bool scaled) {
   return k;
 }
 
-hipError_t run_pm(const nncp_plan* P, int side, float* T, const void* X, bool scaled, hipStream_t st) {
+hipError_t run_pm(const nncp_plan* P, int side, void* T, int t_f64, const void* X, bool scaled, hipStream_t st) {
   const Problem& p = P->p;
   const PmLaunch& pl = P->L.pmL[side];
   for (int c0 = 0; c0 < p.R; c0 += kPmMaxCols) {
@@ -236,6 +238,7 @@ hipError_t run_pm(const nncp_plan* P, int side, float* T, const void* X, bool sc
     a.R = std::min(kPmMaxCols, p.R - c0);
     a.col0 = c0;
     a.T = T;
+    a.t_f64 = t_f64;
     a.partial = P->pmpart();
     a.counters = P->counters();
     a.nsplit = pl.nsplit;
@@ -252,48 +255,56 @@ hipError_t run_pm(const nncp_plan* P, int side, float* T, const void* X, bool sc
   return hipSuccess;
 }
 
-// Computes M^(n) (node op + leaf op) on stream st; returns the buffer holding it.
-hipError_t mttkrp_mode(const nncp_plan* P, int n, bool scaled, hipStream_t st, const float** Mout,
-                       int phase_ev = 0) {
+// Node op for mode n: the root partial MTTKRP (n starts its half) or the leading
+// multi-TTV from node {n-1..b}.
+hipError_t node_op(const nncp_plan* P, int n, bool scaled, hipStream_t st) {
   const Problem& p = P->p;
   const int b = sub_end(p, n), start = sub_start(p, n);
-  float* nodebuf = P->node(n);
-  hipError_t e;
-  if (n == start) {
-    e = run_pm(P, n == 0 ? 0 : 1, nodebuf, P->X, scaled, st);
-  } else {
-    MttvArgs a{};
-    a.T = P->node(n - 1);
-    a.Ia = p.dims[n - 1];
-    a.J = prod_range(p, n, b);
-    a.R = p.R;
-    a.krp = krp_for(P, n - 1, n - 1, scaled);
-    a.out = nodebuf;
-    e = mttv_lead_launch(a, st);
-  }
-  if (e != hipSuccess) return e;
+  const int f64 = P->L.node_f64;
+  if (n == start) return run_pm(P, n == 0 ? 0 : 1, P->node(n), f64, P->X, scaled, st);
+  MttvArgs a{};
+  a.T = P->node(n - 1);
+  a.t_f64 = f64;
+  a.Ia = p.dims[n - 1];
+  a.J = prod_range(p, n, b);
+  a.R = p.R;
+  a.krp = krp_for(P, n - 1, n - 1, scaled);
+  a.out = P->node(n);
+  a.out_f64 = f64;
+  return mttv_lead_launch(a, st);
+}
+
+// Leaf op for mode n: M^(n) from node {n..b} by the trailing multi-TTV, or the
+// node itself when it is the leaf. *M and *m_f64 describe where M^(n) lives.
+hipError_t leaf_op(const nncp_plan* P, int n, bool scaled, hipStream_t st, const void** M, int* m_f64) {
+  const Problem& p = P->p;
+  const int b = sub_end(p, n);
   if (n == b) {
-    *Mout = nodebuf;
+    *M = P->node(n);
+    *m_f64 = P->L.node_f64;
     return hipSuccess;
   }
   MttvArgs a{};
-  a.T = nodebuf;
+  a.T = P->node(n);
+  a.t_f64 = P->L.node_f64;
   a.Ia = p.dims[n];
   a.J = prod_range(p, n + 1, b);
   a.R = p.R;
   a.krp = krp_for(P, n + 1, b, scaled);
   a.out = P->Mbuf();
-  e = mttv_trail_launch(a, st);
-  *Mout = P->Mbuf();
-  return e;
+  a.out_f64 = 1;
+  *M = P->Mbuf();
+  *m_f64 = 1;
+  return mttv_trail_launch(a, st);
 }
 
-hipError_t finalize_mode(const nncp_plan* P, int n, const float* M, int set_model, int next_mode,
+hipError_t finalize_mode(const nncp_plan* P, int n, const void* M, int m_f64, int set_model, int next_mode,
                          int do_fit, hipStream_t st) {
   const Problem& p = P->p;
   FinalizeArgs f{};
   f.W = P->H[n];
   f.M = M;
+  f.m_f64 = m_f64;
   f.I = p.dims[n];
   f.R = p.R;
   f.N = p.N;
@@ -331,28 +342,17 @@ hipError_t enqueue_iteration(nncp_plan* P, hipStream_t st, std::vector<std::pair
   };
   hipError_t e;
   for (int n = 0; n < p.N; ++n) {
-    const int b = sub_end(p, n), start = sub_start(p, n);
-    const float* M = nullptr;
+    const int start = sub_start(p, n);
+    const void* M = nullptr;
+    int m_f64 = 1;
     if ((e = mark(n == start ? PH_PM : PH_MTTV)) != hipSuccess) return e;
-    if (marks && n == start && n != b) {
-      // time the PM and the trailing mTTV separately
-      if ((e = run_pm(P, n == 0 ? 0 : 1, P->node(n), P->X, true, st)) != hipSuccess) return e;
-      if ((e = mark(PH_MTTV)) != hipSuccess) return e;
-      MttvArgs a{};
-      a.T = P->node(n);
-      a.Ia = p.dims[n];
-      a.J = prod_range(p, n + 1, b);
-      a.R = p.R;
-      a.krp = krp_for(P, n + 1, b, true);
-      a.out = P->Mbuf();
-      if ((e = mttv_trail_launch(a, st)) != hipSuccess) return e;
-      M = P->Mbuf();
-    } else {
-      if ((e = mttkrp_mode(P, n, true, st, &M)) != hipSuccess) return e;
-    }
+    if ((e = node_op(P, n, true, st)) != hipSuccess) return e;
+    if ((e = mark(PH_MTTV)) != hipSuccess) return e;
+    if ((e = leaf_op(P, n, true, st, &M, &m_f64)) != hipSuccess) return e;
     if ((e = mark(PH_NLS)) != hipSuccess) return e;
     UpdateArgs u{};
     u.M = M;
+    u.m_f64 = m_f64;
     u.W = P->H[n];
     u.I = p.dims[n];
     u.R = p.R;
@@ -363,7 +363,7 @@ hipError_t enqueue_iteration(nncp_plan* P, hipStream_t st, std::vector<std::pair
     if ((e = update_launch(u, st)) != hipSuccess) return e;
     const bool last = (n == p.N - 1);
     if ((e = mark(last ? PH_ERR : PH_GRAM)) != hipSuccess) return e;
-    if ((e = finalize_mode(P, n, M, 1, (n + 1) % p.N, last ? 1 : 0, st)) != hipSuccess) return e;
+    if ((e = finalize_mode(P, n, M, m_f64, 1, (n + 1) % p.N, last ? 1 : 0, st)) != hipSuccess) return e;
   }
   return mark(-1);
 }
@@ -486,12 +486,35 @@ int nncp_plan_create(nncp_plan** out, const void* X, int dtype, int N, const int
     return fail(NNCP_EDEVICE);
   // starting Grams / norms per mode, then model weights and S^(1)
   for (int k = 0; k < N; ++k)
-    if (finalize_mode(P, k, nullptr, 0, -1, 0, s) != hipSuccess) return fail(NNCP_EDEVICE);
+    if (finalize_mode(P, k, nullptr, 0, 0, -1, 0, s) != hipSuccess) return fail(NNCP_EDEVICE);
   if (init_model_launch(P->lam_in(), P->lam(), P->lam_model(), P->G(), P->S(), N, R, s) != hipSuccess)
     return fail(NNCP_EDEVICE);
   if (hipStreamSynchronize(s) != hipSuccess) return fail(NNCP_EDEVICE);
   *out = P;
   return NNCP_OK;
+}
+
+int nncp_plan_time_node(nncp_plan* P, int mode, int reps, double* ms_avg) {
+  if (!P || !ms_avg || reps < 1 || mode < 0 || mode >= P->p.N) return NNCP_EINVAL;
+  hipStream_t s = P->user_stream;
+  hipEvent_t e0, e1;
+  HIPCHK(hipEventCreate(&e0));
+  if (hipEventCreate(&e1) != hipSuccess) {
+    hipEventDestroy(e0);
+    return NNCP_EDEVICE;
+  }
+  int st = NNCP_OK;
+  if (hipEventRecord(e0, s) != hipSuccess) st = NNCP_EDEVICE;
+  for (int i = 0; st == NNCP_OK && i < reps; ++i)
+    if (node_op(P, mode, true, s) != hipSuccess) st = NNCP_EDEVICE;
+  float ms = 0.f;
+  if (st == NNCP_OK && (hipEventRecord(e1, s) != hipSuccess || hipEventSynchronize(e1) != hipSuccess ||
+                        hipEventElapsedTime(&ms, e0, e1) != hipSuccess))
+    st = NNCP_EDEVICE;
+  hipEventDestroy(e0);
+  hipEventDestroy(e1);
+  *ms_avg = (double)ms / reps;
+  return st;
 }
 
 int nncp_plan_destroy(nncp_plan* P) {
@@ -655,20 +678,20 @@ static int step_ctx(StepCtx& c, const void* X, int dtype, int N, const int64_t* 
 }
 
 int nncp_partial_mttkrp(const void* X, int dtype, int N, const int64_t* dims, int s, int side,
-                        float* const* H, int R, float* T, void* stream) {
+                        float* const* H, int R, double* T, void* stream) {
   if (!X || !H || !T || (side != 0 && side != 1) || s < 1) return NNCP_EINVAL;
   StepCtx c;
   int st = step_ctx(c, X, dtype, N, dims, s, H, R);
   if (st != NNCP_OK) return st;
   hipStream_t hs = (hipStream_t)stream;
   if (hipDeviceSynchronize() != hipSuccess) return NNCP_EDEVICE;
-  if (run_pm(&c.P, side, T, X, false, hs) != hipSuccess) return NNCP_EDEVICE;
+  if (run_pm(&c.P, side, T, 1, X, false, hs) != hipSuccess) return NNCP_EDEVICE;
   if (hipStreamSynchronize(hs) != hipSuccess) return NNCP_EDEVICE;
   return NNCP_OK;
 }
 
-int nncp_mttv(const float* T, int nm, const int64_t* node_dims, int kind, float* const* Hf, int R,
-              float* out, void* stream) {
+int nncp_mttv(const double* T, int nm, const int64_t* node_dims, int kind, float* const* Hf, int R,
+              double* out, void* stream) {
   if (!T || !node_dims || !Hf || !out || nm < 2 || nm > kMaxModes || R < 1 || R > kMaxRank ||
       (kind != 0 && kind != 1))
     return NNCP_EINVAL;
@@ -676,12 +699,14 @@ int nncp_mttv(const float* T, int nm, const int64_t* node_dims, int kind, float*
     if (node_dims[k] < 1 || node_dims[k] > INT32_MAX) return NNCP_EINVAL;
   MttvArgs a{};
   a.T = T;
+  a.t_f64 = 1;
   a.Ia = node_dims[0];
   a.J = 1;
   for (int k = 1; k < nm; ++k) a.J *= node_dims[k];
   if (a.J > (int64_t)UINT32_MAX) return NNCP_EINVAL;
   a.R = R;
   a.out = out;
+  a.out_f64 = 1;
   a.krp.lam = nullptr;
   if (kind == 0) {
     a.krp.nm = nm - 1;
@@ -704,38 +729,22 @@ int nncp_mttv(const float* T, int nm, const int64_t* node_dims, int kind, float*
 }
 
 int nncp_mttkrp(const void* X, int dtype, int N, const int64_t* dims, int s, int n, float* const* H, int R,
-                float* M, void* stream) {
+                double* M, void* stream) {
   if (!X || !H || !M || s < 1 || n < 0 || n >= N) return NNCP_EINVAL;
   StepCtx c;
   int st = step_ctx(c, X, dtype, N, dims, s, H, R);
   if (st != NNCP_OK) return st;
   hipStream_t hs = (hipStream_t)stream;
   if (hipDeviceSynchronize() != hipSuccess) return NNCP_EDEVICE;
-  // walk the subtree of n from its root branch: nodes {start..b}, {start+1..b}, ... {n..b}
+  // walk n's subtree from its root branch: nodes {start..b}, {start+1..b}, ..., {n..b}
   const Problem& p = c.P.p;
-  const int start = sub_start(p, n);
-  const float* Mp = nullptr;
-  for (int k = start; k <= n; ++k) {
-    if (k < n) {
-      // only the node is needed on the way down
-      const int b = sub_end(p, k);
-      if (k == start) {
-        if (run_pm(&c.P, k == 0 ? 0 : 1, c.P.node(k), X, false, hs) != hipSuccess) return NNCP_EDEVICE;
-      } else {
-        MttvArgs a{};
-        a.T = c.P.node(k - 1);
-        a.Ia = p.dims[k - 1];
-        a.J = prod_range(p, k, b);
-        a.R = p.R;
-        a.krp = krp_for(&c.P, k - 1, k - 1, false);
-        a.out = c.P.node(k);
-        if (mttv_lead_launch(a, hs) != hipSuccess) return NNCP_EDEVICE;
-      }
-    } else if (mttkrp_mode(&c.P, k, false, hs, &Mp) != hipSuccess) {
-      return NNCP_EDEVICE;
-    }
-  }
-  if (hipMemcpyAsync(M, Mp, sizeof(float) * (size_t)p.dims[n] * R, hipMemcpyDeviceToDevice, hs) != hipSuccess)
+  for (int k = sub_start(p, n); k <= n; ++k)
+    if (node_op(&c.P, k, false, hs) != hipSuccess) return NNCP_EDEVICE;
+  const void* Mp = nullptr;
+  int m_f64 = 1;
+  if (leaf_op(&c.P, n, false, hs, &Mp, &m_f64) != hipSuccess) return NNCP_EDEVICE;
+  if (!m_f64) return NNCP_EINVAL;
+  if (hipMemcpyAsync(M, Mp, sizeof(double) * (size_t)p.dims[n] * R, hipMemcpyDeviceToDevice, hs) != hipSuccess)
     return NNCP_EDEVICE;
   return hipStreamSynchronize(hs) == hipSuccess ? NNCP_OK : NNCP_EDEVICE;
 }
@@ -783,7 +792,7 @@ int nncp_gram(const float* H, int64_t I, int R, double* G, void* stream) {
   return st;
 }
 
-int nncp_nls_update(const float* M, float* H, int64_t I, int R, const double* S, double* lambda, int update,
+int nncp_nls_update(const double* M, float* H, int64_t I, int R, const double* S, double* lambda, int update,
                     double* G, void* stream) {
   if (!M || !H || !S || !lambda || !G || I < 1 || R < 1 || R > kMaxRank ||
       (update != NNCP_HALS && update != NNCP_MU))
@@ -801,6 +810,7 @@ int nncp_nls_update(const float* M, float* H, int64_t I, int R, const double* S,
   int st = NNCP_OK;
   UpdateArgs u{};
   u.M = M;
+  u.m_f64 = 1;
   u.W = H;
   u.I = I;
   u.R = R;

@@ -37,9 +37,10 @@ struct PmArgs {
   int64_t IL, IR;        // X viewed as column-major IL x IR
   KrpDesc krp;           // contracted modes
   int R;                 // columns handled by this launch (<= kPmMaxCols)
-  int col0;              // first column (offset into factor columns and colscale)
-  float* T;              // output, column-major, ld = Mtot, columns col0..col0+R-1 -> T + Mtot*r
-  float* partial;        // split-K partials
+  int col0;              // first column (offset into factor columns)
+  void* T;               // output, column-major, ld = Mtot: column c at T + Mtot*c
+  int t_f64;             // T is double (else float)
+  double* partial;       // split-K partials (FP64)
   unsigned* counters;    // one per M tile; zero on entry, left zero on exit
   int nsplit;
   int64_t kchunk;        // reduction range per split (multiple of the tile depth)
@@ -54,27 +55,35 @@ struct PmLaunch {
   int mtiles;
   int nsplit;
   int64_t kchunk;
-  size_t partial_floats;
+  size_t partial_doubles;
   int ncounters;
 };
 
 PmLaunch pm_plan(int side, int dtype, int64_t IL, int64_t IR, int R);
 hipError_t pm_launch(const PmLaunch& L, const PmArgs& a, hipStream_t st);
+// per-dtype kernels (pm_kernels.hip, pm16_kernels.hip)
+int pm_f32_wave_rows(int side, int nb);
+hipError_t pm_launch_f32(const PmLaunch& L, const PmArgs& a, hipStream_t st);
+int pm_16_wave_rows(int side, int nb);
+hipError_t pm_launch_16(const PmLaunch& L, const PmArgs& a, hipStream_t st);
 
 // Multi-TTV kernels ---------------------------------------------------------
 struct MttvArgs {
-  const float* T;       // node temporary: I_a x J x R (column-major)
+  const void* T;        // node temporary: I_a x J x R (column-major)
+  int t_f64;            // T is double (else float)
   int64_t Ia, J;
   int R;
   KrpDesc krp;          // trail: modes a+1..b (first fastest); lead: one mode (a)
-  float* out;
+  void* out;
+  int out_f64;          // out is double (else float)
 };
 hipError_t mttv_trail_launch(const MttvArgs& a, hipStream_t st);
 hipError_t mttv_lead_launch(const MttvArgs& a, hipStream_t st);
 
 // Factor update, Gram, lambda, fit -----------------------------------------
 struct UpdateArgs {
-  const float* M;         // I x R MTTKRP result (others normalised)
+  const void* M;          // I x R MTTKRP result (others normalised)
+  int m_f64;              // M is double (else float)
   float* W;               // in: stored factor of this mode (scaled by lam_self), out: new W_hat
   int64_t I;
   int R;
@@ -87,7 +96,8 @@ hipError_t update_launch(const UpdateArgs& a, hipStream_t st);
 
 struct FinalizeArgs {
   const float* W;         // I x R new factor (unnormalised)
-  const float* M;         // I x R (for beta) or nullptr
+  const void* M;          // I x R (for beta) or nullptr
+  int m_f64;
   int64_t I;
   int R;
   int N, mode;

@@ -1,134 +1,45 @@
-// Partial MTTKRP on MFMA (the root edges of the dimension tree, Section IV-A,
-// Figure 2a): T = X_[L] * K (left node) or T = X_[L]^T * K (right node), where
-// X_[L] is the tensor viewed as the column-major I_L x I_R matrix (modes 1..s
-// on the rows) and K is the Khatri-Rao product of the other side's factors.
+// Partial MTTKRP on MFMA for FP32 tensors (the root edges of the dimension
+// tree, Section IV-A, Figure 2a): T = X_[L] * K (left node) or
+// T = X_[L]^T * K (right node), where X_[L] is the tensor viewed as the
+// column-major I_L x I_R matrix (modes 1..s on the rows) and K is the
+// Khatri-Rao product of the other side's factors.
 //
 // Design (gfx950, wave64):
 //  * The reduction index k runs over X's columns (left) or rows (right). The
 //    Khatri-Rao operand is never materialised in HBM: each work-group forms a
 //    BK x R tile of it in LDS from factor rows (double-buffered), and every wave
 //    of the group reads its MFMA B operand from that tile.
-//  * X is streamed straight from HBM into VGPRs with 16-byte loads, one k-step
-//    ahead of the MFMAs. FP32 uses v_mfma_f32_16x16x4_f32. The K order inside a
-//    16- or 32-wide super-step is permuted so that one 16-byte load per lane
-//    feeds four MFMAs while A and B agree on which k sits in which slot.
-//  * Split-K over work-groups with FP32 partials; the last work-group to finish
-//    an output tile (device-scope counter) sums the partials in FP64 in split
-//    order, so results do not depend on scheduling.
-#include "nncp_internal.hpp"
+//  * X is streamed straight from HBM into VGPRs with 8- or 16-byte loads, one
+//    k-step ahead of the MFMAs (v_mfma_f32_16x16x4_f32). The k order inside a
+//    16- or 32-wide k-step is permuted so that one wide load per lane feeds
+//    several MFMAs while A and B agree on which k sits in which slot.
+//  * Precision: each MFMA chain covers one k-step only (4 or 8 MFMAs, 16 or 32
+//    products per output) and is then added into FP64 accumulators, so the FP32
+//    rounding of a running sum never spans more than 32 terms; split-K
+//    partials, the cross-wave reduction and the output are FP64.
+//  * Split-K over work-groups; the last work-group to finish an output tile
+//    (device-scope counter) sums the partials in split order, so results do
+//    not depend on scheduling.
+#include "pm_common.hpp"
 
 namespace nncpk {
 namespace {
 
-typedef float f4 __attribute__((ext_vector_type(4)));
-typedef float f4u __attribute__((ext_vector_type(4), aligned(4)));
-
-constexpr int BK = 128;          // Khatri-Rao tile depth (k rows per LDS tile)
-constexpr int PITCH = BK + 4;    // floats per tile column in LDS
-constexpr int NT = 256;          // threads per work-group (4 waves)
-
-__device__ __forceinline__ f4 mfma4(float a, float b, f4 c) {
-  return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
-}
-
-// Build rows [k0, k0+BK) of the Khatri-Rao operand into LDS tile `kt`
-// (layout kt[col * PITCH + k]). Rows at or beyond kend are zero.
-template <int NB>
-__device__ __forceinline__ void build_tile(float* kt, const KrpDesc& krp, const double* cs,
-                                           int64_t k0, int64_t kend, int R, int col0) {
-  constexpr int RP = NB * 16;
-  const int kl = threadIdx.x % BK;
-  const int c0 = threadIdx.x / BK;  // 0 or 1
-  const int64_t k = k0 + kl;
-  int d[kMaxModes];
-  bool valid = k < kend;
-  if (valid) {
-    uint32_t rem = (uint32_t)k;  // operand rows are < 2^32
-#pragma unroll
-    for (int j = 0; j < kMaxModes; ++j) {
-      if (j < krp.nm) {
-        uint32_t dj = (uint32_t)krp.dim[j];
-        d[j] = (int)(rem % dj);
-        rem /= dj;
-      }
-    }
-  }
-  for (int c = c0; c < RP; c += NT / BK) {
-    float v = 0.f;
-    if (valid && c < R) {
-      double p = cs[c];
-#pragma unroll
-      for (int j = 0; j < kMaxModes; ++j)
-        if (j < krp.nm) p *= (double)krp.f[j][(int64_t)d[j] + (int64_t)krp.dim[j] * (col0 + c)];
-      v = (float)p;
-    }
-    kt[c * PITCH + kl] = v;
-  }
-}
-
-// Deterministic split-K epilogue: write this group's partial, count, and let the
-// last group of the M tile reduce all splits in FP64 into T.
-__device__ void splitk_finish(const PmArgs& a, int64_t Mtot, int mtile, int64_t mbeg, int RP,
-                              int64_t Mpad) {
-  __shared__ int s_last;
-  __threadfence();
-  __syncthreads();
-  if (threadIdx.x == 0) {
-    unsigned prev = __hip_atomic_fetch_add(&a.counters[blockIdx.x], 1u, __ATOMIC_ACQ_REL,
-                                           __HIP_MEMORY_SCOPE_AGENT);
-    s_last = (prev == (unsigned)(a.nsplit - 1));
-  }
-  __syncthreads();
-  if (!s_last) return;
-  __threadfence();
-  const int64_t rows = (Mtot - mbeg) < mtile ? (Mtot - mbeg) : mtile;
-  const int64_t total = rows * a.R;
-  const size_t sstride = (size_t)RP * (size_t)Mpad;
-  for (int64_t e = threadIdx.x; e < total; e += NT) {
-    int r = (int)(e / rows);
-    int64_t m = mbeg + (e - (int64_t)r * rows);
-    const float* p = a.partial + (size_t)r * Mpad + m;
-    double s = 0.0;
-    for (int sp = 0; sp < a.nsplit; ++sp) s += (double)__builtin_nontemporal_load(p + sp * sstride);
-    a.T[m + Mtot * (int64_t)(a.col0 + r)] = (float)s;
-  }
-  if (threadIdx.x == 0)
-    __hip_atomic_store(&a.counters[blockIdx.x], 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-}
-
-// Sum the accumulators of the WK waves that share an M range (WK > 1) through LDS;
-// wave wk == 0 ends with the total. `acc` is NACC f4 per lane.
-template <int NACC>
-__device__ __forceinline__ void wave_reduce_k(f4* acc, float* lds, int wk, int wm, int WK, int WM) {
-  if (WK == 1) return;
-  const int lane = threadIdx.x & 63;
-  for (int src = 1; src < WK; ++src) {
-    __syncthreads();
-    if (wk == src) {
-#pragma unroll
-      for (int v = 0; v < NACC; ++v) *(f4*)&lds[((wm * NACC + v) * 64 + lane) * 4] = acc[v];
-    }
-    __syncthreads();
-    if (wk == 0) {
-#pragma unroll
-      for (int v = 0; v < NACC; ++v) acc[v] += *(f4*)&lds[((wm * NACC + v) * 64 + lane) * 4];
-    }
-  }
-}
-
 // ----------------------------------------------------------------------------
-// Left side, FP32: T(m, r) = sum_k X[m + IL*k] * K(k, r); m is contiguous in X.
-// Wave tile: MR groups of 64 rows x all RP columns. Lane (i, q) loads rows
-// 4i..4i+3 of a group for column k = base + 4q + u; MFMA t uses row 4i+t.
+// Left side: T(m, r) = sum_k X[m + IL*k] * K(k, r); m is contiguous in X.
+// A wave covers 16*TR rows. Lane (i, q) loads rows TR*i .. TR*i+TR-1 of column
+// k = base + 4q + u (u = 0..3); MFMA t uses row TR*i + t of that load.
 // ----------------------------------------------------------------------------
-template <int NB, int MR, int WM, bool VEC>
+template <int NB, int TR, int WM, bool VEC>
 __global__ __launch_bounds__(NT, 2) void pm_left_f32(PmArgs a) {
   constexpr int RP = NB * 16;
   constexpr int WK = 4 / WM;
-  constexpr int KS = 16;                  // k per super-step
-  constexpr int SPT = BK / WK / KS;       // super-steps per tile per wave
-  constexpr int NACC = MR * 4 * NB;
+  constexpr int KS = 16;                  // k per k-step
+  constexpr int SPT = BK / WK / KS;       // k-steps per tile per wave
+  constexpr int NACC = TR * NB;           // 4-element accumulators per lane
+  constexpr int WROWS = 16 * TR;
   static_assert(SPT >= 1, "tile too shallow");
+  typedef float vT __attribute__((ext_vector_type(TR)));
   extern __shared__ float lds[];
   float* kt0 = lds;
   float* kt1 = lds + RP * PITCH;
@@ -138,9 +49,9 @@ __global__ __launch_bounds__(NT, 2) void pm_left_f32(PmArgs a) {
   const int wm = wave % WM, wk = wave / WM;
   const int li = lane & 15, lq = lane >> 4;
   const int64_t Mtot = a.IL, Ktot = a.IR;
-  const int mtile = WM * 64 * MR;
+  const int mtile = WM * WROWS;
   const int64_t mbeg = (int64_t)blockIdx.x * mtile;
-  const int64_t mw = mbeg + wm * 64 * MR;
+  const int64_t mw = mbeg + wm * WROWS;
   const int64_t kbeg = (int64_t)blockIdx.y * a.kchunk;
   int64_t kend = kbeg + a.kchunk;
   if (kend > Ktot) kend = Ktot;
@@ -150,30 +61,30 @@ __global__ __launch_bounds__(NT, 2) void pm_left_f32(PmArgs a) {
   for (int c = threadIdx.x; c < RP; c += NT) cs[c] = (c < a.R) ? krp_colscale(a.krp, a.col0 + c) : 0.0;
   __syncthreads();
 
-  f4 acc[NACC];
+  double acc[NACC][4];
 #pragma unroll
-  for (int v = 0; v < NACC; ++v) acc[v] = f4{0.f, 0.f, 0.f, 0.f};
+  for (int v = 0; v < NACC; ++v)
+#pragma unroll
+    for (int e = 0; e < 4; ++e) acc[v][e] = 0.0;
 
-  auto load_step = [&](int s, f4 (&A)[MR][4]) {
+  const int64_t m = mw + TR * li;
+  const bool mfull = m + TR <= Mtot;
+  auto load_step = [&](int s, vT (&A)[4]) {
     const int t = s / SPT, w = s % SPT;
     const int64_t kb = kbeg + (int64_t)t * BK + wk * (BK / WK) + w * KS + 4 * lq;
 #pragma unroll
     for (int u = 0; u < 4; ++u) {
       const int64_t k = kb + u;
       const bool kv = k < kend;
-      const float* col = X + Ktot * 0 + Mtot * (kv ? k : 0);
+      const float* col = X + Mtot * (kv ? k : 0);
+      if (VEC) {
+        if (kv && mfull) A[u] = __builtin_nontemporal_load((const vT*)(col + m));
+        else A[u] = vT{};
+      } else {
+        vT v;
 #pragma unroll
-      for (int g = 0; g < MR; ++g) {
-        const int64_t m = mw + 64 * g + 4 * li;
-        if (VEC) {
-          if (kv && m < Mtot) A[g][u] = __builtin_nontemporal_load((const f4*)(col + m));
-          else A[g][u] = f4{0.f, 0.f, 0.f, 0.f};
-        } else {
-          f4 v;
-#pragma unroll
-          for (int e = 0; e < 4; ++e) v[e] = (kv && m + e < Mtot) ? col[m + e] : 0.f;
-          A[g][u] = v;
-        }
+        for (int e = 0; e < TR; ++e) v[e] = (kv && m + e < Mtot) ? col[m + e] : 0.f;
+        A[u] = v;
       }
     }
   };
@@ -182,11 +93,11 @@ __global__ __launch_bounds__(NT, 2) void pm_left_f32(PmArgs a) {
   __syncthreads();
 
   const int nsteps = ntiles * SPT;
-  f4 Acur[MR][4], Anxt[MR][4];
+  vT Acur[4], Anxt[4];
   if (nsteps > 0) load_step(0, Acur);
   for (int t = 0; t < ntiles; ++t) {
     const float* kt = (t & 1) ? kt1 : kt0;
-#pragma unroll
+#pragma unroll 1
     for (int w = 0; w < SPT; ++w) {
       const int s = t * SPT + w;
       if (s + 1 < nsteps) load_step(s + 1, Anxt);
@@ -195,19 +106,19 @@ __global__ __launch_bounds__(NT, 2) void pm_left_f32(PmArgs a) {
 #pragma unroll
       for (int nb = 0; nb < NB; ++nb) B[nb] = *(const f4*)&kt[(16 * nb + li) * PITCH + kk];
 #pragma unroll
-      for (int u = 0; u < 4; ++u)
+      for (int tt = 0; tt < TR; ++tt)
 #pragma unroll
-        for (int g = 0; g < MR; ++g)
+        for (int nb = 0; nb < NB; ++nb) {
+          f4 c = mfma4(Acur[0][tt], B[nb][0], f4{0.f, 0.f, 0.f, 0.f});
+          c = mfma4(Acur[1][tt], B[nb][1], c);
+          c = mfma4(Acur[2][tt], B[nb][2], c);
+          c = mfma4(Acur[3][tt], B[nb][3], c);
 #pragma unroll
-          for (int tt = 0; tt < 4; ++tt)
-#pragma unroll
-            for (int nb = 0; nb < NB; ++nb)
-              acc[(g * 4 + tt) * NB + nb] = mfma4(Acur[g][u][tt], B[nb][u], acc[(g * 4 + tt) * NB + nb]);
+          for (int e = 0; e < 4; ++e) acc[tt * NB + nb][e] += (double)c[e];
+        }
       if (s + 1 < nsteps) {
 #pragma unroll
-        for (int g = 0; g < MR; ++g)
-#pragma unroll
-          for (int u = 0; u < 4; ++u) Acur[g][u] = Anxt[g][u];
+        for (int u = 0; u < 4; ++u) Acur[u] = Anxt[u];
       }
     }
     if (t + 1 < ntiles)
@@ -215,43 +126,28 @@ __global__ __launch_bounds__(NT, 2) void pm_left_f32(PmArgs a) {
     __syncthreads();
   }
 
-  wave_reduce_k<NACC>(acc, lds, wk, wm, WK, WM);
+  wave_reduce_k<NACC>(acc, (double*)lds, wk, wm, WK);
   if (wk != 0 && a.nsplit == 1) return;
 
-  // Output element of acc[(g*4+t)*NB+nb][v]: row mw + 64g + 16*lq + 4v + t, column 16nb + li.
+  // acc[tt*NB+nb][v]: row mw + TR*(4*lq + v) + tt, rank column 16nb + li.
   const bool direct = (a.nsplit == 1);
   const int64_t Mpad = (int64_t)gridDim.x * mtile;
   if (wk == 0) {
 #pragma unroll
-    for (int g = 0; g < MR; ++g)
+    for (int nb = 0; nb < NB; ++nb)
 #pragma unroll
-      for (int nb = 0; nb < NB; ++nb) {
-        const int r = 16 * nb + li;
+      for (int v = 0; v < 4; ++v)
 #pragma unroll
-        for (int v = 0; v < 4; ++v) {
-          const int64_t m = mw + 64 * g + 16 * lq + 4 * v;
-          f4 o = f4{acc[(g * 4 + 0) * NB + nb][v], acc[(g * 4 + 1) * NB + nb][v],
-                    acc[(g * 4 + 2) * NB + nb][v], acc[(g * 4 + 3) * NB + nb][v]};
-          if (direct) {
-            if (r < a.R) {
-              float* dst = a.T + Mtot * (int64_t)(a.col0 + r);
-#pragma unroll
-              for (int e = 0; e < 4; ++e)
-                if (m + e < Mtot) dst[m + e] = o[e];
-            }
-          } else {
-            *(f4*)&a.partial[((size_t)blockIdx.y * RP + r) * Mpad + m] = o;
-          }
-        }
-      }
+        for (int tt = 0; tt < TR; ++tt)
+          pm_store(a, direct, Mtot, Mpad, RP, 16 * nb + li, mw + TR * (4 * lq + v) + tt, acc[tt * NB + nb][v]);
   }
   if (!direct) splitk_finish(a, Mtot, mtile, mbeg, RP, Mpad);
 }
 
 // ----------------------------------------------------------------------------
-// Right side, FP32: T(c, r) = sum_k X[k + IL*c] * K(k, r); k is contiguous in X.
-// Wave tile: MC groups of 16 columns c. Lane (i, q) loads k = base + 16h + 4q + u
-// (u = 0..3 in one 16-byte load, h = 0..1) of column c = group + i.
+// Right side: T(c, r) = sum_k X[k + IL*c] * K(k, r); k is contiguous in X.
+// A wave covers MC groups of 16 columns c. Lane (i, q) loads k = base + 16h +
+// 4q + u (u = 0..3 in one 16-byte load, h = 0..1) of column c = group + i.
 // ----------------------------------------------------------------------------
 template <int NB, int MC, int WM, bool VEC>
 __global__ __launch_bounds__(NT, 2) void pm_right_f32(PmArgs a) {
@@ -282,9 +178,11 @@ __global__ __launch_bounds__(NT, 2) void pm_right_f32(PmArgs a) {
   for (int c = threadIdx.x; c < RP; c += NT) cs[c] = (c < a.R) ? krp_colscale(a.krp, a.col0 + c) : 0.0;
   __syncthreads();
 
-  f4 acc[NACC];
+  double acc[NACC][4];
 #pragma unroll
-  for (int v = 0; v < NACC; ++v) acc[v] = f4{0.f, 0.f, 0.f, 0.f};
+  for (int v = 0; v < NACC; ++v)
+#pragma unroll
+    for (int e = 0; e < 4; ++e) acc[v][e] = 0.0;
 
   auto load_step = [&](int s, f4 (&A)[MC][2]) {
     const int t = s / SPT, w = s % SPT;
@@ -318,24 +216,31 @@ __global__ __launch_bounds__(NT, 2) void pm_right_f32(PmArgs a) {
   if (nsteps > 0) load_step(0, Acur);
   for (int t = 0; t < ntiles; ++t) {
     const float* kt = (t & 1) ? kt1 : kt0;
-#pragma unroll
+#pragma unroll 1
     for (int w = 0; w < SPT; ++w) {
       const int s = t * SPT + w;
       if (s + 1 < nsteps) load_step(s + 1, Anxt);
       const int kk = wk * (BK / WK) + w * KS + 4 * lq;
+      f4 B[2][NB];
 #pragma unroll
-      for (int h = 0; h < 2; ++h) {
-        f4 B[NB];
+      for (int h = 0; h < 2; ++h)
 #pragma unroll
-        for (int nb = 0; nb < NB; ++nb) B[nb] = *(const f4*)&kt[(16 * nb + li) * PITCH + kk + 16 * h];
+        for (int nb = 0; nb < NB; ++nb) B[h][nb] = *(const f4*)&kt[(16 * nb + li) * PITCH + kk + 16 * h];
 #pragma unroll
-        for (int u = 0; u < 4; ++u)
+      for (int g = 0; g < MC; ++g)
 #pragma unroll
-          for (int g = 0; g < MC; ++g)
+        for (int nb = 0; nb < NB; ++nb) {
+          f4 c = mfma4(Acur[g][0][0], B[0][nb][0], f4{0.f, 0.f, 0.f, 0.f});
+          c = mfma4(Acur[g][0][1], B[0][nb][1], c);
+          c = mfma4(Acur[g][0][2], B[0][nb][2], c);
+          c = mfma4(Acur[g][0][3], B[0][nb][3], c);
+          c = mfma4(Acur[g][1][0], B[1][nb][0], c);
+          c = mfma4(Acur[g][1][1], B[1][nb][1], c);
+          c = mfma4(Acur[g][1][2], B[1][nb][2], c);
+          c = mfma4(Acur[g][1][3], B[1][nb][3], c);
 #pragma unroll
-            for (int nb = 0; nb < NB; ++nb)
-              acc[g * NB + nb] = mfma4(Acur[g][h][u], B[nb][u], acc[g * NB + nb]);
-      }
+          for (int e = 0; e < 4; ++e) acc[g * NB + nb][e] += (double)c[e];
+        }
       if (s + 1 < nsteps) {
 #pragma unroll
         for (int g = 0; g < MC; ++g)
@@ -348,7 +253,7 @@ __global__ __launch_bounds__(NT, 2) void pm_right_f32(PmArgs a) {
     __syncthreads();
   }
 
-  wave_reduce_k<NACC>(acc, lds, wk, wm, WK, WM);
+  wave_reduce_k<NACC>(acc, (double*)lds, wk, wm, WK);
   if (wk != 0 && a.nsplit == 1) return;
 
   // acc[g*NB+nb][v]: column c = cw + 16g + 4*lq + v, rank column 16nb + li.
@@ -358,98 +263,48 @@ __global__ __launch_bounds__(NT, 2) void pm_right_f32(PmArgs a) {
 #pragma unroll
     for (int g = 0; g < MC; ++g)
 #pragma unroll
-      for (int nb = 0; nb < NB; ++nb) {
-        const int r = 16 * nb + li;
-        const int64_t c = cw + 16 * g + 4 * lq;
-        f4 o = acc[g * NB + nb];
-        if (direct) {
-          if (r < a.R) {
-            float* dst = a.T + Mtot * (int64_t)(a.col0 + r);
+      for (int nb = 0; nb < NB; ++nb)
 #pragma unroll
-            for (int e = 0; e < 4; ++e)
-              if (c + e < Mtot) dst[c + e] = o[e];
-          }
-        } else {
-          *(f4*)&a.partial[((size_t)blockIdx.y * RP + r) * Mpad + c] = o;
-        }
-      }
+        for (int v = 0; v < 4; ++v)
+          pm_store(a, direct, Mtot, Mpad, RP, 16 * nb + li, cw + 16 * g + 4 * lq + v, acc[g * NB + nb][v]);
   }
   if (!direct) splitk_finish(a, Mtot, mtile, mbeg, RP, Mpad);
 }
 
-// Row groups (64 rows each) per wave on the left side: the accumulators of four
-// column blocks leave no room for a second group without spilling.
-constexpr int left_mr(int nb) { return nb >= 4 ? 1 : 2; }
-
-template <int NB>
-size_t pm_lds_bytes() {
-  return (size_t)2 * NB * 16 * PITCH * sizeof(float) + NB * 16 * sizeof(double);
-}
+// Rows per left wave = 16 * left_tr(NB); columns per right wave = 16 * right_mc(NB).
+// Chosen so that the FP64 accumulators (2 VGPRs per output) leave room for a
+// double-buffered k-step of X without spilling.
+constexpr int left_tr(int nb) { return nb >= 4 ? 2 : 4; }
+constexpr int right_mc(int nb) { return nb >= 4 ? 2 : 4; }
 
 template <int NB, int WM>
 hipError_t launch_f32(const PmLaunch& L, const PmArgs& a, bool vec, hipStream_t st) {
   dim3 grid(L.mtiles, L.nsplit), block(NT);
-  size_t lds = pm_lds_bytes<NB>();
-  // The cross-wave reduction reuses the tile buffers; they hold WM * NACC * 64 f4.
+  size_t lds = pm_lds_bytes(NB);
   if (L.side == 0) {
-    constexpr int MR = left_mr(NB);
-    constexpr int NACC = MR * 4 * NB;
-    size_t need = (size_t)WM * NACC * 64 * 16;
+    constexpr int TR = left_tr(NB);
+    const size_t need = (size_t)WM * TR * NB * 4 * 64 * sizeof(double);
     if (WM < 4 && need > lds) lds = need;
-    if (vec) hipLaunchKernelGGL((pm_left_f32<NB, MR, WM, true>), grid, block, lds, st, a);
-    else hipLaunchKernelGGL((pm_left_f32<NB, MR, WM, false>), grid, block, lds, st, a);
+    if (vec) hipLaunchKernelGGL((pm_left_f32<NB, TR, WM, true>), grid, block, lds, st, a);
+    else hipLaunchKernelGGL((pm_left_f32<NB, TR, WM, false>), grid, block, lds, st, a);
   } else {
-    constexpr int NACC = 4 * NB;
-    size_t need = (size_t)WM * NACC * 64 * 16;
+    constexpr int MC = right_mc(NB);
+    const size_t need = (size_t)WM * MC * NB * 4 * 64 * sizeof(double);
     if (WM < 4 && need > lds) lds = need;
-    if (vec) hipLaunchKernelGGL((pm_right_f32<NB, 4, WM, true>), grid, block, lds, st, a);
-    else hipLaunchKernelGGL((pm_right_f32<NB, 4, WM, false>), grid, block, lds, st, a);
+    if (vec) hipLaunchKernelGGL((pm_right_f32<NB, MC, WM, true>), grid, block, lds, st, a);
+    else hipLaunchKernelGGL((pm_right_f32<NB, MC, WM, false>), grid, block, lds, st, a);
   }
   return hipGetLastError();
 }
 
 }  // namespace
 
-// Tile/split heuristic: aim for >= ~4 work-groups per CU across the chip, keep each
-// split at least two tiles deep, and prefer the narrower M tile (one wave along
-// M, four along K) when the output has few rows.
-PmLaunch pm_plan(int side, int dtype, int64_t IL, int64_t IR, int R) {
-  PmLaunch L{};
-  L.side = side;
-  L.dtype = dtype;
-  const int Rc = R < kPmMaxCols ? R : kPmMaxCols;
-  L.nb = Rc <= 16 ? 1 : (Rc <= 32 ? 2 : 4);
-  const int64_t Mtot = side == 0 ? IL : IR;
-  const int64_t Ktot = side == 0 ? IR : IL;
-  const int wave_rows = side == 0 ? 64 * left_mr(L.nb) : 64;
-  const int64_t target = 1024;
-  int wm = 4;
-  if ((Mtot + 4 * wave_rows - 1) / (4 * wave_rows) < 64) wm = 1;
-  L.mtile = wm * wave_rows;
-  L.mtiles = (int)((Mtot + L.mtile - 1) / L.mtile);
-  const int64_t ktiles = (Ktot + BK - 1) / BK;
-  int64_t ns = (target + L.mtiles - 1) / L.mtiles;
-  int64_t maxs = ktiles / 2 > 0 ? ktiles / 2 : 1;
-  if (ns > maxs) ns = maxs;
-  if (ns > 256) ns = 256;
-  if (ns < 1) ns = 1;
-  int64_t tiles_per = (ktiles + ns - 1) / ns;
-  L.kchunk = tiles_per * BK;
-  L.nsplit = (int)((Ktot + L.kchunk - 1) / L.kchunk);
-  if (L.nsplit < 1) L.nsplit = 1;
-  L.partial_floats = L.nsplit > 1 ? (size_t)L.nsplit * L.nb * 16 * (size_t)L.mtiles * L.mtile : 0;
-  L.ncounters = L.mtiles;
-  return L;
-}
+int pm_f32_wave_rows(int side, int nb) { return side == 0 ? 16 * left_tr(nb) : 16 * right_mc(nb); }
 
-hipError_t pm_launch(const PmLaunch& L, const PmArgs& a, hipStream_t st) {
-  const int64_t Mtot = L.side == 0 ? a.IL : a.IR;
-  const int64_t Ktot = L.side == 0 ? a.IR : a.IL;
-  (void)Ktot;
-  bool vec = ((uintptr_t)a.X % 16 == 0) && ((L.side == 0 ? a.IL : a.IL) % 4 == 0);
-  (void)Mtot;
-  if (L.dtype != NNCP_F32) return hipErrorInvalidValue;
-  const int wm = L.mtile / (L.side == 0 ? 64 * left_mr(L.nb) : 64);
+hipError_t pm_launch_f32(const PmLaunch& L, const PmArgs& a, hipStream_t st) {
+  // vector loads need a 16-byte aligned base and I_L % 4 == 0 (every column aligned)
+  const bool vec = ((uintptr_t)a.X % 16 == 0) && (a.IL % 4 == 0);
+  const int wm = L.mtile / pm_f32_wave_rows(L.side, L.nb);
   switch (L.nb * 10 + (wm == 4 ? 4 : 1)) {
     case 14: return launch_f32<1, 4>(L, a, vec, st);
     case 11: return launch_f32<1, 1>(L, a, vec, st);

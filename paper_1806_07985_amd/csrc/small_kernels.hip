@@ -24,6 +24,15 @@ __device__ __forceinline__ double to_f64<__bf16>(__bf16 v) { return (double)(flo
 template <>
 __device__ __forceinline__ double to_f64<_Float16>(_Float16 v) { return (double)(float)v; }
 
+// Element i of a buffer that holds doubles (f64 != 0) or floats.
+__device__ __forceinline__ double ldv(const void* p, int64_t i, int f64) {
+  return f64 ? ((const double*)p)[i] : (double)((const float*)p)[i];
+}
+__device__ __forceinline__ void stv(void* p, int64_t i, int f64, double v) {
+  if (f64) ((double*)p)[i] = v;
+  else ((float*)p)[i] = (float)v;
+}
+
 __device__ __forceinline__ double block_sum(double v, double* sh) {
   for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
   const int w = threadIdx.x >> 6, l = threadIdx.x & 63;
@@ -107,6 +116,7 @@ __global__ void unit_lambda_kernel(double* lam, int64_t n) {
 // --------------------------------------------------------------------------
 constexpr int TRAIL_KCH = 1024;
 
+template <typename TN>
 __global__ __launch_bounds__(NT) void mttv_trail_kernel(MttvArgs a) {
   __shared__ double kv[TRAIL_KCH];
   __shared__ double red[4][64];
@@ -114,7 +124,7 @@ __global__ __launch_bounds__(NT) void mttv_trail_kernel(MttvArgs a) {
   const int ti = threadIdx.x & 63, ph = threadIdx.x >> 6;
   const int64_t i = (int64_t)blockIdx.x * 64 + ti;
   const double scale = krp_colscale(a.krp, r);
-  const float* Tr = a.T + (int64_t)r * a.Ia * a.J;
+  const TN* Tr = (const TN*)a.T + (int64_t)r * a.Ia * a.J;
   double acc = 0.0;
   for (int64_t j0 = 0; j0 < a.J; j0 += TRAIL_KCH) {
     const int cnt = (int)((a.J - j0) < TRAIL_KCH ? (a.J - j0) : TRAIL_KCH);
@@ -132,7 +142,7 @@ __global__ __launch_bounds__(NT) void mttv_trail_kernel(MttvArgs a) {
     }
     __syncthreads();
     if (i < a.Ia) {
-      const float* base = Tr + i + a.Ia * j0;
+      const TN* base = Tr + i + a.Ia * j0;
       int e = ph;
       for (; e + 12 < cnt; e += 16) {
         double t0 = base[a.Ia * e], t1 = base[a.Ia * (e + 4)];
@@ -149,7 +159,7 @@ __global__ __launch_bounds__(NT) void mttv_trail_kernel(MttvArgs a) {
   __syncthreads();
   if (ph == 0 && i < a.Ia) {
     double s = red[0][ti] + red[1][ti] + red[2][ti] + red[3][ti];
-    a.out[i + a.Ia * r] = (float)s;
+    stv(a.out, i + a.Ia * r, a.out_f64, s);
   }
 }
 
@@ -157,7 +167,7 @@ __global__ __launch_bounds__(NT) void mttv_trail_kernel(MttvArgs a) {
 // Multi-TTV, leading mode: out(j, r) = sum_i T(i, j, r) H(i, r), one lane group
 // of GS lanes per output (contiguous dot product, shuffle reduction).
 // --------------------------------------------------------------------------
-template <int GS>
+template <int GS, typename TN>
 __global__ __launch_bounds__(NT) void mttv_lead_kernel(MttvArgs a) {
   constexpr int OPB = NT / GS;
   const int g = threadIdx.x / GS, p = threadIdx.x % GS;
@@ -168,13 +178,13 @@ __global__ __launch_bounds__(NT) void mttv_lead_kernel(MttvArgs a) {
   if (o < total) {
     r = (int)(o / a.J);
     const int64_t j = o - (int64_t)r * a.J;
-    const float* Tc = a.T + a.Ia * (j + a.J * (int64_t)r);
+    const TN* Tc = (const TN*)a.T + a.Ia * (j + a.J * (int64_t)r);
     const float* Hc = a.krp.f[0] + a.Ia * (int64_t)r;
     for (int64_t i = p; i < a.Ia; i += GS) acc += (double)Tc[i] * (double)Hc[i];
   }
 #pragma unroll
   for (int off = GS / 2; off > 0; off >>= 1) acc += __shfl_xor(acc, off, GS);
-  if (p == 0 && o < total) a.out[o] = (float)(acc * krp_colscale(a.krp, r));
+  if (p == 0 && o < total) stv(a.out, o, a.out_f64, acc * krp_colscale(a.krp, r));
 }
 
 // --------------------------------------------------------------------------
@@ -207,7 +217,7 @@ __global__ __launch_bounds__(NT) void update_kernel(UpdateArgs a) {
       const double ls = a.lam_self[k];
       const double f = ls > 0.0 ? a.lam_model[k] / ls : 0.0;
       w[v] = (double)a.W[rr + a.I * k] * f;
-      m[v] = (double)a.M[rr + a.I * k];
+      m[v] = ldv(a.M, rr + a.I * k, a.m_f64);
     }
   }
   // g = w S (with the current w)
@@ -294,7 +304,7 @@ __global__ __launch_bounds__(NT) void finalize_kernel(FinalizeArgs a) {
       const int k = e / cnt, rw = e - k * cnt;
       const double wv = (double)a.W[s0 + rw + a.I * k];
       fl[rw * R + k] = wv;
-      if (a.do_fit && a.M) bsum += wv * (double)a.M[s0 + rw + a.I * k];
+      if (a.do_fit && a.M) bsum += wv * ldv(a.M, s0 + rw + a.I * k, a.m_f64);
     }
     __syncthreads();
 #pragma unroll
@@ -455,7 +465,8 @@ hipError_t unit_lambda_launch(double* lam, int64_t n, hipStream_t st) {
 hipError_t mttv_trail_launch(const MttvArgs& a, hipStream_t st) {
   if (a.Ia <= 0 || a.R <= 0) return hipSuccess;
   dim3 g((unsigned)((a.Ia + 63) / 64), a.R), b(NT);
-  hipLaunchKernelGGL(mttv_trail_kernel, g, b, 0, st, a);
+  if (a.t_f64) hipLaunchKernelGGL(mttv_trail_kernel<double>, g, b, 0, st, a);
+  else hipLaunchKernelGGL(mttv_trail_kernel<float>, g, b, 0, st, a);
   return hipGetLastError();
 }
 
@@ -466,13 +477,17 @@ hipError_t mttv_lead_launch(const MttvArgs& a, hipStream_t st) {
   while (gs < 64 && gs < a.Ia) gs <<= 1;
   const int64_t blocks = (outputs * gs + NT - 1) / NT;
   dim3 g((unsigned)blocks), b(NT);
+#define NNCP_LEAD(GSV)                                                           \
+  if (a.t_f64) hipLaunchKernelGGL((mttv_lead_kernel<GSV, double>), g, b, 0, st, a); \
+  else hipLaunchKernelGGL((mttv_lead_kernel<GSV, float>), g, b, 0, st, a);
   switch (gs) {
-    case 4: hipLaunchKernelGGL(mttv_lead_kernel<4>, g, b, 0, st, a); break;
-    case 8: hipLaunchKernelGGL(mttv_lead_kernel<8>, g, b, 0, st, a); break;
-    case 16: hipLaunchKernelGGL(mttv_lead_kernel<16>, g, b, 0, st, a); break;
-    case 32: hipLaunchKernelGGL(mttv_lead_kernel<32>, g, b, 0, st, a); break;
-    default: hipLaunchKernelGGL(mttv_lead_kernel<64>, g, b, 0, st, a); break;
+    case 4: NNCP_LEAD(4) break;
+    case 8: NNCP_LEAD(8) break;
+    case 16: NNCP_LEAD(16) break;
+    case 32: NNCP_LEAD(32) break;
+    default: NNCP_LEAD(64) break;
   }
+#undef NNCP_LEAD
   return hipGetLastError();
 }
 

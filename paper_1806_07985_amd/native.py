@@ -67,6 +67,8 @@ def _declare(L):
     L.nncp_plan_finish.argtypes = [c_vp, c_dp]
     L.nncp_plan_phase_ms.restype = ctypes.c_int
     L.nncp_plan_phase_ms.argtypes = [c_vp, c_dp]
+    L.nncp_plan_time_node.restype = ctypes.c_int
+    L.nncp_plan_time_node.argtypes = [c_vp, ctypes.c_int, ctypes.c_int, c_dp]
     L.nncp_plan_destroy.restype = ctypes.c_int
     L.nncp_plan_destroy.argtypes = [c_vp]
     L.nncp_quantize.restype = ctypes.c_int
@@ -253,6 +255,12 @@ class Plan:
         _check(lib().nncp_plan_phase_ms(self._h, ms), "nncp_plan_phase_ms")
         return dict(zip(["pm", "mttv", "nls", "gram", "err", "total"], list(ms)))
 
+    def time_node(self, mode: int, reps: int = 20) -> float:
+        """Average ms per launch of the node kernel computed before `mode`'s update."""
+        ms = ctypes.c_double(0.0)
+        _check(lib().nncp_plan_time_node(self._h, mode, reps, ctypes.byref(ms)), "nncp_plan_time_node")
+        return ms.value
+
     def close(self):
         if getattr(self, "_h", None):
             lib().nncp_plan_destroy(self._h)
@@ -286,7 +294,7 @@ def partial_mttkrp(X, dims, s, side, H, R, stream=None):
     IL = int(np.prod(dims[:s]))
     IR = int(np.prod(dims[s:]))
     rows = IL if side == 0 else IR
-    T = torch.empty((R, rows), dtype=torch.float32, device=X.device)
+    T = torch.empty((R, rows), dtype=torch.float64, device=X.device)
     _check(lib().nncp_partial_mttkrp(_ptr(X), _dtype_code(X), len(dims), _dims(dims), s, side, _ptr_array(H), R,
                                      _ptr(T), _stream(stream)), "nncp_partial_mttkrp")
     return T
@@ -294,10 +302,11 @@ def partial_mttkrp(X, dims, s, side, H, R, stream=None):
 
 def mttv(T, node_dims, kind, Hf, R, stream=None):
     import torch
+    _need(T, int(np.prod(node_dims)) * R, torch.float64, name="T")
     if kind == 0:
-        out = torch.empty((R, node_dims[0]), dtype=torch.float32, device=T.device)
+        out = torch.empty((R, node_dims[0]), dtype=torch.float64, device=T.device)
     else:
-        out = torch.empty((R, int(np.prod(node_dims[1:]))), dtype=torch.float32, device=T.device)
+        out = torch.empty((R, int(np.prod(node_dims[1:]))), dtype=torch.float64, device=T.device)
     _check(lib().nncp_mttv(_ptr(T), len(node_dims), _dims(node_dims), kind, _ptr_array(Hf), R, _ptr(out),
                            _stream(stream)), "nncp_mttv")
     return out
@@ -305,7 +314,7 @@ def mttv(T, node_dims, kind, Hf, R, stream=None):
 
 def mttkrp(X, dims, s, n, H, R, stream=None):
     import torch
-    M = torch.empty((R, dims[n]), dtype=torch.float32, device=X.device)
+    M = torch.empty((R, dims[n]), dtype=torch.float64, device=X.device)
     _check(lib().nncp_mttkrp(_ptr(X), _dtype_code(X), len(dims), _dims(dims), s, n, _ptr_array(H), R, _ptr(M),
                              _stream(stream)), "nncp_mttkrp")
     return M
@@ -319,8 +328,9 @@ def gram(H, I, R, stream=None):
 
 
 def nls_update(M, H, I, R, S, lam, update="hals", stream=None):
-    """In place: H <- normalised update; returns (lam, G) as device tensors."""
+    """In place: H <- normalised update; returns (lam, G) as device tensors. M is float64."""
     import torch
+    _need(M, I * R, torch.float64, name="M")
     lam_t = lam.clone()
     G = torch.empty((R, R), dtype=torch.float64, device=H.device)
     _check(lib().nncp_nls_update(_ptr(M), _ptr(H), I, R, _ptr(S), _ptr(lam_t), _UPDATE[update], _ptr(G),

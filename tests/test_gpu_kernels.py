@@ -2,9 +2,9 @@
 
 Inputs are seeded and synthetic; the oracle sees exactly the values the GPU
 sees (the FP32 tensor and FP32 factors, widened to FP64). Tolerances follow
-from the arithmetic: FP32 MFMA products accumulated in FP32 over one split
-(at most a few thousand terms) and then in FP64, so each MTTKRP entry is off
-by a few units of 2^-24 times sqrt(chain length) relative to sum |x k|.
+from the arithmetic: FP32 MFMA products summed in FP32 for 16 or 32 terms and
+then in FP64, so each MTTKRP entry is off by a few units of 2^-24 relative to
+sum |x k|; multi-TTV, Gram and update arithmetic are FP64.
 """
 
 import math
@@ -65,7 +65,7 @@ def test_partial_mttkrp_matches_oracle(gpu_lib, dims, R, s, side):
     print(f"case pm dims={dims} R={R} s={s} side={side}", flush=True)
     X, H = _setup(dims, R, seed=hash((dims, R, s)) % 1000)
     Xd, Hd = _to_gpu(X, H)
-    T = native.partial_mttkrp(Xd, list(dims), s, side, Hd, R).cpu().numpy().astype(np.float64).T
+    T = native.partial_mttkrp(Xd, list(dims), s, side, Hd, R).cpu().numpy().T
     X64 = X.astype(np.float64)
     H64 = [h.astype(np.float64) for h in H]
     fn = O.partial_mttkrp_left if side == 0 else O.partial_mttkrp_right
@@ -74,7 +74,8 @@ def test_partial_mttkrp_matches_oracle(gpu_lib, dims, R, s, side):
     bound = fn(np.abs(X64), [np.abs(h) for h in H64], s).reshape(-1, R, order="F")
     err = np.abs(T - ref)
     assert T.shape == ref.shape
-    assert np.all(err <= 2e-6 * bound + 1e-30), float(np.max(err / (bound + 1e-30)))
+    # FP32 products, FP64 sums after every 16-32 terms: well below 1e-6 of sum |x k|
+    assert np.all(err <= 1e-6 * bound + 1e-30), float(np.max(err / (bound + 1e-30)))
 
 
 def test_partial_mttkrp_signed_data(gpu_lib):
@@ -83,11 +84,11 @@ def test_partial_mttkrp_signed_data(gpu_lib):
     X, H = _setup(dims, R, seed=5, signed=True)
     Xd, Hd = _to_gpu(X, H)
     for side in (0, 1):
-        T = native.partial_mttkrp(Xd, list(dims), s, side, Hd, R).cpu().numpy().astype(np.float64).T
+        T = native.partial_mttkrp(Xd, list(dims), s, side, Hd, R).cpu().numpy().T
         fn = O.partial_mttkrp_left if side == 0 else O.partial_mttkrp_right
         ref = fn(X.astype(np.float64), [h.astype(np.float64) for h in H], s).reshape(-1, R, order="F")
         bound = fn(np.abs(X.astype(np.float64)), [h.astype(np.float64) for h in H], s).reshape(-1, R, order="F")
-        assert np.all(np.abs(T - ref) <= 2e-6 * bound)
+        assert np.all(np.abs(T - ref) <= 1e-6 * bound)
 
 
 @pytest.mark.parametrize("node_dims,R", [((30, 20, 10), 8), ((128, 128), 32), ((33, 9), 50), ((7, 5, 3, 2), 5),
@@ -96,19 +97,19 @@ def test_mttv_matches_oracle(gpu_lib, node_dims, R):
     import torch
     from paper_1806_07985_amd import native
     rng = np.random.default_rng(len(node_dims) * 100 + R)
-    T = rng.random(tuple(node_dims) + (R,)).astype(np.float32)
+    T = rng.random(tuple(node_dims) + (R,))
     Hs = [rng.random((d, R)).astype(np.float32) for d in node_dims]
     Td = native.tensor_to_device(T)
     # trailing: contract modes 2.. with their factors
     out = native.mttv(Td, list(node_dims), 0, [native.factor_to_device(h) for h in Hs[1:]], R)
-    ref = O.mttv_trail(T.astype(np.float64), [h.astype(np.float64) for h in Hs[1:]])
-    got = out.cpu().numpy().astype(np.float64).T
-    np.testing.assert_allclose(got, ref, rtol=2e-6)
+    ref = O.mttv_trail(T, [h.astype(np.float64) for h in Hs[1:]])
+    got = out.cpu().numpy().T
+    np.testing.assert_allclose(got, ref, rtol=1e-12)
     # leading: contract mode 1
     out = native.mttv(Td, list(node_dims), 1, [native.factor_to_device(Hs[0])], R)
-    ref = O.mttv_lead(T.astype(np.float64), Hs[0].astype(np.float64)).reshape(-1, R, order="F")
-    got = out.cpu().numpy().astype(np.float64).T
-    np.testing.assert_allclose(got, ref, rtol=2e-6)
+    ref = O.mttv_lead(T, Hs[0].astype(np.float64)).reshape(-1, R, order="F")
+    got = out.cpu().numpy().T
+    np.testing.assert_allclose(got, ref, rtol=1e-12)
 
 
 @pytest.mark.parametrize("dims,R", [((12, 10, 8), 4), ((9, 8, 7, 6), 8), ((6, 5, 4, 3, 5), 3), ((40, 30), 6)])
@@ -121,9 +122,9 @@ def test_tree_mttkrp_every_mode_and_split_matches_direct(gpu_lib, dims, R):
     for s in range(1, len(dims)):
         for n in range(len(dims)):
             print(f"case tree dims={dims} R={R} s={s} n={n}", flush=True)
-            M = native.mttkrp(Xd, list(dims), s, n, Hd, R).cpu().numpy().astype(np.float64).T
+            M = native.mttkrp(Xd, list(dims), s, n, Hd, R).cpu().numpy().T
             ref = O.mttkrp_direct(X64, H64, n)
-            np.testing.assert_allclose(M, ref, rtol=3e-6)
+            np.testing.assert_allclose(M, ref, rtol=5e-7)
 
 
 @pytest.mark.parametrize("I,R", [(1, 1), (37, 5), (128, 32), (1344, 50), (300, 64), (90, 100)])
@@ -145,15 +146,16 @@ def test_nls_update_matches_oracle(gpu_lib, update, I, R):
     S = K.T @ K
     S = S / np.sqrt(np.outer(np.diag(S), np.diag(S)))  # unit diagonal, like normalised factors
     A = rng.random((I, 4 * R + 10))
-    M = (A @ K / np.sqrt(np.diag(K.T @ K))).astype(np.float32)
+    M = A @ K / np.sqrt(np.diag(K.T @ K))
     Hn = rng.random((I, R)).astype(np.float32)
     lam = rng.random(R) + 0.5
     dev = torch.device("cuda:0")
     Hd = native.factor_to_device(Hn)
-    lam_t, G = native.nls_update(native.factor_to_device(M), Hd, I, R, torch.from_numpy(S).to(dev),
+    Md = torch.from_numpy(np.ascontiguousarray(M.T)).to(dev)
+    lam_t, G = native.nls_update(Md, Hd, I, R, torch.from_numpy(S).to(dev),
                                  torch.from_numpy(lam).to(dev), update)
     upd = O.hals_update if update == "hals" else O.mu_update
-    W = upd(Hn.astype(np.float64) * lam[None, :], S, M.astype(np.float64))
+    W = upd(Hn.astype(np.float64) * lam[None, :], S, M)
     Href, lref = O.normalize_columns(W)
     got = native.factor_to_host(Hd)
     assert np.linalg.norm(got - Href) <= 1e-6 * np.linalg.norm(Href)
