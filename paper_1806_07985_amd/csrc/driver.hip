@@ -44,13 +44,12 @@ struct Node {
 };
 
 struct Layout {
-  size_t off_alpha, off_iter, off_counters, off_lam, off_lammodel, off_lamin, off_G, off_S, off_fit,
+  size_t off_zeros, off_alpha, off_iter, off_counters, off_lam, off_lammodel, off_lamin, off_G, off_S, off_fit,
       off_finpart, off_pmpart, off_nspart, off_M, off_nodes, total;
   int ncounters;
   int64_t node_bytes[kMaxModes];
   int node_f64;  // tree temporaries are FP64 for FP32 tensors, FP32 for 16-bit tensors
   PmLaunch pmL[2];
-  int fin_chunks, fin_rows;
   int ns_blocks;
 };
 
@@ -130,16 +129,16 @@ Layout make_layout(const Problem& p) {
     o = align256(o + bytes);
     return at;
   };
-  L.pmL[0] = pm_plan(0, p.dtype, p.IL, p.IR, R);
-  L.pmL[1] = pm_plan(1, p.dtype, p.IL, p.IR, R);
-  L.fin_chunks = finalize_chunks(1, &L.fin_rows);
+  L.pmL[0] = pm_plan(0, p.dtype, p.IL, p.IR, (int)p.dims[p.s], R);
+  L.pmL[1] = pm_plan(1, p.dtype, p.IL, p.IR, (int)p.dims[0], R);
   int maxchunks = 1;
   for (int k = 0; k < N; ++k) {
     int rpc;
-    maxchunks = std::max(maxchunks, finalize_chunks(p.dims[k], &rpc));
+    maxchunks = std::max(maxchunks, finalize_chunks(p.dims[k], R, &rpc));
   }
   L.ns_blocks = norm_sq_blocks(p.I);
   L.ncounters = std::max(L.pmL[0].ncounters, L.pmL[1].ncounters) + 4;
+  L.off_zeros = take(256);
   L.off_alpha = take(sizeof(double));
   L.off_iter = take(sizeof(int));
   L.off_counters = take(sizeof(unsigned) * L.ncounters);
@@ -191,6 +190,7 @@ struct nncp_plan {
 
   template <typename T>
   T* at(size_t off) const { return (T*)(ws + off); }
+  unsigned* zeros() const { return at<unsigned>(L.off_zeros); }
   double* alpha() const { return at<double>(L.off_alpha); }
   int* iter() const { return at<int>(L.off_iter); }
   unsigned* counters() const { return at<unsigned>(L.off_counters); }
@@ -228,7 +228,7 @@ KrpDesc krp_for(const nncp_plan* P, int a, int b, bool scaled) {
 
 hipError_t run_pm(const nncp_plan* P, int side, void* T, int t_f64, const void* X, bool scaled, hipStream_t st) {
   const Problem& p = P->p;
-  const PmLaunch& pl = P->L.pmL[side];
+  const int I1 = (int)(side == 0 ? p.dims[p.s] : p.dims[0]);
   for (int c0 = 0; c0 < p.R; c0 += kPmMaxCols) {
     PmArgs a{};
     a.X = X;
@@ -240,16 +240,11 @@ hipError_t run_pm(const nncp_plan* P, int side, void* T, int t_f64, const void* 
     a.T = T;
     a.t_f64 = t_f64;
     a.partial = P->pmpart();
+    a.zeros = P->zeros();
     a.counters = P->counters();
-    a.nsplit = pl.nsplit;
-    a.kchunk = pl.kchunk;
-    PmLaunch l2 = pl;
-    if (a.R != p.R) {
-      l2 = pm_plan(side, p.dtype, p.IL, p.IR, a.R);
-    }
-    a.nsplit = l2.nsplit;
-    a.kchunk = l2.kchunk;
-    hipError_t e = pm_launch(l2, a, st);
+    const PmLaunch l = (a.R == std::min(kPmMaxCols, p.R)) ? P->L.pmL[side] : pm_plan(side, p.dtype, p.IL, p.IR, I1, a.R);
+    pm_fill_args(l, a);
+    hipError_t e = pm_launch(l, a, st);
     if (e != hipSuccess) return e;
   }
   return hipSuccess;
@@ -321,8 +316,7 @@ hipError_t finalize_mode(const nncp_plan* P, int n, const void* M, int m_f64, in
   f.iter_counter = P->iter();
   f.fit_capacity = kFitCap;
   f.partial = P->finpart();
-  f.counter = P->counters() + P->L.ncounters - 1;
-  f.nchunks = finalize_chunks(p.dims[n], &f.rows_per_chunk);
+  f.nchunks = finalize_chunks(p.dims[n], p.R, &f.rows_per_chunk);
   return finalize_launch(f, st);
 }
 
@@ -470,8 +464,9 @@ int nncp_plan_create(nncp_plan** out, const void* X, int dtype, int N, const int
   if (hipStreamCreateWithFlags(&P->cap_stream, hipStreamNonBlocking) != hipSuccess) return fail(NNCP_EDEVICE);
   if (hipEventCreateWithFlags(&P->ev[0], hipEventDisableTiming) != hipSuccess) return fail(NNCP_EDEVICE);
   if (hipEventCreateWithFlags(&P->ev[1], hipEventDisableTiming) != hipSuccess) return fail(NNCP_EDEVICE);
-  // zero counters, iteration counter
+  // zero counters, iteration counter, the zero block read by masked loads
   if (fill_u32_launch(P->counters(), P->L.ncounters, 0u, s) != hipSuccess) return fail(NNCP_EDEVICE);
+  if (fill_u32_launch(P->zeros(), 64, 0u, s) != hipSuccess) return fail(NNCP_EDEVICE);
   if (fill_u32_launch((unsigned*)P->iter(), 1, 0u, s) != hipSuccess) return fail(NNCP_EDEVICE);
   // lambda_in
   if (lambda_in) {
@@ -674,6 +669,7 @@ static int step_ctx(StepCtx& c, const void* X, int dtype, int N, const int64_t* 
   if (hipMalloc(&c.mem, c.P.L.total) != hipSuccess) return NNCP_ENOMEM;
   c.P.ws = (char*)c.mem;
   if (fill_u32_launch(c.P.counters(), c.P.L.ncounters, 0u, nullptr) != hipSuccess) return NNCP_EDEVICE;
+  if (fill_u32_launch(c.P.zeros(), 64, 0u, nullptr) != hipSuccess) return NNCP_EDEVICE;
   return NNCP_OK;
 }
 
@@ -753,7 +749,7 @@ int nncp_gram(const float* H, int64_t I, int R, double* G, void* stream) {
   if (!H || !G || I < 1 || R < 1 || R > kMaxRank) return NNCP_EINVAL;
   hipStream_t hs = (hipStream_t)stream;
   int rpc;
-  const int chunks = finalize_chunks(I, &rpc);
+  const int chunks = finalize_chunks(I, R, &rpc);
   const size_t RR = (size_t)R * R;
   size_t bytes = align256(sizeof(double) * chunks * (RR + 1)) + align256(sizeof(double) * RR) +
                  align256(sizeof(double) * R) * 2 + 256;
@@ -767,8 +763,6 @@ int nncp_gram(const float* H, int64_t I, int R, double* G, void* stream) {
   double* lam = (double*)(mem + o);
   o += align256(sizeof(double) * R);
   double* lamm = (double*)(mem + o);
-  o += align256(sizeof(double) * R);
-  unsigned* ctr = (unsigned*)(mem + o);
   FinalizeArgs f{};
   f.W = H;
   f.I = I;
@@ -781,13 +775,10 @@ int nncp_gram(const float* H, int64_t I, int R, double* G, void* stream) {
   f.next_mode = -1;
   f.gram_raw = G;
   f.partial = part;
-  f.counter = ctr;
   f.nchunks = chunks;
   f.rows_per_chunk = rpc;
   int st = NNCP_OK;
-  if (fill_u32_launch(ctr, 1, 0u, hs) != hipSuccess || finalize_launch(f, hs) != hipSuccess ||
-      hipStreamSynchronize(hs) != hipSuccess)
-    st = NNCP_EDEVICE;
+  if (finalize_launch(f, hs) != hipSuccess || hipStreamSynchronize(hs) != hipSuccess) st = NNCP_EDEVICE;
   hipFree(mem);
   return st;
 }
@@ -799,14 +790,13 @@ int nncp_nls_update(const double* M, float* H, int64_t I, int R, const double* S
     return NNCP_EINVAL;
   hipStream_t hs = (hipStream_t)stream;
   int rpc;
-  const int chunks = finalize_chunks(I, &rpc);
+  const int chunks = finalize_chunks(I, R, &rpc);
   const size_t RR = (size_t)R * R;
   size_t bytes = align256(sizeof(double) * chunks * (RR + 1)) + align256(sizeof(double) * R) * 2 + 256;
   char* mem = nullptr;
   if (hipMalloc(&mem, bytes) != hipSuccess) return NNCP_ENOMEM;
   double* part = (double*)mem;
   double* ones = (double*)(mem + align256(sizeof(double) * chunks * (RR + 1)));
-  unsigned* ctr = (unsigned*)((char*)ones + align256(sizeof(double) * R));
   int st = NNCP_OK;
   UpdateArgs u{};
   u.M = M;
@@ -829,10 +819,9 @@ int nncp_nls_update(const double* M, float* H, int64_t I, int R, const double* S
   f.lam_model = lambda;
   f.next_mode = -1;
   f.partial = part;
-  f.counter = ctr;
   f.nchunks = chunks;
   f.rows_per_chunk = rpc;
-  if (fill_f64_launch(ones, R, 1.0, hs) != hipSuccess || fill_u32_launch(ctr, 1, 0u, hs) != hipSuccess ||
+  if (fill_f64_launch(ones, R, 1.0, hs) != hipSuccess ||
       update_launch(u, hs) != hipSuccess || finalize_launch(f, hs) != hipSuccess ||
       normalize_out_launch(H, I, R, lambda, hs) != hipSuccess || hipStreamSynchronize(hs) != hipSuccess)
     st = NNCP_EDEVICE;

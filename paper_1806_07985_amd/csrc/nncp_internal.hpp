@@ -32,18 +32,28 @@ struct KrpDesc {
   int lam_ld;
 };
 
+// The reduction index k of a partial MTTKRP runs over the contracted modes
+// (krp.dim[0] fastest); it is split as k = i1 + I1*j with i1 the first contracted
+// mode's index and j the index over the remaining contracted modes. The operand
+// row is K(k, :) = H_1(i1, :) * Krest(j, :): the kernels keep the H_1 rows of
+// their i1 block in LDS and apply Krest(j, :) (times the column scales) as a
+// per-output-column factor when the FP32 MFMA partial sums are added into FP64.
 struct PmArgs {
   const void* X;
   int64_t IL, IR;        // X viewed as column-major IL x IR
-  KrpDesc krp;           // contracted modes
+  KrpDesc krp;           // contracted modes (first = fastest)
+  int I1, I1pad;         // extent of the first contracted mode, padded to the k-step
+  int i1blk, n_i1blk;    // i1 rows per split block, number of i1 blocks
+  int64_t J;             // product of the remaining contracted extents
+  int jblk, n_jblk;      // j per split block, number of j blocks
   int R;                 // columns handled by this launch (<= kPmMaxCols)
   int col0;              // first column (offset into factor columns)
   void* T;               // output, column-major, ld = Mtot: column c at T + Mtot*c
   int t_f64;             // T is double (else float)
   double* partial;       // split-K partials (FP64)
+  const void* zeros;     // >= 64 bytes of zeros in device memory (read by out-of-range lanes)
   unsigned* counters;    // one per M tile; zero on entry, left zero on exit
-  int nsplit;
-  int64_t kchunk;        // reduction range per split (multiple of the tile depth)
+  int nsplit;            // n_i1blk * n_jblk
 };
 
 // Plan of one partial-MTTKRP launch (tile shape and split count).
@@ -54,12 +64,17 @@ struct PmLaunch {
   int mtile;     // output rows per work-group
   int mtiles;
   int nsplit;
-  int64_t kchunk;
+  int I1, I1pad, i1blk, n_i1blk, jblk, n_jblk;
+  int64_t J;
+  size_t lds_bytes;
   size_t partial_doubles;
   int ncounters;
 };
 
-PmLaunch pm_plan(int side, int dtype, int64_t IL, int64_t IR, int R);
+// I1 = extent of the first contracted mode (mode s+1 for the left node, mode 1
+// for the right node).
+PmLaunch pm_plan(int side, int dtype, int64_t IL, int64_t IR, int I1, int R);
+void pm_fill_args(const PmLaunch& L, PmArgs& a);
 hipError_t pm_launch(const PmLaunch& L, const PmArgs& a, hipStream_t st);
 // per-dtype kernels (pm_kernels.hip, pm16_kernels.hip)
 int pm_f32_wave_rows(int side, int nb);
@@ -116,11 +131,10 @@ struct FinalizeArgs {
   // scratch
   double* gram_raw;       // optional: W^T W (unnormalised) written here
   double* partial;        // nchunks x (R*R + 1)
-  unsigned* counter;      // zero on entry, left zero
   int nchunks;
   int rows_per_chunk;
 };
-int finalize_chunks(int64_t I, int* rows_per_chunk);
+int finalize_chunks(int64_t I, int R, int* rows_per_chunk);
 hipError_t finalize_launch(const FinalizeArgs& a, hipStream_t st);
 
 // lam_model = lam_in * prod_k lam[k]; S[0] = prod_{k != 0} G[k]

@@ -3,6 +3,8 @@
 
 namespace nncpk {
 int pm_16_wave_rows(int side, int nb) { (void)side; (void)nb; return 64; }
+int pm_16_kstep(int side) { return side == 0 ? 32 : 32; }
+int pm_16_blocks_per_cu(int side, int nb, int wm, size_t lds) { (void)side; (void)nb; (void)wm; (void)lds; return 2; }
 hipError_t pm_launch_16(const PmLaunch& L, const PmArgs& a, hipStream_t st) {
   (void)L; (void)a; (void)st;
   return hipErrorInvalidValue;

@@ -6,93 +6,45 @@
 namespace nncpk {
 
 typedef float f4 __attribute__((ext_vector_type(4)));
+typedef float f2 __attribute__((ext_vector_type(2)));
 
-constexpr int BK = 128;          // Khatri-Rao tile depth (operand rows per LDS tile)
-constexpr int PITCH = BK + 4;    // floats per tile column in LDS (FP32 tiles)
 constexpr int NT = 256;          // threads per work-group (4 waves)
 
 __device__ __forceinline__ f4 mfma4(float a, float b, f4 c) {
   return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
 }
 
-// Operand-row digits: row k of a Khatri-Rao operand over nm modes (first mode
-// fastest) picks row d_j of factor j.
-__device__ __forceinline__ void krp_digits(const KrpDesc& krp, uint32_t k, int* d) {
-#pragma unroll
-  for (int j = 0; j < kMaxModes; ++j) {
-    if (j < krp.nm) {
-      const uint32_t dj = (uint32_t)krp.dim[j];
-      const uint32_t q = k / dj;
-      d[j] = (int)(k - q * dj);
-      k = q;
-    }
+// Digits of index j over the contracted modes 1..nm-1 (mode 1 fastest) and the
+// product of those factors' entries in column `col`, in FP64.
+__device__ __forceinline__ double krest_value(const KrpDesc& krp, uint32_t j, int col) {
+  double p = 1.0;
+  for (int m = 1; m < krp.nm; ++m) {
+    const uint32_t d = (uint32_t)krp.dim[m];
+    const uint32_t q = j / d;
+    p *= (double)krp.f[m][(int64_t)(j - q * d) + (int64_t)krp.dim[m] * col];
+    j = q;
   }
-}
-
-// Value of the (scaled) operand at digits d, column col (computed in FP64).
-__device__ __forceinline__ double krp_value(const KrpDesc& krp, const int* d, int col, double scale) {
-  double p = scale;
-#pragma unroll
-  for (int j = 0; j < kMaxModes; ++j)
-    if (j < krp.nm) p *= (double)krp.f[j][(int64_t)d[j] + (int64_t)krp.dim[j] * col];
   return p;
 }
 
-// Build rows [k0, k0+BK) of the Khatri-Rao operand into the FP32 LDS tile `kt`
-// (layout kt[col * PITCH + k]). Rows at or beyond kend and columns >= R are zero.
-template <int NB>
-__device__ __forceinline__ void build_tile(float* kt, const KrpDesc& krp, const double* cs,
-                                           int64_t k0, int64_t kend, int R, int col0) {
-  constexpr int RP = NB * 16;
-  const int kl = threadIdx.x % BK;
-  const int c0 = threadIdx.x / BK;
-  const int64_t k = k0 + kl;
-  int d[kMaxModes];
-  const bool valid = k < kend;
-  if (valid) krp_digits(krp, (uint32_t)k, d);
-  for (int c = c0; c < RP; c += NT / BK) {
-    float v = 0.f;
-    if (valid && c < R) v = (float)krp_value(krp, d, col0 + c, cs[c]);
-    kt[c * PITCH + kl] = v;
+// LDS prologue shared by the FP32 kernels: the block's rows of the first
+// contracted factor, hs[r * hp + i] = H_1(i1_0 + i, col0 + r) (zero padded), and
+// the per-(j, column) scales sc[jj * RP + r] = Krest(j0 + jj, col0 + r) times the
+// column's 1/lambda product.
+__device__ __forceinline__ void pm_prologue(const PmArgs& a, float* hs, int hp, double* sc, int RP, int i1_0,
+                                            int i1n, int64_t j0, int jn) {
+  const float* f0 = a.krp.f[0];
+  for (int e = threadIdx.x; e < RP * i1n; e += NT) {
+    const int r = e / i1n, i = e - r * i1n;
+    const int i1 = i1_0 + i;
+    hs[r * hp + i] = (r < a.R && i1 < a.I1) ? f0[(int64_t)i1 + (int64_t)a.I1 * (a.col0 + r)] : 0.f;
   }
-}
-
-// Deterministic split-K epilogue: the group has written its FP64 partial; the
-// last group of the M tile to arrive sums all splits in split order into T.
-template <typename TO>
-__device__ void splitk_finish_t(const PmArgs& a, int64_t Mtot, int mtile, int64_t mbeg, int RP,
-                                int64_t Mpad) {
-  __shared__ int s_last;
-  __threadfence();
-  __syncthreads();
-  if (threadIdx.x == 0) {
-    unsigned prev = __hip_atomic_fetch_add(&a.counters[blockIdx.x], 1u, __ATOMIC_ACQ_REL,
-                                           __HIP_MEMORY_SCOPE_AGENT);
-    s_last = (prev == (unsigned)(a.nsplit - 1));
+  for (int e = threadIdx.x; e < jn * RP; e += NT) {
+    const int jj = e / RP, r = e - jj * RP;
+    double v = 0.0;
+    if (r < a.R) v = krp_colscale(a.krp, a.col0 + r) * krest_value(a.krp, (uint32_t)(j0 + jj), a.col0 + r);
+    sc[e] = v;
   }
-  __syncthreads();
-  if (!s_last) return;
-  __threadfence();
-  const int64_t rows = (Mtot - mbeg) < mtile ? (Mtot - mbeg) : mtile;
-  const int64_t total = rows * a.R;
-  const size_t sstride = (size_t)RP * (size_t)Mpad;
-  TO* T = (TO*)a.T;
-  for (int64_t e = threadIdx.x; e < total; e += NT) {
-    const int r = (int)(e / rows);
-    const int64_t m = mbeg + (e - (int64_t)r * rows);
-    const double* p = a.partial + (size_t)r * Mpad + m;
-    double s = 0.0;
-    for (int sp = 0; sp < a.nsplit; ++sp) s += __builtin_nontemporal_load(p + sp * sstride);
-    T[m + Mtot * (int64_t)(a.col0 + r)] = (TO)s;
-  }
-  if (threadIdx.x == 0)
-    __hip_atomic_store(&a.counters[blockIdx.x], 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-}
-
-__device__ __forceinline__ void splitk_finish(const PmArgs& a, int64_t Mtot, int mtile, int64_t mbeg, int RP,
-                                              int64_t Mpad) {
-  if (a.t_f64) splitk_finish_t<double>(a, Mtot, mtile, mbeg, RP, Mpad);
-  else splitk_finish_t<float>(a, Mtot, mtile, mbeg, RP, Mpad);
 }
 
 // Sum the FP64 accumulators of the WK waves that share an M range through LDS;
@@ -133,8 +85,11 @@ __device__ __forceinline__ void pm_store(const PmArgs& a, bool direct, int64_t M
   }
 }
 
-inline size_t pm_lds_bytes(int nb) {
-  return (size_t)2 * nb * 16 * PITCH * sizeof(float) + nb * 16 * sizeof(double);
+// Split of a flat step range [0, n) into WK contiguous parts.
+__device__ __forceinline__ void wave_range(int n, int wk, int WK, int* b, int* e) {
+  const int per = (n + WK - 1) / WK;
+  *b = wk * per < n ? wk * per : n;
+  *e = (wk + 1) * per < n ? (wk + 1) * per : n;
 }
 
 }  // namespace nncpk

@@ -1,65 +1,70 @@
-// Partial MTTKRP on MFMA for FP32 tensors (the root edges of the dimension
-// tree, Section IV-A, Figure 2a): T = X_[L] * K (left node) or
-// T = X_[L]^T * K (right node), where X_[L] is the tensor viewed as the
-// column-major I_L x I_R matrix (modes 1..s on the rows) and K is the
-// Khatri-Rao product of the other side's factors.
+// Partial MTTKRP on MFMA for FP32 tensors: the root edges of the dimension tree
+// (Section IV-A, Figure 2a), T = X_[L] * K (left node {1..s}) or
+// T = X_[L]^T * K (right node {s+1..N}), where X_[L] is the tensor viewed as the
+// column-major I_L x I_R matrix and K the Khatri-Rao product of the other
+// side's factors (first contracted mode fastest).
 //
 // Design (gfx950, wave64):
-//  * The reduction index k runs over X's columns (left) or rows (right). The
-//    Khatri-Rao operand is never materialised in HBM: each work-group forms a
-//    BK x R tile of it in LDS from factor rows (double-buffered), and every wave
-//    of the group reads its MFMA B operand from that tile.
-//  * X is streamed straight from HBM into VGPRs with 8- or 16-byte loads, one
-//    k-step ahead of the MFMAs (v_mfma_f32_16x16x4_f32). The k order inside a
-//    16- or 32-wide k-step is permuted so that one wide load per lane feeds
-//    several MFMAs while A and B agree on which k sits in which slot.
-//  * Precision: each MFMA chain covers one k-step only (4 or 8 MFMAs, 16 or 32
-//    products per output) and is then added into FP64 accumulators, so the FP32
-//    rounding of a running sum never spans more than 32 terms; split-K
-//    partials, the cross-wave reduction and the output are FP64.
-//  * Split-K over work-groups; the last work-group to finish an output tile
-//    (device-scope counter) sums the partials in split order, so results do
-//    not depend on scheduling.
+//  * The reduction index is split as k = i1 + I1*j (i1: first contracted mode).
+//    K(k, :) = H_1(i1, :) * Krest(j, :), so a work-group keeps the H_1 rows of
+//    its i1 block in LDS for the whole kernel (the MFMA B operand), and applies
+//    Krest(j, :) as a per-column factor when it folds each k-step's FP32 MFMA
+//    result into FP64 accumulators (one v_fma_f64 per output). The Khatri-Rao
+//    product is never formed, and the main loop has no barrier.
+//  * X streams from HBM straight into VGPRs with 8/16-byte loads, two k-steps
+//    ahead of the MFMAs (v_mfma_f32_16x16x4_f32), with no branches around the
+//    loads (out-of-range lanes read a valid address and are zeroed).
+//  * Precision: each MFMA chain covers one k-step (16 or 32 products per
+//    output) before it is added into FP64; split-K partials, the cross-wave
+//    reduction and the output are FP64.
+//  * Split-K over (i1 block, j block) pairs: each work-group writes an FP64
+//    partial; a separate reduction kernel sums them in split order, so results
+//    do not depend on scheduling and no cross-XCD fence is needed.
 #include "pm_common.hpp"
 
 namespace nncpk {
 namespace {
 
 // ----------------------------------------------------------------------------
-// Left side: T(m, r) = sum_k X[m + IL*k] * K(k, r); m is contiguous in X.
-// A wave covers 16*TR rows. Lane (i, q) loads rows TR*i .. TR*i+TR-1 of column
-// k = base + 4q + u (u = 0..3); MFMA t uses row TR*i + t of that load.
+// Left side: T(m, r) = sum_k X[m + IL*k] K(k, r); m is contiguous in X.
+// A wave covers 16*TR rows m. In a k-step (16 consecutive i1 of one j), lane
+// (li, lq) loads rows TR*li .. TR*li+TR-1 of the columns i1 = base + 4*lq + u,
+// u = 0..3; MFMA chain tt uses row TR*li + tt of every load.
 // ----------------------------------------------------------------------------
-template <int NB, int TR, int WM, bool VEC>
+template <int NB, int TR, int WM, bool VEC, int D>
 __global__ __launch_bounds__(NT, 2) void pm_left_f32(PmArgs a) {
   constexpr int RP = NB * 16;
   constexpr int WK = 4 / WM;
-  constexpr int KS = 16;                  // k per k-step
-  constexpr int SPT = BK / WK / KS;       // k-steps per tile per wave
-  constexpr int NACC = TR * NB;           // 4-element accumulators per lane
+  constexpr int KS = 16;
+  constexpr int NACC = TR * NB;
   constexpr int WROWS = 16 * TR;
-  static_assert(SPT >= 1, "tile too shallow");
   typedef float vT __attribute__((ext_vector_type(TR)));
-  extern __shared__ float lds[];
-  float* kt0 = lds;
-  float* kt1 = lds + RP * PITCH;
-  double* cs = (double*)(lds + 2 * RP * PITCH);
+  extern __shared__ double lds_d[];
+  const int hp = a.i1blk + 4;
+  float* hs = (float*)lds_d;
+  double* sc = lds_d + (RP * hp + 1) / 2;
 
-  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int lane = threadIdx.x & 63;
+  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   const int wm = wave % WM, wk = wave / WM;
   const int li = lane & 15, lq = lane >> 4;
-  const int64_t Mtot = a.IL, Ktot = a.IR;
+  const int64_t Mtot = a.IL;
   const int mtile = WM * WROWS;
   const int64_t mbeg = (int64_t)blockIdx.x * mtile;
   const int64_t mw = mbeg + wm * WROWS;
-  const int64_t kbeg = (int64_t)blockIdx.y * a.kchunk;
-  int64_t kend = kbeg + a.kchunk;
-  if (kend > Ktot) kend = Ktot;
-  const int ntiles = (int)((kend - kbeg + BK - 1) / BK);
+  const int ib = blockIdx.y % a.n_i1blk, jb = blockIdx.y / a.n_i1blk;
+  const int i1_0 = ib * a.i1blk;
+  const int i1n = min(a.i1blk, a.I1pad - i1_0);
+  const int64_t j0 = (int64_t)jb * a.jblk;
+  const int jn = (int)min((int64_t)a.jblk, a.J - j0);
   const float* X = (const float*)a.X;
 
-  for (int c = threadIdx.x; c < RP; c += NT) cs[c] = (c < a.R) ? krp_colscale(a.krp, a.col0 + c) : 0.0;
+  pm_prologue(a, hs, hp, sc, RP, i1_0, i1n, j0, jn);
   __syncthreads();
+
+  const int S1 = i1n / KS;
+  int sb, se;
+  wave_range(S1 * jn, wk, WK, &sb, &se);
 
   double acc[NACC][4];
 #pragma unroll
@@ -68,70 +73,96 @@ __global__ __launch_bounds__(NT, 2) void pm_left_f32(PmArgs a) {
     for (int e = 0; e < 4; ++e) acc[v][e] = 0.0;
 
   const int64_t m = mw + TR * li;
-  const bool mfull = m + TR <= Mtot;
-  auto load_step = [&](int s, vT (&A)[4]) {
-    const int t = s / SPT, w = s % SPT;
-    const int64_t kb = kbeg + (int64_t)t * BK + wk * (BK / WK) + w * KS + 4 * lq;
+  const int64_t mload = (m + TR <= Mtot) ? m : 0;
+  const int ilim = a.I1 - i1_0;  // lane i1 offsets >= ilim are padding
+  const float* zeros = (const float*)a.zeros;
+  // lane part of the address of column (colbase + 4*lq + u): loop invariant
+  int64_t lane_off[4];
+#pragma unroll
+  for (int u = 0; u < 4; ++u) lane_off[u] = Mtot * (int64_t)(4 * lq + u) + (VEC ? mload : 0);
+
+  // load cursor (uniform): step = jl * S1 + tl
+  int jl = sb / S1, tl = sb - (sb / S1) * S1;
+  auto load = [&](vT (&A)[4], bool sv) {
+    const int64_t colbase = (int64_t)a.I1 * (j0 + jl) + i1_0 + KS * tl;
+    const float* base = X + Mtot * colbase;
 #pragma unroll
     for (int u = 0; u < 4; ++u) {
-      const int64_t k = kb + u;
-      const bool kv = k < kend;
-      const float* col = X + Mtot * (kv ? k : 0);
+      const bool kv = sv && (KS * tl + 4 * lq + u) < ilim;
       if (VEC) {
-        if (kv && mfull) A[u] = __builtin_nontemporal_load((const vT*)(col + m));
-        else A[u] = vT{};
+        const float* p = kv ? base + lane_off[u] : zeros;
+        A[u] = __builtin_nontemporal_load((const vT*)p);
       } else {
         vT v;
 #pragma unroll
-        for (int e = 0; e < TR; ++e) v[e] = (kv && m + e < Mtot) ? col[m + e] : 0.f;
+        for (int e = 0; e < TR; ++e) {
+          const float* p = (kv && m + e < Mtot) ? base + lane_off[u] + m + e : zeros;
+          v[e] = *p;
+        }
         A[u] = v;
       }
     }
+    if (++tl == S1) {
+      tl = 0;
+      ++jl;
+    }
+  };
+  int jc = jl, tc = tl;
+  auto compute = [&](const vT (&A)[4]) {
+    const int kk = KS * tc + 4 * lq;
+    f4 B[NB];
+    double scl[NB];
+#pragma unroll
+    for (int nb = 0; nb < NB; ++nb) {
+      B[nb] = *(const f4*)&hs[(16 * nb + li) * hp + kk];
+      scl[nb] = sc[jc * RP + 16 * nb + li];
+    }
+#pragma unroll
+    for (int tt = 0; tt < TR; ++tt)
+#pragma unroll
+      for (int nb = 0; nb < NB; ++nb) {
+        f4 c = mfma4(A[0][tt], B[nb][0], f4{0.f, 0.f, 0.f, 0.f});
+        c = mfma4(A[1][tt], B[nb][1], c);
+        c = mfma4(A[2][tt], B[nb][2], c);
+        c = mfma4(A[3][tt], B[nb][3], c);
+#pragma unroll
+        for (int e = 0; e < 4; ++e) acc[tt * NB + nb][e] = __builtin_fma((double)c[e], scl[nb], acc[tt * NB + nb][e]);
+      }
+    if (++tc == S1) {
+      tc = 0;
+      ++jc;
+    }
   };
 
-  build_tile<NB>(kt0, a.krp, cs, kbeg, kend, a.R, a.col0);
-  __syncthreads();
-
-  const int nsteps = ntiles * SPT;
-  vT Acur[4], Anxt[4];
-  if (nsteps > 0) load_step(0, Acur);
-  for (int t = 0; t < ntiles; ++t) {
-    const float* kt = (t & 1) ? kt1 : kt0;
-#pragma unroll 1
-    for (int w = 0; w < SPT; ++w) {
-      const int s = t * SPT + w;
-      if (s + 1 < nsteps) load_step(s + 1, Anxt);
-      const int kk = wk * (BK / WK) + w * KS + 4 * lq;
-      f4 B[NB];
+  // D k-steps of X in flight: the loads of step s+D are issued right after step
+  // s is consumed. sched_barrier keeps the compiler from sinking them.
+  vT A[D][4];
+  int s = sb;
+  if (sb < se) {
 #pragma unroll
-      for (int nb = 0; nb < NB; ++nb) B[nb] = *(const f4*)&kt[(16 * nb + li) * PITCH + kk];
-#pragma unroll
-      for (int tt = 0; tt < TR; ++tt)
-#pragma unroll
-        for (int nb = 0; nb < NB; ++nb) {
-          f4 c = mfma4(Acur[0][tt], B[nb][0], f4{0.f, 0.f, 0.f, 0.f});
-          c = mfma4(Acur[1][tt], B[nb][1], c);
-          c = mfma4(Acur[2][tt], B[nb][2], c);
-          c = mfma4(Acur[3][tt], B[nb][3], c);
-#pragma unroll
-          for (int e = 0; e < 4; ++e) acc[tt * NB + nb][e] += (double)c[e];
-        }
-      if (s + 1 < nsteps) {
-#pragma unroll
-        for (int u = 0; u < 4; ++u) Acur[u] = Anxt[u];
-      }
-    }
-    if (t + 1 < ntiles)
-      build_tile<NB>((t & 1) ? kt0 : kt1, a.krp, cs, kbeg + (int64_t)(t + 1) * BK, kend, a.R, a.col0);
-    __syncthreads();
+    for (int d = 0; d < D; ++d) load(A[d], sb + d < se);
   }
+  for (; s + D - 1 < se; s += D) {
+#pragma unroll
+    for (int d = 0; d < D; ++d) {
+      compute(A[d]);
+      __builtin_amdgcn_sched_barrier(0);
+      load(A[d], s + D + d < se);
+      __builtin_amdgcn_sched_barrier(0);
+    }
+  }
+#pragma unroll
+  for (int d = 0; d < D - 1; ++d)
+    if (s + d < se) compute(A[d]);
 
-  wave_reduce_k<NACC>(acc, (double*)lds, wk, wm, WK);
+  __syncthreads();  // LDS is reused by the cross-wave reduction
+  wave_reduce_k<NACC>(acc, lds_d, wk, wm, WK);
   if (wk != 0 && a.nsplit == 1) return;
 
   // acc[tt*NB+nb][v]: row mw + TR*(4*lq + v) + tt, rank column 16nb + li.
   const bool direct = (a.nsplit == 1);
   const int64_t Mpad = (int64_t)gridDim.x * mtile;
+  (void)mbeg;
   if (wk == 0) {
 #pragma unroll
     for (int nb = 0; nb < NB; ++nb)
@@ -141,42 +172,46 @@ __global__ __launch_bounds__(NT, 2) void pm_left_f32(PmArgs a) {
         for (int tt = 0; tt < TR; ++tt)
           pm_store(a, direct, Mtot, Mpad, RP, 16 * nb + li, mw + TR * (4 * lq + v) + tt, acc[tt * NB + nb][v]);
   }
-  if (!direct) splitk_finish(a, Mtot, mtile, mbeg, RP, Mpad);
 }
 
 // ----------------------------------------------------------------------------
-// Right side: T(c, r) = sum_k X[k + IL*c] * K(k, r); k is contiguous in X.
-// A wave covers MC groups of 16 columns c. Lane (i, q) loads k = base + 16h +
-// 4q + u (u = 0..3 in one 16-byte load, h = 0..1) of column c = group + i.
+// Right side: T(c, r) = sum_k X[k + IL*c] K(k, r); k is contiguous in X.
+// A wave covers MC groups of 16 columns c. In a k-step (32 consecutive i1 of
+// one j), lane (li, lq) loads k = base + 16h + 4*lq + u (u = 0..3 in one
+// 16-byte load, h = 0..1) of column c = group + li.
 // ----------------------------------------------------------------------------
-template <int NB, int MC, int WM, bool VEC>
+template <int NB, int MC, int WM, bool VEC, int D>
 __global__ __launch_bounds__(NT, 2) void pm_right_f32(PmArgs a) {
   constexpr int RP = NB * 16;
   constexpr int WK = 4 / WM;
   constexpr int KS = 32;
-  constexpr int SPT = BK / WK / KS;
   constexpr int NACC = MC * NB;
-  static_assert(SPT >= 1, "tile too shallow");
-  extern __shared__ float lds[];
-  float* kt0 = lds;
-  float* kt1 = lds + RP * PITCH;
-  double* cs = (double*)(lds + 2 * RP * PITCH);
+  extern __shared__ double lds_d[];
+  const int hp = a.i1blk + 4;
+  float* hs = (float*)lds_d;
+  double* sc = lds_d + (RP * hp + 1) / 2;
 
-  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int lane = threadIdx.x & 63;
+  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   const int wm = wave % WM, wk = wave / WM;
   const int li = lane & 15, lq = lane >> 4;
   const int64_t Mtot = a.IR, Ktot = a.IL;
   const int mtile = WM * 16 * MC;
   const int64_t mbeg = (int64_t)blockIdx.x * mtile;
   const int64_t cw = mbeg + wm * 16 * MC;
-  const int64_t kbeg = (int64_t)blockIdx.y * a.kchunk;
-  int64_t kend = kbeg + a.kchunk;
-  if (kend > Ktot) kend = Ktot;
-  const int ntiles = (int)((kend - kbeg + BK - 1) / BK);
+  const int ib = blockIdx.y % a.n_i1blk, jb = blockIdx.y / a.n_i1blk;
+  const int i1_0 = ib * a.i1blk;
+  const int i1n = min(a.i1blk, a.I1pad - i1_0);
+  const int64_t j0 = (int64_t)jb * a.jblk;
+  const int jn = (int)min((int64_t)a.jblk, a.J - j0);
   const float* X = (const float*)a.X;
 
-  for (int c = threadIdx.x; c < RP; c += NT) cs[c] = (c < a.R) ? krp_colscale(a.krp, a.col0 + c) : 0.0;
+  pm_prologue(a, hs, hp, sc, RP, i1_0, i1n, j0, jn);
   __syncthreads();
+
+  const int S1 = i1n / KS;
+  int sb, se;
+  wave_range(S1 * jn, wk, WK, &sb, &se);
 
   double acc[NACC][4];
 #pragma unroll
@@ -184,81 +219,103 @@ __global__ __launch_bounds__(NT, 2) void pm_right_f32(PmArgs a) {
 #pragma unroll
     for (int e = 0; e < 4; ++e) acc[v][e] = 0.0;
 
-  auto load_step = [&](int s, f4 (&A)[MC][2]) {
-    const int t = s / SPT, w = s % SPT;
-    const int64_t kb = kbeg + (int64_t)t * BK + wk * (BK / WK) + w * KS + 4 * lq;
+  const float* colp[MC];
 #pragma unroll
-    for (int g = 0; g < MC; ++g) {
-      const int64_t c = cw + 16 * g + li;
-      const bool cv = c < Mtot;
-      const float* col = X + Ktot * (cv ? c : 0);
+  for (int g = 0; g < MC; ++g) {
+    const int64_t c = cw + 16 * g + li;
+    colp[g] = X + Ktot * (c < Mtot ? c : 0) + 4 * lq;
+  }
+  const int ilim = a.I1 - i1_0;
+  const float* zeros = (const float*)a.zeros;
+
+  int jl = sb / S1, tl = sb - (sb / S1) * S1;
+  auto load = [&](f4 (&A)[MC][2], bool sv) {
+    const int64_t lbase = (int64_t)a.I1 * (j0 + jl) + i1_0 + KS * tl;
 #pragma unroll
-      for (int h = 0; h < 2; ++h) {
-        const int64_t k = kb + 16 * h;
+    for (int h = 0; h < 2; ++h) {
+      const int off = KS * tl + 16 * h + 4 * lq;
+#pragma unroll
+      for (int g = 0; g < MC; ++g) {
         if (VEC) {
-          if (cv && k < kend) A[g][h] = __builtin_nontemporal_load((const f4*)(col + k));
-          else A[g][h] = f4{0.f, 0.f, 0.f, 0.f};
+          const bool kv = sv && off < ilim;
+          const float* p = kv ? colp[g] + lbase + 16 * h : zeros;
+          A[g][h] = __builtin_nontemporal_load((const f4*)p);
         } else {
           f4 v;
 #pragma unroll
-          for (int e = 0; e < 4; ++e) v[e] = (cv && k + e < kend) ? col[k + e] : 0.f;
+          for (int e = 0; e < 4; ++e) {
+            const bool kv = sv && off + e < ilim;
+            const float* p = kv ? colp[g] + lbase + 16 * h + e : zeros;
+            v[e] = *p;
+          }
           A[g][h] = v;
         }
       }
     }
+    if (++tl == S1) {
+      tl = 0;
+      ++jl;
+    }
+  };
+  int jc = jl, tc = tl;
+  auto compute = [&](const f4 (&A)[MC][2]) {
+    const int kk = KS * tc + 4 * lq;
+    f4 B[2][NB];
+    double scl[NB];
+#pragma unroll
+    for (int nb = 0; nb < NB; ++nb) {
+#pragma unroll
+      for (int h = 0; h < 2; ++h) B[h][nb] = *(const f4*)&hs[(16 * nb + li) * hp + kk + 16 * h];
+      scl[nb] = sc[jc * RP + 16 * nb + li];
+    }
+#pragma unroll
+    for (int g = 0; g < MC; ++g)
+#pragma unroll
+      for (int nb = 0; nb < NB; ++nb) {
+        f4 c = mfma4(A[g][0][0], B[0][nb][0], f4{0.f, 0.f, 0.f, 0.f});
+        c = mfma4(A[g][0][1], B[0][nb][1], c);
+        c = mfma4(A[g][0][2], B[0][nb][2], c);
+        c = mfma4(A[g][0][3], B[0][nb][3], c);
+        c = mfma4(A[g][1][0], B[1][nb][0], c);
+        c = mfma4(A[g][1][1], B[1][nb][1], c);
+        c = mfma4(A[g][1][2], B[1][nb][2], c);
+        c = mfma4(A[g][1][3], B[1][nb][3], c);
+#pragma unroll
+        for (int e = 0; e < 4; ++e) acc[g * NB + nb][e] = __builtin_fma((double)c[e], scl[nb], acc[g * NB + nb][e]);
+      }
+    if (++tc == S1) {
+      tc = 0;
+      ++jc;
+    }
   };
 
-  build_tile<NB>(kt0, a.krp, cs, kbeg, kend, a.R, a.col0);
-  __syncthreads();
-
-  const int nsteps = ntiles * SPT;
-  f4 Acur[MC][2], Anxt[MC][2];
-  if (nsteps > 0) load_step(0, Acur);
-  for (int t = 0; t < ntiles; ++t) {
-    const float* kt = (t & 1) ? kt1 : kt0;
-#pragma unroll 1
-    for (int w = 0; w < SPT; ++w) {
-      const int s = t * SPT + w;
-      if (s + 1 < nsteps) load_step(s + 1, Anxt);
-      const int kk = wk * (BK / WK) + w * KS + 4 * lq;
-      f4 B[2][NB];
+  f4 A[D][MC][2];
+  int s = sb;
+  if (sb < se) {
 #pragma unroll
-      for (int h = 0; h < 2; ++h)
-#pragma unroll
-        for (int nb = 0; nb < NB; ++nb) B[h][nb] = *(const f4*)&kt[(16 * nb + li) * PITCH + kk + 16 * h];
-#pragma unroll
-      for (int g = 0; g < MC; ++g)
-#pragma unroll
-        for (int nb = 0; nb < NB; ++nb) {
-          f4 c = mfma4(Acur[g][0][0], B[0][nb][0], f4{0.f, 0.f, 0.f, 0.f});
-          c = mfma4(Acur[g][0][1], B[0][nb][1], c);
-          c = mfma4(Acur[g][0][2], B[0][nb][2], c);
-          c = mfma4(Acur[g][0][3], B[0][nb][3], c);
-          c = mfma4(Acur[g][1][0], B[1][nb][0], c);
-          c = mfma4(Acur[g][1][1], B[1][nb][1], c);
-          c = mfma4(Acur[g][1][2], B[1][nb][2], c);
-          c = mfma4(Acur[g][1][3], B[1][nb][3], c);
-#pragma unroll
-          for (int e = 0; e < 4; ++e) acc[g * NB + nb][e] += (double)c[e];
-        }
-      if (s + 1 < nsteps) {
-#pragma unroll
-        for (int g = 0; g < MC; ++g)
-#pragma unroll
-          for (int h = 0; h < 2; ++h) Acur[g][h] = Anxt[g][h];
-      }
-    }
-    if (t + 1 < ntiles)
-      build_tile<NB>((t & 1) ? kt0 : kt1, a.krp, cs, kbeg + (int64_t)(t + 1) * BK, kend, a.R, a.col0);
-    __syncthreads();
+    for (int d = 0; d < D; ++d) load(A[d], sb + d < se);
   }
+  for (; s + D - 1 < se; s += D) {
+#pragma unroll
+    for (int d = 0; d < D; ++d) {
+      compute(A[d]);
+      __builtin_amdgcn_sched_barrier(0);
+      load(A[d], s + D + d < se);
+      __builtin_amdgcn_sched_barrier(0);
+    }
+  }
+#pragma unroll
+  for (int d = 0; d < D - 1; ++d)
+    if (s + d < se) compute(A[d]);
 
-  wave_reduce_k<NACC>(acc, (double*)lds, wk, wm, WK);
+  __syncthreads();
+  wave_reduce_k<NACC>(acc, lds_d, wk, wm, WK);
   if (wk != 0 && a.nsplit == 1) return;
 
   // acc[g*NB+nb][v]: column c = cw + 16g + 4*lq + v, rank column 16nb + li.
   const bool direct = (a.nsplit == 1);
   const int64_t Mpad = (int64_t)gridDim.x * mtile;
+  (void)mbeg;
   if (wk == 0) {
 #pragma unroll
     for (int g = 0; g < MC; ++g)
@@ -268,52 +325,76 @@ __global__ __launch_bounds__(NT, 2) void pm_right_f32(PmArgs a) {
         for (int v = 0; v < 4; ++v)
           pm_store(a, direct, Mtot, Mpad, RP, 16 * nb + li, cw + 16 * g + 4 * lq + v, acc[g * NB + nb][v]);
   }
-  if (!direct) splitk_finish(a, Mtot, mtile, mbeg, RP, Mpad);
 }
 
 // Rows per left wave = 16 * left_tr(NB); columns per right wave = 16 * right_mc(NB).
-// Chosen so that the FP64 accumulators (2 VGPRs per output) leave room for a
-// double-buffered k-step of X without spilling.
+// Chosen so that the FP64 accumulators (2 VGPRs per output) leave room for
+// several k-steps of X in flight without spilling. PF = k-steps in flight.
 constexpr int left_tr(int nb) { return nb >= 4 ? 2 : 4; }
 constexpr int right_mc(int nb) { return nb >= 4 ? 2 : 4; }
+constexpr int left_pf(int nb) { return nb == 2 ? 3 : 4; }
+constexpr int right_pf(int nb) { return nb >= 4 ? 3 : 3; }
 
-template <int NB, int WM>
-hipError_t launch_f32(const PmLaunch& L, const PmArgs& a, bool vec, hipStream_t st) {
-  dim3 grid(L.mtiles, L.nsplit), block(NT);
-  size_t lds = pm_lds_bytes(NB);
-  if (L.side == 0) {
-    constexpr int TR = left_tr(NB);
-    const size_t need = (size_t)WM * TR * NB * 4 * 64 * sizeof(double);
-    if (WM < 4 && need > lds) lds = need;
-    if (vec) hipLaunchKernelGGL((pm_left_f32<NB, TR, WM, true>), grid, block, lds, st, a);
-    else hipLaunchKernelGGL((pm_left_f32<NB, TR, WM, false>), grid, block, lds, st, a);
-  } else {
-    constexpr int MC = right_mc(NB);
-    const size_t need = (size_t)WM * MC * NB * 4 * 64 * sizeof(double);
-    if (WM < 4 && need > lds) lds = need;
-    if (vec) hipLaunchKernelGGL((pm_right_f32<NB, MC, WM, true>), grid, block, lds, st, a);
-    else hipLaunchKernelGGL((pm_right_f32<NB, MC, WM, false>), grid, block, lds, st, a);
+template <int NB, int WM, bool VEC>
+const void* kernel_ptr(int side) {
+  if (side == 0) return (const void*)pm_left_f32<NB, left_tr(NB), WM, VEC, left_pf(NB)>;
+  return (const void*)pm_right_f32<NB, right_mc(NB), WM, VEC, right_pf(NB)>;
+}
+
+const void* select_kernel(int side, int nb, int wm, bool vec) {
+  switch (nb * 100 + wm * 10 + (vec ? 1 : 0)) {
+    case 141: return kernel_ptr<1, 4, true>(side);
+    case 140: return kernel_ptr<1, 4, false>(side);
+    case 111: return kernel_ptr<1, 1, true>(side);
+    case 110: return kernel_ptr<1, 1, false>(side);
+    case 241: return kernel_ptr<2, 4, true>(side);
+    case 240: return kernel_ptr<2, 4, false>(side);
+    case 211: return kernel_ptr<2, 1, true>(side);
+    case 210: return kernel_ptr<2, 1, false>(side);
+    case 441: return kernel_ptr<4, 4, true>(side);
+    case 440: return kernel_ptr<4, 4, false>(side);
+    case 411: return kernel_ptr<4, 1, true>(side);
+    case 410: return kernel_ptr<4, 1, false>(side);
+    default: return nullptr;
   }
-  return hipGetLastError();
+}
+
+size_t reduce_lds(int side, int nb, int wm) {
+  if (wm >= 4) return 0;
+  const int nacc = side == 0 ? left_tr(nb) * nb : right_mc(nb) * nb;
+  return (size_t)wm * nacc * 4 * 64 * sizeof(double);
 }
 
 }  // namespace
 
 int pm_f32_wave_rows(int side, int nb) { return side == 0 ? 16 * left_tr(nb) : 16 * right_mc(nb); }
+int pm_f32_kstep(int side) { return side == 0 ? 16 : 32; }
+
+static bool f32_vec(const PmArgs& a, int side) {
+  // Left: 16-byte row loads need an aligned base and I_L % 4 == 0. Right: 16-byte
+  // loads along k also need I1 % 4 == 0 so a group of four never straddles j.
+  bool vec = ((uintptr_t)a.X % 16 == 0) && (a.IL % 4 == 0);
+  if (side == 1) vec = vec && (a.I1 % 4 == 0);
+  return vec;
+}
+
+int pm_f32_blocks_per_cu(int side, int nb, int wm, size_t lds) {
+  const void* k = select_kernel(side, nb, wm, true);
+  if (!k) return 1;
+  const size_t l = lds > reduce_lds(side, nb, wm) ? lds : reduce_lds(side, nb, wm);
+  int blocks = 0;
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&blocks, k, NT, l) != hipSuccess || blocks < 1) return 1;
+  return blocks;
+}
 
 hipError_t pm_launch_f32(const PmLaunch& L, const PmArgs& a, hipStream_t st) {
-  // vector loads need a 16-byte aligned base and I_L % 4 == 0 (every column aligned)
-  const bool vec = ((uintptr_t)a.X % 16 == 0) && (a.IL % 4 == 0);
   const int wm = L.mtile / pm_f32_wave_rows(L.side, L.nb);
-  switch (L.nb * 10 + (wm == 4 ? 4 : 1)) {
-    case 14: return launch_f32<1, 4>(L, a, vec, st);
-    case 11: return launch_f32<1, 1>(L, a, vec, st);
-    case 24: return launch_f32<2, 4>(L, a, vec, st);
-    case 21: return launch_f32<2, 1>(L, a, vec, st);
-    case 44: return launch_f32<4, 4>(L, a, vec, st);
-    case 41: return launch_f32<4, 1>(L, a, vec, st);
-    default: return hipErrorInvalidValue;
-  }
+  const void* k = select_kernel(L.side, L.nb, wm, f32_vec(a, L.side));
+  if (!k) return hipErrorInvalidValue;
+  size_t lds = L.lds_bytes;
+  if (reduce_lds(L.side, L.nb, wm) > lds) lds = reduce_lds(L.side, L.nb, wm);
+  void* args[] = {(void*)&a};
+  return hipLaunchKernel(k, dim3(L.mtiles, L.nsplit), dim3(NT), args, lds, st);
 }
 
 }  // namespace nncpk

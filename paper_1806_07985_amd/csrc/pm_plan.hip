@@ -1,43 +1,142 @@
 // Tile and split-K plan of a partial-MTTKRP launch, and dispatch by tensor dtype.
+#include <cstdlib>
+
 #include "pm_common.hpp"
 
 namespace nncpk {
 
-// Heuristic: aim for >= ~4 work-groups per CU over the chip, keep each split at
-// least two LDS tiles deep, and use the narrow M tile (one wave along M, four
-// along K) when the output has few rows, so split-K partial traffic stays small.
-PmLaunch pm_plan(int side, int dtype, int64_t IL, int64_t IR, int R) {
+int pm_f32_kstep(int side);
+int pm_16_kstep(int side);
+int pm_f32_blocks_per_cu(int side, int nb, int wm, size_t lds);
+int pm_16_blocks_per_cu(int side, int nb, int wm, size_t lds);
+
+static int num_cus() {
+  static int n = [] {
+    int dev = 0, cus = 0;
+    if (hipGetDevice(&dev) != hipSuccess) return 256;
+    if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || cus < 1)
+      return 256;
+    return cus;
+  }();
+  return n;
+}
+
+static int64_t cdiv(int64_t a, int64_t b) { return (a + b - 1) / b; }
+
+// Work-groups a launch aims for: one co-resident round (CUs x blocks per CU for
+// this kernel), so no partial second round idles most of the chip.
+// NNCP_PM_TARGET_WGS overrides it for tuning.
+static int64_t target_wgs(int blocks_per_cu) {
+  static const long env = [] {
+    const char* e = std::getenv("NNCP_PM_TARGET_WGS");
+    return e ? std::atol(e) : 0L;
+  }();
+  if (env > 0) return env;
+  return (int64_t)num_cus() * blocks_per_cu;
+}
+
+PmLaunch pm_plan(int side, int dtype, int64_t IL, int64_t IR, int I1, int R) {
   PmLaunch L{};
   L.side = side;
   L.dtype = dtype;
   const int Rc = R < kPmMaxCols ? R : kPmMaxCols;
   L.nb = Rc <= 16 ? 1 : (Rc <= 32 ? 2 : 4);
+  const int RP = 16 * L.nb;
+  const bool f32 = dtype == NNCP_F32;
   const int64_t Mtot = side == 0 ? IL : IR;
   const int64_t Ktot = side == 0 ? IR : IL;
-  const int wave_rows = dtype == NNCP_F32 ? pm_f32_wave_rows(side, L.nb) : pm_16_wave_rows(side, L.nb);
-  const int64_t target = 1024;
+  const int ks = f32 ? pm_f32_kstep(side) : pm_16_kstep(side);
+  const int wave_rows = f32 ? pm_f32_wave_rows(side, L.nb) : pm_16_wave_rows(side, L.nb);
+  const int hbytes = f32 ? 4 : 4;  // LDS bytes per cached factor entry (hi+lo halves for 16-bit)
+
+  L.I1 = I1;
+  L.J = Ktot / I1;
+  L.I1pad = (int)cdiv(I1, ks) * ks;
+  // i1 block: at most ~48 KB of LDS for the cached H_1 rows
+  int maxrows = (int)((48 * 1024) / (RP * hbytes)) / ks * ks;
+  if (maxrows < ks) maxrows = ks;
+  L.n_i1blk = (int)cdiv(L.I1pad, maxrows);
+  L.i1blk = (int)cdiv(cdiv(L.I1pad, L.n_i1blk), ks) * ks;
+  L.n_i1blk = (int)cdiv(L.I1pad, L.i1blk);
+
   int wm = 4;
-  if ((Mtot + 4 * wave_rows - 1) / (4 * wave_rows) < 64) wm = 1;
+  if (cdiv(Mtot, 4 * wave_rows) < 64) wm = 1;
   L.mtile = wm * wave_rows;
-  L.mtiles = (int)((Mtot + L.mtile - 1) / L.mtile);
-  const int64_t ktiles = (Ktot + BK - 1) / BK;
-  int64_t ns = (target + L.mtiles - 1) / L.mtiles;
-  const int64_t maxs = ktiles / 2 > 0 ? ktiles / 2 : 1;
-  if (ns > maxs) ns = maxs;
-  if (ns > 256) ns = 256;
-  if (ns < 1) ns = 1;
-  const int64_t tiles_per = (ktiles + ns - 1) / ns;
-  L.kchunk = tiles_per * BK;
-  L.nsplit = (int)((Ktot + L.kchunk - 1) / L.kchunk);
-  if (L.nsplit < 1) L.nsplit = 1;
-  L.partial_doubles = L.nsplit > 1 ? (size_t)L.nsplit * L.nb * 16 * (size_t)L.mtiles * L.mtile : 0;
+  L.mtiles = (int)cdiv(Mtot, L.mtile);
+
+  const int64_t steps_per_j = L.i1blk / ks;
+  const size_t lds_est = (size_t)RP * (L.i1blk + 4) * sizeof(float) + 8 + (size_t)64 * RP * sizeof(double);
+  const int bpc = f32 ? pm_f32_blocks_per_cu(side, L.nb, wm, lds_est) : pm_16_blocks_per_cu(side, L.nb, wm, lds_est);
+  int64_t want_splits = target_wgs(bpc) / L.mtiles;
+  if (want_splits < 1) want_splits = 1;
+  int64_t n_jblk = cdiv(want_splits, L.n_i1blk);
+  // each wave should own a few k-steps, and the per-(j, column) scales fit LDS
+  const int64_t min_j = cdiv(8 * (4 / wm), steps_per_j);
+  int64_t jblk = cdiv(L.J, n_jblk < 1 ? 1 : n_jblk);
+  if (jblk < min_j) jblk = min_j;
+  if (jblk > 64) jblk = 64;
+  if (jblk > L.J) jblk = L.J;
+  if (jblk < 1) jblk = 1;
+  L.jblk = (int)jblk;
+  L.n_jblk = (int)cdiv(L.J, jblk);
+  L.nsplit = L.n_i1blk * L.n_jblk;
+  L.lds_bytes = (size_t)RP * (L.i1blk + 4) * sizeof(float) + 8 + (size_t)L.jblk * RP * sizeof(double);
+  L.partial_doubles = L.nsplit > 1 ? (size_t)L.nsplit * RP * (size_t)L.mtiles * L.mtile : 0;
   L.ncounters = L.mtiles;
   return L;
 }
 
+void pm_fill_args(const PmLaunch& L, PmArgs& a) {
+  a.I1 = L.I1;
+  a.I1pad = L.I1pad;
+  a.i1blk = L.i1blk;
+  a.n_i1blk = L.n_i1blk;
+  a.J = L.J;
+  a.jblk = L.jblk;
+  a.n_jblk = L.n_jblk;
+  a.nsplit = L.nsplit;
+}
+
+// T(m, col0 + r) = sum over splits (in split order) of partial[(sp*RP + r)*Mpad + m],
+// one thread per output element pair (coalesced along m).
+template <typename TO>
+__global__ __launch_bounds__(256) void pm_reduce_kernel(const double* __restrict__ part, TO* __restrict__ T,
+                                                        int64_t Mtot, int64_t Mpad, int RP, int R, int col0,
+                                                        int nsplit) {
+  const int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  const int64_t total = Mtot * R;
+  if (e >= total) return;
+  const int r = (int)(e / Mtot);
+  const int64_t m = e - (int64_t)r * Mtot;
+  const double* p = part + (size_t)r * Mpad + m;
+  const size_t st = (size_t)RP * Mpad;
+  double s = 0.0;
+  int sp = 0;
+  for (; sp + 4 <= nsplit; sp += 4) {
+    const double v0 = p[(sp + 0) * st], v1 = p[(sp + 1) * st], v2 = p[(sp + 2) * st], v3 = p[(sp + 3) * st];
+    s += v0;
+    s += v1;
+    s += v2;
+    s += v3;
+  }
+  for (; sp < nsplit; ++sp) s += p[sp * st];
+  T[m + Mtot * (int64_t)(col0 + r)] = (TO)s;
+}
+
 hipError_t pm_launch(const PmLaunch& L, const PmArgs& a, hipStream_t st) {
-  if (L.dtype == NNCP_F32) return pm_launch_f32(L, a, st);
-  return pm_launch_16(L, a, st);
+  hipError_t e = (L.dtype == NNCP_F32) ? pm_launch_f32(L, a, st) : pm_launch_16(L, a, st);
+  if (e != hipSuccess || L.nsplit <= 1) return e;
+  const int64_t Mtot = L.side == 0 ? a.IL : a.IR;
+  const int64_t Mpad = (int64_t)L.mtiles * L.mtile;
+  const int64_t total = Mtot * a.R;
+  const dim3 grid((unsigned)((total + 255) / 256));
+  if (a.t_f64)
+    hipLaunchKernelGGL(pm_reduce_kernel<double>, grid, dim3(256), 0, st, a.partial, (double*)a.T, Mtot, Mpad,
+                       16 * L.nb, a.R, a.col0, L.nsplit);
+  else
+    hipLaunchKernelGGL(pm_reduce_kernel<float>, grid, dim3(256), 0, st, a.partial, (float*)a.T, Mtot, Mpad,
+                       16 * L.nb, a.R, a.col0, L.nsplit);
+  return hipGetLastError();
 }
 
 }  // namespace nncpk

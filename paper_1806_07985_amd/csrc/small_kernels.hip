@@ -280,25 +280,27 @@ __global__ __launch_bounds__(NT) void update_kernel(UpdateArgs a) {
 // then the last block forms lambda = sqrt(diag G_hat), the normalised Gram,
 // optionally the model weights, S for the next mode, and the fit.
 // --------------------------------------------------------------------------
-constexpr int FIN_SUB = 32;  // rows staged in LDS at a time
+// Rows of W staged in LDS at a time (FP64): about 32 KB.
+__host__ __device__ inline int fin_sub_rows(int R) {
+  int r = 4096 / (R > 0 ? R : 1);
+  return r < 1 ? 1 : (r > 256 ? 256 : r);
+}
 
-__global__ __launch_bounds__(NT) void finalize_kernel(FinalizeArgs a) {
-  extern __shared__ double fl[];  // FIN_SUB x R rows, then R*R scratch
-  __shared__ double sh[NT / 64];
+// Stage 1: W^T W (and <M, W> when the fit is due) over this block's row chunk,
+// written to partial[chunk] (R*R + 1 doubles).
+__device__ void gram_chunk(const FinalizeArgs& a, double* fl, double* sh) {
   const int R = a.R, RR = R * R;
+  const int sub = fin_sub_rows(R);
   const int64_t r0 = (int64_t)blockIdx.x * a.rows_per_chunk;
   int64_t r1 = r0 + a.rows_per_chunk;
   if (r1 > a.I) r1 = a.I;
   double* part = a.partial + (size_t)blockIdx.x * (RR + 1);
-
-  // each thread owns entries e = tid, tid + NT, ... of the R x R Gram
-  constexpr int MAXE = (kMaxRank * kMaxRank + NT - 1) / NT;
-  double acc[MAXE];
-#pragma unroll
-  for (int q = 0; q < MAXE; ++q) acc[q] = 0.0;
+  // Each thread owns entries e = tid, tid + NT, ...; the running sums live in
+  // this block's partial slot (only this thread touches them).
   double bsum = 0.0;
-  for (int64_t s0 = r0; s0 < r1; s0 += FIN_SUB) {
-    const int cnt = (int)((r1 - s0) < FIN_SUB ? (r1 - s0) : FIN_SUB);
+  bool first = true;
+  for (int64_t s0 = r0; s0 < r1 || first; s0 += sub) {
+    const int cnt = (int)((r1 - s0) < sub ? (r1 - s0) : sub);
     __syncthreads();
     for (int e = threadIdx.x; e < cnt * R; e += NT) {
       const int k = e / cnt, rw = e - k * cnt;
@@ -307,28 +309,24 @@ __global__ __launch_bounds__(NT) void finalize_kernel(FinalizeArgs a) {
       if (a.do_fit && a.M) bsum += wv * ldv(a.M, s0 + rw + a.I * k, a.m_f64);
     }
     __syncthreads();
-#pragma unroll
-    for (int q = 0; q < MAXE; ++q) {
-      const int e = threadIdx.x + q * NT;
-      if (e < RR) {
-        const int x = e / R, y = e - x * R;
-        double s = 0.0;
-        for (int rw = 0; rw < cnt; ++rw) s += fl[rw * R + x] * fl[rw * R + y];
-        acc[q] += s;
-      }
+    for (int e = threadIdx.x; e < RR; e += NT) {
+      const int x = e / R, y = e - x * R;
+      double sacc = 0.0;
+      for (int rw = 0; rw < cnt; ++rw) sacc += fl[rw * R + x] * fl[rw * R + y];
+      part[e] = first ? sacc : part[e] + sacc;
     }
-  }
-#pragma unroll
-  for (int q = 0; q < MAXE; ++q) {
-    const int e = threadIdx.x + q * NT;
-    if (e < RR) part[e] = acc[q];
+    first = false;
   }
   double bt = block_sum(bsum, sh);
   if (threadIdx.x == 0) part[RR] = bt;
-  if (!last_block(a.counter, gridDim.x)) return;
+}
 
-  // ---- last block: reduce chunks in order ----
-  double* Gh = fl;  // R*R scratch (reuses the row stage)
+// Stage 2 (one block): reduce the chunk partials in chunk order, then lambda =
+// sqrt(diag G_hat), the normalised Gram, the model weights, S for the next mode
+// and, after the last mode, the fit.
+__device__ void finalize_tail(const FinalizeArgs& a, double* fl, double* sh) {
+  const int R = a.R, RR = R * R;
+  double* Gh = fl;  // R*R + 1 scratch
   for (int e = threadIdx.x; e < RR + 1; e += NT) {
     double s = 0.0;
     for (int c = 0; c < a.nchunks; ++c) s += a.partial[(size_t)c * (RR + 1) + e];
@@ -349,10 +347,9 @@ __global__ __launch_bounds__(NT) void finalize_kernel(FinalizeArgs a) {
     const double lx = sqrt(Gh[x * R + x]), ly = sqrt(Gh[y * R + y]);
     Gm[e] = (lx > 0.0 && ly > 0.0) ? Gh[e] / (lx * ly) : 0.0;
   }
-  __threadfence_block();
   __syncthreads();
   if (a.do_fit) {
-    // gamma = 1^T (S^(mode) * G_hat) 1 ; S^(mode) is the Hadamard of the others.
+    // gamma = 1^T (S^(mode) * G_hat) 1, S^(mode) the Hadamard of the other Grams
     const double* Sm = a.S + (int64_t)a.mode * RR;
     double gp = 0.0;
     for (int e = threadIdx.x; e < RR; e += NT) gp += Sm[e] * Gh[e];
@@ -370,6 +367,7 @@ __global__ __launch_bounds__(NT) void finalize_kernel(FinalizeArgs a) {
     __syncthreads();
   }
   if (a.next_mode >= 0) {
+    // this block wrote G[mode] above; the other modes' Grams are from earlier kernels
     double* Sn = a.S + (int64_t)a.next_mode * RR;
     for (int e = threadIdx.x; e < RR; e += NT) {
       double s = 1.0;
@@ -378,6 +376,27 @@ __global__ __launch_bounds__(NT) void finalize_kernel(FinalizeArgs a) {
       Sn[e] = s;
     }
   }
+}
+
+// One block does both stages (a single row chunk).
+__global__ __launch_bounds__(NT) void finalize_fused_kernel(FinalizeArgs a) {
+  extern __shared__ double fl[];
+  __shared__ double sh[NT / 64];
+  gram_chunk(a, fl, sh);
+  __syncthreads();
+  finalize_tail(a, fl, sh);
+}
+
+__global__ __launch_bounds__(NT) void gram_chunks_kernel(FinalizeArgs a) {
+  extern __shared__ double fl[];
+  __shared__ double sh[NT / 64];
+  gram_chunk(a, fl, sh);
+}
+
+__global__ __launch_bounds__(NT) void finalize_tail_kernel(FinalizeArgs a) {
+  extern __shared__ double fl[];
+  __shared__ double sh[NT / 64];
+  finalize_tail(a, fl, sh);
 }
 
 __global__ void init_model_kernel(const double* lam_in, const double* lam, double* lam_model,
@@ -506,23 +525,33 @@ hipError_t update_launch(const UpdateArgs& a, hipStream_t st) {
   return hipGetLastError();
 }
 
-int finalize_chunks(int64_t I, int* rows_per_chunk) {
-  int64_t chunks = (I + 63) / 64;
-  if (chunks > 16) chunks = 16;
+// Row chunks for the Gram: one block when the work is small (no second launch),
+// otherwise chunks of about 2^19 multiply-adds each (at most 64).
+int finalize_chunks(int64_t I, int R, int* rows_per_chunk) {
+  const int64_t work = I * (int64_t)R * R;
+  int64_t chunks = (work + (1 << 19) - 1) >> 19;
+  if (chunks > 64) chunks = 64;
+  if (chunks > I) chunks = I;
   if (chunks < 1) chunks = 1;
   int64_t rpc = (I + chunks - 1) / chunks;
   if (rpc < 1) rpc = 1;
   chunks = (I + rpc - 1) / rpc;
-  if (chunks < 1) chunks = 1;
   *rows_per_chunk = (int)rpc;
   return (int)chunks;
 }
 
 hipError_t finalize_launch(const FinalizeArgs& a, hipStream_t st) {
-  size_t lds = (size_t)FIN_SUB * a.R * sizeof(double);
+  size_t lds = (size_t)fin_sub_rows(a.R) * a.R * sizeof(double);
   const size_t need = ((size_t)a.R * a.R + 1) * sizeof(double);
   if (need > lds) lds = need;
-  hipLaunchKernelGGL(finalize_kernel, dim3(a.nchunks), dim3(NT), lds, st, a);
+  if (a.nchunks <= 1) {
+    hipLaunchKernelGGL(finalize_fused_kernel, dim3(1), dim3(NT), lds, st, a);
+    return hipGetLastError();
+  }
+  hipLaunchKernelGGL(gram_chunks_kernel, dim3(a.nchunks), dim3(NT), lds, st, a);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(finalize_tail_kernel, dim3(1), dim3(NT), lds, st, a);
   return hipGetLastError();
 }
 
