@@ -107,6 +107,8 @@ def main(argv=None):
     ap.add_argument("--split", type=int, default=2)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-iters", type=int, default=3)
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="also run a plain 1 GiB device-to-device copy (for scaling HBM counters)")
     args = ap.parse_args(argv)
 
     if args.gpus != 1:
@@ -162,6 +164,13 @@ def main(argv=None):
 
     lam = plan.finish()
     plan.close()
+    if args.copy_calibration:
+        src = torch.empty(1 << 28, dtype=torch.float32, device=dev).fill_(1.0)
+        dst = torch.empty_like(src)
+        torch.cuda.synchronize()
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
     I = int(np.prod(dims))
     flops_pm = 2.0 * I * R
 

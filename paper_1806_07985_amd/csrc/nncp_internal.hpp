@@ -46,6 +46,7 @@ struct PmArgs {
   int i1blk, n_i1blk;    // i1 rows per split block, number of i1 blocks
   int64_t J;             // product of the remaining contracted extents
   int jblk, n_jblk;      // j per split block, number of j blocks
+  int fold;              // k-steps summed in FP32 before folding into FP64 (divides i1blk/k-step)
   int R;                 // columns handled by this launch (<= kPmMaxCols)
   int col0;              // first column (offset into factor columns)
   void* T;               // output, column-major, ld = Mtot: column c at T + Mtot*c
@@ -64,7 +65,7 @@ struct PmLaunch {
   int mtile;     // output rows per work-group
   int mtiles;
   int nsplit;
-  int I1, I1pad, i1blk, n_i1blk, jblk, n_jblk;
+  int I1, I1pad, i1blk, n_i1blk, jblk, n_jblk, fold;
   int64_t J;
   size_t lds_bytes;
   size_t partial_doubles;

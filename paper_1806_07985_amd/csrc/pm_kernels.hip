@@ -31,8 +31,9 @@ namespace {
 // (li, lq) loads rows TR*li .. TR*li+TR-1 of the columns i1 = base + 4*lq + u,
 // u = 0..3; MFMA chain tt uses row TR*li + tt of every load.
 // ----------------------------------------------------------------------------
-template <int NB, int TR, int WM, bool VEC, int D>
+template <int NB, int TR, int WM, bool FAST, int D>
 __global__ __launch_bounds__(NT, 2) void pm_left_f32(PmArgs a) {
+  constexpr bool VEC = FAST;
   constexpr int RP = NB * 16;
   constexpr int WK = 4 / WM;
   constexpr int KS = 16;
@@ -81,18 +82,24 @@ __global__ __launch_bounds__(NT, 2) void pm_left_f32(PmArgs a) {
 #pragma unroll
   for (int u = 0; u < 4; ++u) lane_off[u] = Mtot * (int64_t)(4 * lq + u) + (VEC ? mload : 0);
 
-  // load cursor (uniform): step = jl * S1 + tl
-  int jl = sb / S1, tl = sb - (sb / S1) * S1;
+  // load cursor (uniform): step = jl * S1 + tl. With one wave along K the group
+  // starts at a j rotated by its M tile, so groups that share a split do not all
+  // request the same addresses modulo the column stride at the same time.
+  const int jrot = (WK == 1 && jn > 1) ? (int)((blockIdx.x * 5u) % (unsigned)jn) : 0;
+  int jl = sb / S1 + jrot, tl = sb - (sb / S1) * S1;
+  // The cursor always stays inside the group's j block (it wraps), so loads of
+  // steps past the wave's range read valid memory and are simply not used.
   auto load = [&](vT (&A)[4], bool sv) {
+    (void)sv;
     const int64_t colbase = (int64_t)a.I1 * (j0 + jl) + i1_0 + KS * tl;
     const float* base = X + Mtot * colbase;
 #pragma unroll
     for (int u = 0; u < 4; ++u) {
-      const bool kv = sv && (KS * tl + 4 * lq + u) < ilim;
-      if (VEC) {
-        const float* p = kv ? base + lane_off[u] : zeros;
-        A[u] = __builtin_nontemporal_load((const vT*)p);
+      if (FAST) {
+        // I1 is a multiple of the k-step and rows are aligned: no padding lanes
+        A[u] = __builtin_nontemporal_load((const vT*)(base + lane_off[u]));
       } else {
+        const bool kv = (KS * tl + 4 * lq + u) < ilim;
         vT v;
 #pragma unroll
         for (int e = 0; e < TR; ++e) {
@@ -104,44 +111,59 @@ __global__ __launch_bounds__(NT, 2) void pm_left_f32(PmArgs a) {
     }
     if (++tl == S1) {
       tl = 0;
-      ++jl;
+      if (++jl == jn) jl = 0;
     }
   };
-  int jc = jl, tc = tl;
+
+  // FP32 partial sums (one 16x16 block per (tt, nb)) live for `fold` k-steps and
+  // are then added into the FP64 accumulators with the chunk's column scale.
+  f4 c32[TR][NB];
+#pragma unroll
+  for (int tt = 0; tt < TR; ++tt)
+#pragma unroll
+    for (int nb = 0; nb < NB; ++nb) c32[tt][nb] = f4{0.f, 0.f, 0.f, 0.f};
+  int jc = jl, tc = tl, fc = tl % a.fold, sc_left = se - sb;
   auto compute = [&](const vT (&A)[4]) {
     const int kk = KS * tc + 4 * lq;
     f4 B[NB];
-    double scl[NB];
 #pragma unroll
-    for (int nb = 0; nb < NB; ++nb) {
-      B[nb] = *(const f4*)&hs[(16 * nb + li) * hp + kk];
-      scl[nb] = sc[jc * RP + 16 * nb + li];
-    }
+    for (int nb = 0; nb < NB; ++nb) B[nb] = *(const f4*)&hs[(16 * nb + li) * hp + kk];
+    // u-major: consecutive MFMAs go to different accumulators
 #pragma unroll
-    for (int tt = 0; tt < TR; ++tt)
+    for (int u = 0; u < 4; ++u)
+#pragma unroll
+      for (int tt = 0; tt < TR; ++tt)
+#pragma unroll
+        for (int nb = 0; nb < NB; ++nb) c32[tt][nb] = mfma4(A[u][tt], B[nb][u], c32[tt][nb]);
+    --sc_left;
+    if (++fc == a.fold || sc_left == 0) {
 #pragma unroll
       for (int nb = 0; nb < NB; ++nb) {
-        f4 c = mfma4(A[0][tt], B[nb][0], f4{0.f, 0.f, 0.f, 0.f});
-        c = mfma4(A[1][tt], B[nb][1], c);
-        c = mfma4(A[2][tt], B[nb][2], c);
-        c = mfma4(A[3][tt], B[nb][3], c);
+        const double scl = sc[jc * RP + 16 * nb + li];
 #pragma unroll
-        for (int e = 0; e < 4; ++e) acc[tt * NB + nb][e] = __builtin_fma((double)c[e], scl[nb], acc[tt * NB + nb][e]);
+        for (int tt = 0; tt < TR; ++tt) {
+#pragma unroll
+          for (int e = 0; e < 4; ++e) acc[tt * NB + nb][e] = __builtin_fma((double)c32[tt][nb][e], scl, acc[tt * NB + nb][e]);
+          c32[tt][nb] = f4{0.f, 0.f, 0.f, 0.f};
+        }
       }
+      fc = 0;
+    }
     if (++tc == S1) {
       tc = 0;
-      ++jc;
+      if (++jc == jn) jc = 0;
     }
   };
 
   // D k-steps of X in flight: the loads of step s+D are issued right after step
   // s is consumed. sched_barrier keeps the compiler from sinking them.
+  // The first D loads are issued unconditionally (out-of-range steps read the
+  // zero block) so every path into the loop has the same loads in flight and the
+  // compiler's wait counts stay precise.
   vT A[D][4];
   int s = sb;
-  if (sb < se) {
 #pragma unroll
-    for (int d = 0; d < D; ++d) load(A[d], sb + d < se);
-  }
+  for (int d = 0; d < D; ++d) load(A[d], sb + d < se);
   for (; s + D - 1 < se; s += D) {
 #pragma unroll
     for (int d = 0; d < D; ++d) {
@@ -180,8 +202,9 @@ __global__ __launch_bounds__(NT, 2) void pm_left_f32(PmArgs a) {
 // one j), lane (li, lq) loads k = base + 16h + 4*lq + u (u = 0..3 in one
 // 16-byte load, h = 0..1) of column c = group + li.
 // ----------------------------------------------------------------------------
-template <int NB, int MC, int WM, bool VEC, int D>
+template <int NB, int MC, int WM, bool FAST, int D>
 __global__ __launch_bounds__(NT, 2) void pm_right_f32(PmArgs a) {
+  constexpr bool VEC = FAST;
   constexpr int RP = NB * 16;
   constexpr int WK = 4 / WM;
   constexpr int KS = 32;
@@ -228,23 +251,23 @@ __global__ __launch_bounds__(NT, 2) void pm_right_f32(PmArgs a) {
   const int ilim = a.I1 - i1_0;
   const float* zeros = (const float*)a.zeros;
 
-  int jl = sb / S1, tl = sb - (sb / S1) * S1;
+  const int jrot = (WK == 1 && jn > 1) ? (int)((blockIdx.x * 5u) % (unsigned)jn) : 0;
+  int jl = sb / S1 + jrot, tl = sb - (sb / S1) * S1;
   auto load = [&](f4 (&A)[MC][2], bool sv) {
+    (void)sv;
     const int64_t lbase = (int64_t)a.I1 * (j0 + jl) + i1_0 + KS * tl;
 #pragma unroll
     for (int h = 0; h < 2; ++h) {
       const int off = KS * tl + 16 * h + 4 * lq;
 #pragma unroll
       for (int g = 0; g < MC; ++g) {
-        if (VEC) {
-          const bool kv = sv && off < ilim;
-          const float* p = kv ? colp[g] + lbase + 16 * h : zeros;
-          A[g][h] = __builtin_nontemporal_load((const f4*)p);
+        if (FAST) {
+          A[g][h] = __builtin_nontemporal_load((const f4*)(colp[g] + lbase + 16 * h));
         } else {
           f4 v;
 #pragma unroll
           for (int e = 0; e < 4; ++e) {
-            const bool kv = sv && off + e < ilim;
+            const bool kv = off + e < ilim;
             const float* p = kv ? colp[g] + lbase + 16 * h + e : zeros;
             v[e] = *p;
           }
@@ -254,47 +277,55 @@ __global__ __launch_bounds__(NT, 2) void pm_right_f32(PmArgs a) {
     }
     if (++tl == S1) {
       tl = 0;
-      ++jl;
+      if (++jl == jn) jl = 0;
     }
   };
-  int jc = jl, tc = tl;
+
+  f4 c32[MC][NB];
+#pragma unroll
+  for (int g = 0; g < MC; ++g)
+#pragma unroll
+    for (int nb = 0; nb < NB; ++nb) c32[g][nb] = f4{0.f, 0.f, 0.f, 0.f};
+  int jc = jl, tc = tl, fc = tl % a.fold, sc_left = se - sb;
   auto compute = [&](const f4 (&A)[MC][2]) {
     const int kk = KS * tc + 4 * lq;
     f4 B[2][NB];
-    double scl[NB];
 #pragma unroll
-    for (int nb = 0; nb < NB; ++nb) {
+    for (int nb = 0; nb < NB; ++nb)
 #pragma unroll
       for (int h = 0; h < 2; ++h) B[h][nb] = *(const f4*)&hs[(16 * nb + li) * hp + kk + 16 * h];
-      scl[nb] = sc[jc * RP + 16 * nb + li];
-    }
 #pragma unroll
-    for (int g = 0; g < MC; ++g)
+    for (int h = 0; h < 2; ++h)
+#pragma unroll
+      for (int u = 0; u < 4; ++u)
+#pragma unroll
+        for (int g = 0; g < MC; ++g)
+#pragma unroll
+          for (int nb = 0; nb < NB; ++nb) c32[g][nb] = mfma4(A[g][h][u], B[h][nb][u], c32[g][nb]);
+    --sc_left;
+    if (++fc == a.fold || sc_left == 0) {
 #pragma unroll
       for (int nb = 0; nb < NB; ++nb) {
-        f4 c = mfma4(A[g][0][0], B[0][nb][0], f4{0.f, 0.f, 0.f, 0.f});
-        c = mfma4(A[g][0][1], B[0][nb][1], c);
-        c = mfma4(A[g][0][2], B[0][nb][2], c);
-        c = mfma4(A[g][0][3], B[0][nb][3], c);
-        c = mfma4(A[g][1][0], B[1][nb][0], c);
-        c = mfma4(A[g][1][1], B[1][nb][1], c);
-        c = mfma4(A[g][1][2], B[1][nb][2], c);
-        c = mfma4(A[g][1][3], B[1][nb][3], c);
+        const double scl = sc[jc * RP + 16 * nb + li];
 #pragma unroll
-        for (int e = 0; e < 4; ++e) acc[g * NB + nb][e] = __builtin_fma((double)c[e], scl[nb], acc[g * NB + nb][e]);
+        for (int g = 0; g < MC; ++g) {
+#pragma unroll
+          for (int e = 0; e < 4; ++e) acc[g * NB + nb][e] = __builtin_fma((double)c32[g][nb][e], scl, acc[g * NB + nb][e]);
+          c32[g][nb] = f4{0.f, 0.f, 0.f, 0.f};
+        }
       }
+      fc = 0;
+    }
     if (++tc == S1) {
       tc = 0;
-      ++jc;
+      if (++jc == jn) jc = 0;
     }
   };
 
   f4 A[D][MC][2];
   int s = sb;
-  if (sb < se) {
 #pragma unroll
-    for (int d = 0; d < D; ++d) load(A[d], sb + d < se);
-  }
+  for (int d = 0; d < D; ++d) load(A[d], sb + d < se);
   for (; s + D - 1 < se; s += D) {
 #pragma unroll
     for (int d = 0; d < D; ++d) {
@@ -371,11 +402,11 @@ int pm_f32_wave_rows(int side, int nb) { return side == 0 ? 16 * left_tr(nb) : 1
 int pm_f32_kstep(int side) { return side == 0 ? 16 : 32; }
 
 static bool f32_vec(const PmArgs& a, int side) {
-  // Left: 16-byte row loads need an aligned base and I_L % 4 == 0. Right: 16-byte
-  // loads along k also need I1 % 4 == 0 so a group of four never straddles j.
+  // Fast path: vector loads with no masked lanes. Left: 16-byte row loads need an
+  // aligned base and I_L % 4 == 0. Both sides: I1 must be a multiple of the
+  // k-step so the zero-padded tail of H_1 never occurs.
   bool vec = ((uintptr_t)a.X % 16 == 0) && (a.IL % 4 == 0);
-  if (side == 1) vec = vec && (a.I1 % 4 == 0);
-  return vec;
+  return vec && (a.I1 % pm_f32_kstep(side) == 0);
 }
 
 int pm_f32_blocks_per_cu(int side, int nb, int wm, size_t lds) {

@@ -1,4 +1,5 @@
 // Tile and split-K plan of a partial-MTTKRP launch, and dispatch by tensor dtype.
+#include <cmath>
 #include <cstdlib>
 
 #include "pm_common.hpp"
@@ -78,6 +79,19 @@ PmLaunch pm_plan(int side, int dtype, int64_t IL, int64_t IR, int I1, int R) {
   if (jblk > L.J) jblk = L.J;
   if (jblk < 1) jblk = 1;
   L.jblk = (int)jblk;
+  // FP32 partial sums span `fold` k-steps (fold*ks products) before they are
+  // added into FP64. A running FP32 sum of c products over a reduction of K
+  // terms leaves a relative error of about 0.3 u c / sqrt(3 K) once the chunks
+  // are summed exactly; fold keeps c <= 0.6 sqrt(3 K), i.e. under ~0.2 u.
+  {
+    const double cmax = 0.6 * std::sqrt(3.0 * (double)Ktot);
+    int fmax = (int)(cmax / ks);
+    if (fmax < 1) fmax = 1;
+    int f = 1;
+    for (int d = 1; d <= steps_per_j && d <= fmax; ++d)
+      if (steps_per_j % d == 0) f = d;
+    L.fold = f;
+  }
   L.n_jblk = (int)cdiv(L.J, jblk);
   L.nsplit = L.n_i1blk * L.n_jblk;
   L.lds_bytes = (size_t)RP * (L.i1blk + 4) * sizeof(float) + 8 + (size_t)L.jblk * RP * sizeof(double);
@@ -94,6 +108,7 @@ void pm_fill_args(const PmLaunch& L, PmArgs& a) {
   a.J = L.J;
   a.jblk = L.jblk;
   a.n_jblk = L.n_jblk;
+  a.fold = L.fold;
   a.nsplit = L.nsplit;
 }
 

@@ -188,75 +188,88 @@ __global__ __launch_bounds__(NT) void mttv_lead_kernel(MttvArgs a) {
 }
 
 // --------------------------------------------------------------------------
-// NLS update. A group of GS lanes owns one row; lane p holds columns
-// k = p + GS*v (v < VPL) of the warm start w, the MTTKRP row m and the running
-// product g = w S. HALS visits r = 0..R-1 in order (Gauss-Seidel): the owner of
-// column r computes the new value, broadcasts the change d, and every lane
-// updates g += d S(r, :). S lives in LDS (FP64).
+// NLS update (Section II-B), one wave per row. Lane p holds columns
+// k = p + 64*v (v < VPL) of the warm start w, the MTTKRP row m and the running
+// product g = w S. HALS visits r = 0..R-1 in order (Gauss-Seidel): every lane
+// forms its candidate change, the owner's one is broadcast with readlane, and
+// every lane updates g += d S(r, :). S and 1/S(r,r) live in LDS; all FP64.
 // --------------------------------------------------------------------------
-template <int GS, int VPL>
+__device__ __forceinline__ double readlane_f64(double v, int lane) {
+  const uint64_t u = __builtin_bit_cast(uint64_t, v);
+  const uint32_t lo = __builtin_amdgcn_readlane((uint32_t)u, lane);
+  const uint32_t hi = __builtin_amdgcn_readlane((uint32_t)(u >> 32), lane);
+  return __builtin_bit_cast(double, ((uint64_t)hi << 32) | lo);
+}
+
+template <int VPL>
 __global__ __launch_bounds__(NT) void update_kernel(UpdateArgs a) {
-  extern __shared__ double Sl[];
+  extern __shared__ double Sl[];  // R*R, then R inverse diagonals
   const int R = a.R;
+  double* invd = Sl + R * R;
   for (int e = threadIdx.x; e < R * R; e += NT) Sl[e] = a.S[e];
+  for (int k = threadIdx.x; k < R; k += NT) {
+    const double d = a.S[k * R + k];
+    invd[k] = d > 0.0 ? 1.0 / d : 0.0;
+  }
   __syncthreads();
-  constexpr int RPB = NT / GS;  // rows per block
-  const int grp = threadIdx.x / GS, p = threadIdx.x % GS;
-  const int64_t row = (int64_t)blockIdx.x * RPB + grp;
-  const bool active = row < a.I;
-  const int64_t rr = active ? row : 0;
+  const int p = threadIdx.x & 63;
+  const int64_t row = (int64_t)blockIdx.x * (NT / 64) + (threadIdx.x >> 6);
+  if (row >= a.I) return;  // whole wave leaves together (row is wave-uniform)
 
   double w[VPL], m[VPL], g[VPL];
 #pragma unroll
   for (int v = 0; v < VPL; ++v) {
-    const int k = p + GS * v;
+    const int k = p + 64 * v;
     w[v] = 0.0;
     m[v] = 0.0;
     g[v] = 0.0;
     if (k < R) {
       const double ls = a.lam_self[k];
       const double f = ls > 0.0 ? a.lam_model[k] / ls : 0.0;
-      w[v] = (double)a.W[rr + a.I * k] * f;
-      m[v] = ldv(a.M, rr + a.I * k, a.m_f64);
+      w[v] = (double)a.W[row + a.I * k] * f;
+      m[v] = ldv(a.M, row + a.I * k, a.m_f64);
     }
   }
-  // g = w S (with the current w)
+  // g = w S with the starting w
   for (int r = 0; r < R; ++r) {
-    const int owner = r % GS, slot = r / GS;
-    double wr = 0.0;
+    const int v = r >> 6;
+    double wv = w[0];
 #pragma unroll
-    for (int v = 0; v < VPL; ++v)
-      if (v == slot) wr = w[v];
-    wr = __shfl(wr, owner, GS);
+    for (int q = 1; q < VPL; ++q)
+      if (v == q) wv = w[q];
+    const double wr = readlane_f64(wv, r & 63);
 #pragma unroll
-    for (int v = 0; v < VPL; ++v) {
-      const int k = p + GS * v;
-      if (k < R) g[v] += wr * Sl[r * R + k];
+    for (int q = 0; q < VPL; ++q) {
+      const int k = p + 64 * q;
+      if (k < R) g[q] += wr * Sl[r * R + k];
     }
   }
   if (a.update == NNCP_HALS) {
     for (int r = 0; r < R; ++r) {
-      const int owner = r % GS, slot = r / GS;
-      double d = 0.0;
-      if (p == owner) {
+      const int v = r >> 6;
+      double wv = w[0], mv = m[0], gv = g[0];
 #pragma unroll
-        for (int v = 0; v < VPL; ++v)
-          if (v == slot) {
-            const double srr = Sl[r * R + r];
-            double wn = 0.0;
-            if (srr > 0.0) {
-              wn = w[v] + (m[v] - g[v]) / srr;
-              wn = wn > 0.0 ? wn : 0.0;
-            }
-            d = wn - w[v];
-            w[v] = wn;
-          }
+      for (int q = 1; q < VPL; ++q)
+        if (v == q) {
+          wv = w[q];
+          mv = m[q];
+          gv = g[q];
+        }
+      // column r: W(:,r) <- max(0, W(:,r) + (M(:,r) - (W S)(:,r)) / S(r,r)); a zero
+      // diagonal (all-zero column elsewhere) sets the column to zero
+      const double id = invd[r];
+      double wn = id > 0.0 ? wv + (mv - gv) * id : 0.0;
+      wn = wn > 0.0 ? wn : 0.0;
+      const double d = readlane_f64(wn - wv, r & 63);
+      if (p == (r & 63)) {
+#pragma unroll
+        for (int q = 0; q < VPL; ++q)
+          if (v == q) w[q] += d;
       }
-      d = __shfl(d, owner, GS);
 #pragma unroll
-      for (int v = 0; v < VPL; ++v) {
-        const int k = p + GS * v;
-        if (k < R) g[v] += d * Sl[r * R + k];
+      for (int q = 0; q < VPL; ++q) {
+        const int k = p + 64 * q;
+        if (k < R) g[q] += d * Sl[r * R + k];
       }
     }
   } else {
@@ -266,20 +279,13 @@ __global__ __launch_bounds__(NT) void update_kernel(UpdateArgs a) {
       w[v] = w[v] * m[v] / den;
     }
   }
-  if (active) {
 #pragma unroll
-    for (int v = 0; v < VPL; ++v) {
-      const int k = p + GS * v;
-      if (k < R) a.W[row + a.I * k] = (float)w[v];
-    }
+  for (int v = 0; v < VPL; ++v) {
+    const int k = p + 64 * v;
+    if (k < R) a.W[row + a.I * k] = (float)w[v];
   }
 }
 
-// --------------------------------------------------------------------------
-// Finalize one mode after its update: G_hat = W^T W (FP64) over row chunks,
-// then the last block forms lambda = sqrt(diag G_hat), the normalised Gram,
-// optionally the model weights, S for the next mode, and the fit.
-// --------------------------------------------------------------------------
 // Rows of W staged in LDS at a time (FP64): about 32 KB.
 __host__ __device__ inline int fin_sub_rows(int R) {
   int r = 4096 / (R > 0 ? R : 1);
@@ -309,11 +315,28 @@ __device__ void gram_chunk(const FinalizeArgs& a, double* fl, double* sh) {
       if (a.do_fit && a.M) bsum += wv * ldv(a.M, s0 + rw + a.I * k, a.m_f64);
     }
     __syncthreads();
-    for (int e = threadIdx.x; e < RR; e += NT) {
-      const int x = e / R, y = e - x * R;
-      double sacc = 0.0;
-      for (int rw = 0; rw < cnt; ++rw) sacc += fl[rw * R + x] * fl[rw * R + y];
-      part[e] = first ? sacc : part[e] + sacc;
+    // four entries per thread at a time (independent FMA chains), rows unrolled
+    for (int eg = threadIdx.x; eg < RR; eg += 4 * NT) {
+      int ex[4], ey[4];
+      double sacc[4];
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        const int e = eg + q * NT < RR ? eg + q * NT : eg;
+        ex[q] = e / R;
+        ey[q] = e - ex[q] * R;
+        sacc[q] = 0.0;
+      }
+#pragma unroll 4
+      for (int rw = 0; rw < cnt; ++rw) {
+        const double* row = fl + rw * R;
+#pragma unroll
+        for (int q = 0; q < 4; ++q) sacc[q] += row[ex[q]] * row[ey[q]];
+      }
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        const int e = eg + q * NT;
+        if (e < RR) part[e] = first ? sacc[q] : part[e] + sacc[q];
+      }
     }
     first = false;
   }
@@ -512,16 +535,11 @@ hipError_t mttv_lead_launch(const MttvArgs& a, hipStream_t st) {
 
 hipError_t update_launch(const UpdateArgs& a, hipStream_t st) {
   if (a.I <= 0) return hipSuccess;
-  const size_t lds = (size_t)a.R * a.R * sizeof(double);
-  int gs = 16;
-  while (gs < 64 && gs < a.R) gs <<= 1;
-  const int vpl = (a.R + gs - 1) / gs;
-  const int rpb = NT / gs;
+  const size_t lds = ((size_t)a.R * a.R + a.R) * sizeof(double);
+  const int rpb = NT / 64;
   dim3 g((unsigned)((a.I + rpb - 1) / rpb)), b(NT);
-  if (gs == 16) hipLaunchKernelGGL((update_kernel<16, 1>), g, b, lds, st, a);
-  else if (gs == 32) hipLaunchKernelGGL((update_kernel<32, 1>), g, b, lds, st, a);
-  else if (vpl == 1) hipLaunchKernelGGL((update_kernel<64, 1>), g, b, lds, st, a);
-  else hipLaunchKernelGGL((update_kernel<64, 2>), g, b, lds, st, a);
+  if (a.R <= 64) hipLaunchKernelGGL((update_kernel<1>), g, b, lds, st, a);
+  else hipLaunchKernelGGL((update_kernel<2>), g, b, lds, st, a);
   return hipGetLastError();
 }
 
