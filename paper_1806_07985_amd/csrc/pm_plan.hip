@@ -24,8 +24,10 @@ static int num_cus() {
 
 static int64_t cdiv(int64_t a, int64_t b) { return (a + b - 1) / b; }
 
-// Work-groups a launch aims for: one co-resident round (CUs x blocks per CU for
-// this kernel), so no partial second round idles most of the chip.
+// Work-groups a launch aims for: one per CU. Measured on the 128^4 rank-32
+// workload, one group of four waves per CU (each with three k-steps of loads in
+// flight) streams X faster than two or three co-resident groups, and it keeps
+// the split-K partial traffic small. The occupancy query still caps the count.
 // NNCP_PM_TARGET_WGS overrides it for tuning.
 static int64_t target_wgs(int blocks_per_cu) {
   static const long env = [] {
@@ -33,7 +35,7 @@ static int64_t target_wgs(int blocks_per_cu) {
     return e ? std::atol(e) : 0L;
   }();
   if (env > 0) return env;
-  return (int64_t)num_cus() * blocks_per_cu;
+  return (int64_t)num_cus() * (blocks_per_cu < 1 ? 1 : 1);
 }
 
 PmLaunch pm_plan(int side, int dtype, int64_t IL, int64_t IR, int I1, int R) {
@@ -62,6 +64,14 @@ PmLaunch pm_plan(int side, int dtype, int64_t IL, int64_t IR, int I1, int R) {
 
   int wm = 4;
   if (cdiv(Mtot, 4 * wave_rows) < 64) wm = 1;
+  {
+    // tuning override: NNCP_PM_WM = 1 or 4 (waves along M per work-group)
+    static const int env_wm = [] {
+      const char* e = std::getenv("NNCP_PM_WM");
+      return e ? std::atoi(e) : 0;
+    }();
+    if (env_wm == 1 || env_wm == 4) wm = env_wm;
+  }
   L.mtile = wm * wave_rows;
   L.mtiles = (int)cdiv(Mtot, L.mtile);
 
