@@ -30,9 +30,11 @@ HBM_PEAK_GBS = 8000.0
 FP32_MFMA_PEAK_TFLOPS = 157.3
 
 
-def _pm_sources_digest() -> str:
+def _pm_sources_digest(dtype: str = "f32") -> str:
+    """Digest of the sources of the partial-MTTKRP kernels for one tensor dtype."""
     h = hashlib.sha256()
-    for f in ("pm_common.hpp", "pm_kernels.hip", "pm16_kernels.hip", "pm_plan.hip"):
+    kern = "pm_kernels.hip" if dtype == "f32" else "pm16_kernels.hip"
+    for f in ("pm_common.hpp", kern, "pm_plan.hip"):
         p = os.path.join(ROOT, "paper_1806_07985_amd", "csrc", f)
         if os.path.exists(p):
             h.update(open(p, "rb").read())
@@ -49,12 +51,12 @@ def _traffic_from_profile(workload: str, launch_bytes: float):
         d = json.load(open(p))
     except Exception:
         return None
-    if d.get("pm_sources_digest") != _pm_sources_digest():
+    if d.get("pm_sources_digest") != _pm_sources_digest("f32"):
         return None
     return d.get("hbm_bytes_per_launch")
 
 
-def _algorithmic_bytes(dims, s, R, sx, node_bytes=8):
+def _algorithmic_bytes(dims, s, R, sx, node_bytes):
     """Algorithmic HBM bytes of the tree MTTKRP per outer iteration.
 
     Per root partial MTTKRP: the tensor once (I * s_X), the node temporary
@@ -96,6 +98,75 @@ def _cpu_baseline(X, H0, iters, seconds_cap=40.0):
                        f"BLAS threads = {os.environ.get('OPENBLAS_NUM_THREADS', cores)}")
 
 
+def _fit_against(Xd, dims, s, Hd, lam):
+    """fit = 1 - ||X - [[lam; H]]|| / ||X|| for a normalised model, evaluated with
+    the library's own MTTKRP and Gram (FP64 outputs) on tensor Xd."""
+    from paper_1806_07985_amd import native
+    N, R = len(dims), len(lam)
+    alpha = native.norm_sq(Xd)
+    M = native.mttkrp(Xd, list(dims), s, N - 1, Hd, R).cpu().numpy().T      # I_N x R
+    HN = native.factor_to_host(Hd[N - 1])
+    beta = float(np.sum(M * HN, axis=0) @ lam)
+    Gh = np.ones((R, R))
+    for n in range(N):
+        Gh *= native.gram(Hd[n], dims[n], R).cpu().numpy()
+    gamma = float(lam @ Gh @ lam)
+    return 1.0 - math.sqrt(max(0.0, alpha - 2.0 * beta + gamma) / alpha)
+
+
+def _node_rates(plan, dims, s, R, sx, node_bytes, reps=20):
+    ms_left = plan.time_node(0, reps)
+    ms_right = plan.time_node(s, reps)
+    pm_l, pm_r, mttv_bytes = _algorithmic_bytes(dims, s, R, sx, node_bytes)
+    return dict(left_ms=ms_left, right_ms=ms_right,
+                left_GBs=pm_l / (ms_left * 1e-3) / 1e9, right_GBs=pm_r / (ms_right * 1e-3) / 1e9,
+                left_bytes=pm_l, right_bytes=pm_r, mttv_bytes=mttv_bytes)
+
+
+def _lowprec_study(dev, iters, seconds_note=None):
+    """FP32 vs BF16 vs FP16 storage on the hyperspectral-shaped 1024x1344x33x9
+    tensor (planted rank 50 + 2% noise), NNCP R=50, HALS, split {1}|{2,3,4}: the
+    same starting factors and iteration count for every storage type; each
+    final model is scored against the FP32 tensor."""
+    import torch
+    from paper_1806_07985_amd import inputs, native
+    dims, R, s = (1024, 1344, 33, 9), 50, 1
+    t0 = time.perf_counter()
+    X, _ = inputs.hsi_like(dims, R, 0.02, seed=5)
+    H0 = [h.astype(np.float32) for h in inputs.init_factors(dims, R, seed=6)]
+    gen_s = time.perf_counter() - t0
+    X32 = native.tensor_to_device(X, device=dev)
+    del X
+    out = {"workload": "1024x1344x33x9 hyperspectral-shaped, planted rank 50 + 2% noise, NNCP R=50, HALS, "
+                       "split {1}|{2,3,4}", "iters": iters, "generate_s": gen_s}
+    for dt in ("f32", "bf16", "f16"):
+        Xd = X32 if dt == "f32" else native.quantize(X32, dt)
+        Hd = [native.factor_to_device(h, device=dev) for h in H0]
+        plan = native.Plan(Xd, list(dims), R, Hd, update="hals", split=s)
+        f0 = plan.run(1)                       # first replay builds the graph
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        fits = plan.run(iters - 1)
+        torch.cuda.synchronize()
+        dt_s = time.perf_counter() - t0
+        rates = _node_rates(plan, dims, s, R, 4 if dt == "f32" else 2, 8 if dt == "f32" else 4)
+        lam = plan.finish()
+        plan.close()
+        out[dt] = dict(iters_per_s=(iters - 1) / dt_s, fit_in_loop=float(fits[-1]) if len(fits) else float(f0[-1]),
+                       fit_vs_fp32_tensor=_fit_against(X32, dims, s, Hd, lam),
+                       pm_left_ms=rates["left_ms"], pm_right_ms=rates["right_ms"],
+                       pm_left_GBs=rates["left_GBs"], pm_right_GBs=rates["right_GBs"])
+        del Hd
+        if dt != "f32":
+            del Xd
+    for dt in ("bf16", "f16"):
+        out[dt]["speedup_vs_f32"] = out[dt]["iters_per_s"] / out["f32"]["iters_per_s"]
+        out[dt]["fit_diff_vs_f32"] = out[dt]["fit_vs_fp32_tensor"] - out["f32"]["fit_vs_fp32_tensor"]
+    del X32
+    torch.cuda.empty_cache()
+    return out
+
+
 def main(argv=None):
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -107,6 +178,9 @@ def main(argv=None):
     ap.add_argument("--split", type=int, default=2)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-iters", type=int, default=3)
+    ap.add_argument("--no-lowprec", action="store_true",
+                    help="skip the FP32 / BF16 / FP16 study on the 1024x1344x33x9 tensor")
+    ap.add_argument("--lowprec-iters", type=int, default=100)
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run a plain 1 GiB device-to-device copy (for scaling HBM counters)")
     args = ap.parse_args(argv)
@@ -141,15 +215,10 @@ def main(argv=None):
 
     # Dominant kernel: the root partial MTTKRPs (left = mode 1's node, right =
     # mode s+1's node), timed with HIP events on the plan's stream.
-    reps = 20
-    ms_left = plan.time_node(0, reps)
-    ms_right = plan.time_node(s, reps)
-    pm_l, pm_r, mttv_bytes = _algorithmic_bytes(dims, s, R, 4)
-    gbs_left = pm_l / (ms_left * 1e-3) / 1e9
-    gbs_right = pm_r / (ms_right * 1e-3) / 1e9
-    dom = "left" if ms_left >= ms_right else "right"
-    ms_dom = max(ms_left, ms_right)
-    bytes_dom = pm_l if dom == "left" else pm_r
+    rt = _node_rates(plan, dims, s, R, 4, 8)
+    dom = "left" if rt["left_ms"] >= rt["right_ms"] else "right"
+    ms_dom = rt[dom + "_ms"]
+    bytes_dom = rt[dom + "_bytes"]
     achieved = bytes_dom / (ms_dom * 1e-3) / 1e9
 
     # phase breakdown (events between kernels, no graph)
@@ -160,7 +229,8 @@ def main(argv=None):
     pplan.close()
     ph = {k: v / 3 for k, v in ph.items()}
     mttkrp_ms = ph["pm"] + ph["mttv"]
-    mttkrp_gbs = (pm_l + pm_r + mttv_bytes) / (mttkrp_ms * 1e-3) / 1e9 if mttkrp_ms > 0 else None
+    mttkrp_gbs = ((rt["left_bytes"] + rt["right_bytes"] + rt["mttv_bytes"]) / (mttkrp_ms * 1e-3) / 1e9
+                  if mttkrp_ms > 0 else None)
 
     lam = plan.finish()
     plan.close()
@@ -197,13 +267,17 @@ def main(argv=None):
                      "bytes_per_launch": bytes_dom, "ms_per_launch": ms_dom,
                      "mfma_fp32_tflops": flops_pm / (ms_dom * 1e-3) / 1e12,
                      "mfma_fp32_frac": flops_pm / (ms_dom * 1e-3) / 1e12 / FP32_MFMA_PEAK_TFLOPS},
-        "pm": {"left_ms": ms_left, "right_ms": ms_right, "left_GBs": gbs_left, "right_GBs": gbs_right},
+        "pm": {k: rt[k] for k in ("left_ms", "right_ms", "left_GBs", "right_GBs")},
         "mttkrp_GBs": mttkrp_gbs,
         "phase_ms_per_iter": ph,
         "fit_first": fits[0] if fits else None,
         "fit_last": fits[-1] if fits else None,
         "lambda_max": float(np.max(lam)),
     }
+    del plan, pplan, Xd, Hd, Hp
+    torch.cuda.empty_cache()
+    if not args.no_lowprec:
+        out["lowprec"] = _lowprec_study(dev, args.lowprec_iters)
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = _cpu_baseline(X, [h.astype(np.float64) for h in H0], args.cpu_iters)
     print(json.dumps(out), flush=True)

@@ -45,7 +45,7 @@ struct Node {
 
 struct Layout {
   size_t off_zeros, off_alpha, off_iter, off_counters, off_lam, off_lammodel, off_lamin, off_G, off_S, off_fit,
-      off_finpart, off_pmpart, off_nspart, off_M, off_nodes, total;
+      off_finpart, off_pmpart, off_hpack, off_nspart, off_M, off_nodes, total;
   int ncounters;
   int64_t node_bytes[kMaxModes];
   int node_f64;  // tree temporaries are FP64 for FP32 tensors, FP32 for 16-bit tensors
@@ -150,6 +150,7 @@ Layout make_layout(const Problem& p) {
   L.off_fit = take(sizeof(double) * kFitCap);
   L.off_finpart = take(sizeof(double) * (size_t)maxchunks * (RR + 1));
   L.off_pmpart = take(sizeof(double) * std::max(L.pmL[0].partial_doubles, L.pmL[1].partial_doubles));
+  L.off_hpack = take(std::max(L.pmL[0].pack_bytes, L.pmL[1].pack_bytes));
   L.off_nspart = take(sizeof(double) * L.ns_blocks);
   int64_t maxI = 0;
   for (int k = 0; k < N; ++k) maxI = std::max(maxI, p.dims[k]);
@@ -202,6 +203,9 @@ struct nncp_plan {
   double* fit() const { return at<double>(L.off_fit); }
   double* finpart() const { return at<double>(L.off_finpart); }
   double* pmpart() const { return at<double>(L.off_pmpart); }
+  // 16-bit tensors: 64 column scales, then the packed hi/lo first factor
+  float* hscale() const { return at<float>(L.off_hpack); }
+  unsigned short* hpack() const { return at<unsigned short>(L.off_hpack + 256); }
   double* nspart() const { return at<double>(L.off_nspart); }
   double* Mbuf() const { return at<double>(L.off_M); }
   void* node(int n) const {
@@ -240,6 +244,8 @@ hipError_t run_pm(const nncp_plan* P, int side, void* T, int t_f64, const void* 
     a.T = T;
     a.t_f64 = t_f64;
     a.partial = P->pmpart();
+    a.hpack = P->hpack();
+    a.hscale = P->hscale();
     a.zeros = P->zeros();
     a.counters = P->counters();
     const PmLaunch l = (a.R == std::min(kPmMaxCols, p.R)) ? P->L.pmL[side] : pm_plan(side, p.dtype, p.IL, p.IR, I1, a.R);
@@ -423,7 +429,6 @@ int nncp_plan_create(nncp_plan** out, const void* X, int dtype, int N, const int
   if (st != NNCP_OK) return st;
   for (int k = 0; k < N; ++k)
     if (!H[k]) return NNCP_EINVAL;
-  if (dtype != NNCP_F32) return NNCP_EINVAL;  // low-precision PM kernels: see nncp_quantize
   nncp_plan* P = new (std::nothrow) nncp_plan();
   if (!P) return NNCP_ENOMEM;
   P->p = p;
@@ -659,7 +664,6 @@ static int step_ctx(StepCtx& c, const void* X, int dtype, int N, const int64_t* 
                     int R) {
   int st = fill_problem(c.P.p, N, dims, R, dtype, NNCP_HALS, s);
   if (st != NNCP_OK) return st;
-  if (dtype != NNCP_F32) return NNCP_EINVAL;
   c.P.L = make_layout(c.P.p);
   c.P.X = X;
   for (int k = 0; k < N; ++k) {
@@ -739,8 +743,9 @@ int nncp_mttkrp(const void* X, int dtype, int N, const int64_t* dims, int s, int
   const void* Mp = nullptr;
   int m_f64 = 1;
   if (leaf_op(&c.P, n, false, hs, &Mp, &m_f64) != hipSuccess) return NNCP_EDEVICE;
-  if (!m_f64) return NNCP_EINVAL;
-  if (hipMemcpyAsync(M, Mp, sizeof(double) * (size_t)p.dims[n] * R, hipMemcpyDeviceToDevice, hs) != hipSuccess)
+  const int64_t cnt = p.dims[n] * R;
+  if ((m_f64 ? copy_f64_launch(M, (const double*)Mp, cnt, hs) : widen_f32_launch(M, (const float*)Mp, cnt, hs)) !=
+      hipSuccess)
     return NNCP_EDEVICE;
   return hipStreamSynchronize(hs) == hipSuccess ? NNCP_OK : NNCP_EDEVICE;
 }

@@ -54,7 +54,14 @@ struct PmArgs {
   double* partial;       // split-K partials (FP64)
   const void* zeros;     // >= 64 bytes of zeros in device memory (read by out-of-range lanes)
   unsigned* counters;    // one per M tile; zero on entry, left zero on exit
-  int nsplit;            // n_i1blk * n_jblk
+  int nsplit;            // (n_i1blk / istages) * n_jblk
+  // 16-bit tensors only: the first contracted factor split into a hi + lo pair of
+  // the tensor's 16-bit type, scaled per column by a power of two (hscale holds
+  // the inverse), laid out [hi rows RP][lo rows RP] x I1pad; and the number of
+  // i1 blocks one work-group walks in turn (restaging LDS between them).
+  unsigned short* hpack;
+  float* hscale;
+  int istages;
 };
 
 // Plan of one partial-MTTKRP launch (tile shape and split count).
@@ -65,10 +72,11 @@ struct PmLaunch {
   int mtile;     // output rows per work-group
   int mtiles;
   int nsplit;
-  int I1, I1pad, i1blk, n_i1blk, jblk, n_jblk, fold;
+  int I1, I1pad, i1blk, n_i1blk, jblk, n_jblk, fold, istages;
   int64_t J;
   size_t lds_bytes;
   size_t partial_doubles;
+  size_t pack_bytes;     // 16-bit tensors: bytes of the packed hi/lo factor + scales
   int ncounters;
 };
 
@@ -81,6 +89,7 @@ hipError_t pm_launch(const PmLaunch& L, const PmArgs& a, hipStream_t st);
 int pm_f32_wave_rows(int side, int nb);
 hipError_t pm_launch_f32(const PmLaunch& L, const PmArgs& a, hipStream_t st);
 int pm_16_wave_rows(int side, int nb);
+int pm_16_kstep(int side);
 hipError_t pm_launch_16(const PmLaunch& L, const PmArgs& a, hipStream_t st);
 
 // Multi-TTV kernels ---------------------------------------------------------
@@ -151,6 +160,7 @@ hipError_t quantize_launch(const float* src, void* dst, int dtype, int64_t n, hi
 hipError_t fill_u32_launch(unsigned* p, int64_t n, unsigned v, hipStream_t st);
 hipError_t fill_f64_launch(double* p, int64_t n, double v, hipStream_t st);
 hipError_t copy_f64_launch(double* dst, const double* src, int64_t n, hipStream_t st);
+hipError_t widen_f32_launch(double* dst, const float* src, int64_t n, hipStream_t st);
 // lam[k] <- (lam[k] > 0 ? 1 : 0), n entries (after normalize_out)
 hipError_t unit_lambda_launch(double* lam, int64_t n, hipStream_t st);
 

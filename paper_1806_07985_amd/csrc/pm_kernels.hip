@@ -87,6 +87,7 @@ __global__ __launch_bounds__(NT, 2) void pm_left_f32(PmArgs a) {
   // request the same addresses modulo the column stride at the same time.
   const int jrot = (WK == 1 && jn > 1) ? (int)((blockIdx.x * 5u) % (unsigned)jn) : 0;
   int jl = sb / S1 + jrot, tl = sb - (sb / S1) * S1;
+  if (jl >= jn) jl -= jn;  // an empty range (sb == S1 * jn) starts at the block's first j
   // The cursor always stays inside the group's j block (it wraps), so loads of
   // steps past the wave's range read valid memory and are simply not used.
   auto load = [&](vT (&A)[4], bool sv) {
@@ -253,6 +254,7 @@ __global__ __launch_bounds__(NT, 2) void pm_right_f32(PmArgs a) {
 
   const int jrot = (WK == 1 && jn > 1) ? (int)((blockIdx.x * 5u) % (unsigned)jn) : 0;
   int jl = sb / S1 + jrot, tl = sb - (sb / S1) * S1;
+  if (jl >= jn) jl -= jn;  // an empty range (sb == S1 * jn) starts at the block's first j
   auto load = [&](f4 (&A)[MC][2], bool sv) {
     (void)sv;
     const int64_t lbase = (int64_t)a.I1 * (j0 + jl) + i1_0 + KS * tl;
@@ -407,15 +409,6 @@ static bool f32_vec(const PmArgs& a, int side) {
   // k-step so the zero-padded tail of H_1 never occurs.
   bool vec = ((uintptr_t)a.X % 16 == 0) && (a.IL % 4 == 0);
   return vec && (a.I1 % pm_f32_kstep(side) == 0);
-}
-
-int pm_f32_blocks_per_cu(int side, int nb, int wm, size_t lds) {
-  const void* k = select_kernel(side, nb, wm, true);
-  if (!k) return 1;
-  const size_t l = lds > reduce_lds(side, nb, wm) ? lds : reduce_lds(side, nb, wm);
-  int blocks = 0;
-  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&blocks, k, NT, l) != hipSuccess || blocks < 1) return 1;
-  return blocks;
 }
 
 hipError_t pm_launch_f32(const PmLaunch& L, const PmArgs& a, hipStream_t st) {

@@ -8,8 +8,6 @@ namespace nncpk {
 
 int pm_f32_kstep(int side);
 int pm_16_kstep(int side);
-int pm_f32_blocks_per_cu(int side, int nb, int wm, size_t lds);
-int pm_16_blocks_per_cu(int side, int nb, int wm, size_t lds);
 
 static int num_cus() {
   static int n = [] {
@@ -27,15 +25,15 @@ static int64_t cdiv(int64_t a, int64_t b) { return (a + b - 1) / b; }
 // Work-groups a launch aims for: one per CU. Measured on the 128^4 rank-32
 // workload, one group of four waves per CU (each with three k-steps of loads in
 // flight) streams X faster than two or three co-resident groups, and it keeps
-// the split-K partial traffic small. The occupancy query still caps the count.
+// the split-K partial traffic small.
 // NNCP_PM_TARGET_WGS overrides it for tuning.
-static int64_t target_wgs(int blocks_per_cu) {
+static int64_t target_wgs() {
   static const long env = [] {
     const char* e = std::getenv("NNCP_PM_TARGET_WGS");
     return e ? std::atol(e) : 0L;
   }();
   if (env > 0) return env;
-  return (int64_t)num_cus() * (blocks_per_cu < 1 ? 1 : 1);
+  return (int64_t)num_cus();
 }
 
 PmLaunch pm_plan(int side, int dtype, int64_t IL, int64_t IR, int I1, int R) {
@@ -50,13 +48,15 @@ PmLaunch pm_plan(int side, int dtype, int64_t IL, int64_t IR, int I1, int R) {
   const int64_t Ktot = side == 0 ? IR : IL;
   const int ks = f32 ? pm_f32_kstep(side) : pm_16_kstep(side);
   const int wave_rows = f32 ? pm_f32_wave_rows(side, L.nb) : pm_16_wave_rows(side, L.nb);
-  const int hbytes = f32 ? 4 : 4;  // LDS bytes per cached factor entry (hi+lo halves for 16-bit)
 
   L.I1 = I1;
   L.J = Ktot / I1;
   L.I1pad = (int)cdiv(I1, ks) * ks;
-  // i1 block: at most ~48 KB of LDS for the cached H_1 rows
-  int maxrows = (int)((48 * 1024) / (RP * hbytes)) / ks * ks;
+  // i1 block held in LDS: FP32 rows of H_1 in ~48 KB (two groups may share a
+  // CU), or the 16-bit hi + lo rows in up to 128 KB (one group per CU).
+  const int row_bytes = RP * 4;
+  const int budget = f32 ? 48 * 1024 : 128 * 1024;
+  int maxrows = budget / row_bytes / ks * ks;
   if (maxrows < ks) maxrows = ks;
   L.n_i1blk = (int)cdiv(L.I1pad, maxrows);
   L.i1blk = (int)cdiv(cdiv(L.I1pad, L.n_i1blk), ks) * ks;
@@ -75,12 +75,17 @@ PmLaunch pm_plan(int side, int dtype, int64_t IL, int64_t IR, int I1, int R) {
   L.mtile = wm * wave_rows;
   L.mtiles = (int)cdiv(Mtot, L.mtile);
 
+  // A 16-bit right node with a tall output and several i1 blocks walks the
+  // blocks inside each work-group (restaging LDS) instead of splitting K: the
+  // split-K partials of a tall output would cost more HBM traffic than X.
+  L.istages = 1;
+  if (!f32 && side == 1 && wm == 4 && L.n_i1blk > 1 && L.mtiles >= target_wgs()) L.istages = L.n_i1blk;
+  const int n_i1grp = L.n_i1blk / L.istages;
+
   const int64_t steps_per_j = L.i1blk / ks;
-  const size_t lds_est = (size_t)RP * (L.i1blk + 4) * sizeof(float) + 8 + (size_t)64 * RP * sizeof(double);
-  const int bpc = f32 ? pm_f32_blocks_per_cu(side, L.nb, wm, lds_est) : pm_16_blocks_per_cu(side, L.nb, wm, lds_est);
-  int64_t want_splits = target_wgs(bpc) / L.mtiles;
+  int64_t want_splits = target_wgs() / L.mtiles;
   if (want_splits < 1) want_splits = 1;
-  int64_t n_jblk = cdiv(want_splits, L.n_i1blk);
+  int64_t n_jblk = cdiv(want_splits, n_i1grp);
   // each wave should own a few k-steps, and the per-(j, column) scales fit LDS
   const int64_t min_j = cdiv(8 * (4 / wm), steps_per_j);
   int64_t jblk = cdiv(L.J, n_jblk < 1 ? 1 : n_jblk);
@@ -93,6 +98,7 @@ PmLaunch pm_plan(int side, int dtype, int64_t IL, int64_t IR, int I1, int R) {
   // added into FP64. A running FP32 sum of c products over a reduction of K
   // terms leaves a relative error of about 0.3 u c / sqrt(3 K) once the chunks
   // are summed exactly; fold keeps c <= 0.6 sqrt(3 K), i.e. under ~0.2 u.
+  // (The 16-bit kernels add each j's FP32 sum into FP32 accumulators.)
   {
     const double cmax = 0.6 * std::sqrt(3.0 * (double)Ktot);
     int fmax = (int)(cmax / ks);
@@ -103,8 +109,14 @@ PmLaunch pm_plan(int side, int dtype, int64_t IL, int64_t IR, int I1, int R) {
     L.fold = f;
   }
   L.n_jblk = (int)cdiv(L.J, jblk);
-  L.nsplit = L.n_i1blk * L.n_jblk;
-  L.lds_bytes = (size_t)RP * (L.i1blk + 4) * sizeof(float) + 8 + (size_t)L.jblk * RP * sizeof(double);
+  L.nsplit = n_i1grp * L.n_jblk;
+  if (f32) {
+    L.lds_bytes = (size_t)RP * (L.i1blk + 4) * sizeof(float) + 8 + (size_t)L.jblk * RP * sizeof(double);
+    L.pack_bytes = 0;
+  } else {
+    L.lds_bytes = (size_t)2 * RP * (L.i1blk + 8) * sizeof(unsigned short) + (size_t)L.jblk * RP * sizeof(float);
+    L.pack_bytes = (size_t)2 * RP * L.I1pad * sizeof(unsigned short) + 256 + (size_t)RP * sizeof(float);
+  }
   L.partial_doubles = L.nsplit > 1 ? (size_t)L.nsplit * RP * (size_t)L.mtiles * L.mtile : 0;
   L.ncounters = L.mtiles;
   return L;
@@ -120,6 +132,7 @@ void pm_fill_args(const PmLaunch& L, PmArgs& a) {
   a.n_jblk = L.n_jblk;
   a.fold = L.fold;
   a.nsplit = L.nsplit;
+  a.istages = L.istages;
 }
 
 // T(m, col0 + r) = sum over splits (in split order) of partial[(sp*RP + r)*Mpad + m],

@@ -105,6 +105,10 @@ __global__ void copy_f64_kernel(double* d, const double* s, int64_t n) {
   int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i < n) d[i] = s[i];
 }
+__global__ void widen_f32_kernel(double* d, const float* s, int64_t n) {
+  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) d[i] = (double)s[i];
+}
 __global__ void unit_lambda_kernel(double* lam, int64_t n) {
   int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i < n) lam[i] = lam[i] > 0.0 ? 1.0 : 0.0;
@@ -491,6 +495,11 @@ hipError_t fill_u32_launch(unsigned* p, int64_t n, unsigned v, hipStream_t st) {
 hipError_t fill_f64_launch(double* p, int64_t n, double v, hipStream_t st) {
   if (n <= 0) return hipSuccess;
   hipLaunchKernelGGL(fill_f64_kernel, dim3(grid_for(n, NT)), dim3(NT), 0, st, p, n, v);
+  return hipGetLastError();
+}
+hipError_t widen_f32_launch(double* d, const float* s, int64_t n, hipStream_t st) {
+  if (n <= 0) return hipSuccess;
+  hipLaunchKernelGGL(widen_f32_kernel, dim3(grid_for(n, NT)), dim3(NT), 0, st, d, s, n);
   return hipGetLastError();
 }
 hipError_t copy_f64_launch(double* d, const double* s, int64_t n, hipStream_t st) {
