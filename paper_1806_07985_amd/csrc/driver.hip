@@ -37,6 +37,12 @@ constexpr int kFitCap = 1024;
 
 inline size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
 
+inline Sink sink_of(hipStream_t st) {
+  Sink s;
+  s.st = st;
+  return s;
+}
+
 struct Node {
   int a = 0, b = 0;
   float* buf = nullptr;
@@ -230,7 +236,7 @@ KrpDesc krp_for(const nncp_plan* P, int a, int b, bool scaled) {
   return k;
 }
 
-hipError_t run_pm(const nncp_plan* P, int side, void* T, int t_f64, const void* X, bool scaled, hipStream_t st) {
+hipError_t run_pm(const nncp_plan* P, int side, void* T, int t_f64, const void* X, bool scaled, const Sink& st) {
   const Problem& p = P->p;
   const int I1 = (int)(side == 0 ? p.dims[p.s] : p.dims[0]);
   for (int c0 = 0; c0 < p.R; c0 += kPmMaxCols) {
@@ -258,7 +264,7 @@ hipError_t run_pm(const nncp_plan* P, int side, void* T, int t_f64, const void* 
 
 // Node op for mode n: the root partial MTTKRP (n starts its half) or the leading
 // multi-TTV from node {n-1..b}.
-hipError_t node_op(const nncp_plan* P, int n, bool scaled, hipStream_t st) {
+hipError_t node_op(const nncp_plan* P, int n, bool scaled, const Sink& st) {
   const Problem& p = P->p;
   const int b = sub_end(p, n), start = sub_start(p, n);
   const int f64 = P->L.node_f64;
@@ -277,7 +283,7 @@ hipError_t node_op(const nncp_plan* P, int n, bool scaled, hipStream_t st) {
 
 // Leaf op for mode n: M^(n) from node {n..b} by the trailing multi-TTV, or the
 // node itself when it is the leaf. *M and *m_f64 describe where M^(n) lives.
-hipError_t leaf_op(const nncp_plan* P, int n, bool scaled, hipStream_t st, const void** M, int* m_f64) {
+hipError_t leaf_op(const nncp_plan* P, int n, bool scaled, const Sink& st, const void** M, int* m_f64) {
   const Problem& p = P->p;
   const int b = sub_end(p, n);
   if (n == b) {
@@ -300,7 +306,7 @@ hipError_t leaf_op(const nncp_plan* P, int n, bool scaled, hipStream_t st, const
 }
 
 hipError_t finalize_mode(const nncp_plan* P, int n, const void* M, int m_f64, int set_model, int next_mode,
-                         int do_fit, hipStream_t st) {
+                         int do_fit, const Sink& st) {
   const Problem& p = P->p;
   FinalizeArgs f{};
   f.W = P->H[n];
@@ -329,14 +335,14 @@ hipError_t finalize_mode(const nncp_plan* P, int n, const void* M, int m_f64, in
 enum { PH_PM = 0, PH_MTTV = 1, PH_NLS = 2, PH_GRAM = 3, PH_ERR = 4, PH_TOTAL = 5 };
 
 // Enqueue one outer iteration. With timers, events bracket each phase (no graph).
-hipError_t enqueue_iteration(nncp_plan* P, hipStream_t st, std::vector<std::pair<int, hipEvent_t>>* marks) {
+hipError_t enqueue_iteration(nncp_plan* P, const Sink& st, std::vector<std::pair<int, hipEvent_t>>* marks) {
   const Problem& p = P->p;
   auto mark = [&](int phase) -> hipError_t {
     if (!marks) return hipSuccess;
     hipEvent_t e;
     hipError_t r = hipEventCreate(&e);
     if (r != hipSuccess) return r;
-    r = hipEventRecord(e, st);
+    r = hipEventRecord(e, st.st);
     marks->push_back({phase, e});
     return r;
   };
@@ -379,7 +385,7 @@ int destroy_graph(nncp_plan* P) {
 int build_graph(nncp_plan* P) {
   destroy_graph(P);
   HIPCHK(hipStreamBeginCapture(P->cap_stream, hipStreamCaptureModeThreadLocal));
-  hipError_t e = enqueue_iteration(P, P->cap_stream, nullptr);
+  hipError_t e = enqueue_iteration(P, sink_of(P->cap_stream), nullptr);
   hipGraph_t g = nullptr;
   hipError_t e2 = hipStreamEndCapture(P->cap_stream, &g);
   if (e != hipSuccess || e2 != hipSuccess) {
@@ -553,7 +559,7 @@ int nncp_plan_run(nncp_plan* P, int iters, double* fit, int* iters_done) {
     } else if (P->phase_timers) {
       for (int i = 0; i < chunk; ++i) {
         std::vector<std::pair<int, hipEvent_t>> marks;
-        hipError_t e = enqueue_iteration(P, us, &marks);
+        hipError_t e = enqueue_iteration(P, sink_of(us), &marks);
         if (e == hipSuccess) e = hipStreamSynchronize(us);
         for (size_t j = 0; j + 1 < marks.size(); ++j) {
           float ms = 0.f;
@@ -571,7 +577,7 @@ int nncp_plan_run(nncp_plan* P, int iters, double* fit, int* iters_done) {
       }
     } else {
       for (int i = 0; i < chunk; ++i)
-        if (enqueue_iteration(P, us, nullptr) != hipSuccess) return NNCP_EDEVICE;
+        if (enqueue_iteration(P, sink_of(us), nullptr) != hipSuccess) return NNCP_EDEVICE;
     }
     hfit.resize(chunk);
     HIPCHK(hipMemcpyAsync(hfit.data(), P->fit(), sizeof(double) * chunk, hipMemcpyDeviceToHost, us));

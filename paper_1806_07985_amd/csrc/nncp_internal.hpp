@@ -85,12 +85,15 @@ struct PmLaunch {
 PmLaunch pm_plan(int side, int dtype, int64_t IL, int64_t IR, int I1, int R);
 void pm_fill_args(const PmLaunch& L, PmArgs& a);
 hipError_t pm_launch(const PmLaunch& L, const PmArgs& a, hipStream_t st);
+struct Sink;
+struct ReduceArgs;
+hipError_t pm_launch(const PmLaunch& L, const PmArgs& a, const Sink& sk);
 // per-dtype kernels (pm_kernels.hip, pm16_kernels.hip)
 int pm_f32_wave_rows(int side, int nb);
-hipError_t pm_launch_f32(const PmLaunch& L, const PmArgs& a, hipStream_t st);
+hipError_t pm_launch_f32(const PmLaunch& L, const PmArgs& a, const Sink& sk);
 int pm_16_wave_rows(int side, int nb);
 int pm_16_kstep(int side);
-hipError_t pm_launch_16(const PmLaunch& L, const PmArgs& a, hipStream_t st);
+hipError_t pm_launch_16(const PmLaunch& L, const PmArgs& a, const Sink& sk);
 
 // Multi-TTV kernels ---------------------------------------------------------
 struct MttvArgs {
@@ -104,6 +107,8 @@ struct MttvArgs {
 };
 hipError_t mttv_trail_launch(const MttvArgs& a, hipStream_t st);
 hipError_t mttv_lead_launch(const MttvArgs& a, hipStream_t st);
+hipError_t mttv_trail_launch(const MttvArgs& a, const Sink& sk);
+hipError_t mttv_lead_launch(const MttvArgs& a, const Sink& sk);
 
 // Factor update, Gram, lambda, fit -----------------------------------------
 struct UpdateArgs {
@@ -118,6 +123,7 @@ struct UpdateArgs {
   int update;             // NNCP_HALS / NNCP_MU
 };
 hipError_t update_launch(const UpdateArgs& a, hipStream_t st);
+hipError_t update_launch(const UpdateArgs& a, const Sink& sk);
 
 struct FinalizeArgs {
   const float* W;         // I x R new factor (unnormalised)
@@ -146,6 +152,8 @@ struct FinalizeArgs {
 };
 int finalize_chunks(int64_t I, int R, int* rows_per_chunk);
 hipError_t finalize_launch(const FinalizeArgs& a, hipStream_t st);
+hipError_t finalize_launch(const FinalizeArgs& a, const Sink& sk);
+hipError_t pm_reduce_launch(const ReduceArgs& r, const Sink& sk);
 
 // lam_model = lam_in * prod_k lam[k]; S[0] = prod_{k != 0} G[k]
 hipError_t init_model_launch(const double* lam_in, double* lam, double* lam_model, const double* G,
@@ -163,6 +171,85 @@ hipError_t copy_f64_launch(double* dst, const double* src, int64_t n, hipStream_
 hipError_t widen_f32_launch(double* dst, const float* src, int64_t n, hipStream_t st);
 // lam[k] <- (lam[k] > 0 ? 1 : 0), n entries (after normalize_out)
 hipError_t unit_lambda_launch(double* lam, int64_t n, hipStream_t st);
+
+// ---------------------------------------------------------------------------
+// Launch records. Every kernel launch of the iteration goes through a Sink: it
+// is either launched on the sink's stream at once, or appended to the sink's
+// record as data (kernel kind + template variant + stand-alone grid + args).
+// The batched executor records one outer iteration per job and replays the
+// records of many jobs through persistent work-list kernels, one launch per
+// step and kernel family, so each job's arithmetic (tiling, split order) is
+// exactly that of its stand-alone launches.
+// ---------------------------------------------------------------------------
+struct ReduceArgs {      // split-K sum of partial-MTTKRP partials
+  const double* part;
+  void* T;
+  int t_f64;
+  int64_t Mtot, Mpad;
+  int RP, R, col0, nsplit;
+};
+struct PackArgs {        // hi/lo pack of the first contracted factor (16-bit tensors)
+  const float* H1;
+  int I1, I1pad, R, col0, RP;
+  unsigned short* pack;
+  float* hscale;
+};
+
+enum KKind : int {
+  K_PM_F32 = 1,     // variant: side*1000 + nb*100 + wm*10 + fast
+  K_PM_16 = 2,      // variant: (dtype == BF16)*10000 + side*1000 + nb*100 + wm*10 + fast
+  K_PACK16 = 3,     // variant: dtype == BF16
+  K_PM_REDUCE = 4,  // variant: t_f64
+  K_MTTV_TRAIL = 5, // variant: t_f64
+  K_MTTV_LEAD = 6,  // variant: group size * 10 + t_f64
+  K_UPDATE = 7,     // variant: values per lane (1 or 2)
+  K_FIN_SMALL = 8,
+  K_FIN_FUSED = 9,
+  K_GRAM_CHUNKS = 10,
+  K_FIN_TAIL = 11
+};
+// Kernel families: one persistent batched kernel each.
+enum KFamily : int { KF_PM_F32 = 0, KF_PM_16 = 1, KF_SMALL = 2, KF_COUNT = 3 };
+inline int kfamily(int kind) { return kind == K_PM_F32 ? KF_PM_F32 : ((kind == K_PM_16 || kind == K_PACK16) ? KF_PM_16 : KF_SMALL); }
+
+struct KOp {
+  int kind;
+  int variant;
+  unsigned gx, gy;   // work-groups of the stand-alone launch (x, y)
+  unsigned lds;      // dynamic LDS bytes
+  union {
+    PmArgs pm;
+    MttvArgs mt;
+    UpdateArgs up;
+    FinalizeArgs fin;
+    ReduceArgs red;
+    PackArgs pk;
+  } u;
+};
+
+// One work-group's share of a recorded launch: op index and its (x, y) tile.
+struct BItem {
+  int op;
+  int bx, by;
+};
+
+struct Sink {
+  hipStream_t st = nullptr;
+  void* rec = nullptr;  // std::vector<KOp>* when recording
+  Sink() = default;
+  Sink(hipStream_t s) : st(s) {}  // launch on s (implicit: a stream is a launching sink)
+};
+// Append a record (host); returns hipSuccess.
+hipError_t sink_record(const Sink& s, const KOp& op);
+
+// Persistent batched kernels: work-group b walks items b, b + grid, ... < *count
+// of `items`, each naming an op in `ops` (device arrays).
+hipError_t batch_launch_pm_f32(const BItem* items, const int* count, const KOp* ops, unsigned grid, size_t lds,
+                               hipStream_t st);
+hipError_t batch_launch_pm_16(const BItem* items, const int* count, const KOp* ops, unsigned grid, size_t lds,
+                              hipStream_t st);
+hipError_t batch_launch_small(const BItem* items, const int* count, const KOp* ops, unsigned grid, size_t lds,
+                              hipStream_t st);
 
 // Column scale of a Khatri-Rao operand, prod_j 1/lam[mode_j][r] (device code).
 __device__ __forceinline__ double krp_colscale(const KrpDesc& k, int r) {

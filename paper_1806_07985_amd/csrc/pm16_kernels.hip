@@ -62,11 +62,12 @@ struct T16<NNCP_F16> {
 // hi = round(v), lo = round(v - hi); rows I1..I1pad-1 and columns r >= R are 0.
 // hscale[r] = 2^-e.
 template <int DT>
-__global__ __launch_bounds__(256) void pm16_pack_kernel(const float* __restrict__ H1, int I1, int I1pad, int R,
-                                                        int col0, int RP, unsigned short* __restrict__ pack,
-                                                        float* __restrict__ hscale) {
+__device__ __forceinline__ void pm16_pack_body(const PackArgs& pa, int r) {
   __shared__ float red[256];
-  const int r = blockIdx.x;
+  const float* __restrict__ H1 = pa.H1;
+  const int I1 = pa.I1, I1pad = pa.I1pad, R = pa.R, col0 = pa.col0, RP = pa.RP;
+  unsigned short* __restrict__ pack = pa.pack;
+  float* __restrict__ hscale = pa.hscale;
   const bool live = r < R;
   const float* h = H1 + (int64_t)I1 * (col0 + r);
   float mx = 0.f;
@@ -96,6 +97,11 @@ __global__ __launch_bounds__(256) void pm16_pack_kernel(const float* __restrict_
     lo[i] = T16<DT>::enc(v - T16<DT>::dec(uh));
   }
   if (threadIdx.x == 0) hscale[r] = live ? ldexpf(1.f, -e) : 0.f;
+}
+
+template <int DT>
+__global__ __launch_bounds__(256) void pm16_pack_kernel(PackArgs pa) {
+  pm16_pack_body<DT>(pa, blockIdx.x);
 }
 
 // Per-(j, column) factors of a work-group's j block: Krest(j0 + jj, col0 + r)
@@ -144,7 +150,7 @@ __device__ __forceinline__ void pm16_reduce_store(const PmArgs& a, float (&accf)
 // row TR*li + tt of those 8 loads as its 8-k operand.
 // ----------------------------------------------------------------------------
 template <int DT, int NB, int TR, int WM, bool FAST, int D>
-__global__ __launch_bounds__(NT, 1) void pm_left_16(PmArgs a) {
+__device__ __forceinline__ void pm_left_16_body(const PmArgs& a, int bx, int by, int gx) {
   constexpr int RP = NB * 16;
   constexpr int WK = 4 / WM;
   constexpr int KS = 32;
@@ -162,8 +168,8 @@ __global__ __launch_bounds__(NT, 1) void pm_left_16(PmArgs a) {
   const int li = lane & 15, lq = lane >> 4;
   const int64_t Mtot = a.IL;
   const int mtile = WM * WROWS;
-  const int64_t mw = (int64_t)blockIdx.x * mtile + wm * WROWS;
-  const int ib = blockIdx.y % a.n_i1blk, jb = blockIdx.y / a.n_i1blk;
+  const int64_t mw = (int64_t)bx * mtile + wm * WROWS;
+  const int ib = by % a.n_i1blk, jb = by / a.n_i1blk;
   const int i1_0 = ib * a.i1blk;
   const int i1n = min(a.i1blk, a.I1pad - i1_0);
   const int64_t j0 = (int64_t)jb * a.jblk;
@@ -189,7 +195,7 @@ __global__ __launch_bounds__(NT, 1) void pm_left_16(PmArgs a) {
   const int ilim = a.I1 - i1_0;
   const unsigned short* zeros = (const unsigned short*)a.zeros;
 
-  const int jrot = (WK == 1 && jn > 1) ? (int)((blockIdx.x * 5u) % (unsigned)jn) : 0;
+  const int jrot = (WK == 1 && jn > 1) ? (int)(((unsigned)bx * 5u) % (unsigned)jn) : 0;
   int jl = sb / S1 + jrot, tl = sb - (sb / S1) * S1;
   if (jl >= jn) jl -= jn;
   auto load = [&](vT (&A)[8]) {
@@ -282,14 +288,14 @@ __global__ __launch_bounds__(NT, 1) void pm_left_16(PmArgs a) {
   pm16_reduce_store<NACC>(a, acc, lds_d, wk, wm, WK);
   if (wk != 0) return;
   const bool direct = (a.nsplit == 1);
-  const int64_t Mpad = (int64_t)gridDim.x * mtile;
+  const int64_t Mpad = (int64_t)gx * mtile;
 #pragma unroll
   for (int nb = 0; nb < NB; ++nb)
 #pragma unroll
     for (int v = 0; v < 4; ++v)
 #pragma unroll
       for (int tt = 0; tt < TR; ++tt)
-        pm_store(a, direct, Mtot, Mpad, RP, 16 * nb + li, mw + TR * (4 * lq + v) + tt, (double)acc[tt * NB + nb][v]);
+        pm_store(a, direct, Mtot, Mpad, RP, by, 16 * nb + li, mw + TR * (4 * lq + v) + tt, (double)acc[tt * NB + nb][v]);
 }
 
 // ----------------------------------------------------------------------------
@@ -300,7 +306,7 @@ __global__ __launch_bounds__(NT, 1) void pm_left_16(PmArgs a) {
 // between them; istages > 1 only with every wave on its own columns (WM = 4).
 // ----------------------------------------------------------------------------
 template <int DT, int NB, int MC, int WM, bool FAST, int D>
-__global__ __launch_bounds__(NT, 1) void pm_right_16(PmArgs a) {
+__device__ __forceinline__ void pm_right_16_body(const PmArgs& a, int bx, int by, int gx) {
   constexpr int RP = NB * 16;
   constexpr int WK = 4 / WM;
   constexpr int KS = 64;
@@ -316,9 +322,9 @@ __global__ __launch_bounds__(NT, 1) void pm_right_16(PmArgs a) {
   const int li = lane & 15, lq = lane >> 4;
   const int64_t Mtot = a.IR, Ktot = a.IL;
   const int mtile = WM * 16 * MC;
-  const int64_t cw = (int64_t)blockIdx.x * mtile + wm * 16 * MC;
+  const int64_t cw = (int64_t)bx * mtile + wm * 16 * MC;
   const int n_i1grp = a.n_i1blk / a.istages;
-  const int ib0 = (blockIdx.y % n_i1grp) * a.istages, jb = blockIdx.y / n_i1grp;
+  const int ib0 = (by % n_i1grp) * a.istages, jb = by / n_i1grp;
   const int64_t j0 = (int64_t)jb * a.jblk;
   const int jn = (int)min((int64_t)a.jblk, a.J - j0);
   const unsigned short* X = (const unsigned short*)a.X;
@@ -352,7 +358,7 @@ __global__ __launch_bounds__(NT, 1) void pm_right_16(PmArgs a) {
   // cursor (stage, j, t): t over the stage's k-steps, j over the block (rotated
   // start with one wave along K), stages in order. The load cursor runs D steps
   // ahead and wraps to the start after the last step, so it stays in bounds.
-  const int jrot = (WK == 1 && jn > 1) ? (int)((blockIdx.x * 5u) % (unsigned)jn) : 0;
+  const int jrot = (WK == 1 && jn > 1) ? (int)(((unsigned)bx * 5u) % (unsigned)jn) : 0;
   int stL = 0, S1L = stage_rows(0) / KS;
   int jl, tl, jcntL;
   {
@@ -470,14 +476,14 @@ __global__ __launch_bounds__(NT, 1) void pm_right_16(PmArgs a) {
   pm16_reduce_store<NACC>(a, acc, lds_d, wk, wm, WK);
   if (wk != 0) return;
   const bool direct = (a.nsplit == 1);
-  const int64_t Mpad = (int64_t)gridDim.x * mtile;
+  const int64_t Mpad = (int64_t)gx * mtile;
 #pragma unroll
   for (int g = 0; g < MC; ++g)
 #pragma unroll
     for (int nb = 0; nb < NB; ++nb)
 #pragma unroll
       for (int v = 0; v < 4; ++v)
-        pm_store(a, direct, Mtot, Mpad, RP, 16 * nb + li, cw + 16 * g + 4 * lq + v, (double)acc[g * NB + nb][v]);
+        pm_store(a, direct, Mtot, Mpad, RP, by, 16 * nb + li, cw + 16 * g + 4 * lq + v, (double)acc[g * NB + nb][v]);
 }
 
 // Rows per left wave = 16 * TR, columns per right wave = 16 * MC.
@@ -485,6 +491,15 @@ constexpr int left_tr16(int nb) { return nb >= 4 ? 4 : 8; }
 constexpr int right_mc16(int nb) { return nb >= 4 ? 4 : 4; }
 constexpr int left_pf16(int nb) { return nb >= 4 ? 3 : 3; }
 constexpr int right_pf16(int nb) { return nb >= 4 ? 3 : 3; }
+
+template <int DT, int NB, int TR, int WM, bool FAST, int D>
+__global__ __launch_bounds__(NT, 1) void pm_left_16(PmArgs a) {
+  pm_left_16_body<DT, NB, TR, WM, FAST, D>(a, blockIdx.x, blockIdx.y, gridDim.x);
+}
+template <int DT, int NB, int MC, int WM, bool FAST, int D>
+__global__ __launch_bounds__(NT, 1) void pm_right_16(PmArgs a) {
+  pm_right_16_body<DT, NB, MC, WM, FAST, D>(a, blockIdx.x, blockIdx.y, gridDim.x);
+}
 
 template <int DT, int NB, int WM, bool VEC>
 const void* kernel16(int side) {
@@ -511,6 +526,52 @@ const void* select16(int side, int nb, int wm, bool vec) {
   }
 }
 
+template <int DT, int NB, int WM, bool VEC>
+__device__ __forceinline__ void body16(int side, const PmArgs& a, int bx, int by, int gx) {
+  if (side == 0) pm_left_16_body<DT, NB, left_tr16(NB), WM, VEC, left_pf16(NB)>(a, bx, by, gx);
+  else pm_right_16_body<DT, NB, right_mc16(NB), WM, VEC, right_pf16(NB)>(a, bx, by, gx);
+}
+
+template <int DT>
+__device__ __forceinline__ void dispatch16(int v, const PmArgs& a, int bx, int by, int gx) {
+  const int side = (v / 1000) % 10;
+  switch (v % 1000) {
+    case 141: body16<DT, 1, 4, true>(side, a, bx, by, gx); break;
+    case 140: body16<DT, 1, 4, false>(side, a, bx, by, gx); break;
+    case 111: body16<DT, 1, 1, true>(side, a, bx, by, gx); break;
+    case 110: body16<DT, 1, 1, false>(side, a, bx, by, gx); break;
+    case 241: body16<DT, 2, 4, true>(side, a, bx, by, gx); break;
+    case 240: body16<DT, 2, 4, false>(side, a, bx, by, gx); break;
+    case 211: body16<DT, 2, 1, true>(side, a, bx, by, gx); break;
+    case 210: body16<DT, 2, 1, false>(side, a, bx, by, gx); break;
+    case 441: body16<DT, 4, 4, true>(side, a, bx, by, gx); break;
+    case 440: body16<DT, 4, 4, false>(side, a, bx, by, gx); break;
+    case 411: body16<DT, 4, 1, true>(side, a, bx, by, gx); break;
+    case 410: body16<DT, 4, 1, false>(side, a, bx, by, gx); break;
+    default: break;
+  }
+}
+
+// Persistent batched form (pack ops and 16-bit partial-MTTKRP tiles).
+__global__ __launch_bounds__(NT, 1) void pm16_batch_kernel(const BItem* __restrict__ items,
+                                                           const int* __restrict__ count,
+                                                           const KOp* __restrict__ ops) {
+  const int n = *count;
+  for (int i = blockIdx.x; i < n; i += gridDim.x) {
+    const BItem it = items[i];
+    const KOp& op = ops[it.op];
+    if (op.kind == K_PACK16) {
+      if (op.variant) pm16_pack_body<NNCP_BF16>(op.u.pk, it.bx);
+      else pm16_pack_body<NNCP_F16>(op.u.pk, it.bx);
+    } else if (op.variant >= 10000) {
+      dispatch16<NNCP_BF16>(op.variant, op.u.pm, it.bx, it.by, op.gx);
+    } else {
+      dispatch16<NNCP_F16>(op.variant, op.u.pm, it.bx, it.by, op.gx);
+    }
+    __syncthreads();
+  }
+}
+
 size_t reduce_lds16(int side, int nb, int wm) {
   if (wm >= 4) return 0;
   const int nacc = side == 0 ? left_tr16(nb) * nb : right_mc16(nb) * nb;
@@ -530,34 +591,62 @@ static bool vec16(const PmArgs& a, int side) {
   return vec && (a.I1 % pm_16_kstep(side) == 0);
 }
 
-hipError_t pm_launch_16(const PmLaunch& L, const PmArgs& a, hipStream_t st) {
+hipError_t pm_launch_16(const PmLaunch& L, const PmArgs& a, const Sink& sk) {
   const int RP = 16 * L.nb;
   if (!a.hpack || !a.hscale) return hipErrorInvalidValue;
-  const float* H1 = a.krp.f[0];
-  if (L.dtype == NNCP_BF16)
-    hipLaunchKernelGGL(pm16_pack_kernel<NNCP_BF16>, dim3(RP), dim3(256), 0, st, H1, a.I1, a.I1pad, a.R, a.col0, RP,
-                       a.hpack, a.hscale);
-  else
-    hipLaunchKernelGGL(pm16_pack_kernel<NNCP_F16>, dim3(RP), dim3(256), 0, st, H1, a.I1, a.I1pad, a.R, a.col0, RP,
-                       a.hpack, a.hscale);
-  hipError_t e = hipGetLastError();
-  if (e != hipSuccess) return e;
+  const bool bf = L.dtype == NNCP_BF16;
+  PackArgs pa{a.krp.f[0], a.I1, a.I1pad, a.R, a.col0, RP, a.hpack, a.hscale};
   const int wm = L.mtile / pm_16_wave_rows(L.side, L.nb);
   const bool v = vec16(a, L.side);
-  const void* k = L.dtype == NNCP_BF16 ? select16<NNCP_BF16>(L.side, L.nb, wm, v)
-                                       : select16<NNCP_F16>(L.side, L.nb, wm, v);
+  const int variant = (bf ? 10000 : 0) + L.side * 1000 + L.nb * 100 + wm * 10 + (v ? 1 : 0);
+  const void* k = bf ? select16<NNCP_BF16>(L.side, L.nb, wm, v) : select16<NNCP_F16>(L.side, L.nb, wm, v);
   if (!k) return hipErrorInvalidValue;
   size_t lds = L.lds_bytes;
   if (reduce_lds16(L.side, L.nb, wm) > lds) lds = reduce_lds16(L.side, L.nb, wm);
+  if (sk.rec) {
+    KOp op{};
+    op.kind = K_PACK16;
+    op.variant = bf ? 1 : 0;
+    op.gx = (unsigned)RP;
+    op.gy = 1;
+    op.u.pk = pa;
+    hipError_t e = sink_record(sk, op);
+    if (e != hipSuccess) return e;
+    KOp pm{};
+    pm.kind = K_PM_16;
+    pm.variant = variant;
+    pm.gx = (unsigned)L.mtiles;
+    pm.gy = (unsigned)L.nsplit;
+    pm.lds = (unsigned)lds;
+    pm.u.pm = a;
+    return sink_record(sk, pm);
+  }
+  if (bf) hipLaunchKernelGGL(pm16_pack_kernel<NNCP_BF16>, dim3(RP), dim3(256), 0, sk.st, pa);
+  else hipLaunchKernelGGL(pm16_pack_kernel<NNCP_F16>, dim3(RP), dim3(256), 0, sk.st, pa);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
   static bool attr_done[2][2][3][2][2] = {};
-  bool& done = attr_done[L.dtype == NNCP_BF16][L.side][L.nb == 1 ? 0 : (L.nb == 2 ? 1 : 2)][wm == 4][v];
+  bool& done = attr_done[bf][L.side][L.nb == 1 ? 0 : (L.nb == 2 ? 1 : 2)][wm == 4][v];
   if (!done) {
     if (hipFuncSetAttribute(k, hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024) != hipSuccess)
       (void)hipGetLastError();
     done = true;
   }
   void* args[] = {(void*)&a};
-  return hipLaunchKernel(k, dim3(L.mtiles, L.nsplit), dim3(NT), args, lds, st);
+  return hipLaunchKernel(k, dim3(L.mtiles, L.nsplit), dim3(NT), args, lds, sk.st);
+}
+
+hipError_t batch_launch_pm_16(const BItem* items, const int* count, const KOp* ops, unsigned grid, size_t lds,
+                              hipStream_t st) {
+  static bool attr = [] {
+    (void)hipFuncSetAttribute((const void*)pm16_batch_kernel, hipFuncAttributeMaxDynamicSharedMemorySize,
+                              160 * 1024);
+    (void)hipGetLastError();
+    return true;
+  }();
+  (void)attr;
+  hipLaunchKernelGGL(pm16_batch_kernel, dim3(grid), dim3(NT), lds, st, items, count, ops);
+  return hipGetLastError();
 }
 
 }  // namespace nncpk

@@ -71,8 +71,9 @@ __device__ __forceinline__ void wave_reduce_k(double (&acc)[NACC][4], double* ld
   }
 }
 
-// Store one output element: directly into T (FP64 or FP32) or into the split partials.
-__device__ __forceinline__ void pm_store(const PmArgs& a, bool direct, int64_t Mtot, int64_t Mpad, int RP,
+// Store one output element: directly into T (FP64 or FP32) or into the split
+// partials of split `by`.
+__device__ __forceinline__ void pm_store(const PmArgs& a, bool direct, int64_t Mtot, int64_t Mpad, int RP, int by,
                                          int r, int64_t mm, double o) {
   if (direct) {
     if (r < a.R && mm < Mtot) {
@@ -81,7 +82,7 @@ __device__ __forceinline__ void pm_store(const PmArgs& a, bool direct, int64_t M
       else ((float*)a.T)[idx] = (float)o;
     }
   } else {
-    a.partial[((size_t)blockIdx.y * RP + r) * Mpad + mm] = o;
+    a.partial[((size_t)by * RP + r) * Mpad + mm] = o;
   }
 }
 

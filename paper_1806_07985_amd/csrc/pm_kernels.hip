@@ -32,7 +32,7 @@ namespace {
 // u = 0..3; MFMA chain tt uses row TR*li + tt of every load.
 // ----------------------------------------------------------------------------
 template <int NB, int TR, int WM, bool FAST, int D>
-__global__ __launch_bounds__(NT, 2) void pm_left_f32(PmArgs a) {
+__device__ __forceinline__ void pm_left_f32_body(const PmArgs& a, int bx, int by, int gx) {
   constexpr bool VEC = FAST;
   constexpr int RP = NB * 16;
   constexpr int WK = 4 / WM;
@@ -51,9 +51,9 @@ __global__ __launch_bounds__(NT, 2) void pm_left_f32(PmArgs a) {
   const int li = lane & 15, lq = lane >> 4;
   const int64_t Mtot = a.IL;
   const int mtile = WM * WROWS;
-  const int64_t mbeg = (int64_t)blockIdx.x * mtile;
+  const int64_t mbeg = (int64_t)bx * mtile;
   const int64_t mw = mbeg + wm * WROWS;
-  const int ib = blockIdx.y % a.n_i1blk, jb = blockIdx.y / a.n_i1blk;
+  const int ib = by % a.n_i1blk, jb = by / a.n_i1blk;
   const int i1_0 = ib * a.i1blk;
   const int i1n = min(a.i1blk, a.I1pad - i1_0);
   const int64_t j0 = (int64_t)jb * a.jblk;
@@ -85,7 +85,7 @@ __global__ __launch_bounds__(NT, 2) void pm_left_f32(PmArgs a) {
   // load cursor (uniform): step = jl * S1 + tl. With one wave along K the group
   // starts at a j rotated by its M tile, so groups that share a split do not all
   // request the same addresses modulo the column stride at the same time.
-  const int jrot = (WK == 1 && jn > 1) ? (int)((blockIdx.x * 5u) % (unsigned)jn) : 0;
+  const int jrot = (WK == 1 && jn > 1) ? (int)(((unsigned)bx * 5u) % (unsigned)jn) : 0;
   int jl = sb / S1 + jrot, tl = sb - (sb / S1) * S1;
   if (jl >= jn) jl -= jn;  // an empty range (sb == S1 * jn) starts at the block's first j
   // The cursor always stays inside the group's j block (it wraps), so loads of
@@ -184,7 +184,7 @@ __global__ __launch_bounds__(NT, 2) void pm_left_f32(PmArgs a) {
 
   // acc[tt*NB+nb][v]: row mw + TR*(4*lq + v) + tt, rank column 16nb + li.
   const bool direct = (a.nsplit == 1);
-  const int64_t Mpad = (int64_t)gridDim.x * mtile;
+  const int64_t Mpad = (int64_t)gx * mtile;
   (void)mbeg;
   if (wk == 0) {
 #pragma unroll
@@ -193,7 +193,7 @@ __global__ __launch_bounds__(NT, 2) void pm_left_f32(PmArgs a) {
       for (int v = 0; v < 4; ++v)
 #pragma unroll
         for (int tt = 0; tt < TR; ++tt)
-          pm_store(a, direct, Mtot, Mpad, RP, 16 * nb + li, mw + TR * (4 * lq + v) + tt, acc[tt * NB + nb][v]);
+          pm_store(a, direct, Mtot, Mpad, RP, by, 16 * nb + li, mw + TR * (4 * lq + v) + tt, acc[tt * NB + nb][v]);
   }
 }
 
@@ -204,7 +204,7 @@ __global__ __launch_bounds__(NT, 2) void pm_left_f32(PmArgs a) {
 // 16-byte load, h = 0..1) of column c = group + li.
 // ----------------------------------------------------------------------------
 template <int NB, int MC, int WM, bool FAST, int D>
-__global__ __launch_bounds__(NT, 2) void pm_right_f32(PmArgs a) {
+__device__ __forceinline__ void pm_right_f32_body(const PmArgs& a, int bx, int by, int gx) {
   constexpr bool VEC = FAST;
   constexpr int RP = NB * 16;
   constexpr int WK = 4 / WM;
@@ -221,9 +221,9 @@ __global__ __launch_bounds__(NT, 2) void pm_right_f32(PmArgs a) {
   const int li = lane & 15, lq = lane >> 4;
   const int64_t Mtot = a.IR, Ktot = a.IL;
   const int mtile = WM * 16 * MC;
-  const int64_t mbeg = (int64_t)blockIdx.x * mtile;
+  const int64_t mbeg = (int64_t)bx * mtile;
   const int64_t cw = mbeg + wm * 16 * MC;
-  const int ib = blockIdx.y % a.n_i1blk, jb = blockIdx.y / a.n_i1blk;
+  const int ib = by % a.n_i1blk, jb = by / a.n_i1blk;
   const int i1_0 = ib * a.i1blk;
   const int i1n = min(a.i1blk, a.I1pad - i1_0);
   const int64_t j0 = (int64_t)jb * a.jblk;
@@ -252,7 +252,7 @@ __global__ __launch_bounds__(NT, 2) void pm_right_f32(PmArgs a) {
   const int ilim = a.I1 - i1_0;
   const float* zeros = (const float*)a.zeros;
 
-  const int jrot = (WK == 1 && jn > 1) ? (int)((blockIdx.x * 5u) % (unsigned)jn) : 0;
+  const int jrot = (WK == 1 && jn > 1) ? (int)(((unsigned)bx * 5u) % (unsigned)jn) : 0;
   int jl = sb / S1 + jrot, tl = sb - (sb / S1) * S1;
   if (jl >= jn) jl -= jn;  // an empty range (sb == S1 * jn) starts at the block's first j
   auto load = [&](f4 (&A)[MC][2], bool sv) {
@@ -347,7 +347,7 @@ __global__ __launch_bounds__(NT, 2) void pm_right_f32(PmArgs a) {
 
   // acc[g*NB+nb][v]: column c = cw + 16g + 4*lq + v, rank column 16nb + li.
   const bool direct = (a.nsplit == 1);
-  const int64_t Mpad = (int64_t)gridDim.x * mtile;
+  const int64_t Mpad = (int64_t)gx * mtile;
   (void)mbeg;
   if (wk == 0) {
 #pragma unroll
@@ -356,7 +356,7 @@ __global__ __launch_bounds__(NT, 2) void pm_right_f32(PmArgs a) {
       for (int nb = 0; nb < NB; ++nb)
 #pragma unroll
         for (int v = 0; v < 4; ++v)
-          pm_store(a, direct, Mtot, Mpad, RP, 16 * nb + li, cw + 16 * g + 4 * lq + v, acc[g * NB + nb][v]);
+          pm_store(a, direct, Mtot, Mpad, RP, by, 16 * nb + li, cw + 16 * g + 4 * lq + v, acc[g * NB + nb][v]);
   }
 }
 
@@ -368,14 +368,26 @@ constexpr int right_mc(int nb) { return nb >= 4 ? 2 : 4; }
 constexpr int left_pf(int nb) { return nb == 2 ? 3 : 4; }
 constexpr int right_pf(int nb) { return nb >= 4 ? 3 : 3; }
 
+// Stand-alone kernels: one work-group per (M tile, split).
+template <int NB, int TR, int WM, bool FAST, int D>
+__global__ __launch_bounds__(NT, 2) void pm_left_f32(PmArgs a) {
+  pm_left_f32_body<NB, TR, WM, FAST, D>(a, blockIdx.x, blockIdx.y, gridDim.x);
+}
+template <int NB, int MC, int WM, bool FAST, int D>
+__global__ __launch_bounds__(NT, 2) void pm_right_f32(PmArgs a) {
+  pm_right_f32_body<NB, MC, WM, FAST, D>(a, blockIdx.x, blockIdx.y, gridDim.x);
+}
+
 template <int NB, int WM, bool VEC>
 const void* kernel_ptr(int side) {
   if (side == 0) return (const void*)pm_left_f32<NB, left_tr(NB), WM, VEC, left_pf(NB)>;
   return (const void*)pm_right_f32<NB, right_mc(NB), WM, VEC, right_pf(NB)>;
 }
 
-const void* select_kernel(int side, int nb, int wm, bool vec) {
-  switch (nb * 100 + wm * 10 + (vec ? 1 : 0)) {
+// variant = side*1000 + nb*100 + wm*10 + vec
+const void* select_variant(int v) {
+  const int side = v / 1000;
+  switch (v % 1000) {
     case 141: return kernel_ptr<1, 4, true>(side);
     case 140: return kernel_ptr<1, 4, false>(side);
     case 111: return kernel_ptr<1, 1, true>(side);
@@ -389,6 +401,41 @@ const void* select_kernel(int side, int nb, int wm, bool vec) {
     case 411: return kernel_ptr<4, 1, true>(side);
     case 410: return kernel_ptr<4, 1, false>(side);
     default: return nullptr;
+  }
+}
+
+template <int NB, int WM, bool VEC>
+__device__ __forceinline__ void body_for(int side, const PmArgs& a, int bx, int by, int gx) {
+  if (side == 0) pm_left_f32_body<NB, left_tr(NB), WM, VEC, left_pf(NB)>(a, bx, by, gx);
+  else pm_right_f32_body<NB, right_mc(NB), WM, VEC, right_pf(NB)>(a, bx, by, gx);
+}
+
+// Persistent batched form: work-group b takes items b, b + gridDim.x, ...; each
+// item is one (M tile, split) work-group of a recorded stand-alone launch.
+__global__ __launch_bounds__(NT, 1) void pm_f32_batch_kernel(const BItem* __restrict__ items,
+                                                             const int* __restrict__ count,
+                                                             const KOp* __restrict__ ops) {
+  const int n = *count;
+  for (int i = blockIdx.x; i < n; i += gridDim.x) {
+    const BItem it = items[i];
+    const KOp& op = ops[it.op];
+    const int v = op.variant, side = v / 1000;
+    switch (v % 1000) {
+      case 141: body_for<1, 4, true>(side, op.u.pm, it.bx, it.by, op.gx); break;
+      case 140: body_for<1, 4, false>(side, op.u.pm, it.bx, it.by, op.gx); break;
+      case 111: body_for<1, 1, true>(side, op.u.pm, it.bx, it.by, op.gx); break;
+      case 110: body_for<1, 1, false>(side, op.u.pm, it.bx, it.by, op.gx); break;
+      case 241: body_for<2, 4, true>(side, op.u.pm, it.bx, it.by, op.gx); break;
+      case 240: body_for<2, 4, false>(side, op.u.pm, it.bx, it.by, op.gx); break;
+      case 211: body_for<2, 1, true>(side, op.u.pm, it.bx, it.by, op.gx); break;
+      case 210: body_for<2, 1, false>(side, op.u.pm, it.bx, it.by, op.gx); break;
+      case 441: body_for<4, 4, true>(side, op.u.pm, it.bx, it.by, op.gx); break;
+      case 440: body_for<4, 4, false>(side, op.u.pm, it.bx, it.by, op.gx); break;
+      case 411: body_for<4, 1, true>(side, op.u.pm, it.bx, it.by, op.gx); break;
+      case 410: body_for<4, 1, false>(side, op.u.pm, it.bx, it.by, op.gx); break;
+      default: break;
+    }
+    __syncthreads();  // LDS is reused by the next item
   }
 }
 
@@ -411,14 +458,38 @@ static bool f32_vec(const PmArgs& a, int side) {
   return vec && (a.I1 % pm_f32_kstep(side) == 0);
 }
 
-hipError_t pm_launch_f32(const PmLaunch& L, const PmArgs& a, hipStream_t st) {
+hipError_t pm_launch_f32(const PmLaunch& L, const PmArgs& a, const Sink& sk) {
   const int wm = L.mtile / pm_f32_wave_rows(L.side, L.nb);
-  const void* k = select_kernel(L.side, L.nb, wm, f32_vec(a, L.side));
+  const int variant = L.side * 1000 + L.nb * 100 + wm * 10 + (f32_vec(a, L.side) ? 1 : 0);
+  const void* k = select_variant(variant);
   if (!k) return hipErrorInvalidValue;
   size_t lds = L.lds_bytes;
   if (reduce_lds(L.side, L.nb, wm) > lds) lds = reduce_lds(L.side, L.nb, wm);
+  if (sk.rec) {
+    KOp op{};
+    op.kind = K_PM_F32;
+    op.variant = variant;
+    op.gx = (unsigned)L.mtiles;
+    op.gy = (unsigned)L.nsplit;
+    op.lds = (unsigned)lds;
+    op.u.pm = a;
+    return sink_record(sk, op);
+  }
   void* args[] = {(void*)&a};
-  return hipLaunchKernel(k, dim3(L.mtiles, L.nsplit), dim3(NT), args, lds, st);
+  return hipLaunchKernel(k, dim3(L.mtiles, L.nsplit), dim3(NT), args, lds, sk.st);
+}
+
+hipError_t batch_launch_pm_f32(const BItem* items, const int* count, const KOp* ops, unsigned grid, size_t lds,
+                               hipStream_t st) {
+  static bool attr = [] {
+    (void)hipFuncSetAttribute((const void*)pm_f32_batch_kernel, hipFuncAttributeMaxDynamicSharedMemorySize,
+                              160 * 1024);
+    (void)hipGetLastError();
+    return true;
+  }();
+  (void)attr;
+  hipLaunchKernelGGL(pm_f32_batch_kernel, dim3(grid), dim3(NT), lds, st, items, count, ops);
+  return hipGetLastError();
 }
 
 }  // namespace nncpk

@@ -135,46 +135,26 @@ void pm_fill_args(const PmLaunch& L, PmArgs& a) {
   a.istages = L.istages;
 }
 
-// T(m, col0 + r) = sum over splits (in split order) of partial[(sp*RP + r)*Mpad + m],
-// one thread per output element pair (coalesced along m).
-template <typename TO>
-__global__ __launch_bounds__(256) void pm_reduce_kernel(const double* __restrict__ part, TO* __restrict__ T,
-                                                        int64_t Mtot, int64_t Mpad, int RP, int R, int col0,
-                                                        int nsplit) {
-  const int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x;
-  const int64_t total = Mtot * R;
-  if (e >= total) return;
-  const int r = (int)(e / Mtot);
-  const int64_t m = e - (int64_t)r * Mtot;
-  const double* p = part + (size_t)r * Mpad + m;
-  const size_t st = (size_t)RP * Mpad;
-  double s = 0.0;
-  int sp = 0;
-  for (; sp + 4 <= nsplit; sp += 4) {
-    const double v0 = p[(sp + 0) * st], v1 = p[(sp + 1) * st], v2 = p[(sp + 2) * st], v3 = p[(sp + 3) * st];
-    s += v0;
-    s += v1;
-    s += v2;
-    s += v3;
-  }
-  for (; sp < nsplit; ++sp) s += p[sp * st];
-  T[m + Mtot * (int64_t)(col0 + r)] = (TO)s;
+hipError_t pm_launch(const PmLaunch& L, const PmArgs& a, const Sink& sk) {
+  hipError_t e = (L.dtype == NNCP_F32) ? pm_launch_f32(L, a, sk) : pm_launch_16(L, a, sk);
+  if (e != hipSuccess || L.nsplit <= 1) return e;
+  ReduceArgs r{};
+  r.part = a.partial;
+  r.T = a.T;
+  r.t_f64 = a.t_f64;
+  r.Mtot = L.side == 0 ? a.IL : a.IR;
+  r.Mpad = (int64_t)L.mtiles * L.mtile;
+  r.RP = 16 * L.nb;
+  r.R = a.R;
+  r.col0 = a.col0;
+  r.nsplit = L.nsplit;
+  return pm_reduce_launch(r, sk);
 }
 
 hipError_t pm_launch(const PmLaunch& L, const PmArgs& a, hipStream_t st) {
-  hipError_t e = (L.dtype == NNCP_F32) ? pm_launch_f32(L, a, st) : pm_launch_16(L, a, st);
-  if (e != hipSuccess || L.nsplit <= 1) return e;
-  const int64_t Mtot = L.side == 0 ? a.IL : a.IR;
-  const int64_t Mpad = (int64_t)L.mtiles * L.mtile;
-  const int64_t total = Mtot * a.R;
-  const dim3 grid((unsigned)((total + 255) / 256));
-  if (a.t_f64)
-    hipLaunchKernelGGL(pm_reduce_kernel<double>, grid, dim3(256), 0, st, a.partial, (double*)a.T, Mtot, Mpad,
-                       16 * L.nb, a.R, a.col0, L.nsplit);
-  else
-    hipLaunchKernelGGL(pm_reduce_kernel<float>, grid, dim3(256), 0, st, a.partial, (float*)a.T, Mtot, Mpad,
-                       16 * L.nb, a.R, a.col0, L.nsplit);
-  return hipGetLastError();
+  Sink sk;
+  sk.st = st;
+  return pm_launch(L, a, sk);
 }
 
 }  // namespace nncpk

@@ -8,6 +8,9 @@
 //    (Section IV-B, appendix algorithm), all accumulated in FP64 with a
 //    deterministic two-stage reduction;
 //  * ||X||^2 and FP32 -> BF16/FP16 quantisation of the stored tensor.
+#include <cstring>
+#include <vector>
+
 #include "nncp_internal.hpp"
 
 namespace nncpk {
@@ -121,12 +124,11 @@ __global__ void unit_lambda_kernel(double* lam, int64_t n) {
 constexpr int TRAIL_KCH = 1024;
 
 template <typename TN>
-__global__ __launch_bounds__(NT) void mttv_trail_kernel(MttvArgs a) {
+__device__ __forceinline__ void mttv_trail_body(const MttvArgs& a, int bx, int r) {
   __shared__ double kv[TRAIL_KCH];
   __shared__ double red[4][64];
-  const int r = blockIdx.y;
   const int ti = threadIdx.x & 63, ph = threadIdx.x >> 6;
-  const int64_t i = (int64_t)blockIdx.x * 64 + ti;
+  const int64_t i = (int64_t)bx * 64 + ti;
   const double scale = krp_colscale(a.krp, r);
   const TN* Tr = (const TN*)a.T + (int64_t)r * a.Ia * a.J;
   double acc = 0.0;
@@ -166,16 +168,20 @@ __global__ __launch_bounds__(NT) void mttv_trail_kernel(MttvArgs a) {
     stv(a.out, i + a.Ia * r, a.out_f64, s);
   }
 }
+template <typename TN>
+__global__ __launch_bounds__(NT) void mttv_trail_kernel(MttvArgs a) {
+  mttv_trail_body<TN>(a, blockIdx.x, blockIdx.y);
+}
 
 // --------------------------------------------------------------------------
 // Multi-TTV, leading mode: out(j, r) = sum_i T(i, j, r) H(i, r), one lane group
 // of GS lanes per output (contiguous dot product, shuffle reduction).
 // --------------------------------------------------------------------------
 template <int GS, typename TN>
-__global__ __launch_bounds__(NT) void mttv_lead_kernel(MttvArgs a) {
+__device__ __forceinline__ void mttv_lead_body(const MttvArgs& a, int bx) {
   constexpr int OPB = NT / GS;
   const int g = threadIdx.x / GS, p = threadIdx.x % GS;
-  const int64_t o = (int64_t)blockIdx.x * OPB + g;  // output index j + J*r
+  const int64_t o = (int64_t)bx * OPB + g;  // output index j + J*r
   const int64_t total = a.J * a.R;
   double acc = 0.0;
   int r = 0;
@@ -189,6 +195,10 @@ __global__ __launch_bounds__(NT) void mttv_lead_kernel(MttvArgs a) {
 #pragma unroll
   for (int off = GS / 2; off > 0; off >>= 1) acc += __shfl_xor(acc, off, GS);
   if (p == 0 && o < total) stv(a.out, o, a.out_f64, acc * krp_colscale(a.krp, r));
+}
+template <int GS, typename TN>
+__global__ __launch_bounds__(NT) void mttv_lead_kernel(MttvArgs a) {
+  mttv_lead_body<GS, TN>(a, blockIdx.x);
 }
 
 // --------------------------------------------------------------------------
@@ -206,20 +216,14 @@ __device__ __forceinline__ double readlane_f64(double v, int lane) {
 }
 
 template <int VPL>
-__global__ __launch_bounds__(NT) void update_kernel(UpdateArgs a) {
+__device__ __forceinline__ void update_body(const UpdateArgs& a, int bx) {
   extern __shared__ double Sl[];  // R*R, then R inverse diagonals
   const int R = a.R;
   double* invd = Sl + R * R;
-  for (int e = threadIdx.x; e < R * R; e += NT) Sl[e] = a.S[e];
-  for (int k = threadIdx.x; k < R; k += NT) {
-    const double d = a.S[k * R + k];
-    invd[k] = d > 0.0 ? 1.0 / d : 0.0;
-  }
-  __syncthreads();
   const int p = threadIdx.x & 63;
-  const int64_t row = (int64_t)blockIdx.x * (NT / 64) + (threadIdx.x >> 6);
-  if (row >= a.I) return;  // whole wave leaves together (row is wave-uniform)
-
+  const int64_t row = (int64_t)bx * (NT / 64) + (threadIdx.x >> 6);
+  const bool live = row < a.I;  // wave-uniform
+  // this row's loads are issued before S is staged, so their latency overlaps it
   double w[VPL], m[VPL], g[VPL];
 #pragma unroll
   for (int v = 0; v < VPL; ++v) {
@@ -227,13 +231,21 @@ __global__ __launch_bounds__(NT) void update_kernel(UpdateArgs a) {
     w[v] = 0.0;
     m[v] = 0.0;
     g[v] = 0.0;
-    if (k < R) {
+    if (live && k < R) {
       const double ls = a.lam_self[k];
       const double f = ls > 0.0 ? a.lam_model[k] / ls : 0.0;
       w[v] = (double)a.W[row + a.I * k] * f;
       m[v] = ldv(a.M, row + a.I * k, a.m_f64);
     }
   }
+  for (int e = threadIdx.x; e < R * R; e += NT) Sl[e] = a.S[e];
+  for (int k = threadIdx.x; k < R; k += NT) {
+    const double d = a.S[k * R + k];
+    invd[k] = d > 0.0 ? 1.0 / d : 0.0;
+  }
+  __syncthreads();
+  if (!live) return;  // whole wave leaves together
+
   // g = w S with the starting w
   for (int r = 0; r < R; ++r) {
     const int v = r >> 6;
@@ -289,6 +301,10 @@ __global__ __launch_bounds__(NT) void update_kernel(UpdateArgs a) {
     if (k < R) a.W[row + a.I * k] = (float)w[v];
   }
 }
+template <int VPL>
+__global__ __launch_bounds__(NT) void update_kernel(UpdateArgs a) {
+  update_body<VPL>(a, blockIdx.x);
+}
 
 // Rows of W staged in LDS at a time (FP64): about 32 KB.
 __host__ __device__ inline int fin_sub_rows(int R) {
@@ -298,13 +314,13 @@ __host__ __device__ inline int fin_sub_rows(int R) {
 
 // Stage 1: W^T W (and <M, W> when the fit is due) over this block's row chunk,
 // written to partial[chunk] (R*R + 1 doubles).
-__device__ void gram_chunk(const FinalizeArgs& a, double* fl, double* sh) {
+__device__ void gram_chunk(const FinalizeArgs& a, double* fl, double* sh, int bx) {
   const int R = a.R, RR = R * R;
   const int sub = fin_sub_rows(R);
-  const int64_t r0 = (int64_t)blockIdx.x * a.rows_per_chunk;
+  const int64_t r0 = (int64_t)bx * a.rows_per_chunk;
   int64_t r1 = r0 + a.rows_per_chunk;
   if (r1 > a.I) r1 = a.I;
-  double* part = a.partial + (size_t)blockIdx.x * (RR + 1);
+  double* part = a.partial + (size_t)bx * (RR + 1);
   // Each thread owns entries e = tid, tid + NT, ...; the running sums live in
   // this block's partial slot (only this thread touches them).
   double bsum = 0.0;
@@ -405,25 +421,227 @@ __device__ void finalize_tail(const FinalizeArgs& a, double* fl, double* sh) {
   }
 }
 
+// Small problems (one row chunk, R <= 64): one work-group does everything.
+// The other modes' Gram product (for S of the next mode) and S of this mode
+// (for gamma) are read into LDS first, so their latency overlaps the Gram. Each
+// thread accumulates a 4 x 4 block of W^T W over one phase of the rows in
+// registers (FP64); phases are summed through LDS in phase order, and the tail
+// (lambda, normalised Gram, fit, next S) works from LDS.
+constexpr int kSmallMaxR = 64;
+
+__device__ __forceinline__ void finalize_small_body(const FinalizeArgs& a) {
+  extern __shared__ double lds[];
+  __shared__ double sh[NT / 64];
+  const int R = a.R, RR = R * R;
+  const int nb4 = (R + 3) >> 2, R4 = nb4 << 2;
+  const int nblk = nb4 * nb4;
+  const int nph = NT / nblk;  // >= 1 for R <= 64
+  double* Gh = lds;                  // RR + 1 (raw Gram, beta)
+  double* P = Gh + RR + 1;           // RR: product of the Grams other than mode and next_mode
+  double* Sm = P + RR;               // RR: S of this mode (fit only)
+  double* work = Sm + RR;            // staging rows [sub][R4], then phase partials [nph][nblk][16]
+  const int sub = (int)(4096 / R4) < 1 ? 1 : (int)(4096 / R4);
+  const int tid = threadIdx.x;
+
+  if (a.next_mode >= 0)
+    for (int e = tid; e < RR; e += NT) {
+      double v = 1.0;
+      for (int k = 0; k < a.N; ++k)
+        if (k != a.next_mode && k != a.mode) v *= a.G[(int64_t)k * RR + e];
+      P[e] = v;
+    }
+  if (a.do_fit)
+    for (int e = tid; e < RR; e += NT) Sm[e] = a.S[(int64_t)a.mode * RR + e];
+
+  const bool active = tid < nblk * nph;
+  const int blk = tid % nblk, ph = tid / nblk;
+  const int bx = blk / nb4, by = blk - bx * nb4;
+  double acc[4][4];
+#pragma unroll
+  for (int i = 0; i < 4; ++i)
+#pragma unroll
+    for (int j = 0; j < 4; ++j) acc[i][j] = 0.0;
+  double bsum = 0.0;
+  for (int64_t s0 = 0; s0 < a.I; s0 += sub) {
+    const int cnt = (int)((a.I - s0) < sub ? (a.I - s0) : sub);
+    __syncthreads();
+    for (int e = tid; e < cnt * R4; e += NT) {
+      const int k = e / cnt, rw = e - k * cnt;
+      double wv = 0.0;
+      if (k < R) {
+        wv = (double)a.W[s0 + rw + a.I * k];
+        if (a.do_fit && a.M) bsum += wv * ldv(a.M, s0 + rw + a.I * k, a.m_f64);
+      }
+      work[rw * R4 + k] = wv;
+    }
+    __syncthreads();
+    if (active) {
+      for (int rw = ph; rw < cnt; rw += nph) {
+        const double* row = work + rw * R4;
+        double x[4], y[4];
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+          x[i] = row[4 * bx + i];
+          y[i] = row[4 * by + i];
+        }
+#pragma unroll
+        for (int i = 0; i < 4; ++i)
+#pragma unroll
+          for (int j = 0; j < 4; ++j) acc[i][j] += x[i] * y[j];
+      }
+    }
+  }
+  const double beta = block_sum(bsum, sh);
+  __syncthreads();
+  if (active) {
+    double* dst = work + ((size_t)ph * nblk + blk) * 16;
+#pragma unroll
+    for (int i = 0; i < 4; ++i)
+#pragma unroll
+      for (int j = 0; j < 4; ++j) dst[i * 4 + j] = acc[i][j];
+  }
+  __syncthreads();
+  for (int e = tid; e < RR; e += NT) {
+    const int x = e / R, y = e - x * R;
+    const int b = (x >> 2) * nb4 + (y >> 2), q = (x & 3) * 4 + (y & 3);
+    double v = 0.0;
+    for (int p = 0; p < nph; ++p) v += work[((size_t)p * nblk + b) * 16 + q];
+    Gh[e] = v;
+  }
+  if (tid == 0) Gh[RR] = beta;
+  __syncthreads();
+
+  if (a.gram_raw)
+    for (int e = tid; e < RR; e += NT) a.gram_raw[e] = Gh[e];
+  double* lamm = a.lam + (int64_t)a.mode * R;
+  for (int k = tid; k < R; k += NT) {
+    const double l = sqrt(Gh[k * R + k]);
+    lamm[k] = l;
+    if (a.set_model) a.lam_model[k] = l;
+  }
+  double* Gm = a.G + (int64_t)a.mode * RR;
+  double gp = 0.0;
+  for (int e = tid; e < RR; e += NT) {
+    const int x = e / R, y = e - x * R;
+    const double lx = sqrt(Gh[x * R + x]), ly = sqrt(Gh[y * R + y]);
+    const double g = (lx > 0.0 && ly > 0.0) ? Gh[e] / (lx * ly) : 0.0;
+    Gm[e] = g;
+    if (a.next_mode >= 0) a.S[(int64_t)a.next_mode * RR + e] = P[e] * g;
+    if (a.do_fit) gp += Sm[e] * Gh[e];
+  }
+  if (a.do_fit) {
+    // gamma = 1^T (S^(mode) * G_hat) 1 with G_hat the Gram of the unnormalised factor
+    const double gamma = block_sum(gp, sh);
+    if (tid == 0) {
+      const double alpha = a.alpha[0];
+      double num = alpha - 2.0 * Gh[RR] + gamma;
+      num = num > 0.0 ? num : 0.0;
+      const double eps = alpha > 0.0 ? sqrt(num / alpha) : 0.0;
+      const int it = *a.iter_counter;
+      if (it < a.fit_capacity) a.fit_out[it] = 1.0 - eps;
+      *a.iter_counter = it + 1;
+    }
+  }
+}
+
+__global__ __launch_bounds__(NT) void finalize_small_kernel(FinalizeArgs a) { finalize_small_body(a); }
+
 // One block does both stages (a single row chunk).
-__global__ __launch_bounds__(NT) void finalize_fused_kernel(FinalizeArgs a) {
+__device__ __forceinline__ void finalize_fused_body(const FinalizeArgs& a) {
   extern __shared__ double fl[];
   __shared__ double sh[NT / 64];
-  gram_chunk(a, fl, sh);
+  gram_chunk(a, fl, sh, 0);
   __syncthreads();
   finalize_tail(a, fl, sh);
 }
-
-__global__ __launch_bounds__(NT) void gram_chunks_kernel(FinalizeArgs a) {
+__device__ __forceinline__ void gram_chunks_body(const FinalizeArgs& a, int bx) {
   extern __shared__ double fl[];
   __shared__ double sh[NT / 64];
-  gram_chunk(a, fl, sh);
+  gram_chunk(a, fl, sh, bx);
 }
-
-__global__ __launch_bounds__(NT) void finalize_tail_kernel(FinalizeArgs a) {
+__device__ __forceinline__ void finalize_tail_body(const FinalizeArgs& a) {
   extern __shared__ double fl[];
   __shared__ double sh[NT / 64];
   finalize_tail(a, fl, sh);
+}
+__global__ __launch_bounds__(NT) void finalize_fused_kernel(FinalizeArgs a) { finalize_fused_body(a); }
+__global__ __launch_bounds__(NT) void gram_chunks_kernel(FinalizeArgs a) { gram_chunks_body(a, blockIdx.x); }
+__global__ __launch_bounds__(NT) void finalize_tail_kernel(FinalizeArgs a) { finalize_tail_body(a); }
+
+// Split-K sum of partial-MTTKRP partials: T(m, col0 + r) = sum over splits (in
+// split order) of part[(sp*RP + r)*Mpad + m], one thread per output (coalesced along m).
+template <typename TO>
+__device__ __forceinline__ void pm_reduce_body(const ReduceArgs& ra, int bx) {
+  const int64_t e = (int64_t)bx * NT + threadIdx.x;
+  const int64_t total = ra.Mtot * ra.R;
+  if (e >= total) return;
+  const int r = (int)(e / ra.Mtot);
+  const int64_t m = e - (int64_t)r * ra.Mtot;
+  const double* p = ra.part + (size_t)r * ra.Mpad + m;
+  const size_t st = (size_t)ra.RP * ra.Mpad;
+  double s = 0.0;
+  int sp = 0;
+  for (; sp + 4 <= ra.nsplit; sp += 4) {
+    const double v0 = p[(sp + 0) * st], v1 = p[(sp + 1) * st], v2 = p[(sp + 2) * st], v3 = p[(sp + 3) * st];
+    s += v0;
+    s += v1;
+    s += v2;
+    s += v3;
+  }
+  for (; sp < ra.nsplit; ++sp) s += p[sp * st];
+  ((TO*)ra.T)[m + ra.Mtot * (int64_t)(ra.col0 + r)] = (TO)s;
+}
+template <typename TO>
+__global__ __launch_bounds__(NT) void pm_reduce_kernel(ReduceArgs ra) {
+  pm_reduce_body<TO>(ra, blockIdx.x);
+}
+
+// Persistent batched form of the small kernels of the iteration.
+__device__ __forceinline__ void small_op(const KOp& op, int bx, int by) {
+  switch (op.kind) {
+    case K_PM_REDUCE:
+      if (op.variant) pm_reduce_body<double>(op.u.red, bx);
+      else pm_reduce_body<float>(op.u.red, bx);
+      break;
+    case K_MTTV_TRAIL:
+      if (op.variant) mttv_trail_body<double>(op.u.mt, bx, by);
+      else mttv_trail_body<float>(op.u.mt, bx, by);
+      break;
+    case K_MTTV_LEAD:
+      switch (op.variant) {
+        case 41: mttv_lead_body<4, double>(op.u.mt, bx); break;
+        case 40: mttv_lead_body<4, float>(op.u.mt, bx); break;
+        case 81: mttv_lead_body<8, double>(op.u.mt, bx); break;
+        case 80: mttv_lead_body<8, float>(op.u.mt, bx); break;
+        case 161: mttv_lead_body<16, double>(op.u.mt, bx); break;
+        case 160: mttv_lead_body<16, float>(op.u.mt, bx); break;
+        case 321: mttv_lead_body<32, double>(op.u.mt, bx); break;
+        case 320: mttv_lead_body<32, float>(op.u.mt, bx); break;
+        case 641: mttv_lead_body<64, double>(op.u.mt, bx); break;
+        default: mttv_lead_body<64, float>(op.u.mt, bx); break;
+      }
+      break;
+    case K_UPDATE:
+      if (op.variant == 1) update_body<1>(op.u.up, bx);
+      else update_body<2>(op.u.up, bx);
+      break;
+    case K_FIN_SMALL: finalize_small_body(op.u.fin); break;
+    case K_FIN_FUSED: finalize_fused_body(op.u.fin); break;
+    case K_GRAM_CHUNKS: gram_chunks_body(op.u.fin, bx); break;
+    case K_FIN_TAIL: finalize_tail_body(op.u.fin); break;
+    default: break;
+  }
+}
+
+__global__ __launch_bounds__(NT) void small_batch_kernel(const BItem* __restrict__ items,
+                                                         const int* __restrict__ count,
+                                                         const KOp* __restrict__ ops) {
+  const int n = *count;
+  for (int i = blockIdx.x; i < n; i += gridDim.x) {
+    const BItem it = items[i];
+    small_op(ops[it.op], it.bx, it.by);
+    __syncthreads();
+  }
 }
 
 __global__ void init_model_kernel(const double* lam_in, const double* lam, double* lam_model,
@@ -513,24 +731,38 @@ hipError_t unit_lambda_launch(double* lam, int64_t n, hipStream_t st) {
   return hipGetLastError();
 }
 
-hipError_t mttv_trail_launch(const MttvArgs& a, hipStream_t st) {
-  if (a.Ia <= 0 || a.R <= 0) return hipSuccess;
-  dim3 g((unsigned)((a.Ia + 63) / 64), a.R), b(NT);
-  if (a.t_f64) hipLaunchKernelGGL(mttv_trail_kernel<double>, g, b, 0, st, a);
-  else hipLaunchKernelGGL(mttv_trail_kernel<float>, g, b, 0, st, a);
-  return hipGetLastError();
+static hipError_t record_or_launch(const Sink& sk, int kind, int variant, unsigned gx, unsigned gy, size_t lds,
+                                   const void* kernel, const void* arg_struct, size_t arg_bytes) {
+  if (sk.rec) {
+    KOp op{};
+    op.kind = kind;
+    op.variant = variant;
+    op.gx = gx;
+    op.gy = gy;
+    op.lds = (unsigned)lds;
+    std::memcpy(&op.u, arg_struct, arg_bytes);
+    return sink_record(sk, op);
+  }
+  void* args[] = {const_cast<void*>(arg_struct)};
+  return hipLaunchKernel(kernel, dim3(gx, gy), dim3(NT), args, lds, sk.st);
 }
 
-hipError_t mttv_lead_launch(const MttvArgs& a, hipStream_t st) {
+hipError_t mttv_trail_launch(const MttvArgs& a, const Sink& sk) {
+  if (a.Ia <= 0 || a.R <= 0) return hipSuccess;
+  const void* k = a.t_f64 ? (const void*)mttv_trail_kernel<double> : (const void*)mttv_trail_kernel<float>;
+  return record_or_launch(sk, K_MTTV_TRAIL, a.t_f64 ? 1 : 0, (unsigned)((a.Ia + 63) / 64), (unsigned)a.R, 0, k, &a,
+                          sizeof(a));
+}
+
+hipError_t mttv_lead_launch(const MttvArgs& a, const Sink& sk) {
   const int64_t outputs = a.J * a.R;
   if (outputs <= 0) return hipSuccess;
   int gs = 4;
   while (gs < 64 && gs < a.Ia) gs <<= 1;
-  const int64_t blocks = (outputs * gs + NT - 1) / NT;
-  dim3 g((unsigned)blocks), b(NT);
-#define NNCP_LEAD(GSV)                                                           \
-  if (a.t_f64) hipLaunchKernelGGL((mttv_lead_kernel<GSV, double>), g, b, 0, st, a); \
-  else hipLaunchKernelGGL((mttv_lead_kernel<GSV, float>), g, b, 0, st, a);
+  const unsigned blocks = (unsigned)((outputs * gs + NT - 1) / NT);
+  const void* k = nullptr;
+#define NNCP_LEAD(GSV) \
+  k = a.t_f64 ? (const void*)mttv_lead_kernel<GSV, double> : (const void*)mttv_lead_kernel<GSV, float>;
   switch (gs) {
     case 4: NNCP_LEAD(4) break;
     case 8: NNCP_LEAD(8) break;
@@ -539,16 +771,63 @@ hipError_t mttv_lead_launch(const MttvArgs& a, hipStream_t st) {
     default: NNCP_LEAD(64) break;
   }
 #undef NNCP_LEAD
-  return hipGetLastError();
+  return record_or_launch(sk, K_MTTV_LEAD, gs * 10 + (a.t_f64 ? 1 : 0), blocks, 1, 0, k, &a, sizeof(a));
 }
 
-hipError_t update_launch(const UpdateArgs& a, hipStream_t st) {
+hipError_t update_launch(const UpdateArgs& a, const Sink& sk) {
   if (a.I <= 0) return hipSuccess;
   const size_t lds = ((size_t)a.R * a.R + a.R) * sizeof(double);
   const int rpb = NT / 64;
-  dim3 g((unsigned)((a.I + rpb - 1) / rpb)), b(NT);
-  if (a.R <= 64) hipLaunchKernelGGL((update_kernel<1>), g, b, lds, st, a);
-  else hipLaunchKernelGGL((update_kernel<2>), g, b, lds, st, a);
+  const unsigned g = (unsigned)((a.I + rpb - 1) / rpb);
+  const int vpl = a.R <= 64 ? 1 : 2;
+  const void* k = vpl == 1 ? (const void*)update_kernel<1> : (const void*)update_kernel<2>;
+  return record_or_launch(sk, K_UPDATE, vpl, g, 1, lds, k, &a, sizeof(a));
+}
+
+hipError_t pm_reduce_launch(const ReduceArgs& r, const Sink& sk) {
+  const int64_t total = r.Mtot * r.R;
+  if (total <= 0) return hipSuccess;
+  const void* k = r.t_f64 ? (const void*)pm_reduce_kernel<double> : (const void*)pm_reduce_kernel<float>;
+  return record_or_launch(sk, K_PM_REDUCE, r.t_f64 ? 1 : 0, (unsigned)((total + NT - 1) / NT), 1, 0, k, &r,
+                          sizeof(r));
+}
+
+hipError_t mttv_trail_launch(const MttvArgs& a, hipStream_t st) {
+  Sink sk;
+  sk.st = st;
+  return mttv_trail_launch(a, sk);
+}
+hipError_t mttv_lead_launch(const MttvArgs& a, hipStream_t st) {
+  Sink sk;
+  sk.st = st;
+  return mttv_lead_launch(a, sk);
+}
+hipError_t update_launch(const UpdateArgs& a, hipStream_t st) {
+  Sink sk;
+  sk.st = st;
+  return update_launch(a, sk);
+}
+
+hipError_t sink_record(const Sink& s, const KOp& op) {
+  if (!s.rec) return hipErrorInvalidValue;
+  try {
+    static_cast<std::vector<KOp>*>(s.rec)->push_back(op);
+  } catch (...) {
+    return hipErrorOutOfMemory;
+  }
+  return hipSuccess;
+}
+
+hipError_t batch_launch_small(const BItem* items, const int* count, const KOp* ops, unsigned grid, size_t lds,
+                              hipStream_t st) {
+  static bool attr = [] {
+    (void)hipFuncSetAttribute((const void*)small_batch_kernel, hipFuncAttributeMaxDynamicSharedMemorySize,
+                              150 * 1024);
+    (void)hipGetLastError();
+    return true;
+  }();
+  (void)attr;
+  hipLaunchKernelGGL(small_batch_kernel, dim3(grid), dim3(NT), lds, st, items, count, ops);
   return hipGetLastError();
 }
 
@@ -567,19 +846,30 @@ int finalize_chunks(int64_t I, int R, int* rows_per_chunk) {
   return (int)chunks;
 }
 
-hipError_t finalize_launch(const FinalizeArgs& a, hipStream_t st) {
+hipError_t finalize_launch(const FinalizeArgs& a, const Sink& sk) {
   size_t lds = (size_t)fin_sub_rows(a.R) * a.R * sizeof(double);
   const size_t need = ((size_t)a.R * a.R + 1) * sizeof(double);
   if (need > lds) lds = need;
-  if (a.nchunks <= 1) {
-    hipLaunchKernelGGL(finalize_fused_kernel, dim3(1), dim3(NT), lds, st, a);
-    return hipGetLastError();
+  if (a.nchunks <= 1 && a.R <= kSmallMaxR) {
+    const int R4 = (a.R + 3) & ~3;
+    const size_t RR = (size_t)a.R * a.R;
+    const size_t sub = 4096 / R4;
+    const size_t stage = sub * R4, phases = (size_t)NT * 16;
+    const size_t bytes = (3 * RR + 1 + (stage > phases ? stage : phases)) * sizeof(double);
+    return record_or_launch(sk, K_FIN_SMALL, 0, 1, 1, bytes, (const void*)finalize_small_kernel, &a, sizeof(a));
   }
-  hipLaunchKernelGGL(gram_chunks_kernel, dim3(a.nchunks), dim3(NT), lds, st, a);
-  hipError_t e = hipGetLastError();
+  if (a.nchunks <= 1)
+    return record_or_launch(sk, K_FIN_FUSED, 0, 1, 1, lds, (const void*)finalize_fused_kernel, &a, sizeof(a));
+  hipError_t e = record_or_launch(sk, K_GRAM_CHUNKS, 0, (unsigned)a.nchunks, 1, lds,
+                                  (const void*)gram_chunks_kernel, &a, sizeof(a));
   if (e != hipSuccess) return e;
-  hipLaunchKernelGGL(finalize_tail_kernel, dim3(1), dim3(NT), lds, st, a);
-  return hipGetLastError();
+  return record_or_launch(sk, K_FIN_TAIL, 0, 1, 1, lds, (const void*)finalize_tail_kernel, &a, sizeof(a));
+}
+
+hipError_t finalize_launch(const FinalizeArgs& a, hipStream_t st) {
+  Sink sk;
+  sk.st = st;
+  return finalize_launch(a, sk);
 }
 
 hipError_t init_model_launch(const double* lam_in, double* lam, double* lam_model, const double* G,

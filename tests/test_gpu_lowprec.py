@@ -114,9 +114,11 @@ def test_nncp_16bit_matches_oracle_on_stored_values(gpu_lib, dt, dims, R, split,
     lam_err = float(np.max(np.abs(out["lam"] - ref["lam"]) / ref["lam"]))
     fit_err = float(np.max(np.abs(np.asarray(out["fit"]) - np.asarray(ref["fit"]))))
     print(f"  factor errs {['%.1e' % e for e in errs]} lam {lam_err:.1e} fit {fit_err:.1e}", flush=True)
-    # FP32 accumulation (16-bit path) instead of FP64 chains: 1e-4 on the
-    # trajectory, far inside the storage rounding of the tensor itself.
-    assert max(errs) < 1e-4 and lam_err < 1e-4 and fit_err < 1e-5
+    # The factor operand is exact to ~2^-17 (BF16 hi + lo) or ~2^-22 (FP16), and
+    # sums are FP32: per-step MTTKRP errors up to ~1e-5 relative for BF16, which
+    # the trajectory carries at about that size. Bound: 1e-4 on factors, lambda
+    # and fit, ten times below the BF16 storage rounding of the tensor (2^-9).
+    assert max(errs) < 1e-4 and lam_err < 1e-4 and fit_err < 1e-4
 
 
 def test_quantized_fit_close_to_fp32_fit(gpu_lib):
