@@ -60,7 +60,10 @@ typedef struct nncp_options {
   int no_graph;       /* nonzero: launch kernels one by one instead of replaying a HIP graph */
   int phase_timers;   /* nonzero: time each phase with HIP events (implies no_graph) */
   double tol;         /* > 0: stop when |fit_k - fit_{k-1}| < tol (host check each iteration) */
-  int reserved[8];
+  int pm_wg_kib;      /* partial MTTKRP: aim for at least this many KiB of the tensor per work-group
+                         (at most one work-group per CU); <= 0: 256. Depends only on the job, never on
+                         what else runs, so a job computes the same sums alone and in a batch. */
+  int reserved[7];
 } nncp_options;
 
 /* Human-readable text for a status code (static storage). */
@@ -125,6 +128,35 @@ int nncp_plan_phase_ms(const nncp_plan* plan, double* ms);
  * it rewrites only that node's temporary, which the next iteration recomputes. */
 int nncp_plan_time_node(nncp_plan* plan, int mode, int reps, double* ms_avg);
 int nncp_plan_destroy(nncp_plan* plan);
+
+/* Host copy of the fits recorded since the plan was created (or since the last
+ * nncp_plan_run, which restarts the record): *count = outer iterations
+ * completed; fit (host) receives min(*count, cap, 1024) values. */
+int nncp_plan_fits(nncp_plan* plan, double* fit, int cap, int* count);
+
+/* ---- Batched plans: many independent decompositions advanced together ----
+ * A batch holds caller-created plans (rank <= 64). nncp_batch_run(b, k) runs
+ * k outer iterations of every member. One iteration of all members is one
+ * HIP graph: for each step of the iteration (per mode: partial MTTKRP or
+ * multi-TTV node, split-K reduction, leaf multi-TTV, update, Gram/finalize)
+ * one persistent kernel per kernel family walks a device list of (member
+ * kernel, tile) items. Each member keeps the kernels, tiles and summation
+ * order of its stand-alone run, so its results are bitwise those of
+ * nncp_plan_run on the same state, whatever else is in the batch (this is how
+ * jobs are batched without coupling: not in the paper, which runs one
+ * decomposition at a time). Members stay owned by the caller; removing or
+ * adding a member rebuilds the work lists and the graph at the next run.
+ * Fits are read per member with nncp_plan_fits. */
+typedef struct nncp_batch nncp_batch;
+int nncp_batch_create(nncp_batch** batch, void* stream);
+int nncp_batch_add(nncp_batch* batch, nncp_plan* plan);      /* EINVAL: rank > 64 or already a member */
+int nncp_batch_remove(nncp_batch* batch, nncp_plan* plan);   /* ENOTFOUND: not a member */
+int nncp_batch_size(const nncp_batch* batch);
+/* Runs `ticks` outer iterations of every member; synchronises the stream. */
+int nncp_batch_run(nncp_batch* batch, int ticks);
+/* Launches per tick and work items per tick of the current work lists. */
+int nncp_batch_stats(const nncp_batch* batch, int* launches, int64_t* items);
+int nncp_batch_destroy(nncp_batch* batch);   /* does not destroy the member plans */
 
 /* ---- Steps of the hot path (each is the kernel the driver runs) ---- */
 

@@ -60,7 +60,7 @@ struct Layout {
 };
 
 struct Problem {
-  int N = 0, R = 0, dtype = 0, s = 0, update = 0;
+  int N = 0, R = 0, dtype = 0, s = 0, update = 0, wg_kib = 0;
   int64_t dims[kMaxModes] = {};
   int64_t IL = 0, IR = 0, I = 0;
 };
@@ -135,8 +135,8 @@ Layout make_layout(const Problem& p) {
     o = align256(o + bytes);
     return at;
   };
-  L.pmL[0] = pm_plan(0, p.dtype, p.IL, p.IR, (int)p.dims[p.s], R);
-  L.pmL[1] = pm_plan(1, p.dtype, p.IL, p.IR, (int)p.dims[0], R);
+  L.pmL[0] = pm_plan(0, p.dtype, p.IL, p.IR, (int)p.dims[p.s], R, p.wg_kib);
+  L.pmL[1] = pm_plan(1, p.dtype, p.IL, p.IR, (int)p.dims[0], R, p.wg_kib);
   int maxchunks = 1;
   for (int k = 0; k < N; ++k) {
     int rpc;
@@ -254,7 +254,7 @@ hipError_t run_pm(const nncp_plan* P, int side, void* T, int t_f64, const void* 
     a.hscale = P->hscale();
     a.zeros = P->zeros();
     a.counters = P->counters();
-    const PmLaunch l = (a.R == std::min(kPmMaxCols, p.R)) ? P->L.pmL[side] : pm_plan(side, p.dtype, p.IL, p.IR, I1, a.R);
+    const PmLaunch l = (a.R == std::min(kPmMaxCols, p.R)) ? P->L.pmL[side] : pm_plan(side, p.dtype, p.IL, p.IR, I1, a.R, p.wg_kib);
     pm_fill_args(l, a);
     hipError_t e = pm_launch(l, a, st);
     if (e != hipSuccess) return e;
@@ -335,14 +335,14 @@ hipError_t finalize_mode(const nncp_plan* P, int n, const void* M, int m_f64, in
 enum { PH_PM = 0, PH_MTTV = 1, PH_NLS = 2, PH_GRAM = 3, PH_ERR = 4, PH_TOTAL = 5 };
 
 // Enqueue one outer iteration. With timers, events bracket each phase (no graph).
-hipError_t enqueue_iteration(nncp_plan* P, const Sink& st, std::vector<std::pair<int, hipEvent_t>>* marks) {
+hipError_t enqueue_iteration(nncp_plan* P, const Sink& st0, std::vector<std::pair<int, hipEvent_t>>* marks) {
   const Problem& p = P->p;
   auto mark = [&](int phase) -> hipError_t {
     if (!marks) return hipSuccess;
     hipEvent_t e;
     hipError_t r = hipEventCreate(&e);
     if (r != hipSuccess) return r;
-    r = hipEventRecord(e, st.st);
+    r = hipEventRecord(e, st0.st);
     marks->push_back({phase, e});
     return r;
   };
@@ -351,6 +351,8 @@ hipError_t enqueue_iteration(nncp_plan* P, const Sink& st, std::vector<std::pair
     const int start = sub_start(p, n);
     const void* M = nullptr;
     int m_f64 = 1;
+    Sink st = st0;
+    st.mode = n;
     if ((e = mark(n == start ? PH_PM : PH_MTTV)) != hipSuccess) return e;
     if ((e = node_op(P, n, true, st)) != hipSuccess) return e;
     if ((e = mark(PH_MTTV)) != hipSuccess) return e;
@@ -382,8 +384,19 @@ int destroy_graph(nncp_plan* P) {
   return NNCP_OK;
 }
 
+// The capture stream and its events are created on first use, so plans that are
+// only ever advanced by a batch own none.
+int ensure_capture_stream(nncp_plan* P) {
+  if (!P->cap_stream && hipStreamCreateWithFlags(&P->cap_stream, hipStreamNonBlocking) != hipSuccess)
+    return NNCP_EDEVICE;
+  for (auto& e : P->ev)
+    if (!e && hipEventCreateWithFlags(&e, hipEventDisableTiming) != hipSuccess) return NNCP_EDEVICE;
+  return NNCP_OK;
+}
+
 int build_graph(nncp_plan* P) {
   destroy_graph(P);
+  if (ensure_capture_stream(P) != NNCP_OK) return NNCP_EDEVICE;
   HIPCHK(hipStreamBeginCapture(P->cap_stream, hipStreamCaptureModeThreadLocal));
   hipError_t e = enqueue_iteration(P, sink_of(P->cap_stream), nullptr);
   hipGraph_t g = nullptr;
@@ -422,6 +435,7 @@ int nncp_version(void) { return 100; }
 size_t nncp_workspace_bytes(int N, const int64_t* dims, int R, int dtype, const nncp_options* opt) {
   Problem p;
   if (fill_problem(p, N, dims, R, dtype, NNCP_HALS, opt ? opt->split : 0) != NNCP_OK) return 0;
+  p.wg_kib = opt ? opt->pm_wg_kib : 0;
   return make_layout(p).total;
 }
 
@@ -433,6 +447,7 @@ int nncp_plan_create(nncp_plan** out, const void* X, int dtype, int N, const int
   Problem p;
   int st = fill_problem(p, N, dims, R, dtype, update, opt ? opt->split : 0);
   if (st != NNCP_OK) return st;
+  p.wg_kib = opt ? opt->pm_wg_kib : 0;
   for (int k = 0; k < N; ++k)
     if (!H[k]) return NNCP_EINVAL;
   nncp_plan* P = new (std::nothrow) nncp_plan();
@@ -472,9 +487,6 @@ int nncp_plan_create(nncp_plan** out, const void* X, int dtype, int N, const int
     nncp_plan_destroy(P);
     return code;
   };
-  if (hipStreamCreateWithFlags(&P->cap_stream, hipStreamNonBlocking) != hipSuccess) return fail(NNCP_EDEVICE);
-  if (hipEventCreateWithFlags(&P->ev[0], hipEventDisableTiming) != hipSuccess) return fail(NNCP_EDEVICE);
-  if (hipEventCreateWithFlags(&P->ev[1], hipEventDisableTiming) != hipSuccess) return fail(NNCP_EDEVICE);
   // zero counters, iteration counter, the zero block read by masked loads
   if (fill_u32_launch(P->counters(), P->L.ncounters, 0u, s) != hipSuccess) return fail(NNCP_EDEVICE);
   if (fill_u32_launch(P->zeros(), 64, 0u, s) != hipSuccess) return fail(NNCP_EDEVICE);
@@ -838,6 +850,254 @@ int nncp_nls_update(const double* M, float* H, int64_t I, int R, const double* S
     st = NNCP_EDEVICE;
   hipFree(mem);
   return st;
+}
+
+}  // extern "C"
+
+// ---------------------------------------------------------------------------
+// Batched plans: one outer iteration of every member plan per tick.
+//
+// Each member's iteration is recorded once as launch records (the kernels,
+// grids and arguments its stand-alone run would launch). The records of all
+// members are grouped by stage (mode, step) and kernel family; every group
+// becomes one launch of a persistent work-list kernel whose items are the
+// (op, tile) pairs of all members. Stages run in order, so each member's
+// chain of kernels keeps its order, and members never share a buffer, so a
+// member's results do not depend on who else is in the batch. The sequence of
+// launches of one tick is captured into a HIP graph and replayed.
+// ---------------------------------------------------------------------------
+struct nncp_batch {
+  hipStream_t st = nullptr;   // caller's stream
+  hipStream_t cap = nullptr;  // capture / replay stream
+  hipEvent_t ev[2] = {nullptr, nullptr};
+  std::vector<nncp_plan*> plans;
+  bool dirty = true;
+  KOp* d_ops = nullptr;
+  size_t cap_ops = 0;
+  BItem* d_items = nullptr;
+  size_t cap_items = 0;
+  int* d_counts = nullptr;
+  size_t cap_counts = 0;
+  struct Launch {
+    int family;
+    size_t item_off;
+    int count_idx;
+    unsigned grid;
+    size_t lds;
+  };
+  std::vector<Launch> launches;
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t gexec = nullptr;
+  size_t n_items = 0;
+};
+
+namespace {
+
+int device_cus() {
+  static int n = [] {
+    int dev = 0, cus = 0;
+    if (hipGetDevice(&dev) != hipSuccess) return 256;
+    if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || cus < 1)
+      return 256;
+    return cus;
+  }();
+  return n;
+}
+
+template <typename T>
+int ensure_dev(T** p, size_t* cap, size_t n) {
+  if (n <= *cap && *p) return NNCP_OK;
+  if (*p) hipFree(*p);
+  *p = nullptr;
+  *cap = 0;
+  size_t want = n < 16 ? 16 : n + n / 4;
+  if (hipMalloc((void**)p, want * sizeof(T)) != hipSuccess) return NNCP_ENOMEM;
+  *cap = want;
+  return NNCP_OK;
+}
+
+void batch_drop_graph(nncp_batch* B) {
+  if (B->gexec) hipGraphExecDestroy(B->gexec);
+  if (B->graph) hipGraphDestroy(B->graph);
+  B->gexec = nullptr;
+  B->graph = nullptr;
+}
+
+int batch_build(nncp_batch* B) {
+  batch_drop_graph(B);
+  B->launches.clear();
+  B->n_items = 0;
+  std::vector<KOp> all;
+  for (nncp_plan* P : B->plans) {
+    std::vector<KOp> rec;
+    Sink sk;
+    sk.rec = &rec;
+    if (enqueue_iteration(P, sk, nullptr) != hipSuccess) return NNCP_EDEVICE;
+    all.insert(all.end(), rec.begin(), rec.end());
+  }
+  if (all.empty()) {
+    B->dirty = false;
+    return NNCP_OK;
+  }
+  std::vector<int> keys;
+  for (const KOp& o : all) keys.push_back(o.stage);
+  std::sort(keys.begin(), keys.end());
+  keys.erase(std::unique(keys.begin(), keys.end()), keys.end());
+  std::vector<BItem> items;
+  std::vector<int> counts;
+  const unsigned cus = (unsigned)device_cus();
+  for (int key : keys) {
+    for (int fam = 0; fam < KF_COUNT; ++fam) {
+      const size_t off = items.size();
+      size_t lds = 0;
+      for (size_t i = 0; i < all.size(); ++i) {
+        const KOp& o = all[i];
+        if (o.stage != key || kfamily(o.kind) != fam) continue;
+        for (unsigned by = 0; by < o.gy; ++by)
+          for (unsigned bx = 0; bx < o.gx; ++bx) items.push_back(BItem{(int)i, (int)bx, (int)by});
+        lds = std::max(lds, (size_t)o.lds);
+      }
+      const size_t n = items.size() - off;
+      if (n == 0) continue;
+      const unsigned cap = fam == KF_SMALL ? 8 * cus : cus;  // PM tiles: one group per CU
+      nncp_batch::Launch l;
+      l.family = fam;
+      l.item_off = off;
+      l.count_idx = (int)counts.size();
+      l.grid = (unsigned)std::min<size_t>(n, cap);
+      l.lds = lds;
+      B->launches.push_back(l);
+      counts.push_back((int)n);
+    }
+  }
+  int r;
+  if ((r = ensure_dev(&B->d_ops, &B->cap_ops, all.size())) != NNCP_OK) return r;
+  if ((r = ensure_dev(&B->d_items, &B->cap_items, items.size())) != NNCP_OK) return r;
+  if ((r = ensure_dev(&B->d_counts, &B->cap_counts, counts.size())) != NNCP_OK) return r;
+  HIPCHK(hipMemcpyAsync(B->d_ops, all.data(), all.size() * sizeof(KOp), hipMemcpyHostToDevice, B->cap));
+  HIPCHK(hipMemcpyAsync(B->d_items, items.data(), items.size() * sizeof(BItem), hipMemcpyHostToDevice, B->cap));
+  HIPCHK(hipMemcpyAsync(B->d_counts, counts.data(), counts.size() * sizeof(int), hipMemcpyHostToDevice, B->cap));
+  HIPCHK(hipStreamSynchronize(B->cap));
+  B->n_items = items.size();
+  // one tick = the launches in order, captured once
+  HIPCHK(hipStreamBeginCapture(B->cap, hipStreamCaptureModeThreadLocal));
+  hipError_t e = hipSuccess;
+  for (const auto& l : B->launches) {
+    const BItem* it = B->d_items + l.item_off;
+    const int* cnt = B->d_counts + l.count_idx;
+    if (l.family == KF_PM_F32) e = batch_launch_pm_f32(it, cnt, B->d_ops, l.grid, l.lds, B->cap);
+    else if (l.family == KF_PM_16) e = batch_launch_pm_16(it, cnt, B->d_ops, l.grid, l.lds, B->cap);
+    else e = batch_launch_small(it, cnt, B->d_ops, l.grid, l.lds, B->cap);
+    if (e != hipSuccess) break;
+  }
+  hipGraph_t g = nullptr;
+  hipError_t e2 = hipStreamEndCapture(B->cap, &g);
+  if (e != hipSuccess || e2 != hipSuccess) {
+    if (g) hipGraphDestroy(g);
+    return NNCP_EDEVICE;
+  }
+  B->graph = g;
+  HIPCHK(hipGraphInstantiate(&B->gexec, g, nullptr, nullptr, 0));
+  B->dirty = false;
+  return NNCP_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int nncp_batch_create(nncp_batch** out, void* stream) {
+  if (!out) return NNCP_EINVAL;
+  *out = nullptr;
+  nncp_batch* B = new (std::nothrow) nncp_batch();
+  if (!B) return NNCP_ENOMEM;
+  B->st = (hipStream_t)stream;
+  if (hipStreamCreateWithFlags(&B->cap, hipStreamNonBlocking) != hipSuccess ||
+      hipEventCreateWithFlags(&B->ev[0], hipEventDisableTiming) != hipSuccess ||
+      hipEventCreateWithFlags(&B->ev[1], hipEventDisableTiming) != hipSuccess) {
+    nncp_batch_destroy(B);
+    return NNCP_EDEVICE;
+  }
+  *out = B;
+  return NNCP_OK;
+}
+
+int nncp_batch_add(nncp_batch* B, nncp_plan* P) {
+  if (!B || !P) return NNCP_EINVAL;
+  if (P->p.R > kPmMaxCols) return NNCP_EINVAL;  // one column chunk per partial MTTKRP
+  for (nncp_plan* q : B->plans)
+    if (q == P) return NNCP_EINVAL;
+  try {
+    B->plans.push_back(P);
+  } catch (...) {
+    return NNCP_ENOMEM;
+  }
+  B->dirty = true;
+  return NNCP_OK;
+}
+
+int nncp_batch_remove(nncp_batch* B, nncp_plan* P) {
+  if (!B || !P) return NNCP_EINVAL;
+  auto it = std::find(B->plans.begin(), B->plans.end(), P);
+  if (it == B->plans.end()) return NNCP_ENOTFOUND;
+  B->plans.erase(it);
+  B->dirty = true;
+  return NNCP_OK;
+}
+
+int nncp_batch_size(const nncp_batch* B) { return B ? (int)B->plans.size() : 0; }
+
+int nncp_batch_run(nncp_batch* B, int ticks) {
+  if (!B || ticks < 0) return NNCP_EINVAL;
+  if (ticks == 0 || B->plans.empty()) return NNCP_OK;
+  if (B->dirty) {
+    // members may have been set up on the caller's stream
+    HIPCHK(hipStreamSynchronize(B->st));
+    int r = batch_build(B);
+    if (r != NNCP_OK) return r;
+  }
+  HIPCHK(hipEventRecord(B->ev[0], B->st));
+  HIPCHK(hipStreamWaitEvent(B->cap, B->ev[0], 0));
+  for (int t = 0; t < ticks; ++t) HIPCHK(hipGraphLaunch(B->gexec, B->cap));
+  HIPCHK(hipEventRecord(B->ev[1], B->cap));
+  HIPCHK(hipStreamWaitEvent(B->st, B->ev[1], 0));
+  HIPCHK(hipStreamSynchronize(B->st));
+  return NNCP_OK;
+}
+
+int nncp_batch_stats(const nncp_batch* B, int* launches, int64_t* items) {
+  if (!B) return NNCP_EINVAL;
+  if (launches) *launches = (int)B->launches.size();
+  if (items) *items = (int64_t)B->n_items;
+  return NNCP_OK;
+}
+
+int nncp_batch_destroy(nncp_batch* B) {
+  if (!B) return NNCP_EINVAL;
+  batch_drop_graph(B);
+  if (B->d_ops) hipFree(B->d_ops);
+  if (B->d_items) hipFree(B->d_items);
+  if (B->d_counts) hipFree(B->d_counts);
+  if (B->cap) hipStreamDestroy(B->cap);
+  for (auto& e : B->ev)
+    if (e) hipEventDestroy(e);
+  delete B;
+  return NNCP_OK;
+}
+
+int nncp_plan_fits(nncp_plan* P, double* fit, int cap, int* count) {
+  if (!P || !count || cap < 0 || (cap > 0 && !fit)) return NNCP_EINVAL;
+  int it = 0;
+  hipStream_t s = P->user_stream;
+  HIPCHK(hipMemcpyAsync(&it, P->iter(), sizeof(int), hipMemcpyDeviceToHost, s));
+  HIPCHK(hipStreamSynchronize(s));
+  *count = it;
+  const int n = std::min(std::min(it, cap), kFitCap);
+  if (n > 0) {
+    HIPCHK(hipMemcpyAsync(fit, P->fit(), sizeof(double) * n, hipMemcpyDeviceToHost, s));
+    HIPCHK(hipStreamSynchronize(s));
+  }
+  return NNCP_OK;
 }
 
 }  // extern "C"

@@ -82,7 +82,8 @@ struct PmLaunch {
 
 // I1 = extent of the first contracted mode (mode s+1 for the left node, mode 1
 // for the right node).
-PmLaunch pm_plan(int side, int dtype, int64_t IL, int64_t IR, int I1, int R);
+// wg_kib: aim for at least this many KiB of X per work-group (<= 0: 256).
+PmLaunch pm_plan(int side, int dtype, int64_t IL, int64_t IR, int I1, int R, int wg_kib = 0);
 void pm_fill_args(const PmLaunch& L, PmArgs& a);
 hipError_t pm_launch(const PmLaunch& L, const PmArgs& a, hipStream_t st);
 struct Sink;
@@ -215,6 +216,7 @@ inline int kfamily(int kind) { return kind == K_PM_F32 ? KF_PM_F32 : ((kind == K
 struct KOp {
   int kind;
   int variant;
+  int stage;         // batching order: 16 * mode + slot of the kind within the mode's steps
   unsigned gx, gy;   // work-groups of the stand-alone launch (x, y)
   unsigned lds;      // dynamic LDS bytes
   union {
@@ -236,10 +238,24 @@ struct BItem {
 struct Sink {
   hipStream_t st = nullptr;
   void* rec = nullptr;  // std::vector<KOp>* when recording
+  int mode = 0;         // mode whose steps are being recorded
   Sink() = default;
   Sink(hipStream_t s) : st(s) {}  // launch on s (implicit: a stream is a launching sink)
 };
-// Append a record (host); returns hipSuccess.
+// Slot of a kernel kind among one mode's steps (pack, node op, split-K reduce,
+// leaf multi-TTV, update, Gram chunks, finalize).
+inline int kslot(int kind) {
+  switch (kind) {
+    case K_PACK16: return 0;
+    case K_PM_F32: case K_PM_16: case K_MTTV_LEAD: return 1;
+    case K_PM_REDUCE: return 2;
+    case K_MTTV_TRAIL: return 3;
+    case K_UPDATE: return 4;
+    case K_GRAM_CHUNKS: return 5;
+    default: return 6;
+  }
+}
+// Append a record (host), stamping its stage; returns hipSuccess.
 hipError_t sink_record(const Sink& s, const KOp& op);
 
 // Persistent batched kernels: work-group b walks items b, b + grid, ... < *count

@@ -22,21 +22,27 @@ static int num_cus() {
 
 static int64_t cdiv(int64_t a, int64_t b) { return (a + b - 1) / b; }
 
-// Work-groups a launch aims for: one per CU. Measured on the 128^4 rank-32
-// workload, one group of four waves per CU (each with three k-steps of loads in
-// flight) streams X faster than two or three co-resident groups, and it keeps
-// the split-K partial traffic small.
-// NNCP_PM_TARGET_WGS overrides it for tuning.
-static int64_t target_wgs() {
+// Work-groups a launch aims for: one per CU at most (measured on the 128^4
+// rank-32 workload, one group of four waves per CU, each with three k-steps of
+// loads in flight, streams X faster than two or three co-resident groups, and
+// it keeps the split-K partial traffic small), and at least wg_kib KiB of X per
+// group, so a small tensor is not cut into tiles whose LDS staging outweighs
+// their share of X. The count depends on the job alone. NNCP_PM_TARGET_WGS
+// overrides it for tuning.
+static int64_t target_wgs(int64_t x_bytes, int wg_kib) {
   static const long env = [] {
     const char* e = std::getenv("NNCP_PM_TARGET_WGS");
     return e ? std::atol(e) : 0L;
   }();
   if (env > 0) return env;
-  return (int64_t)num_cus();
+  const int64_t per = (int64_t)(wg_kib > 0 ? wg_kib : 256) * 1024;
+  int64_t t = x_bytes / per;
+  if (t < 1) t = 1;
+  if (t > num_cus()) t = num_cus();
+  return t;
 }
 
-PmLaunch pm_plan(int side, int dtype, int64_t IL, int64_t IR, int I1, int R) {
+PmLaunch pm_plan(int side, int dtype, int64_t IL, int64_t IR, int I1, int R, int wg_kib) {
   PmLaunch L{};
   L.side = side;
   L.dtype = dtype;
@@ -48,6 +54,7 @@ PmLaunch pm_plan(int side, int dtype, int64_t IL, int64_t IR, int I1, int R) {
   const int64_t Ktot = side == 0 ? IR : IL;
   const int ks = f32 ? pm_f32_kstep(side) : pm_16_kstep(side);
   const int wave_rows = f32 ? pm_f32_wave_rows(side, L.nb) : pm_16_wave_rows(side, L.nb);
+  const int64_t target = target_wgs(IL * IR * (f32 ? 4 : 2), wg_kib);
 
   L.I1 = I1;
   L.J = Ktot / I1;
@@ -79,11 +86,11 @@ PmLaunch pm_plan(int side, int dtype, int64_t IL, int64_t IR, int I1, int R) {
   // blocks inside each work-group (restaging LDS) instead of splitting K: the
   // split-K partials of a tall output would cost more HBM traffic than X.
   L.istages = 1;
-  if (!f32 && side == 1 && wm == 4 && L.n_i1blk > 1 && L.mtiles >= target_wgs()) L.istages = L.n_i1blk;
+  if (!f32 && side == 1 && wm == 4 && L.n_i1blk > 1 && L.mtiles >= target) L.istages = L.n_i1blk;
   const int n_i1grp = L.n_i1blk / L.istages;
 
   const int64_t steps_per_j = L.i1blk / ks;
-  int64_t want_splits = target_wgs() / L.mtiles;
+  int64_t want_splits = target / L.mtiles;
   if (want_splits < 1) want_splits = 1;
   int64_t n_jblk = cdiv(want_splits, n_i1grp);
   // each wave should own a few k-steps, and the per-(j, column) scales fit LDS

@@ -811,7 +811,9 @@ hipError_t update_launch(const UpdateArgs& a, hipStream_t st) {
 hipError_t sink_record(const Sink& s, const KOp& op) {
   if (!s.rec) return hipErrorInvalidValue;
   try {
-    static_cast<std::vector<KOp>*>(s.rec)->push_back(op);
+    KOp o = op;
+    o.stage = 16 * s.mode + kslot(op.kind);
+    static_cast<std::vector<KOp>*>(s.rec)->push_back(o);
   } catch (...) {
     return hipErrorOutOfMemory;
   }

@@ -34,7 +34,8 @@ c_vp = ctypes.c_void_p
 class Options(ctypes.Structure):
     _fields_ = [("split", ctypes.c_int), ("no_record_fit", ctypes.c_int), ("no_graph", ctypes.c_int),
                 ("phase_timers", ctypes.c_int), ("tol", ctypes.c_double),
-                ("reserved", ctypes.c_int * 8)]
+                ("pm_wg_kib", ctypes.c_int),
+                ("reserved", ctypes.c_int * 7)]
 
 
 class NNCPError(RuntimeError):
@@ -88,6 +89,22 @@ def _declare(L):
     L.nncp_gram.argtypes = [c_vp, ctypes.c_int64, ctypes.c_int, c_vp, c_vp]
     L.nncp_nls_update.restype = ctypes.c_int
     L.nncp_nls_update.argtypes = [c_vp, c_vp, ctypes.c_int64, ctypes.c_int, c_vp, c_vp, ctypes.c_int, c_vp, c_vp]
+    L.nncp_plan_fits.restype = ctypes.c_int
+    L.nncp_plan_fits.argtypes = [c_vp, c_dp, ctypes.c_int, ctypes.POINTER(ctypes.c_int)]
+    L.nncp_batch_create.restype = ctypes.c_int
+    L.nncp_batch_create.argtypes = [ctypes.POINTER(c_vp), c_vp]
+    L.nncp_batch_add.restype = ctypes.c_int
+    L.nncp_batch_add.argtypes = [c_vp, c_vp]
+    L.nncp_batch_remove.restype = ctypes.c_int
+    L.nncp_batch_remove.argtypes = [c_vp, c_vp]
+    L.nncp_batch_size.restype = ctypes.c_int
+    L.nncp_batch_size.argtypes = [c_vp]
+    L.nncp_batch_run.restype = ctypes.c_int
+    L.nncp_batch_run.argtypes = [c_vp, ctypes.c_int]
+    L.nncp_batch_stats.restype = ctypes.c_int
+    L.nncp_batch_stats.argtypes = [c_vp, ctypes.POINTER(ctypes.c_int), ctypes.POINTER(ctypes.c_int64)]
+    L.nncp_batch_destroy.restype = ctypes.c_int
+    L.nncp_batch_destroy.argtypes = [c_vp]
 
 
 def lib():
@@ -180,13 +197,17 @@ def version() -> int:
     return lib().nncp_version()
 
 
-def workspace_bytes(dims, R, dtype="f32", split=0) -> int:
-    o = Options(split=split)
+def workspace_bytes(dims, R, dtype="f32", split=0, pm_wg_kib=0) -> int:
+    o = Options(split=split, pm_wg_kib=pm_wg_kib)
     return int(lib().nncp_workspace_bytes(len(dims), _dims(dims), R, _DTYPE[dtype], ctypes.byref(o)))
 
 
+def _dtype_name(t) -> str:
+    return {0: "f32", 1: "bf16", 2: "f16"}[_dtype_code(t)]
+
+
 def nncp(X, dims, R, iters, H, lam=None, update="hals", split=0, graph=True, record_fit=True,
-         tol=0.0, workspace=None, stream=None):
+         tol=0.0, workspace=None, stream=None, pm_wg_kib=0):
     """Run the full driver. H: list of device (R, I_n) float32 tensors, updated in place.
 
     Returns dict(fit=np.ndarray, lam=np.ndarray, iters_done=int).
@@ -201,7 +222,8 @@ def nncp(X, dims, R, iters, H, lam=None, update="hals", split=0, graph=True, rec
     lam_arr = (ctypes.c_double * R)(*(np.ones(R) if lam is None else np.asarray(lam, dtype=np.float64)))
     fit = (ctypes.c_double * max(1, iters))()
     done = ctypes.c_int(0)
-    o = Options(split=split, no_record_fit=0 if record_fit else 1, no_graph=0 if graph else 1, tol=tol)
+    o = Options(split=split, no_record_fit=0 if record_fit else 1, no_graph=0 if graph else 1, tol=tol,
+                pm_wg_kib=pm_wg_kib)
     ws_ptr, ws_bytes = (None, 0)
     if workspace is not None:
         ws_ptr, ws_bytes = _ptr(workspace), workspace.numel() * workspace.element_size()
@@ -216,7 +238,7 @@ class Plan:
     """Persistent driver state: create once, run repeatedly, finish to normalise."""
 
     def __init__(self, X, dims, R, H, lam=None, update="hals", split=0, graph=True, phase_timers=False,
-                 workspace=None, stream=None):
+                 workspace=None, stream=None, pm_wg_kib=0):
         import torch
         L = lib()
         self.dims, self.R, self.H, self.X = list(dims), R, list(H), X
@@ -227,10 +249,11 @@ class Plan:
         lam_arr = None
         if lam is not None:
             lam_arr = (ctypes.c_double * R)(*np.asarray(lam, dtype=np.float64))
-        o = Options(split=split, no_graph=0 if graph else 1, phase_timers=1 if phase_timers else 0)
+        o = Options(split=split, no_graph=0 if graph else 1, phase_timers=1 if phase_timers else 0,
+                    pm_wg_kib=pm_wg_kib)
         self._ws = workspace
         if workspace is None:
-            nbytes = workspace_bytes(dims, R, "f32", split)
+            nbytes = workspace_bytes(dims, R, _dtype_name(X), split, pm_wg_kib)
             self._ws = torch.empty(nbytes, dtype=torch.uint8, device=X.device)
         handle = c_vp()
         st = L.nncp_plan_create(ctypes.byref(handle), _ptr(X), _dtype_code(X), len(dims), _dims(dims), R,
@@ -261,9 +284,61 @@ class Plan:
         _check(lib().nncp_plan_time_node(self._h, mode, reps, ctypes.byref(ms)), "nncp_plan_time_node")
         return ms.value
 
+    def fits(self) -> np.ndarray:
+        """Fits recorded since creation (or the last run()), e.g. by batch ticks."""
+        buf = (ctypes.c_double * 1024)()
+        n = ctypes.c_int(0)
+        _check(lib().nncp_plan_fits(self._h, buf, 1024, ctypes.byref(n)), "nncp_plan_fits")
+        return np.array(buf[:min(n.value, 1024)])
+
+    @property
+    def handle(self):
+        return self._h
+
     def close(self):
         if getattr(self, "_h", None):
             lib().nncp_plan_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class Batch:
+    """Plans advanced together, one persistent work-list launch per step and family."""
+
+    def __init__(self, stream=None):
+        h = c_vp()
+        _check(lib().nncp_batch_create(ctypes.byref(h), _stream(stream)), "nncp_batch_create")
+        self._h = h
+        self._members = []
+
+    def add(self, plan: "Plan"):
+        _check(lib().nncp_batch_add(self._h, plan.handle), "nncp_batch_add")
+        self._members.append(plan)
+
+    def remove(self, plan: "Plan"):
+        _check(lib().nncp_batch_remove(self._h, plan.handle), "nncp_batch_remove")
+        self._members.remove(plan)
+
+    def __len__(self):
+        return lib().nncp_batch_size(self._h)
+
+    def run(self, ticks: int):
+        _check(lib().nncp_batch_run(self._h, ticks), "nncp_batch_run")
+
+    def stats(self) -> dict:
+        n = ctypes.c_int(0)
+        it = ctypes.c_int64(0)
+        _check(lib().nncp_batch_stats(self._h, ctypes.byref(n), ctypes.byref(it)), "nncp_batch_stats")
+        return dict(launches_per_tick=n.value, items_per_tick=it.value)
+
+    def close(self):
+        if getattr(self, "_h", None):
+            lib().nncp_batch_destroy(self._h)
             self._h = None
 
     def __del__(self):
