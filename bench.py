@@ -167,6 +167,142 @@ def _lowprec_study(dev, iters, seconds_note=None):
     return out
 
 
+def _batch_study(dev, n_jobs, iters):
+    """The batch workload: n_jobs 3-way FP32 tensors, each dim U[32, 256], planted
+    rank R in {8, 16, 32} + 1% noise, NNCP at that R, HALS, `iters` outer
+    iterations. All jobs advance together (one persistent work-list launch per
+    step and kernel family, one HIP graph per tick); the same jobs are also run
+    one after another on their own, and every job's factors are compared."""
+    import torch
+    from paper_1806_07985_amd import inputs, native
+    t0 = time.perf_counter()
+    shapes = inputs.batch_shapes(n_jobs, seed=9)
+    jobs = []
+    for j, (d, R) in enumerate(shapes):
+        X, _ = inputs.planted(d, R, 0.01, seed=1000 + j, dtype=np.float32)
+        H0 = [h.astype(np.float32) for h in inputs.init_factors(d, R, seed=5000 + j)]
+        jobs.append(dict(dims=d, R=R, X=native.tensor_to_device(X, device=dev), H0=H0))
+    gen_s = time.perf_counter() - t0
+    entries = sum(int(np.prod(j["dims"])) for j in jobs)
+
+    def plans(graph):
+        out = []
+        for j in jobs:
+            H = [native.factor_to_device(h, device=dev) for h in j["H0"]]
+            out.append((native.Plan(j["X"], list(j["dims"]), j["R"], H, graph=graph), H))
+        return out
+
+    mixed = plans(graph=False)
+    batch = native.Batch()
+    for p_, _ in mixed:
+        batch.add(p_)
+    batch.run(1)                         # builds the work lists and the graph: one tick
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    batch.run(iters - 1)
+    torch.cuda.synchronize()
+    t_batch = time.perf_counter() - t0
+    st = batch.stats()
+    alone = plans(graph=True)
+    for p_, _ in alone:                  # first run of each plan builds its graph: one iteration
+        p_.run(1)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for p_, _ in alone:
+        p_.run(iters - 1)
+    torch.cuda.synchronize()
+    t_alone = time.perf_counter() - t0
+    same = all(all(torch.equal(a, b) for a, b in zip(ha, hb)) for (_, ha), (_, hb) in zip(alone, mixed))
+    fits = [float(p_.fits()[-1]) for p_, _ in mixed]
+    batch.close()
+    for p_, _ in mixed + alone:
+        p_.close()
+    del jobs, mixed, alone
+    torch.cuda.empty_cache()
+    ticks = iters - 1
+    return {"workload": f"{n_jobs} 3-way FP32 jobs, dims U[32,256], planted rank R in {{8,16,32}} + 1% noise, "
+                        f"NNCP at that R, HALS, {iters} iterations",
+            "entries_total": entries, "generate_s": gen_s,
+            "makespan_ms_per_iter": 1e3 * t_batch / ticks, "alone_ms_per_iter": 1e3 * t_alone / ticks,
+            "speedup_vs_alone_sequential": t_alone / t_batch,
+            "makespan_ms_30_iters_est": 1e3 * t_batch / ticks * iters,
+            "jobs_per_s": n_jobs / (t_batch / ticks * iters),
+            "tensor_GBs": 2.0 * 4 * entries * ticks / t_batch / 1e9,
+            "launches_per_tick": st["launches_per_tick"], "items_per_tick": st["items_per_tick"],
+            "batch_equals_alone_bitwise": bool(same),
+            "fit_min": min(fits), "fit_median": float(np.median(fits))}
+
+
+def _serving_study(dev, n_pool, n_jobs, load_fracs, iters, budget_gb, max_active):
+    """Serving stream: jobs of 3-, 4- and 5-way tensors, 1e5..2e8 entries
+    (log-uniform, Dirichlet split of log I over the modes), R in {8,16,32,64},
+    FP32 or BF16 storage with equal odds, planted rank R + 1% noise, HALS,
+    `iters` iterations each, submitted as pinned host tensors. First all jobs
+    are queued at once (saturation throughput mu), then jobs arrive as a Poisson
+    stream at each fraction of mu; latency = submit to result on the host."""
+    import torch
+    from paper_1806_07985_amd import inputs, native
+    t0 = time.perf_counter()
+    rng = np.random.default_rng(21)
+    pool = []
+    for k in range(n_pool):
+        dims, R = inputs.serving_job_shape(rng)
+        dt = "bf16" if rng.random() < 0.5 else "f32"
+        X = inputs.planted_device(dims, R, 0.01, seed=3000 + k, device=dev)
+        if dt == "bf16":
+            X = X.to(torch.bfloat16)
+        Xh = torch.empty(X.shape, dtype=X.dtype, pin_memory=True)
+        Xh.copy_(X)
+        del X
+        H0 = [h.astype(np.float32) for h in inputs.init_factors(dims, R, seed=4000 + k)]
+        pool.append(dict(dims=dims, R=R, dt=dt, X=Xh, H0=H0, entries=int(np.prod(dims))))
+    torch.cuda.synchronize()
+    torch.cuda.empty_cache()
+    gen_s = time.perf_counter() - t0
+
+    def run(rate):
+        srv = native.Server(int(budget_gb * (1 << 30)), max_active=max_active)
+        arr = np.random.default_rng(77)
+        ids, t_start = [], time.perf_counter()
+        t_next = t_start
+        for j in range(n_jobs):
+            if rate:
+                t_next += arr.exponential(1.0 / rate)
+                while time.perf_counter() < t_next:
+                    time.sleep(min(0.002, max(0.0, t_next - time.perf_counter())))
+            p_ = pool[j % n_pool]
+            ids.append(srv.submit(p_["X"], p_["dims"], p_["R"], p_["H0"], iters))
+        for i in ids:
+            srv.wait(i, -1.0)
+        res = [srv.poll(i) for i in ids]
+        st = srv.stats()
+        srv.close()
+        ok = all(r["status"] == 0 for r in res)
+        lat = np.array([r["done_s"] - r["submit_s"] for r in res])
+        dev_lat = np.array([r["done_s"] - r["admit_s"] for r in res])
+        span = max(r["done_s"] for r in res) - min(r["submit_s"] for r in res)
+        return dict(jobs=n_jobs, ok=ok, jobs_per_s=n_jobs / span, span_s=span,
+                    p50_s=float(np.percentile(lat, 50)), p99_s=float(np.percentile(lat, 99)),
+                    p50_device_s=float(np.percentile(dev_lat, 50)), p99_device_s=float(np.percentile(dev_lat, 99)),
+                    mean_s=float(lat.mean()), peak_active=st["peak_active"], ticks=st["ticks"],
+                    busy_frac=st["busy_s"] / max(span, 1e-9), peak_GB=st["peak_bytes"] / 1e9)
+
+    entries_mean = float(np.mean([p_["entries"] for p_ in pool]))
+    sat = run(None)
+    mu = sat["jobs_per_s"]
+    levels = {"saturation": sat}
+    for f in load_fracs:
+        levels[f"{f:.2f}mu"] = run(f * mu)
+    del pool
+    torch.cuda.empty_cache()
+    return {"workload": f"Poisson stream of 3/4/5-way jobs, 1e5..2e8 entries log-uniform, R in {{8,16,32,64}}, "
+                        f"FP32 or BF16, planted + 1% noise, HALS {iters} iterations; {n_pool} distinct tensors "
+                        f"cycled, {n_jobs} jobs per load level",
+            "generate_s": gen_s, "hbm_budget_GB": budget_gb, "max_active": max_active,
+            "pool_entries_mean": entries_mean,
+            "levels": levels}
+
+
 def main(argv=None):
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -181,6 +317,14 @@ def main(argv=None):
     ap.add_argument("--no-lowprec", action="store_true",
                     help="skip the FP32 / BF16 / FP16 study on the 1024x1344x33x9 tensor")
     ap.add_argument("--lowprec-iters", type=int, default=100)
+    ap.add_argument("--no-batch", action="store_true", help="skip the 256-job batch study")
+    ap.add_argument("--batch-jobs", type=int, default=256)
+    ap.add_argument("--batch-iters", type=int, default=30)
+    ap.add_argument("--no-serve", action="store_true", help="skip the serving-stream study")
+    ap.add_argument("--serve-pool", type=int, default=16)
+    ap.add_argument("--serve-jobs", type=int, default=24)
+    ap.add_argument("--serve-loads", default="0.7", help="comma-separated fractions of the saturation rate")
+    ap.add_argument("--serve-iters", type=int, default=30)
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run a plain 1 GiB device-to-device copy (for scaling HBM counters)")
     args = ap.parse_args(argv)
@@ -278,6 +422,12 @@ def main(argv=None):
     torch.cuda.empty_cache()
     if not args.no_lowprec:
         out["lowprec"] = _lowprec_study(dev, args.lowprec_iters)
+    if not args.no_batch:
+        out["batch"] = _batch_study(dev, args.batch_jobs, args.batch_iters)
+    if not args.no_serve:
+        loads = [float(x) for x in args.serve_loads.split(",") if x]
+        out["serving"] = _serving_study(dev, args.serve_pool, args.serve_jobs, loads, args.serve_iters,
+                                        budget_gb=96.0, max_active=64)
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = _cpu_baseline(X, [h.astype(np.float64) for h in H0], args.cpu_iters)
     print(json.dumps(out), flush=True)

@@ -158,6 +158,54 @@ int nncp_batch_run(nncp_batch* batch, int ticks);
 int nncp_batch_stats(const nncp_batch* batch, int* launches, int64_t* items);
 int nncp_batch_destroy(nncp_batch* batch);   /* does not destroy the member plans */
 
+/* ---- Serving: continuous batching of jobs that arrive over time ----
+ * A worker thread admits submitted jobs in arrival order while fewer than
+ * max_active are running and their device footprint (tensor + factors +
+ * workspace) fits in hbm_budget_bytes next to the running ones; a job that can
+ * never fit is rejected with NNCP_ENOMEM. Admitted jobs stay resident and all
+ * of them advance one outer iteration per tick through one batch; a job leaves
+ * after its `iters` iterations (results copied to host, device memory freed)
+ * and queued jobs are admitted between ticks. Each job's result is that of its
+ * stand-alone plan (see nncp_batch). Times are seconds on the server's clock. */
+typedef struct nncp_server nncp_server;
+#define NNCP_SERVER_SIMULATE 1  /* flag: run the scheduler without a GPU (ticks sleep); for host tests */
+typedef struct nncp_job_request {
+  const void* X;            /* host tensor in `dtype` storage, mode 1 fastest; must stay valid until the
+                               job is done (it is read when the job is admitted) */
+  int dtype, N;
+  const int64_t* dims;      /* host, N extents (copied) */
+  int R;                    /* 1..64 */
+  int update, iters, split; /* split <= 0: automatic */
+  const float* const* H0;   /* host, N starting factors I_n x R column-major (copied at submit) */
+} nncp_job_request;
+typedef struct nncp_job_result {
+  int status;               /* NNCP_EBUSY while queued or running, then NNCP_OK or the error */
+  int iters_done;
+  double submit_s, admit_s, done_s;
+  size_t footprint_bytes;
+} nncp_job_result;
+typedef struct nncp_server_stats {
+  int queued, active, peak_active;
+  int64_t ticks, completed, rejected;
+  size_t bytes_in_use, peak_bytes, budget_bytes;
+  double busy_s, now_s;     /* time spent in ticks; server clock now */
+} nncp_server_stats;
+int nncp_server_create(nncp_server** server, size_t hbm_budget_bytes, int max_active, int flags);
+int nncp_server_submit(nncp_server* server, const nncp_job_request* req, uint64_t* id);
+/* NNCP_EBUSY while the job is queued or running, NNCP_OK when done (res->status
+ * says how), NNCP_ENOTFOUND for an unknown or already fetched id. */
+int nncp_server_poll(nncp_server* server, uint64_t id, nncp_job_result* res);
+/* Blocks until the job is done (timeout_s < 0: no limit); NNCP_EBUSY on timeout. */
+int nncp_server_wait(nncp_server* server, uint64_t id, double timeout_s);
+/* Copies a finished job's normalised factors (H[n]: host I_n x R floats), lambda
+ * (host R) and fits (host, up to fit_cap) and forgets the job. Any output may be
+ * NULL. Returns the job's status. */
+int nncp_server_fetch(nncp_server* server, uint64_t id, float* const* H, double* lambda, double* fit,
+                      int fit_cap, int* fit_count);
+int nncp_server_get_stats(nncp_server* server, nncp_server_stats* stats);
+/* Cancels queued jobs, lets running ones finish, stops the worker. */
+int nncp_server_destroy(nncp_server* server);
+
 /* ---- Steps of the hot path (each is the kernel the driver runs) ---- */
 
 /* Round float32 to bfloat16 / float16 (round to nearest even), n entries, device. */

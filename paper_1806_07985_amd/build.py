@@ -11,8 +11,7 @@ ROOT = os.path.dirname(PKG)
 CSRC = os.path.join(PKG, "csrc")
 LIB_DIR = os.path.join(PKG, "lib")
 LIB = os.path.join(LIB_DIR, "libnncp.so")
-SOURCES = ["pm_plan.hip", "pm_kernels.hip", "pm16_kernels.hip", "small_kernels.hip", "batch_kernels.hip",
-           "driver.hip", "batch.hip", "server.cpp"]
+SOURCES = ["pm_plan.hip", "pm_kernels.hip", "pm16_kernels.hip", "small_kernels.hip", "driver.hip", "server.cpp"]
 
 HIPCC_FLAGS = [
     "--offload-arch=gfx950", "-O3", "-fPIC", "-std=c++17",
@@ -23,7 +22,7 @@ HIPCC_FLAGS = [
 
 
 def sources():
-    return [os.path.join(CSRC, s) for s in SOURCES if os.path.exists(os.path.join(CSRC, s))]
+    return [os.path.join(CSRC, s) for s in SOURCES]
 
 
 def build(verbose: bool = False, jobs: int = 8) -> str:
@@ -39,7 +38,8 @@ def build(verbose: bool = False, jobs: int = 8) -> str:
         objs.append(obj)
         cmd = [hipcc, *HIPCC_FLAGS, *incs, "-c", src, "-o", obj]
         if src.endswith(".cpp"):
-            cmd = [hipcc, "-O2", "-fPIC", "-std=c++17", "-Wno-unused-result", *incs, "-c", src, "-o", obj]
+            cmd = [hipcc, "--offload-arch=gfx950", "-O2", "-fPIC", "-std=c++17", "-Wno-unused-result", *incs, "-c", src,
+                   "-o", obj]
         log = open(obj + ".log", "w")
         procs.append((src, subprocess.Popen(cmd, stdout=log, stderr=subprocess.STDOUT)))
         log.close()

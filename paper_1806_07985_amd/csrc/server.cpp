@@ -1,0 +1,408 @@
+// Serving loop: NNCP jobs of uneven order, shape, rank and storage type arrive
+// at any time; a worker thread admits them by device footprint against an HBM
+// budget, keeps each admitted job's tensor, factors and workspace resident, and
+// advances every admitted job by one outer iteration per tick through one
+// batch (continuous batching: jobs join and leave between ticks while others
+// keep running). A job's arithmetic is that of its stand-alone plan, so its
+// result does not depend on the mix. Not part of the paper, which runs one
+// decomposition at a time; this is the serving layer around its method.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <chrono>
+#include <condition_variable>
+#include <cstring>
+#include <deque>
+#include <map>
+#include <memory>
+#include <mutex>
+#include <new>
+#include <thread>
+#include <vector>
+
+#include "nncp.h"
+
+namespace {
+
+using Clock = std::chrono::steady_clock;
+
+size_t elem_bytes(int dtype) { return dtype == NNCP_F32 ? 4 : 2; }
+
+struct Job {
+  uint64_t id = 0;
+  // request
+  const void* X = nullptr;  // caller's host tensor (valid until the job is done)
+  int dtype = 0, N = 0, R = 0, update = 0, iters = 0, split = 0;
+  int64_t dims[NNCP_MAX_MODES] = {};
+  int64_t I = 0;
+  std::vector<std::vector<float>> H0;  // copied at submit
+  size_t footprint = 0;
+  // device state while active
+  void* Xd = nullptr;
+  float* Hd[NNCP_MAX_MODES] = {};
+  void* ws = nullptr;
+  nncp_plan* plan = nullptr;
+  int done_iters = 0;
+  // timeline (seconds on the server clock) and outcome
+  double t_submit = 0, t_admit = 0, t_done = 0;
+  int status = NNCP_EBUSY;  // EBUSY while queued/active, then OK or an error
+  std::vector<std::vector<float>> H;  // results
+  std::vector<double> lam, fit;
+};
+
+}  // namespace
+
+struct nncp_server {
+  size_t budget = 0;
+  int max_active = 0;
+  bool simulate = false;
+  int device = 0;
+  Clock::time_point t0;
+  std::mutex mu;
+  std::condition_variable cv_work, cv_done;
+  std::deque<uint64_t> queue;
+  std::map<uint64_t, std::unique_ptr<Job>> jobs;
+  std::vector<Job*> active;
+  uint64_t next_id = 1;
+  size_t used = 0, peak_used = 0;
+  int64_t ticks = 0, completed = 0, rejected = 0;
+  int peak_active = 0;
+  double busy_s = 0;
+  bool stop = false;
+  hipStream_t st = nullptr;
+  nncp_batch* batch = nullptr;
+  std::thread worker;
+
+  double now() const { return std::chrono::duration<double>(Clock::now() - t0).count(); }
+};
+
+namespace {
+
+size_t job_footprint(const Job& j) {
+  size_t b = (size_t)j.I * elem_bytes(j.dtype);
+  for (int n = 0; n < j.N; ++n) b += (size_t)j.dims[n] * j.R * sizeof(float) + 256;
+  nncp_options o{};
+  o.split = j.split;
+  b += nncp_workspace_bytes(j.N, j.dims, j.R, j.dtype, &o) + 256;
+  return b;
+}
+
+void release_device(Job* j) {
+  if (j->plan) nncp_plan_destroy(j->plan);
+  j->plan = nullptr;
+  for (int n = 0; n < j->N; ++n)
+    if (j->Hd[n]) hipFree(j->Hd[n]);
+  if (j->Xd) hipFree(j->Xd);
+  if (j->ws) hipFree(j->ws);
+  j->Xd = nullptr;
+  j->ws = nullptr;
+  for (auto& h : j->Hd) h = nullptr;
+}
+
+// Upload the tensor and starting factors and create the job's plan.
+int admit_device(nncp_server* S, Job* j) {
+  const size_t xb = (size_t)j->I * elem_bytes(j->dtype);
+  if (hipMalloc(&j->Xd, xb) != hipSuccess) return NNCP_ENOMEM;
+  if (hipMemcpyAsync(j->Xd, j->X, xb, hipMemcpyHostToDevice, S->st) != hipSuccess) return NNCP_EDEVICE;
+  for (int n = 0; n < j->N; ++n) {
+    const size_t hb = (size_t)j->dims[n] * j->R * sizeof(float);
+    if (hipMalloc((void**)&j->Hd[n], hb) != hipSuccess) return NNCP_ENOMEM;
+    if (hipMemcpyAsync(j->Hd[n], j->H0[n].data(), hb, hipMemcpyHostToDevice, S->st) != hipSuccess)
+      return NNCP_EDEVICE;
+  }
+  nncp_options o{};
+  o.split = j->split;
+  o.no_graph = 1;
+  const size_t wsb = nncp_workspace_bytes(j->N, j->dims, j->R, j->dtype, &o);
+  if (wsb == 0) return NNCP_EINVAL;
+  if (hipMalloc(&j->ws, wsb) != hipSuccess) return NNCP_ENOMEM;
+  int r = nncp_plan_create(&j->plan, j->Xd, j->dtype, j->N, j->dims, j->R, j->update, j->Hd, nullptr, j->ws, wsb,
+                           &o, S->st);
+  if (r != NNCP_OK) return r;
+  return nncp_batch_add(S->batch, j->plan);
+}
+
+// Finished: normalised factors, lambda and fits to host, then free the device side.
+int retire_device(nncp_server* S, Job* j) {
+  int r = nncp_batch_remove(S->batch, j->plan);
+  j->lam.assign(j->R, 0.0);
+  if (r == NNCP_OK) r = nncp_plan_finish(j->plan, j->lam.data());
+  if (r == NNCP_OK) {
+    j->fit.assign(std::min(j->iters, 1024), 0.0);
+    int cnt = 0;
+    r = nncp_plan_fits(j->plan, j->fit.data(), (int)j->fit.size(), &cnt);
+    j->fit.resize(std::min<size_t>(j->fit.size(), (size_t)std::max(cnt, 0)));
+  }
+  j->H.resize(j->N);
+  for (int n = 0; r == NNCP_OK && n < j->N; ++n) {
+    j->H[n].resize((size_t)j->dims[n] * j->R);
+    if (hipMemcpyAsync(j->H[n].data(), j->Hd[n], j->H[n].size() * sizeof(float), hipMemcpyDeviceToHost, S->st) !=
+        hipSuccess)
+      r = NNCP_EDEVICE;
+  }
+  if (hipStreamSynchronize(S->st) != hipSuccess && r == NNCP_OK) r = NNCP_EDEVICE;
+  release_device(j);
+  return r;
+}
+
+void worker_loop(nncp_server* S) {
+  if (!S->simulate) (void)hipSetDevice(S->device);
+  std::unique_lock<std::mutex> lk(S->mu);
+  while (true) {
+    // admission, in arrival order, while slots and memory allow
+    while (!S->queue.empty() && (int)S->active.size() < S->max_active) {
+      Job* j = S->jobs[S->queue.front()].get();
+      if (j->footprint > S->budget) {  // can never fit
+        S->queue.pop_front();
+        j->status = NNCP_ENOMEM;
+        j->t_done = S->now();
+        ++S->rejected;
+        S->cv_done.notify_all();
+        continue;
+      }
+      if (S->used + j->footprint > S->budget) break;  // wait for memory to free up
+      S->queue.pop_front();
+      S->used += j->footprint;
+      S->peak_used = std::max(S->peak_used, S->used);
+      j->t_admit = S->now();
+      int r = NNCP_OK;
+      if (!S->simulate) {
+        lk.unlock();
+        r = admit_device(S, j);
+        lk.lock();
+      }
+      if (r != NNCP_OK) {
+        if (!S->simulate) {
+          if (j->plan) nncp_batch_remove(S->batch, j->plan);
+          release_device(j);
+        }
+        S->used -= j->footprint;
+        j->status = r;
+        j->t_done = S->now();
+        ++S->rejected;
+        S->cv_done.notify_all();
+        continue;
+      }
+      S->active.push_back(j);
+      S->peak_active = std::max(S->peak_active, (int)S->active.size());
+    }
+    if (S->active.empty()) {
+      if (S->stop) break;
+      S->cv_work.wait(lk);
+      continue;
+    }
+    // one tick: every active job advances one outer iteration
+    std::vector<Job*> act = S->active;
+    lk.unlock();
+    const double tb = S->now();
+    int r = NNCP_OK;
+    if (S->simulate) {
+      int64_t e = 0;
+      for (Job* j : act) e += j->I;
+      std::this_thread::sleep_for(std::chrono::microseconds(50 + e / 1000000));
+    } else {
+      r = nncp_batch_run(S->batch, 1);
+    }
+    const double te = S->now();
+    lk.lock();
+    S->busy_s += te - tb;
+    ++S->ticks;
+    std::vector<Job*> finished;
+    for (Job* j : act) {
+      ++j->done_iters;
+      if (r != NNCP_OK || j->done_iters >= j->iters) finished.push_back(j);
+    }
+    lk.unlock();
+    std::vector<int> codes(finished.size(), r);
+    if (!S->simulate)
+      for (size_t k = 0; k < finished.size(); ++k) {
+        if (r == NNCP_OK) {
+          codes[k] = retire_device(S, finished[k]);
+        } else {
+          nncp_batch_remove(S->batch, finished[k]->plan);
+          release_device(finished[k]);
+        }
+      }
+    lk.lock();
+    const double td = S->now();
+    for (size_t k = 0; k < finished.size(); ++k) {
+      Job* j = finished[k];
+      S->active.erase(std::find(S->active.begin(), S->active.end(), j));
+      S->used -= j->footprint;
+      j->status = codes[k];
+      j->t_done = td;
+      ++S->completed;
+    }
+    if (!finished.empty()) S->cv_done.notify_all();
+  }
+}
+
+}  // namespace
+
+extern "C" {
+
+int nncp_server_create(nncp_server** out, size_t hbm_budget_bytes, int max_active, int flags) {
+  if (!out || hbm_budget_bytes == 0 || max_active < 1) return NNCP_EINVAL;
+  *out = nullptr;
+  nncp_server* S = new (std::nothrow) nncp_server();
+  if (!S) return NNCP_ENOMEM;
+  S->budget = hbm_budget_bytes;
+  S->max_active = max_active;
+  S->simulate = (flags & NNCP_SERVER_SIMULATE) != 0;
+  S->t0 = Clock::now();
+  if (!S->simulate) {
+    if (hipGetDevice(&S->device) != hipSuccess || hipStreamCreateWithFlags(&S->st, hipStreamNonBlocking) != hipSuccess) {
+      delete S;
+      return NNCP_EDEVICE;
+    }
+    int r = nncp_batch_create(&S->batch, S->st);
+    if (r != NNCP_OK) {
+      hipStreamDestroy(S->st);
+      delete S;
+      return r;
+    }
+  }
+  try {
+    S->worker = std::thread(worker_loop, S);
+  } catch (...) {
+    if (S->batch) nncp_batch_destroy(S->batch);
+    if (S->st) hipStreamDestroy(S->st);
+    delete S;
+    return NNCP_ENOMEM;
+  }
+  *out = S;
+  return NNCP_OK;
+}
+
+int nncp_server_submit(nncp_server* S, const nncp_job_request* q, uint64_t* id) {
+  if (!S || !q || !id || !q->X || !q->dims || !q->H0 || q->iters < 1) return NNCP_EINVAL;
+  if (q->N < 2 || q->N > NNCP_MAX_MODES || q->R < 1 || q->R > 64) return NNCP_EINVAL;
+  if (q->dtype != NNCP_F32 && q->dtype != NNCP_BF16 && q->dtype != NNCP_F16) return NNCP_EINVAL;
+  if (q->update != NNCP_HALS && q->update != NNCP_MU) return NNCP_EINVAL;
+  std::unique_ptr<Job> j(new (std::nothrow) Job());
+  if (!j) return NNCP_ENOMEM;
+  j->X = q->X;
+  j->dtype = q->dtype;
+  j->N = q->N;
+  j->R = q->R;
+  j->update = q->update;
+  j->iters = q->iters;
+  j->split = q->split;
+  j->I = 1;
+  for (int n = 0; n < q->N; ++n) {
+    if (q->dims[n] < 1 || !q->H0[n]) return NNCP_EINVAL;
+    j->dims[n] = q->dims[n];
+    j->I *= q->dims[n];
+  }
+  nncp_options o{};
+  o.split = q->split;
+  if (nncp_workspace_bytes(j->N, j->dims, j->R, j->dtype, &o) == 0) return NNCP_EINVAL;
+  try {
+    j->H0.resize(q->N);
+    for (int n = 0; n < q->N; ++n) j->H0[n].assign(q->H0[n], q->H0[n] + (size_t)q->dims[n] * q->R);
+  } catch (...) {
+    return NNCP_ENOMEM;
+  }
+  j->footprint = job_footprint(*j);
+  std::lock_guard<std::mutex> lk(S->mu);
+  if (S->stop) return NNCP_ECANCELED;
+  j->id = S->next_id++;
+  j->t_submit = S->now();
+  *id = j->id;
+  S->queue.push_back(j->id);
+  S->jobs[j->id] = std::move(j);
+  S->cv_work.notify_one();
+  return NNCP_OK;
+}
+
+int nncp_server_poll(nncp_server* S, uint64_t id, nncp_job_result* res) {
+  if (!S) return NNCP_EINVAL;
+  std::lock_guard<std::mutex> lk(S->mu);
+  auto it = S->jobs.find(id);
+  if (it == S->jobs.end()) return NNCP_ENOTFOUND;
+  const Job* j = it->second.get();
+  if (res) {
+    res->status = j->status;
+    res->iters_done = j->done_iters;
+    res->submit_s = j->t_submit;
+    res->admit_s = j->t_admit;
+    res->done_s = j->t_done;
+    res->footprint_bytes = j->footprint;
+  }
+  return j->status == NNCP_EBUSY ? NNCP_EBUSY : NNCP_OK;
+}
+
+int nncp_server_fetch(nncp_server* S, uint64_t id, float* const* H, double* lambda, double* fit, int fit_cap,
+                      int* fit_count) {
+  if (!S) return NNCP_EINVAL;
+  std::unique_ptr<Job> j;
+  {
+    std::lock_guard<std::mutex> lk(S->mu);
+    auto it = S->jobs.find(id);
+    if (it == S->jobs.end()) return NNCP_ENOTFOUND;
+    if (it->second->status == NNCP_EBUSY) return NNCP_EBUSY;
+    j = std::move(it->second);
+    S->jobs.erase(it);
+  }
+  if (j->status != NNCP_OK) return j->status;
+  // (a simulated server computes nothing: its jobs finish with empty results)
+  for (int n = 0; H && n < (int)j->H.size(); ++n)
+    if (H[n]) std::memcpy(H[n], j->H[n].data(), j->H[n].size() * sizeof(float));
+  if (lambda && !j->lam.empty()) std::memcpy(lambda, j->lam.data(), j->lam.size() * sizeof(double));
+  const int nf = std::min<int>((int)j->fit.size(), std::max(fit_cap, 0));
+  if (fit && nf > 0) std::memcpy(fit, j->fit.data(), nf * sizeof(double));
+  if (fit_count) *fit_count = (int)j->fit.size();
+  return NNCP_OK;
+}
+
+int nncp_server_wait(nncp_server* S, uint64_t id, double timeout_s) {
+  if (!S) return NNCP_EINVAL;
+  std::unique_lock<std::mutex> lk(S->mu);
+  auto done = [&] {
+    auto it = S->jobs.find(id);
+    return it == S->jobs.end() || it->second->status != NNCP_EBUSY;
+  };
+  if (timeout_s < 0) S->cv_done.wait(lk, done);
+  else if (!S->cv_done.wait_for(lk, std::chrono::duration<double>(timeout_s), done)) return NNCP_EBUSY;
+  return S->jobs.count(id) ? NNCP_OK : NNCP_ENOTFOUND;
+}
+
+int nncp_server_get_stats(nncp_server* S, nncp_server_stats* out) {
+  if (!S || !out) return NNCP_EINVAL;
+  std::lock_guard<std::mutex> lk(S->mu);
+  out->queued = (int)S->queue.size();
+  out->active = (int)S->active.size();
+  out->peak_active = S->peak_active;
+  out->ticks = S->ticks;
+  out->completed = S->completed;
+  out->rejected = S->rejected;
+  out->bytes_in_use = S->used;
+  out->peak_bytes = S->peak_used;
+  out->budget_bytes = S->budget;
+  out->busy_s = S->busy_s;
+  out->now_s = S->now();
+  return NNCP_OK;
+}
+
+int nncp_server_destroy(nncp_server* S) {
+  if (!S) return NNCP_EINVAL;
+  {
+    std::lock_guard<std::mutex> lk(S->mu);
+    S->stop = true;
+    // queued jobs that never started are cancelled; active ones finish
+    for (uint64_t id : S->queue) {
+      Job* j = S->jobs[id].get();
+      j->status = NNCP_ECANCELED;
+      j->t_done = S->now();
+    }
+    S->queue.clear();
+  }
+  S->cv_work.notify_all();
+  if (S->worker.joinable()) S->worker.join();
+  if (S->batch) nncp_batch_destroy(S->batch);
+  if (S->st) hipStreamDestroy(S->st);
+  delete S;
+  return NNCP_OK;
+}
+
+}  // extern "C"

@@ -198,3 +198,29 @@ def serving_job_shape(rng: np.random.Generator, min_entries: float = 1e5,
     dims = tuple(max(min_dim, int(round(math.exp(logI * wi)))) for wi in w)
     R = int(rng.choice(np.asarray(ranks)))
     return dims, R
+
+
+def planted_device(dims: Sequence[int], R: int, noise: float, seed: int, device="cuda"):
+    """The ``planted`` recipe drawn with torch on a device (for large serving
+    jobs, where host generation would dominate): factors U[0,1) and N(0,1)
+    noise from a seeded torch generator, X = max(0, X_c + noise * ||X_c|| /
+    ||E|| * E). Returns the flat FP32 tensor, mode 1 fastest. Its values differ
+    from ``planted`` for the same seed (different random streams)."""
+    import torch
+    dims = _as_dims(dims)
+    g = torch.Generator(device=device)
+    g.manual_seed(int(seed))
+    fs = [torch.rand((d, R), generator=g, device=device, dtype=torch.float32) for d in dims]
+    # P[q, r] over modes 1..N-1 with mode 1 fastest, then X[q + Q*iN] = sum_r P[q, r] H_N[iN, r]
+    P = fs[0]
+    for f in fs[1:-1]:
+        P = (f[:, None, :] * P[None, :, :]).reshape(-1, R)
+    X = (fs[-1] @ P.T).reshape(-1)
+    del P
+    if noise:
+        E = torch.randn(X.numel(), generator=g, device=device, dtype=torch.float32)
+        scale = noise * torch.linalg.vector_norm(X.double()) / torch.linalg.vector_norm(E.double())
+        X.add_(E, alpha=float(scale))
+        del E
+        X.clamp_(min=0.0)
+    return X

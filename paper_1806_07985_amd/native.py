@@ -38,6 +38,24 @@ class Options(ctypes.Structure):
                 ("reserved", ctypes.c_int * 7)]
 
 
+class JobRequest(ctypes.Structure):
+    _fields_ = [("X", ctypes.c_void_p), ("dtype", ctypes.c_int), ("N", ctypes.c_int),
+                ("dims", ctypes.POINTER(ctypes.c_int64)), ("R", ctypes.c_int), ("update", ctypes.c_int),
+                ("iters", ctypes.c_int), ("split", ctypes.c_int), ("H0", ctypes.POINTER(ctypes.c_void_p))]
+
+
+class JobResult(ctypes.Structure):
+    _fields_ = [("status", ctypes.c_int), ("iters_done", ctypes.c_int), ("submit_s", ctypes.c_double),
+                ("admit_s", ctypes.c_double), ("done_s", ctypes.c_double), ("footprint_bytes", ctypes.c_size_t)]
+
+
+class ServerStats(ctypes.Structure):
+    _fields_ = [("queued", ctypes.c_int), ("active", ctypes.c_int), ("peak_active", ctypes.c_int),
+                ("ticks", ctypes.c_int64), ("completed", ctypes.c_int64), ("rejected", ctypes.c_int64),
+                ("bytes_in_use", ctypes.c_size_t), ("peak_bytes", ctypes.c_size_t), ("budget_bytes", ctypes.c_size_t),
+                ("busy_s", ctypes.c_double), ("now_s", ctypes.c_double)]
+
+
 class NNCPError(RuntimeError):
     def __init__(self, status: int, what: str):
         msg = _lib.nncp_strerror(status).decode() if _lib is not None else str(status)
@@ -105,6 +123,21 @@ def _declare(L):
     L.nncp_batch_stats.argtypes = [c_vp, ctypes.POINTER(ctypes.c_int), ctypes.POINTER(ctypes.c_int64)]
     L.nncp_batch_destroy.restype = ctypes.c_int
     L.nncp_batch_destroy.argtypes = [c_vp]
+    L.nncp_server_create.restype = ctypes.c_int
+    L.nncp_server_create.argtypes = [ctypes.POINTER(c_vp), ctypes.c_size_t, ctypes.c_int, ctypes.c_int]
+    L.nncp_server_submit.restype = ctypes.c_int
+    L.nncp_server_submit.argtypes = [c_vp, ctypes.POINTER(JobRequest), ctypes.POINTER(ctypes.c_uint64)]
+    L.nncp_server_poll.restype = ctypes.c_int
+    L.nncp_server_poll.argtypes = [c_vp, ctypes.c_uint64, ctypes.POINTER(JobResult)]
+    L.nncp_server_wait.restype = ctypes.c_int
+    L.nncp_server_wait.argtypes = [c_vp, ctypes.c_uint64, ctypes.c_double]
+    L.nncp_server_fetch.restype = ctypes.c_int
+    L.nncp_server_fetch.argtypes = [c_vp, ctypes.c_uint64, ctypes.POINTER(c_vp), c_dp, c_dp, ctypes.c_int,
+                                    ctypes.POINTER(ctypes.c_int)]
+    L.nncp_server_get_stats.restype = ctypes.c_int
+    L.nncp_server_get_stats.argtypes = [c_vp, ctypes.POINTER(ServerStats)]
+    L.nncp_server_destroy.restype = ctypes.c_int
+    L.nncp_server_destroy.argtypes = [c_vp]
 
 
 def lib():
@@ -340,6 +373,98 @@ class Batch:
         if getattr(self, "_h", None):
             lib().nncp_batch_destroy(self._h)
             self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+SERVER_SIMULATE = 1
+
+
+class Server:
+    """Continuous-batching NNCP server (native worker thread; see nncp.h).
+
+    submit() takes a host tensor (numpy array in its storage dtype, or a CPU
+    torch tensor, e.g. pinned BF16) that must stay alive until the job is done;
+    the server keeps a reference for that long.
+    """
+
+    def __init__(self, hbm_budget_bytes: int, max_active: int = 64, simulate: bool = False):
+        h = c_vp()
+        _check(lib().nncp_server_create(ctypes.byref(h), int(hbm_budget_bytes), int(max_active),
+                                        SERVER_SIMULATE if simulate else 0), "nncp_server_create")
+        self._h = h
+        self._keep = {}
+
+    def submit(self, X, dims, R, H0, iters, update="hals", split=0) -> int:
+        import torch
+        if isinstance(X, torch.Tensor):
+            if X.is_cuda:
+                raise ValueError("submit takes a host tensor")
+            Xc = X.contiguous()
+            code = _dtype_code(Xc)
+            ptr = Xc.data_ptr()
+        else:
+            Xc = np.ascontiguousarray(np.asarray(X).ravel(order="F"))
+            if Xc.dtype == np.float32:
+                code = 0
+            elif Xc.dtype == np.float16:
+                code = 2
+            else:
+                raise TypeError(f"unsupported host tensor dtype {Xc.dtype}")
+            ptr = Xc.ctypes.data
+        Hs = [np.asfortranarray(np.asarray(h, dtype=np.float32)) for h in H0]
+        Hp = (c_vp * len(Hs))(*[h.ctypes.data for h in Hs])
+        dims_arr = _dims(dims)
+        req = JobRequest(X=ptr, dtype=code, N=len(dims), dims=dims_arr, R=int(R), update=_UPDATE[update],
+                         iters=int(iters), split=int(split), H0=Hp)
+        jid = ctypes.c_uint64(0)
+        _check(lib().nncp_server_submit(self._h, ctypes.byref(req), ctypes.byref(jid)), "nncp_server_submit")
+        self._keep[jid.value] = (Xc, list(dims), int(R))
+        return jid.value
+
+    def poll(self, jid: int):
+        """None while queued or running, else dict(status, iters_done, submit_s, admit_s, done_s, footprint)."""
+        r = JobResult()
+        st = lib().nncp_server_poll(self._h, jid, ctypes.byref(r))
+        if st == -4:  # NNCP_EBUSY
+            return None
+        _check(st, "nncp_server_poll")
+        return dict(status=r.status, iters_done=r.iters_done, submit_s=r.submit_s, admit_s=r.admit_s,
+                    done_s=r.done_s, footprint=r.footprint_bytes)
+
+    def wait(self, jid: int, timeout_s: float = -1.0) -> bool:
+        st = lib().nncp_server_wait(self._h, jid, float(timeout_s))
+        if st == -4:
+            return False
+        _check(st, "nncp_server_wait")
+        return True
+
+    def fetch(self, jid: int) -> dict:
+        _, dims, R = self._keep[jid]
+        H = [np.zeros((d, R), dtype=np.float32, order="F") for d in dims]
+        Hp = (c_vp * len(H))(*[h.ctypes.data for h in H])
+        lam = (ctypes.c_double * R)()
+        fit = (ctypes.c_double * 1024)()
+        nf = ctypes.c_int(0)
+        st = lib().nncp_server_fetch(self._h, jid, Hp, lam, fit, 1024, ctypes.byref(nf))
+        self._keep.pop(jid, None)
+        _check(st, "nncp_server_fetch")
+        return dict(H=[h.astype(np.float64) for h in H], lam=np.array(lam[:]), fit=np.array(fit[:min(nf.value, 1024)]))
+
+    def stats(self) -> dict:
+        s = ServerStats()
+        _check(lib().nncp_server_get_stats(self._h, ctypes.byref(s)), "nncp_server_get_stats")
+        return {k: getattr(s, k) for k, _ in ServerStats._fields_}
+
+    def close(self):
+        if getattr(self, "_h", None):
+            lib().nncp_server_destroy(self._h)
+            self._h = None
+            self._keep.clear()
 
     def __del__(self):
         try:

@@ -1,0 +1,71 @@
+"""Serving loop on the GPU: jobs of mixed order, rank and storage type arrive
+while others run; each result equals the same job run alone (bitwise: a job
+keeps its own tiling and summation order in the mix) and the FP32 jobs agree
+with the FP64 oracle."""
+
+import time
+
+import numpy as np
+import pytest
+
+import oracle as O
+from paper_1806_07985_amd import inputs
+
+pytestmark = pytest.mark.gpu
+
+JOBS = [  # dims, R, dtype, update, iters
+    ((40, 30, 20), 8, "f32", "hals", 12),
+    ((24, 20, 18, 6), 16, "bf16", "hals", 9),
+    ((12, 10, 9, 8, 7), 4, "f32", "mu", 15),
+    ((64, 48, 40), 32, "f32", "hals", 7),
+    ((30, 28, 26), 64, "f16", "hals", 5),
+    ((50, 33, 17), 24, "f32", "hals", 20),
+]
+
+
+def _host_tensor(dims, R, dt, seed):
+    import torch
+    X, _ = inputs.planted(dims, R, 0.01, seed=seed, dtype=np.float32)
+    flat = torch.from_numpy(np.ascontiguousarray(X.ravel(order="F")))
+    if dt != "f32":
+        flat = flat.to({"bf16": torch.bfloat16, "f16": torch.float16}[dt])
+    return flat, flat.to(torch.float64).numpy().reshape(dims, order="F")
+
+
+def test_served_jobs_equal_alone_and_oracle(gpu_lib):
+    import torch
+    from paper_1806_07985_amd import native
+    srv = native.Server(8 << 30, max_active=4)
+    specs, ids = [], []
+    for k, (dims, R, dt, upd, iters) in enumerate(JOBS):
+        Xh, X64 = _host_tensor(dims, R, dt, 700 + k)
+        H0 = [h.astype(np.float32) for h in inputs.init_factors(dims, R, seed=800 + k)]
+        specs.append((Xh, X64, H0))
+        ids.append(srv.submit(Xh, dims, R, H0, iters, update=upd))
+        print(f"case served submit {dims} R={R} {dt} {upd} iters={iters}", flush=True)
+        time.sleep(0.002 * k)                   # staggered arrivals
+    for i in ids:
+        assert srv.wait(i, 60)
+    res = [srv.poll(i) for i in ids]
+    st = srv.stats()
+    print(f"server stats {st}", flush=True)
+    assert st["peak_active"] <= 4 and st["completed"] == len(JOBS)
+    outs = [srv.fetch(i) for i in ids]
+    srv.close()
+    for k, ((dims, R, dt, upd, iters), (Xh, X64, H0), r, out) in enumerate(zip(JOBS, specs, res, outs)):
+        assert r["status"] == 0 and r["iters_done"] == iters
+        # the same job alone
+        Hd = [native.factor_to_device(h) for h in H0]
+        plan = native.Plan(Xh.cuda(), list(dims), R, Hd, update=upd)
+        fit_alone = plan.run(iters)
+        lam_alone = plan.finish()
+        plan.close()
+        same = all(np.array_equal(native.factor_to_host(h), hs) for h, hs in zip(Hd, out["H"]))
+        print(f"case served {dims} {dt}: equal alone {same}, lam equal {np.array_equal(lam_alone, out['lam'])}",
+              flush=True)
+        assert same and np.array_equal(lam_alone, out["lam"]) and np.array_equal(fit_alone, out["fit"])
+        if dt == "f32":
+            ref = O.nncp(X64, [h.astype(np.float64) for h in H0], iters, update=upd)
+            errs = [np.linalg.norm(h - rh) / np.linalg.norm(rh) for h, rh in zip(out["H"], ref["H"])]
+            assert max(errs) < 1e-5, errs
+            assert np.max(np.abs(out["fit"] - np.asarray(ref["fit"]))) < 1e-5
