@@ -28,6 +28,7 @@ sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
 FP32_MFMA_PEAK_TFLOPS = 157.3
+BF16_MFMA_PEAK_TFLOPS = 2500.0   # dense BF16 / FP16 MFMA
 
 
 def _pm_sources_digest(dtype: str = "f32") -> str:
@@ -312,6 +313,9 @@ def main(argv=None):
     ap.add_argument("--dims", default="128,128,128,128")
     ap.add_argument("--rank", type=int, default=32)
     ap.add_argument("--split", type=int, default=2)
+    ap.add_argument("--workload", default="planted", choices=["planted", "hsi"],
+                    help="main workload: planted U[0,1) factors + 1%% noise, or the hyperspectral-shaped recipe")
+    ap.add_argument("--dtype", default="f32", choices=["f32", "bf16", "f16"], help="tensor storage of the main run")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-iters", type=int, default=3)
     ap.add_argument("--no-lowprec", action="store_true",
@@ -340,11 +344,17 @@ def main(argv=None):
     dims = [int(d) for d in args.dims.split(",")]
     R, s = args.rank, args.split
     workload = "x".join(map(str, dims)) + f"_r{R}"
-    X, _ = inputs.planted(dims, R, 0.01, seed=1, dtype=np.float32)
+    if args.workload == "hsi":
+        X, _ = inputs.hsi_like(dims, R, 0.02, seed=5)
+    else:
+        X, _ = inputs.planted(dims, R, 0.01, seed=1, dtype=np.float32)
     H0 = [h.astype(np.float32) for h in inputs.init_factors(dims, R, seed=2)]
 
     dev = torch.device("cuda:0")
     Xd = native.tensor_to_device(X, device=dev)
+    if args.dtype != "f32":
+        Xd = native.quantize(Xd, args.dtype)
+    sx, nodeb = (4, 8) if args.dtype == "f32" else (2, 4)
     Hd = [native.factor_to_device(h, device=dev) for h in H0]
     torch.cuda.synchronize()
 
@@ -359,7 +369,7 @@ def main(argv=None):
 
     # Dominant kernel: the root partial MTTKRPs (left = mode 1's node, right =
     # mode s+1's node), timed with HIP events on the plan's stream.
-    rt = _node_rates(plan, dims, s, R, 4, 8)
+    rt = _node_rates(plan, dims, s, R, sx, nodeb)
     dom = "left" if rt["left_ms"] >= rt["right_ms"] else "right"
     ms_dom = rt[dom + "_ms"]
     bytes_dom = rt[dom + "_bytes"]
@@ -399,18 +409,20 @@ def main(argv=None):
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f32",
+        "dtype": args.dtype,
         "data": "synthetic",
-        "config": {"workload": f"{'x'.join(map(str, dims))} FP32 planted rank {R} + 1% noise, NNCP R={R}, "
-                               f"{args.update.upper()}, tree split {{1..{s}}}|{{{s + 1}..{len(dims)}}}",
-                   "dims": dims, "R": R, "split": s, "update": args.update, "tensor_dtype": "f32"},
+        "config": {"workload": f"{'x'.join(map(str, dims))} {args.dtype.upper()} "
+                               f"{'hyperspectral-shaped rank 50 + 2% noise' if args.workload == 'hsi' else 'planted rank %d + 1%% noise' % R}"
+                               f", NNCP R={R}, {args.update.upper()}, tree split {{1..{s}}}|{{{s + 1}..{len(dims)}}}",
+                   "dims": dims, "R": R, "split": s, "update": args.update, "tensor_dtype": args.dtype},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS,
-                     "traffic": _traffic_from_profile(workload, bytes_dom),
+                     "traffic": _traffic_from_profile(workload, bytes_dom) if args.dtype == "f32" else None,
                      "kernel": f"partial MTTKRP ({dom} root node)",
                      "bytes_per_launch": bytes_dom, "ms_per_launch": ms_dom,
-                     "mfma_fp32_tflops": flops_pm / (ms_dom * 1e-3) / 1e12,
-                     "mfma_fp32_frac": flops_pm / (ms_dom * 1e-3) / 1e12 / FP32_MFMA_PEAK_TFLOPS},
+                     "mfma_tflops": flops_pm / (ms_dom * 1e-3) / 1e12,
+                     "mfma_frac": flops_pm / (ms_dom * 1e-3) / 1e12 /
+                     (FP32_MFMA_PEAK_TFLOPS if args.dtype == "f32" else BF16_MFMA_PEAK_TFLOPS)},
         "pm": {k: rt[k] for k in ("left_ms", "right_ms", "left_GBs", "right_GBs")},
         "mttkrp_GBs": mttkrp_gbs,
         "phase_ms_per_iter": ph,
