@@ -107,22 +107,35 @@ __global__ __launch_bounds__(256) void pm16_pack_kernel(PackArgs pa) {
 // Per-(j, column) factors of a work-group's j block: Krest(j0 + jj, col0 + r)
 // times the column's 1/lambda product times the pack scale, in FP32.
 __device__ __forceinline__ void pm16_scales(const PmArgs& a, float* sc, int RP, int64_t j0, int jn) {
-  for (int e = threadIdx.x; e < jn * RP; e += NT) {
-    const int jj = e / RP, r = e - jj * RP;
-    float v = 0.f;
-    if (r < a.R)
-      v = (float)(krp_colscale(a.krp, a.col0 + r) * krest_value(a.krp, (uint32_t)(j0 + jj), a.col0 + r)) *
-          a.hscale[r];
-    sc[e] = v;
-  }
+  pm_fill_scales<float>(a, sc, RP, j0, jn, a.hscale);
 }
 
-// Copy rows [i1_0, i1_0 + i1n) of the packed hi/lo factor into LDS (pitch lp).
+// Copy rows [i1_0, i1_0 + i1n) of the packed hi/lo factor into LDS (pitch lp):
+// 16-byte chunks, eight loads in flight per thread before they are stored.
 __device__ __forceinline__ void pm16_stage(const PmArgs& a, unsigned short* hs, int lp, int RP, int i1_0, int i1n) {
   const int chunks = i1n >> 3;
-  for (int e = threadIdx.x; e < 2 * RP * chunks; e += NT) {
-    const int row = e / chunks, c = e - row * chunks;
-    *(u4*)&hs[row * lp + 8 * c] = *(const u4*)&a.hpack[(size_t)row * a.I1pad + i1_0 + 8 * c];
+  const int total = 2 * RP * chunks;
+  constexpr int CH = 8;
+  const int drow = NT / chunks, dc = NT - drow * chunks;
+  int row = threadIdx.x / chunks, c = threadIdx.x - row * chunks;
+  for (int e0 = threadIdx.x; e0 < total; e0 += NT * CH) {
+    u4 v[CH];
+    int dst[CH];
+#pragma unroll
+    for (int q = 0; q < CH; ++q) {
+      const bool ok = e0 + NT * q < total;
+      v[q] = *(const u4*)&a.hpack[ok ? (size_t)row * a.I1pad + i1_0 + 8 * c : 0];
+      dst[q] = ok ? row * lp + 8 * c : -1;
+      row += drow;
+      c += dc;
+      if (c >= chunks) {
+        c -= chunks;
+        ++row;
+      }
+    }
+#pragma unroll
+    for (int q = 0; q < CH; ++q)
+      if (dst[q] >= 0) *(u4*)&hs[dst[q]] = v[q];
   }
 }
 

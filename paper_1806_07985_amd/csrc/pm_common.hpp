@@ -14,37 +14,99 @@ __device__ __forceinline__ f4 mfma4(float a, float b, f4 c) {
   return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
 }
 
-// Digits of index j over the contracted modes 1..nm-1 (mode 1 fastest) and the
-// product of those factors' entries in column `col`, in FP64.
-__device__ __forceinline__ double krest_value(const KrpDesc& krp, uint32_t j, int col) {
-  double p = 1.0;
-  for (int m = 1; m < krp.nm; ++m) {
-    const uint32_t d = (uint32_t)krp.dim[m];
+// Per-(j, column) factor of the Khatri-Rao row: Krest(j, col) = product over the
+// contracted modes 1..nm-1 (mode 1 fastest in j) of their factor entries, times
+// the column's 1/lambda product over all nm contracted modes (0 where a norm is
+// 0), in FP64. All of the entry's loads are issued unconditionally from valid
+// addresses before any is used (a load guarded by a branch would be waited for
+// at the join), so a batch of entries costs one memory round trip.
+__device__ __forceinline__ double krp_scale_entry(const KrpDesc& krp, uint32_t j, int col) {
+  float fv[kMaxModes];
+  double lv[kMaxModes];
+  const int nm = krp.nm;
+#pragma unroll
+  for (int m = 0; m < kMaxModes; ++m) {
+    const int mm = m < nm ? m : 0;
+    const uint32_t d = (uint32_t)krp.dim[mm];
     const uint32_t q = j / d;
-    p *= (double)krp.f[m][(int64_t)(j - q * d) + (int64_t)krp.dim[m] * col];
-    j = q;
+    const uint32_t dig = (m >= 1 && m < nm) ? j - q * d : 0u;
+    if (m >= 1 && m < nm) j = q;
+    fv[m] = krp.f[mm][(int64_t)dig + (int64_t)krp.dim[mm] * col];
+    lv[m] = krp.lam ? krp.lam[(int64_t)krp.mode[mm] * krp.lam_ld + col] : 1.0;
+  }
+  double p = 1.0;
+#pragma unroll
+  for (int m = 0; m < kMaxModes; ++m) {
+    if (m < nm) {
+      if (m >= 1) p *= (double)fv[m];
+      p = lv[m] > 0.0 ? p / lv[m] : 0.0;
+    }
   }
   return p;
 }
 
+// Fill sc[jj * RP + r] (jj < jn, r < RP) with the Khatri-Rao scales of columns
+// col0 + r (times extra[r] when given); 0 for r >= R. Four entries per thread
+// per round trip.
+template <typename T>
+__device__ __forceinline__ void pm_fill_scales(const PmArgs& a, T* sc, int RP, int64_t j0, int jn,
+                                               const float* extra) {
+  const int total = jn * RP;
+  constexpr int CH = 4;
+  for (int e0 = threadIdx.x; e0 < total; e0 += NT * CH) {
+    double v[CH];
+#pragma unroll
+    for (int c = 0; c < CH; ++c) {
+      const int e = e0 + NT * c;
+      const int ec = e < total ? e : 0;
+      const int jj = ec / RP, r = ec - jj * RP;
+      const int rc = r < a.R ? r : 0;
+      v[c] = krp_scale_entry(a.krp, (uint32_t)(j0 + jj), a.col0 + rc);
+      if (extra) v[c] *= (double)extra[rc];
+      if (r >= a.R) v[c] = 0.0;
+    }
+#pragma unroll
+    for (int c = 0; c < CH; ++c) {
+      const int e = e0 + NT * c;
+      if (e < total) sc[e] = (T)v[c];
+    }
+  }
+}
+
 // LDS prologue shared by the FP32 kernels: the block's rows of the first
 // contracted factor, hs[r * hp + i] = H_1(i1_0 + i, col0 + r) (zero padded), and
-// the per-(j, column) scales sc[jj * RP + r] = Krest(j0 + jj, col0 + r) times the
-// column's 1/lambda product.
+// the per-(j, column) scales sc[jj * RP + r]. Eight rows per thread per round
+// trip, loads unconditional from valid addresses.
 __device__ __forceinline__ void pm_prologue(const PmArgs& a, float* hs, int hp, double* sc, int RP, int i1_0,
                                             int i1n, int64_t j0, int jn) {
   const float* f0 = a.krp.f[0];
-  for (int e = threadIdx.x; e < RP * i1n; e += NT) {
-    const int r = e / i1n, i = e - r * i1n;
-    const int i1 = i1_0 + i;
-    hs[r * hp + i] = (r < a.R && i1 < a.I1) ? f0[(int64_t)i1 + (int64_t)a.I1 * (a.col0 + r)] : 0.f;
+  const int total = RP * i1n;
+  constexpr int CH = 8;
+  const int dr = NT / i1n, di = NT - dr * i1n;
+  int r = threadIdx.x / i1n, i = threadIdx.x - r * i1n;
+  for (int e0 = threadIdx.x; e0 < total; e0 += NT * CH) {
+    float v[CH];
+    int dst[CH];
+#pragma unroll
+    for (int c = 0; c < CH; ++c) {
+      const int e = e0 + NT * c;
+      const int i1 = i1_0 + i;
+      const bool ok = e < total && r < a.R && i1 < a.I1;
+      const float x = f0[ok ? (int64_t)i1 + (int64_t)a.I1 * (a.col0 + r) : 0];
+      v[c] = ok ? x : 0.f;
+      dst[c] = e < total ? r * hp + i : -1;
+      r += dr;
+      i += di;
+      if (i >= i1n) {
+        i -= i1n;
+        ++r;
+      }
+    }
+#pragma unroll
+    for (int c = 0; c < CH; ++c)
+      if (dst[c] >= 0) hs[dst[c]] = v[c];
   }
-  for (int e = threadIdx.x; e < jn * RP; e += NT) {
-    const int jj = e / RP, r = e - jj * RP;
-    double v = 0.0;
-    if (r < a.R) v = krp_colscale(a.krp, a.col0 + r) * krest_value(a.krp, (uint32_t)(j0 + jj), a.col0 + r);
-    sc[e] = v;
-  }
+  pm_fill_scales<double>(a, sc, RP, j0, jn, nullptr);
 }
 
 // Sum the FP64 accumulators of the WK waves that share an M range through LDS;

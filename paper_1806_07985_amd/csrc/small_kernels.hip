@@ -306,6 +306,58 @@ __global__ __launch_bounds__(NT) void update_kernel(UpdateArgs a) {
   update_body<VPL>(a, blockIdx.x);
 }
 
+// The same update for R <= RB <= 64 with lane k's column of S held in registers
+// and the column sweeps unrolled over RB (every broadcast uses a constant lane),
+// so the Gauss-Seidel chain touches no memory.
+template <int RB>
+__device__ __forceinline__ void update_reg_body(const UpdateArgs& a, int bx) {
+  const int R = a.R;
+  const int k = threadIdx.x & 63;
+  const int64_t row = (int64_t)bx * (NT / 64) + (threadIdx.x >> 6);
+  if (row >= a.I) return;  // wave-uniform; no barrier in this kernel
+  const bool col = k < R;
+  const int kc = col ? k : 0;  // every load is unconditional (from a valid index), masked after
+  double srow[RB];
+  const double ls = a.lam_self[kc], lm = a.lam_model[kc];
+  const double w0 = (double)a.W[row + a.I * kc];
+  const double m0 = ldv(a.M, row + a.I * kc, a.m_f64);
+#pragma unroll
+  for (int r = 0; r < RB; ++r) srow[r] = a.S[(int64_t)(r < R ? r : 0) * R + kc];  // S symmetric
+  const double dg = a.S[(int64_t)kc * R + kc];
+  const double f = ls > 0.0 ? lm / ls : 0.0;
+  double w = col ? w0 * f : 0.0;
+  const double m = col ? m0 : 0.0;
+  const double invd = (col && dg > 0.0) ? 1.0 / dg : 0.0;
+#pragma unroll
+  for (int r = 0; r < RB; ++r)
+    if (!(col && r < R)) srow[r] = 0.0;
+  double g = 0.0;
+#pragma unroll
+  for (int r = 0; r < RB; ++r) g += readlane_f64(w, r) * srow[r];
+  if (a.update == NNCP_HALS) {
+#pragma unroll
+    for (int r = 0; r < RB; ++r) {
+      if (r < R) {  // uniform
+        // column r: W(:,r) <- max(0, W(:,r) + (M(:,r) - (W S)(:,r)) / S(r,r)); a zero
+        // diagonal sets the column to zero (lane r owns column r)
+        double wn = invd > 0.0 ? w + (m - g) * invd : 0.0;
+        wn = wn > 0.0 ? wn : 0.0;
+        const double dlt = readlane_f64(wn - w, r);
+        if (k == r) w += dlt;
+        g += dlt * srow[r];
+      }
+    }
+  } else {
+    const double den = g > 1e-16 ? g : 1e-16;
+    w = w * m / den;
+  }
+  if (col) a.W[row + a.I * k] = (float)w;
+}
+template <int RB>
+__global__ __launch_bounds__(NT) void update_reg_kernel(UpdateArgs a) {
+  update_reg_body<RB>(a, blockIdx.x);
+}
+
 // Rows of W staged in LDS at a time (FP64): about 32 KB.
 __host__ __device__ inline int fin_sub_rows(int R) {
   int r = 4096 / (R > 0 ? R : 1);
@@ -421,63 +473,123 @@ __device__ void finalize_tail(const FinalizeArgs& a, double* fl, double* sh) {
   }
 }
 
-// Small problems (one row chunk, R <= 64): one work-group does everything.
-// The other modes' Gram product (for S of the next mode) and S of this mode
-// (for gamma) are read into LDS first, so their latency overlaps the Gram. Each
-// thread accumulates a 4 x 4 block of W^T W over one phase of the rows in
-// registers (FP64); phases are summed through LDS in phase order, and the tail
-// (lambda, normalised Gram, fit, next S) works from LDS.
+// Register-blocked Gram for R <= 64. W rows are staged in LDS (FP64) a few
+// dozen KB at a time; thread (block b, phase p) accumulates the 4 x 4 block b of
+// W^T W over rows p, p + nph, ... in registers, so each row costs 8 LDS reads for
+// 16 FMAs. Phases are summed through LDS in phase order. Index loops advance
+// incrementally (no integer division in a loop): with one wave per SIMD every
+// instruction's latency is exposed.
 constexpr int kSmallMaxR = 64;
 
-__device__ __forceinline__ void finalize_small_body(const FinalizeArgs& a) {
-  extern __shared__ double lds[];
-  __shared__ double sh[NT / 64];
+__host__ __device__ inline int gram_r4(int R) { return (R + 3) & ~3; }
+__host__ __device__ inline int gram_sub_rows(int R) { return 4096 / gram_r4(R); }
+// LDS doubles of the staging/partials area
+__host__ __device__ inline int gram_work_doubles(int R) {
+  const int stage = gram_sub_rows(R) * gram_r4(R), phases = NT * 16;
+  return stage > phases ? stage : phases;
+}
+
+// Gram (and beta = sum M o W when the fit is due) of rows [r0, r1) into out[RR]
+// and out[RR]. out may be global (a chunk's partial) or LDS. Block-wide.
+__device__ void gram_rows_blocked(const FinalizeArgs& a, int64_t r0, int64_t r1, double* work, double* sh,
+                                  double* out) {
   const int R = a.R, RR = R * R;
-  const int nb4 = (R + 3) >> 2, R4 = nb4 << 2;
-  const int nblk = nb4 * nb4;
-  const int nph = NT / nblk;  // >= 1 for R <= 64
-  double* Gh = lds;                  // RR + 1 (raw Gram, beta)
-  double* P = Gh + RR + 1;           // RR: product of the Grams other than mode and next_mode
-  double* Sm = P + RR;               // RR: S of this mode (fit only)
-  double* work = Sm + RR;            // staging rows [sub][R4], then phase partials [nph][nblk][16]
-  const int sub = (int)(4096 / R4) < 1 ? 1 : (int)(4096 / R4);
+  const int R4 = gram_r4(R), nb4 = R4 >> 2, nblk = nb4 * nb4;
+  const int nph = NT / nblk;
+  const int sub = gram_sub_rows(R);
   const int tid = threadIdx.x;
-
-  if (a.next_mode >= 0)
-    for (int e = tid; e < RR; e += NT) {
-      double v = 1.0;
-      for (int k = 0; k < a.N; ++k)
-        if (k != a.next_mode && k != a.mode) v *= a.G[(int64_t)k * RR + e];
-      P[e] = v;
-    }
-  if (a.do_fit)
-    for (int e = tid; e < RR; e += NT) Sm[e] = a.S[(int64_t)a.mode * RR + e];
-
   const bool active = tid < nblk * nph;
   const int blk = tid % nblk, ph = tid / nblk;
-  const int bx = blk / nb4, by = blk - bx * nb4;
+  const int bx = blk / nb4, by = blk - (blk / nb4) * nb4;
+  const bool fit = a.do_fit && a.M;
   double acc[4][4];
 #pragma unroll
   for (int i = 0; i < 4; ++i)
 #pragma unroll
     for (int j = 0; j < 4; ++j) acc[i][j] = 0.0;
   double bsum = 0.0;
-  for (int64_t s0 = 0; s0 < a.I; s0 += sub) {
-    const int cnt = (int)((a.I - s0) < sub ? (a.I - s0) : sub);
+  for (int64_t s0 = r0; s0 < r1; s0 += sub) {
+    const int cnt = (int)((r1 - s0) < sub ? (r1 - s0) : sub);
     __syncthreads();
-    for (int e = tid; e < cnt * R4; e += NT) {
-      const int k = e / cnt, rw = e - k * cnt;
-      double wv = 0.0;
-      if (k < R) {
-        wv = (double)a.W[s0 + rw + a.I * k];
-        if (a.do_fit && a.M) bsum += wv * ldv(a.M, s0 + rw + a.I * k, a.m_f64);
+    // element e = tid + NT*q of the cnt x R4 tile (q < 16: cnt * R4 <= 4096):
+    // k = e / cnt, rw = e % cnt, stepped. All of a thread's loads are issued
+    // before any is used, so the tile costs one memory round trip, not sixteen.
+    const int dk = NT / cnt, drw = NT - dk * cnt;
+    constexpr int QMAX = 4096 / NT;
+    const int k0 = tid / cnt, rw0 = tid - k0 * cnt;
+    float wf[QMAX];
+    {
+      int k = k0, rw = rw0;
+#pragma unroll
+      for (int q = 0; q < QMAX; ++q) {
+        // unconditional load from a valid index, zeroed afterwards: a guarded
+        // load would wait for its value at the branch join, one by one
+        const bool ok = tid + NT * q < cnt * R4 && k < R;
+        const float w = a.W[ok ? s0 + rw + a.I * (int64_t)k : 0];
+        wf[q] = ok ? w : 0.f;
+        k += dk;
+        rw += drw;
+        if (rw >= cnt) {
+          rw -= cnt;
+          ++k;
+        }
       }
-      work[rw * R4 + k] = wv;
+    }
+    if (fit) {
+      double mv[QMAX];
+      int k = k0, rw = rw0;
+#pragma unroll
+      for (int q = 0; q < QMAX; ++q) {
+        const bool ok = tid + NT * q < cnt * R4 && k < R;
+        const double m = ldv(a.M, ok ? s0 + rw + a.I * (int64_t)k : 0, a.m_f64);
+        mv[q] = ok ? m : 0.0;
+        k += dk;
+        rw += drw;
+        if (rw >= cnt) {
+          rw -= cnt;
+          ++k;
+        }
+      }
+#pragma unroll
+      for (int q = 0; q < QMAX; ++q) bsum += (double)wf[q] * mv[q];
+    }
+    {
+      int k = k0, rw = rw0;
+#pragma unroll
+      for (int q = 0; q < QMAX; ++q) {
+        if (tid + NT * q < cnt * R4) work[rw * R4 + k] = (double)wf[q];
+        k += dk;
+        rw += drw;
+        if (rw >= cnt) {
+          rw -= cnt;
+          ++k;
+        }
+      }
     }
     __syncthreads();
     if (active) {
-      for (int rw = ph; rw < cnt; rw += nph) {
-        const double* row = work + rw * R4;
+      // four rows per step: their 32 LDS reads are in flight together
+      int r = ph;
+      for (; r + 3 * nph < cnt; r += 4 * nph) {
+        double x[4][4], y[4][4];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+          const double* row = work + (r + u * nph) * R4;
+#pragma unroll
+          for (int i = 0; i < 4; ++i) {
+            x[u][i] = row[4 * bx + i];
+            y[u][i] = row[4 * by + i];
+          }
+        }
+#pragma unroll
+        for (int u = 0; u < 4; ++u)
+#pragma unroll
+          for (int i = 0; i < 4; ++i)
+#pragma unroll
+            for (int j = 0; j < 4; ++j) acc[i][j] += x[u][i] * y[u][j];
+      }
+      for (; r < cnt; r += nph) {
+        const double* row = work + r * R4;
         double x[4], y[4];
 #pragma unroll
         for (int i = 0; i < 4; ++i) {
@@ -494,23 +606,82 @@ __device__ __forceinline__ void finalize_small_body(const FinalizeArgs& a) {
   const double beta = block_sum(bsum, sh);
   __syncthreads();
   if (active) {
-    double* dst = work + ((size_t)ph * nblk + blk) * 16;
+    // layout [entry q][phase][block]: consecutive lanes write consecutive doubles
 #pragma unroll
     for (int i = 0; i < 4; ++i)
 #pragma unroll
-      for (int j = 0; j < 4; ++j) dst[i * 4 + j] = acc[i][j];
+      for (int j = 0; j < 4; ++j) work[((size_t)(i * 4 + j) * nph + ph) * nblk + blk] = acc[i][j];
   }
   __syncthreads();
-  for (int e = tid; e < RR; e += NT) {
-    const int x = e / R, y = e - x * R;
-    const int b = (x >> 2) * nb4 + (y >> 2), q = (x & 3) * 4 + (y & 3);
-    double v = 0.0;
-    for (int p = 0; p < nph; ++p) v += work[((size_t)p * nblk + b) * 16 + q];
-    Gh[e] = v;
+  {
+    const int dx = NT / R, dy = NT - dx * R;
+    int x = tid / R, y = tid - x * R;
+    for (int e = tid; e < RR; e += NT) {
+      const int b = (x >> 2) * nb4 + (y >> 2), q = (x & 3) * 4 + (y & 3);
+      const double* src = work + (size_t)q * nph * nblk + b;
+      double v = 0.0;
+      for (int p = 0; p < nph; ++p) v += src[(size_t)p * nblk];
+      out[e] = v;
+      x += dx;
+      y += dy;
+      if (y >= R) {
+        y -= R;
+        ++x;
+      }
+    }
   }
-  if (tid == 0) Gh[RR] = beta;
-  __syncthreads();
+  if (tid == 0) out[RR] = beta;
+}
 
+// The product of the Grams of the modes other than `mode` and `next_mode` (for
+// S of the next mode) and S of this mode (for gamma), into LDS.
+// (R <= 64: a thread's entries e = tid + NT*q, q < 16; each mode's loads are
+// issued together)
+__device__ __forceinline__ void fin_prefetch(const FinalizeArgs& a, double* P, double* Sm) {
+  const int RR = a.R * a.R;
+  constexpr int QM = kSmallMaxR * kSmallMaxR / NT;
+  if (a.next_mode >= 0) {
+    double v[QM];
+#pragma unroll
+    for (int q = 0; q < QM; ++q) v[q] = 1.0;
+    for (int k = 0; k < a.N; ++k) {
+      if (k == a.next_mode || k == a.mode) continue;
+      double t[QM];
+#pragma unroll
+      for (int q = 0; q < QM; ++q) {
+        const int e = threadIdx.x + NT * q;
+        t[q] = a.G[(int64_t)k * RR + (e < RR ? e : 0)];
+      }
+#pragma unroll
+      for (int q = 0; q < QM; ++q) v[q] *= t[q];
+    }
+#pragma unroll
+    for (int q = 0; q < QM; ++q) {
+      const int e = threadIdx.x + NT * q;
+      if (e < RR) P[e] = v[q];
+    }
+  }
+  if (a.do_fit) {
+    double t[QM];
+#pragma unroll
+    for (int q = 0; q < QM; ++q) {
+      const int e = threadIdx.x + NT * q;
+      t[q] = a.S[(int64_t)a.mode * RR + (e < RR ? e : 0)];
+    }
+#pragma unroll
+    for (int q = 0; q < QM; ++q) {
+      const int e = threadIdx.x + NT * q;
+      if (e < RR) Sm[e] = t[q];
+    }
+  }
+}
+
+// lambda = sqrt(diag Gh), the normalised Gram, S of the next mode and the fit,
+// from the raw Gram Gh[RR] and beta Gh[RR] in LDS. il (LDS, R doubles) receives
+// 1/lambda (0 for a zero column) so each entry costs two multiplications.
+__device__ void fin_tail_lds(const FinalizeArgs& a, const double* Gh, const double* P, const double* Sm,
+                             double* il, double* sh) {
+  const int R = a.R, RR = R * R, tid = threadIdx.x;
   if (a.gram_raw)
     for (int e = tid; e < RR; e += NT) a.gram_raw[e] = Gh[e];
   double* lamm = a.lam + (int64_t)a.mode * R;
@@ -518,16 +689,25 @@ __device__ __forceinline__ void finalize_small_body(const FinalizeArgs& a) {
     const double l = sqrt(Gh[k * R + k]);
     lamm[k] = l;
     if (a.set_model) a.lam_model[k] = l;
+    il[k] = l > 0.0 ? 1.0 / l : 0.0;
   }
+  __syncthreads();
   double* Gm = a.G + (int64_t)a.mode * RR;
+  double* Sn = a.next_mode >= 0 ? a.S + (int64_t)a.next_mode * RR : nullptr;
   double gp = 0.0;
+  const int dx = NT / R, dy = NT - dx * R;
+  int x = tid / R, y = tid - x * R;
   for (int e = tid; e < RR; e += NT) {
-    const int x = e / R, y = e - x * R;
-    const double lx = sqrt(Gh[x * R + x]), ly = sqrt(Gh[y * R + y]);
-    const double g = (lx > 0.0 && ly > 0.0) ? Gh[e] / (lx * ly) : 0.0;
+    const double g = Gh[e] * il[x] * il[y];
     Gm[e] = g;
-    if (a.next_mode >= 0) a.S[(int64_t)a.next_mode * RR + e] = P[e] * g;
+    if (Sn) Sn[e] = P[e] * g;
     if (a.do_fit) gp += Sm[e] * Gh[e];
+    x += dx;
+    y += dy;
+    if (y >= R) {
+      y -= R;
+      ++x;
+    }
   }
   if (a.do_fit) {
     // gamma = 1^T (S^(mode) * G_hat) 1 with G_hat the Gram of the unnormalised factor
@@ -542,6 +722,67 @@ __device__ __forceinline__ void finalize_small_body(const FinalizeArgs& a) {
       *a.iter_counter = it + 1;
     }
   }
+}
+
+// One row chunk: one work-group does everything.
+__device__ __forceinline__ void finalize_small_body(const FinalizeArgs& a) {
+  extern __shared__ double lds[];
+  __shared__ double sh[NT / 64];
+  const int RR = a.R * a.R;
+  double* Gh = lds;          // RR + 1
+  double* P = Gh + RR + 1;   // RR
+  double* Sm = P + RR;       // RR
+  double* il = Sm + RR;      // 64
+  double* work = il + kSmallMaxR;
+  fin_prefetch(a, P, Sm);
+  gram_rows_blocked(a, 0, a.I, work, sh, Gh);
+  __syncthreads();
+  fin_tail_lds(a, Gh, P, Sm, il, sh);
+}
+
+// Several row chunks: chunk bx's Gram into partial[bx], then one work-group sums
+// the partials in chunk order and finishes.
+__device__ __forceinline__ void gram_chunks_blocked_body(const FinalizeArgs& a, int bx) {
+  extern __shared__ double lds[];
+  __shared__ double sh[NT / 64];
+  const int64_t r0 = (int64_t)bx * a.rows_per_chunk;
+  const int64_t r1 = r0 + a.rows_per_chunk < a.I ? r0 + a.rows_per_chunk : a.I;
+  gram_rows_blocked(a, r0, r1, lds, sh, a.partial + (size_t)bx * (a.R * a.R + 1));
+}
+__device__ __forceinline__ void finalize_tail_blocked_body(const FinalizeArgs& a) {
+  extern __shared__ double lds[];
+  __shared__ double sh[NT / 64];
+  const int RR = a.R * a.R;
+  double* Gh = lds;
+  double* P = Gh + RR + 1;
+  double* Sm = P + RR;
+  double* il = Sm + RR;
+  fin_prefetch(a, P, Sm);
+  // chunk-major: each chunk's loads of all this thread's entries are issued
+  // together, then added in chunk order (RR + 1 <= 4097 = 17 x NT)
+  constexpr int EPT = (kSmallMaxR * kSmallMaxR + 1 + NT - 1) / NT;
+  double v[EPT];
+#pragma unroll
+  for (int q = 0; q < EPT; ++q) v[q] = 0.0;
+  for (int c = 0; c < a.nchunks; ++c) {
+    const double* pc = a.partial + (size_t)c * (RR + 1);
+    double t[EPT];
+#pragma unroll
+    for (int q = 0; q < EPT; ++q) {
+      const int e = threadIdx.x + NT * q;
+      const double u = pc[e < RR + 1 ? e : 0];
+      t[q] = e < RR + 1 ? u : 0.0;
+    }
+#pragma unroll
+    for (int q = 0; q < EPT; ++q) v[q] += t[q];
+  }
+#pragma unroll
+  for (int q = 0; q < EPT; ++q) {
+    const int e = threadIdx.x + NT * q;
+    if (e < RR + 1) Gh[e] = v[q];
+  }
+  __syncthreads();
+  fin_tail_lds(a, Gh, P, Sm, il, sh);
 }
 
 __global__ __launch_bounds__(NT) void finalize_small_kernel(FinalizeArgs a) { finalize_small_body(a); }
@@ -567,6 +808,10 @@ __device__ __forceinline__ void finalize_tail_body(const FinalizeArgs& a) {
 __global__ __launch_bounds__(NT) void finalize_fused_kernel(FinalizeArgs a) { finalize_fused_body(a); }
 __global__ __launch_bounds__(NT) void gram_chunks_kernel(FinalizeArgs a) { gram_chunks_body(a, blockIdx.x); }
 __global__ __launch_bounds__(NT) void finalize_tail_kernel(FinalizeArgs a) { finalize_tail_body(a); }
+__global__ __launch_bounds__(NT) void gram_chunks_blocked_kernel(FinalizeArgs a) {
+  gram_chunks_blocked_body(a, blockIdx.x);
+}
+__global__ __launch_bounds__(NT) void finalize_tail_blocked_kernel(FinalizeArgs a) { finalize_tail_blocked_body(a); }
 
 // Split-K sum of partial-MTTKRP partials: T(m, col0 + r) = sum over splits (in
 // split order) of part[(sp*RP + r)*Mpad + m], one thread per output (coalesced along m).
@@ -622,13 +867,24 @@ __device__ __forceinline__ void small_op(const KOp& op, int bx, int by) {
       }
       break;
     case K_UPDATE:
-      if (op.variant == 1) update_body<1>(op.u.up, bx);
-      else update_body<2>(op.u.up, bx);
+      switch (op.variant) {
+        case 1: update_body<1>(op.u.up, bx); break;
+        case 2: update_body<2>(op.u.up, bx); break;
+        case 16: update_reg_body<16>(op.u.up, bx); break;
+        case 32: update_reg_body<32>(op.u.up, bx); break;
+        default: update_reg_body<64>(op.u.up, bx); break;
+      }
       break;
     case K_FIN_SMALL: finalize_small_body(op.u.fin); break;
     case K_FIN_FUSED: finalize_fused_body(op.u.fin); break;
-    case K_GRAM_CHUNKS: gram_chunks_body(op.u.fin, bx); break;
-    case K_FIN_TAIL: finalize_tail_body(op.u.fin); break;
+    case K_GRAM_CHUNKS:
+      if (op.variant) gram_chunks_blocked_body(op.u.fin, bx);
+      else gram_chunks_body(op.u.fin, bx);
+      break;
+    case K_FIN_TAIL:
+      if (op.variant) finalize_tail_blocked_body(op.u.fin);
+      else finalize_tail_body(op.u.fin);
+      break;
     default: break;
   }
 }
@@ -776,9 +1032,15 @@ hipError_t mttv_lead_launch(const MttvArgs& a, const Sink& sk) {
 
 hipError_t update_launch(const UpdateArgs& a, const Sink& sk) {
   if (a.I <= 0) return hipSuccess;
-  const size_t lds = ((size_t)a.R * a.R + a.R) * sizeof(double);
   const int rpb = NT / 64;
   const unsigned g = (unsigned)((a.I + rpb - 1) / rpb);
+  if (a.R <= 64) {
+    const int rb = a.R <= 16 ? 16 : (a.R <= 32 ? 32 : 64);
+    const void* k = rb == 16 ? (const void*)update_reg_kernel<16>
+                             : (rb == 32 ? (const void*)update_reg_kernel<32> : (const void*)update_reg_kernel<64>);
+    return record_or_launch(sk, K_UPDATE, rb, g, 1, 0, k, &a, sizeof(a));
+  }
+  const size_t lds = ((size_t)a.R * a.R + a.R) * sizeof(double);
   const int vpl = a.R <= 64 ? 1 : 2;
   const void* k = vpl == 1 ? (const void*)update_kernel<1> : (const void*)update_kernel<2>;
   return record_or_launch(sk, K_UPDATE, vpl, g, 1, lds, k, &a, sizeof(a));
@@ -834,10 +1096,13 @@ hipError_t batch_launch_small(const BItem* items, const int* count, const KOp* o
 }
 
 // Row chunks for the Gram: one block when the work is small (no second launch),
-// otherwise chunks of about 2^19 multiply-adds each (at most 64).
+// otherwise chunks of about 2^18 (register-blocked, R <= 64) or 2^19
+// multiply-adds each, at most 64.
 int finalize_chunks(int64_t I, int R, int* rows_per_chunk) {
-  const int64_t work = I * (int64_t)R * R;
-  int64_t chunks = (work + (1 << 19) - 1) >> 19;
+  const int shift = 19;
+  const int64_t R4 = R <= kSmallMaxR ? gram_r4(R) : R;
+  const int64_t work = I * R4 * R4;
+  int64_t chunks = (work + (1ll << shift) - 1) >> shift;
   if (chunks > 64) chunks = 64;
   if (chunks > I) chunks = I;
   if (chunks < 1) chunks = 1;
@@ -849,17 +1114,22 @@ int finalize_chunks(int64_t I, int R, int* rows_per_chunk) {
 }
 
 hipError_t finalize_launch(const FinalizeArgs& a, const Sink& sk) {
-  size_t lds = (size_t)fin_sub_rows(a.R) * a.R * sizeof(double);
-  const size_t need = ((size_t)a.R * a.R + 1) * sizeof(double);
-  if (need > lds) lds = need;
-  if (a.nchunks <= 1 && a.R <= kSmallMaxR) {
-    const int R4 = (a.R + 3) & ~3;
-    const size_t RR = (size_t)a.R * a.R;
-    const size_t sub = 4096 / R4;
-    const size_t stage = sub * R4, phases = (size_t)NT * 16;
-    const size_t bytes = (3 * RR + 1 + (stage > phases ? stage : phases)) * sizeof(double);
-    return record_or_launch(sk, K_FIN_SMALL, 0, 1, 1, bytes, (const void*)finalize_small_kernel, &a, sizeof(a));
+  const size_t RR = (size_t)a.R * a.R;
+  if (a.R <= kSmallMaxR) {
+    if (a.nchunks <= 1) {
+      const size_t bytes = (3 * RR + 1 + kSmallMaxR + gram_work_doubles(a.R)) * sizeof(double);
+      return record_or_launch(sk, K_FIN_SMALL, 0, 1, 1, bytes, (const void*)finalize_small_kernel, &a, sizeof(a));
+    }
+    hipError_t e = record_or_launch(sk, K_GRAM_CHUNKS, 1, (unsigned)a.nchunks, 1,
+                                    gram_work_doubles(a.R) * sizeof(double),
+                                    (const void*)gram_chunks_blocked_kernel, &a, sizeof(a));
+    if (e != hipSuccess) return e;
+    return record_or_launch(sk, K_FIN_TAIL, 1, 1, 1, (3 * RR + 1 + kSmallMaxR) * sizeof(double),
+                            (const void*)finalize_tail_blocked_kernel, &a, sizeof(a));
   }
+  size_t lds = (size_t)fin_sub_rows(a.R) * a.R * sizeof(double);
+  const size_t need = (RR + 1) * sizeof(double);
+  if (need > lds) lds = need;
   if (a.nchunks <= 1)
     return record_or_launch(sk, K_FIN_FUSED, 0, 1, 1, lds, (const void*)finalize_fused_kernel, &a, sizeof(a));
   hipError_t e = record_or_launch(sk, K_GRAM_CHUNKS, 0, (unsigned)a.nchunks, 1, lds,
