@@ -305,10 +305,12 @@ __device__ __forceinline__ void pm_left_16_body(const PmArgs& a, int bx, int by,
 #pragma unroll
   for (int nb = 0; nb < NB; ++nb)
 #pragma unroll
-    for (int v = 0; v < 4; ++v)
+    for (int v = 0; v < 4; ++v) {
+      double o[TR];
 #pragma unroll
-      for (int tt = 0; tt < TR; ++tt)
-        pm_store(a, direct, Mtot, Mpad, RP, by, 16 * nb + li, mw + TR * (4 * lq + v) + tt, (double)acc[tt * NB + nb][v]);
+      for (int tt = 0; tt < TR; ++tt) o[tt] = (double)acc[tt * NB + nb][v];
+      pm_store_rows<TR>(a, direct, Mtot, Mpad, RP, by, 16 * nb + li, mw + TR * (4 * lq + v), o);
+    }
 }
 
 // ----------------------------------------------------------------------------
@@ -493,10 +495,12 @@ __device__ __forceinline__ void pm_right_16_body(const PmArgs& a, int bx, int by
 #pragma unroll
   for (int g = 0; g < MC; ++g)
 #pragma unroll
-    for (int nb = 0; nb < NB; ++nb)
+    for (int nb = 0; nb < NB; ++nb) {
+      double o[4];
 #pragma unroll
-      for (int v = 0; v < 4; ++v)
-        pm_store(a, direct, Mtot, Mpad, RP, by, 16 * nb + li, cw + 16 * g + 4 * lq + v, (double)acc[g * NB + nb][v]);
+      for (int v = 0; v < 4; ++v) o[v] = (double)acc[g * NB + nb][v];
+      pm_store_rows<4>(a, direct, Mtot, Mpad, RP, by, 16 * nb + li, cw + 16 * g + 4 * lq, o);
+    }
 }
 
 // Rows per left wave = 16 * TR, columns per right wave = 16 * MC.

@@ -133,18 +133,43 @@ __device__ __forceinline__ void wave_reduce_k(double (&acc)[NACC][4], double* ld
   }
 }
 
-// Store one output element: directly into T (FP64 or FP32) or into the split
-// partials of split `by`.
-__device__ __forceinline__ void pm_store(const PmArgs& a, bool direct, int64_t Mtot, int64_t Mpad, int RP, int by,
-                                         int r, int64_t mm, double o) {
+// Store L consecutive output rows m0 .. m0+L-1 of rank column r (values o[]):
+// 16-byte stores when the run is in range and aligned (rows are contiguous in
+// T and in the partials), element stores otherwise.
+template <int L>
+__device__ __forceinline__ void pm_store_rows(const PmArgs& a, bool direct, int64_t Mtot, int64_t Mpad, int RP,
+                                              int by, int r, int64_t m0, const double (&o)[L]) {
+  typedef double d2 __attribute__((ext_vector_type(2)));
+  typedef float fv2 __attribute__((ext_vector_type(2)));
   if (direct) {
-    if (r < a.R && mm < Mtot) {
-      const int64_t idx = mm + Mtot * (int64_t)(a.col0 + r);
-      if (a.t_f64) ((double*)a.T)[idx] = o;
-      else ((float*)a.T)[idx] = (float)o;
+    if (r >= a.R) return;
+    const int64_t base = m0 + Mtot * (int64_t)(a.col0 + r);
+    if (m0 + L <= Mtot && (base % L) == 0) {
+      if (a.t_f64) {
+        d2* p = (d2*)((double*)a.T + base);
+#pragma unroll
+        for (int i = 0; i < L / 2; ++i) p[i] = d2{o[2 * i], o[2 * i + 1]};
+      } else if (L >= 4) {
+        f4* p = (f4*)((float*)a.T + base);
+#pragma unroll
+        for (int i = 0; i < L / 4; ++i)
+          p[i] = f4{(float)o[4 * i], (float)o[4 * i + 1], (float)o[4 * i + 2], (float)o[4 * i + 3]};
+      } else {
+        *(fv2*)((float*)a.T + base) = fv2{(float)o[0], (float)o[1]};
+      }
+    } else {
+#pragma unroll
+      for (int i = 0; i < L; ++i)
+        if (m0 + i < Mtot) {
+          if (a.t_f64) ((double*)a.T)[base + i] = o[i];
+          else ((float*)a.T)[base + i] = (float)o[i];
+        }
     }
   } else {
-    a.partial[((size_t)by * RP + r) * Mpad + mm] = o;
+    // Mpad is a multiple of the M tile and m0 of L: aligned
+    d2* p = (d2*)(a.partial + ((size_t)by * RP + r) * Mpad + m0);
+#pragma unroll
+    for (int i = 0; i < L / 2; ++i) p[i] = d2{o[2 * i], o[2 * i + 1]};
   }
 }
 

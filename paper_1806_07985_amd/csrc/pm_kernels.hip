@@ -190,10 +190,12 @@ __device__ __forceinline__ void pm_left_f32_body(const PmArgs& a, int bx, int by
 #pragma unroll
     for (int nb = 0; nb < NB; ++nb)
 #pragma unroll
-      for (int v = 0; v < 4; ++v)
+      for (int v = 0; v < 4; ++v) {
+        double o[TR];
 #pragma unroll
-        for (int tt = 0; tt < TR; ++tt)
-          pm_store(a, direct, Mtot, Mpad, RP, by, 16 * nb + li, mw + TR * (4 * lq + v) + tt, acc[tt * NB + nb][v]);
+        for (int tt = 0; tt < TR; ++tt) o[tt] = acc[tt * NB + nb][v];
+        pm_store_rows<TR>(a, direct, Mtot, Mpad, RP, by, 16 * nb + li, mw + TR * (4 * lq + v), o);
+      }
   }
 }
 
@@ -353,10 +355,12 @@ __device__ __forceinline__ void pm_right_f32_body(const PmArgs& a, int bx, int b
 #pragma unroll
     for (int g = 0; g < MC; ++g)
 #pragma unroll
-      for (int nb = 0; nb < NB; ++nb)
+      for (int nb = 0; nb < NB; ++nb) {
+        double o[4];
 #pragma unroll
-        for (int v = 0; v < 4; ++v)
-          pm_store(a, direct, Mtot, Mpad, RP, by, 16 * nb + li, cw + 16 * g + 4 * lq + v, acc[g * NB + nb][v]);
+        for (int v = 0; v < 4; ++v) o[v] = acc[g * NB + nb][v];
+        pm_store_rows<4>(a, direct, Mtot, Mpad, RP, by, 16 * nb + li, cw + 16 * g + 4 * lq, o);
+      }
   }
 }
 
