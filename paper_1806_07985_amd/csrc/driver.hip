@@ -952,7 +952,7 @@ int batch_build(nncp_batch* B) {
       size_t lds = 0;
       for (size_t i = 0; i < all.size(); ++i) {
         const KOp& o = all[i];
-        if (o.stage != key || kfamily(o.kind) != fam) continue;
+        if (o.stage != key || kfamily(o.kind, o.variant) != fam) continue;
         for (unsigned by = 0; by < o.gy; ++by)
           for (unsigned bx = 0; bx < o.gx; ++bx) items.push_back(BItem{(int)i, (int)bx, (int)by});
         lds = std::max(lds, (size_t)o.lds);
@@ -987,6 +987,7 @@ int batch_build(nncp_batch* B) {
     const int* cnt = B->d_counts + l.count_idx;
     if (l.family == KF_PM_F32) e = batch_launch_pm_f32(it, cnt, B->d_ops, l.grid, l.lds, B->cap);
     else if (l.family == KF_PM_16) e = batch_launch_pm_16(it, cnt, B->d_ops, l.grid, l.lds, B->cap);
+    else if (l.family == KF_PM_16J1) e = batch_launch_pm_16j1(it, cnt, B->d_ops, l.grid, l.lds, B->cap);
     else e = batch_launch_small(it, cnt, B->d_ops, l.grid, l.lds, B->cap);
     if (e != hipSuccess) break;
   }

@@ -73,6 +73,7 @@ struct PmLaunch {
   int mtiles;
   int nsplit;
   int I1, I1pad, i1blk, n_i1blk, jblk, n_jblk, fold, istages;
+  int j1;        // 16-bit right node with J == 1: the specialised kernel (column scale at the end)
   int64_t J;
   size_t lds_bytes;
   size_t partial_doubles;
@@ -92,7 +93,7 @@ hipError_t pm_launch(const PmLaunch& L, const PmArgs& a, const Sink& sk);
 // per-dtype kernels (pm_kernels.hip, pm16_kernels.hip)
 int pm_f32_wave_rows(int side, int nb);
 hipError_t pm_launch_f32(const PmLaunch& L, const PmArgs& a, const Sink& sk);
-int pm_16_wave_rows(int side, int nb);
+int pm_16_wave_rows(int side, int nb, int j1 = 0);
 int pm_16_kstep(int side);
 hipError_t pm_launch_16(const PmLaunch& L, const PmArgs& a, const Sink& sk);
 
@@ -209,9 +210,16 @@ enum KKind : int {
   K_GRAM_CHUNKS = 10,
   K_FIN_TAIL = 11
 };
-// Kernel families: one persistent batched kernel each.
-enum KFamily : int { KF_PM_F32 = 0, KF_PM_16 = 1, KF_SMALL = 2, KF_COUNT = 3 };
-inline int kfamily(int kind) { return kind == K_PM_F32 ? KF_PM_F32 : ((kind == K_PM_16 || kind == K_PACK16) ? KF_PM_16 : KF_SMALL); }
+// Kernel families: one persistent batched kernel each. The 16-bit right-node
+// kernel for J == 1 (variant >= 100000) has a family of its own: it needs ~480
+// registers, and in one kernel with the other bodies it would make them spill.
+enum KFamily : int { KF_PM_F32 = 0, KF_PM_16 = 1, KF_SMALL = 2, KF_PM_16J1 = 3, KF_COUNT = 4 };
+inline int kfamily(int kind, int variant) {
+  if (kind == K_PM_F32) return KF_PM_F32;
+  if (kind == K_PM_16) return variant >= 100000 ? KF_PM_16J1 : KF_PM_16;
+  if (kind == K_PACK16) return KF_PM_16;
+  return KF_SMALL;
+}
 
 struct KOp {
   int kind;
@@ -266,6 +274,8 @@ hipError_t batch_launch_pm_16(const BItem* items, const int* count, const KOp* o
                               hipStream_t st);
 hipError_t batch_launch_small(const BItem* items, const int* count, const KOp* ops, unsigned grid, size_t lds,
                               hipStream_t st);
+hipError_t batch_launch_pm_16j1(const BItem* items, const int* count, const KOp* ops, unsigned grid, size_t lds,
+                                hipStream_t st);
 
 // Column scale of a Khatri-Rao operand, prod_j 1/lam[mode_j][r] (device code).
 __device__ __forceinline__ double krp_colscale(const KrpDesc& k, int r) {

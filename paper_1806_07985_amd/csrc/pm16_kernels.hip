@@ -320,8 +320,12 @@ __device__ __forceinline__ void pm_left_16_body(const PmArgs& a, int bx, int by,
 // The work-group walks `istages` i1 blocks (j inside each), restaging LDS
 // between them; istages > 1 only with every wave on its own columns (WM = 4).
 // ----------------------------------------------------------------------------
-template <int DT, int NB, int MC, int WM, bool FAST, int D>
+template <int DT, int NB, int MC, int WM, bool FAST, int D, bool J1 = false>
 __device__ __forceinline__ void pm_right_16_body(const PmArgs& a, int bx, int by, int gx) {
+  // J1: the remaining contracted extent is 1, so the Khatri-Rao scale is one
+  // factor per column: the MFMA sums run over all of K (FP32) and are scaled
+  // once at the end; no separate accumulators (every wave owns its columns).
+  static_assert(!J1 || WM == 4, "J1 needs one wave per column range");
   constexpr int RP = NB * 16;
   constexpr int WK = 4 / WM;
   constexpr int KS = 64;
@@ -443,7 +447,7 @@ __device__ __forceinline__ void pm_right_16_body(const PmArgs& a, int bx, int by
           c32[g][nb] = T16<DT>::mfma(__builtin_bit_cast(u4, A[g][h]), Bl[nb], c32[g][nb]);
     }
     --left;
-    if (tc + 1 == S1C || left == 0) {
+    if (!J1 && (tc + 1 == S1C || left == 0)) {
 #pragma unroll
       for (int nb = 0; nb < NB; ++nb) {
         const float s = sc[jc * RP + 16 * nb + li];
@@ -488,7 +492,18 @@ __device__ __forceinline__ void pm_right_16_body(const PmArgs& a, int bx, int by
   for (int d = 0; d < D - 1; ++d)
     if (s + d < se) compute(A[d]);
 
-  pm16_reduce_store<NACC>(a, acc, lds_d, wk, wm, WK);
+  if (J1) {
+#pragma unroll
+    for (int nb = 0; nb < NB; ++nb) {
+      const float s = sc[16 * nb + li];
+#pragma unroll
+      for (int g = 0; g < MC; ++g)
+#pragma unroll
+        for (int e = 0; e < 4; ++e) acc[g * NB + nb][e] = c32[g][nb][e] * s;
+    }
+  } else {
+    pm16_reduce_store<NACC>(a, acc, lds_d, wk, wm, WK);
+  }
   if (wk != 0) return;
   const bool direct = (a.nsplit == 1);
   const int64_t Mpad = (int64_t)gx * mtile;
@@ -506,6 +521,8 @@ __device__ __forceinline__ void pm_right_16_body(const PmArgs& a, int bx, int by
 // Rows per left wave = 16 * TR, columns per right wave = 16 * MC.
 constexpr int left_tr16(int nb) { return nb >= 4 ? 4 : 8; }
 constexpr int right_mc16(int nb) { return nb >= 4 ? 4 : 4; }
+constexpr int right_mc16_j1(int nb) { return 8; }
+constexpr int right_pf16_j1(int nb) { return nb >= 4 ? 2 : 3; }
 constexpr int left_pf16(int nb) { return nb >= 4 ? 3 : 3; }
 constexpr int right_pf16(int nb) { return nb >= 4 ? 3 : 3; }
 
@@ -513,19 +530,32 @@ template <int DT, int NB, int TR, int WM, bool FAST, int D>
 __global__ __launch_bounds__(NT, 1) void pm_left_16(PmArgs a) {
   pm_left_16_body<DT, NB, TR, WM, FAST, D>(a, blockIdx.x, blockIdx.y, gridDim.x);
 }
-template <int DT, int NB, int MC, int WM, bool FAST, int D>
+template <int DT, int NB, int MC, int WM, bool FAST, int D, bool J1>
 __global__ __launch_bounds__(NT, 1) void pm_right_16(PmArgs a) {
-  pm_right_16_body<DT, NB, MC, WM, FAST, D>(a, blockIdx.x, blockIdx.y, gridDim.x);
+  pm_right_16_body<DT, NB, MC, WM, FAST, D, J1>(a, blockIdx.x, blockIdx.y, gridDim.x);
 }
 
 template <int DT, int NB, int WM, bool VEC>
 const void* kernel16(int side) {
   if (side == 0) return (const void*)pm_left_16<DT, NB, left_tr16(NB), WM, VEC, left_pf16(NB)>;
-  return (const void*)pm_right_16<DT, NB, right_mc16(NB), WM, VEC, right_pf16(NB)>;
+  return (const void*)pm_right_16<DT, NB, right_mc16(NB), WM, VEC, right_pf16(NB), false>;
+}
+template <int DT, int NB, bool VEC>
+const void* kernel16_j1() {
+  return (const void*)pm_right_16<DT, NB, right_mc16_j1(NB), 4, VEC, right_pf16_j1(NB), true>;
 }
 
 template <int DT>
-const void* select16(int side, int nb, int wm, bool vec) {
+const void* select16(int side, int nb, int wm, bool vec, bool j1) {
+  if (j1) {  // planned only where the unmasked 16-byte path applies
+    if (side != 1 || wm != 4 || !vec) return nullptr;
+    switch (nb) {
+      case 1: return kernel16_j1<DT, 1, true>();
+      case 2: return kernel16_j1<DT, 2, true>();
+      case 4: return kernel16_j1<DT, 4, true>();
+      default: return nullptr;
+    }
+  }
   switch (nb * 100 + wm * 10 + (vec ? 1 : 0)) {
     case 141: return kernel16<DT, 1, 4, true>(side);
     case 140: return kernel16<DT, 1, 4, false>(side);
@@ -547,6 +577,21 @@ template <int DT, int NB, int WM, bool VEC>
 __device__ __forceinline__ void body16(int side, const PmArgs& a, int bx, int by, int gx) {
   if (side == 0) pm_left_16_body<DT, NB, left_tr16(NB), WM, VEC, left_pf16(NB)>(a, bx, by, gx);
   else pm_right_16_body<DT, NB, right_mc16(NB), WM, VEC, right_pf16(NB)>(a, bx, by, gx);
+}
+template <int DT, int NB, bool VEC>
+__device__ __forceinline__ void body16_j1(const PmArgs& a, int bx, int by, int gx) {
+  pm_right_16_body<DT, NB, right_mc16_j1(NB), 4, VEC, right_pf16_j1(NB), true>(a, bx, by, gx);
+}
+
+// variant = j1*100000 + bf16*10000 + side*1000 + nb*100 + wm*10 + vec
+template <int DT>
+__device__ __forceinline__ void dispatch16_j1(int v, const PmArgs& a, int bx, int by, int gx) {
+  switch ((v % 1000) / 100) {
+    case 1: body16_j1<DT, 1, true>(a, bx, by, gx); break;
+    case 2: body16_j1<DT, 2, true>(a, bx, by, gx); break;
+    case 4: body16_j1<DT, 4, true>(a, bx, by, gx); break;
+    default: break;
+  }
 }
 
 template <int DT>
@@ -580,7 +625,7 @@ __global__ __launch_bounds__(NT, 1) void pm16_batch_kernel(const BItem* __restri
     if (op.kind == K_PACK16) {
       if (op.variant) pm16_pack_body<NNCP_BF16>(op.u.pk, it.bx);
       else pm16_pack_body<NNCP_F16>(op.u.pk, it.bx);
-    } else if (op.variant >= 10000) {
+    } else if ((op.variant / 10000) % 10) {
       dispatch16<NNCP_BF16>(op.variant, op.u.pm, it.bx, it.by, op.gx);
     } else {
       dispatch16<NNCP_F16>(op.variant, op.u.pm, it.bx, it.by, op.gx);
@@ -589,15 +634,31 @@ __global__ __launch_bounds__(NT, 1) void pm16_batch_kernel(const BItem* __restri
   }
 }
 
+// The J == 1 right-node tiles of 16-bit tensors (a family of their own).
+__global__ __launch_bounds__(NT, 1) void pm16j1_batch_kernel(const BItem* __restrict__ items,
+                                                             const int* __restrict__ count,
+                                                             const KOp* __restrict__ ops) {
+  const int n = *count;
+  for (int i = blockIdx.x; i < n; i += gridDim.x) {
+    const BItem it = items[i];
+    const KOp& op = ops[it.op];
+    if ((op.variant / 10000) % 10) dispatch16_j1<NNCP_BF16>(op.variant, op.u.pm, it.bx, it.by, op.gx);
+    else dispatch16_j1<NNCP_F16>(op.variant, op.u.pm, it.bx, it.by, op.gx);
+    __syncthreads();
+  }
+}
+
 size_t reduce_lds16(int side, int nb, int wm) {
-  if (wm >= 4) return 0;
+  if (wm >= 4) return 0;  // (also every J1 launch: one wave per column range)
   const int nacc = side == 0 ? left_tr16(nb) * nb : right_mc16(nb) * nb;
   return (size_t)wm * nacc * 4 * 64 * sizeof(double);
 }
 
 }  // namespace
 
-int pm_16_wave_rows(int side, int nb) { return side == 0 ? 16 * left_tr16(nb) : 16 * right_mc16(nb); }
+int pm_16_wave_rows(int side, int nb, int j1) {
+  return side == 0 ? 16 * left_tr16(nb) : 16 * (j1 ? right_mc16_j1(nb) : right_mc16(nb));
+}
 int pm_16_kstep(int side) { return side == 0 ? 32 : 64; }
 
 static bool vec16(const PmArgs& a, int side) {
@@ -613,10 +674,11 @@ hipError_t pm_launch_16(const PmLaunch& L, const PmArgs& a, const Sink& sk) {
   if (!a.hpack || !a.hscale) return hipErrorInvalidValue;
   const bool bf = L.dtype == NNCP_BF16;
   PackArgs pa{a.krp.f[0], a.I1, a.I1pad, a.R, a.col0, RP, a.hpack, a.hscale};
-  const int wm = L.mtile / pm_16_wave_rows(L.side, L.nb);
+  const int wm = L.mtile / pm_16_wave_rows(L.side, L.nb, L.j1);
   const bool v = vec16(a, L.side);
-  const int variant = (bf ? 10000 : 0) + L.side * 1000 + L.nb * 100 + wm * 10 + (v ? 1 : 0);
-  const void* k = bf ? select16<NNCP_BF16>(L.side, L.nb, wm, v) : select16<NNCP_F16>(L.side, L.nb, wm, v);
+  const int variant = (L.j1 ? 100000 : 0) + (bf ? 10000 : 0) + L.side * 1000 + L.nb * 100 + wm * 10 + (v ? 1 : 0);
+  const void* k = bf ? select16<NNCP_BF16>(L.side, L.nb, wm, v, L.j1 != 0)
+                     : select16<NNCP_F16>(L.side, L.nb, wm, v, L.j1 != 0);
   if (!k) return hipErrorInvalidValue;
   size_t lds = L.lds_bytes;
   if (reduce_lds16(L.side, L.nb, wm) > lds) lds = reduce_lds16(L.side, L.nb, wm);
@@ -642,8 +704,8 @@ hipError_t pm_launch_16(const PmLaunch& L, const PmArgs& a, const Sink& sk) {
   else hipLaunchKernelGGL(pm16_pack_kernel<NNCP_F16>, dim3(RP), dim3(256), 0, sk.st, pa);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
-  static bool attr_done[2][2][3][2][2] = {};
-  bool& done = attr_done[bf][L.side][L.nb == 1 ? 0 : (L.nb == 2 ? 1 : 2)][wm == 4][v];
+  static bool attr_done[2][2][2][3][2][2] = {};
+  bool& done = attr_done[L.j1 != 0][bf][L.side][L.nb == 1 ? 0 : (L.nb == 2 ? 1 : 2)][wm == 4][v];
   if (!done) {
     if (hipFuncSetAttribute(k, hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024) != hipSuccess)
       (void)hipGetLastError();
@@ -651,6 +713,19 @@ hipError_t pm_launch_16(const PmLaunch& L, const PmArgs& a, const Sink& sk) {
   }
   void* args[] = {(void*)&a};
   return hipLaunchKernel(k, dim3(L.mtiles, L.nsplit), dim3(NT), args, lds, sk.st);
+}
+
+hipError_t batch_launch_pm_16j1(const BItem* items, const int* count, const KOp* ops, unsigned grid, size_t lds,
+                                hipStream_t st) {
+  static bool attr = [] {
+    (void)hipFuncSetAttribute((const void*)pm16j1_batch_kernel, hipFuncAttributeMaxDynamicSharedMemorySize,
+                              160 * 1024);
+    (void)hipGetLastError();
+    return true;
+  }();
+  (void)attr;
+  hipLaunchKernelGGL(pm16j1_batch_kernel, dim3(grid), dim3(NT), lds, st, items, count, ops);
+  return hipGetLastError();
 }
 
 hipError_t batch_launch_pm_16(const BItem* items, const int* count, const KOp* ops, unsigned grid, size_t lds,

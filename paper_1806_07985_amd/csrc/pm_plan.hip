@@ -53,7 +53,14 @@ PmLaunch pm_plan(int side, int dtype, int64_t IL, int64_t IR, int I1, int R, int
   const int64_t Mtot = side == 0 ? IL : IR;
   const int64_t Ktot = side == 0 ? IR : IL;
   const int ks = f32 ? pm_f32_kstep(side) : pm_16_kstep(side);
-  const int wave_rows = f32 ? pm_f32_wave_rows(side, L.nb) : pm_16_wave_rows(side, L.nb);
+  // a tall 16-bit right node with J == 1 uses the specialised kernel (wider waves)
+  // (only where the unmasked path applies: column starts and I1 fit the
+  // 16-byte loads; the tensor base must then be 16-byte aligned at launch)
+  L.j1 = (!f32 && side == 1 && Ktot / I1 == 1 && IL % 8 == 0 && I1 % pm_16_kstep(1) == 0 &&
+          cdiv(Mtot, 4 * pm_16_wave_rows(1, L.nb, 1)) >= 64)
+             ? 1
+             : 0;
+  const int wave_rows = f32 ? pm_f32_wave_rows(side, L.nb) : pm_16_wave_rows(side, L.nb, L.j1);
   const int64_t target = target_wgs(IL * IR * (f32 ? 4 : 2), wg_kib);
 
   L.I1 = I1;
@@ -79,6 +86,7 @@ PmLaunch pm_plan(int side, int dtype, int64_t IL, int64_t IR, int I1, int R, int
     }();
     if (env_wm == 1 || env_wm == 4) wm = env_wm;
   }
+  if (L.j1) wm = 4;
   L.mtile = wm * wave_rows;
   L.mtiles = (int)cdiv(Mtot, L.mtile);
 
@@ -92,7 +100,10 @@ PmLaunch pm_plan(int side, int dtype, int64_t IL, int64_t IR, int I1, int R, int
   const int64_t steps_per_j = L.i1blk / ks;
   int64_t want_splits = target / L.mtiles;
   if (want_splits < 1) want_splits = 1;
-  int64_t n_jblk = cdiv(want_splits, n_i1grp);
+  // never more groups than the target: a second partial round of groups (one
+  // group fills a CU's LDS) would double the kernel's time for a few groups
+  int64_t n_jblk = want_splits / n_i1grp;
+  if (n_jblk < 1) n_jblk = 1;
   // each wave should own a few k-steps, and the per-(j, column) scales fit LDS
   const int64_t min_j = cdiv(8 * (4 / wm), steps_per_j);
   int64_t jblk = cdiv(L.J, n_jblk < 1 ? 1 : n_jblk);

@@ -24,6 +24,7 @@ JOBS = [
     ((64, 48, 40), 24, "hals", 2, "f16", 16),
     ((50, 33, 17), 50, "hals", 0, "f32", 2),
     ((37, 29, 23), 12, "hals", 1, "f32", 0),
+    ((64, 40, 1000), 16, "hals", 1, "bf16", 0),   # tall right node with J == 1: its own kernel family
 ]
 
 
