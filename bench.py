@@ -151,12 +151,16 @@ def _lowprec_study(dev, iters, seconds_note=None):
         torch.cuda.synchronize()
         dt_s = time.perf_counter() - t0
         rates = _node_rates(plan, dims, s, R, 4 if dt == "f32" else 2, 8 if dt == "f32" else 4)
+        ms_tree = plan.time_mttkrp(10)
         lam = plan.finish()
         plan.close()
         out[dt] = dict(iters_per_s=(iters - 1) / dt_s, fit_in_loop=float(fits[-1]) if len(fits) else float(f0[-1]),
                        fit_vs_fp32_tensor=_fit_against(X32, dims, s, Hd, lam),
                        pm_left_ms=rates["left_ms"], pm_right_ms=rates["right_ms"],
-                       pm_left_GBs=rates["left_GBs"], pm_right_GBs=rates["right_GBs"])
+                       pm_left_GBs=rates["left_GBs"], pm_right_GBs=rates["right_GBs"],
+                       mttkrp_ms=ms_tree,
+                       mttkrp_GBs=(rates["left_bytes"] + rates["right_bytes"] + rates["mttv_bytes"]) /
+                       (ms_tree * 1e-3) / 1e9)
         del Hd
         if dt != "f32":
             del Xd
@@ -375,6 +379,10 @@ def main(argv=None):
     bytes_dom = rt[dom + "_bytes"]
     achieved = bytes_dom / (ms_dom * 1e-3) / 1e9
 
+    # the whole tree MTTKRP of one iteration (node ops + leaf multi-TTVs), events around 10 trees
+    ms_tree = plan.time_mttkrp(10)
+    tree_bytes = rt["left_bytes"] + rt["right_bytes"] + rt["mttv_bytes"]
+
     # phase breakdown (events between kernels, no graph)
     Hp = [native.factor_to_device(h, device=dev) for h in H0]
     pplan = native.Plan(Xd, dims, R, Hp, update=args.update, split=s, graph=False, phase_timers=True)
@@ -382,9 +390,7 @@ def main(argv=None):
     ph = pplan.phase_ms()
     pplan.close()
     ph = {k: v / 3 for k, v in ph.items()}
-    mttkrp_ms = ph["pm"] + ph["mttv"]
-    mttkrp_gbs = ((rt["left_bytes"] + rt["right_bytes"] + rt["mttv_bytes"]) / (mttkrp_ms * 1e-3) / 1e9
-                  if mttkrp_ms > 0 else None)
+    mttkrp_gbs = tree_bytes / (ms_tree * 1e-3) / 1e9
 
     lam = plan.finish()
     plan.close()
@@ -425,6 +431,8 @@ def main(argv=None):
                      (FP32_MFMA_PEAK_TFLOPS if args.dtype == "f32" else BF16_MFMA_PEAK_TFLOPS)},
         "pm": {k: rt[k] for k in ("left_ms", "right_ms", "left_GBs", "right_GBs")},
         "mttkrp_GBs": mttkrp_gbs,
+        "mttkrp_ms": ms_tree,
+        "mttkrp_hbm_frac": mttkrp_gbs / HBM_PEAK_GBS,
         "phase_ms_per_iter": ph,
         "fit_first": fits[0] if fits else None,
         "fit_last": fits[-1] if fits else None,

@@ -127,6 +127,11 @@ int nncp_plan_phase_ms(const nncp_plan* plan, double* ms);
  * average milliseconds per launch from HIP events. Reads the current factors;
  * it rewrites only that node's temporary, which the next iteration recomputes. */
 int nncp_plan_time_node(nncp_plan* plan, int mode, int reps, double* ms_avg);
+/* Re-runs the whole dimension-tree MTTKRP of one outer iteration (every mode's
+ * node op and leaf multi-TTV, with the current factors; no update) `reps`
+ * times back to back and returns the average milliseconds per tree from HIP
+ * events. Rewrites only the tree temporaries and M. */
+int nncp_plan_time_mttkrp(nncp_plan* plan, int reps, double* ms_avg);
 int nncp_plan_destroy(nncp_plan* plan);
 
 /* Host copy of the fits recorded since the plan was created (or since the last

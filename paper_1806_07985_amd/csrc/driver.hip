@@ -535,6 +535,34 @@ int nncp_plan_time_node(nncp_plan* P, int mode, int reps, double* ms_avg) {
   return st;
 }
 
+int nncp_plan_time_mttkrp(nncp_plan* P, int reps, double* ms_avg) {
+  if (!P || !ms_avg || reps < 1) return NNCP_EINVAL;
+  hipStream_t s = P->user_stream;
+  hipEvent_t e0, e1;
+  HIPCHK(hipEventCreate(&e0));
+  if (hipEventCreate(&e1) != hipSuccess) {
+    hipEventDestroy(e0);
+    return NNCP_EDEVICE;
+  }
+  int st = NNCP_OK;
+  if (hipEventRecord(e0, s) != hipSuccess) st = NNCP_EDEVICE;
+  for (int i = 0; st == NNCP_OK && i < reps; ++i)
+    for (int n = 0; st == NNCP_OK && n < P->p.N; ++n) {
+      const void* M = nullptr;
+      int m_f64 = 1;
+      if (node_op(P, n, true, s) != hipSuccess || leaf_op(P, n, true, s, &M, &m_f64) != hipSuccess)
+        st = NNCP_EDEVICE;
+    }
+  float ms = 0.f;
+  if (st == NNCP_OK && (hipEventRecord(e1, s) != hipSuccess || hipEventSynchronize(e1) != hipSuccess ||
+                        hipEventElapsedTime(&ms, e0, e1) != hipSuccess))
+    st = NNCP_EDEVICE;
+  hipEventDestroy(e0);
+  hipEventDestroy(e1);
+  *ms_avg = (double)ms / reps;
+  return st;
+}
+
 int nncp_plan_destroy(nncp_plan* P) {
   if (!P) return NNCP_EINVAL;
   destroy_graph(P);

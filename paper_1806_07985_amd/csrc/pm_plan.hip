@@ -76,8 +76,12 @@ PmLaunch pm_plan(int side, int dtype, int64_t IL, int64_t IR, int I1, int R, int
   L.i1blk = (int)cdiv(cdiv(L.I1pad, L.n_i1blk), ks) * ks;
   L.n_i1blk = (int)cdiv(L.I1pad, L.i1blk);
 
+  // waves along M per group: four, unless the output is short; a left node
+  // whose one-wave M tiles alone fill the GPU takes one wave along M and its
+  // four waves split K inside the group (no split-K partials, no reduction)
   int wm = 4;
   if (cdiv(Mtot, 4 * wave_rows) < 64) wm = 1;
+  if (side == 0 && cdiv(Mtot, wave_rows) >= target) wm = 1;
   {
     // tuning override: NNCP_PM_WM = 1 or 4 (waves along M per work-group)
     static const int env_wm = [] {

@@ -88,6 +88,8 @@ def _declare(L):
     L.nncp_plan_phase_ms.argtypes = [c_vp, c_dp]
     L.nncp_plan_time_node.restype = ctypes.c_int
     L.nncp_plan_time_node.argtypes = [c_vp, ctypes.c_int, ctypes.c_int, c_dp]
+    L.nncp_plan_time_mttkrp.restype = ctypes.c_int
+    L.nncp_plan_time_mttkrp.argtypes = [c_vp, ctypes.c_int, c_dp]
     L.nncp_plan_destroy.restype = ctypes.c_int
     L.nncp_plan_destroy.argtypes = [c_vp]
     L.nncp_quantize.restype = ctypes.c_int
@@ -315,6 +317,12 @@ class Plan:
         """Average ms per launch of the node kernel computed before `mode`'s update."""
         ms = ctypes.c_double(0.0)
         _check(lib().nncp_plan_time_node(self._h, mode, reps, ctypes.byref(ms)), "nncp_plan_time_node")
+        return ms.value
+
+    def time_mttkrp(self, reps: int = 10) -> float:
+        """Average ms of one whole tree MTTKRP (all node ops and leaf multi-TTVs)."""
+        ms = ctypes.c_double(0.0)
+        _check(lib().nncp_plan_time_mttkrp(self._h, reps, ctypes.byref(ms)), "nncp_plan_time_mttkrp")
         return ms.value
 
     def fits(self) -> np.ndarray:
