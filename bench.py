@@ -326,6 +326,7 @@ def main(argv=None):
                     help="skip the FP32 / BF16 / FP16 study on the 1024x1344x33x9 tensor")
     ap.add_argument("--lowprec-iters", type=int, default=100)
     ap.add_argument("--no-batch", action="store_true", help="skip the 256-job batch study")
+    ap.add_argument("--no-ablation", action="store_true", help="skip the run without the dimension tree")
     ap.add_argument("--batch-jobs", type=int, default=256)
     ap.add_argument("--batch-iters", type=int, default=30)
     ap.add_argument("--no-serve", action="store_true", help="skip the serving-stream study")
@@ -394,6 +395,25 @@ def main(argv=None):
 
     lam = plan.finish()
     plan.close()
+
+    # the same run without the dimension tree: every mode's MTTKRP from X (N
+    # passes over the tensor per iteration instead of two)
+    no_tree = None
+    if not args.no_ablation:
+        Hn = [native.factor_to_device(h, device=dev) for h in H0]
+        nplan = native.Plan(Xd, dims, R, Hn, update=args.update, split=s, no_tree=True)
+        nplan.run(args.warmup)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        nplan.run(args.steps)
+        torch.cuda.synchronize()
+        dt_nt = time.perf_counter() - t0
+        ms_nt = nplan.time_mttkrp(10)
+        nplan.close()
+        del Hn
+        no_tree = {"iters_per_s": args.steps / dt_nt, "mttkrp_ms": ms_nt,
+                   "tree_speedup_iters": iters_per_s / (args.steps / dt_nt),
+                   "tree_speedup_mttkrp": ms_nt / ms_tree}
     if args.copy_calibration:
         src = torch.empty(1 << 28, dtype=torch.float32, device=dev).fill_(1.0)
         dst = torch.empty_like(src)
@@ -434,6 +454,7 @@ def main(argv=None):
         "mttkrp_ms": ms_tree,
         "mttkrp_hbm_frac": mttkrp_gbs / HBM_PEAK_GBS,
         "phase_ms_per_iter": ph,
+        "no_tree": no_tree,
         "fit_first": fits[0] if fits else None,
         "fit_last": fits[-1] if fits else None,
         "lambda_max": float(np.max(lam)),

@@ -63,7 +63,10 @@ typedef struct nncp_options {
   int pm_wg_kib;      /* partial MTTKRP: aim for at least this many KiB of the tensor per work-group
                          (at most one work-group per CU); <= 0: 256. Depends only on the job, never on
                          what else runs, so a job computes the same sums alone and in a batch. */
-  int reserved[7];
+  int no_tree;         /* nonzero: compute every mode's MTTKRP directly from the tensor (one partial
+                          MTTKRP + multi-TTVs per mode, N passes over X per iteration) instead of
+                          through the dimension tree (two passes): the tree-less baseline */
+  int reserved[6];
 } nncp_options;
 
 /* Human-readable text for a status code (static storage). */
@@ -154,7 +157,7 @@ int nncp_plan_fits(nncp_plan* plan, double* fit, int cap, int* count);
  * Fits are read per member with nncp_plan_fits. */
 typedef struct nncp_batch nncp_batch;
 int nncp_batch_create(nncp_batch** batch, void* stream);
-int nncp_batch_add(nncp_batch* batch, nncp_plan* plan);      /* EINVAL: rank > 64 or already a member */
+int nncp_batch_add(nncp_batch* batch, nncp_plan* plan);      /* EINVAL: rank > 64, no_tree, or already a member */
 int nncp_batch_remove(nncp_batch* batch, nncp_plan* plan);   /* ENOTFOUND: not a member */
 int nncp_batch_size(const nncp_batch* batch);
 /* Runs `ticks` outer iterations of every member; synchronises the stream. */

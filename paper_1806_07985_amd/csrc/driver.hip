@@ -56,11 +56,16 @@ struct Layout {
   int64_t node_bytes[kMaxModes];
   int node_f64;  // tree temporaries are FP64 for FP32 tensors, FP32 for 16-bit tensors
   PmLaunch pmL[2];
+  // without the dimension tree (ablation): per mode, the side and split of the
+  // partial MTTKRP that computes it from X, and two temporaries
+  int dside[kMaxModes], dsplit[kMaxModes];
+  PmLaunch dpm[kMaxModes];
+  size_t off_dtA, off_dtB;
   int ns_blocks;
 };
 
 struct Problem {
-  int N = 0, R = 0, dtype = 0, s = 0, update = 0, wg_kib = 0;
+  int N = 0, R = 0, dtype = 0, s = 0, update = 0, wg_kib = 0, no_tree = 0;
   int64_t dims[kMaxModes] = {};
   int64_t IL = 0, IR = 0, I = 0;
 };
@@ -168,6 +173,37 @@ Layout make_layout(const Problem& p) {
     L.node_bytes[n] = prod_range(p, n, b) * R * (L.node_f64 ? 8 : 4);
     take((size_t)L.node_bytes[n]);
   }
+  L.off_dtA = L.off_dtB = 0;
+  if (p.no_tree) {
+    // mode n from X directly: left with split n+1 (temporary over modes 1..n, then
+    // leading multi-TTVs down to mode n) or right with split n (temporary over
+    // modes n..N, then one trailing multi-TTV), whichever temporary is smaller
+    int64_t tmax = 1;
+    size_t part = 0, pack = 0;
+    for (int n = 0; n < N; ++n) {
+      const int64_t tl = n <= N - 2 ? prod_range(p, 0, n) : INT64_MAX;
+      const int64_t tr = n >= 1 ? prod_range(p, n, N - 1) : INT64_MAX;
+      const int side = tl <= tr ? 0 : 1;
+      const int s = side == 0 ? n + 1 : n;
+      L.dside[n] = side;
+      L.dsplit[n] = s;
+      const int64_t IL = prod_range(p, 0, s - 1), IR = p.I / IL;
+      L.dpm[n] = pm_plan(side, p.dtype, IL, IR, (int)(side == 0 ? p.dims[s] : p.dims[0]), R, p.wg_kib);
+      tmax = std::max(tmax, side == 0 ? tl : tr);
+      part = std::max(part, L.dpm[n].partial_doubles);
+      pack = std::max(pack, L.dpm[n].pack_bytes);
+    }
+    const size_t tb = (size_t)tmax * R * (L.node_f64 ? 8 : 4);
+    L.off_dtA = take(tb);
+    L.off_dtB = take(tb);
+    if (part > std::max(L.pmL[0].partial_doubles, L.pmL[1].partial_doubles) ||
+        pack > std::max(L.pmL[0].pack_bytes, L.pmL[1].pack_bytes)) {
+      // relocate the partial and pack regions to fit the no-tree launches too
+      L.off_pmpart = take(sizeof(double) * std::max(part, std::max(L.pmL[0].partial_doubles,
+                                                                    L.pmL[1].partial_doubles)));
+      L.off_hpack = take(std::max(pack, std::max(L.pmL[0].pack_bytes, L.pmL[1].pack_bytes)));
+    }
+  }
   L.total = o + 256;
   return L;
 }
@@ -212,6 +248,8 @@ struct nncp_plan {
   // 16-bit tensors: 64 column scales, then the packed hi/lo first factor
   float* hscale() const { return at<float>(L.off_hpack); }
   unsigned short* hpack() const { return at<unsigned short>(L.off_hpack + 256); }
+  void* dtA() const { return (void*)(ws + L.off_dtA); }
+  void* dtB() const { return (void*)(ws + L.off_dtB); }
   double* nspart() const { return at<double>(L.off_nspart); }
   double* Mbuf() const { return at<double>(L.off_M); }
   void* node(int n) const {
@@ -236,15 +274,19 @@ KrpDesc krp_for(const nncp_plan* P, int a, int b, bool scaled) {
   return k;
 }
 
-hipError_t run_pm(const nncp_plan* P, int side, void* T, int t_f64, const void* X, bool scaled, const Sink& st) {
+// Partial MTTKRP of X split after mode s (0-based: rows are modes 0..s-1) on
+// `side`, with launch plan lp for the first column chunk, into T.
+hipError_t run_pm_at(const nncp_plan* P, int side, int s, const PmLaunch& lp, void* T, int t_f64, const void* X,
+                     bool scaled, const Sink& st) {
   const Problem& p = P->p;
-  const int I1 = (int)(side == 0 ? p.dims[p.s] : p.dims[0]);
+  const int I1 = (int)(side == 0 ? p.dims[s] : p.dims[0]);
+  const int64_t IL = prod_range(p, 0, s - 1), IR = p.I / IL;
   for (int c0 = 0; c0 < p.R; c0 += kPmMaxCols) {
     PmArgs a{};
     a.X = X;
-    a.IL = p.IL;
-    a.IR = p.IR;
-    a.krp = side == 0 ? krp_for(P, p.s, p.N - 1, scaled) : krp_for(P, 0, p.s - 1, scaled);
+    a.IL = IL;
+    a.IR = IR;
+    a.krp = side == 0 ? krp_for(P, s, p.N - 1, scaled) : krp_for(P, 0, s - 1, scaled);
     a.R = std::min(kPmMaxCols, p.R - c0);
     a.col0 = c0;
     a.T = T;
@@ -254,12 +296,65 @@ hipError_t run_pm(const nncp_plan* P, int side, void* T, int t_f64, const void* 
     a.hscale = P->hscale();
     a.zeros = P->zeros();
     a.counters = P->counters();
-    const PmLaunch l = (a.R == std::min(kPmMaxCols, p.R)) ? P->L.pmL[side] : pm_plan(side, p.dtype, p.IL, p.IR, I1, a.R, p.wg_kib);
+    const PmLaunch l = (a.R == std::min(kPmMaxCols, p.R)) ? lp : pm_plan(side, p.dtype, IL, IR, I1, a.R, p.wg_kib);
     pm_fill_args(l, a);
     hipError_t e = pm_launch(l, a, st);
     if (e != hipSuccess) return e;
   }
   return hipSuccess;
+}
+
+hipError_t run_pm(const nncp_plan* P, int side, void* T, int t_f64, const void* X, bool scaled, const Sink& st) {
+  return run_pm_at(P, side, P->p.s, P->L.pmL[side], T, t_f64, X, scaled, st);
+}
+
+// MTTKRP of mode n without the dimension tree: one partial MTTKRP from X, then
+// multi-TTVs down to M^(n). *M / *m_f64 say where it lives.
+hipError_t direct_mttkrp(const nncp_plan* P, int n, bool scaled, const Sink& st, const void** M, int* m_f64) {
+  const Problem& p = P->p;
+  const int side = P->L.dside[n], s = P->L.dsplit[n];
+  const int f64 = P->L.node_f64;
+  void* cur = P->dtA();
+  void* nxt = P->dtB();
+  hipError_t e = run_pm_at(P, side, s, P->L.dpm[n], cur, f64, P->X, scaled, st);
+  if (e != hipSuccess) return e;
+  if (side == 0) {
+    // temporary over modes 0..n: contract modes 0..n-1 one at a time
+    for (int k = 0; k < n; ++k) {
+      MttvArgs a{};
+      a.T = cur;
+      a.t_f64 = f64;
+      a.Ia = p.dims[k];
+      a.J = prod_range(p, k + 1, n);
+      a.R = p.R;
+      a.krp = krp_for(P, k, k, scaled);
+      a.out = nxt;
+      a.out_f64 = f64;
+      if ((e = mttv_lead_launch(a, st)) != hipSuccess) return e;
+      std::swap(cur, nxt);
+    }
+    *M = cur;
+    *m_f64 = f64;
+    return hipSuccess;
+  }
+  // temporary over modes n..N-1: contract modes n+1..N-1 at once
+  if (n == p.N - 1) {
+    *M = cur;
+    *m_f64 = f64;
+    return hipSuccess;
+  }
+  MttvArgs a{};
+  a.T = cur;
+  a.t_f64 = f64;
+  a.Ia = p.dims[n];
+  a.J = prod_range(p, n + 1, p.N - 1);
+  a.R = p.R;
+  a.krp = krp_for(P, n + 1, p.N - 1, scaled);
+  a.out = P->Mbuf();
+  a.out_f64 = 1;
+  *M = P->Mbuf();
+  *m_f64 = 1;
+  return mttv_trail_launch(a, st);
 }
 
 // Node op for mode n: the root partial MTTKRP (n starts its half) or the leading
@@ -353,10 +448,15 @@ hipError_t enqueue_iteration(nncp_plan* P, const Sink& st0, std::vector<std::pai
     int m_f64 = 1;
     Sink st = st0;
     st.mode = n;
-    if ((e = mark(n == start ? PH_PM : PH_MTTV)) != hipSuccess) return e;
-    if ((e = node_op(P, n, true, st)) != hipSuccess) return e;
-    if ((e = mark(PH_MTTV)) != hipSuccess) return e;
-    if ((e = leaf_op(P, n, true, st, &M, &m_f64)) != hipSuccess) return e;
+    if (p.no_tree) {
+      if ((e = mark(PH_PM)) != hipSuccess) return e;
+      if ((e = direct_mttkrp(P, n, true, st, &M, &m_f64)) != hipSuccess) return e;
+    } else {
+      if ((e = mark(n == start ? PH_PM : PH_MTTV)) != hipSuccess) return e;
+      if ((e = node_op(P, n, true, st)) != hipSuccess) return e;
+      if ((e = mark(PH_MTTV)) != hipSuccess) return e;
+      if ((e = leaf_op(P, n, true, st, &M, &m_f64)) != hipSuccess) return e;
+    }
     if ((e = mark(PH_NLS)) != hipSuccess) return e;
     UpdateArgs u{};
     u.M = M;
@@ -436,6 +536,7 @@ size_t nncp_workspace_bytes(int N, const int64_t* dims, int R, int dtype, const 
   Problem p;
   if (fill_problem(p, N, dims, R, dtype, NNCP_HALS, opt ? opt->split : 0) != NNCP_OK) return 0;
   p.wg_kib = opt ? opt->pm_wg_kib : 0;
+  p.no_tree = opt ? (opt->no_tree != 0) : 0;
   return make_layout(p).total;
 }
 
@@ -448,6 +549,7 @@ int nncp_plan_create(nncp_plan** out, const void* X, int dtype, int N, const int
   int st = fill_problem(p, N, dims, R, dtype, update, opt ? opt->split : 0);
   if (st != NNCP_OK) return st;
   p.wg_kib = opt ? opt->pm_wg_kib : 0;
+  p.no_tree = opt ? (opt->no_tree != 0) : 0;
   for (int k = 0; k < N; ++k)
     if (!H[k]) return NNCP_EINVAL;
   nncp_plan* P = new (std::nothrow) nncp_plan();
@@ -550,8 +652,11 @@ int nncp_plan_time_mttkrp(nncp_plan* P, int reps, double* ms_avg) {
     for (int n = 0; st == NNCP_OK && n < P->p.N; ++n) {
       const void* M = nullptr;
       int m_f64 = 1;
-      if (node_op(P, n, true, s) != hipSuccess || leaf_op(P, n, true, s, &M, &m_f64) != hipSuccess)
+      if (P->p.no_tree) {
+        if (direct_mttkrp(P, n, true, s, &M, &m_f64) != hipSuccess) st = NNCP_EDEVICE;
+      } else if (node_op(P, n, true, s) != hipSuccess || leaf_op(P, n, true, s, &M, &m_f64) != hipSuccess) {
         st = NNCP_EDEVICE;
+      }
     }
   float ms = 0.f;
   if (st == NNCP_OK && (hipEventRecord(e1, s) != hipSuccess || hipEventSynchronize(e1) != hipSuccess ||
@@ -1054,6 +1159,7 @@ int nncp_batch_create(nncp_batch** out, void* stream) {
 int nncp_batch_add(nncp_batch* B, nncp_plan* P) {
   if (!B || !P) return NNCP_EINVAL;
   if (P->p.R > kPmMaxCols) return NNCP_EINVAL;  // one column chunk per partial MTTKRP
+  if (P->p.no_tree) return NNCP_EINVAL;         // its chains of multi-TTVs share one stage slot
   for (nncp_plan* q : B->plans)
     if (q == P) return NNCP_EINVAL;
   try {

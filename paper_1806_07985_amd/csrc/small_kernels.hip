@@ -135,30 +135,43 @@ __device__ __forceinline__ void mttv_trail_body(const MttvArgs& a, int bx, int r
   for (int64_t j0 = 0; j0 < a.J; j0 += TRAIL_KCH) {
     const int cnt = (int)((a.J - j0) < TRAIL_KCH ? (a.J - j0) : TRAIL_KCH);
     __syncthreads();
+    // the Khatri-Rao column chunk: every factor load is issued (from a valid
+    // address) before any product is formed
     for (int e = threadIdx.x; e < cnt; e += NT) {
       uint32_t rem = (uint32_t)(j0 + e);
-      double p = scale;
-      for (int m = 0; m < a.krp.nm; ++m) {
-        uint32_t d = (uint32_t)a.krp.dim[m];
-        uint32_t q = rem / d;
-        p *= (double)a.krp.f[m][(int64_t)(rem - q * d) + (int64_t)a.krp.dim[m] * r];
-        rem = q;
+      float fv[kMaxModes];
+#pragma unroll
+      for (int m = 0; m < kMaxModes; ++m) {
+        const int mm = m < a.krp.nm ? m : 0;
+        const uint32_t d = (uint32_t)a.krp.dim[mm];
+        const uint32_t q = rem / d;
+        const uint32_t dig = m < a.krp.nm ? rem - q * d : 0u;
+        if (m < a.krp.nm) rem = q;
+        fv[m] = a.krp.f[mm][(int64_t)dig + (int64_t)a.krp.dim[mm] * r];
       }
+      double p = scale;
+#pragma unroll
+      for (int m = 0; m < kMaxModes; ++m)
+        if (m < a.krp.nm) p *= (double)fv[m];
       kv[e] = p;
     }
     __syncthreads();
-    if (i < a.Ia) {
-      const TN* base = Tr + i + a.Ia * j0;
-      int e = ph;
-      for (; e + 12 < cnt; e += 16) {
-        double t0 = base[a.Ia * e], t1 = base[a.Ia * (e + 4)];
-        double t2 = base[a.Ia * (e + 8)], t3 = base[a.Ia * (e + 12)];
-        acc += t0 * kv[e];
-        acc += t1 * kv[e + 4];
-        acc += t2 * kv[e + 8];
-        acc += t3 * kv[e + 12];
+    // eight rows j of this phase in flight per step; rows past the chunk (or
+    // past I_a) read a valid element and are weighted by zero
+    const int64_t ic = i < a.Ia ? i : 0;
+    const TN* base = Tr + ic + a.Ia * j0;
+    for (int e = ph; e < cnt; e += 32) {
+      TN t[8];
+#pragma unroll
+      for (int u = 0; u < 8; ++u) {
+        const int ej = e + 4 * u;
+        t[u] = base[a.Ia * (int64_t)(ej < cnt ? ej : e)];
       }
-      for (; e < cnt; e += 4) acc += (double)base[a.Ia * e] * kv[e];
+#pragma unroll
+      for (int u = 0; u < 8; ++u) {
+        const int ej = e + 4 * u;
+        if (ej < cnt) acc += (double)t[u] * kv[ej];
+      }
     }
   }
   red[ph][ti] = acc;

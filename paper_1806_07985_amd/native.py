@@ -35,7 +35,8 @@ class Options(ctypes.Structure):
     _fields_ = [("split", ctypes.c_int), ("no_record_fit", ctypes.c_int), ("no_graph", ctypes.c_int),
                 ("phase_timers", ctypes.c_int), ("tol", ctypes.c_double),
                 ("pm_wg_kib", ctypes.c_int),
-                ("reserved", ctypes.c_int * 7)]
+                ("no_tree", ctypes.c_int),
+                ("reserved", ctypes.c_int * 6)]
 
 
 class JobRequest(ctypes.Structure):
@@ -232,8 +233,8 @@ def version() -> int:
     return lib().nncp_version()
 
 
-def workspace_bytes(dims, R, dtype="f32", split=0, pm_wg_kib=0) -> int:
-    o = Options(split=split, pm_wg_kib=pm_wg_kib)
+def workspace_bytes(dims, R, dtype="f32", split=0, pm_wg_kib=0, no_tree=False) -> int:
+    o = Options(split=split, pm_wg_kib=pm_wg_kib, no_tree=1 if no_tree else 0)
     return int(lib().nncp_workspace_bytes(len(dims), _dims(dims), R, _DTYPE[dtype], ctypes.byref(o)))
 
 
@@ -242,7 +243,7 @@ def _dtype_name(t) -> str:
 
 
 def nncp(X, dims, R, iters, H, lam=None, update="hals", split=0, graph=True, record_fit=True,
-         tol=0.0, workspace=None, stream=None, pm_wg_kib=0):
+         tol=0.0, workspace=None, stream=None, pm_wg_kib=0, no_tree=False):
     """Run the full driver. H: list of device (R, I_n) float32 tensors, updated in place.
 
     Returns dict(fit=np.ndarray, lam=np.ndarray, iters_done=int).
@@ -258,7 +259,7 @@ def nncp(X, dims, R, iters, H, lam=None, update="hals", split=0, graph=True, rec
     fit = (ctypes.c_double * max(1, iters))()
     done = ctypes.c_int(0)
     o = Options(split=split, no_record_fit=0 if record_fit else 1, no_graph=0 if graph else 1, tol=tol,
-                pm_wg_kib=pm_wg_kib)
+                pm_wg_kib=pm_wg_kib, no_tree=1 if no_tree else 0)
     ws_ptr, ws_bytes = (None, 0)
     if workspace is not None:
         ws_ptr, ws_bytes = _ptr(workspace), workspace.numel() * workspace.element_size()
@@ -273,7 +274,7 @@ class Plan:
     """Persistent driver state: create once, run repeatedly, finish to normalise."""
 
     def __init__(self, X, dims, R, H, lam=None, update="hals", split=0, graph=True, phase_timers=False,
-                 workspace=None, stream=None, pm_wg_kib=0):
+                 workspace=None, stream=None, pm_wg_kib=0, no_tree=False):
         import torch
         L = lib()
         self.dims, self.R, self.H, self.X = list(dims), R, list(H), X
@@ -285,10 +286,10 @@ class Plan:
         if lam is not None:
             lam_arr = (ctypes.c_double * R)(*np.asarray(lam, dtype=np.float64))
         o = Options(split=split, no_graph=0 if graph else 1, phase_timers=1 if phase_timers else 0,
-                    pm_wg_kib=pm_wg_kib)
+                    pm_wg_kib=pm_wg_kib, no_tree=1 if no_tree else 0)
         self._ws = workspace
         if workspace is None:
-            nbytes = workspace_bytes(dims, R, _dtype_name(X), split, pm_wg_kib)
+            nbytes = workspace_bytes(dims, R, _dtype_name(X), split, pm_wg_kib, no_tree)
             self._ws = torch.empty(nbytes, dtype=torch.uint8, device=X.device)
         handle = c_vp()
         st = L.nncp_plan_create(ctypes.byref(handle), _ptr(X), _dtype_code(X), len(dims), _dims(dims), R,

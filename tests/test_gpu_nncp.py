@@ -134,3 +134,32 @@ def test_lambda_input_scales_the_model(gpu_lib):
     H0 = [h.astype(np.float32) for h in inputs.init_factors(dims, R, seed=62)]
     lam = np.array([2.0, 0.5, 3.0])
     _compare(_run_gpu(X, H0, R, 4, lam=lam), _run_oracle(X, H0, 4, lam=lam))
+
+
+@pytest.mark.parametrize("dims,R,dt", [((30, 24, 20), 6, "f32"), ((16, 14, 12, 10), 8, "f32"),
+                                       ((10, 9, 8, 7, 6), 4, "f32"), ((40, 30), 5, "f32"),
+                                       ((20, 18, 16, 14), 8, "bf16")])
+def test_no_tree_matches_oracle_and_tree(gpu_lib, dims, R, dt):
+    """Every mode's MTTKRP straight from the tensor (the tree-less baseline) gives
+    the oracle's trajectory, like the dimension tree."""
+    import torch
+    from paper_1806_07985_amd import native
+    print(f"case no-tree dims={dims} R={R} {dt}", flush=True)
+    X, _ = inputs.planted(dims, R, 0.01, seed=21, dtype=np.float32)
+    H0 = [h.astype(np.float32) for h in inputs.init_factors(dims, R, seed=22)]
+    flat = torch.from_numpy(np.ascontiguousarray(X.ravel(order="F")))
+    if dt == "bf16":
+        flat = flat.to(torch.bfloat16)
+    X64 = flat.to(torch.float64).numpy().reshape(dims, order="F")
+    out = {}
+    for nt in (False, True):
+        Hd = [native.factor_to_device(h) for h in H0]
+        r = native.nncp(flat.cuda(), list(dims), R, 10, Hd, no_tree=nt)
+        out[nt] = ([native.factor_to_host(h) for h in Hd], r["lam"], r["fit"])
+    ref = O.nncp(X64, [h.astype(np.float64) for h in H0], 10)
+    tol = 1e-5 if dt == "f32" else 1e-4
+    for nt in (False, True):
+        H, lam, fit = out[nt]
+        errs = [np.linalg.norm(h - rh) / np.linalg.norm(rh) for h, rh in zip(H, ref["H"])]
+        print(f"  no_tree={nt}: factors {max(errs):.1e} fit {np.max(np.abs(fit - ref['fit'])):.1e}", flush=True)
+        assert max(errs) < tol and np.max(np.abs(fit - np.asarray(ref["fit"]))) < tol
