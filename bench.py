@@ -308,6 +308,46 @@ def _serving_study(dev, n_pool, n_jobs, load_fracs, iters, budget_gb, max_active
             "levels": levels}
 
 
+def _workloads_study(dev, steps):
+    """The paper's other synthetic workloads at full size on one GPU: the 3-way
+    1024^3 tensor of its strong-scaling runs and the 5-way 64^5 tensor of its 5D
+    runs, rank 32, planted + 1% noise (drawn on the device), HALS; iterations/s
+    with and without the dimension tree and the tree MTTKRP's HBM rate."""
+    import torch
+    from paper_1806_07985_amd import inputs, native
+    out = {}
+    for name, dims, R in (("1024^3", (1024, 1024, 1024), 32), ("64^5", (64, 64, 64, 64, 64), 32)):
+        X = inputs.planted_device(dims, R, 0.01, seed=41, device=dev)
+        H0 = [h.astype(np.float32) for h in inputs.init_factors(dims, R, seed=42)]
+        res = {"dims": list(dims), "R": R}
+        for nt in (False, True):
+            Hd = [native.factor_to_device(h, device=dev) for h in H0]
+            plan = native.Plan(X, list(dims), R, Hd, no_tree=nt)
+            plan.run(2)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            plan.run(steps)
+            torch.cuda.synchronize()
+            dt = time.perf_counter() - t0
+            ms = plan.time_mttkrp(5)
+            fit = float(plan.fits()[-1]) if len(plan.fits()) else None
+            plan.close()
+            key = "no_tree" if nt else "tree"
+            res[key] = {"iters_per_s": steps / dt, "mttkrp_ms": ms, "fit": fit}
+        # algorithmic tree bytes with the automatic split
+        N = len(dims)
+        best = min(range(1, N), key=lambda s_: int(np.prod(dims[:s_])) + int(np.prod(dims[s_:])))
+        pl, pr, mt = _algorithmic_bytes(list(dims), best, R, 4, 8)
+        res["split"] = best
+        res["tree"]["mttkrp_GBs"] = (pl + pr + mt) / (res["tree"]["mttkrp_ms"] * 1e-3) / 1e9
+        res["tree_speedup_iters"] = res["tree"]["iters_per_s"] / res["no_tree"]["iters_per_s"]
+        res["tree_speedup_mttkrp"] = res["no_tree"]["mttkrp_ms"] / res["tree"]["mttkrp_ms"]
+        out[name] = res
+        del X
+        torch.cuda.empty_cache()
+    return out
+
+
 def main(argv=None):
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -327,6 +367,7 @@ def main(argv=None):
     ap.add_argument("--lowprec-iters", type=int, default=100)
     ap.add_argument("--no-batch", action="store_true", help="skip the 256-job batch study")
     ap.add_argument("--no-ablation", action="store_true", help="skip the run without the dimension tree")
+    ap.add_argument("--no-workloads", action="store_true", help="skip the 1024^3 and 64^5 workloads")
     ap.add_argument("--batch-jobs", type=int, default=256)
     ap.add_argument("--batch-iters", type=int, default=30)
     ap.add_argument("--no-serve", action="store_true", help="skip the serving-stream study")
@@ -463,6 +504,8 @@ def main(argv=None):
     torch.cuda.empty_cache()
     if not args.no_lowprec:
         out["lowprec"] = _lowprec_study(dev, args.lowprec_iters)
+    if not args.no_workloads:
+        out["workloads"] = _workloads_study(dev, 20)
     if not args.no_batch:
         out["batch"] = _batch_study(dev, args.batch_jobs, args.batch_iters)
     if not args.no_serve:

@@ -137,7 +137,9 @@ __device__ __forceinline__ void pm_left_f32_body(const PmArgs& a, int bx, int by
 #pragma unroll
         for (int nb = 0; nb < NB; ++nb) c32[tt][nb] = mfma4(A[u][tt], B[nb][u], c32[tt][nb]);
     --sc_left;
-    if (++fc == a.fold || sc_left == 0) {
+    // fold every `fold` k-steps, at the end of each j (the last i1 block can be
+    // shorter than the others, so fold need not divide its steps) and at the end
+    if (++fc == a.fold || tc + 1 == S1 || sc_left == 0) {
 #pragma unroll
       for (int nb = 0; nb < NB; ++nb) {
         const double scl = sc[jc * RP + 16 * nb + li];
@@ -307,7 +309,9 @@ __device__ __forceinline__ void pm_right_f32_body(const PmArgs& a, int bx, int b
 #pragma unroll
           for (int nb = 0; nb < NB; ++nb) c32[g][nb] = mfma4(A[g][h][u], B[h][nb][u], c32[g][nb]);
     --sc_left;
-    if (++fc == a.fold || sc_left == 0) {
+    // fold every `fold` k-steps, at the end of each j (the last i1 block can be
+    // shorter than the others, so fold need not divide its steps) and at the end
+    if (++fc == a.fold || tc + 1 == S1 || sc_left == 0) {
 #pragma unroll
       for (int nb = 0; nb < NB; ++nb) {
         const double scl = sc[jc * RP + 16 * nb + li];

@@ -62,3 +62,43 @@ def test_c2_trajectory_50(c2_data, update):
     if update == "hals":
         assert all(g["fit"][i + 1] >= g["fit"][i] - 1e-9 for i in range(len(g["fit"]) - 1))
     _compare(g, o, 1e-5)
+
+
+def _row_mttkrp(sl, hs):
+    """sum over the slice's modes of sl * prod_k hs[k][i_k, r], for every r (FP64):
+    contract the last mode with its factor, then the others diagonally in r."""
+    T = np.tensordot(sl, hs[-1], axes=([sl.ndim - 1], [0]))
+    for h in reversed(hs[:-1]):
+        T = np.einsum("...kr,kr->...r", T, h)
+    return T
+
+
+@pytest.mark.parametrize("dims", [(1024, 1024, 1024), (64, 64, 64, 64, 64)])
+def test_large_workload_sampled_mttkrp_rows(gpu_lib, dims):
+    """The paper's 1024^3 and 64^5 workloads at full size: sampled rows of every
+    mode's tree MTTKRP against FP64 sums on the host (the whole oracle MTTKRP
+    would take minutes per mode at this size)."""
+    import torch
+    from paper_1806_07985_amd import native
+    R = 32
+    print(f"case large sampled rows dims={dims}", flush=True)
+    X = inputs.planted_device(dims, R, 0.01, seed=41, device="cuda")
+    H = [h.astype(np.float32) for h in inputs.init_factors(dims, R, seed=43)]
+    Hd = [native.factor_to_device(h) for h in H]
+    Xh = X.cpu().numpy().reshape(dims, order="F")
+    H64 = [h.astype(np.float64) for h in H]
+    N = len(dims)
+    s = min(range(1, N), key=lambda s_: int(np.prod(dims[:s_])) + int(np.prod(dims[s_:])))
+    rng = np.random.default_rng(5)
+    for n in range(N):
+        M = native.mttkrp(X, list(dims), s, n, Hd, R).cpu().numpy().T     # I_n x R
+        others = [H64[k] for k in range(N) if k != n]
+        print(f"  mode {n}", flush=True)
+        for i in rng.choice(dims[n], size=3, replace=False):
+            sl = Xh[(slice(None),) * n + (int(i),)].astype(np.float64)   # a strided view, then one copy
+            ref = _row_mttkrp(sl, others)
+            bound = _row_mttkrp(np.abs(sl), others)
+            err = np.abs(M[i] - ref)
+            assert np.all(err <= 1e-6 * bound), (n, int(i), float(np.max(err / bound)))
+    del X
+    torch.cuda.empty_cache()

@@ -55,6 +55,8 @@ PM_CASES = [
     ((20, 18, 22), 100, 2),      # more than 64 columns: column chunks
     ((7, 3), 3, 1),              # tiny matrix
     ((1024, 300), 24, 1),        # long reduction, many splits
+    ((64, 1040, 8), 32, 1),      # left: three i1 blocks (352, 352, 336 rows) with FP32 chains of 2 steps;
+                                 # the short last block has an odd step count (chains must end with each j)
 ]
 
 
