@@ -51,6 +51,7 @@ typedef enum { NNCP_F32 = 0, NNCP_BF16 = 1, NNCP_F16 = 2 } nncp_dtype;
 
 #define NNCP_MAX_MODES 8
 #define NNCP_MAX_RANK 128
+#define NNCP_MAX_SWEEPS 1024
 
 /* Options; zero-initialised means: automatic split, record every fit, use a
  * HIP graph per outer iteration, no early stop. */
@@ -66,7 +67,11 @@ typedef struct nncp_options {
   int no_tree;         /* nonzero: compute every mode's MTTKRP directly from the tensor (one partial
                           MTTKRP + multi-TTVs per mode, N passes over X per iteration) instead of
                           through the dimension tree (two passes): the tree-less baseline */
-  int reserved[6];
+  int inner_sweeps;   /* update sweeps per block update, 1..NNCP_MAX_SWEEPS (<= 0: 1). HALS: that many
+                         Gauss-Seidel passes over the columns, each an exact coordinate minimisation,
+                         so many sweeps approach the exact NNLS solution of the block subproblem
+                         (Section II-B); MU: that many multiplicative steps. EINVAL above the maximum. */
+  int reserved[5];
 } nncp_options;
 
 /* Human-readable text for a status code (static storage). */

@@ -367,7 +367,8 @@ class DimTree:
 def nncp(X: np.ndarray, H0: Sequence[np.ndarray], iters: int, update: str = "hals",
          lam0: Optional[np.ndarray] = None, mttkrp: str = "direct",
          split: Optional[int] = None, alpha: Optional[float] = None,
-         callback: Optional[Callable[[int, int, dict], None]] = None) -> dict:
+         callback: Optional[Callable[[int, int, dict], None]] = None,
+         inner_sweeps: int = 1) -> dict:
     """Alternating-update NNCP, ``iters`` outer iterations (Algorithm 1).
 
     Per mode n = 1..N: M^(n) = MTTKRP, S^(n) = Hadamard of the other Grams,
@@ -384,7 +385,12 @@ def nncp(X: np.ndarray, H0: Sequence[np.ndarray], iters: int, update: str = "hal
     * the update for mode n starts from H^(n) diag(lambda) (the current
       model's mode-n block with the other factors at unit norm); the update
       rules are scale-covariant, so this equals unnormalised BCD exactly;
-    * fit = 1 - epsilon, recorded after every outer iteration.
+    * fit = 1 - epsilon, recorded after every outer iteration;
+    * ``inner_sweeps`` applies the update rule that many times per block
+      update (with M and S fixed). For HALS every sweep is an exact
+      coordinate minimisation of the block subproblem, so many sweeps
+      approach the exact NNLS solution that Section II-B names as the
+      alternative to a single sweep (BPP solves it directly).
 
     ``mttkrp`` selects "direct" (the plain definition) or "tree" (the FP64
     dimension tree, used only to show that both give the same iterates).
@@ -411,7 +417,9 @@ def nncp(X: np.ndarray, H0: Sequence[np.ndarray], iters: int, update: str = "hal
         for n in range(N):
             M = tree.mttkrp(H, n) if tree is not None else mttkrp_direct(X, H, n)
             S = hadamard_others(G, n)
-            W = upd(H[n] * lam[None, :], S, M)
+            W = H[n] * lam[None, :]
+            for _ in range(max(1, inner_sweeps)):
+                W = upd(W, S, M)
             H[n], lam = normalize_columns(W)
             G[n] = gram(H[n])
             if callback is not None:

@@ -65,7 +65,7 @@ struct Layout {
 };
 
 struct Problem {
-  int N = 0, R = 0, dtype = 0, s = 0, update = 0, wg_kib = 0, no_tree = 0;
+  int N = 0, R = 0, dtype = 0, s = 0, update = 0, wg_kib = 0, no_tree = 0, sweeps = 1;
   int64_t dims[kMaxModes] = {};
   int64_t IL = 0, IR = 0, I = 0;
 };
@@ -468,6 +468,7 @@ hipError_t enqueue_iteration(nncp_plan* P, const Sink& st0, std::vector<std::pai
     u.lam_model = P->lam_model();
     u.lam_self = P->lam() + (int64_t)n * p.R;
     u.update = p.update;
+    u.sweeps = p.sweeps;
     if ((e = update_launch(u, st)) != hipSuccess) return e;
     const bool last = (n == p.N - 1);
     if ((e = mark(last ? PH_ERR : PH_GRAM)) != hipSuccess) return e;
@@ -550,6 +551,8 @@ int nncp_plan_create(nncp_plan** out, const void* X, int dtype, int N, const int
   if (st != NNCP_OK) return st;
   p.wg_kib = opt ? opt->pm_wg_kib : 0;
   p.no_tree = opt ? (opt->no_tree != 0) : 0;
+  p.sweeps = (opt && opt->inner_sweeps > 0) ? opt->inner_sweeps : 1;
+  if (p.sweeps > NNCP_MAX_SWEEPS) return NNCP_EINVAL;
   for (int k = 0; k < N; ++k)
     if (!H[k]) return NNCP_EINVAL;
   nncp_plan* P = new (std::nothrow) nncp_plan();
@@ -964,6 +967,7 @@ int nncp_nls_update(const double* M, float* H, int64_t I, int R, const double* S
   u.lam_model = lambda;
   u.lam_self = ones;
   u.update = update;
+  u.sweeps = 1;
   FinalizeArgs f{};
   f.W = H;
   f.I = I;

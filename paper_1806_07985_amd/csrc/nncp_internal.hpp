@@ -123,6 +123,7 @@ struct UpdateArgs {
   const double* lam_model;  // current model weights
   const double* lam_self;   // column norms of W as stored
   int update;             // NNCP_HALS / NNCP_MU
+  int sweeps;             // update sweeps (>= 1; 0 is taken as 1)
 };
 hipError_t update_launch(const UpdateArgs& a, hipStream_t st);
 hipError_t update_launch(const UpdateArgs& a, const Sink& sk);

@@ -260,20 +260,28 @@ __device__ __forceinline__ void update_body(const UpdateArgs& a, int bx) {
   if (!live) return;  // whole wave leaves together
 
   // g = w S with the starting w
-  for (int r = 0; r < R; ++r) {
-    const int v = r >> 6;
-    double wv = w[0];
+  auto wS = [&]() {
 #pragma unroll
-    for (int q = 1; q < VPL; ++q)
-      if (v == q) wv = w[q];
-    const double wr = readlane_f64(wv, r & 63);
+    for (int q = 0; q < VPL; ++q) g[q] = 0.0;
+    for (int r = 0; r < R; ++r) {
+      const int v = r >> 6;
+      double wv = w[0];
 #pragma unroll
-    for (int q = 0; q < VPL; ++q) {
-      const int k = p + 64 * q;
-      if (k < R) g[q] += wr * Sl[r * R + k];
+      for (int q = 1; q < VPL; ++q)
+        if (v == q) wv = w[q];
+      const double wr = readlane_f64(wv, r & 63);
+#pragma unroll
+      for (int q = 0; q < VPL; ++q) {
+        const int k = p + 64 * q;
+        if (k < R) g[q] += wr * Sl[r * R + k];
+      }
     }
-  }
+  };
+  wS();
+  const int sweeps = a.sweeps > 1 ? a.sweeps : 1;
   if (a.update == NNCP_HALS) {
+    // g stays equal to w S across sweeps: every column change is added to it
+    for (int sw = 0; sw < sweeps; ++sw)
     for (int r = 0; r < R; ++r) {
       const int v = r >> 6;
       double wv = w[0], mv = m[0], gv = g[0];
@@ -302,10 +310,13 @@ __device__ __forceinline__ void update_body(const UpdateArgs& a, int bx) {
       }
     }
   } else {
+    for (int sw = 0; sw < sweeps; ++sw) {
+      if (sw > 0) wS();
 #pragma unroll
-    for (int v = 0; v < VPL; ++v) {
-      const double den = g[v] > 1e-16 ? g[v] : 1e-16;
-      w[v] = w[v] * m[v] / den;
+      for (int v = 0; v < VPL; ++v) {
+        const double den = g[v] > 1e-16 ? g[v] : 1e-16;
+        w[v] = w[v] * m[v] / den;
+      }
     }
   }
 #pragma unroll
@@ -347,22 +358,40 @@ __device__ __forceinline__ void update_reg_body(const UpdateArgs& a, int bx) {
   double g = 0.0;
 #pragma unroll
   for (int r = 0; r < RB; ++r) g += readlane_f64(w, r) * srow[r];
+  const int sweeps = a.sweeps > 1 ? a.sweeps : 1;
   if (a.update == NNCP_HALS) {
+    auto sweep = [&]() {
+      // fresh copies of the lane index and the rank per sweep: the per-column
+      // compares below then stay inside the sweep instead of being hoisted out of
+      // the sweep loop into 64 live lane masks
+      int kv, Rv;
+      asm volatile("v_mov_b32 %0, %1" : "=v"(kv) : "v"(k));
+      asm volatile("s_mov_b32 %0, %1" : "=s"(Rv) : "s"(R));
 #pragma unroll
-    for (int r = 0; r < RB; ++r) {
-      if (r < R) {  // uniform
-        // column r: W(:,r) <- max(0, W(:,r) + (M(:,r) - (W S)(:,r)) / S(r,r)); a zero
-        // diagonal sets the column to zero (lane r owns column r)
-        double wn = invd > 0.0 ? w + (m - g) * invd : 0.0;
-        wn = wn > 0.0 ? wn : 0.0;
-        const double dlt = readlane_f64(wn - w, r);
-        if (k == r) w += dlt;
-        g += dlt * srow[r];
+      for (int r = 0; r < RB; ++r) {
+        if (r < Rv) {  // uniform
+          // column r: W(:,r) <- max(0, W(:,r) + (M(:,r) - (W S)(:,r)) / S(r,r)); a zero
+          // diagonal sets the column to zero (lane r owns column r)
+          double wn = invd > 0.0 ? w + (m - g) * invd : 0.0;
+          wn = wn > 0.0 ? wn : 0.0;
+          const double dlt = readlane_f64(wn - w, r);
+          if (kv == r) w += dlt;
+          g += dlt * srow[r];
+        }
       }
-    }
+    };
+    // g stays equal to w S across sweeps: every column change is added to it
+    for (int sw = 0; sw < sweeps; ++sw) sweep();
   } else {
-    const double den = g > 1e-16 ? g : 1e-16;
-    w = w * m / den;
+    for (int sw = 0; sw < sweeps; ++sw) {
+      if (sw > 0) {
+        g = 0.0;
+#pragma unroll
+        for (int r = 0; r < RB; ++r) g += readlane_f64(w, r) * srow[r];
+      }
+      const double den = g > 1e-16 ? g : 1e-16;
+      w = w * m / den;
+    }
   }
   if (col) a.W[row + a.I * k] = (float)w;
 }

@@ -36,7 +36,8 @@ class Options(ctypes.Structure):
                 ("phase_timers", ctypes.c_int), ("tol", ctypes.c_double),
                 ("pm_wg_kib", ctypes.c_int),
                 ("no_tree", ctypes.c_int),
-                ("reserved", ctypes.c_int * 6)]
+                ("inner_sweeps", ctypes.c_int),
+                ("reserved", ctypes.c_int * 5)]
 
 
 class JobRequest(ctypes.Structure):
@@ -243,7 +244,7 @@ def _dtype_name(t) -> str:
 
 
 def nncp(X, dims, R, iters, H, lam=None, update="hals", split=0, graph=True, record_fit=True,
-         tol=0.0, workspace=None, stream=None, pm_wg_kib=0, no_tree=False):
+         tol=0.0, workspace=None, stream=None, pm_wg_kib=0, no_tree=False, inner_sweeps=1):
     """Run the full driver. H: list of device (R, I_n) float32 tensors, updated in place.
 
     Returns dict(fit=np.ndarray, lam=np.ndarray, iters_done=int).
@@ -259,7 +260,7 @@ def nncp(X, dims, R, iters, H, lam=None, update="hals", split=0, graph=True, rec
     fit = (ctypes.c_double * max(1, iters))()
     done = ctypes.c_int(0)
     o = Options(split=split, no_record_fit=0 if record_fit else 1, no_graph=0 if graph else 1, tol=tol,
-                pm_wg_kib=pm_wg_kib, no_tree=1 if no_tree else 0)
+                pm_wg_kib=pm_wg_kib, no_tree=1 if no_tree else 0, inner_sweeps=inner_sweeps)
     ws_ptr, ws_bytes = (None, 0)
     if workspace is not None:
         ws_ptr, ws_bytes = _ptr(workspace), workspace.numel() * workspace.element_size()
@@ -274,7 +275,7 @@ class Plan:
     """Persistent driver state: create once, run repeatedly, finish to normalise."""
 
     def __init__(self, X, dims, R, H, lam=None, update="hals", split=0, graph=True, phase_timers=False,
-                 workspace=None, stream=None, pm_wg_kib=0, no_tree=False):
+                 workspace=None, stream=None, pm_wg_kib=0, no_tree=False, inner_sweeps=1):
         import torch
         L = lib()
         self.dims, self.R, self.H, self.X = list(dims), R, list(H), X
@@ -286,7 +287,7 @@ class Plan:
         if lam is not None:
             lam_arr = (ctypes.c_double * R)(*np.asarray(lam, dtype=np.float64))
         o = Options(split=split, no_graph=0 if graph else 1, phase_timers=1 if phase_timers else 0,
-                    pm_wg_kib=pm_wg_kib, no_tree=1 if no_tree else 0)
+                    pm_wg_kib=pm_wg_kib, no_tree=1 if no_tree else 0, inner_sweeps=inner_sweeps)
         self._ws = workspace
         if workspace is None:
             nbytes = workspace_bytes(dims, R, _dtype_name(X), split, pm_wg_kib, no_tree)

@@ -83,3 +83,18 @@ def test_entry_points_reject_bad_arguments_without_a_device():
     assert L.nncp_partial_mttkrp(None, 0, 3, dims, 1, 0, None, 2, None, None) == -1
     assert L.nncp_nls_update(None, None, 4, 2, None, None, 0, None, None) == -1
     assert L.nncp_gram(None, 4, 2, None, None) == -1
+
+
+def test_inner_sweeps_option_layout_and_limit():
+    """The options struct keeps its size (inner_sweeps took a reserved slot) and
+    a sweep count above the maximum is rejected before any device work."""
+    from paper_1806_07985_amd import native
+    L = _lib()
+    assert ctypes.sizeof(native.Options) == 56
+    assert native.Options.inner_sweeps.offset == 32
+    dims = native._dims([4, 4, 4])
+    lam = (ctypes.c_double * 2)(1.0, 1.0)
+    H = (native.c_vp * 3)(ctypes.c_void_p(16), ctypes.c_void_p(16), ctypes.c_void_p(16))
+    o = native.Options(inner_sweeps=1025)
+    assert L.nncp(ctypes.c_void_p(16), 0, 3, dims, 2, 1, 0, H, lam, None, None, None, 0, ctypes.byref(o),
+                  None) == -1

@@ -240,6 +240,78 @@ def test_hals_converges_to_bruteforce_nnls_and_kkt(R):
     assert O.kkt_residual(W, S, M) < 1e-10
 
 
+def test_inner_sweeps_solve_each_block_exactly():
+    """With many HALS sweeps per block update the driver's block update is the
+    exact NNLS solution of that block's subproblem (Section II-B's exact
+    alternative to one sweep): checked against brute-force active-set
+    enumeration and against scipy's Lawson-Hanson NNLS on the Cholesky form."""
+    from scipy.optimize import nnls
+    dims, R = (6, 5, 4), 3
+    X, _ = inputs.planted(dims, R, 0.05, seed=41)
+    H0 = inputs.init_factors(dims, R, seed=42)
+    seen = []
+
+    def cb(it, n, d):
+        S, M, W = d["S"], d["M"], d["W"]
+        L = np.linalg.cholesky(S)
+        for i in range(M.shape[0]):
+            h = O.nnls_bruteforce(S, M[i])
+            scale = max(1.0, np.max(np.abs(h)))
+            np.testing.assert_allclose(W[i], h, rtol=0, atol=1e-9 * scale)
+            hs, _ = nnls(L.T, np.linalg.solve(L, M[i]))
+            np.testing.assert_allclose(W[i], hs, rtol=0, atol=1e-8 * scale)
+        assert O.kkt_residual(W, S, M) < 1e-9
+        seen.append((it, n))
+
+    out = O.nncp(X, H0, 2, update="hals", callback=cb, inner_sweeps=3000)
+    assert len(seen) == 2 * len(dims)
+    # exact block solves still decrease the objective monotonically
+    e = O.nncp(X, H0, 6, update="hals", inner_sweeps=3000)["eps"]
+    assert all(e[i + 1] <= e[i] + 1e-12 for i in range(len(e) - 1))
+    assert out["eps"][-1] <= e[1] + 1e-12
+
+
+@pytest.mark.parametrize("upd", ["hals", "mu"])
+def test_inner_sweeps_repeat_the_rule_on_fixed_subproblem(upd):
+    """k sweeps per block equal k applications of the one-sweep rule to the
+    same (S, M), and a single sweep is the default driver."""
+    dims, R = (5, 4, 6), 3
+    X, _ = inputs.planted(dims, R, 0.05, seed=43)
+    H0 = inputs.init_factors(dims, R, seed=44)
+    rule = {"hals": O.hals_update, "mu": O.mu_update}[upd]
+    base = O.nncp(X, H0, 3, update=upd)
+    same = O.nncp(X, H0, 3, update=upd, inner_sweeps=1)
+    for a, b in zip(base["H"], same["H"]):
+        assert np.array_equal(a, b)
+    # one block by hand: start from the normalised factors, mode 1, iteration 1
+    Hn, lam = [], np.ones(R)
+    for h in H0:
+        hn, nr = O.normalize_columns(h)
+        Hn.append(hn)
+        lam = lam * nr
+    G = [O.gram(h) for h in Hn]
+    M = O.mttkrp_direct(X, Hn, 0)
+    S = O.hadamard_others(G, 0)
+    W = Hn[0] * lam[None, :]
+    for _ in range(4):
+        W = rule(W, S, M)
+    got = {}
+
+    def cb(it, n, d):
+        if (it, n) == (0, 0):
+            got["W"] = d["W"].copy()
+
+    O.nncp(X, H0, 1, update=upd, inner_sweeps=4, callback=cb)
+    np.testing.assert_allclose(got["W"], W, rtol=1e-14, atol=0)
+    # more sweeps never increase the block objective
+    objs = []
+    Wk = Hn[0] * lam[None, :]
+    for _ in range(6):
+        Wk = rule(Wk, S, M)
+        objs.append(O.nls_objective(Wk, S, M))
+    assert all(objs[i + 1] <= objs[i] + 1e-12 * abs(objs[i]) for i in range(len(objs) - 1))
+
+
 def test_nnls_bruteforce_matches_unconstrained_when_interior():
     S, M = _subproblem(30, I=1, R=3)
     h = np.linalg.solve(S, M[0])
