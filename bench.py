@@ -311,35 +311,54 @@ def _serving_study(dev, n_pool, n_jobs, load_fracs, iters, budget_gb, max_active
 def _workloads_study(dev, steps):
     """The paper's other synthetic workloads at full size on one GPU: the 3-way
     1024^3 tensor of its strong-scaling runs and the 5-way 64^5 tensor of its 5D
-    runs, rank 32, planted + 1% noise (drawn on the device), HALS; iterations/s
-    with and without the dimension tree and the tree MTTKRP's HBM rate."""
+    runs (rank 32, FP32), and the 30012 x 1200 x 500 shape of its fMRI tensor
+    (rank 10, stored in BF16: 36 GB), planted + 1% noise drawn on the device,
+    HALS. Per workload: iterations/s with and without the dimension tree, the
+    tree MTTKRP's HBM rate, and the root split chosen by timing every split."""
     import torch
     from paper_1806_07985_amd import inputs, native
     out = {}
-    for name, dims, R in (("1024^3", (1024, 1024, 1024), 32), ("64^5", (64, 64, 64, 64, 64), 32)):
-        X = inputs.planted_device(dims, R, 0.01, seed=41, device=dev)
+    cases = (("1024^3", (1024, 1024, 1024), 32, "f32"), ("64^5", (64, 64, 64, 64, 64), 32, "f32"),
+             ("30012x1200x500 bf16", (30012, 1200, 500), 10, "bf16"))
+    for name, dims, R, dt in cases:
+        t_gen = time.perf_counter()
+        if dt == "f32":
+            X = inputs.planted_device(dims, R, 0.01, seed=41, device=dev)
+        else:
+            X = inputs.planted_device_slabs(dims, R, 0.01, seed=41, dtype=dt, device=dev)
+        torch.cuda.synchronize()
+        gen_s = time.perf_counter() - t_gen
         H0 = [h.astype(np.float32) for h in inputs.init_factors(dims, R, seed=42)]
-        res = {"dims": list(dims), "R": R}
-        for nt in (False, True):
+        res = {"dims": list(dims), "R": R, "tensor_dtype": dt, "generate_s": gen_s}
+        N = len(dims)
+        auto = min(range(1, N), key=lambda s_: int(np.prod(dims[:s_])) + int(np.prod(dims[s_:])))
+        Hd = [native.factor_to_device(h, device=dev) for h in H0]
+        tuned, split_ms = native.autotune_split(X, list(dims), R, Hd, reps=3)
+        res["split_default"] = auto
+        res["split_autotuned"] = tuned
+        res["mttkrp_ms_by_split"] = {str(s_ + 1): t for s_, t in enumerate(split_ms)}
+        runs = [("tree", False, auto), ("no_tree", True, auto)]
+        if tuned != auto:
+            runs.append(("tree_autotuned", False, tuned))
+        for key, nt, split in runs:
             Hd = [native.factor_to_device(h, device=dev) for h in H0]
-            plan = native.Plan(X, list(dims), R, Hd, no_tree=nt)
+            plan = native.Plan(X, list(dims), R, Hd, no_tree=nt, split=split)
             plan.run(2)
             torch.cuda.synchronize()
             t0 = time.perf_counter()
             plan.run(steps)
             torch.cuda.synchronize()
-            dt = time.perf_counter() - t0
+            dt_s = time.perf_counter() - t0
             ms = plan.time_mttkrp(5)
             fit = float(plan.fits()[-1]) if len(plan.fits()) else None
             plan.close()
-            key = "no_tree" if nt else "tree"
-            res[key] = {"iters_per_s": steps / dt, "mttkrp_ms": ms, "fit": fit}
-        # algorithmic tree bytes with the automatic split
-        N = len(dims)
-        best = min(range(1, N), key=lambda s_: int(np.prod(dims[:s_])) + int(np.prod(dims[s_:])))
-        pl, pr, mt = _algorithmic_bytes(list(dims), best, R, 4, 8)
-        res["split"] = best
-        res["tree"]["mttkrp_GBs"] = (pl + pr + mt) / (res["tree"]["mttkrp_ms"] * 1e-3) / 1e9
+            res[key] = {"iters_per_s": steps / dt_s, "mttkrp_ms": ms, "fit": fit, "split": split}
+            print(f"[bench] workload {name} {key}: {res[key]}", file=sys.stderr, flush=True)
+        sx, nb = (4, 8) if dt == "f32" else (2, 4)
+        for key in ("tree", "tree_autotuned"):
+            if key in res:
+                pl, pr, mt = _algorithmic_bytes(list(dims), res[key]["split"], R, sx, nb)
+                res[key]["mttkrp_GBs"] = (pl + pr + mt) / (res[key]["mttkrp_ms"] * 1e-3) / 1e9
         res["tree_speedup_iters"] = res["tree"]["iters_per_s"] / res["no_tree"]["iters_per_s"]
         res["tree_speedup_mttkrp"] = res["no_tree"]["mttkrp_ms"] / res["tree"]["mttkrp_ms"]
         out[name] = res
@@ -378,6 +397,7 @@ def main(argv=None):
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run a plain 1 GiB device-to-device copy (for scaling HBM counters)")
     args = ap.parse_args(argv)
+    t_start = time.perf_counter()
 
     if args.gpus != 1:
         print(json.dumps({"error": "this build runs on one GPU; multi-GPU sharding is design-only "
@@ -502,18 +522,27 @@ def main(argv=None):
     }
     del plan, pplan, Xd, Hd, Hp
     torch.cuda.empty_cache()
+    def note(what):
+        print(f"[bench] {what} done at {time.perf_counter() - t_start:.1f} s", file=sys.stderr, flush=True)
+
+    note("main workload")
     if not args.no_lowprec:
         out["lowprec"] = _lowprec_study(dev, args.lowprec_iters)
+        note("low-precision study")
     if not args.no_workloads:
         out["workloads"] = _workloads_study(dev, 20)
+        note("workloads study")
     if not args.no_batch:
         out["batch"] = _batch_study(dev, args.batch_jobs, args.batch_iters)
+        note("batch study")
     if not args.no_serve:
         loads = [float(x) for x in args.serve_loads.split(",") if x]
         out["serving"] = _serving_study(dev, args.serve_pool, args.serve_jobs, loads, args.serve_iters,
                                         budget_gb=96.0, max_active=64)
+        note("serving study")
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = _cpu_baseline(X, [h.astype(np.float64) for h in H0], args.cpu_iters)
+        note("CPU baseline")
     print(json.dumps(out), flush=True)
     return 0
 

@@ -142,6 +142,20 @@ int nncp_plan_time_node(nncp_plan* plan, int mode, int reps, double* ms_avg);
 int nncp_plan_time_mttkrp(nncp_plan* plan, int reps, double* ms_avg);
 int nncp_plan_destroy(nncp_plan* plan);
 
+/* Root-split autotuning (Section IV-A leaves the root split of the dimension
+ * tree free; the cost model picks the split with the smallest node
+ * temporaries, which is not always the fastest on the device). For every
+ * split s = 1..N-1 this builds a plan with the given options (split
+ * overridden), times one dimension-tree MTTKRP sweep of all N modes
+ * (nncp_plan_time_mttkrp: one warm-up sweep, then the average of `reps`),
+ * and returns the fastest in *best_split. X and H (device) are only read.
+ * ms (host, optional) receives N-1 values: ms[s-1] for split s. Each
+ * candidate allocates its own workspace for the call; a split whose
+ * workspace cannot be allocated gets ms = -1 and is skipped (NNCP_ENOMEM if
+ * none fits). Same argument rules as nncp_plan_create; reps >= 1. */
+int nncp_autotune_split(const void* X, int dtype, int N, const int64_t* dims, int R, float* const* H,
+                        const nncp_options* opt, int reps, int* best_split, double* ms, void* stream);
+
 /* Host copy of the fits recorded since the plan was created (or since the last
  * nncp_plan_run, which restarts the record): *count = outer iterations
  * completed; fit (host) receives min(*count, cap, 1024) values. */

@@ -400,8 +400,8 @@ hipError_t leaf_op(const nncp_plan* P, int n, bool scaled, const Sink& st, const
   return mttv_trail_launch(a, st);
 }
 
-hipError_t finalize_mode(const nncp_plan* P, int n, const void* M, int m_f64, int set_model, int next_mode,
-                         int do_fit, const Sink& st) {
+FinalizeArgs fin_args(const nncp_plan* P, int n, const void* M, int m_f64, int set_model, int next_mode,
+                      int do_fit) {
   const Problem& p = P->p;
   FinalizeArgs f{};
   f.W = P->H[n];
@@ -424,7 +424,7 @@ hipError_t finalize_mode(const nncp_plan* P, int n, const void* M, int m_f64, in
   f.fit_capacity = kFitCap;
   f.partial = P->finpart();
   f.nchunks = finalize_chunks(p.dims[n], p.R, &f.rows_per_chunk);
-  return finalize_launch(f, st);
+  return f;
 }
 
 enum { PH_PM = 0, PH_MTTV = 1, PH_NLS = 2, PH_GRAM = 3, PH_ERR = 4, PH_TOTAL = 5 };
@@ -472,7 +472,7 @@ hipError_t enqueue_iteration(nncp_plan* P, const Sink& st0, std::vector<std::pai
     if ((e = update_launch(u, st)) != hipSuccess) return e;
     const bool last = (n == p.N - 1);
     if ((e = mark(last ? PH_ERR : PH_GRAM)) != hipSuccess) return e;
-    if ((e = finalize_mode(P, n, M, m_f64, 1, (n + 1) % p.N, last ? 1 : 0, st)) != hipSuccess) return e;
+    if ((e = finalize_launch(fin_args(P, n, M, m_f64, 1, (n + 1) % p.N, last ? 1 : 0), st)) != hipSuccess) return e;
   }
   return mark(-1);
 }
@@ -609,7 +609,7 @@ int nncp_plan_create(nncp_plan** out, const void* X, int dtype, int N, const int
     return fail(NNCP_EDEVICE);
   // starting Grams / norms per mode, then model weights and S^(1)
   for (int k = 0; k < N; ++k)
-    if (finalize_mode(P, k, nullptr, 0, 0, -1, 0, s) != hipSuccess) return fail(NNCP_EDEVICE);
+    if (finalize_launch(fin_args(P, k, nullptr, 0, 0, -1, 0), s) != hipSuccess) return fail(NNCP_EDEVICE);
   if (init_model_launch(P->lam_in(), P->lam(), P->lam_model(), P->G(), P->S(), N, R, s) != hipSuccess)
     return fail(NNCP_EDEVICE);
   if (hipStreamSynchronize(s) != hipSuccess) return fail(NNCP_EDEVICE);
@@ -669,6 +669,41 @@ int nncp_plan_time_mttkrp(nncp_plan* P, int reps, double* ms_avg) {
   hipEventDestroy(e1);
   *ms_avg = (double)ms / reps;
   return st;
+}
+
+int nncp_autotune_split(const void* X, int dtype, int N, const int64_t* dims, int R, float* const* H,
+                        const nncp_options* opt, int reps, int* best_split, double* ms, void* stream) {
+  if (!X || !H || !dims || !best_split || reps < 1 || N < 2 || N > kMaxModes) return NNCP_EINVAL;
+  nncp_options o{};
+  if (opt) o = *opt;
+  o.no_graph = 1;  // no iteration is run: nothing to capture
+  int best = 0, st_any = NNCP_ENOMEM;
+  double best_ms = 0.0;
+  for (int s = 1; s < N; ++s) {
+    if (ms) ms[s - 1] = -1.0;
+    o.split = s;
+    nncp_plan* P = nullptr;
+    int st = nncp_plan_create(&P, X, dtype, N, dims, R, NNCP_HALS, H, nullptr, nullptr, 0, &o, stream);
+    if (st == NNCP_ENOMEM) {
+      (void)hipGetLastError();
+      continue;
+    }
+    if (st != NNCP_OK) return st;
+    double warm = 0.0, t = 0.0;
+    st = nncp_plan_time_mttkrp(P, 1, &warm);
+    if (st == NNCP_OK) st = nncp_plan_time_mttkrp(P, reps, &t);
+    nncp_plan_destroy(P);
+    if (st != NNCP_OK) return st;
+    st_any = NNCP_OK;
+    if (ms) ms[s - 1] = t;
+    if (best == 0 || t < best_ms) {
+      best = s;
+      best_ms = t;
+    }
+  }
+  if (best == 0) return st_any;
+  *best_split = best;
+  return NNCP_OK;
 }
 
 int nncp_plan_destroy(nncp_plan* P) {
@@ -1096,7 +1131,7 @@ int batch_build(nncp_batch* B) {
       }
       const size_t n = items.size() - off;
       if (n == 0) continue;
-      const unsigned cap = fam == KF_SMALL ? 8 * cus : cus;  // PM tiles: one group per CU
+      const unsigned cap = fam == KF_SMALL ? 8 * cus : cus;  // PM tiles, 1024-thread groups: one per CU
       nncp_batch::Launch l;
       l.family = fam;
       l.item_off = off;
@@ -1125,6 +1160,7 @@ int batch_build(nncp_batch* B) {
     if (l.family == KF_PM_F32) e = batch_launch_pm_f32(it, cnt, B->d_ops, l.grid, l.lds, B->cap);
     else if (l.family == KF_PM_16) e = batch_launch_pm_16(it, cnt, B->d_ops, l.grid, l.lds, B->cap);
     else if (l.family == KF_PM_16J1) e = batch_launch_pm_16j1(it, cnt, B->d_ops, l.grid, l.lds, B->cap);
+    else if (l.family == KF_FIN) e = batch_launch_fin(it, cnt, B->d_ops, l.grid, l.lds, B->cap);
     else e = batch_launch_small(it, cnt, B->d_ops, l.grid, l.lds, B->cap);
     if (e != hipSuccess) break;
   }

@@ -156,6 +156,7 @@ struct FinalizeArgs {
 int finalize_chunks(int64_t I, int R, int* rows_per_chunk);
 hipError_t finalize_launch(const FinalizeArgs& a, hipStream_t st);
 hipError_t finalize_launch(const FinalizeArgs& a, const Sink& sk);
+
 hipError_t pm_reduce_launch(const ReduceArgs& r, const Sink& sk);
 
 // lam_model = lam_in * prod_k lam[k]; S[0] = prod_{k != 0} G[k]
@@ -205,18 +206,22 @@ enum KKind : int {
   K_PM_REDUCE = 4,  // variant: t_f64
   K_MTTV_TRAIL = 5, // variant: t_f64
   K_MTTV_LEAD = 6,  // variant: group size * 10 + t_f64
-  K_UPDATE = 7,     // variant: values per lane (1 or 2)
-  K_FIN_SMALL = 8,
-  K_FIN_FUSED = 9,
+  K_UPDATE = 7,     // variant: R > 64: values per lane (1, 2); R <= 64: register columns (16, 32, 64)
+  K_FIN_FUSED = 9,  // R > 64: one row chunk
   K_GRAM_CHUNKS = 10,
-  K_FIN_TAIL = 11
+  K_FIN_TAIL = 11,
+  K_FIN1K = 12,     // R <= 64, one row chunk, 1024 threads; variant: R x R entries per thread
+  K_GRAM1K = 13,    // R <= 64, one row chunk's Gram partial, 1024 threads; variant as K_FIN1K
+  K_TAIL1K = 14     // R <= 64, sum of the chunk partials and the finish, 1024 threads
 };
 // Kernel families: one persistent batched kernel each. The 16-bit right-node
 // kernel for J == 1 (variant >= 100000) has a family of its own: it needs ~480
 // registers, and in one kernel with the other bodies it would make them spill.
-enum KFamily : int { KF_PM_F32 = 0, KF_PM_16 = 1, KF_SMALL = 2, KF_PM_16J1 = 3, KF_COUNT = 4 };
+// The Gram/finalize kernels for R <= 64 run 1024-thread groups: a family of their own.
+enum KFamily : int { KF_PM_F32 = 0, KF_PM_16 = 1, KF_SMALL = 2, KF_PM_16J1 = 3, KF_FIN = 4, KF_COUNT = 5 };
 inline int kfamily(int kind, int variant) {
   if (kind == K_PM_F32) return KF_PM_F32;
+  if (kind == K_FIN1K || kind == K_GRAM1K || kind == K_TAIL1K) return KF_FIN;
   if (kind == K_PM_16) return variant >= 100000 ? KF_PM_16J1 : KF_PM_16;
   if (kind == K_PACK16) return KF_PM_16;
   return KF_SMALL;
@@ -260,7 +265,7 @@ inline int kslot(int kind) {
     case K_PM_REDUCE: return 2;
     case K_MTTV_TRAIL: return 3;
     case K_UPDATE: return 4;
-    case K_GRAM_CHUNKS: return 5;
+    case K_GRAM_CHUNKS: case K_GRAM1K: return 5;
     default: return 6;
   }
 }
@@ -273,6 +278,8 @@ hipError_t batch_launch_pm_f32(const BItem* items, const int* count, const KOp* 
                                hipStream_t st);
 hipError_t batch_launch_pm_16(const BItem* items, const int* count, const KOp* ops, unsigned grid, size_t lds,
                               hipStream_t st);
+hipError_t batch_launch_fin(const BItem* items, const int* count, const KOp* ops, unsigned grid, size_t lds,
+                            hipStream_t st);
 hipError_t batch_launch_small(const BItem* items, const int* count, const KOp* ops, unsigned grid, size_t lds,
                               hipStream_t st);
 hipError_t batch_launch_pm_16j1(const BItem* items, const int* count, const KOp* ops, unsigned grid, size_t lds,

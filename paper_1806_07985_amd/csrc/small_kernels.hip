@@ -330,36 +330,19 @@ __global__ __launch_bounds__(NT) void update_kernel(UpdateArgs a) {
   update_body<VPL>(a, blockIdx.x);
 }
 
-// The same update for R <= RB <= 64 with lane k's column of S held in registers
-// and the column sweeps unrolled over RB (every broadcast uses a constant lane),
-// so the Gauss-Seidel chain touches no memory.
+// One row's update with lane k's column of S in registers (R <= RB <= 64): w =
+// W(row, k) scaled to the model, m = M(row, k), srow[r] = S(r, k) (zero for r >= R
+// or k >= R), invd = 1 / S(k, k) (zero unless positive). The column sweeps are
+// unrolled over RB, so every broadcast uses a constant lane and the Gauss-Seidel
+// chain touches no memory. Returns the new w.
 template <int RB>
-__device__ __forceinline__ void update_reg_body(const UpdateArgs& a, int bx) {
-  const int R = a.R;
-  const int k = threadIdx.x & 63;
-  const int64_t row = (int64_t)bx * (NT / 64) + (threadIdx.x >> 6);
-  if (row >= a.I) return;  // wave-uniform; no barrier in this kernel
-  const bool col = k < R;
-  const int kc = col ? k : 0;  // every load is unconditional (from a valid index), masked after
-  double srow[RB];
-  const double ls = a.lam_self[kc], lm = a.lam_model[kc];
-  const double w0 = (double)a.W[row + a.I * kc];
-  const double m0 = ldv(a.M, row + a.I * kc, a.m_f64);
-#pragma unroll
-  for (int r = 0; r < RB; ++r) srow[r] = a.S[(int64_t)(r < R ? r : 0) * R + kc];  // S symmetric
-  const double dg = a.S[(int64_t)kc * R + kc];
-  const double f = ls > 0.0 ? lm / ls : 0.0;
-  double w = col ? w0 * f : 0.0;
-  const double m = col ? m0 : 0.0;
-  const double invd = (col && dg > 0.0) ? 1.0 / dg : 0.0;
-#pragma unroll
-  for (int r = 0; r < RB; ++r)
-    if (!(col && r < R)) srow[r] = 0.0;
+__device__ __forceinline__ double update_row_reg(double w, const double m, const double (&srow)[RB],
+                                                 const double invd, const int k, const int R, const int update,
+                                                 const int sweeps) {
   double g = 0.0;
 #pragma unroll
   for (int r = 0; r < RB; ++r) g += readlane_f64(w, r) * srow[r];
-  const int sweeps = a.sweeps > 1 ? a.sweeps : 1;
-  if (a.update == NNCP_HALS) {
+  if (update == NNCP_HALS) {
     auto sweep = [&]() {
       // fresh copies of the lane index and the rank per sweep: the per-column
       // compares below then stay inside the sweep instead of being hoisted out of
@@ -393,6 +376,41 @@ __device__ __forceinline__ void update_reg_body(const UpdateArgs& a, int bx) {
       w = w * m / den;
     }
   }
+  return w;
+}
+
+// Lane k's column of S (zero outside R x R) and 1 / S(k, k), loaded unconditionally.
+template <int RB>
+__device__ __forceinline__ void load_s_column(const UpdateArgs& a, int k, double (&srow)[RB], double& invd) {
+  const int R = a.R;
+  const bool col = k < R;
+  const int kc = col ? k : 0;
+#pragma unroll
+  for (int r = 0; r < RB; ++r) srow[r] = a.S[(int64_t)(r < R ? r : 0) * R + kc];  // S symmetric
+  const double dg = a.S[(int64_t)kc * R + kc];
+  invd = (col && dg > 0.0) ? 1.0 / dg : 0.0;
+#pragma unroll
+  for (int r = 0; r < RB; ++r)
+    if (!(col && r < R)) srow[r] = 0.0;
+}
+
+// The update for R <= RB <= 64: one wave per row.
+template <int RB>
+__device__ __forceinline__ void update_reg_body(const UpdateArgs& a, int bx) {
+  const int R = a.R;
+  const int k = threadIdx.x & 63;
+  const int64_t row = (int64_t)bx * (NT / 64) + (threadIdx.x >> 6);
+  if (row >= a.I) return;  // wave-uniform; no barrier in this kernel
+  const bool col = k < R;
+  const int kc = col ? k : 0;  // every load is unconditional (from a valid index), masked after
+  const double ls = a.lam_self[kc], lm = a.lam_model[kc];
+  const double w0 = (double)a.W[row + a.I * kc];
+  const double m0 = ldv(a.M, row + a.I * kc, a.m_f64);
+  double srow[RB], invd;
+  load_s_column<RB>(a, k, srow, invd);
+  const double f = ls > 0.0 ? lm / ls : 0.0;
+  const double w = update_row_reg<RB>(col ? w0 * f : 0.0, col ? m0 : 0.0, srow, invd, k, R, a.update,
+                                      a.sweeps > 1 ? a.sweeps : 1);
   if (col) a.W[row + a.I * k] = (float)w;
 }
 template <int RB>
@@ -515,319 +533,10 @@ __device__ void finalize_tail(const FinalizeArgs& a, double* fl, double* sh) {
   }
 }
 
-// Register-blocked Gram for R <= 64. W rows are staged in LDS (FP64) a few
-// dozen KB at a time; thread (block b, phase p) accumulates the 4 x 4 block b of
-// W^T W over rows p, p + nph, ... in registers, so each row costs 8 LDS reads for
-// 16 FMAs. Phases are summed through LDS in phase order. Index loops advance
-// incrementally (no integer division in a loop): with one wave per SIMD every
-// instruction's latency is exposed.
+// Ranks up to this use the 1024-thread Gram kernels below (4 x 4 register blocks of W^T W).
 constexpr int kSmallMaxR = 64;
 
 __host__ __device__ inline int gram_r4(int R) { return (R + 3) & ~3; }
-__host__ __device__ inline int gram_sub_rows(int R) { return 4096 / gram_r4(R); }
-// LDS doubles of the staging/partials area
-__host__ __device__ inline int gram_work_doubles(int R) {
-  const int stage = gram_sub_rows(R) * gram_r4(R), phases = NT * 16;
-  return stage > phases ? stage : phases;
-}
-
-// Gram (and beta = sum M o W when the fit is due) of rows [r0, r1) into out[RR]
-// and out[RR]. out may be global (a chunk's partial) or LDS. Block-wide.
-__device__ void gram_rows_blocked(const FinalizeArgs& a, int64_t r0, int64_t r1, double* work, double* sh,
-                                  double* out) {
-  const int R = a.R, RR = R * R;
-  const int R4 = gram_r4(R), nb4 = R4 >> 2, nblk = nb4 * nb4;
-  const int nph = NT / nblk;
-  const int sub = gram_sub_rows(R);
-  const int tid = threadIdx.x;
-  const bool active = tid < nblk * nph;
-  const int blk = tid % nblk, ph = tid / nblk;
-  const int bx = blk / nb4, by = blk - (blk / nb4) * nb4;
-  const bool fit = a.do_fit && a.M;
-  double acc[4][4];
-#pragma unroll
-  for (int i = 0; i < 4; ++i)
-#pragma unroll
-    for (int j = 0; j < 4; ++j) acc[i][j] = 0.0;
-  double bsum = 0.0;
-  for (int64_t s0 = r0; s0 < r1; s0 += sub) {
-    const int cnt = (int)((r1 - s0) < sub ? (r1 - s0) : sub);
-    __syncthreads();
-    // element e = tid + NT*q of the cnt x R4 tile (q < 16: cnt * R4 <= 4096):
-    // k = e / cnt, rw = e % cnt, stepped. All of a thread's loads are issued
-    // before any is used, so the tile costs one memory round trip, not sixteen.
-    const int dk = NT / cnt, drw = NT - dk * cnt;
-    constexpr int QMAX = 4096 / NT;
-    const int k0 = tid / cnt, rw0 = tid - k0 * cnt;
-    float wf[QMAX];
-    {
-      int k = k0, rw = rw0;
-#pragma unroll
-      for (int q = 0; q < QMAX; ++q) {
-        // unconditional load from a valid index, zeroed afterwards: a guarded
-        // load would wait for its value at the branch join, one by one
-        const bool ok = tid + NT * q < cnt * R4 && k < R;
-        const float w = a.W[ok ? s0 + rw + a.I * (int64_t)k : 0];
-        wf[q] = ok ? w : 0.f;
-        k += dk;
-        rw += drw;
-        if (rw >= cnt) {
-          rw -= cnt;
-          ++k;
-        }
-      }
-    }
-    if (fit) {
-      double mv[QMAX];
-      int k = k0, rw = rw0;
-#pragma unroll
-      for (int q = 0; q < QMAX; ++q) {
-        const bool ok = tid + NT * q < cnt * R4 && k < R;
-        const double m = ldv(a.M, ok ? s0 + rw + a.I * (int64_t)k : 0, a.m_f64);
-        mv[q] = ok ? m : 0.0;
-        k += dk;
-        rw += drw;
-        if (rw >= cnt) {
-          rw -= cnt;
-          ++k;
-        }
-      }
-#pragma unroll
-      for (int q = 0; q < QMAX; ++q) bsum += (double)wf[q] * mv[q];
-    }
-    {
-      int k = k0, rw = rw0;
-#pragma unroll
-      for (int q = 0; q < QMAX; ++q) {
-        if (tid + NT * q < cnt * R4) work[rw * R4 + k] = (double)wf[q];
-        k += dk;
-        rw += drw;
-        if (rw >= cnt) {
-          rw -= cnt;
-          ++k;
-        }
-      }
-    }
-    __syncthreads();
-    if (active) {
-      // four rows per step: their 32 LDS reads are in flight together
-      int r = ph;
-      for (; r + 3 * nph < cnt; r += 4 * nph) {
-        double x[4][4], y[4][4];
-#pragma unroll
-        for (int u = 0; u < 4; ++u) {
-          const double* row = work + (r + u * nph) * R4;
-#pragma unroll
-          for (int i = 0; i < 4; ++i) {
-            x[u][i] = row[4 * bx + i];
-            y[u][i] = row[4 * by + i];
-          }
-        }
-#pragma unroll
-        for (int u = 0; u < 4; ++u)
-#pragma unroll
-          for (int i = 0; i < 4; ++i)
-#pragma unroll
-            for (int j = 0; j < 4; ++j) acc[i][j] += x[u][i] * y[u][j];
-      }
-      for (; r < cnt; r += nph) {
-        const double* row = work + r * R4;
-        double x[4], y[4];
-#pragma unroll
-        for (int i = 0; i < 4; ++i) {
-          x[i] = row[4 * bx + i];
-          y[i] = row[4 * by + i];
-        }
-#pragma unroll
-        for (int i = 0; i < 4; ++i)
-#pragma unroll
-          for (int j = 0; j < 4; ++j) acc[i][j] += x[i] * y[j];
-      }
-    }
-  }
-  const double beta = block_sum(bsum, sh);
-  __syncthreads();
-  if (active) {
-    // layout [entry q][phase][block]: consecutive lanes write consecutive doubles
-#pragma unroll
-    for (int i = 0; i < 4; ++i)
-#pragma unroll
-      for (int j = 0; j < 4; ++j) work[((size_t)(i * 4 + j) * nph + ph) * nblk + blk] = acc[i][j];
-  }
-  __syncthreads();
-  {
-    const int dx = NT / R, dy = NT - dx * R;
-    int x = tid / R, y = tid - x * R;
-    for (int e = tid; e < RR; e += NT) {
-      const int b = (x >> 2) * nb4 + (y >> 2), q = (x & 3) * 4 + (y & 3);
-      const double* src = work + (size_t)q * nph * nblk + b;
-      double v = 0.0;
-      for (int p = 0; p < nph; ++p) v += src[(size_t)p * nblk];
-      out[e] = v;
-      x += dx;
-      y += dy;
-      if (y >= R) {
-        y -= R;
-        ++x;
-      }
-    }
-  }
-  if (tid == 0) out[RR] = beta;
-}
-
-// The product of the Grams of the modes other than `mode` and `next_mode` (for
-// S of the next mode) and S of this mode (for gamma), into LDS.
-// (R <= 64: a thread's entries e = tid + NT*q, q < 16; each mode's loads are
-// issued together)
-__device__ __forceinline__ void fin_prefetch(const FinalizeArgs& a, double* P, double* Sm) {
-  const int RR = a.R * a.R;
-  constexpr int QM = kSmallMaxR * kSmallMaxR / NT;
-  if (a.next_mode >= 0) {
-    double v[QM];
-#pragma unroll
-    for (int q = 0; q < QM; ++q) v[q] = 1.0;
-    for (int k = 0; k < a.N; ++k) {
-      if (k == a.next_mode || k == a.mode) continue;
-      double t[QM];
-#pragma unroll
-      for (int q = 0; q < QM; ++q) {
-        const int e = threadIdx.x + NT * q;
-        t[q] = a.G[(int64_t)k * RR + (e < RR ? e : 0)];
-      }
-#pragma unroll
-      for (int q = 0; q < QM; ++q) v[q] *= t[q];
-    }
-#pragma unroll
-    for (int q = 0; q < QM; ++q) {
-      const int e = threadIdx.x + NT * q;
-      if (e < RR) P[e] = v[q];
-    }
-  }
-  if (a.do_fit) {
-    double t[QM];
-#pragma unroll
-    for (int q = 0; q < QM; ++q) {
-      const int e = threadIdx.x + NT * q;
-      t[q] = a.S[(int64_t)a.mode * RR + (e < RR ? e : 0)];
-    }
-#pragma unroll
-    for (int q = 0; q < QM; ++q) {
-      const int e = threadIdx.x + NT * q;
-      if (e < RR) Sm[e] = t[q];
-    }
-  }
-}
-
-// lambda = sqrt(diag Gh), the normalised Gram, S of the next mode and the fit,
-// from the raw Gram Gh[RR] and beta Gh[RR] in LDS. il (LDS, R doubles) receives
-// 1/lambda (0 for a zero column) so each entry costs two multiplications.
-__device__ void fin_tail_lds(const FinalizeArgs& a, const double* Gh, const double* P, const double* Sm,
-                             double* il, double* sh) {
-  const int R = a.R, RR = R * R, tid = threadIdx.x;
-  if (a.gram_raw)
-    for (int e = tid; e < RR; e += NT) a.gram_raw[e] = Gh[e];
-  double* lamm = a.lam + (int64_t)a.mode * R;
-  for (int k = tid; k < R; k += NT) {
-    const double l = sqrt(Gh[k * R + k]);
-    lamm[k] = l;
-    if (a.set_model) a.lam_model[k] = l;
-    il[k] = l > 0.0 ? 1.0 / l : 0.0;
-  }
-  __syncthreads();
-  double* Gm = a.G + (int64_t)a.mode * RR;
-  double* Sn = a.next_mode >= 0 ? a.S + (int64_t)a.next_mode * RR : nullptr;
-  double gp = 0.0;
-  const int dx = NT / R, dy = NT - dx * R;
-  int x = tid / R, y = tid - x * R;
-  for (int e = tid; e < RR; e += NT) {
-    const double g = Gh[e] * il[x] * il[y];
-    Gm[e] = g;
-    if (Sn) Sn[e] = P[e] * g;
-    if (a.do_fit) gp += Sm[e] * Gh[e];
-    x += dx;
-    y += dy;
-    if (y >= R) {
-      y -= R;
-      ++x;
-    }
-  }
-  if (a.do_fit) {
-    // gamma = 1^T (S^(mode) * G_hat) 1 with G_hat the Gram of the unnormalised factor
-    const double gamma = block_sum(gp, sh);
-    if (tid == 0) {
-      const double alpha = a.alpha[0];
-      double num = alpha - 2.0 * Gh[RR] + gamma;
-      num = num > 0.0 ? num : 0.0;
-      const double eps = alpha > 0.0 ? sqrt(num / alpha) : 0.0;
-      const int it = *a.iter_counter;
-      if (it < a.fit_capacity) a.fit_out[it] = 1.0 - eps;
-      *a.iter_counter = it + 1;
-    }
-  }
-}
-
-// One row chunk: one work-group does everything.
-__device__ __forceinline__ void finalize_small_body(const FinalizeArgs& a) {
-  extern __shared__ double lds[];
-  __shared__ double sh[NT / 64];
-  const int RR = a.R * a.R;
-  double* Gh = lds;          // RR + 1
-  double* P = Gh + RR + 1;   // RR
-  double* Sm = P + RR;       // RR
-  double* il = Sm + RR;      // 64
-  double* work = il + kSmallMaxR;
-  fin_prefetch(a, P, Sm);
-  gram_rows_blocked(a, 0, a.I, work, sh, Gh);
-  __syncthreads();
-  fin_tail_lds(a, Gh, P, Sm, il, sh);
-}
-
-// Several row chunks: chunk bx's Gram into partial[bx], then one work-group sums
-// the partials in chunk order and finishes.
-__device__ __forceinline__ void gram_chunks_blocked_body(const FinalizeArgs& a, int bx) {
-  extern __shared__ double lds[];
-  __shared__ double sh[NT / 64];
-  const int64_t r0 = (int64_t)bx * a.rows_per_chunk;
-  const int64_t r1 = r0 + a.rows_per_chunk < a.I ? r0 + a.rows_per_chunk : a.I;
-  gram_rows_blocked(a, r0, r1, lds, sh, a.partial + (size_t)bx * (a.R * a.R + 1));
-}
-__device__ __forceinline__ void finalize_tail_blocked_body(const FinalizeArgs& a) {
-  extern __shared__ double lds[];
-  __shared__ double sh[NT / 64];
-  const int RR = a.R * a.R;
-  double* Gh = lds;
-  double* P = Gh + RR + 1;
-  double* Sm = P + RR;
-  double* il = Sm + RR;
-  fin_prefetch(a, P, Sm);
-  // chunk-major: each chunk's loads of all this thread's entries are issued
-  // together, then added in chunk order (RR + 1 <= 4097 = 17 x NT)
-  constexpr int EPT = (kSmallMaxR * kSmallMaxR + 1 + NT - 1) / NT;
-  double v[EPT];
-#pragma unroll
-  for (int q = 0; q < EPT; ++q) v[q] = 0.0;
-  for (int c = 0; c < a.nchunks; ++c) {
-    const double* pc = a.partial + (size_t)c * (RR + 1);
-    double t[EPT];
-#pragma unroll
-    for (int q = 0; q < EPT; ++q) {
-      const int e = threadIdx.x + NT * q;
-      const double u = pc[e < RR + 1 ? e : 0];
-      t[q] = e < RR + 1 ? u : 0.0;
-    }
-#pragma unroll
-    for (int q = 0; q < EPT; ++q) v[q] += t[q];
-  }
-#pragma unroll
-  for (int q = 0; q < EPT; ++q) {
-    const int e = threadIdx.x + NT * q;
-    if (e < RR + 1) Gh[e] = v[q];
-  }
-  __syncthreads();
-  fin_tail_lds(a, Gh, P, Sm, il, sh);
-}
-
-__global__ __launch_bounds__(NT) void finalize_small_kernel(FinalizeArgs a) { finalize_small_body(a); }
 
 // One block does both stages (a single row chunk).
 __device__ __forceinline__ void finalize_fused_body(const FinalizeArgs& a) {
@@ -850,10 +559,373 @@ __device__ __forceinline__ void finalize_tail_body(const FinalizeArgs& a) {
 __global__ __launch_bounds__(NT) void finalize_fused_kernel(FinalizeArgs a) { finalize_fused_body(a); }
 __global__ __launch_bounds__(NT) void gram_chunks_kernel(FinalizeArgs a) { gram_chunks_body(a, blockIdx.x); }
 __global__ __launch_bounds__(NT) void finalize_tail_kernel(FinalizeArgs a) { finalize_tail_body(a); }
-__global__ __launch_bounds__(NT) void gram_chunks_blocked_kernel(FinalizeArgs a) {
-  gram_chunks_blocked_body(a, blockIdx.x);
+
+// ---------------------------------------------------------------------------
+// Gram, lambda, next S and the fit for R <= 64 with 1024-thread work-groups.
+// Sixteen waves per group (four per SIMD) hide one another's latencies where a
+// 4-wave group left every latency exposed; only the upper triangle of 4x4
+// blocks of W^T W is computed (the lower one is its mirror, bit for bit); and
+// every global value the group needs is requested before the first is used.
+// The staged rows have an odd stride in doubles, so a wave's column writes
+// spread over the LDS banks. Entry e of an R x R matrix belongs to thread
+// e mod 1024, slot e / 1024 (at most four slots).
+constexpr int NTF = 1024;
+constexpr int kFinStage = 8192;           // staged elements (rows x R4) per round
+constexpr int kFinQS = kFinStage / NTF;   // staged elements per thread
+constexpr int kFinMaxPh = 32;             // at most this many row phases per block
+
+__host__ __device__ inline int fin_nb4(int R) { return gram_r4(R) >> 2; }
+__host__ __device__ inline int fin_nblk(int R) { return fin_nb4(R) * (fin_nb4(R) + 1) / 2; }
+__host__ __device__ inline int fin_nph(int R) {
+  const int p = NTF / fin_nblk(R);
+  return p < kFinMaxPh ? p : kFinMaxPh;
 }
-__global__ __launch_bounds__(NT) void finalize_tail_blocked_kernel(FinalizeArgs a) { finalize_tail_blocked_body(a); }
+__host__ __device__ inline int fin_rows(int R) { return kFinStage / gram_r4(R); }
+__host__ __device__ inline int fin_stride(int R) { return gram_r4(R) + 1; }
+// dynamic LDS doubles: the staged rows, reused for the phase partials (<= 128 KB)
+__host__ __device__ inline int fin_work_doubles(int R) {
+  const int st = fin_rows(R) * fin_stride(R), ph = 16 * fin_nph(R) * fin_nblk(R);
+  return st > ph ? st : ph;
+}
+// R x R entries per thread: 1, 2 or 4
+__host__ __device__ inline int fin_ep(int R) { return R * R <= NTF ? 1 : (R * R <= 2 * NTF ? 2 : 4); }
+
+// block (bx, by), bx <= by, of upper-triangle index b (row-major over the triangle)
+__device__ __forceinline__ void tri_block(int b, int nb4, int& bx, int& by) {
+  int x = 0;
+  while (b >= nb4 - x) {
+    b -= nb4 - x;
+    ++x;
+  }
+  bx = x;
+  by = x + b;
+}
+__device__ __forceinline__ int tri_index(int bx, int by, int nb4) { return bx * nb4 - bx * (bx - 1) / 2 + (by - bx); }
+
+// Stage-load of rows [s0, s0 + cnt): element e = tid + NTF*q is (row s0 + e mod cnt,
+// column e / cnt); columns R..R4-1 are zero. Loads are unconditional (clamped index).
+__device__ __forceinline__ void fin_load(const FinalizeArgs& a, int64_t s0, int cnt, bool fit, float (&wf)[kFinQS],
+                                         double (&mv)[kFinQS]) {
+  const int R4 = gram_r4(a.R), tid = threadIdx.x;
+  const int dk = NTF / cnt, drw = NTF - dk * cnt;
+  int k = tid / cnt, rw = tid - (tid / cnt) * cnt;
+#pragma unroll
+  for (int q = 0; q < kFinQS; ++q) {
+    const bool ok = tid + NTF * q < cnt * R4 && k < a.R;
+    const int64_t idx = ok ? s0 + rw + a.I * (int64_t)k : 0;
+    const float w = a.W[idx];
+    wf[q] = ok ? w : 0.f;
+    if (fit) {
+      const double m = ldv(a.M, idx, a.m_f64);
+      mv[q] = ok ? m : 0.0;
+    }
+    k += dk;
+    rw += drw;
+    if (rw >= cnt) {
+      rw -= cnt;
+      ++k;
+    }
+  }
+}
+__device__ __forceinline__ void fin_store(const FinalizeArgs& a, int cnt, const float (&wf)[kFinQS], double* work) {
+  const int R4 = gram_r4(a.R), str = R4 + 1, tid = threadIdx.x;
+  const int dk = NTF / cnt, drw = NTF - dk * cnt;
+  int k = tid / cnt, rw = tid - (tid / cnt) * cnt;
+#pragma unroll
+  for (int q = 0; q < kFinQS; ++q) {
+    if (tid + NTF * q < cnt * R4) work[rw * str + k] = (double)wf[q];
+    k += dk;
+    rw += drw;
+    if (rw >= cnt) {
+      rw -= cnt;
+      ++k;
+    }
+  }
+}
+
+// W^T W over rows [r0, r1) into g[q] (entry tid + NTF*q; raw, unnormalised) and
+// beta = sum of M o W over those rows (thread 0, when the fit is due). Block-wide;
+// work: fin_work_doubles. The code is kept short on purpose: these kernels run
+// once per mode on one group, and their time follows the instruction bytes that
+// must be fetched more than the arithmetic.
+template <int EP>
+__device__ __forceinline__ void gram1k_rows(const FinalizeArgs& a, int64_t r0, int64_t r1, double* work, double* sh,
+                                            double (&g)[EP], double& beta) {
+  const int R = a.R, RR = R * R, tid = threadIdx.x;
+  const int nb4 = fin_nb4(R), nblk = fin_nblk(R), nph = fin_nph(R), str = fin_stride(R), sub = fin_rows(R);
+  const bool active = tid < nblk * nph;
+  const int blk = tid % nblk, ph = tid / nblk;
+  int bx, by;
+  tri_block(active ? blk : 0, nb4, bx, by);
+  const bool fit = a.do_fit && a.M;
+  double acc[4][4];
+#pragma unroll
+  for (int i = 0; i < 4; ++i)
+#pragma unroll
+    for (int j = 0; j < 4; ++j) acc[i][j] = 0.0;
+  double bsum = 0.0;
+  for (int64_t s0 = r0; s0 < r1; s0 += sub) {
+    const int cnt = (int)(r1 - s0 < sub ? r1 - s0 : sub);
+    float wf[kFinQS];
+    double mv[kFinQS];
+    fin_load(a, s0, cnt, fit, wf, mv);
+    if (fit) {
+#pragma unroll
+      for (int q = 0; q < kFinQS; ++q) bsum += (double)wf[q] * mv[q];
+    }
+    __syncthreads();  // the previous round's rows are no longer read
+    fin_store(a, cnt, wf, work);
+    __syncthreads();
+    if (active) {
+      for (int r = ph; r < cnt; r += nph) {
+        const double* row = work + r * str;
+        double x[4], y[4];
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+          x[i] = row[4 * bx + i];
+          y[i] = row[4 * by + i];
+        }
+#pragma unroll
+        for (int i = 0; i < 4; ++i)
+#pragma unroll
+          for (int j = 0; j < 4; ++j) acc[i][j] += x[i] * y[j];
+      }
+    }
+  }
+  beta = fit ? block_sum(bsum, sh) : 0.0;
+  // phases summed in phase order through LDS: [block entry][phase][block]
+  __syncthreads();
+  if (active) {
+#pragma unroll
+    for (int i = 0; i < 4; ++i)
+#pragma unroll
+      for (int j = 0; j < 4; ++j) work[((i * 4 + j) * nph + ph) * nblk + blk] = acc[i][j];
+  }
+  __syncthreads();
+#pragma unroll
+  for (int q = 0; q < EP; ++q) {
+    const int e = tid + NTF * q;
+    const int ec = e < RR ? e : 0;
+    const int x = ec / R, y = ec - (ec / R) * R;
+    const int X = x >> 2, Y = y >> 2;
+    const int b = X <= Y ? tri_index(X, Y, nb4) : tri_index(Y, X, nb4);
+    const int qv = X <= Y ? (x & 3) * 4 + (y & 3) : (y & 3) * 4 + (x & 3);
+    const double* src = work + (size_t)qv * nph * nblk + b;
+    double s = 0.0;
+    for (int p0 = 0; p0 < nph; p0 += 8) {  // eight loads in flight, added in order
+      double t[8];
+#pragma unroll
+      for (int u = 0; u < 8; ++u) t[u] = src[(size_t)(p0 + u < nph ? p0 + u : 0) * nblk];
+#pragma unroll
+      for (int u = 0; u < 8; ++u) s += p0 + u < nph ? t[u] : 0.0;
+    }
+    g[q] = s;
+  }
+}
+
+// What the tail needs from global memory, requested up front: the product P of
+// the Grams of the modes other than `mode` and `next_mode` (for S of the next
+// mode), S of this mode (for gamma), alpha and the iteration counter.
+template <int EP>
+struct FinPre {
+  double P[EP], Sm[EP];
+  double alpha;
+  int it;
+};
+template <int EP>
+__device__ __forceinline__ void fin_preload(const FinalizeArgs& a, FinPre<EP>& p) {
+  const int RR = a.R * a.R, tid = threadIdx.x;
+#pragma unroll
+  for (int q = 0; q < EP; ++q) p.P[q] = 1.0;
+  if (a.next_mode >= 0) {
+    const int lo = a.mode < a.next_mode ? a.mode : a.next_mode;
+    const int hi = a.mode < a.next_mode ? a.next_mode : a.mode;
+#pragma unroll
+    for (int j = 0; j < kMaxModes - 2; ++j) {
+      int k = j;
+      if (k >= lo) ++k;
+      if (k >= hi) ++k;
+      const bool use = k < a.N;
+      const int kc = use ? k : 0;
+      double t[EP];
+#pragma unroll
+      for (int q = 0; q < EP; ++q) {
+        const int e = tid + NTF * q;
+        t[q] = a.G[(int64_t)kc * RR + (e < RR ? e : 0)];
+      }
+#pragma unroll
+      for (int q = 0; q < EP; ++q) p.P[q] *= use ? t[q] : 1.0;
+    }
+  }
+#pragma unroll
+  for (int q = 0; q < EP; ++q) p.Sm[q] = 0.0;
+  p.alpha = 0.0;
+  p.it = 0;
+  if (a.do_fit) {  // S, alpha and the counter are only there when the fit is due
+#pragma unroll
+    for (int q = 0; q < EP; ++q) {
+      const int e = tid + NTF * q;
+      p.Sm[q] = a.S[(int64_t)a.mode * RR + (e < RR ? e : 0)];
+    }
+    p.alpha = a.alpha[0];
+    p.it = *a.iter_counter;
+  }
+}
+
+// lambda, normalised Gram, S of the next mode, the raw Gram if asked, and the fit.
+template <int EP>
+__device__ __forceinline__ void fin1k_tail(const FinalizeArgs& a, const double (&g)[EP], double beta, const FinPre<EP>& p,
+                           double* sh) {
+  __shared__ double dg[kSmallMaxR], il[kSmallMaxR];
+  const int R = a.R, RR = R * R, tid = threadIdx.x;
+  int xs[EP], ys[EP];
+#pragma unroll
+  for (int q = 0; q < EP; ++q) {
+    const int e = tid + NTF * q;
+    const int ec = e < RR ? e : 0;
+    xs[q] = ec / R;
+    ys[q] = ec - xs[q] * R;
+    if (e < RR && xs[q] == ys[q]) dg[xs[q]] = g[q];
+  }
+  __syncthreads();
+  double* lamm = a.lam + (int64_t)a.mode * R;
+  if (tid < R) {
+    const double l = sqrt(dg[tid]);
+    lamm[tid] = l;
+    if (a.set_model) a.lam_model[tid] = l;
+    il[tid] = l > 0.0 ? 1.0 / l : 0.0;
+  }
+  __syncthreads();
+  double* Gm = a.G + (int64_t)a.mode * RR;
+  double* Sn = a.next_mode >= 0 ? a.S + (int64_t)a.next_mode * RR : nullptr;
+  double gp = 0.0;
+#pragma unroll
+  for (int q = 0; q < EP; ++q) {
+    const int e = tid + NTF * q;
+    if (e < RR) {
+      const double gn = g[q] * il[xs[q]] * il[ys[q]];
+      Gm[e] = gn;
+      if (Sn) Sn[e] = p.P[q] * gn;
+      if (a.gram_raw) a.gram_raw[e] = g[q];
+      gp += p.Sm[q] * g[q];
+    }
+  }
+  if (a.do_fit) {
+    // gamma = 1^T (S^(mode) * G_hat) 1 with G_hat the Gram of the unnormalised factor
+    const double gamma = block_sum(gp, sh);
+    if (tid == 0) {
+      double num = p.alpha - 2.0 * beta + gamma;
+      num = num > 0.0 ? num : 0.0;
+      const double eps = p.alpha > 0.0 ? sqrt(num / p.alpha) : 0.0;
+      if (p.it < a.fit_capacity) a.fit_out[p.it] = 1.0 - eps;
+      *a.iter_counter = p.it + 1;
+    }
+  }
+}
+
+// One row chunk: everything in one group.
+template <int EP>
+__device__ __forceinline__ void fin1k_body(const FinalizeArgs& a) {
+  extern __shared__ double lds[];
+  __shared__ double sh[NTF / 64];
+  FinPre<EP> p;
+  fin_preload(a, p);
+  double g[EP], beta;
+  gram1k_rows<EP>(a, 0, a.I, lds, sh, g, beta);
+  fin1k_tail<EP>(a, g, beta, p, sh);
+}
+// Several row chunks: chunk bx's Gram and beta into partial[bx] ...
+template <int EP>
+__device__ __forceinline__ void gram1k_chunk_body(const FinalizeArgs& a, int bx) {
+  extern __shared__ double lds[];
+  __shared__ double sh[NTF / 64];
+  const int RR = a.R * a.R;
+  const int64_t r0 = (int64_t)bx * a.rows_per_chunk;
+  const int64_t r1 = r0 + a.rows_per_chunk < a.I ? r0 + a.rows_per_chunk : a.I;
+  double g[EP], beta;
+  gram1k_rows<EP>(a, r0, r1, lds, sh, g, beta);
+  double* out = a.partial + (size_t)bx * (RR + 1);
+#pragma unroll
+  for (int q = 0; q < EP; ++q) {
+    const int e = threadIdx.x + NTF * q;
+    if (e < RR) out[e] = g[q];
+  }
+  if (threadIdx.x == 0) out[RR] = beta;
+}
+// ... then one group sums the partials in chunk order and finishes.
+template <int EP>
+__device__ __forceinline__ void tail1k_body(const FinalizeArgs& a) {
+  __shared__ double sh[NTF / 64];
+  const int RR = a.R * a.R, tid = threadIdx.x;
+  FinPre<EP> p;
+  fin_preload(a, p);
+  double g[EP];
+#pragma unroll
+  for (int q = 0; q < EP; ++q) g[q] = 0.0;
+  double beta = 0.0;
+  constexpr int CB = EP == 1 ? 16 : (EP == 2 ? 8 : 4);  // chunks whose loads fly together
+  for (int c0 = 0; c0 < a.nchunks; c0 += CB) {
+    double t[CB][EP], tb[CB];
+#pragma unroll
+    for (int u = 0; u < CB; ++u) {
+      const int c = c0 + u < a.nchunks ? c0 + u : 0;
+      const double* pc = a.partial + (size_t)c * (RR + 1);
+#pragma unroll
+      for (int q = 0; q < EP; ++q) {
+        const int e = tid + NTF * q;
+        t[u][q] = pc[e < RR ? e : 0];
+      }
+      tb[u] = pc[RR];
+    }
+#pragma unroll
+    for (int u = 0; u < CB; ++u) {
+      if (c0 + u < a.nchunks) {
+#pragma unroll
+        for (int q = 0; q < EP; ++q) g[q] += t[u][q];
+        beta += tb[u];
+      }
+    }
+  }
+  fin1k_tail<EP>(a, g, beta, p, sh);
+}
+
+template <int EP>
+__global__ __launch_bounds__(NTF) void fin1k_kernel(FinalizeArgs a) { fin1k_body<EP>(a); }
+template <int EP>
+__global__ __launch_bounds__(NTF) void gram1k_chunk_kernel(FinalizeArgs a) { gram1k_chunk_body<EP>(a, blockIdx.x); }
+template <int EP>
+__global__ __launch_bounds__(NTF) void tail1k_kernel(FinalizeArgs a) { tail1k_body<EP>(a); }
+
+__device__ __forceinline__ void fin_op(const KOp& op, int bx) {
+  switch (op.kind) {
+    case K_FIN1K:
+      if (op.variant == 1) fin1k_body<1>(op.u.fin);
+      else if (op.variant == 2) fin1k_body<2>(op.u.fin);
+      else fin1k_body<4>(op.u.fin);
+      break;
+    case K_GRAM1K:
+      if (op.variant == 1) gram1k_chunk_body<1>(op.u.fin, bx);
+      else if (op.variant == 2) gram1k_chunk_body<2>(op.u.fin, bx);
+      else gram1k_chunk_body<4>(op.u.fin, bx);
+      break;
+    case K_TAIL1K:
+      if (op.variant == 1) tail1k_body<1>(op.u.fin);
+      else if (op.variant == 2) tail1k_body<2>(op.u.fin);
+      else tail1k_body<4>(op.u.fin);
+      break;
+    default: break;
+  }
+}
+// Persistent batched form of the 1024-thread finalize kernels.
+__global__ __launch_bounds__(NTF) void fin_batch_kernel(const BItem* __restrict__ items, const int* __restrict__ count,
+                                                        const KOp* __restrict__ ops) {
+  const int n = *count;
+  for (int i = blockIdx.x; i < n; i += gridDim.x) {
+    const BItem it = items[i];
+    fin_op(ops[it.op], it.bx);
+    __syncthreads();
+  }
+}
 
 // Split-K sum of partial-MTTKRP partials: T(m, col0 + r) = sum over splits (in
 // split order) of part[(sp*RP + r)*Mpad + m], one thread per output (coalesced along m).
@@ -917,16 +989,9 @@ __device__ __forceinline__ void small_op(const KOp& op, int bx, int by) {
         default: update_reg_body<64>(op.u.up, bx); break;
       }
       break;
-    case K_FIN_SMALL: finalize_small_body(op.u.fin); break;
     case K_FIN_FUSED: finalize_fused_body(op.u.fin); break;
-    case K_GRAM_CHUNKS:
-      if (op.variant) gram_chunks_blocked_body(op.u.fin, bx);
-      else gram_chunks_body(op.u.fin, bx);
-      break;
-    case K_FIN_TAIL:
-      if (op.variant) finalize_tail_blocked_body(op.u.fin);
-      else finalize_tail_body(op.u.fin);
-      break;
+    case K_GRAM_CHUNKS: gram_chunks_body(op.u.fin, bx); break;
+    case K_FIN_TAIL: finalize_tail_body(op.u.fin); break;
     default: break;
   }
 }
@@ -1030,7 +1095,7 @@ hipError_t unit_lambda_launch(double* lam, int64_t n, hipStream_t st) {
 }
 
 static hipError_t record_or_launch(const Sink& sk, int kind, int variant, unsigned gx, unsigned gy, size_t lds,
-                                   const void* kernel, const void* arg_struct, size_t arg_bytes) {
+                                   const void* kernel, const void* arg_struct, size_t arg_bytes, int threads = NT) {
   if (sk.rec) {
     KOp op{};
     op.kind = kind;
@@ -1042,7 +1107,7 @@ static hipError_t record_or_launch(const Sink& sk, int kind, int variant, unsign
     return sink_record(sk, op);
   }
   void* args[] = {const_cast<void*>(arg_struct)};
-  return hipLaunchKernel(kernel, dim3(gx, gy), dim3(NT), args, lds, sk.st);
+  return hipLaunchKernel(kernel, dim3(gx, gy), dim3(threads), args, lds, sk.st);
 }
 
 hipError_t mttv_trail_launch(const MttvArgs& a, const Sink& sk) {
@@ -1124,6 +1189,18 @@ hipError_t sink_record(const Sink& s, const KOp& op) {
   return hipSuccess;
 }
 
+hipError_t batch_launch_fin(const BItem* items, const int* count, const KOp* ops, unsigned grid, size_t lds,
+                            hipStream_t st) {
+  static bool attr = [] {
+    (void)hipFuncSetAttribute((const void*)fin_batch_kernel, hipFuncAttributeMaxDynamicSharedMemorySize, 150 * 1024);
+    (void)hipGetLastError();
+    return true;
+  }();
+  (void)attr;
+  hipLaunchKernelGGL(fin_batch_kernel, dim3(grid), dim3(NTF), lds, st, items, count, ops);
+  return hipGetLastError();
+}
+
 hipError_t batch_launch_small(const BItem* items, const int* count, const KOp* ops, unsigned grid, size_t lds,
                               hipStream_t st) {
   static bool attr = [] {
@@ -1137,11 +1214,11 @@ hipError_t batch_launch_small(const BItem* items, const int* count, const KOp* o
   return hipGetLastError();
 }
 
-// Row chunks for the Gram: one block when the work is small (no second launch),
-// otherwise chunks of about 2^18 (register-blocked, R <= 64) or 2^19
-// multiply-adds each, at most 64.
+// Row chunks for the Gram: one group when the work is small (no second launch),
+// otherwise chunks of about I_chunk x R4^2 = 2^20 (R <= 64: 1024-thread groups
+// that compute only the upper triangle) or 2^19 (R > 64) products each, at most 64.
 int finalize_chunks(int64_t I, int R, int* rows_per_chunk) {
-  const int shift = 19;
+  const int shift = R <= kSmallMaxR ? 20 : 19;
   const int64_t R4 = R <= kSmallMaxR ? gram_r4(R) : R;
   const int64_t work = I * R4 * R4;
   int64_t chunks = (work + (1ll << shift) - 1) >> shift;
@@ -1158,16 +1235,30 @@ int finalize_chunks(int64_t I, int R, int* rows_per_chunk) {
 hipError_t finalize_launch(const FinalizeArgs& a, const Sink& sk) {
   const size_t RR = (size_t)a.R * a.R;
   if (a.R <= kSmallMaxR) {
+    static bool attr = [] {
+      const void* ks[] = {(const void*)fin1k_kernel<1>,        (const void*)fin1k_kernel<2>,
+                          (const void*)fin1k_kernel<4>,        (const void*)gram1k_chunk_kernel<1>,
+                          (const void*)gram1k_chunk_kernel<2>, (const void*)gram1k_chunk_kernel<4>};
+      for (const void* k : ks)
+        if (hipFuncSetAttribute(k, hipFuncAttributeMaxDynamicSharedMemorySize, 150 * 1024) != hipSuccess)
+          (void)hipGetLastError();
+      return true;
+    }();
+    (void)attr;
+    const int ep = fin_ep(a.R);
+    const size_t lds = (size_t)fin_work_doubles(a.R) * sizeof(double);
     if (a.nchunks <= 1) {
-      const size_t bytes = (3 * RR + 1 + kSmallMaxR + gram_work_doubles(a.R)) * sizeof(double);
-      return record_or_launch(sk, K_FIN_SMALL, 0, 1, 1, bytes, (const void*)finalize_small_kernel, &a, sizeof(a));
+      const void* k = ep == 1 ? (const void*)fin1k_kernel<1>
+                              : (ep == 2 ? (const void*)fin1k_kernel<2> : (const void*)fin1k_kernel<4>);
+      return record_or_launch(sk, K_FIN1K, ep, 1, 1, lds, k, &a, sizeof(a), NTF);
     }
-    hipError_t e = record_or_launch(sk, K_GRAM_CHUNKS, 1, (unsigned)a.nchunks, 1,
-                                    gram_work_doubles(a.R) * sizeof(double),
-                                    (const void*)gram_chunks_blocked_kernel, &a, sizeof(a));
+    const void* kc = ep == 1 ? (const void*)gram1k_chunk_kernel<1>
+                             : (ep == 2 ? (const void*)gram1k_chunk_kernel<2> : (const void*)gram1k_chunk_kernel<4>);
+    hipError_t e = record_or_launch(sk, K_GRAM1K, ep, (unsigned)a.nchunks, 1, lds, kc, &a, sizeof(a), NTF);
     if (e != hipSuccess) return e;
-    return record_or_launch(sk, K_FIN_TAIL, 1, 1, 1, (3 * RR + 1 + kSmallMaxR) * sizeof(double),
-                            (const void*)finalize_tail_blocked_kernel, &a, sizeof(a));
+    const void* kt = ep == 1 ? (const void*)tail1k_kernel<1>
+                             : (ep == 2 ? (const void*)tail1k_kernel<2> : (const void*)tail1k_kernel<4>);
+    return record_or_launch(sk, K_TAIL1K, ep, 1, 1, 0, kt, &a, sizeof(a), NTF);
   }
   size_t lds = (size_t)fin_sub_rows(a.R) * a.R * sizeof(double);
   const size_t need = (RR + 1) * sizeof(double);
@@ -1185,6 +1276,7 @@ hipError_t finalize_launch(const FinalizeArgs& a, hipStream_t st) {
   sk.st = st;
   return finalize_launch(a, sk);
 }
+
 
 hipError_t init_model_launch(const double* lam_in, double* lam, double* lam_model, const double* G,
                              double* S, int N, int R, hipStream_t st) {

@@ -224,3 +224,56 @@ def planted_device(dims: Sequence[int], R: int, noise: float, seed: int, device=
         del E
         X.clamp_(min=0.0)
     return X
+
+
+def planted_device_slabs(dims: Sequence[int], R: int, noise: float, seed: int, dtype: str = "bf16",
+                         device="cuda", slab_bytes: int = 1 << 30):
+    """The ``planted`` recipe for tensors too large to hold twice in FP32 (the
+    30012 x 1200 x 500 fMRI-shaped tensor is 72 GB in FP32): drawn slab by slab
+    along the last mode, straight into the storage type ("f32", "bf16", "f16").
+    Factors U[0,1) and N(0,1) noise from seeded torch generators; ||X_c||^2 is
+    the closed form sum_{r,s} prod_n (F_n^T F_n)[r, s] in FP64, ||E||^2 is
+    summed over the slabs in a first pass, and each slab's noise is drawn again
+    from its own seed in the second; X = max(0, X_c + noise ||X_c|| / ||E|| E)
+    is then rounded to the storage type. Returns the flat tensor, mode 1
+    fastest. Its values differ from ``planted`` and ``planted_device``."""
+    import torch
+    dims = _as_dims(dims)
+    tdt = {"f32": torch.float32, "bf16": torch.bfloat16, "f16": torch.float16}[dtype]
+    g = torch.Generator(device=device)
+    g.manual_seed(int(seed))
+    fs = [torch.rand((d, R), generator=g, device=device, dtype=torch.float32) for d in dims]
+    gh = torch.ones((R, R), dtype=torch.float64, device=device)
+    for f in fs:
+        fd = f.double()
+        gh *= fd.T @ fd
+    xc_norm = math.sqrt(max(0.0, float(gh.sum())))
+    P = fs[0]
+    for f in fs[1:-1]:
+        P = (f[:, None, :] * P[None, :, :]).reshape(-1, R)
+    Q, K = P.shape[0], dims[-1]
+    per = max(1, int(slab_bytes // (Q * 4)))
+
+    def slab_noise(k0, k1):
+        gk = torch.Generator(device=device)
+        gk.manual_seed(int(seed) * 1000003 + 7919 * k0 + 1)
+        return torch.randn(Q * (k1 - k0), generator=gk, device=device, dtype=torch.float32)
+
+    scale = 0.0
+    if noise:
+        e2 = 0.0
+        for k0 in range(0, K, per):
+            E = slab_noise(k0, min(K, k0 + per))
+            e2 += float(torch.linalg.vector_norm(E, dtype=torch.float64) ** 2)
+            del E
+        scale = noise * xc_norm / math.sqrt(e2) if e2 > 0 else 0.0
+    out = torch.empty(Q * K, dtype=tdt, device=device)
+    for k0 in range(0, K, per):
+        k1 = min(K, k0 + per)
+        Xs = (fs[-1][k0:k1] @ P.T).reshape(-1)  # (k, q) with q (modes 1..N-1, mode 1 fastest) fastest
+        if noise:
+            Xs.add_(slab_noise(k0, k1), alpha=scale)
+            Xs.clamp_(min=0.0)
+        out[k0 * Q:k1 * Q] = Xs.to(tdt)
+        del Xs
+    return out

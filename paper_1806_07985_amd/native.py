@@ -94,6 +94,9 @@ def _declare(L):
     L.nncp_plan_time_mttkrp.argtypes = [c_vp, ctypes.c_int, c_dp]
     L.nncp_plan_destroy.restype = ctypes.c_int
     L.nncp_plan_destroy.argtypes = [c_vp]
+    L.nncp_autotune_split.restype = ctypes.c_int
+    L.nncp_autotune_split.argtypes = [c_vp, ctypes.c_int, ctypes.c_int, c_i64p, ctypes.c_int, ctypes.POINTER(c_vp),
+                                      c_vp, ctypes.c_int, ctypes.POINTER(ctypes.c_int), c_dp, c_vp]
     L.nncp_quantize.restype = ctypes.c_int
     L.nncp_quantize.argtypes = [c_vp, c_vp, ctypes.c_int, ctypes.c_int64, c_vp]
     L.nncp_norm_sq.restype = ctypes.c_int
@@ -269,6 +272,25 @@ def nncp(X, dims, R, iters, H, lam=None, update="hals", split=0, graph=True, rec
     _check(st, "nncp")
     n_fit = done.value if record_fit else 1
     return dict(fit=np.array(fit[:n_fit]), lam=np.array(lam_arr[:]), iters_done=done.value)
+
+
+def autotune_split(X, dims, R, H, reps=3, pm_wg_kib=0, stream=None):
+    """Fastest root split of the dimension tree for this problem, timed on the
+    device (nncp_autotune_split). H: device factors (read only).
+
+    Returns (best_split, ms) with ms[s - 1] the tree-MTTKRP time of split s
+    (-1 where its workspace did not fit)."""
+    import torch
+    N = len(dims)
+    _need(X, int(np.prod(dims)), name="X")
+    for n, h in enumerate(H):
+        _need(h, dims[n] * R, torch.float32, name=f"H[{n}]")
+    o = Options(pm_wg_kib=pm_wg_kib)
+    best = ctypes.c_int(0)
+    ms = (ctypes.c_double * (N - 1))()
+    _check(lib().nncp_autotune_split(_ptr(X), _dtype_code(X), N, _dims(dims), R, _ptr_array(H), ctypes.byref(o),
+                                     reps, ctypes.byref(best), ms, _stream(stream)), "nncp_autotune_split")
+    return best.value, list(ms)
 
 
 class Plan:

@@ -98,3 +98,17 @@ def test_inner_sweeps_option_layout_and_limit():
     o = native.Options(inner_sweeps=1025)
     assert L.nncp(ctypes.c_void_p(16), 0, 3, dims, 2, 1, 0, H, lam, None, None, None, 0, ctypes.byref(o),
                   None) == -1
+
+
+def test_autotune_split_rejects_bad_arguments_without_a_device():
+    from paper_1806_07985_amd import native
+    L = _lib()
+    dims = native._dims([4, 4, 4])
+    best = ctypes.c_int(0)
+    H = (native.c_vp * 3)(ctypes.c_void_p(16), ctypes.c_void_p(16), ctypes.c_void_p(16))
+    assert L.nncp_autotune_split(None, 0, 3, dims, 2, H, None, 3, ctypes.byref(best), None, None) == -1
+    assert L.nncp_autotune_split(ctypes.c_void_p(16), 0, 3, dims, 2, H, None, 0, ctypes.byref(best), None,
+                                 None) == -1
+    assert L.nncp_autotune_split(ctypes.c_void_p(16), 0, 1, dims, 2, H, None, 3, ctypes.byref(best), None,
+                                 None) == -1
+    assert L.nncp_autotune_split(ctypes.c_void_p(16), 0, 3, dims, 2, H, None, 3, None, None, None) == -1

@@ -219,3 +219,31 @@ def test_inner_sweeps_above_maximum_rejected(gpu_lib):
     Hd = [native.factor_to_device(h.astype(np.float32)) for h in inputs.init_factors(dims, R, seed=56)]
     with pytest.raises(Exception):
         native.nncp(native.tensor_to_device(X), list(dims), R, 1, Hd, inner_sweeps=100000)
+
+
+@pytest.mark.parametrize("dims,R,dt", [((24, 20, 18, 16), 8, "f32"), ((40, 36, 30), 12, "bf16"),
+                                       ((12, 10, 9, 8, 7), 4, "f32")])
+def test_autotune_split_picks_the_fastest_timed_split(gpu_lib, dims, R, dt):
+    """Every root split is timed; the returned one is the fastest; the factors
+    are left untouched; a plan on that split still matches the oracle."""
+    import torch
+    from paper_1806_07985_amd import native
+    print(f"case autotune dims={dims} R={R} {dt}", flush=True)
+    X, _ = inputs.planted(dims, R, 0.01, seed=61, dtype=np.float32)
+    H0 = [h.astype(np.float32) for h in inputs.init_factors(dims, R, seed=62)]
+    flat = torch.from_numpy(np.ascontiguousarray(X.ravel(order="F")))
+    if dt == "bf16":
+        flat = flat.to(torch.bfloat16)
+    X64 = flat.to(torch.float64).numpy().reshape(dims, order="F")
+    Xd = flat.cuda()
+    Hd = [native.factor_to_device(h) for h in H0]
+    best, ms = native.autotune_split(Xd, list(dims), R, Hd, reps=2)
+    print(f"  best split {best}, ms {ms}", flush=True)
+    assert len(ms) == len(dims) - 1 and all(t > 0 for t in ms)
+    assert 1 <= best <= len(dims) - 1 and ms[best - 1] == min(ms)
+    for h, h0 in zip(Hd, H0):
+        assert np.array_equal(native.factor_to_host(h), h0)
+    r = native.nncp(Xd, list(dims), R, 5, Hd, split=best)
+    ref = O.nncp(X64, [h.astype(np.float64) for h in H0], 5)
+    tol = 1e-5 if dt == "f32" else 1e-4
+    assert np.max(np.abs(r["fit"] - np.asarray(ref["fit"]))) < tol
