@@ -376,8 +376,9 @@ def main(argv=None):
     ap.add_argument("--dims", default="128,128,128,128")
     ap.add_argument("--rank", type=int, default=32)
     ap.add_argument("--split", type=int, default=2)
-    ap.add_argument("--workload", default="planted", choices=["planted", "hsi"],
-                    help="main workload: planted U[0,1) factors + 1%% noise, or the hyperspectral-shaped recipe")
+    ap.add_argument("--workload", default="planted", choices=["planted", "hsi", "device"],
+                    help="main workload: planted U[0,1) factors + 1%% noise (host), the hyperspectral-shaped "
+                         "recipe, or the planted recipe drawn on the device slab by slab (large tensors)")
     ap.add_argument("--dtype", default="f32", choices=["f32", "bf16", "f16"], help="tensor storage of the main run")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-iters", type=int, default=3)
@@ -410,16 +411,19 @@ def main(argv=None):
     dims = [int(d) for d in args.dims.split(",")]
     R, s = args.rank, args.split
     workload = "x".join(map(str, dims)) + f"_r{R}"
+    dev = torch.device("cuda:0")
+    X = None
     if args.workload == "hsi":
         X, _ = inputs.hsi_like(dims, R, 0.02, seed=5)
-    else:
+    elif args.workload == "planted":
         X, _ = inputs.planted(dims, R, 0.01, seed=1, dtype=np.float32)
     H0 = [h.astype(np.float32) for h in inputs.init_factors(dims, R, seed=2)]
-
-    dev = torch.device("cuda:0")
-    Xd = native.tensor_to_device(X, device=dev)
-    if args.dtype != "f32":
-        Xd = native.quantize(Xd, args.dtype)
+    if X is not None:
+        Xd = native.tensor_to_device(X, device=dev)
+        if args.dtype != "f32":
+            Xd = native.quantize(Xd, args.dtype)
+    else:  # drawn on the device straight into the storage type (tensors too large for the host path)
+        Xd = inputs.planted_device_slabs(dims, R, 0.01, seed=1, dtype=args.dtype, device=dev)
     sx, nodeb = (4, 8) if args.dtype == "f32" else (2, 4)
     Hd = [native.factor_to_device(h, device=dev) for h in H0]
     torch.cuda.synchronize()
@@ -540,7 +544,7 @@ def main(argv=None):
         out["serving"] = _serving_study(dev, args.serve_pool, args.serve_jobs, loads, args.serve_iters,
                                         budget_gb=96.0, max_active=64)
         note("serving study")
-    if not args.no_cpu_baseline:
+    if not args.no_cpu_baseline and X is not None:
         out["cpu_baseline"] = _cpu_baseline(X, [h.astype(np.float64) for h in H0], args.cpu_iters)
         note("CPU baseline")
     print(json.dumps(out), flush=True)

@@ -211,13 +211,32 @@ __device__ __forceinline__ void pm_left_16_body(const PmArgs& a, int bx, int by,
   const int jrot = (WK == 1 && jn > 1) ? (int)(((unsigned)bx * 5u) % (unsigned)jn) : 0;
   int jl = sb / S1 + jrot, tl = sb - (sb / S1) * S1;
   if (jl >= jn) jl -= jn;
+  // Without the unmasked path: on every k-step that lies inside I1, TR-row loads
+  // where I_L % TR == 0, else 8-byte loads (4 rows) where I_L % 4 == 0 (every
+  // 4-row group is then all in or all out of M); element loads only for the
+  // ragged last k-step or odd I_L.
+  const bool mid = !FAST && (Mtot % 4 == 0) && ((uintptr_t)a.X % 8 == 0);
+  const bool wide = mid && (Mtot % TR == 0) && ((uintptr_t)a.X % (2 * TR) == 0);  // TR-row loads fit
   auto load = [&](vT (&A)[8]) {
     const int64_t colbase = (int64_t)a.I1 * (j0 + jl) + i1_0 + KS * tl + 8 * lq;
     const unsigned short* base = X + Mtot * colbase;
+    const bool full = KS * tl + KS <= ilim;  // wave-uniform
 #pragma unroll
     for (int e = 0; e < 8; ++e) {
       if (FAST) {
         A[e] = __builtin_nontemporal_load((const vT*)(base + Mtot * e + mload));
+      } else if (wide && full) {
+        A[e] = __builtin_nontemporal_load((const vT*)(base + Mtot * e + mload));
+      } else if (mid && full) {
+        vT v;
+#pragma unroll
+        for (int h = 0; h < TR / 4; ++h) {
+          const int64_t mm = (m + 4 * h + 4 <= Mtot) ? m + 4 * h : 0;
+          const us4 q = __builtin_nontemporal_load((const us4*)(base + Mtot * e + mm));
+#pragma unroll
+          for (int t = 0; t < 4; ++t) v[4 * h + t] = q[t];
+        }
+        A[e] = v;
       } else {
         const bool kv = (KS * tl + 8 * lq + e) < ilim;
         vT v;
@@ -387,9 +406,15 @@ __device__ __forceinline__ void pm_right_16_body(const PmArgs& a, int bx, int by
     jl = jcntL + jrot;
     if (jl >= jn) jl -= jn;
   }
+  // Without the unmasked path: on every k-step that lies inside I1, 16-byte loads
+  // where column starts allow them (I_L % 8 == 0), else two 8-byte loads per 8 k
+  // (I_L % 4 == 0); element loads only for the ragged last k-step or odd I_L.
+  const bool mid = !FAST && (Ktot % 4 == 0) && ((uintptr_t)a.X % 8 == 0);
+  const bool wide = mid && (Ktot % 8 == 0) && ((uintptr_t)a.X % 16 == 0);  // 16-byte loads fit
   auto load = [&](us8 (&A)[MC][2]) {
     const int ilimL = a.I1 - (ib0 + stL) * a.i1blk;
     const int64_t lbase = (int64_t)a.I1 * (j0 + jl) + (int64_t)(ib0 + stL) * a.i1blk + KS * tl;
+    const bool full = KS * tl + KS <= ilimL;  // wave-uniform
 #pragma unroll
     for (int h = 0; h < 2; ++h) {
       const int off = KS * tl + 32 * h + 8 * lq;
@@ -397,6 +422,12 @@ __device__ __forceinline__ void pm_right_16_body(const PmArgs& a, int bx, int by
       for (int g = 0; g < MC; ++g) {
         if (FAST) {
           A[g][h] = __builtin_nontemporal_load((const us8*)(colp[g] + lbase + 32 * h));
+        } else if (wide && full) {
+          A[g][h] = __builtin_nontemporal_load((const us8*)(colp[g] + lbase + 32 * h));
+        } else if (mid && full) {
+          const us4* p = (const us4*)(colp[g] + lbase + 32 * h);
+          const us4 lo = __builtin_nontemporal_load(p), hi = __builtin_nontemporal_load(p + 1);
+          A[g][h] = us8{lo[0], lo[1], lo[2], lo[3], hi[0], hi[1], hi[2], hi[3]};
         } else {
           us8 v;
 #pragma unroll

@@ -25,6 +25,7 @@ JOBS = [
     ((50, 33, 17), 50, "hals", 0, "f32", 2),
     ((37, 29, 23), 12, "hals", 1, "f32", 0),
     ((64, 40, 1000), 16, "hals", 1, "bf16", 0),   # tall right node with J == 1: its own kernel family
+    ((60, 300, 120), 10, "hals", 1, "bf16", 0),   # the same, masked form (I_L % 8 == 4, ragged I1)
 ]
 
 

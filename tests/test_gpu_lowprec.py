@@ -48,6 +48,10 @@ PM_CASES = [
     ((20, 18, 22), 100, 2),      # column chunks of 64
     ((1024, 300), 24, 1),
     ((128, 64, 33, 9), 50, 1),   # the hyperspectral shape family, small
+    ((3012, 12, 10), 10, 1),     # the fMRI shape family: I_L % 8 == 4, ragged I1 (8-byte loads)
+    ((300, 20, 10), 10, 2),      # I_L % 8 == 0 but I1 ragged: 8-byte loads on full k-steps
+    ((60, 200, 200), 10, 1),     # tall right node with J == 1, masked form (I_L % 8 == 4, ragged I1)
+    ((36, 300, 120), 24, 1),     # the same with two column blocks
 ]
 
 
