@@ -129,8 +129,10 @@ def test_tree_mttkrp_every_mode_and_split_matches_direct(gpu_lib, dims, R):
             np.testing.assert_allclose(M, ref, rtol=5e-7)
 
 
-@pytest.mark.parametrize("I,R", [(1, 1), (37, 5), (128, 32), (1344, 50), (300, 64), (90, 100)])
+@pytest.mark.parametrize("I,R", [(1, 1), (37, 5), (128, 32), (1344, 50), (300, 64), (90, 100),
+                                 (5000, 16), (2000, 40), (700, 45), (1030, 33)])
 def test_gram_matches_oracle(gpu_lib, I, R):
+    """Single and several row chunks, one, two and four R x R entries per thread."""
     from paper_1806_07985_amd import native
     rng = np.random.default_rng(I + R)
     H = rng.random((I, R)).astype(np.float32)

@@ -247,3 +247,15 @@ def test_autotune_split_picks_the_fastest_timed_split(gpu_lib, dims, R, dt):
     ref = O.nncp(X64, [h.astype(np.float64) for h in H0], 5)
     tol = 1e-5 if dt == "f32" else 1e-4
     assert np.max(np.abs(r["fit"] - np.asarray(ref["fit"]))) < tol
+
+
+@pytest.mark.parametrize("dims,R", [((12, 10, 5000), 16), ((8, 6, 1500), 40)])
+def test_multichunk_gram_and_fit_match_oracle(gpu_lib, dims, R):
+    """A last mode long enough that its Gram (and the fit) is summed over several
+    row chunks, with one and two R x R entries per thread."""
+    print(f"case multichunk dims={dims} R={R}", flush=True)
+    X, _ = inputs.planted(dims, min(R, 6), 0.02, seed=71, dtype=np.float32)
+    H0 = [h.astype(np.float32) for h in inputs.init_factors(dims, R, seed=72)]
+    g = _run_gpu(X, H0, R, 5)
+    o = _run_oracle(X, H0, 5)
+    _compare(g, o)
