@@ -30,7 +30,7 @@ __all__ = [
     "relerr_explicit", "fit_from_terms", "choose_split",
     "partial_mttkrp_left", "partial_mttkrp_right", "mttv_trail", "mttv_lead",
     "DimTree", "nncp", "nncp_unnormalized", "nnls_bruteforce",
-    "nls_objective", "kkt_residual", "MU_EPS", "subtree_schedule",
+    "nls_objective", "kkt_residual", "MU_EPS", "subtree_schedule", "fit_of_model", "block_update",
 ]
 
 MU_EPS = 1e-16
@@ -109,25 +109,29 @@ def mttkrp_direct(X: np.ndarray, H: Sequence[np.ndarray], n: int,
                   max_krp_rows: int = 1 << 21) -> np.ndarray:
     """M^(n) = X_(n) K^(n) with K^(n) formed explicitly (Section II-A).
 
-    When K^(n) would be large, the column blocks of X_(n) belonging to one
-    index of the slowest remaining mode are multiplied by the matching rows
-    of K^(n) and summed; this is the same sum over columns, only split.
+    When K^(n) would be large, the columns of X_(n) are taken in blocks, one
+    per index t of the slowest remaining mode `top`: those columns are
+    contiguous in X_(n), and the matching rows of K^(n) are K_rest scaled
+    by row t of H^(top) (K_rest = the Khatri-Rao product of the other
+    remaining modes). Block t then contributes
+    (X_(n)[:, block t] K_rest) * H^(top)(t, :); this is the same sum over
+    columns, only split.
     """
     X = np.asarray(X)
     N = X.ndim
     R = H[0].shape[1]
-    ncols = X.size // X.shape[n]
+    Xn = unfold(X, n)
+    ncols = Xn.shape[1]
     if ncols <= max_krp_rows:
-        return unfold(X, n) @ krp_for_mode(H, n)
+        return Xn @ krp_for_mode(H, n)
     top = max(k for k in range(N) if k != n)
     rest = [k for k in range(N) if k != n and k != top]
     K_rest = khatri_rao_list([H[k] for k in reversed(rest)]) if rest else np.ones((1, R))
+    C = ncols // X.shape[top]
+    Htop = np.asarray(H[top], dtype=np.float64)
     M = np.zeros((X.shape[n], R))
-    n_in_slab = n if n < top else n - 1
     for t in range(X.shape[top]):
-        slab = np.take(X, t, axis=top)
-        Kt = K_rest * np.asarray(H[top][t], dtype=np.float64)[None, :]
-        M += unfold(slab, n_in_slab) @ Kt
+        M += (Xn[:, t * C:(t + 1) * C] @ K_rest) * Htop[t][None, :]
     return M
 
 
@@ -191,6 +195,35 @@ def mu_update(W: np.ndarray, S: np.ndarray, M: np.ndarray, eps: float = MU_EPS) 
     return W * np.asarray(M, dtype=np.float64) / np.maximum(W @ np.asarray(S, dtype=np.float64), eps)
 
 
+def block_update(W: np.ndarray, S: np.ndarray, M: np.ndarray, update: str = "hals", sweeps: int = 1,
+                 tol: float = 0.0) -> np.ndarray:
+    """The NLS-Update of one block (Section II-B): the update rule applied
+    `sweeps` times to the fixed subproblem min_{W >= 0} 1/2 tr(W S W^T) - <M, W>.
+
+    Each row of W is a separate NNLS problem in its own unknowns. With tol > 0
+    a row stops as soon as one application changes none of its entries by more
+    than tol times its largest entry, so with a large `sweeps` every row is
+    solved to that tolerance; for HALS (exact coordinate minimisation) that is
+    the exact block solve the paper's faithful BCD asks for.
+    """
+    upd = {"hals": hals_update, "mu": mu_update}[update]
+    W = np.array(W, dtype=np.float64, copy=True)
+    M = np.asarray(M, dtype=np.float64)
+    if tol <= 0.0:
+        for _ in range(max(1, sweeps)):
+            W = upd(W, S, M)
+        return W
+    active = np.arange(W.shape[0])
+    for _ in range(max(1, sweeps)):
+        if active.size == 0:
+            break
+        Wn = upd(W[active], S, M[active])
+        change = np.max(np.abs(Wn - W[active]), axis=1)
+        W[active] = Wn
+        active = active[change > tol * np.max(np.abs(Wn), axis=1)]
+    return W
+
+
 def normalize_columns(W: np.ndarray) -> Tuple[np.ndarray, np.ndarray]:
     """lambda = column 2-norms of W, H = W diag(1/lambda) (appendix algorithm).
 
@@ -235,6 +268,29 @@ def fit_from_terms(alpha: float, beta: float, gamma: float) -> Tuple[float, floa
     num = max(0.0, alpha - 2.0 * beta + gamma)
     eps = math.sqrt(num / alpha) if alpha > 0 else 0.0
     return 1.0 - eps, eps
+
+
+def fit_of_model(X: np.ndarray, lam: np.ndarray, H: Sequence[np.ndarray]) -> float:
+    """fit = 1 - ||X - [[lam; H]]|| / ||X|| of a given model, for any tensor size.
+
+    The error is expanded as in Section IV-B: ||X||^2 - 2 <X, model> + ||model||^2
+    with <X, model> = sum_r lam_r (M^(1)(:, r) . H^(1)(:, r)), M^(1) the mode-1
+    MTTKRP of X with the model's factors, and ||model||^2 = lam^T (*_n H^(n)T H^(n)) lam.
+    Used to score a model found on one tensor (e.g. a 16-bit copy) against
+    another (the FP32 original) without forming the model tensor.
+    """
+    X = np.asarray(X)
+    lam = np.asarray(lam, dtype=np.float64)
+    Hs = [np.asarray(h, dtype=np.float64) for h in H]
+    Xf = X.reshape(-1, order="A")
+    alpha = float(np.dot(Xf.astype(np.float64, copy=False), Xf.astype(np.float64, copy=False)))
+    M1 = mttkrp_direct(X, Hs, 0)
+    beta = float(np.sum(M1 * Hs[0], axis=0) @ lam)
+    G = np.ones((lam.size, lam.size))
+    for h in Hs:
+        G = G * gram(h)
+    gamma = float(lam @ G @ lam)
+    return fit_from_terms(alpha, beta, gamma)[0]
 
 
 # ----------------------------------------------------------------------------
@@ -368,29 +424,33 @@ def nncp(X: np.ndarray, H0: Sequence[np.ndarray], iters: int, update: str = "hal
          lam0: Optional[np.ndarray] = None, mttkrp: str = "direct",
          split: Optional[int] = None, alpha: Optional[float] = None,
          callback: Optional[Callable[[int, int, dict], None]] = None,
-         inner_sweeps: int = 1) -> dict:
+         inner_sweeps: int = 1, inner_tol: float = 0.0, normalize: bool = True) -> dict:
     """Alternating-update NNCP, ``iters`` outer iterations (Algorithm 1).
 
-    Per mode n = 1..N: M^(n) = MTTKRP, S^(n) = Hadamard of the other Grams,
-    H^(n) = NLS-Update(S^(n), M^(n)), column normalisation giving lambda,
-    G^(n) = H^(n)^T H^(n); after mode N the relative error is evaluated from
-    alpha = ||X||^2, beta = <M^(N), H_hat^(N)> and
-    gamma = lambda^T (S^(N) * G^(N)) lambda (appendix algorithm).
+    Each outer iteration visits the modes in order; for mode n it forms the
+    MTTKRP M^(n), the Hadamard product S^(n) of the other modes' Grams, solves
+    the block subproblem (``block_update``) and refreshes G^(n). With
+    ``normalize`` (the appendix algorithm) the new block is split into unit
+    columns and weights lambda; after the last mode the relative error comes
+    from alpha = ||X||^2, beta = <M^(N), W^(N)> and
+    gamma = lambda^T (S^(N) * G^(N)) lambda (Section IV-B).
 
     Readings:
     * all N factors are initialised by the caller (the paper initialises
-      modes 2..N only, but HALS needs a starting H^(1)); the starting
-      factors are normalised first and their column norms are multiplied
-      into lambda (``lam0`` defaults to ones);
+      modes 2..N only, but HALS needs a starting H^(1)); with ``normalize``
+      the starting factors are normalised first and their column norms are
+      multiplied into lambda (``lam0`` defaults to ones);
     * the update for mode n starts from H^(n) diag(lambda) (the current
       model's mode-n block with the other factors at unit norm); the update
-      rules are scale-covariant, so this equals unnormalised BCD exactly;
+      rules are scale-covariant, so this equals the unnormalised iteration
+      (``normalize=False``: plain factors, lambda fixed at ones) exactly;
     * fit = 1 - epsilon, recorded after every outer iteration;
-    * ``inner_sweeps`` applies the update rule that many times per block
-      update (with M and S fixed). For HALS every sweep is an exact
-      coordinate minimisation of the block subproblem, so many sweeps
-      approach the exact NNLS solution that Section II-B names as the
-      alternative to a single sweep (BPP solves it directly).
+    * ``inner_sweeps`` / ``inner_tol``: the block update applies the rule up
+      to ``inner_sweeps`` times, row by row until a row stops changing
+      (``block_update``). For HALS every sweep is an exact coordinate
+      minimisation, so the sweeps converge to the exact NNLS solution that
+      Section II-B names as the alternative to a single sweep (BPP solves it
+      directly).
 
     ``mttkrp`` selects "direct" (the plain definition) or "tree" (the FP64
     dimension tree, used only to show that both give the same iterates).
@@ -399,13 +459,15 @@ def nncp(X: np.ndarray, H0: Sequence[np.ndarray], iters: int, update: str = "hal
     X = np.asarray(X)
     N = X.ndim
     R = H0[0].shape[1]
-    upd = {"hals": hals_update, "mu": mu_update}[update]
-    H = []
     lam = np.ones(R) if lam0 is None else np.array(lam0, dtype=np.float64)
+    H = []
     for h in H0:
-        hn, nr = normalize_columns(h)
-        H.append(hn)
-        lam = lam * nr
+        if normalize:
+            hn, nr = normalize_columns(h)
+            H.append(hn)
+            lam = lam * nr
+        else:
+            H.append(np.array(h, dtype=np.float64, copy=True))
     G = [gram(h) for h in H]
     if alpha is None:
         Xf = np.asarray(X, dtype=np.float64)
@@ -417,10 +479,12 @@ def nncp(X: np.ndarray, H0: Sequence[np.ndarray], iters: int, update: str = "hal
         for n in range(N):
             M = tree.mttkrp(H, n) if tree is not None else mttkrp_direct(X, H, n)
             S = hadamard_others(G, n)
-            W = H[n] * lam[None, :]
-            for _ in range(max(1, inner_sweeps)):
-                W = upd(W, S, M)
-            H[n], lam = normalize_columns(W)
+            start = H[n] * lam[None, :] if normalize else H[n]
+            W = block_update(start, S, M, update, inner_sweeps, inner_tol)
+            if normalize:
+                H[n], lam = normalize_columns(W)
+            else:
+                H[n] = W
             G[n] = gram(H[n])
             if callback is not None:
                 callback(it, n, dict(M=M, S=S, W=W, H=H, lam=lam))
@@ -434,21 +498,9 @@ def nncp(X: np.ndarray, H0: Sequence[np.ndarray], iters: int, update: str = "hal
 
 def nncp_unnormalized(X: np.ndarray, H0: Sequence[np.ndarray], iters: int,
                       update: str = "hals") -> List[np.ndarray]:
-    """Algorithm 1 exactly as printed: no normalisation, unscaled factors.
-
-    Used to pin that the normalised driver above computes the same model.
-    """
-    N = X.ndim
-    upd = {"hals": hals_update, "mu": mu_update}[update]
-    H = [np.array(h, dtype=np.float64, copy=True) for h in H0]
-    G = [gram(h) for h in H]
-    for _ in range(iters):
-        for n in range(N):
-            M = mttkrp_direct(X, H, n)
-            S = hadamard_others(G, n)
-            H[n] = upd(H[n], S, M)
-            G[n] = gram(H[n])
-    return H
+    """The factors of ``nncp`` run without normalisation (Algorithm 1 with plain
+    factors); used to pin that the normalised iteration computes the same model."""
+    return nncp(X, H0, iters, update=update, normalize=False)["H"]
 
 
 # ----------------------------------------------------------------------------

@@ -161,6 +161,24 @@ def test_fit_identity_matches_explicit_residual():
     assert abs(O.relerr_explicit(X, lam, H) - e) < 1e-12
 
 
+@pytest.mark.parametrize("dims", [(5, 4, 3), (4, 3, 5, 2), (3, 2, 2, 3, 2)])
+def test_fit_of_model_matches_explicit_residual(dims):
+    """Scoring a model against a tensor (used for the equal-fit comparison of the
+    16-bit runs) equals the residual formed entry by entry, for any lambda."""
+    X = _rand_tensor(dims, 31)
+    H = _rand_factors(dims, 3, 32)
+    lam = np.array([0.4, 1.1, 2.3])
+    ref = 1.0 - O.relerr_explicit(X, lam, H)
+    assert abs(O.fit_of_model(X, lam, H) - ref) < 1e-12
+    # a Fortran-ordered float32 copy scores the same values
+    X32 = np.asfortranarray(X.astype(np.float32))
+    ref32 = 1.0 - O.relerr_explicit(X32.astype(np.float64), lam, H)
+    assert abs(O.fit_of_model(X32, lam, H) - ref32) < 1e-12
+    # the exact model scores 1 (up to the identity's cancellation)
+    Xm = O.model_tensor_cp(lam, H)
+    assert O.fit_of_model(Xm, lam, H) > 1.0 - 1e-6
+
+
 def test_fit_clamps_negative_numerator():
     f, e = O.fit_from_terms(1.0, 1.0, 1.0 - 1e-17)
     assert e == 0.0 and f == 1.0
@@ -269,6 +287,42 @@ def test_inner_sweeps_solve_each_block_exactly():
     e = O.nncp(X, H0, 6, update="hals", inner_sweeps=3000)["eps"]
     assert all(e[i + 1] <= e[i] + 1e-12 for i in range(len(e) - 1))
     assert out["eps"][-1] <= e[1] + 1e-12
+
+
+@pytest.mark.parametrize("R", [2, 4, 6])
+def test_block_update_to_tolerance_is_exact_nnls(R):
+    """HALS sweeps stopped row by row at a relative change of 1e-13 give every
+    row the exact NNLS solution (brute-force active sets) and satisfy KKT; a
+    stopped row is no longer changed by a further sweep beyond that tolerance."""
+    rng = np.random.default_rng(60 + R)
+    K = rng.random((40, R)) + 0.1 * np.eye(40, R)
+    S = K.T @ K
+    M = rng.standard_normal((30, R)) * 3.0  # mixed signs: some constraints active
+    W0 = rng.random(M.shape)
+    W = O.block_update(W0, S, M, "hals", sweeps=100000, tol=1e-13)
+    for i in range(M.shape[0]):
+        h = O.nnls_bruteforce(S, M[i])
+        np.testing.assert_allclose(W[i], h, rtol=0, atol=1e-10 * max(1.0, np.max(np.abs(h))))
+    assert O.kkt_residual(W, S, M) < 1e-10
+    W1 = O.hals_update(W, S, M)
+    assert np.all(np.max(np.abs(W1 - W), axis=1) <= 1e-12 * np.maximum(np.max(np.abs(W), axis=1), 1e-300))
+    # without a tolerance, k sweeps are k applications of the rule
+    W3 = O.block_update(W0, S, M, "hals", sweeps=3)
+    np.testing.assert_array_equal(W3, O.hals_update(O.hals_update(O.hals_update(W0, S, M), S, M), S, M))
+
+
+def test_block_update_rows_stop_independently():
+    """A row that has converged stops while another keeps sweeping: the result
+    of each row is that of the same rule applied to that row alone."""
+    rng = np.random.default_rng(71)
+    K = rng.random((20, 3))
+    S = K.T @ K
+    M = rng.random((4, 3)) * 2.0
+    W0 = rng.random(M.shape)
+    W = O.block_update(W0, S, M, "hals", sweeps=50, tol=1e-6)
+    for i in range(M.shape[0]):
+        Wi = O.block_update(W0[i:i + 1], S, M[i:i + 1], "hals", sweeps=50, tol=1e-6)
+        np.testing.assert_array_equal(W[i], Wi[0])
 
 
 @pytest.mark.parametrize("upd", ["hals", "mu"])
