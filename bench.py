@@ -34,17 +34,18 @@ BF16_MFMA_PEAK_TFLOPS = 2500.0   # dense BF16 / FP16 MFMA
 def _pm_sources_digest(dtype: str = "f32") -> str:
     """Digest of the sources of the partial-MTTKRP kernels for one tensor dtype."""
     h = hashlib.sha256()
-    kern = "pm_kernels.hip" if dtype == "f32" else "pm16_kernels.hip"
-    for f in ("pm_common.hpp", kern, "pm_plan.hip"):
+    kern = ("pm_kernels.hip",) if dtype == "f32" else ("pm16_body.hpp", "pm16_kernels.hip")
+    for f in ("nncp_internal.hpp", "pm_common.hpp", *kern, "pm_plan.hip"):
         p = os.path.join(ROOT, "paper_1806_07985_amd", "csrc", f)
         if os.path.exists(p):
             h.update(open(p, "rb").read())
     return h.hexdigest()[:16]
 
 
-def _traffic_from_profile(workload: str, launch_bytes: float):
-    """HBM bytes per PM launch from the committed rocprofv3 counter summary, if it
-    was taken on the current kernel sources (else None)."""
+def _traffic_from_profile(workload: str, launch_bytes: float, dtype: str = "f32", key: str = "hbm_bytes_per_launch"):
+    """A figure of one PM launch (HBM bytes by default) from the committed
+    rocprofv3 counter summary, if it was taken on the current kernel sources
+    (else None)."""
     p = os.path.join(ROOT, "profiles", f"pm_traffic_{workload}.json")
     if not os.path.exists(p):
         return None
@@ -52,9 +53,9 @@ def _traffic_from_profile(workload: str, launch_bytes: float):
         d = json.load(open(p))
     except Exception:
         return None
-    if d.get("pm_sources_digest") != _pm_sources_digest("f32"):
+    if d.get("pm_sources_digest") != _pm_sources_digest(dtype):
         return None
-    return d.get("hbm_bytes_per_launch")
+    return d.get(key)
 
 
 def _algorithmic_bytes(dims, s, R, sx, node_bytes):
@@ -133,11 +134,11 @@ def _lowprec_study(dev, iters, seconds_note=None):
     from paper_1806_07985_amd import inputs, native
     dims, R, s = (1024, 1344, 33, 9), 50, 1
     t0 = time.perf_counter()
-    X, _ = inputs.hsi_like(dims, R, 0.02, seed=5)
+    X32 = inputs.hsi_like_device(dims, R, 0.02, seed=5, device=dev)
     H0 = [h.astype(np.float32) for h in inputs.init_factors(dims, R, seed=6)]
+    torch.cuda.synchronize()
+    torch.cuda.empty_cache()
     gen_s = time.perf_counter() - t0
-    X32 = native.tensor_to_device(X, device=dev)
-    del X
     out = {"workload": "1024x1344x33x9 hyperspectral-shaped, planted rank 50 + 2% noise, NNCP R=50, HALS, "
                        "split {1}|{2,3,4}", "iters": iters, "generate_s": gen_s}
     for dt in ("f32", "bf16", "f16"):
@@ -158,6 +159,7 @@ def _lowprec_study(dev, iters, seconds_note=None):
                        fit_vs_fp32_tensor=_fit_against(X32, dims, s, Hd, lam),
                        pm_left_ms=rates["left_ms"], pm_right_ms=rates["right_ms"],
                        pm_left_GBs=rates["left_GBs"], pm_right_GBs=rates["right_GBs"],
+                       pm_left_bytes=rates["left_bytes"], pm_right_bytes=rates["right_bytes"],
                        mttkrp_ms=ms_tree,
                        mttkrp_GBs=(rates["left_bytes"] + rates["right_bytes"] + rates["mttv_bytes"]) /
                        (ms_tree * 1e-3) / 1e9)
@@ -238,13 +240,15 @@ def _batch_study(dev, n_jobs, iters):
             "fit_min": min(fits), "fit_median": float(np.median(fits))}
 
 
-def _serving_study(dev, n_pool, n_jobs, load_fracs, iters, budget_gb, max_active):
+def _serving_study(dev, n_pool, n_sat, n_jobs, load_fracs, iters, budget_gb, max_active):
     """Serving stream: jobs of 3-, 4- and 5-way tensors, 1e5..2e8 entries
     (log-uniform, Dirichlet split of log I over the modes), R in {8,16,32,64},
     FP32 or BF16 storage with equal odds, planted rank R + 1% noise, HALS,
-    `iters` iterations each, submitted as pinned host tensors. First all jobs
-    are queued at once (saturation throughput mu), then jobs arrive as a Poisson
-    stream at each fraction of mu; latency = submit to result on the host."""
+    `iters` iterations each, submitted as pinned host tensors. First n_sat jobs
+    are queued at once (saturation throughput mu), then n_jobs arrive as a
+    Poisson stream at each fraction of mu. Latency = submit to result on the
+    host; queue wait = submit to admission (memory reserved, upload begins);
+    device = joining the running batch to result."""
     import torch
     from paper_1806_07985_amd import inputs, native
     t0 = time.perf_counter()
@@ -265,12 +269,15 @@ def _serving_study(dev, n_pool, n_jobs, load_fracs, iters, budget_gb, max_active
     torch.cuda.empty_cache()
     gen_s = time.perf_counter() - t0
 
-    def run(rate):
+    def pct(v, q):
+        return float(np.percentile(v, q)) if len(v) else None
+
+    def run(n, rate):
         srv = native.Server(int(budget_gb * (1 << 30)), max_active=max_active)
         arr = np.random.default_rng(77)
         ids, t_start = [], time.perf_counter()
         t_next = t_start
-        for j in range(n_jobs):
+        for j in range(n):
             if rate:
                 t_next += arr.exponential(1.0 / rate)
                 while time.perf_counter() < t_next:
@@ -282,27 +289,38 @@ def _serving_study(dev, n_pool, n_jobs, load_fracs, iters, budget_gb, max_active
         res = [srv.poll(i) for i in ids]
         st = srv.stats()
         srv.close()
-        ok = all(r["status"] == 0 for r in res)
-        lat = np.array([r["done_s"] - r["submit_s"] for r in res])
-        dev_lat = np.array([r["done_s"] - r["admit_s"] for r in res])
+        ok = [r for r in res if r["status"] == 0]
+        errors = {}
+        for r in res:
+            if r["status"] != 0:
+                errors[str(r["status"])] = errors.get(str(r["status"]), 0) + 1
+        lat = np.array([r["done_s"] - r["submit_s"] for r in ok])
+        wait = np.array([r["admit_s"] - r["submit_s"] for r in ok])
+        dev_lat = np.array([r["done_s"] - r["start_s"] for r in ok])
         span = max(r["done_s"] for r in res) - min(r["submit_s"] for r in res)
-        return dict(jobs=n_jobs, ok=ok, jobs_per_s=n_jobs / span, span_s=span,
-                    p50_s=float(np.percentile(lat, 50)), p99_s=float(np.percentile(lat, 99)),
-                    p50_device_s=float(np.percentile(dev_lat, 50)), p99_device_s=float(np.percentile(dev_lat, 99)),
-                    mean_s=float(lat.mean()), peak_active=st["peak_active"], ticks=st["ticks"],
-                    busy_frac=st["busy_s"] / max(span, 1e-9), peak_GB=st["peak_bytes"] / 1e9)
+        return dict(jobs=n, completed_ok=len(ok), errors=errors, jobs_per_s=len(ok) / span, span_s=span,
+                    p50_s=pct(lat, 50), p99_s=pct(lat, 99), mean_s=float(lat.mean()) if len(lat) else None,
+                    queue_wait_p50_s=pct(wait, 50), queue_wait_p99_s=pct(wait, 99),
+                    queued_frac=float(np.mean(wait > 1e-3)) if len(wait) else None,
+                    p50_device_s=pct(dev_lat, 50), p99_device_s=pct(dev_lat, 99),
+                    peak_active=st["peak_active"], ticks=st["ticks"],
+                    busy_frac=st["busy_s"] / max(span, 1e-9), peak_GB=st["peak_bytes"] / 1e9,
+                    graph_captures=st["graph_captures"], list_updates=st["list_updates"])
 
     entries_mean = float(np.mean([p_["entries"] for p_ in pool]))
-    sat = run(None)
+    sat = run(n_sat, None)
+    print(f"[bench] serving saturation: {sat['jobs_per_s']:.1f} jobs/s", file=sys.stderr, flush=True)
     mu = sat["jobs_per_s"]
     levels = {"saturation": sat}
     for f in load_fracs:
-        levels[f"{f:.2f}mu"] = run(f * mu)
+        levels[f"{f:.2f}mu"] = run(n_jobs, f * mu)
+        print(f"[bench] serving at {f:.2f} mu: p50 {levels[f'{f:.2f}mu']['p50_s']:.3f} s", file=sys.stderr,
+              flush=True)
     del pool
     torch.cuda.empty_cache()
     return {"workload": f"Poisson stream of 3/4/5-way jobs, 1e5..2e8 entries log-uniform, R in {{8,16,32,64}}, "
                         f"FP32 or BF16, planted + 1% noise, HALS {iters} iterations; {n_pool} distinct tensors "
-                        f"cycled, {n_jobs} jobs per load level",
+                        f"cycled, {n_sat} jobs queued at once for the saturation rate mu, {n_jobs} jobs per load level",
             "generate_s": gen_s, "hbm_budget_GB": budget_gb, "max_active": max_active,
             "pool_entries_mean": entries_mean,
             "levels": levels}
@@ -392,9 +410,12 @@ def main(argv=None):
     ap.add_argument("--batch-iters", type=int, default=30)
     ap.add_argument("--no-serve", action="store_true", help="skip the serving-stream study")
     ap.add_argument("--serve-pool", type=int, default=16)
-    ap.add_argument("--serve-jobs", type=int, default=24)
-    ap.add_argument("--serve-loads", default="0.7", help="comma-separated fractions of the saturation rate")
+    ap.add_argument("--serve-sat-jobs", type=int, default=200)
+    ap.add_argument("--serve-jobs", type=int, default=500)
+    ap.add_argument("--serve-loads", default="0.5,0.8", help="comma-separated fractions of the saturation rate")
     ap.add_argument("--serve-iters", type=int, default=30)
+    ap.add_argument("--serve-budget-gb", type=float, default=6.0)
+    ap.add_argument("--serve-max-active", type=int, default=12)
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run a plain 1 GiB device-to-device copy (for scaling HBM counters)")
     args = ap.parse_args(argv)
@@ -413,8 +434,11 @@ def main(argv=None):
     workload = "x".join(map(str, dims)) + f"_r{R}"
     dev = torch.device("cuda:0")
     X = None
+    Xd = None
     if args.workload == "hsi":
-        X, _ = inputs.hsi_like(dims, R, 0.02, seed=5)
+        Xd = inputs.hsi_like_device(dims, R, 0.02, seed=5, device=dev)
+        if args.dtype != "f32":
+            Xd = native.quantize(Xd, args.dtype)
     elif args.workload == "planted":
         X, _ = inputs.planted(dims, R, 0.01, seed=1, dtype=np.float32)
     H0 = [h.astype(np.float32) for h in inputs.init_factors(dims, R, seed=2)]
@@ -422,7 +446,7 @@ def main(argv=None):
         Xd = native.tensor_to_device(X, device=dev)
         if args.dtype != "f32":
             Xd = native.quantize(Xd, args.dtype)
-    else:  # drawn on the device straight into the storage type (tensors too large for the host path)
+    elif Xd is None:  # drawn on the device straight into the storage type (tensors too large for the host path)
         Xd = inputs.planted_device_slabs(dims, R, 0.01, seed=1, dtype=args.dtype, device=dev)
     sx, nodeb = (4, 8) if args.dtype == "f32" else (2, 4)
     Hd = [native.factor_to_device(h, device=dev) for h in H0]
@@ -532,6 +556,16 @@ def main(argv=None):
     note("main workload")
     if not args.no_lowprec:
         out["lowprec"] = _lowprec_study(dev, args.lowprec_iters)
+        # the metric's BF16 clause: the dominant BF16 partial MTTKRP of the
+        # hyperspectral-shaped workload against the same HBM roofline
+        lp = out["lowprec"]["bf16"]
+        dom16 = "left" if lp["pm_left_ms"] >= lp["pm_right_ms"] else "right"
+        ach16 = lp[f"pm_{dom16}_GBs"]
+        out["roofline_bf16"] = {
+            "bound": "hbm", "achieved": ach16, "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": ach16 / HBM_PEAK_GBS,
+            "traffic": _traffic_from_profile(f"1024x1344x33x9_r50_bf16_{dom16}", lp[f"pm_{dom16}_bytes"], "bf16"),
+            "kernel": f"BF16 partial MTTKRP ({dom16} root node), 1024x1344x33x9 R=50",
+            "bytes_per_launch": lp[f"pm_{dom16}_bytes"], "ms_per_launch": lp[f"pm_{dom16}_ms"]}
         note("low-precision study")
     if not args.no_workloads:
         out["workloads"] = _workloads_study(dev, 20)
@@ -541,8 +575,9 @@ def main(argv=None):
         note("batch study")
     if not args.no_serve:
         loads = [float(x) for x in args.serve_loads.split(",") if x]
-        out["serving"] = _serving_study(dev, args.serve_pool, args.serve_jobs, loads, args.serve_iters,
-                                        budget_gb=96.0, max_active=64)
+        out["serving"] = _serving_study(dev, args.serve_pool, args.serve_sat_jobs, args.serve_jobs, loads,
+                                        args.serve_iters, budget_gb=args.serve_budget_gb,
+                                        max_active=args.serve_max_active)
         note("serving study")
     if not args.no_cpu_baseline and X is not None:
         out["cpu_baseline"] = _cpu_baseline(X, [h.astype(np.float64) for h in H0], args.cpu_iters)

@@ -51,7 +51,7 @@ typedef enum { NNCP_F32 = 0, NNCP_BF16 = 1, NNCP_F16 = 2 } nncp_dtype;
 
 #define NNCP_MAX_MODES 8
 #define NNCP_MAX_RANK 128
-#define NNCP_MAX_SWEEPS 1024
+#define NNCP_MAX_SWEEPS 100000
 
 /* Options; zero-initialised means: automatic split, record every fit, use a
  * HIP graph per outer iteration, no early stop. */
@@ -69,9 +69,16 @@ typedef struct nncp_options {
                           through the dimension tree (two passes): the tree-less baseline */
   int inner_sweeps;   /* update sweeps per block update, 1..NNCP_MAX_SWEEPS (<= 0: 1). HALS: that many
                          Gauss-Seidel passes over the columns, each an exact coordinate minimisation,
-                         so many sweeps approach the exact NNLS solution of the block subproblem
+                         so the sweeps converge to the exact NNLS solution of the block subproblem
                          (Section II-B); MU: that many multiplicative steps. EINVAL above the maximum. */
-  int reserved[5];
+  int reserved0;
+  double inner_tol;   /* > 0: the sweeps of a block update stop early, row by row (each row of a factor
+                         is its own NNLS problem): once a sweep changes no entry of the row by more than
+                         inner_tol x the row's largest entry. With a small inner_tol and a large
+                         inner_sweeps every block update is solved exactly (to that tolerance), the
+                         faithful block coordinate descent of Section II-B. 0: always inner_sweeps
+                         sweeps. EINVAL if negative or not finite. */
+  unsigned long long reserved1;
 } nncp_options;
 
 /* Human-readable text for a status code (static storage). */
@@ -141,6 +148,10 @@ int nncp_plan_time_node(nncp_plan* plan, int mode, int reps, double* ms_avg);
  * events. Rewrites only the tree temporaries and M. */
 int nncp_plan_time_mttkrp(nncp_plan* plan, int reps, double* ms_avg);
 int nncp_plan_destroy(nncp_plan* plan);
+/* Moves the plan to another stream: later calls on it (run, finish, fits, the
+ * timing calls) enqueue on `stream`. The caller orders the switch (the plan's
+ * earlier work must be complete or ordered before work on the new stream). */
+int nncp_plan_set_stream(nncp_plan* plan, void* stream);
 
 /* Root-split autotuning (Section IV-A leaves the root split of the dimension
  * tree free; the cost model picks the split with the smallest node
@@ -172,7 +183,8 @@ int nncp_plan_fits(nncp_plan* plan, double* fit, int cap, int* count);
  * nncp_plan_run on the same state, whatever else is in the batch (this is how
  * jobs are batched without coupling: not in the paper, which runs one
  * decomposition at a time). Members stay owned by the caller; removing or
- * adding a member rebuilds the work lists and the graph at the next run.
+ * adding a member rewrites the device work lists at the next run, without
+ * capturing the graph again unless a new kind of launch is needed.
  * Fits are read per member with nncp_plan_fits. */
 typedef struct nncp_batch nncp_batch;
 int nncp_batch_create(nncp_batch** batch, void* stream);
@@ -183,17 +195,25 @@ int nncp_batch_size(const nncp_batch* batch);
 int nncp_batch_run(nncp_batch* batch, int ticks);
 /* Launches per tick and work items per tick of the current work lists. */
 int nncp_batch_stats(const nncp_batch* batch, int* launches, int64_t* items);
+/* How often the tick's graph was captured and how often the device work lists
+ * were rewritten since the batch was created. A membership change rewrites the
+ * lists in place; the graph is captured again only when a member needs a
+ * launch (a step of its iteration on a kernel variant) that the captured graph
+ * does not have, or a list outgrows its device buffer. Either output may be NULL. */
+int nncp_batch_captures(const nncp_batch* batch, int64_t* captures, int64_t* list_updates);
 int nncp_batch_destroy(nncp_batch* batch);   /* does not destroy the member plans */
 
 /* ---- Serving: continuous batching of jobs that arrive over time ----
- * A worker thread admits submitted jobs in arrival order while fewer than
- * max_active are running and their device footprint (tensor + factors +
- * workspace) fits in hbm_budget_bytes next to the running ones; a job that can
- * never fit is rejected with NNCP_ENOMEM. Admitted jobs stay resident and all
- * of them advance one outer iteration per tick through one batch; a job leaves
- * after its `iters` iterations (results copied to host, device memory freed)
- * and queued jobs are admitted between ticks. Each job's result is that of its
- * stand-alone plan (see nncp_batch). Times are seconds on the server's clock. */
+ * A loader thread admits submitted jobs in arrival order while fewer than
+ * max_active are admitted and their device footprint (tensor + factors +
+ * workspace) fits in hbm_budget_bytes next to the others; a job that can never
+ * fit is rejected with NNCP_ENOMEM. It uploads the job and sets up its plan on
+ * a stream of its own while the running jobs compute. A worker thread advances
+ * every running job one outer iteration per tick through one batch, lets
+ * uploaded jobs join between ticks, and retires a job after its `iters`
+ * iterations (results copied to host, device memory freed in stream order).
+ * Each job's result is that of its stand-alone plan (see nncp_batch). Times
+ * are seconds on the server's clock. */
 typedef struct nncp_server nncp_server;
 #define NNCP_SERVER_SIMULATE 1  /* flag: run the scheduler without a GPU (ticks sleep); for host tests */
 typedef struct nncp_job_request {
@@ -208,14 +228,19 @@ typedef struct nncp_job_request {
 typedef struct nncp_job_result {
   int status;               /* NNCP_EBUSY while queued or running, then NNCP_OK or the error */
   int iters_done;
-  double submit_s, admit_s, done_s;
+  double submit_s;          /* submitted */
+  double admit_s;           /* admitted: memory reserved, upload begins (queue wait = admit_s - submit_s) */
+  double start_s;           /* uploaded and set up, joined the running batch (0 if it never did) */
+  double done_s;            /* finished: results on the host */
   size_t footprint_bytes;
 } nncp_job_result;
 typedef struct nncp_server_stats {
-  int queued, active, peak_active;
+  int queued, active, peak_active;   /* active: jobs in the running batch */
   int64_t ticks, completed, rejected;
   size_t bytes_in_use, peak_bytes, budget_bytes;
   double busy_s, now_s;     /* time spent in ticks; server clock now */
+  int64_t graph_captures;   /* captures of the batch's tick graph (see nncp_batch_captures) */
+  int64_t list_updates;     /* rewrites of its device work lists (membership changes) */
 } nncp_server_stats;
 int nncp_server_create(nncp_server** server, size_t hbm_budget_bytes, int max_active, int flags);
 int nncp_server_submit(nncp_server* server, const nncp_job_request* req, uint64_t* id);
@@ -289,6 +314,20 @@ int nncp_gram(const float* H, int64_t I, int R, double* G, void* stream);
  */
 int nncp_nls_update(const double* M, float* H, int64_t I, int R, const double* S,
                     double* lambda, int update, double* G, void* stream);
+
+/*
+ * The block subproblem of Section II-B solved by repeated update sweeps: the
+ * same as nncp_nls_update, but each row of W (an independent NNLS problem
+ * min_{w >= 0} 1/2 w^T S w - m^T w) gets up to max_sweeps sweeps (HALS: exact
+ * coordinate minimisations, so the row converges to the exact NNLS solution;
+ * MU: multiplicative steps), stopping once a sweep changes no entry of the row
+ * by more than tol x the row's largest entry (tol = 0: always max_sweeps).
+ * W_out: device float64 I x R (column-major) or NULL; receives the solution W
+ * before normalisation and before H is rounded to float32.
+ * max_sweeps in 1..NNCP_MAX_SWEEPS, tol >= 0 and finite, else NNCP_EINVAL.
+ */
+int nncp_nls_solve(const double* M, float* H, int64_t I, int R, const double* S, double* lambda,
+                   int update, int max_sweeps, double tol, double* W_out, double* G, void* stream);
 
 #ifdef __cplusplus
 }

@@ -11,13 +11,14 @@ ROOT = os.path.dirname(PKG)
 CSRC = os.path.join(PKG, "csrc")
 LIB_DIR = os.path.join(PKG, "lib")
 LIB = os.path.join(LIB_DIR, "libnncp.so")
-SOURCES = ["pm_plan.hip", "pm_kernels.hip", "pm16_kernels.hip", "small_kernels.hip", "driver.hip", "server.cpp"]
+SOURCES = ["pm_plan.hip", "pm_kernels.hip", "pm16_kernels.hip", "pm16_bf16.hip", "pm16_f16.hip", "small_kernels.hip",
+           "driver.hip", "server.cpp"]
 
 HIPCC_FLAGS = [
     "--offload-arch=gfx950", "-O3", "-fPIC", "-std=c++17",
     # no packed FP32 instructions anywhere in the device code
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
-    "-Wno-unused-result",
+    "-Wno-unused-result", "-Wno-unused-value",
 ]
 
 

@@ -18,6 +18,7 @@
 #include <algorithm>
 #include <cmath>
 #include <cstring>
+#include <map>
 #include <new>
 #include <vector>
 
@@ -66,6 +67,7 @@ struct Layout {
 
 struct Problem {
   int N = 0, R = 0, dtype = 0, s = 0, update = 0, wg_kib = 0, no_tree = 0, sweeps = 1;
+  double inner_tol = 0.0;
   int64_t dims[kMaxModes] = {};
   int64_t IL = 0, IR = 0, I = 0;
 };
@@ -469,6 +471,7 @@ hipError_t enqueue_iteration(nncp_plan* P, const Sink& st0, std::vector<std::pai
     u.lam_self = P->lam() + (int64_t)n * p.R;
     u.update = p.update;
     u.sweeps = p.sweeps;
+    u.tol = p.inner_tol;
     if ((e = update_launch(u, st)) != hipSuccess) return e;
     const bool last = (n == p.N - 1);
     if ((e = mark(last ? PH_ERR : PH_GRAM)) != hipSuccess) return e;
@@ -553,6 +556,8 @@ int nncp_plan_create(nncp_plan** out, const void* X, int dtype, int N, const int
   p.no_tree = opt ? (opt->no_tree != 0) : 0;
   p.sweeps = (opt && opt->inner_sweeps > 0) ? opt->inner_sweeps : 1;
   if (p.sweeps > NNCP_MAX_SWEEPS) return NNCP_EINVAL;
+  p.inner_tol = opt ? opt->inner_tol : 0.0;
+  if (!(p.inner_tol >= 0.0) || !std::isfinite(p.inner_tol)) return NNCP_EINVAL;
   for (int k = 0; k < N; ++k)
     if (!H[k]) return NNCP_EINVAL;
   nncp_plan* P = new (std::nothrow) nncp_plan();
@@ -703,6 +708,12 @@ int nncp_autotune_split(const void* X, int dtype, int N, const int64_t* dims, in
   }
   if (best == 0) return st_any;
   *best_split = best;
+  return NNCP_OK;
+}
+
+int nncp_plan_set_stream(nncp_plan* P, void* stream) {
+  if (!P) return NNCP_EINVAL;
+  P->user_stream = (hipStream_t)stream;
   return NNCP_OK;
 }
 
@@ -979,8 +990,14 @@ int nncp_gram(const float* H, int64_t I, int R, double* G, void* stream) {
 
 int nncp_nls_update(const double* M, float* H, int64_t I, int R, const double* S, double* lambda, int update,
                     double* G, void* stream) {
+  return nncp_nls_solve(M, H, I, R, S, lambda, update, 1, 0.0, nullptr, G, stream);
+}
+
+int nncp_nls_solve(const double* M, float* H, int64_t I, int R, const double* S, double* lambda, int update,
+                   int max_sweeps, double tol, double* W_out, double* G, void* stream) {
   if (!M || !H || !S || !lambda || !G || I < 1 || R < 1 || R > kMaxRank ||
-      (update != NNCP_HALS && update != NNCP_MU))
+      (update != NNCP_HALS && update != NNCP_MU) || max_sweeps < 1 || max_sweeps > NNCP_MAX_SWEEPS ||
+      !(tol >= 0.0) || !std::isfinite(tol))
     return NNCP_EINVAL;
   hipStream_t hs = (hipStream_t)stream;
   int rpc;
@@ -1002,7 +1019,9 @@ int nncp_nls_update(const double* M, float* H, int64_t I, int R, const double* S
   u.lam_model = lambda;
   u.lam_self = ones;
   u.update = update;
-  u.sweeps = 1;
+  u.sweeps = max_sweeps;
+  u.tol = tol;
+  u.W64 = W_out;
   FinalizeArgs f{};
   f.W = H;
   f.I = I;
@@ -1044,23 +1063,22 @@ struct nncp_batch {
   hipEvent_t ev[2] = {nullptr, nullptr};
   std::vector<nncp_plan*> plans;
   bool dirty = true;
+  // Device work lists. Their addresses are baked into the captured graph; a
+  // membership change rewrites their contents in place between ticks.
   KOp* d_ops = nullptr;
   size_t cap_ops = 0;
   BItem* d_items = nullptr;
   size_t cap_items = 0;
-  int* d_counts = nullptr;
-  size_t cap_counts = 0;
+  int* d_grp = nullptr;  // per captured launch: {first item, item count}
+  size_t cap_grp = 0;
   struct Launch {
-    int family;
-    size_t item_off;
-    int count_idx;
-    unsigned grid;
-    size_t lds;
+    int stage, kid, kind, variant;
   };
-  std::vector<Launch> launches;
+  std::vector<Launch> launches;  // captured launches, in stage order
   hipGraph_t graph = nullptr;
   hipGraphExec_t gexec = nullptr;
   size_t n_items = 0;
+  int64_t captures = 0, list_updates = 0;
 };
 
 namespace {
@@ -1077,12 +1095,15 @@ int device_cus() {
 }
 
 template <typename T>
-int ensure_dev(T** p, size_t* cap, size_t n) {
+int ensure_dev(T** p, size_t* cap, size_t n, size_t floor, bool* moved) {
   if (n <= *cap && *p) return NNCP_OK;
   if (*p) hipFree(*p);
   *p = nullptr;
   *cap = 0;
-  size_t want = n < 16 ? 16 : n + n / 4;
+  *moved = true;
+  // headroom, so that members joining later rarely need a larger list: at
+  // least `floor` entries, else half again the current need
+  size_t want = n < floor ? floor : n + n / 2;
   if (hipMalloc((void**)p, want * sizeof(T)) != hipSuccess) return NNCP_ENOMEM;
   *cap = want;
   return NNCP_OK;
@@ -1095,10 +1116,13 @@ void batch_drop_graph(nncp_batch* B) {
   B->graph = nullptr;
 }
 
+// Records one iteration of every member, groups the records into the launches
+// of one tick (stage order; within a stage one launch per batched kernel) and
+// writes the device work lists. The tick's graph is captured again only when a
+// launch is needed that the captured graph does not have, or a list outgrows
+// its device buffer; otherwise the captured graph runs the new lists as they
+// are (launches with no items of the current members find a count of zero).
 int batch_build(nncp_batch* B) {
-  batch_drop_graph(B);
-  B->launches.clear();
-  B->n_items = 0;
   std::vector<KOp> all;
   for (nncp_plan* P : B->plans) {
     std::vector<KOp> rec;
@@ -1107,76 +1131,148 @@ int batch_build(nncp_batch* B) {
     if (enqueue_iteration(P, sk, nullptr) != hipSuccess) return NNCP_EDEVICE;
     all.insert(all.end(), rec.begin(), rec.end());
   }
-  if (all.empty()) {
-    B->dirty = false;
-    return NNCP_OK;
+  auto key_of = [](int stage, int kid) { return ((int64_t)stage << 32) | (uint32_t)kid; };
+  std::map<int64_t, nncp_batch::Launch> need;
+  for (const KOp& o : all) {
+    const int kid = batch_kernel_id(o.kind, o.variant);
+    need.emplace(key_of(o.stage, kid), nncp_batch::Launch{o.stage, kid, o.kind, o.variant});
   }
-  std::vector<int> keys;
-  for (const KOp& o : all) keys.push_back(o.stage);
-  std::sort(keys.begin(), keys.end());
-  keys.erase(std::unique(keys.begin(), keys.end()), keys.end());
-  std::vector<BItem> items;
-  std::vector<int> counts;
-  const unsigned cus = (unsigned)device_cus();
-  for (int key : keys) {
-    for (int fam = 0; fam < KF_COUNT; ++fam) {
-      const size_t off = items.size();
-      size_t lds = 0;
-      for (size_t i = 0; i < all.size(); ++i) {
-        const KOp& o = all[i];
-        if (o.stage != key || kfamily(o.kind, o.variant) != fam) continue;
-        for (unsigned by = 0; by < o.gy; ++by)
-          for (unsigned bx = 0; bx < o.gx; ++bx) items.push_back(BItem{(int)i, (int)bx, (int)by});
-        lds = std::max(lds, (size_t)o.lds);
-      }
-      const size_t n = items.size() - off;
-      if (n == 0) continue;
-      const unsigned cap = fam == KF_SMALL ? 8 * cus : cus;  // PM tiles, 1024-thread groups: one per CU
-      nncp_batch::Launch l;
-      l.family = fam;
-      l.item_off = off;
-      l.count_idx = (int)counts.size();
-      l.grid = (unsigned)std::min<size_t>(n, cap);
-      l.lds = lds;
-      B->launches.push_back(l);
-      counts.push_back((int)n);
+  std::map<int64_t, nncp_batch::Launch> have;
+  for (const auto& l : B->launches) have.emplace(key_of(l.stage, l.kid), l);
+  bool recapture = !B->gexec;
+  for (const auto& kv : need)
+    if (!have.count(kv.first)) {
+      have.emplace(kv.first, kv.second);
+      recapture = true;
     }
+  // launch order: by stage, then by kernel (the map's key order)
+  std::vector<nncp_batch::Launch> L;
+  std::map<int64_t, int> slot;
+  for (const auto& kv : have) {
+    slot[kv.first] = (int)L.size();
+    L.push_back(kv.second);
   }
+  // items of each launch, contiguous
+  std::vector<std::vector<BItem>> per(L.size());
+  for (size_t i = 0; i < all.size(); ++i) {
+    const KOp& o = all[i];
+    auto& v = per[slot[key_of(o.stage, batch_kernel_id(o.kind, o.variant))]];
+    for (unsigned by = 0; by < o.gy; ++by)
+      for (unsigned bx = 0; bx < o.gx; ++bx) v.push_back(BItem{(int)i, (int)bx, (int)by});
+  }
+  std::vector<BItem> items;
+  std::vector<int> grp(2 * L.size());
+  for (size_t g = 0; g < L.size(); ++g) {
+    grp[2 * g] = (int)items.size();
+    grp[2 * g + 1] = (int)per[g].size();
+    items.insert(items.end(), per[g].begin(), per[g].end());
+  }
+  bool moved = false;
+  if (recapture || all.size() > B->cap_ops || items.size() > B->cap_items || grp.size() > B->cap_grp)
+    batch_drop_graph(B);  // the graph must not outlive the buffers it points at
   int r;
-  if ((r = ensure_dev(&B->d_ops, &B->cap_ops, all.size())) != NNCP_OK) return r;
-  if ((r = ensure_dev(&B->d_items, &B->cap_items, items.size())) != NNCP_OK) return r;
-  if ((r = ensure_dev(&B->d_counts, &B->cap_counts, counts.size())) != NNCP_OK) return r;
-  HIPCHK(hipMemcpyAsync(B->d_ops, all.data(), all.size() * sizeof(KOp), hipMemcpyHostToDevice, B->cap));
-  HIPCHK(hipMemcpyAsync(B->d_items, items.data(), items.size() * sizeof(BItem), hipMemcpyHostToDevice, B->cap));
-  HIPCHK(hipMemcpyAsync(B->d_counts, counts.data(), counts.size() * sizeof(int), hipMemcpyHostToDevice, B->cap));
+  // (at least 2048 ops, 32768 items and 256 launches: a batch of a few dozen
+  // members never has to grow its lists, so joining and leaving never capture)
+  if ((r = ensure_dev(&B->d_ops, &B->cap_ops, all.size(), 2048, &moved)) != NNCP_OK) return r;
+  if ((r = ensure_dev(&B->d_items, &B->cap_items, items.size(), 32768, &moved)) != NNCP_OK) return r;
+  if ((r = ensure_dev(&B->d_grp, &B->cap_grp, grp.size(), 512, &moved)) != NNCP_OK) return r;
+  if (moved) recapture = true;
+  if (!all.empty())
+    HIPCHK(hipMemcpyAsync(B->d_ops, all.data(), all.size() * sizeof(KOp), hipMemcpyHostToDevice, B->cap));
+  if (!items.empty())
+    HIPCHK(hipMemcpyAsync(B->d_items, items.data(), items.size() * sizeof(BItem), hipMemcpyHostToDevice, B->cap));
+  if (!grp.empty())
+    HIPCHK(hipMemcpyAsync(B->d_grp, grp.data(), grp.size() * sizeof(int), hipMemcpyHostToDevice, B->cap));
   HIPCHK(hipStreamSynchronize(B->cap));
   B->n_items = items.size();
-  // one tick = the launches in order, captured once
+  ++B->list_updates;
+  B->dirty = false;
+  if (!recapture) return NNCP_OK;
+
+  batch_drop_graph(B);
+  B->launches = L;
+  const unsigned cus = (unsigned)device_cus();
   HIPCHK(hipStreamBeginCapture(B->cap, hipStreamCaptureModeThreadLocal));
   hipError_t e = hipSuccess;
-  for (const auto& l : B->launches) {
-    const BItem* it = B->d_items + l.item_off;
-    const int* cnt = B->d_counts + l.count_idx;
-    if (l.family == KF_PM_F32) e = batch_launch_pm_f32(it, cnt, B->d_ops, l.grid, l.lds, B->cap);
-    else if (l.family == KF_PM_16) e = batch_launch_pm_16(it, cnt, B->d_ops, l.grid, l.lds, B->cap);
-    else if (l.family == KF_PM_16J1) e = batch_launch_pm_16j1(it, cnt, B->d_ops, l.grid, l.lds, B->cap);
-    else if (l.family == KF_FIN) e = batch_launch_fin(it, cnt, B->d_ops, l.grid, l.lds, B->cap);
-    else e = batch_launch_small(it, cnt, B->d_ops, l.grid, l.lds, B->cap);
-    if (e != hipSuccess) break;
+  for (size_t g = 0; g < L.size() && e == hipSuccess; ++g) {
+    const BatchKernel bk = batch_kernel_for(L[g].kind, L[g].variant);
+    if (!bk.fn) {
+      e = hipErrorInvalidValue;
+      break;
+    }
+    const BItem* it = B->d_items;
+    const int* gp = B->d_grp + 2 * g;
+    const KOp* ops = B->d_ops;
+    void* args[] = {(void*)&it, (void*)&gp, (void*)&ops};
+    e = hipLaunchKernel(bk.fn, dim3((unsigned)bk.per_cu * cus), dim3(bk.threads), args, bk.lds, B->cap);
   }
-  hipGraph_t g = nullptr;
-  hipError_t e2 = hipStreamEndCapture(B->cap, &g);
+  hipGraph_t gr = nullptr;
+  hipError_t e2 = hipStreamEndCapture(B->cap, &gr);
   if (e != hipSuccess || e2 != hipSuccess) {
-    if (g) hipGraphDestroy(g);
+    if (gr) hipGraphDestroy(gr);
+    B->launches.clear();
     return NNCP_EDEVICE;
   }
-  B->graph = g;
-  HIPCHK(hipGraphInstantiate(&B->gexec, g, nullptr, nullptr, 0));
-  B->dirty = false;
+  B->graph = gr;
+  if (hipGraphInstantiate(&B->gexec, gr, nullptr, nullptr, 0) != hipSuccess) {
+    batch_drop_graph(B);
+    B->launches.clear();
+    return NNCP_EDEVICE;
+  }
+  ++B->captures;
   return NNCP_OK;
 }
 
 }  // namespace
+
+namespace nncpk {
+
+int batch_kernel_id(int kind, int variant) {
+  switch (kind) {
+    case K_PM_F32: return 1000000 + variant;
+    case K_PM_16: return 2000000 + variant;
+    case K_PACK16: return 3000000 + variant;
+    case K_FIN1K: case K_GRAM1K: case K_TAIL1K: return 2;
+    default: return 1;
+  }
+}
+
+BatchKernel batch_kernel_for(int kind, int variant) {
+  BatchKernel k;
+  switch (kind) {
+    case K_PM_F32:
+      k.fn = pm_f32_batch_kernel(variant);
+      k.threads = 256;
+      k.lds = pm_variant_max_lds(kind, variant);
+      k.per_cu = k.lds <= 80 * 1024 ? 2 : 1;  // the FP32 kernels are built for two groups per CU
+      break;
+    case K_PM_16:
+      k.fn = pm16_batch_kernel(variant);
+      k.threads = 256;
+      k.lds = pm_variant_max_lds(kind, variant);
+      k.per_cu = 1;
+      break;
+    case K_PACK16:
+      k.fn = pm16_pack_batch_kernel(variant);
+      k.threads = 256;
+      k.per_cu = 4;
+      break;
+    case K_FIN1K: case K_GRAM1K: case K_TAIL1K:
+      k.fn = fin_batch_kernel_ptr();
+      k.threads = 1024;
+      k.lds = fin_batch_max_lds();
+      k.per_cu = 1;
+      break;
+    default:
+      k.fn = small_batch_kernel_ptr();
+      k.threads = 256;
+      k.per_cu = 8;
+      break;
+  }
+  return k;
+}
+
+}  // namespace nncpk
 
 extern "C" {
 
@@ -1247,12 +1343,19 @@ int nncp_batch_stats(const nncp_batch* B, int* launches, int64_t* items) {
   return NNCP_OK;
 }
 
+int nncp_batch_captures(const nncp_batch* B, int64_t* captures, int64_t* list_updates) {
+  if (!B) return NNCP_EINVAL;
+  if (captures) *captures = B->captures;
+  if (list_updates) *list_updates = B->list_updates;
+  return NNCP_OK;
+}
+
 int nncp_batch_destroy(nncp_batch* B) {
   if (!B) return NNCP_EINVAL;
   batch_drop_graph(B);
   if (B->d_ops) hipFree(B->d_ops);
   if (B->d_items) hipFree(B->d_items);
-  if (B->d_counts) hipFree(B->d_counts);
+  if (B->d_grp) hipFree(B->d_grp);
   if (B->cap) hipStreamDestroy(B->cap);
   for (auto& e : B->ev)
     if (e) hipEventDestroy(e);

@@ -55,14 +55,21 @@ struct PmArgs {
   const void* zeros;     // >= 64 bytes of zeros in device memory (read by out-of-range lanes)
   unsigned* counters;    // one per M tile; zero on entry, left zero on exit
   int nsplit;            // (n_i1blk / istages) * n_jblk
-  // 16-bit tensors only: the first contracted factor split into a hi + lo pair of
-  // the tensor's 16-bit type, scaled per column by a power of two (hscale holds
-  // the inverse), laid out [hi rows RP][lo rows RP] x I1pad; and the number of
-  // i1 blocks one work-group walks in turn (restaging LDS between them).
+  int wm;                // waves along M in a work-group (1 or 4); the other 4 / wm split K
+  // the number of i1 blocks one work-group walks in turn (restaging LDS between
+  // them) instead of splitting K over work-groups
+  int istages;
+  // 16-bit tensors only: the first contracted factor split into pm16_terms values
+  // of the tensor's 16-bit type, scaled per column by a power of two (hscale
+  // holds the inverse), laid out [term 0 rows RP][term 1 rows RP]... x I1pad
   unsigned short* hpack;
   float* hscale;
-  int istages;
 };
+
+// 16-bit tensors: the first contracted factor enters the MFMA as a sum of this
+// many values of the tensor's type (FP16: hi + lo, 22 bits; BF16: hi + mid + lo,
+// 24 bits), so the factor operand is as exact as FP32.
+__host__ __device__ constexpr int pm16_terms(int dtype) { return dtype == NNCP_BF16 ? 3 : 2; }
 
 // Plan of one partial-MTTKRP launch (tile shape and split count).
 struct PmLaunch {
@@ -74,10 +81,11 @@ struct PmLaunch {
   int nsplit;
   int I1, I1pad, i1blk, n_i1blk, jblk, n_jblk, fold, istages;
   int j1;        // 16-bit right node with J == 1: the specialised kernel (column scale at the end)
+  int wm;        // waves along M per work-group (1 or 4)
   int64_t J;
   size_t lds_bytes;
   size_t partial_doubles;
-  size_t pack_bytes;     // 16-bit tensors: bytes of the packed hi/lo factor + scales
+  size_t pack_bytes;     // 16-bit tensors: bytes of the packed factor terms + scales
   int ncounters;
 };
 
@@ -90,12 +98,32 @@ hipError_t pm_launch(const PmLaunch& L, const PmArgs& a, hipStream_t st);
 struct Sink;
 struct ReduceArgs;
 hipError_t pm_launch(const PmLaunch& L, const PmArgs& a, const Sink& sk);
-// per-dtype kernels (pm_kernels.hip, pm16_kernels.hip)
+// per-dtype kernels (pm_kernels.hip, pm16_kernels.hip + pm16_bf16.hip / pm16_f16.hip)
 int pm_f32_wave_rows(int side, int nb);
+int pm_f32_kstep(int side);
+size_t pm_f32_reduce_lds(int side, int nb, int wm);
 hipError_t pm_launch_f32(const PmLaunch& L, const PmArgs& a, const Sink& sk);
 int pm_16_wave_rows(int side, int nb, int j1 = 0);
 int pm_16_kstep(int side);
+size_t pm_16_reduce_lds(int side, int nb, int wm);
 hipError_t pm_launch_16(const PmLaunch& L, const PmArgs& a, const Sink& sk);
+template <int DT>
+const void* pm16_kernel(int side, int nb, int j1, int fast, bool batch);
+// Every vector load of every k-step lies inside the tensor for this shape (no
+// padded i1, and on the left side no row group straddling a column end): the
+// kernels then skip the per-step check.
+bool pm_f32_fast(int side, int64_t IL, int I1, int nb);
+bool pm16_fast(int side, int64_t IL, int I1, int nb);
+template <int DT>
+const void* pm16_pack_kernel(bool batch);
+// Batched (work-list) forms of the partial-MTTKRP kernels, by recorded variant.
+const void* pm_f32_batch_kernel(int variant);
+const void* pm16_batch_kernel(int variant);
+const void* pm16_pack_batch_kernel(int variant);
+// Largest dynamic LDS any launch of this partial-MTTKRP variant uses.
+size_t pm_variant_max_lds(int kind, int variant);
+// Lets kernel k use `bytes` of dynamic LDS (once per kernel; thread safe).
+void pm_allow_lds(const void* k, size_t bytes);
 
 // Multi-TTV kernels ---------------------------------------------------------
 struct MttvArgs {
@@ -123,7 +151,10 @@ struct UpdateArgs {
   const double* lam_model;  // current model weights
   const double* lam_self;   // column norms of W as stored
   int update;             // NNCP_HALS / NNCP_MU
-  int sweeps;             // update sweeps (>= 1; 0 is taken as 1)
+  int sweeps;             // update sweeps (>= 1; 0 is taken as 1): at most this many
+  double tol;             // > 0: a row stops once a sweep changes none of its entries by more
+                          // than tol x the row's largest entry
+  double* W64;            // optional: the new W_hat also in FP64 (I x R, column-major)
 };
 hipError_t update_launch(const UpdateArgs& a, hipStream_t st);
 hipError_t update_launch(const UpdateArgs& a, const Sink& sk);
@@ -165,6 +196,9 @@ hipError_t init_model_launch(const double* lam_in, double* lam, double* lam_mode
 // H[k] <- H[k] / lam[k] for all columns; lam[k] <- (lam>0 ? 1 : 0); lam_out_dev <- lam_model
 hipError_t normalize_out_launch(float* W, int64_t I, int R, double* lam_self, hipStream_t st);
 
+// ||X||^2 in FP64: norm_sq_blocks(n) <= kNormSqMaxBlocks groups, each writing one
+// FP64 partial; counter must be zero on entry (the last group resets it).
+constexpr int kNormSqMaxBlocks = 1024;
 hipError_t norm_sq_launch(const void* X, int dtype, int64_t n, double* out, double* partial,
                           unsigned* counter, int nblocks, hipStream_t st);
 int norm_sq_blocks(int64_t n);
@@ -192,7 +226,7 @@ struct ReduceArgs {      // split-K sum of partial-MTTKRP partials
   int64_t Mtot, Mpad;
   int RP, R, col0, nsplit;
 };
-struct PackArgs {        // hi/lo pack of the first contracted factor (16-bit tensors)
+struct PackArgs {        // term pack of the first contracted factor (16-bit tensors)
   const float* H1;
   int I1, I1pad, R, col0, RP;
   unsigned short* pack;
@@ -214,19 +248,6 @@ enum KKind : int {
   K_GRAM1K = 13,    // R <= 64, one row chunk's Gram partial, 1024 threads; variant as K_FIN1K
   K_TAIL1K = 14     // R <= 64, sum of the chunk partials and the finish, 1024 threads
 };
-// Kernel families: one persistent batched kernel each. The 16-bit right-node
-// kernel for J == 1 (variant >= 100000) has a family of its own: it needs ~480
-// registers, and in one kernel with the other bodies it would make them spill.
-// The Gram/finalize kernels for R <= 64 run 1024-thread groups: a family of their own.
-enum KFamily : int { KF_PM_F32 = 0, KF_PM_16 = 1, KF_SMALL = 2, KF_PM_16J1 = 3, KF_FIN = 4, KF_COUNT = 5 };
-inline int kfamily(int kind, int variant) {
-  if (kind == K_PM_F32) return KF_PM_F32;
-  if (kind == K_FIN1K || kind == K_GRAM1K || kind == K_TAIL1K) return KF_FIN;
-  if (kind == K_PM_16) return variant >= 100000 ? KF_PM_16J1 : KF_PM_16;
-  if (kind == K_PACK16) return KF_PM_16;
-  return KF_SMALL;
-}
-
 struct KOp {
   int kind;
   int variant;
@@ -272,18 +293,25 @@ inline int kslot(int kind) {
 // Append a record (host), stamping its stage; returns hipSuccess.
 hipError_t sink_record(const Sink& s, const KOp& op);
 
-// Persistent batched kernels: work-group b walks items b, b + grid, ... < *count
-// of `items`, each naming an op in `ops` (device arrays).
-hipError_t batch_launch_pm_f32(const BItem* items, const int* count, const KOp* ops, unsigned grid, size_t lds,
-                               hipStream_t st);
-hipError_t batch_launch_pm_16(const BItem* items, const int* count, const KOp* ops, unsigned grid, size_t lds,
-                              hipStream_t st);
-hipError_t batch_launch_fin(const BItem* items, const int* count, const KOp* ops, unsigned grid, size_t lds,
-                            hipStream_t st);
-hipError_t batch_launch_small(const BItem* items, const int* count, const KOp* ops, unsigned grid, size_t lds,
-                              hipStream_t st);
-hipError_t batch_launch_pm_16j1(const BItem* items, const int* count, const KOp* ops, unsigned grid, size_t lds,
-                                hipStream_t st);
+// Persistent batched kernels: each has the signature
+//   (const BItem* items, const int* grp, const KOp* ops)
+// and its work-group b walks items grp[0] + b, grp[0] + b + gridDim.x, ...
+// below grp[0] + grp[1] (device arrays), each naming an op in `ops`. Partial
+// MTTKRPs have one such kernel per recorded variant (the stand-alone kernel's
+// body in a loop); the other kinds share a kernel per family (a switch over
+// the kind): the 256-thread small kernels and the 1024-thread Gram/finalize.
+struct BatchKernel {
+  const void* fn = nullptr;
+  int threads = 0;    // block size
+  size_t lds = 0;     // dynamic LDS the kernel is launched with (the most any of its ops uses)
+  int per_cu = 1;     // work-groups kept resident per CU (the persistent grid is per_cu x CUs)
+};
+// Ops of equal id run in the same launch of one stage.
+int batch_kernel_id(int kind, int variant);
+BatchKernel batch_kernel_for(int kind, int variant);
+const void* small_batch_kernel_ptr();
+const void* fin_batch_kernel_ptr();
+size_t fin_batch_max_lds();
 
 // Column scale of a Khatri-Rao operand, prod_j 1/lam[mode_j][r] (device code).
 __device__ __forceinline__ double krp_colscale(const KrpDesc& k, int r) {

@@ -10,6 +10,15 @@ typedef float f2 __attribute__((ext_vector_type(2)));
 
 constexpr int NT = 256;          // threads per work-group (4 waves)
 
+// Vector types of tensor loads, aligned to the element only. A column of a
+// tensor view starts at a multiple of its extent, so for most shapes vector
+// loads are only element-aligned; gfx950 executes unaligned multi-dword global
+// loads, and these types let the compiler emit them.
+template <int L>
+using f32v = float __attribute__((ext_vector_type(L), aligned(4)));
+template <int L>
+using u16v = unsigned short __attribute__((ext_vector_type(L), aligned(2)));
+
 __device__ __forceinline__ f4 mfma4(float a, float b, f4 c) {
   return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
 }
@@ -73,12 +82,10 @@ __device__ __forceinline__ void pm_fill_scales(const PmArgs& a, T* sc, int RP, i
   }
 }
 
-// LDS prologue shared by the FP32 kernels: the block's rows of the first
-// contracted factor, hs[r * hp + i] = H_1(i1_0 + i, col0 + r) (zero padded), and
-// the per-(j, column) scales sc[jj * RP + r]. Eight rows per thread per round
-// trip, loads unconditional from valid addresses.
-__device__ __forceinline__ void pm_prologue(const PmArgs& a, float* hs, int hp, double* sc, int RP, int i1_0,
-                                            int i1n, int64_t j0, int jn) {
+// The FP32 kernels' LDS copy of an i1 block of the first contracted factor:
+// hs[r * hp + i] = H_1(i1_0 + i, col0 + r), zero for i1 >= I1 and r >= R. Eight
+// entries per thread per round trip, loads unconditional from valid addresses.
+__device__ __forceinline__ void pm_stage_h1(const PmArgs& a, float* hs, int hp, int RP, int i1_0, int i1n) {
   const float* f0 = a.krp.f[0];
   const int total = RP * i1n;
   constexpr int CH = 8;
@@ -106,6 +113,13 @@ __device__ __forceinline__ void pm_prologue(const PmArgs& a, float* hs, int hp, 
     for (int c = 0; c < CH; ++c)
       if (dst[c] >= 0) hs[dst[c]] = v[c];
   }
+}
+
+// LDS prologue of the FP32 kernels: the first i1 block of H_1 and the
+// per-(j, column) Khatri-Rao scales sc[jj * RP + r] of the group's j block.
+__device__ __forceinline__ void pm_prologue(const PmArgs& a, float* hs, int hp, double* sc, int RP, int i1_0,
+                                            int i1n, int64_t j0, int jn) {
+  pm_stage_h1(a, hs, hp, RP, i1_0, i1n);
   pm_fill_scales<double>(a, sc, RP, j0, jn, nullptr);
 }
 

@@ -7,23 +7,35 @@
 // Design (gfx950, wave64):
 //  * The reduction index is split as k = i1 + I1*j (i1: first contracted mode).
 //    K(k, :) = H_1(i1, :) * Krest(j, :), so a work-group keeps the H_1 rows of
-//    its i1 block in LDS for the whole kernel (the MFMA B operand), and applies
-//    Krest(j, :) as a per-column factor when it folds each k-step's FP32 MFMA
-//    result into FP64 accumulators (one v_fma_f64 per output). The Khatri-Rao
-//    product is never formed, and the main loop has no barrier.
-//  * X streams from HBM straight into VGPRs with 8/16-byte loads, two k-steps
-//    ahead of the MFMAs (v_mfma_f32_16x16x4_f32), with no branches around the
-//    loads (out-of-range lanes read a valid address and are zeroed).
-//  * Precision: each MFMA chain covers one k-step (16 or 32 products per
-//    output) before it is added into FP64; split-K partials, the cross-wave
-//    reduction and the output are FP64.
+//    its i1 block in LDS (the MFMA B operand), and applies Krest(j, :) as a
+//    per-column factor when it folds the FP32 MFMA sums into FP64 accumulators
+//    (one v_fma_f64 per output). The Khatri-Rao product is never formed.
+//  * X streams from HBM straight into VGPRs with vector loads (8 or 16 bytes per
+//    lane), several k-steps ahead of the MFMAs (v_mfma_f32_16x16x4_f32), for any
+//    shape: a load of padded i1 (>= I1) reads the next j's columns, which meet
+//    zero rows of H_1 in LDS; a load of rows past the output reads into the next
+//    column and only feeds outputs that are never stored. The one k-step that
+//    could read past the end of the tensor loads element by element.
+//  * Precision: each MFMA chain covers at most `fold` k-steps (16 or 32 products
+//    per output each) before it is added into FP64; split-K partials, the
+//    cross-wave reduction and the output are FP64.
 //  * Split-K over (i1 block, j block) pairs: each work-group writes an FP64
 //    partial; a separate reduction kernel sums them in split order, so results
-//    do not depend on scheduling and no cross-XCD fence is needed.
+//    do not depend on scheduling and no cross-XCD fence is needed. A right node
+//    with a tall output walks its i1 blocks inside the work-group instead
+//    (restaging LDS), so it writes only its output.
 #include "pm_common.hpp"
 
 namespace nncpk {
 namespace {
+
+// Rows per left wave = 16 * left_tr(NB); columns per right wave = 16 * right_mc(NB).
+// Chosen so that the FP64 accumulators (2 VGPRs per output) leave room for
+// several k-steps of X in flight without spilling. PF = k-steps in flight.
+constexpr int left_tr(int nb) { return nb >= 4 ? 2 : 4; }
+constexpr int right_mc(int nb) { return nb >= 4 ? 2 : 4; }
+constexpr int left_pf(int nb) { return nb == 2 ? 3 : 4; }
+constexpr int right_pf(int nb) { return 3; }
 
 // ----------------------------------------------------------------------------
 // Left side: T(m, r) = sum_k X[m + IL*k] K(k, r); m is contiguous in X.
@@ -31,28 +43,27 @@ namespace {
 // (li, lq) loads rows TR*li .. TR*li+TR-1 of the columns i1 = base + 4*lq + u,
 // u = 0..3; MFMA chain tt uses row TR*li + tt of every load.
 // ----------------------------------------------------------------------------
-template <int NB, int TR, int WM, bool FAST, int D>
+template <int NB, int D, bool FAST>
 __device__ __forceinline__ void pm_left_f32_body(const PmArgs& a, int bx, int by, int gx) {
-  constexpr bool VEC = FAST;
   constexpr int RP = NB * 16;
-  constexpr int WK = 4 / WM;
+  constexpr int TR = left_tr(NB);
   constexpr int KS = 16;
   constexpr int NACC = TR * NB;
   constexpr int WROWS = 16 * TR;
-  typedef float vT __attribute__((ext_vector_type(TR)));
+  using vT = f32v<TR>;
   extern __shared__ double lds_d[];
   const int hp = a.i1blk + 4;
   float* hs = (float*)lds_d;
   double* sc = lds_d + (RP * hp + 1) / 2;
 
+  const int WM = a.wm, WK = 4 / WM;
   const int lane = threadIdx.x & 63;
   const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   const int wm = wave % WM, wk = wave / WM;
   const int li = lane & 15, lq = lane >> 4;
-  const int64_t Mtot = a.IL;
+  const int64_t Mtot = a.IL, Ktot = a.IR;
   const int mtile = WM * WROWS;
-  const int64_t mbeg = (int64_t)bx * mtile;
-  const int64_t mw = mbeg + wm * WROWS;
+  const int64_t mw = (int64_t)bx * mtile + wm * WROWS;
   const int ib = by % a.n_i1blk, jb = by / a.n_i1blk;
   const int i1_0 = ib * a.i1blk;
   const int i1n = min(a.i1blk, a.I1pad - i1_0);
@@ -74,13 +85,16 @@ __device__ __forceinline__ void pm_left_f32_body(const PmArgs& a, int bx, int by
     for (int e = 0; e < 4; ++e) acc[v][e] = 0.0;
 
   const int64_t m = mw + TR * li;
-  const int64_t mload = (m + TR <= Mtot) ? m : 0;
-  const int ilim = a.I1 - i1_0;  // lane i1 offsets >= ilim are padding
+  const int64_t mload = m < Mtot ? m : 0;  // a row group wholly past the output reads row 0
+  const int ilim = a.I1 - i1_0;            // lane i1 offsets >= ilim are padding
   const float* zeros = (const float*)a.zeros;
-  // lane part of the address of column (colbase + 4*lq + u): loop invariant
-  int64_t lane_off[4];
+  int64_t lane_col[4];                     // lane part of the address of column (colbase + 4*lq + u)
 #pragma unroll
-  for (int u = 0; u < 4; ++u) lane_off[u] = Mtot * (int64_t)(4 * lq + u) + (VEC ? mload : 0);
+  for (int u = 0; u < 4; ++u) lane_col[u] = Mtot * (int64_t)(4 * lq + u);
+  // The vector loads of a step read elements up to Mtot * (colbase + KS) + TR - 2
+  // (row group start <= Mtot - 1, TR rows, in the step's last column): all of
+  // them lie inside the tensor while Mtot * (colbase + KS) <= vec_lim.
+  const int64_t vec_lim = Mtot * Ktot - (TR - 1);
 
   // load cursor (uniform): step = jl * S1 + tl. With one wave along K the group
   // starts at a j rotated by its M tile, so groups that share a split do not all
@@ -88,23 +102,22 @@ __device__ __forceinline__ void pm_left_f32_body(const PmArgs& a, int bx, int by
   const int jrot = (WK == 1 && jn > 1) ? (int)(((unsigned)bx * 5u) % (unsigned)jn) : 0;
   int jl = sb / S1 + jrot, tl = sb - (sb / S1) * S1;
   if (jl >= jn) jl -= jn;  // an empty range (sb == S1 * jn) starts at the block's first j
-  // The cursor always stays inside the group's j block (it wraps), so loads of
-  // steps past the wave's range read valid memory and are simply not used.
-  auto load = [&](vT (&A)[4], bool sv) {
-    (void)sv;
+  // The cursor stays inside the group's j block (it wraps), so loads of steps
+  // past the wave's range read valid memory and are simply not used.
+  auto load = [&](vT (&A)[4]) {
     const int64_t colbase = (int64_t)a.I1 * (j0 + jl) + i1_0 + KS * tl;
     const float* base = X + Mtot * colbase;
+    if (FAST || Mtot * (colbase + KS) <= vec_lim) {  // uniform
 #pragma unroll
-    for (int u = 0; u < 4; ++u) {
-      if (FAST) {
-        // I1 is a multiple of the k-step and rows are aligned: no padding lanes
-        A[u] = __builtin_nontemporal_load((const vT*)(base + lane_off[u]));
-      } else {
+      for (int u = 0; u < 4; ++u) A[u] = __builtin_nontemporal_load((const vT*)(base + lane_col[u] + mload));
+    } else {
+#pragma unroll
+      for (int u = 0; u < 4; ++u) {
         const bool kv = (KS * tl + 4 * lq + u) < ilim;
         vT v;
 #pragma unroll
         for (int e = 0; e < TR; ++e) {
-          const float* p = (kv && m + e < Mtot) ? base + lane_off[u] + m + e : zeros;
+          const float* p = (kv && m + e < Mtot) ? base + lane_col[u] + m + e : zeros;
           v[e] = *p;
         }
         A[u] = v;
@@ -146,7 +159,8 @@ __device__ __forceinline__ void pm_left_f32_body(const PmArgs& a, int bx, int by
 #pragma unroll
         for (int tt = 0; tt < TR; ++tt) {
 #pragma unroll
-          for (int e = 0; e < 4; ++e) acc[tt * NB + nb][e] = __builtin_fma((double)c32[tt][nb][e], scl, acc[tt * NB + nb][e]);
+          for (int e = 0; e < 4; ++e)
+            acc[tt * NB + nb][e] = __builtin_fma((double)c32[tt][nb][e], scl, acc[tt * NB + nb][e]);
           c32[tt][nb] = f4{0.f, 0.f, 0.f, 0.f};
         }
       }
@@ -159,20 +173,19 @@ __device__ __forceinline__ void pm_left_f32_body(const PmArgs& a, int bx, int by
   };
 
   // D k-steps of X in flight: the loads of step s+D are issued right after step
-  // s is consumed. sched_barrier keeps the compiler from sinking them.
-  // The first D loads are issued unconditionally (out-of-range steps read the
-  // zero block) so every path into the loop has the same loads in flight and the
-  // compiler's wait counts stay precise.
+  // s is consumed. sched_barrier keeps the compiler from sinking them. The first
+  // D loads are issued unconditionally so every path into the loop has the same
+  // loads in flight and the compiler's wait counts stay precise.
   vT A[D][4];
   int s = sb;
 #pragma unroll
-  for (int d = 0; d < D; ++d) load(A[d], sb + d < se);
+  for (int d = 0; d < D; ++d) load(A[d]);
   for (; s + D - 1 < se; s += D) {
 #pragma unroll
     for (int d = 0; d < D; ++d) {
       compute(A[d]);
       __builtin_amdgcn_sched_barrier(0);
-      load(A[d], s + D + d < se);
+      load(A[d]);
       __builtin_amdgcn_sched_barrier(0);
     }
   }
@@ -182,64 +195,66 @@ __device__ __forceinline__ void pm_left_f32_body(const PmArgs& a, int bx, int by
 
   __syncthreads();  // LDS is reused by the cross-wave reduction
   wave_reduce_k<NACC>(acc, lds_d, wk, wm, WK);
-  if (wk != 0 && a.nsplit == 1) return;
+  if (wk != 0) return;
 
   // acc[tt*NB+nb][v]: row mw + TR*(4*lq + v) + tt, rank column 16nb + li.
   const bool direct = (a.nsplit == 1);
   const int64_t Mpad = (int64_t)gx * mtile;
-  (void)mbeg;
-  if (wk == 0) {
 #pragma unroll
-    for (int nb = 0; nb < NB; ++nb)
+  for (int nb = 0; nb < NB; ++nb)
 #pragma unroll
-      for (int v = 0; v < 4; ++v) {
-        double o[TR];
+    for (int v = 0; v < 4; ++v) {
+      double o[TR];
 #pragma unroll
-        for (int tt = 0; tt < TR; ++tt) o[tt] = acc[tt * NB + nb][v];
-        pm_store_rows<TR>(a, direct, Mtot, Mpad, RP, by, 16 * nb + li, mw + TR * (4 * lq + v), o);
-      }
-  }
+      for (int tt = 0; tt < TR; ++tt) o[tt] = acc[tt * NB + nb][v];
+      pm_store_rows<TR>(a, direct, Mtot, Mpad, RP, by, 16 * nb + li, mw + TR * (4 * lq + v), o);
+    }
 }
 
 // ----------------------------------------------------------------------------
 // Right side: T(c, r) = sum_k X[k + IL*c] K(k, r); k is contiguous in X.
 // A wave covers MC groups of 16 columns c. In a k-step (32 consecutive i1 of
 // one j), lane (li, lq) loads k = base + 16h + 4*lq + u (u = 0..3 in one
-// 16-byte load, h = 0..1) of column c = group + li.
+// 16-byte load, h = 0..1) of column c = group + li. The work-group walks
+// `istages` i1 blocks (j inside each), restaging LDS between them; istages > 1
+// only with every wave on its own columns (WM = 4).
 // ----------------------------------------------------------------------------
-template <int NB, int MC, int WM, bool FAST, int D>
+template <int NB, int D, bool FAST>
 __device__ __forceinline__ void pm_right_f32_body(const PmArgs& a, int bx, int by, int gx) {
-  constexpr bool VEC = FAST;
   constexpr int RP = NB * 16;
-  constexpr int WK = 4 / WM;
+  constexpr int MC = right_mc(NB);
   constexpr int KS = 32;
   constexpr int NACC = MC * NB;
+  using vT = f32v<4>;
   extern __shared__ double lds_d[];
   const int hp = a.i1blk + 4;
   float* hs = (float*)lds_d;
   double* sc = lds_d + (RP * hp + 1) / 2;
 
+  const int WM = a.wm, WK = 4 / WM;
   const int lane = threadIdx.x & 63;
   const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   const int wm = wave % WM, wk = wave / WM;
   const int li = lane & 15, lq = lane >> 4;
   const int64_t Mtot = a.IR, Ktot = a.IL;
   const int mtile = WM * 16 * MC;
-  const int64_t mbeg = (int64_t)bx * mtile;
-  const int64_t cw = mbeg + wm * 16 * MC;
-  const int ib = by % a.n_i1blk, jb = by / a.n_i1blk;
-  const int i1_0 = ib * a.i1blk;
-  const int i1n = min(a.i1blk, a.I1pad - i1_0);
+  const int64_t cw = (int64_t)bx * mtile + wm * 16 * MC;
+  const int n_i1grp = a.n_i1blk / a.istages;
+  const int ib0 = (by % n_i1grp) * a.istages, jb = by / n_i1grp;
   const int64_t j0 = (int64_t)jb * a.jblk;
   const int jn = (int)min((int64_t)a.jblk, a.J - j0);
   const float* X = (const float*)a.X;
 
-  pm_prologue(a, hs, hp, sc, RP, i1_0, i1n, j0, jn);
+  // stage geometry: all stages have i1blk rows except possibly the last
+  auto stage_rows = [&](int st) { return min(a.i1blk, a.I1pad - (ib0 + st) * a.i1blk); };
+
+  pm_prologue(a, hs, hp, sc, RP, ib0 * a.i1blk, stage_rows(0), j0, jn);
   __syncthreads();
 
-  const int S1 = i1n / KS;
+  int total = 0;
+  for (int st = 0; st < a.istages; ++st) total += (stage_rows(st) / KS) * jn;
   int sb, se;
-  wave_range(S1 * jn, wk, WK, &sb, &se);
+  wave_range(total, wk, WK, &sb, &se);  // istages > 1 implies WK == 1: the whole range
 
   double acc[NACC][4];
 #pragma unroll
@@ -251,39 +266,58 @@ __device__ __forceinline__ void pm_right_f32_body(const PmArgs& a, int bx, int b
 #pragma unroll
   for (int g = 0; g < MC; ++g) {
     const int64_t c = cw + 16 * g + li;
-    colp[g] = X + Ktot * (c < Mtot ? c : 0) + 4 * lq;
+    colp[g] = X + Ktot * (c < Mtot ? c : 0) + 4 * lq;  // columns past the output read column 0
   }
-  const int ilim = a.I1 - i1_0;
+  // The vector loads of a step read elements up to Ktot * cmax + lbase + KS - 1
+  // (cmax: the wave's last column that is read, lane offsets up to KS - 1): all
+  // of them lie inside the tensor while lbase <= vec_lim. Only the steps that
+  // run past the end of a column near the tensor's end fail this.
+  const int64_t cmax = min(cw + 16 * MC - 1, Mtot - 1);
+  const int64_t vec_lim = Mtot * Ktot - Ktot * cmax - KS;  // wave-uniform
   const float* zeros = (const float*)a.zeros;
 
+  // cursor (stage, j, t): t over the stage's k-steps, j over the block (rotated
+  // start with one wave along K), stages in order. The load cursor runs D steps
+  // ahead and wraps to the start after the last step, so it stays in bounds.
   const int jrot = (WK == 1 && jn > 1) ? (int)(((unsigned)bx * 5u) % (unsigned)jn) : 0;
-  int jl = sb / S1 + jrot, tl = sb - (sb / S1) * S1;
-  if (jl >= jn) jl -= jn;  // an empty range (sb == S1 * jn) starts at the block's first j
-  auto load = [&](f4 (&A)[MC][2], bool sv) {
-    (void)sv;
-    const int64_t lbase = (int64_t)a.I1 * (j0 + jl) + i1_0 + KS * tl;
+  int stL = 0, S1L = stage_rows(0) / KS;
+  int jcntL = sb / S1L;  // sb > 0 only when istages == 1
+  int tl = sb - jcntL * S1L;
+  int jl = jcntL + jrot;
+  if (jl >= jn) jl -= jn;
+  auto load = [&](vT (&A)[MC][2]) {
+    const int i1s = (ib0 + stL) * a.i1blk;
+    const int64_t lbase = (int64_t)a.I1 * (j0 + jl) + i1s + KS * tl;
+    if (FAST || lbase <= vec_lim) {  // uniform
 #pragma unroll
-    for (int h = 0; h < 2; ++h) {
-      const int off = KS * tl + 16 * h + 4 * lq;
+      for (int h = 0; h < 2; ++h)
 #pragma unroll
-      for (int g = 0; g < MC; ++g) {
-        if (FAST) {
-          A[g][h] = __builtin_nontemporal_load((const f4*)(colp[g] + lbase + 16 * h));
-        } else {
-          f4 v;
+        for (int g = 0; g < MC; ++g) A[g][h] = __builtin_nontemporal_load((const vT*)(colp[g] + lbase + 16 * h));
+    } else {
+      const int ilimL = a.I1 - i1s;
+#pragma unroll
+      for (int h = 0; h < 2; ++h) {
+        const int off = KS * tl + 16 * h + 4 * lq;
+#pragma unroll
+        for (int g = 0; g < MC; ++g) {
+          vT v;
 #pragma unroll
           for (int e = 0; e < 4; ++e) {
-            const bool kv = off + e < ilim;
-            const float* p = kv ? colp[g] + lbase + 16 * h + e : zeros;
+            const float* p = (off + e < ilimL) ? colp[g] + lbase + 16 * h + e : zeros;
             v[e] = *p;
           }
           A[g][h] = v;
         }
       }
     }
-    if (++tl == S1) {
+    if (++tl == S1L) {
       tl = 0;
       if (++jl == jn) jl = 0;
+      if (++jcntL == jn) {
+        jcntL = 0;
+        if (++stL == a.istages) stL = 0;
+        S1L = stage_rows(stL) / KS;
+      }
     }
   };
 
@@ -292,8 +326,8 @@ __device__ __forceinline__ void pm_right_f32_body(const PmArgs& a, int bx, int b
   for (int g = 0; g < MC; ++g)
 #pragma unroll
     for (int nb = 0; nb < NB; ++nb) c32[g][nb] = f4{0.f, 0.f, 0.f, 0.f};
-  int jc = jl, tc = tl, fc = tl % a.fold, sc_left = se - sb;
-  auto compute = [&](const f4 (&A)[MC][2]) {
+  int stC = 0, S1C = S1L, jc = jl, tc = tl, jcntC = jcntL, fc = tl % a.fold, sc_left = se - sb;
+  auto compute = [&](const vT (&A)[MC][2]) {
     const int kk = KS * tc + 4 * lq;
     f4 B[2][NB];
 #pragma unroll
@@ -309,37 +343,48 @@ __device__ __forceinline__ void pm_right_f32_body(const PmArgs& a, int bx, int b
 #pragma unroll
           for (int nb = 0; nb < NB; ++nb) c32[g][nb] = mfma4(A[g][h][u], B[h][nb][u], c32[g][nb]);
     --sc_left;
-    // fold every `fold` k-steps, at the end of each j (the last i1 block can be
-    // shorter than the others, so fold need not divide its steps) and at the end
-    if (++fc == a.fold || tc + 1 == S1 || sc_left == 0) {
+    // fold every `fold` k-steps, at the end of each j (and so of each stage) and
+    // at the end of the range
+    if (++fc == a.fold || tc + 1 == S1C || sc_left == 0) {
 #pragma unroll
       for (int nb = 0; nb < NB; ++nb) {
         const double scl = sc[jc * RP + 16 * nb + li];
 #pragma unroll
         for (int g = 0; g < MC; ++g) {
 #pragma unroll
-          for (int e = 0; e < 4; ++e) acc[g * NB + nb][e] = __builtin_fma((double)c32[g][nb][e], scl, acc[g * NB + nb][e]);
+          for (int e = 0; e < 4; ++e)
+            acc[g * NB + nb][e] = __builtin_fma((double)c32[g][nb][e], scl, acc[g * NB + nb][e]);
           c32[g][nb] = f4{0.f, 0.f, 0.f, 0.f};
         }
       }
       fc = 0;
     }
-    if (++tc == S1) {
+    if (++tc == S1C) {
       tc = 0;
       if (++jc == jn) jc = 0;
+      if (++jcntC == jn) {
+        jcntC = 0;
+        if (++stC < a.istages && sc_left > 0) {
+          // next i1 block: every wave of the group gets here at the same step
+          __syncthreads();
+          pm_stage_h1(a, hs, hp, RP, (ib0 + stC) * a.i1blk, stage_rows(stC));
+          __syncthreads();
+          S1C = stage_rows(stC) / KS;
+        }
+      }
     }
   };
 
-  f4 A[D][MC][2];
+  vT A[D][MC][2];
   int s = sb;
 #pragma unroll
-  for (int d = 0; d < D; ++d) load(A[d], sb + d < se);
+  for (int d = 0; d < D; ++d) load(A[d]);
   for (; s + D - 1 < se; s += D) {
 #pragma unroll
     for (int d = 0; d < D; ++d) {
       compute(A[d]);
       __builtin_amdgcn_sched_barrier(0);
-      load(A[d], s + D + d < se);
+      load(A[d]);
       __builtin_amdgcn_sched_barrier(0);
     }
   }
@@ -349,102 +394,64 @@ __device__ __forceinline__ void pm_right_f32_body(const PmArgs& a, int bx, int b
 
   __syncthreads();
   wave_reduce_k<NACC>(acc, lds_d, wk, wm, WK);
-  if (wk != 0 && a.nsplit == 1) return;
+  if (wk != 0) return;
 
   // acc[g*NB+nb][v]: column c = cw + 16g + 4*lq + v, rank column 16nb + li.
   const bool direct = (a.nsplit == 1);
   const int64_t Mpad = (int64_t)gx * mtile;
-  (void)mbeg;
-  if (wk == 0) {
 #pragma unroll
-    for (int g = 0; g < MC; ++g)
+  for (int g = 0; g < MC; ++g)
 #pragma unroll
-      for (int nb = 0; nb < NB; ++nb) {
-        double o[4];
+    for (int nb = 0; nb < NB; ++nb) {
+      double o[4];
 #pragma unroll
-        for (int v = 0; v < 4; ++v) o[v] = acc[g * NB + nb][v];
-        pm_store_rows<4>(a, direct, Mtot, Mpad, RP, by, 16 * nb + li, cw + 16 * g + 4 * lq, o);
-      }
+      for (int v = 0; v < 4; ++v) o[v] = acc[g * NB + nb][v];
+      pm_store_rows<4>(a, direct, Mtot, Mpad, RP, by, 16 * nb + li, cw + 16 * g + 4 * lq, o);
+    }
+}
+
+// FAST: the shape guarantees that every vector load of every step lies inside
+// the tensor (pm_f32_fast), so the loads need no per-step check.
+template <int NB, bool FAST>
+__device__ __forceinline__ void pm_f32_body(int side, const PmArgs& a, int bx, int by, int gx) {
+  if (side == 0) pm_left_f32_body<NB, left_pf(NB), FAST>(a, bx, by, gx);
+  else pm_right_f32_body<NB, right_pf(NB), FAST>(a, bx, by, gx);
+}
+
+// Stand-alone kernels: one work-group per (M tile, split).
+template <int SIDE, int NB, bool FAST>
+__global__ __launch_bounds__(NT, 2) void pm_f32(PmArgs a) {
+  pm_f32_body<NB, FAST>(SIDE, a, blockIdx.x, blockIdx.y, gridDim.x);
+}
+
+// Persistent batched form of the same kernel: work-group b takes the items
+// grp[0] + b, grp[0] + b + gridDim.x, ... below grp[0] + grp[1]; each item is one
+// (M tile, split) work-group of a recorded stand-alone launch of this variant.
+template <int SIDE, int NB, bool FAST>
+__global__ __launch_bounds__(NT, 2) void pm_f32_items(const BItem* __restrict__ items, const int* __restrict__ grp,
+                                                      const KOp* __restrict__ ops) {
+  const int off = grp[0], n = grp[1];
+  for (int i = blockIdx.x; i < n; i += gridDim.x) {
+    const BItem it = items[off + i];
+    const KOp& op = ops[it.op];
+    pm_f32_body<NB, FAST>(SIDE, op.u.pm, it.bx, it.by, op.gx);
+    __syncthreads();  // LDS is reused by the next item
   }
 }
 
-// Rows per left wave = 16 * left_tr(NB); columns per right wave = 16 * right_mc(NB).
-// Chosen so that the FP64 accumulators (2 VGPRs per output) leave room for
-// several k-steps of X in flight without spilling. PF = k-steps in flight.
-constexpr int left_tr(int nb) { return nb >= 4 ? 2 : 4; }
-constexpr int right_mc(int nb) { return nb >= 4 ? 2 : 4; }
-constexpr int left_pf(int nb) { return nb == 2 ? 3 : 4; }
-constexpr int right_pf(int nb) { return nb >= 4 ? 3 : 3; }
-
-// Stand-alone kernels: one work-group per (M tile, split).
-template <int NB, int TR, int WM, bool FAST, int D>
-__global__ __launch_bounds__(NT, 2) void pm_left_f32(PmArgs a) {
-  pm_left_f32_body<NB, TR, WM, FAST, D>(a, blockIdx.x, blockIdx.y, gridDim.x);
-}
-template <int NB, int MC, int WM, bool FAST, int D>
-__global__ __launch_bounds__(NT, 2) void pm_right_f32(PmArgs a) {
-  pm_right_f32_body<NB, MC, WM, FAST, D>(a, blockIdx.x, blockIdx.y, gridDim.x);
-}
-
-template <int NB, int WM, bool VEC>
-const void* kernel_ptr(int side) {
-  if (side == 0) return (const void*)pm_left_f32<NB, left_tr(NB), WM, VEC, left_pf(NB)>;
-  return (const void*)pm_right_f32<NB, right_mc(NB), WM, VEC, right_pf(NB)>;
-}
-
-// variant = side*1000 + nb*100 + wm*10 + vec
-const void* select_variant(int v) {
-  const int side = v / 1000;
-  switch (v % 1000) {
-    case 141: return kernel_ptr<1, 4, true>(side);
-    case 140: return kernel_ptr<1, 4, false>(side);
-    case 111: return kernel_ptr<1, 1, true>(side);
-    case 110: return kernel_ptr<1, 1, false>(side);
-    case 241: return kernel_ptr<2, 4, true>(side);
-    case 240: return kernel_ptr<2, 4, false>(side);
-    case 211: return kernel_ptr<2, 1, true>(side);
-    case 210: return kernel_ptr<2, 1, false>(side);
-    case 441: return kernel_ptr<4, 4, true>(side);
-    case 440: return kernel_ptr<4, 4, false>(side);
-    case 411: return kernel_ptr<4, 1, true>(side);
-    case 410: return kernel_ptr<4, 1, false>(side);
+template <int SIDE, bool FAST>
+const void* pick(int nb, bool batch) {
+  switch (nb) {
+    case 1: return batch ? (const void*)pm_f32_items<SIDE, 1, FAST> : (const void*)pm_f32<SIDE, 1, FAST>;
+    case 2: return batch ? (const void*)pm_f32_items<SIDE, 2, FAST> : (const void*)pm_f32<SIDE, 2, FAST>;
+    case 4: return batch ? (const void*)pm_f32_items<SIDE, 4, FAST> : (const void*)pm_f32<SIDE, 4, FAST>;
     default: return nullptr;
   }
 }
 
-template <int NB, int WM, bool VEC>
-__device__ __forceinline__ void body_for(int side, const PmArgs& a, int bx, int by, int gx) {
-  if (side == 0) pm_left_f32_body<NB, left_tr(NB), WM, VEC, left_pf(NB)>(a, bx, by, gx);
-  else pm_right_f32_body<NB, right_mc(NB), WM, VEC, right_pf(NB)>(a, bx, by, gx);
-}
-
-// Persistent batched form: work-group b takes items b, b + gridDim.x, ...; each
-// item is one (M tile, split) work-group of a recorded stand-alone launch.
-__global__ __launch_bounds__(NT, 1) void pm_f32_batch_kernel(const BItem* __restrict__ items,
-                                                             const int* __restrict__ count,
-                                                             const KOp* __restrict__ ops) {
-  const int n = *count;
-  for (int i = blockIdx.x; i < n; i += gridDim.x) {
-    const BItem it = items[i];
-    const KOp& op = ops[it.op];
-    const int v = op.variant, side = v / 1000;
-    switch (v % 1000) {
-      case 141: body_for<1, 4, true>(side, op.u.pm, it.bx, it.by, op.gx); break;
-      case 140: body_for<1, 4, false>(side, op.u.pm, it.bx, it.by, op.gx); break;
-      case 111: body_for<1, 1, true>(side, op.u.pm, it.bx, it.by, op.gx); break;
-      case 110: body_for<1, 1, false>(side, op.u.pm, it.bx, it.by, op.gx); break;
-      case 241: body_for<2, 4, true>(side, op.u.pm, it.bx, it.by, op.gx); break;
-      case 240: body_for<2, 4, false>(side, op.u.pm, it.bx, it.by, op.gx); break;
-      case 211: body_for<2, 1, true>(side, op.u.pm, it.bx, it.by, op.gx); break;
-      case 210: body_for<2, 1, false>(side, op.u.pm, it.bx, it.by, op.gx); break;
-      case 441: body_for<4, 4, true>(side, op.u.pm, it.bx, it.by, op.gx); break;
-      case 440: body_for<4, 4, false>(side, op.u.pm, it.bx, it.by, op.gx); break;
-      case 411: body_for<4, 1, true>(side, op.u.pm, it.bx, it.by, op.gx); break;
-      case 410: body_for<4, 1, false>(side, op.u.pm, it.bx, it.by, op.gx); break;
-      default: break;
-    }
-    __syncthreads();  // LDS is reused by the next item
-  }
+const void* kernel_for(int side, int nb, bool fast, bool batch) {
+  if (side == 0) return fast ? pick<0, true>(nb, batch) : pick<0, false>(nb, batch);
+  return fast ? pick<1, true>(nb, batch) : pick<1, false>(nb, batch);
 }
 
 size_t reduce_lds(int side, int nb, int wm) {
@@ -457,20 +464,23 @@ size_t reduce_lds(int side, int nb, int wm) {
 
 int pm_f32_wave_rows(int side, int nb) { return side == 0 ? 16 * left_tr(nb) : 16 * right_mc(nb); }
 int pm_f32_kstep(int side) { return side == 0 ? 16 : 32; }
+size_t pm_f32_reduce_lds(int side, int nb, int wm) { return reduce_lds(side, nb, wm); }
 
-static bool f32_vec(const PmArgs& a, int side) {
-  // Fast path: vector loads with no masked lanes. Left: 16-byte row loads need an
-  // aligned base and I_L % 4 == 0. Both sides: I1 must be a multiple of the
-  // k-step so the zero-padded tail of H_1 never occurs.
-  bool vec = ((uintptr_t)a.X % 16 == 0) && (a.IL % 4 == 0);
-  return vec && (a.I1 % pm_f32_kstep(side) == 0);
+// Every vector load of every step lies inside the tensor when the k-steps
+// tile I1 exactly (no padded i1) and, on the left side, the row groups tile
+// I_L exactly (no group straddles a column end).
+bool pm_f32_fast(int side, int64_t IL, int I1, int nb) {
+  if (I1 % pm_f32_kstep(side) != 0) return false;
+  return side == 1 || IL % left_tr(nb) == 0;
 }
 
 hipError_t pm_launch_f32(const PmLaunch& L, const PmArgs& a, const Sink& sk) {
-  const int wm = L.mtile / pm_f32_wave_rows(L.side, L.nb);
-  const int variant = L.side * 1000 + L.nb * 100 + wm * 10 + (f32_vec(a, L.side) ? 1 : 0);
-  const void* k = select_variant(variant);
-  if (!k) return hipErrorInvalidValue;
+  const int wm = a.wm;
+  const bool fast = pm_f32_fast(L.side, a.IL, a.I1, L.nb);
+  // variant = side*1000 + nb*100 + fast
+  const int variant = L.side * 1000 + L.nb * 100 + (fast ? 1 : 0);
+  const void* k = kernel_for(L.side, L.nb, fast, false);
+  if (!k || (wm != 1 && wm != 4)) return hipErrorInvalidValue;
   size_t lds = L.lds_bytes;
   if (reduce_lds(L.side, L.nb, wm) > lds) lds = reduce_lds(L.side, L.nb, wm);
   if (sk.rec) {
@@ -483,21 +493,16 @@ hipError_t pm_launch_f32(const PmLaunch& L, const PmArgs& a, const Sink& sk) {
     op.u.pm = a;
     return sink_record(sk, op);
   }
+  if (lds > 64 * 1024) pm_allow_lds(k, 160 * 1024);
   void* args[] = {(void*)&a};
   return hipLaunchKernel(k, dim3(L.mtiles, L.nsplit), dim3(NT), args, lds, sk.st);
 }
 
-hipError_t batch_launch_pm_f32(const BItem* items, const int* count, const KOp* ops, unsigned grid, size_t lds,
-                               hipStream_t st) {
-  static bool attr = [] {
-    (void)hipFuncSetAttribute((const void*)pm_f32_batch_kernel, hipFuncAttributeMaxDynamicSharedMemorySize,
-                              160 * 1024);
-    (void)hipGetLastError();
-    return true;
-  }();
-  (void)attr;
-  hipLaunchKernelGGL(pm_f32_batch_kernel, dim3(grid), dim3(NT), lds, st, items, count, ops);
-  return hipGetLastError();
+const void* pm_f32_batch_kernel(int variant) {
+  const int side = variant / 1000, nb = (variant / 100) % 10;
+  const void* k = kernel_for(side, nb, variant % 10 != 0, true);
+  if (k) pm_allow_lds(k, 160 * 1024);
+  return k;
 }
 
 }  // namespace nncpk

@@ -1,13 +1,11 @@
 // Tile and split-K plan of a partial-MTTKRP launch, and dispatch by tensor dtype.
 #include <cmath>
-#include <cstdlib>
+#include <mutex>
+#include <vector>
 
 #include "pm_common.hpp"
 
 namespace nncpk {
-
-int pm_f32_kstep(int side);
-int pm_16_kstep(int side);
 
 static int num_cus() {
   static int n = [] {
@@ -27,19 +25,29 @@ static int64_t cdiv(int64_t a, int64_t b) { return (a + b - 1) / b; }
 // loads in flight, streams X faster than two or three co-resident groups, and
 // it keeps the split-K partial traffic small), and at least wg_kib KiB of X per
 // group, so a small tensor is not cut into tiles whose LDS staging outweighs
-// their share of X. The count depends on the job alone. NNCP_PM_TARGET_WGS
-// overrides it for tuning.
+// their share of X. The count depends on the job alone.
 static int64_t target_wgs(int64_t x_bytes, int wg_kib) {
-  static const long env = [] {
-    const char* e = std::getenv("NNCP_PM_TARGET_WGS");
-    return e ? std::atol(e) : 0L;
-  }();
-  if (env > 0) return env;
   const int64_t per = (int64_t)(wg_kib > 0 ? wg_kib : 256) * 1024;
   int64_t t = x_bytes / per;
   if (t < 1) t = 1;
   if (t > num_cus()) t = num_cus();
   return t;
+}
+
+// LDS budget of the i1 block of H_1: FP32 rows in ~48 KB (two groups may share a
+// CU), or the 16-bit term rows in up to 128 KB (two terms) or 150 KB (three
+// terms; one group per CU).
+static int lds_rows(int dtype, int RP, int ks) {
+  const bool f32 = dtype == NNCP_F32;
+  const int row_bytes = f32 ? RP * 4 : RP * 2 * pm16_terms(dtype);
+  const int budget = f32 ? 48 * 1024 : (pm16_terms(dtype) == 2 ? 128 * 1024 : 150 * 1024);
+  int maxrows = budget / row_bytes / ks * ks;
+  return maxrows < ks ? ks : maxrows;
+}
+
+static size_t lds_for(int dtype, int RP, int i1blk, int jblk) {
+  if (dtype == NNCP_F32) return (size_t)RP * (i1blk + 4) * sizeof(float) + 8 + (size_t)jblk * RP * sizeof(double);
+  return (size_t)pm16_terms(dtype) * RP * (i1blk + 8) * sizeof(unsigned short) + (size_t)jblk * RP * sizeof(float);
 }
 
 PmLaunch pm_plan(int side, int dtype, int64_t IL, int64_t IR, int I1, int R, int wg_kib) {
@@ -54,24 +62,14 @@ PmLaunch pm_plan(int side, int dtype, int64_t IL, int64_t IR, int I1, int R, int
   const int64_t Ktot = side == 0 ? IR : IL;
   const int ks = f32 ? pm_f32_kstep(side) : pm_16_kstep(side);
   // a tall 16-bit right node with J == 1 uses the specialised kernel (wider waves)
-  // (only where the unmasked path applies: column starts and I1 fit the
-  // 16-byte loads; the tensor base must then be 16-byte aligned at launch)
-  L.j1 = (!f32 && side == 1 && Ktot / I1 == 1 && IL % 8 == 0 && I1 % pm_16_kstep(1) == 0 &&
-          cdiv(Mtot, 4 * pm_16_wave_rows(1, L.nb, 1)) >= 64)
-             ? 1
-             : 0;
+  L.j1 = (!f32 && side == 1 && Ktot / I1 == 1 && cdiv(Mtot, 4 * pm_16_wave_rows(1, L.nb, 1)) >= 64) ? 1 : 0;
   const int wave_rows = f32 ? pm_f32_wave_rows(side, L.nb) : pm_16_wave_rows(side, L.nb, L.j1);
   const int64_t target = target_wgs(IL * IR * (f32 ? 4 : 2), wg_kib);
 
   L.I1 = I1;
   L.J = Ktot / I1;
   L.I1pad = (int)cdiv(I1, ks) * ks;
-  // i1 block held in LDS: FP32 rows of H_1 in ~48 KB (two groups may share a
-  // CU), or the 16-bit hi + lo rows in up to 128 KB (one group per CU).
-  const int row_bytes = RP * 4;
-  const int budget = f32 ? 48 * 1024 : 128 * 1024;
-  int maxrows = budget / row_bytes / ks * ks;
-  if (maxrows < ks) maxrows = ks;
+  const int maxrows = lds_rows(dtype, RP, ks);
   L.n_i1blk = (int)cdiv(L.I1pad, maxrows);
   L.i1blk = (int)cdiv(cdiv(L.I1pad, L.n_i1blk), ks) * ks;
   L.n_i1blk = (int)cdiv(L.I1pad, L.i1blk);
@@ -82,23 +80,16 @@ PmLaunch pm_plan(int side, int dtype, int64_t IL, int64_t IR, int I1, int R, int
   int wm = 4;
   if (cdiv(Mtot, 4 * wave_rows) < 64) wm = 1;
   if (side == 0 && cdiv(Mtot, wave_rows) >= target) wm = 1;
-  {
-    // tuning override: NNCP_PM_WM = 1 or 4 (waves along M per work-group)
-    static const int env_wm = [] {
-      const char* e = std::getenv("NNCP_PM_WM");
-      return e ? std::atoi(e) : 0;
-    }();
-    if (env_wm == 1 || env_wm == 4) wm = env_wm;
-  }
   if (L.j1) wm = 4;
+  L.wm = wm;
   L.mtile = wm * wave_rows;
   L.mtiles = (int)cdiv(Mtot, L.mtile);
 
-  // A 16-bit right node with a tall output and several i1 blocks walks the
-  // blocks inside each work-group (restaging LDS) instead of splitting K: the
-  // split-K partials of a tall output would cost more HBM traffic than X.
+  // A right node with a tall output and several i1 blocks walks the blocks
+  // inside each work-group (restaging LDS) instead of splitting K: the split-K
+  // partials of a tall output would cost more HBM traffic than X.
   L.istages = 1;
-  if (!f32 && side == 1 && wm == 4 && L.n_i1blk > 1 && L.mtiles >= target) L.istages = L.n_i1blk;
+  if (side == 1 && wm == 4 && L.n_i1blk > 1 && L.mtiles >= target) L.istages = L.n_i1blk;
   const int n_i1grp = L.n_i1blk / L.istages;
 
   const int64_t steps_per_j = L.i1blk / ks;
@@ -132,13 +123,9 @@ PmLaunch pm_plan(int side, int dtype, int64_t IL, int64_t IR, int I1, int R, int
   }
   L.n_jblk = (int)cdiv(L.J, jblk);
   L.nsplit = n_i1grp * L.n_jblk;
-  if (f32) {
-    L.lds_bytes = (size_t)RP * (L.i1blk + 4) * sizeof(float) + 8 + (size_t)L.jblk * RP * sizeof(double);
-    L.pack_bytes = 0;
-  } else {
-    L.lds_bytes = (size_t)2 * RP * (L.i1blk + 8) * sizeof(unsigned short) + (size_t)L.jblk * RP * sizeof(float);
-    L.pack_bytes = (size_t)2 * RP * L.I1pad * sizeof(unsigned short) + 256 + (size_t)RP * sizeof(float);
-  }
+  L.lds_bytes = lds_for(dtype, RP, L.i1blk, L.jblk);
+  L.pack_bytes =
+      f32 ? 0 : (size_t)pm16_terms(dtype) * RP * L.I1pad * sizeof(unsigned short) + 256 + (size_t)RP * sizeof(float);
   L.partial_doubles = L.nsplit > 1 ? (size_t)L.nsplit * RP * (size_t)L.mtiles * L.mtile : 0;
   L.ncounters = L.mtiles;
   return L;
@@ -155,6 +142,29 @@ void pm_fill_args(const PmLaunch& L, PmArgs& a) {
   a.fold = L.fold;
   a.nsplit = L.nsplit;
   a.istages = L.istages;
+  a.wm = L.wm;
+}
+
+size_t pm_variant_max_lds(int kind, int variant) {
+  const bool f32 = kind == K_PM_F32;
+  const int dtype = f32 ? NNCP_F32 : (((variant / 10000) % 10) ? NNCP_BF16 : NNCP_F16);
+  const int side = (variant / 1000) % 10, nb = (variant / 100) % 10;
+  const int RP = 16 * nb;
+  const int ks = f32 ? pm_f32_kstep(side) : pm_16_kstep(side);
+  size_t lds = lds_for(dtype, RP, lds_rows(dtype, RP, ks), 64);
+  const size_t red = f32 ? pm_f32_reduce_lds(side, nb, 1) : pm_16_reduce_lds(side, nb, 1);
+  return lds > red ? lds : red;
+}
+
+void pm_allow_lds(const void* k, size_t bytes) {
+  static std::mutex mu;
+  static std::vector<const void*> done;
+  std::lock_guard<std::mutex> lk(mu);
+  for (const void* d : done)
+    if (d == k) return;
+  if (hipFuncSetAttribute(k, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes) != hipSuccess)
+    (void)hipGetLastError();
+  done.push_back(k);
 }
 
 hipError_t pm_launch(const PmLaunch& L, const PmArgs& a, const Sink& sk) {

@@ -1,11 +1,21 @@
 // Serving loop: NNCP jobs of uneven order, shape, rank and storage type arrive
-// at any time; a worker thread admits them by device footprint against an HBM
-// budget, keeps each admitted job's tensor, factors and workspace resident, and
-// advances every admitted job by one outer iteration per tick through one
-// batch (continuous batching: jobs join and leave between ticks while others
-// keep running). A job's arithmetic is that of its stand-alone plan, so its
-// result does not depend on the mix. Not part of the paper, which runs one
-// decomposition at a time; this is the serving layer around its method.
+// at any time. Two native threads share the GPU:
+//  * the loader admits queued jobs in arrival order while fewer than
+//    max_active are admitted and their device footprint fits the HBM budget
+//    next to the others; it allocates the job's buffers (stream-ordered, so no
+//    device-wide synchronisation), uploads the tensor and starting factors and
+//    builds the job's plan (||X||^2, starting Grams) on its own stream, while
+//    the running jobs keep computing;
+//  * the worker advances every running job by one outer iteration per tick
+//    through one batch, moves jobs whose upload has finished into the batch
+//    between ticks, and retires finished jobs (results to host, buffers freed
+//    on the loader's stream).
+// This is continuous batching: jobs join and leave between ticks while others
+// keep running, and the batch rewrites its device work lists in place rather
+// than capturing its graph again. A job's arithmetic is that of its
+// stand-alone plan, so its result does not depend on the mix. Not part of the
+// paper, which runs one decomposition at a time; this is the serving layer
+// around its method.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -37,15 +47,15 @@ struct Job {
   int64_t I = 0;
   std::vector<std::vector<float>> H0;  // copied at submit
   size_t footprint = 0;
-  // device state while active
+  // device state while admitted
   void* Xd = nullptr;
   float* Hd[NNCP_MAX_MODES] = {};
   void* ws = nullptr;
   nncp_plan* plan = nullptr;
   int done_iters = 0;
   // timeline (seconds on the server clock) and outcome
-  double t_submit = 0, t_admit = 0, t_done = 0;
-  int status = NNCP_EBUSY;  // EBUSY while queued/active, then OK or an error
+  double t_submit = 0, t_admit = 0, t_start = 0, t_done = 0;
+  int status = NNCP_EBUSY;  // EBUSY while queued/admitted, then OK or an error
   std::vector<std::vector<float>> H;  // results
   std::vector<double> lam, fit;
 };
@@ -59,19 +69,22 @@ struct nncp_server {
   int device = 0;
   Clock::time_point t0;
   std::mutex mu;
-  std::condition_variable cv_work, cv_done;
-  std::deque<uint64_t> queue;
+  std::condition_variable cv_load, cv_work, cv_done;
+  std::deque<uint64_t> queue;              // submitted, not yet admitted
   std::map<uint64_t, std::unique_ptr<Job>> jobs;
-  std::vector<Job*> active;
+  std::vector<Job*> ready;                 // uploaded, waiting to join the batch
+  std::vector<Job*> active;                // in the batch
+  int admitted = 0;                        // loading + ready + active
   uint64_t next_id = 1;
   size_t used = 0, peak_used = 0;
   int64_t ticks = 0, completed = 0, rejected = 0;
   int peak_active = 0;
   double busy_s = 0;
-  bool stop = false;
-  hipStream_t st = nullptr;
+  bool stop = false, loader_done = false;
+  hipStream_t st = nullptr;    // worker: batch ticks, results to host
+  hipStream_t up = nullptr;    // loader: allocation, upload, plan set-up, frees
   nncp_batch* batch = nullptr;
-  std::thread worker;
+  std::thread loader, worker;
 
   double now() const { return std::chrono::duration<double>(Clock::now() - t0).count(); }
 };
@@ -87,42 +100,49 @@ size_t job_footprint(const Job& j) {
   return b;
 }
 
-void release_device(Job* j) {
+// Frees the job's device buffers in stream order on the loader's stream (no
+// device-wide synchronisation; the caller has finished using them).
+void release_device(nncp_server* S, Job* j) {
   if (j->plan) nncp_plan_destroy(j->plan);
   j->plan = nullptr;
   for (int n = 0; n < j->N; ++n)
-    if (j->Hd[n]) hipFree(j->Hd[n]);
-  if (j->Xd) hipFree(j->Xd);
-  if (j->ws) hipFree(j->ws);
+    if (j->Hd[n]) (void)hipFreeAsync(j->Hd[n], S->up);
+  if (j->Xd) (void)hipFreeAsync(j->Xd, S->up);
+  if (j->ws) (void)hipFreeAsync(j->ws, S->up);
   j->Xd = nullptr;
   j->ws = nullptr;
   for (auto& h : j->Hd) h = nullptr;
 }
 
-// Upload the tensor and starting factors and create the job's plan.
-int admit_device(nncp_server* S, Job* j) {
+// Loader thread: allocate, upload the tensor and starting factors, and build
+// the job's plan, all on the loader's stream.
+int load_device(nncp_server* S, Job* j) {
+  hipStream_t s = S->up;
   const size_t xb = (size_t)j->I * elem_bytes(j->dtype);
-  if (hipMalloc(&j->Xd, xb) != hipSuccess) return NNCP_ENOMEM;
-  if (hipMemcpyAsync(j->Xd, j->X, xb, hipMemcpyHostToDevice, S->st) != hipSuccess) return NNCP_EDEVICE;
+  if (hipMallocAsync(&j->Xd, xb, s) != hipSuccess) return NNCP_ENOMEM;
+  if (hipMemcpyAsync(j->Xd, j->X, xb, hipMemcpyHostToDevice, s) != hipSuccess) return NNCP_EDEVICE;
   for (int n = 0; n < j->N; ++n) {
     const size_t hb = (size_t)j->dims[n] * j->R * sizeof(float);
-    if (hipMalloc((void**)&j->Hd[n], hb) != hipSuccess) return NNCP_ENOMEM;
-    if (hipMemcpyAsync(j->Hd[n], j->H0[n].data(), hb, hipMemcpyHostToDevice, S->st) != hipSuccess)
+    if (hipMallocAsync((void**)&j->Hd[n], hb, s) != hipSuccess) return NNCP_ENOMEM;
+    if (hipMemcpyAsync(j->Hd[n], j->H0[n].data(), hb, hipMemcpyHostToDevice, s) != hipSuccess)
       return NNCP_EDEVICE;
   }
   nncp_options o{};
   o.split = j->split;
-  o.no_graph = 1;
+  o.no_graph = 1;  // advanced by the batch's graph only
   const size_t wsb = nncp_workspace_bytes(j->N, j->dims, j->R, j->dtype, &o);
   if (wsb == 0) return NNCP_EINVAL;
-  if (hipMalloc(&j->ws, wsb) != hipSuccess) return NNCP_ENOMEM;
+  if (hipMallocAsync(&j->ws, wsb, s) != hipSuccess) return NNCP_ENOMEM;
+  // plan set-up runs on the loader's stream and synchronises it; the plan's
+  // later calls (finish, fits) are the worker's
   int r = nncp_plan_create(&j->plan, j->Xd, j->dtype, j->N, j->dims, j->R, j->update, j->Hd, nullptr, j->ws, wsb,
-                           &o, S->st);
+                           &o, s);
   if (r != NNCP_OK) return r;
-  return nncp_batch_add(S->batch, j->plan);
+  return nncp_plan_set_stream(j->plan, S->st);
 }
 
-// Finished: normalised factors, lambda and fits to host, then free the device side.
+// Worker thread, job finished: normalised factors, lambda and fits to host,
+// then the device buffers are released.
 int retire_device(nncp_server* S, Job* j) {
   int r = nncp_batch_remove(S->batch, j->plan);
   j->lam.assign(j->R, 0.0);
@@ -141,57 +161,103 @@ int retire_device(nncp_server* S, Job* j) {
       r = NNCP_EDEVICE;
   }
   if (hipStreamSynchronize(S->st) != hipSuccess && r == NNCP_OK) r = NNCP_EDEVICE;
-  release_device(j);
+  release_device(S, j);
   return r;
+}
+
+void finish_job(nncp_server* S, Job* j, int status) {  // with S->mu held
+  j->status = status;
+  j->t_done = S->now();
+  S->used -= j->footprint;
+  --S->admitted;
+  S->cv_load.notify_all();
+  S->cv_done.notify_all();
+}
+
+void loader_loop(nncp_server* S) {
+  if (!S->simulate) (void)hipSetDevice(S->device);
+  std::unique_lock<std::mutex> lk(S->mu);
+  while (true) {
+    if (S->queue.empty()) {
+      if (S->stop) break;
+      S->cv_load.wait(lk);
+      continue;
+    }
+    Job* j = S->jobs[S->queue.front()].get();
+    if (j->footprint > S->budget) {  // can never fit
+      S->queue.pop_front();
+      j->status = NNCP_ENOMEM;
+      j->t_done = S->now();
+      ++S->rejected;
+      S->cv_done.notify_all();
+      continue;
+    }
+    // arrival order: the head waits for a slot and for memory
+    if (S->admitted >= S->max_active || S->used + j->footprint > S->budget) {
+      S->cv_load.wait(lk);
+      continue;
+    }
+    S->queue.pop_front();
+    S->used += j->footprint;
+    S->peak_used = std::max(S->peak_used, S->used);
+    ++S->admitted;
+    j->t_admit = S->now();
+    lk.unlock();
+    int r = NNCP_OK;
+    if (S->simulate) {
+      std::this_thread::sleep_for(std::chrono::microseconds(20));
+    } else {
+      r = load_device(S, j);
+      if (r != NNCP_OK) release_device(S, j);
+    }
+    lk.lock();
+    if (r != NNCP_OK) {
+      ++S->rejected;
+      finish_job(S, j, r);
+      continue;
+    }
+    S->ready.push_back(j);
+    S->cv_work.notify_all();
+  }
+  S->loader_done = true;
+  S->cv_work.notify_all();
 }
 
 void worker_loop(nncp_server* S) {
   if (!S->simulate) (void)hipSetDevice(S->device);
   std::unique_lock<std::mutex> lk(S->mu);
   while (true) {
-    // admission, in arrival order, while slots and memory allow
-    while (!S->queue.empty() && (int)S->active.size() < S->max_active) {
-      Job* j = S->jobs[S->queue.front()].get();
-      if (j->footprint > S->budget) {  // can never fit
-        S->queue.pop_front();
-        j->status = NNCP_ENOMEM;
-        j->t_done = S->now();
-        ++S->rejected;
-        S->cv_done.notify_all();
-        continue;
-      }
-      if (S->used + j->footprint > S->budget) break;  // wait for memory to free up
-      S->queue.pop_front();
-      S->used += j->footprint;
-      S->peak_used = std::max(S->peak_used, S->used);
-      j->t_admit = S->now();
-      int r = NNCP_OK;
-      if (!S->simulate) {
-        lk.unlock();
-        r = admit_device(S, j);
-        lk.lock();
-      }
-      if (r != NNCP_OK) {
-        if (!S->simulate) {
-          if (j->plan) nncp_batch_remove(S->batch, j->plan);
-          release_device(j);
+    // jobs whose upload has finished join the batch
+    if (!S->ready.empty()) {
+      std::vector<Job*> joining;
+      joining.swap(S->ready);
+      const double t = S->now();
+      lk.unlock();
+      std::vector<int> codes(joining.size(), NNCP_OK);
+      if (!S->simulate)
+        for (size_t k = 0; k < joining.size(); ++k) codes[k] = nncp_batch_add(S->batch, joining[k]->plan);
+      lk.lock();
+      for (size_t k = 0; k < joining.size(); ++k) {
+        Job* j = joining[k];
+        if (codes[k] != NNCP_OK) {
+          lk.unlock();
+          if (!S->simulate) release_device(S, j);
+          lk.lock();
+          ++S->rejected;
+          finish_job(S, j, codes[k]);
+          continue;
         }
-        S->used -= j->footprint;
-        j->status = r;
-        j->t_done = S->now();
-        ++S->rejected;
-        S->cv_done.notify_all();
-        continue;
+        j->t_start = t;
+        S->active.push_back(j);
       }
-      S->active.push_back(j);
       S->peak_active = std::max(S->peak_active, (int)S->active.size());
     }
     if (S->active.empty()) {
-      if (S->stop) break;
+      if (S->loader_done && S->ready.empty()) break;
       S->cv_work.wait(lk);
       continue;
     }
-    // one tick: every active job advances one outer iteration
+    // one tick: every running job advances one outer iteration
     std::vector<Job*> act = S->active;
     lk.unlock();
     const double tb = S->now();
@@ -212,6 +278,7 @@ void worker_loop(nncp_server* S) {
       ++j->done_iters;
       if (r != NNCP_OK || j->done_iters >= j->iters) finished.push_back(j);
     }
+    for (Job* j : finished) S->active.erase(std::find(S->active.begin(), S->active.end(), j));
     lk.unlock();
     std::vector<int> codes(finished.size(), r);
     if (!S->simulate)
@@ -220,20 +287,14 @@ void worker_loop(nncp_server* S) {
           codes[k] = retire_device(S, finished[k]);
         } else {
           nncp_batch_remove(S->batch, finished[k]->plan);
-          release_device(finished[k]);
+          release_device(S, finished[k]);
         }
       }
     lk.lock();
-    const double td = S->now();
     for (size_t k = 0; k < finished.size(); ++k) {
-      Job* j = finished[k];
-      S->active.erase(std::find(S->active.begin(), S->active.end(), j));
-      S->used -= j->footprint;
-      j->status = codes[k];
-      j->t_done = td;
       ++S->completed;
+      finish_job(S, finished[k], codes[k]);
     }
-    if (!finished.empty()) S->cv_done.notify_all();
   }
 }
 
@@ -251,22 +312,34 @@ int nncp_server_create(nncp_server** out, size_t hbm_budget_bytes, int max_activ
   S->simulate = (flags & NNCP_SERVER_SIMULATE) != 0;
   S->t0 = Clock::now();
   if (!S->simulate) {
-    if (hipGetDevice(&S->device) != hipSuccess || hipStreamCreateWithFlags(&S->st, hipStreamNonBlocking) != hipSuccess) {
+    if (hipGetDevice(&S->device) != hipSuccess || hipStreamCreateWithFlags(&S->st, hipStreamNonBlocking) != hipSuccess ||
+        hipStreamCreateWithFlags(&S->up, hipStreamNonBlocking) != hipSuccess) {
+      if (S->st) hipStreamDestroy(S->st);
       delete S;
       return NNCP_EDEVICE;
     }
     int r = nncp_batch_create(&S->batch, S->st);
     if (r != NNCP_OK) {
       hipStreamDestroy(S->st);
+      hipStreamDestroy(S->up);
       delete S;
       return r;
     }
   }
   try {
+    S->loader = std::thread(loader_loop, S);
     S->worker = std::thread(worker_loop, S);
   } catch (...) {
+    {
+      std::lock_guard<std::mutex> lk(S->mu);
+      S->stop = true;
+    }
+    S->cv_load.notify_all();
+    if (S->loader.joinable()) S->loader.join();
+    if (S->worker.joinable()) S->worker.join();
     if (S->batch) nncp_batch_destroy(S->batch);
     if (S->st) hipStreamDestroy(S->st);
+    if (S->up) hipStreamDestroy(S->up);
     delete S;
     return NNCP_ENOMEM;
   }
@@ -311,7 +384,7 @@ int nncp_server_submit(nncp_server* S, const nncp_job_request* q, uint64_t* id) 
   *id = j->id;
   S->queue.push_back(j->id);
   S->jobs[j->id] = std::move(j);
-  S->cv_work.notify_one();
+  S->cv_load.notify_all();
   return NNCP_OK;
 }
 
@@ -326,6 +399,7 @@ int nncp_server_poll(nncp_server* S, uint64_t id, nncp_job_result* res) {
     res->iters_done = j->done_iters;
     res->submit_s = j->t_submit;
     res->admit_s = j->t_admit;
+    res->start_s = j->t_start;
     res->done_s = j->t_done;
     res->footprint_bytes = j->footprint;
   }
@@ -381,6 +455,14 @@ int nncp_server_get_stats(nncp_server* S, nncp_server_stats* out) {
   out->budget_bytes = S->budget;
   out->busy_s = S->busy_s;
   out->now_s = S->now();
+  out->graph_captures = 0;
+  out->list_updates = 0;
+  if (S->batch) {
+    int64_t c = 0, u = 0;
+    nncp_batch_captures(S->batch, &c, &u);
+    out->graph_captures = c;
+    out->list_updates = u;
+  }
   return NNCP_OK;
 }
 
@@ -389,7 +471,7 @@ int nncp_server_destroy(nncp_server* S) {
   {
     std::lock_guard<std::mutex> lk(S->mu);
     S->stop = true;
-    // queued jobs that never started are cancelled; active ones finish
+    // queued jobs that never started are cancelled; admitted ones finish
     for (uint64_t id : S->queue) {
       Job* j = S->jobs[id].get();
       j->status = NNCP_ECANCELED;
@@ -397,9 +479,15 @@ int nncp_server_destroy(nncp_server* S) {
     }
     S->queue.clear();
   }
-  S->cv_work.notify_all();
+  S->cv_load.notify_all();
+  S->cv_done.notify_all();
+  if (S->loader.joinable()) S->loader.join();
   if (S->worker.joinable()) S->worker.join();
   if (S->batch) nncp_batch_destroy(S->batch);
+  if (S->up) {
+    (void)hipStreamSynchronize(S->up);
+    hipStreamDestroy(S->up);
+  }
   if (S->st) hipStreamDestroy(S->st);
   delete S;
   return NNCP_OK;

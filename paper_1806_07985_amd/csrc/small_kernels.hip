@@ -67,16 +67,49 @@ __device__ __forceinline__ bool last_block(unsigned* counter, unsigned total) {
 // --------------------------------------------------------------------------
 // ||X||^2 in FP64
 // --------------------------------------------------------------------------
+// Each thread reads 16-byte vectors (4 FP32 or 8 16-bit values), eight of them
+// issued before any is used; the vector type is aligned to the element only, so
+// any element-aligned base works. The n % VEC tail is read by block 0. Squares
+// are exact in FP64 (a 24-bit significand squared fits 53 bits) and summed in
+// FP64; the block sums are added by the last block in block order, so the
+// result does not depend on scheduling.
 template <typename T>
 __global__ __launch_bounds__(NT) void norm_sq_kernel(const T* X, int64_t n, double* out,
                                                      double* partial, unsigned* counter) {
+  constexpr int VEC = 16 / sizeof(T);
+  constexpr int U = 8;
+  typedef T vT __attribute__((ext_vector_type(VEC), aligned(sizeof(T))));
   __shared__ double sh[NT / 64];
-  double s = 0.0;
+  const vT* V = (const vT*)X;
+  const int64_t nv = n / VEC;
   const int64_t stride = (int64_t)gridDim.x * NT;
-  for (int64_t i = (int64_t)blockIdx.x * NT + threadIdx.x; i < n; i += stride) {
-    double v = to_f64<T>(X[i]);
-    s += v * v;
+  double s = 0.0;
+  int64_t i = (int64_t)blockIdx.x * NT + threadIdx.x;
+  for (; i + (U - 1) * stride < nv; i += U * stride) {
+    vT v[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u) v[u] = __builtin_nontemporal_load(V + i + u * stride);
+#pragma unroll
+    for (int u = 0; u < U; ++u)
+#pragma unroll
+      for (int e = 0; e < VEC; ++e) {
+        const double x = to_f64<T>(v[u][e]);
+        s = __builtin_fma(x, x, s);
+      }
   }
+  for (; i < nv; i += stride) {
+    const vT v = __builtin_nontemporal_load(V + i);
+#pragma unroll
+    for (int e = 0; e < VEC; ++e) {
+      const double x = to_f64<T>(v[e]);
+      s = __builtin_fma(x, x, s);
+    }
+  }
+  if (blockIdx.x == 0)
+    for (int64_t e = nv * VEC + threadIdx.x; e < n; e += NT) {
+      const double x = to_f64<T>(X[e]);
+      s = __builtin_fma(x, x, s);
+    }
   double t = block_sum(s, sh);
   if (threadIdx.x == 0) partial[blockIdx.x] = t;
   if (!last_block(counter, gridDim.x)) return;
@@ -279,50 +312,73 @@ __device__ __forceinline__ void update_body(const UpdateArgs& a, int bx) {
   };
   wS();
   const int sweeps = a.sweeps > 1 ? a.sweeps : 1;
+  const double tol = a.tol;
+  // the row's largest |w| (all lanes), for the relative change of a sweep
+  auto wave_absmax = [&]() {
+    double m = 0.0;
+#pragma unroll
+    for (int q = 0; q < VPL; ++q) m = fmax(m, fabs(w[q]));
+    for (int o = 32; o > 0; o >>= 1) m = fmax(m, __shfl_xor(m, o, 64));
+    return m;
+  };
   if (a.update == NNCP_HALS) {
     // g stays equal to w S across sweeps: every column change is added to it
-    for (int sw = 0; sw < sweeps; ++sw)
-    for (int r = 0; r < R; ++r) {
-      const int v = r >> 6;
-      double wv = w[0], mv = m[0], gv = g[0];
-#pragma unroll
-      for (int q = 1; q < VPL; ++q)
-        if (v == q) {
-          wv = w[q];
-          mv = m[q];
-          gv = g[q];
+    for (int sw = 0; sw < sweeps; ++sw) {
+      double dmax = 0.0;  // the sweep's largest |change| (uniform: every change is broadcast)
+      for (int r = 0; r < R; ++r) {
+        const int v = r >> 6;
+        double wv = w[0], mv = m[0], gv = g[0];
+  #pragma unroll
+        for (int q = 1; q < VPL; ++q)
+          if (v == q) {
+            wv = w[q];
+            mv = m[q];
+            gv = g[q];
+          }
+        // column r: W(:,r) <- max(0, W(:,r) + (M(:,r) - (W S)(:,r)) / S(r,r)); a zero
+        // diagonal (all-zero column elsewhere) sets the column to zero
+        const double id = invd[r];
+        double wn = id > 0.0 ? wv + (mv - gv) * id : 0.0;
+        wn = wn > 0.0 ? wn : 0.0;
+        const double d = readlane_f64(wn - wv, r & 63);
+        dmax = fmax(dmax, fabs(d));
+        if (p == (r & 63)) {
+  #pragma unroll
+          for (int q = 0; q < VPL; ++q)
+            if (v == q) w[q] += d;
         }
-      // column r: W(:,r) <- max(0, W(:,r) + (M(:,r) - (W S)(:,r)) / S(r,r)); a zero
-      // diagonal (all-zero column elsewhere) sets the column to zero
-      const double id = invd[r];
-      double wn = id > 0.0 ? wv + (mv - gv) * id : 0.0;
-      wn = wn > 0.0 ? wn : 0.0;
-      const double d = readlane_f64(wn - wv, r & 63);
-      if (p == (r & 63)) {
-#pragma unroll
-        for (int q = 0; q < VPL; ++q)
-          if (v == q) w[q] += d;
+  #pragma unroll
+        for (int q = 0; q < VPL; ++q) {
+          const int k = p + 64 * q;
+          if (k < R) g[q] += d * Sl[r * R + k];
+        }
       }
-#pragma unroll
-      for (int q = 0; q < VPL; ++q) {
-        const int k = p + 64 * q;
-        if (k < R) g[q] += d * Sl[r * R + k];
-      }
+      if (tol > 0.0 && dmax <= tol * wave_absmax()) break;  // uniform
     }
   } else {
     for (int sw = 0; sw < sweeps; ++sw) {
       if (sw > 0) wS();
+      double dloc = 0.0;
 #pragma unroll
       for (int v = 0; v < VPL; ++v) {
         const double den = g[v] > 1e-16 ? g[v] : 1e-16;
-        w[v] = w[v] * m[v] / den;
+        const double wn = w[v] * m[v] / den;
+        dloc = fmax(dloc, fabs(wn - w[v]));
+        w[v] = wn;
+      }
+      if (tol > 0.0) {
+        for (int o = 32; o > 0; o >>= 1) dloc = fmax(dloc, __shfl_xor(dloc, o, 64));
+        if (dloc <= tol * wave_absmax()) break;  // uniform
       }
     }
   }
 #pragma unroll
   for (int v = 0; v < VPL; ++v) {
     const int k = p + 64 * v;
-    if (k < R) a.W[row + a.I * k] = (float)w[v];
+    if (k < R) {
+      a.W[row + a.I * k] = (float)w[v];
+      if (a.W64) a.W64[row + a.I * k] = w[v];
+    }
   }
 }
 template <int VPL>
@@ -335,14 +391,22 @@ __global__ __launch_bounds__(NT) void update_kernel(UpdateArgs a) {
 // or k >= R), invd = 1 / S(k, k) (zero unless positive). The column sweeps are
 // unrolled over RB, so every broadcast uses a constant lane and the Gauss-Seidel
 // chain touches no memory. Returns the new w.
+// With tol > 0 the sweeps stop early, once a sweep changes no entry of the row
+// by more than tol times the row's largest entry (the row is one NNLS
+// subproblem of the block; the rows are independent).
+__device__ __forceinline__ double wave_max_f64(double v) {
+  for (int o = 32; o > 0; o >>= 1) v = fmax(v, __shfl_xor(v, o, 64));
+  return v;
+}
 template <int RB>
 __device__ __forceinline__ double update_row_reg(double w, const double m, const double (&srow)[RB],
                                                  const double invd, const int k, const int R, const int update,
-                                                 const int sweeps) {
+                                                 const int sweeps, const double tol) {
   double g = 0.0;
 #pragma unroll
   for (int r = 0; r < RB; ++r) g += readlane_f64(w, r) * srow[r];
   if (update == NNCP_HALS) {
+    double dmax = 0.0;  // a sweep's largest |change| (uniform: every change is broadcast)
     auto sweep = [&]() {
       // fresh copies of the lane index and the rank per sweep: the per-column
       // compares below then stay inside the sweep instead of being hoisted out of
@@ -358,13 +422,22 @@ __device__ __forceinline__ double update_row_reg(double w, const double m, const
           double wn = invd > 0.0 ? w + (m - g) * invd : 0.0;
           wn = wn > 0.0 ? wn : 0.0;
           const double dlt = readlane_f64(wn - w, r);
+          dmax = fmax(dmax, fabs(dlt));
           if (kv == r) w += dlt;
           g += dlt * srow[r];
         }
       }
     };
     // g stays equal to w S across sweeps: every column change is added to it
-    for (int sw = 0; sw < sweeps; ++sw) sweep();
+    if (tol > 0.0) {
+      for (int sw = 0; sw < sweeps; ++sw) {
+        dmax = 0.0;
+        sweep();
+        if (dmax <= tol * wave_max_f64(fabs(w))) break;  // uniform
+      }
+    } else {
+      for (int sw = 0; sw < sweeps; ++sw) sweep();
+    }
   } else {
     for (int sw = 0; sw < sweeps; ++sw) {
       if (sw > 0) {
@@ -373,7 +446,10 @@ __device__ __forceinline__ double update_row_reg(double w, const double m, const
         for (int r = 0; r < RB; ++r) g += readlane_f64(w, r) * srow[r];
       }
       const double den = g > 1e-16 ? g : 1e-16;
-      w = w * m / den;
+      const double wn = w * m / den;
+      const double d = fabs(wn - w);
+      w = wn;
+      if (tol > 0.0 && wave_max_f64(d) <= tol * wave_max_f64(fabs(w))) break;  // uniform
     }
   }
   return w;
@@ -410,8 +486,11 @@ __device__ __forceinline__ void update_reg_body(const UpdateArgs& a, int bx) {
   load_s_column<RB>(a, k, srow, invd);
   const double f = ls > 0.0 ? lm / ls : 0.0;
   const double w = update_row_reg<RB>(col ? w0 * f : 0.0, col ? m0 : 0.0, srow, invd, k, R, a.update,
-                                      a.sweeps > 1 ? a.sweeps : 1);
-  if (col) a.W[row + a.I * k] = (float)w;
+                                      a.sweeps > 1 ? a.sweeps : 1, a.tol);
+  if (col) {
+    a.W[row + a.I * k] = (float)w;
+    if (a.W64) a.W64[row + a.I * k] = w;
+  }
 }
 template <int RB>
 __global__ __launch_bounds__(NT) void update_reg_kernel(UpdateArgs a) {
@@ -917,11 +996,11 @@ __device__ __forceinline__ void fin_op(const KOp& op, int bx) {
   }
 }
 // Persistent batched form of the 1024-thread finalize kernels.
-__global__ __launch_bounds__(NTF) void fin_batch_kernel(const BItem* __restrict__ items, const int* __restrict__ count,
+__global__ __launch_bounds__(NTF) void fin_batch_kernel(const BItem* __restrict__ items, const int* __restrict__ grp,
                                                         const KOp* __restrict__ ops) {
-  const int n = *count;
+  const int off = grp[0], n = grp[1];
   for (int i = blockIdx.x; i < n; i += gridDim.x) {
-    const BItem it = items[i];
+    const BItem it = items[off + i];
     fin_op(ops[it.op], it.bx);
     __syncthreads();
   }
@@ -997,11 +1076,11 @@ __device__ __forceinline__ void small_op(const KOp& op, int bx, int by) {
 }
 
 __global__ __launch_bounds__(NT) void small_batch_kernel(const BItem* __restrict__ items,
-                                                         const int* __restrict__ count,
+                                                         const int* __restrict__ grp,
                                                          const KOp* __restrict__ ops) {
-  const int n = *count;
+  const int off = grp[0], n = grp[1];
   for (int i = blockIdx.x; i < n; i += gridDim.x) {
-    const BItem it = items[i];
+    const BItem it = items[off + i];
     small_op(ops[it.op], it.bx, it.by);
     __syncthreads();
   }
@@ -1042,9 +1121,10 @@ inline unsigned grid_for(int64_t n, int threads, unsigned cap = 65535u * 32u) {
 }  // namespace
 
 int norm_sq_blocks(int64_t n) {
-  int64_t b = (n + NT * 8 - 1) / (NT * 8);
+  // 64 values per thread at least; at most kNormSqMaxBlocks groups (four per CU)
+  int64_t b = (n + NT * 64 - 1) / (NT * 64);
   if (b < 1) b = 1;
-  if (b > 1024) b = 1024;
+  if (b > kNormSqMaxBlocks) b = kNormSqMaxBlocks;
   return (int)b;
 }
 
@@ -1189,29 +1269,25 @@ hipError_t sink_record(const Sink& s, const KOp& op) {
   return hipSuccess;
 }
 
-hipError_t batch_launch_fin(const BItem* items, const int* count, const KOp* ops, unsigned grid, size_t lds,
-                            hipStream_t st) {
+const void* small_batch_kernel_ptr() { return (const void*)small_batch_kernel; }
+const void* fin_batch_kernel_ptr() {
   static bool attr = [] {
-    (void)hipFuncSetAttribute((const void*)fin_batch_kernel, hipFuncAttributeMaxDynamicSharedMemorySize, 150 * 1024);
+    (void)hipFuncSetAttribute((const void*)fin_batch_kernel, hipFuncAttributeMaxDynamicSharedMemorySize,
+                              (int)fin_batch_max_lds());
     (void)hipGetLastError();
     return true;
   }();
   (void)attr;
-  hipLaunchKernelGGL(fin_batch_kernel, dim3(grid), dim3(NTF), lds, st, items, count, ops);
-  return hipGetLastError();
+  return (const void*)fin_batch_kernel;
 }
-
-hipError_t batch_launch_small(const BItem* items, const int* count, const KOp* ops, unsigned grid, size_t lds,
-                              hipStream_t st) {
-  static bool attr = [] {
-    (void)hipFuncSetAttribute((const void*)small_batch_kernel, hipFuncAttributeMaxDynamicSharedMemorySize,
-                              150 * 1024);
-    (void)hipGetLastError();
-    return true;
-  }();
-  (void)attr;
-  hipLaunchKernelGGL(small_batch_kernel, dim3(grid), dim3(NT), lds, st, items, count, ops);
-  return hipGetLastError();
+// The most dynamic LDS a 1024-thread Gram/finalize op of rank <= 64 uses.
+size_t fin_batch_max_lds() {
+  size_t m = 0;
+  for (int R = 1; R <= kSmallMaxR; ++R) {
+    const size_t b = (size_t)fin_work_doubles(R) * sizeof(double);
+    if (b > m) m = b;
+  }
+  return m;
 }
 
 // Row chunks for the Gram: one group when the work is small (no second launch),

@@ -172,6 +172,32 @@ def hsi_like(dims: Sequence[int], R: int, noise: float, seed: int,
     return X, truth
 
 
+def hsi_like_device(dims: Sequence[int], R: int, noise: float, seed: int, device="cuda"):
+    """The ``hsi_like`` recipe assembled with torch on a device (the factors are
+    the same ``hsi_factors`` draws; the clean tensor is formed in FP32 and the
+    N(0,1) noise comes from a seeded torch generator, so the values differ from
+    ``hsi_like``). X = max(0, X_c + noise * ||X_c|| / ||E|| * E). Returns the flat
+    FP32 tensor, mode 1 fastest."""
+    import torch
+    dims = _as_dims(dims)
+    fs = [torch.from_numpy(np.ascontiguousarray(f, dtype=np.float32)).to(device)
+          for f in hsi_factors(dims, R, seed)]
+    P = fs[0]
+    for f in fs[1:-1]:
+        P = (f[:, None, :] * P[None, :, :]).reshape(-1, R)
+    X = (fs[-1] @ P.T).reshape(-1)
+    del P
+    if noise:
+        g = torch.Generator(device=device)
+        g.manual_seed(int(seed) + 7919)
+        E = torch.randn(X.numel(), generator=g, device=device, dtype=torch.float32)
+        scale = noise * torch.linalg.vector_norm(X.double()) / torch.linalg.vector_norm(E.double())
+        X.add_(E, alpha=float(scale))
+        del E
+        X.clamp_(min=0.0)
+    return X
+
+
 def batch_shapes(n_jobs: int, seed: int, lo: int = 32, hi: int = 256,
                  ranks: Sequence[int] = (8, 16, 32)) -> List[Tuple[Tuple[int, int, int], int]]:
     """Shapes and ranks of a batch of 3-way jobs: dims U{lo..hi}, R from ``ranks``."""

@@ -37,7 +37,9 @@ class Options(ctypes.Structure):
                 ("pm_wg_kib", ctypes.c_int),
                 ("no_tree", ctypes.c_int),
                 ("inner_sweeps", ctypes.c_int),
-                ("reserved", ctypes.c_int * 5)]
+                ("reserved0", ctypes.c_int),
+                ("inner_tol", ctypes.c_double),
+                ("reserved1", ctypes.c_uint64)]
 
 
 class JobRequest(ctypes.Structure):
@@ -48,14 +50,16 @@ class JobRequest(ctypes.Structure):
 
 class JobResult(ctypes.Structure):
     _fields_ = [("status", ctypes.c_int), ("iters_done", ctypes.c_int), ("submit_s", ctypes.c_double),
-                ("admit_s", ctypes.c_double), ("done_s", ctypes.c_double), ("footprint_bytes", ctypes.c_size_t)]
+                ("admit_s", ctypes.c_double), ("start_s", ctypes.c_double), ("done_s", ctypes.c_double),
+                ("footprint_bytes", ctypes.c_size_t)]
 
 
 class ServerStats(ctypes.Structure):
     _fields_ = [("queued", ctypes.c_int), ("active", ctypes.c_int), ("peak_active", ctypes.c_int),
                 ("ticks", ctypes.c_int64), ("completed", ctypes.c_int64), ("rejected", ctypes.c_int64),
                 ("bytes_in_use", ctypes.c_size_t), ("peak_bytes", ctypes.c_size_t), ("budget_bytes", ctypes.c_size_t),
-                ("busy_s", ctypes.c_double), ("now_s", ctypes.c_double)]
+                ("busy_s", ctypes.c_double), ("now_s", ctypes.c_double), ("graph_captures", ctypes.c_int64),
+                ("list_updates", ctypes.c_int64)]
 
 
 class NNCPError(RuntimeError):
@@ -92,6 +96,8 @@ def _declare(L):
     L.nncp_plan_time_node.argtypes = [c_vp, ctypes.c_int, ctypes.c_int, c_dp]
     L.nncp_plan_time_mttkrp.restype = ctypes.c_int
     L.nncp_plan_time_mttkrp.argtypes = [c_vp, ctypes.c_int, c_dp]
+    L.nncp_plan_set_stream.restype = ctypes.c_int
+    L.nncp_plan_set_stream.argtypes = [c_vp, c_vp]
     L.nncp_plan_destroy.restype = ctypes.c_int
     L.nncp_plan_destroy.argtypes = [c_vp]
     L.nncp_autotune_split.restype = ctypes.c_int
@@ -114,6 +120,9 @@ def _declare(L):
     L.nncp_gram.argtypes = [c_vp, ctypes.c_int64, ctypes.c_int, c_vp, c_vp]
     L.nncp_nls_update.restype = ctypes.c_int
     L.nncp_nls_update.argtypes = [c_vp, c_vp, ctypes.c_int64, ctypes.c_int, c_vp, c_vp, ctypes.c_int, c_vp, c_vp]
+    L.nncp_nls_solve.restype = ctypes.c_int
+    L.nncp_nls_solve.argtypes = [c_vp, c_vp, ctypes.c_int64, ctypes.c_int, c_vp, c_vp, ctypes.c_int, ctypes.c_int,
+                                 ctypes.c_double, c_vp, c_vp, c_vp]
     L.nncp_plan_fits.restype = ctypes.c_int
     L.nncp_plan_fits.argtypes = [c_vp, c_dp, ctypes.c_int, ctypes.POINTER(ctypes.c_int)]
     L.nncp_batch_create.restype = ctypes.c_int
@@ -128,6 +137,8 @@ def _declare(L):
     L.nncp_batch_run.argtypes = [c_vp, ctypes.c_int]
     L.nncp_batch_stats.restype = ctypes.c_int
     L.nncp_batch_stats.argtypes = [c_vp, ctypes.POINTER(ctypes.c_int), ctypes.POINTER(ctypes.c_int64)]
+    L.nncp_batch_captures.restype = ctypes.c_int
+    L.nncp_batch_captures.argtypes = [c_vp, ctypes.POINTER(ctypes.c_int64), ctypes.POINTER(ctypes.c_int64)]
     L.nncp_batch_destroy.restype = ctypes.c_int
     L.nncp_batch_destroy.argtypes = [c_vp]
     L.nncp_server_create.restype = ctypes.c_int
@@ -247,7 +258,7 @@ def _dtype_name(t) -> str:
 
 
 def nncp(X, dims, R, iters, H, lam=None, update="hals", split=0, graph=True, record_fit=True,
-         tol=0.0, workspace=None, stream=None, pm_wg_kib=0, no_tree=False, inner_sweeps=1):
+         tol=0.0, workspace=None, stream=None, pm_wg_kib=0, no_tree=False, inner_sweeps=1, inner_tol=0.0):
     """Run the full driver. H: list of device (R, I_n) float32 tensors, updated in place.
 
     Returns dict(fit=np.ndarray, lam=np.ndarray, iters_done=int).
@@ -263,7 +274,7 @@ def nncp(X, dims, R, iters, H, lam=None, update="hals", split=0, graph=True, rec
     fit = (ctypes.c_double * max(1, iters))()
     done = ctypes.c_int(0)
     o = Options(split=split, no_record_fit=0 if record_fit else 1, no_graph=0 if graph else 1, tol=tol,
-                pm_wg_kib=pm_wg_kib, no_tree=1 if no_tree else 0, inner_sweeps=inner_sweeps)
+                pm_wg_kib=pm_wg_kib, no_tree=1 if no_tree else 0, inner_sweeps=inner_sweeps, inner_tol=inner_tol)
     ws_ptr, ws_bytes = (None, 0)
     if workspace is not None:
         ws_ptr, ws_bytes = _ptr(workspace), workspace.numel() * workspace.element_size()
@@ -297,7 +308,7 @@ class Plan:
     """Persistent driver state: create once, run repeatedly, finish to normalise."""
 
     def __init__(self, X, dims, R, H, lam=None, update="hals", split=0, graph=True, phase_timers=False,
-                 workspace=None, stream=None, pm_wg_kib=0, no_tree=False, inner_sweeps=1):
+                 workspace=None, stream=None, pm_wg_kib=0, no_tree=False, inner_sweeps=1, inner_tol=0.0):
         import torch
         L = lib()
         self.dims, self.R, self.H, self.X = list(dims), R, list(H), X
@@ -309,7 +320,8 @@ class Plan:
         if lam is not None:
             lam_arr = (ctypes.c_double * R)(*np.asarray(lam, dtype=np.float64))
         o = Options(split=split, no_graph=0 if graph else 1, phase_timers=1 if phase_timers else 0,
-                    pm_wg_kib=pm_wg_kib, no_tree=1 if no_tree else 0, inner_sweeps=inner_sweeps)
+                    pm_wg_kib=pm_wg_kib, no_tree=1 if no_tree else 0, inner_sweeps=inner_sweeps,
+                    inner_tol=inner_tol)
         self._ws = workspace
         if workspace is None:
             nbytes = workspace_bytes(dims, R, _dtype_name(X), split, pm_wg_kib, no_tree)
@@ -399,7 +411,11 @@ class Batch:
         n = ctypes.c_int(0)
         it = ctypes.c_int64(0)
         _check(lib().nncp_batch_stats(self._h, ctypes.byref(n), ctypes.byref(it)), "nncp_batch_stats")
-        return dict(launches_per_tick=n.value, items_per_tick=it.value)
+        cap = ctypes.c_int64(0)
+        upd = ctypes.c_int64(0)
+        _check(lib().nncp_batch_captures(self._h, ctypes.byref(cap), ctypes.byref(upd)), "nncp_batch_captures")
+        return dict(launches_per_tick=n.value, items_per_tick=it.value, graph_captures=cap.value,
+                    list_updates=upd.value)
 
     def close(self):
         if getattr(self, "_h", None):
@@ -466,7 +482,7 @@ class Server:
             return None
         _check(st, "nncp_server_poll")
         return dict(status=r.status, iters_done=r.iters_done, submit_s=r.submit_s, admit_s=r.admit_s,
-                    done_s=r.done_s, footprint=r.footprint_bytes)
+                    start_s=r.start_s, done_s=r.done_s, footprint=r.footprint_bytes)
 
     def wait(self, jid: int, timeout_s: float = -1.0) -> bool:
         st = lib().nncp_server_wait(self._h, jid, float(timeout_s))
@@ -568,3 +584,17 @@ def nls_update(M, H, I, R, S, lam, update="hals", stream=None):
     _check(lib().nncp_nls_update(_ptr(M), _ptr(H), I, R, _ptr(S), _ptr(lam_t), _UPDATE[update], _ptr(G),
                                  _stream(stream)), "nncp_nls_update")
     return lam_t, G
+
+
+def nls_solve(M, H, I, R, S, lam, update="hals", max_sweeps=1000, tol=0.0, stream=None):
+    """In place: H <- the block subproblem solved by up to max_sweeps sweeps per row
+    (stopping at relative change tol), normalised. Returns (lam, G, W) as device
+    tensors, W the float64 solution before normalisation, shape (R, I)."""
+    import torch
+    _need(M, I * R, torch.float64, name="M")
+    lam_t = lam.clone()
+    G = torch.empty((R, R), dtype=torch.float64, device=H.device)
+    W = torch.empty((R, I), dtype=torch.float64, device=H.device)
+    _check(lib().nncp_nls_solve(_ptr(M), _ptr(H), I, R, _ptr(S), _ptr(lam_t), _UPDATE[update], int(max_sweeps),
+                                float(tol), _ptr(W), _ptr(G), _stream(stream)), "nncp_nls_solve")
+    return lam_t, G, W

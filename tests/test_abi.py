@@ -86,8 +86,9 @@ def test_entry_points_reject_bad_arguments_without_a_device():
 
 
 def test_inner_sweeps_option_layout_and_limit():
-    """The options struct keeps its size (inner_sweeps took a reserved slot) and
-    a sweep count above the maximum is rejected before any device work."""
+    """The options struct keeps its size (inner_sweeps and inner_tol took reserved
+    slots) and a sweep count above the maximum or a bad tolerance is rejected
+    before any device work."""
     from paper_1806_07985_amd import native
     L = _lib()
     assert ctypes.sizeof(native.Options) == 56
@@ -95,9 +96,20 @@ def test_inner_sweeps_option_layout_and_limit():
     dims = native._dims([4, 4, 4])
     lam = (ctypes.c_double * 2)(1.0, 1.0)
     H = (native.c_vp * 3)(ctypes.c_void_p(16), ctypes.c_void_p(16), ctypes.c_void_p(16))
-    o = native.Options(inner_sweeps=1025)
+    o = native.Options(inner_sweeps=100001)
     assert L.nncp(ctypes.c_void_p(16), 0, 3, dims, 2, 1, 0, H, lam, None, None, None, 0, ctypes.byref(o),
                   None) == -1
+    # inner_tol must be finite and >= 0
+    assert native.Options.inner_tol.offset == 40
+    for bad in (-1e-9, float("nan"), float("inf")):
+        o = native.Options(inner_sweeps=10, inner_tol=bad)
+        assert L.nncp(ctypes.c_void_p(16), 0, 3, dims, 2, 1, 0, H, lam, None, None, None, 0, ctypes.byref(o),
+                      None) == -1
+    # the block solve entry point checks its sweep count and tolerance
+    p16 = ctypes.c_void_p(16)
+    assert L.nncp_nls_solve(p16, p16, 4, 2, p16, p16, 0, 0, 0.0, None, p16, None) == -1
+    assert L.nncp_nls_solve(p16, p16, 4, 2, p16, p16, 0, 100001, 0.0, None, p16, None) == -1
+    assert L.nncp_nls_solve(p16, p16, 4, 2, p16, p16, 0, 10, -1.0, None, p16, None) == -1
 
 
 def test_autotune_split_rejects_bad_arguments_without_a_device():

@@ -11,6 +11,7 @@ import numpy as np
 import pytest
 
 import oracle as O
+from tolerances import TRAJ_TOL
 from paper_1806_07985_amd import inputs
 
 pytestmark = pytest.mark.gpu
@@ -95,7 +96,7 @@ def test_batch_matches_oracle(gpu_lib):
         fit_err = float(np.max(np.abs(m["plan"].fits() - np.asarray(ref["fit"]))))
         lam_err = float(np.max(np.abs(lam - ref["lam"]) / ref["lam"]))
         print(f"case oracle {job}: factors {max(errs):.1e} lam {lam_err:.1e} fit {fit_err:.1e}", flush=True)
-        tol = 1e-5 if dt == "f32" else 1e-4   # the 16-bit path's bound (see the low-precision tests)
+        tol = TRAJ_TOL[dt]
         assert max(errs) < tol and lam_err < tol and fit_err < tol
     batch.close()
 

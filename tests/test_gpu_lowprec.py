@@ -6,17 +6,19 @@ widened to FP64, so these tests measure only the arithmetic of the 16-bit path
 (the storage rounding itself is the workload, not an error).
 
 Tolerances follow from the arithmetic. The first contracted factor enters the
-MFMA as a hi + lo pair of the tensor's 16-bit type, which represents it to
-about 2^-17 (BF16) or 2^-22 (FP16) relative; products are exact in FP32 and
-summed in FP32 over at most one i1 block per Khatri-Rao row group before the
-FP32 column-scaled accumulation. Each partial-MTTKRP entry is therefore within
-2e-5 of sum |x||k| (a bound; typical errors are ~100x smaller).
+MFMA as a sum of values of the tensor's 16-bit type as exact as an FP32 value
+(FP16 hi + lo, BF16 hi + mid + lo); products are exact in FP32 and summed in
+FP32 over at most one i1 block per Khatri-Rao row group before the FP32
+column-scaled accumulation. Each partial-MTTKRP entry is therefore within
+2e-6 of sum |x||k| (a bound; typical errors are ~10x smaller). Whole
+trajectories use the per-storage bounds of tests/tolerances.py.
 """
 
 import numpy as np
 import pytest
 
 import oracle as O
+from tolerances import TRAJ_TOL
 from paper_1806_07985_amd import inputs
 
 pytestmark = pytest.mark.gpu
@@ -52,6 +54,8 @@ PM_CASES = [
     ((300, 20, 10), 10, 2),      # I_L % 8 == 0 but I1 ragged: 8-byte loads on full k-steps
     ((60, 200, 200), 10, 1),     # tall right node with J == 1, masked form (I_L % 8 == 4, ragged I1)
     ((36, 300, 120), 24, 1),     # the same with two column blocks
+    ((9, 8, 16), 6, 2),          # I_L % 8 == 0, odd I1 with J > 1: column offsets not 16-byte aligned
+    ((7, 11, 13), 5, 1),         # every extent odd
 ]
 
 
@@ -72,7 +76,8 @@ def test_partial_mttkrp_16bit(gpu_lib, dt, dims, R, s, side):
     ref = fn(Xq, H64, s).reshape(-1, R, order="F")
     bound = fn(np.abs(Xq), H64, s).reshape(-1, R, order="F")
     err = np.abs(T - ref)
-    assert np.all(err <= 2e-5 * bound + 1e-30), float(np.max(err / (bound + 1e-30)))
+    print(f"  max error / sum|x||k| {float(np.max(err / (bound + 1e-30))):.2e}", flush=True)
+    assert np.all(err <= 2e-6 * bound + 1e-30), float(np.max(err / (bound + 1e-30)))
 
 
 # Tall right nodes whose first mode does not fit one LDS block: the work-group
@@ -90,12 +95,12 @@ def test_partial_mttkrp_16bit_staged_right(gpu_lib, dt, dims, R):
     T = native.partial_mttkrp(Xd, list(dims), 1, 1, Hd, R).cpu().numpy().T
     ref = Xq.T @ H[0].astype(np.float64)
     bound = np.abs(Xq).T @ H[0].astype(np.float64)
-    assert np.all(np.abs(T - ref) <= 2e-5 * bound), float(np.max(np.abs(T - ref) / bound))
+    assert np.all(np.abs(T - ref) <= 2e-6 * bound), float(np.max(np.abs(T - ref) / bound))
     # the left node of the same matrix (short output, split over K)
     T = native.partial_mttkrp(Xd, list(dims), 1, 0, Hd, R).cpu().numpy().T
     ref = Xq @ H[1].astype(np.float64)
     bound = np.abs(Xq) @ H[1].astype(np.float64)
-    assert np.all(np.abs(T - ref) <= 2e-5 * bound), float(np.max(np.abs(T - ref) / bound))
+    assert np.all(np.abs(T - ref) <= 2e-6 * bound), float(np.max(np.abs(T - ref) / bound))
 
 
 @pytest.mark.parametrize("dt", DTYPES)
@@ -118,11 +123,9 @@ def test_nncp_16bit_matches_oracle_on_stored_values(gpu_lib, dt, dims, R, split,
     lam_err = float(np.max(np.abs(out["lam"] - ref["lam"]) / ref["lam"]))
     fit_err = float(np.max(np.abs(np.asarray(out["fit"]) - np.asarray(ref["fit"]))))
     print(f"  factor errs {['%.1e' % e for e in errs]} lam {lam_err:.1e} fit {fit_err:.1e}", flush=True)
-    # The factor operand is exact to ~2^-17 (BF16 hi + lo) or ~2^-22 (FP16), and
-    # sums are FP32: per-step MTTKRP errors up to ~1e-5 relative for BF16, which
-    # the trajectory carries at about that size. Bound: 1e-4 on factors, lambda
-    # and fit, ten times below the BF16 storage rounding of the tensor (2^-9).
-    assert max(errs) < 1e-4 and lam_err < 1e-4 and fit_err < 1e-4
+    # per-storage bounds (tests/tolerances.py)
+    tol = TRAJ_TOL[dt]
+    assert max(errs) < tol and lam_err < tol and fit_err < tol
 
 
 def test_quantized_fit_close_to_fp32_fit(gpu_lib):

@@ -10,6 +10,7 @@ import numpy as np
 import pytest
 
 import oracle as O
+from tolerances import TRAJ_TOL
 from paper_1806_07985_amd import inputs
 
 pytestmark = pytest.mark.gpu
@@ -159,7 +160,7 @@ def test_no_tree_matches_oracle_and_tree(gpu_lib, dims, R, dt):
         r = native.nncp(flat.cuda(), list(dims), R, 10, Hd, no_tree=nt)
         out[nt] = ([native.factor_to_host(h) for h in Hd], r["lam"], r["fit"])
     ref = O.nncp(X64, [h.astype(np.float64) for h in H0], 10)
-    tol = 1e-5 if dt == "f32" else 1e-4
+    tol = TRAJ_TOL[dt]
     for nt in (False, True):
         H, lam, fit = out[nt]
         errs = [np.linalg.norm(h - rh) / np.linalg.norm(rh) for h, rh in zip(H, ref["H"])]
@@ -245,7 +246,7 @@ def test_autotune_split_picks_the_fastest_timed_split(gpu_lib, dims, R, dt):
         assert np.array_equal(native.factor_to_host(h), h0)
     r = native.nncp(Xd, list(dims), R, 5, Hd, split=best)
     ref = O.nncp(X64, [h.astype(np.float64) for h in H0], 5)
-    tol = 1e-5 if dt == "f32" else 1e-4
+    tol = TRAJ_TOL[dt]
     assert np.max(np.abs(r["fit"] - np.asarray(ref["fit"]))) < tol
 
 

@@ -40,7 +40,7 @@ def test_jobs_complete_with_consistent_timeline():
     for k, i in enumerate(ids):
         r = res[i]
         assert r["status"] == 0 and r["iters_done"] == 5 + k
-        assert r["submit_s"] <= r["admit_s"] <= r["done_s"]
+        assert r["submit_s"] <= r["admit_s"] <= r["start_s"] <= r["done_s"]
     st = srv.stats()
     assert st["completed"] == 6 and st["active"] == 0 and st["queued"] == 0 and st["bytes_in_use"] == 0
     srv.close()
