@@ -29,7 +29,8 @@ __all__ = [
     "hals_update", "mu_update", "normalize_columns", "model_tensor_cp",
     "relerr_explicit", "fit_from_terms", "choose_split",
     "partial_mttkrp_left", "partial_mttkrp_right", "mttv_trail", "mttv_lead",
-    "DimTree", "nncp", "nncp_unnormalized", "nnls_bruteforce",
+    "DimTree", "nncp", "nncp_unnormalized", "nnls_bruteforce", "contract_trailing", "contract_leading",
+    "tree_split",
     "nls_objective", "kkt_residual", "MU_EPS", "subtree_schedule", "fit_of_model", "block_update",
 ]
 
@@ -361,27 +362,72 @@ def mttv_lead(T: np.ndarray, H_a: np.ndarray) -> np.ndarray:
     return out.reshape(tuple(T.shape[1:-1]) + (R,), order="F")
 
 
-def subtree_schedule(N: int, s: int) -> List[Tuple[str, int, int]]:
-    """The edges computed just before each mode's update, in mode order.
+def contract_trailing(T: np.ndarray, nkeep: int, H_rest: Sequence[np.ndarray]) -> np.ndarray:
+    """Child {a..c} of node {a..b}: contract the last modes c+1..b of the node
+    temporary T (shape (I_a, ..., I_b, R)) with their factors (Section IV-A):
+    out(i, r) = sum_j T(i, j, r) K(j, r), i over the first `nkeep` modes and
+    K = H^(b) (.) ... (.) H^(c+1) (H^(c+1)'s index fastest)."""
+    R = T.shape[-1]
+    keep = tuple(T.shape[:nkeep])
+    K = khatri_rao_list(list(reversed([np.asarray(h, dtype=np.float64) for h in H_rest])))
+    T3 = np.asarray(T, dtype=np.float64).reshape(math.prod(keep), -1, R, order="F")
+    return np.einsum("ijr,jr->ir", T3, K).reshape(keep + (R,), order="F")
 
-    Reading: the root splits into {1..s} | {s+1..N}; an internal node
-    {a..b} splits into {a} | {a+1..b} (the N = 5 example splits {3,4,5}
-    into {3} | {4,5}). A node {a..b} is computed immediately before mode a
-    is updated, so it sees new factors below a and old ones above b, which
-    is what the direct MTTKRP of each of its leaves would see.
-    Returned tuples are (kind, a, b) with 0-based inclusive modes, where
-    kind is "pm_left", "pm_right" or "lead" for the node {a..b}, followed
-    by the leaf edge ("trail" or "node-is-leaf") for mode a.
+
+def contract_leading(T: np.ndarray, H_lead: Sequence[np.ndarray]) -> np.ndarray:
+    """Child {c+1..b} of node {a..b}: contract the first modes a..c of T with
+    their factors: out(j, r) = sum_i T(i, j, r) K(i, r), K = H^(c) (.) ... (.) H^(a)."""
+    R = T.shape[-1]
+    nlead = len(H_lead)
+    rest = tuple(T.shape[nlead:-1])
+    K = khatri_rao_list(list(reversed([np.asarray(h, dtype=np.float64) for h in H_lead])))
+    T3 = np.asarray(T, dtype=np.float64).reshape(K.shape[0], -1, R, order="F")
+    return np.einsum("ijr,ir->jr", T3, K).reshape(rest + (R,), order="F")
+
+
+def tree_split(a: int, b: int, peel: int = 0) -> int:
+    """Split point c of the internal node {a..b}: children {a..c} and {c+1..b}.
+
+    Reading: the paper allows any binary tree over contiguous mode ranges
+    (Section IV-A); its N = 5 example peels the first mode ({3,4,5} into
+    {3} | {4,5}), the default here. Bit a*8 + b of `peel` (0-based modes)
+    peels the last mode instead: {a..b-1} | {b}.
     """
-    out = []
+    return b - 1 if (peel >> (a * 8 + b)) & 1 else a
+
+
+def subtree_schedule(N: int, s: int, peel: int = 0) -> List[List[Tuple[str, Tuple[int, int], Optional[Tuple[int, int]]]]]:
+    """The tree nodes computed just before each mode's update, in order.
+
+    Reading: the root splits into {1..s} | {s+1..N} and every internal node by
+    ``tree_split``. A node is computed immediately before its lowest mode is
+    updated, from its parent: then modes below it are new and modes above it
+    are old, which is what the direct MTTKRP of each of its leaves sees. A
+    left child {a..c} of {a..b} contracts the parent's last modes (they are
+    old); a right child {c+1..b} contracts its first modes a..c (new).
+    Returns, for each mode n (0-based), a list of (kind, node, parent) with
+    kind "pm_left" / "pm_right" (a root branch from the tensor, parent None),
+    "trail" (left child) or "lead" (right child); nodes are (a, b) inclusive,
+    and the last entry of mode n's list is its leaf (n, n).
+    """
+    out: List[List[Tuple[str, Tuple[int, int], Optional[Tuple[int, int]]]]] = []
     for n in range(N):
-        b = s - 1 if n < s else N - 1
-        start = 0 if n < s else s
-        if n == start:
-            out.append(("pm_left" if n == 0 else "pm_right", n, b))
-        else:
-            out.append(("lead", n, b))
-        out.append(("trail", n, b) if n < b else ("leaf", n, b))
+        lo, hi = (0, s - 1) if n < s else (s, N - 1)
+        ops = []
+        a, b, parent = lo, hi, None
+        while True:
+            if a == n:
+                if parent is None:
+                    ops.append(("pm_left" if lo == 0 else "pm_right", (a, b), None))
+                else:
+                    kind = "trail" if a == parent[0] else "lead"
+                    ops.append((kind, (a, b), parent))
+            if a == b:
+                break
+            c = tree_split(a, b, peel)
+            parent = (a, b)
+            a, b = (a, c) if n <= c else (c + 1, b)
+        out.append(ops)
     return out
 
 
@@ -389,31 +435,31 @@ class DimTree:
     """Dimension-tree MTTKRP along a BCD sweep (Section IV-A).
 
     Call ``mttkrp(H, n)`` for n = 0, 1, ..., N-1 in order, updating H[n]
-    between calls, exactly as Algorithm 1 does; nodes are computed lazily
-    by the validity rule in ``subtree_schedule``.
+    between calls, exactly as Algorithm 1 does; nodes are computed by the
+    validity rule in ``subtree_schedule``.
     """
 
-    def __init__(self, X: np.ndarray, s: Optional[int] = None):
+    def __init__(self, X: np.ndarray, s: Optional[int] = None, peel: int = 0):
         self.X = np.asarray(X, dtype=np.float64)
         self.N = self.X.ndim
         self.s = choose_split(self.X.shape) if s is None else int(s)
         if not 1 <= self.s <= self.N - 1:
             raise ValueError("split must satisfy 1 <= s <= N-1")
+        self.schedule = subtree_schedule(self.N, self.s, peel)
         self.node: Dict[Tuple[int, int], np.ndarray] = {}
 
     def mttkrp(self, H: Sequence[np.ndarray], n: int) -> np.ndarray:
-        N, s = self.N, self.s
-        b = s - 1 if n < s else N - 1
-        start = 0 if n < s else s
-        if n == start:
-            T = (partial_mttkrp_left(self.X, H, s) if n == 0
-                 else partial_mttkrp_right(self.X, H, s))
-        else:
-            T = mttv_lead(self.node[(n - 1, b)], H[n - 1])
-        self.node[(n, b)] = T
-        if n == b:
-            return T.reshape(T.shape[0], -1)
-        return mttv_trail(T, [H[k] for k in range(n + 1, b + 1)])
+        for kind, (a, b), parent in self.schedule[n]:
+            if kind == "pm_left":
+                T = partial_mttkrp_left(self.X, H, self.s)
+            elif kind == "pm_right":
+                T = partial_mttkrp_right(self.X, H, self.s)
+            elif kind == "trail":
+                T = contract_trailing(self.node[parent], b - a + 1, [H[k] for k in range(b + 1, parent[1] + 1)])
+            else:
+                T = contract_leading(self.node[parent], [H[k] for k in range(parent[0], a)])
+            self.node[(a, b)] = T
+        return self.node[(n, n)].reshape(self.X.shape[n], -1)
 
 
 # ----------------------------------------------------------------------------
@@ -424,7 +470,7 @@ def nncp(X: np.ndarray, H0: Sequence[np.ndarray], iters: int, update: str = "hal
          lam0: Optional[np.ndarray] = None, mttkrp: str = "direct",
          split: Optional[int] = None, alpha: Optional[float] = None,
          callback: Optional[Callable[[int, int, dict], None]] = None,
-         inner_sweeps: int = 1, inner_tol: float = 0.0, normalize: bool = True) -> dict:
+         inner_sweeps: int = 1, inner_tol: float = 0.0, normalize: bool = True, peel: int = 0) -> dict:
     """Alternating-update NNCP, ``iters`` outer iterations (Algorithm 1).
 
     Each outer iteration visits the modes in order; for mode n it forms the
@@ -453,7 +499,8 @@ def nncp(X: np.ndarray, H0: Sequence[np.ndarray], iters: int, update: str = "hal
       directly).
 
     ``mttkrp`` selects "direct" (the plain definition) or "tree" (the FP64
-    dimension tree, used only to show that both give the same iterates).
+    dimension tree of root split ``split`` and internal splits ``peel``, used
+    only to show that both give the same iterates).
     Returns dict(H=[...], lam=..., fit=[...], eps=[...]).
     """
     X = np.asarray(X)
@@ -472,7 +519,7 @@ def nncp(X: np.ndarray, H0: Sequence[np.ndarray], iters: int, update: str = "hal
     if alpha is None:
         Xf = np.asarray(X, dtype=np.float64)
         alpha = float(np.sum(Xf * Xf))
-    tree = DimTree(X, split) if mttkrp == "tree" else None
+    tree = DimTree(X, split, peel) if mttkrp == "tree" else None
     fits, epss = [], []
     for it in range(iters):
         M = S = W = None

@@ -82,40 +82,105 @@ def test_mttkrp_rank_one_closed_form():
 
 # --- dimension tree ----------------------------------------------------------
 
-@pytest.mark.parametrize("dims", [(3, 4, 5), (4, 3, 5, 2), (2, 3, 2, 3, 2), (5, 2)])
-def test_tree_equals_direct_every_mode_every_split(dims):
+def _peel_masks(N, s):
+    """Every choice of internal splits of both halves (bits of nodes with three
+    or more modes, reachable or not)."""
+    bits = [a * 8 + b for a in range(N) for b in range(a + 2, N)]
+    masks = set()
+    for k in range(1 << len(bits)):
+        masks.add(sum(1 << bits[i] for i in range(len(bits)) if k >> i & 1))
+    return sorted(masks)
+
+
+@pytest.mark.parametrize("dims", [(3, 4, 5), (4, 3, 5, 2), (2, 3, 2, 3, 2), (5, 2), (2, 2, 3, 2, 2, 2)])
+def test_tree_equals_direct_every_mode_every_split_every_shape(dims):
     N = len(dims)
     X = _rand_tensor(dims, 7)
     for s in range(1, N):
-        H = _rand_factors(dims, 3, 8)
-        tree = O.DimTree(X, s)
-        rng = np.random.default_rng(9)
-        for sweep in range(2):
-            for n in range(N):
-                Mt = tree.mttkrp(H, n)
-                Md = O.mttkrp_direct(X, H, n)
-                assert np.linalg.norm(Mt - Md) <= 1e-12 * np.linalg.norm(Md)
-                H[n] = rng.random(H[n].shape)  # a new factor, as an update would make
+        for peel in _peel_masks(N, s)[:64]:
+            H = _rand_factors(dims, 3, 8)
+            tree = O.DimTree(X, s, peel)
+            rng = np.random.default_rng(9)
+            for sweep in range(2):
+                for n in range(N):
+                    Mt = tree.mttkrp(H, n)
+                    Md = O.mttkrp_direct(X, H, n)
+                    assert np.linalg.norm(Mt - Md) <= 1e-12 * np.linalg.norm(Md), (s, peel, n)
+                    H[n] = rng.random(H[n].shape)  # a new factor, as an update would make
 
 
 def test_tree_equals_direct_along_bcd():
     dims = (6, 5, 4, 3)
     X, _ = inputs.planted(dims, 3, 0.01, seed=11)
     H0 = inputs.init_factors(dims, 3, seed=12)
-    for s in (1, 2, 3):
-        a = O.nncp(X, H0, 4, mttkrp="direct")
-        b = O.nncp(X, H0, 4, mttkrp="tree", split=s)
+    a = O.nncp(X, H0, 4, mttkrp="direct")
+    for s, peel in ((1, 0), (2, 0), (3, 0), (1, 1 << (1 * 8 + 3)), (1, (1 << (1 * 8 + 3)) | (1 << (1 * 8 + 2)))):
+        b = O.nncp(X, H0, 4, mttkrp="tree", split=s, peel=peel)
         for Ha, Hb in zip(a["H"], b["H"]):
             assert np.linalg.norm(Ha - Hb) <= 1e-11 * np.linalg.norm(Ha)
         np.testing.assert_allclose(a["fit"], b["fit"], rtol=0, atol=1e-12)
 
 
 def test_subtree_schedule_shape():
+    # the N = 5 example: {3,4,5} splits as {3} | {4,5} by default
     sch = O.subtree_schedule(5, 2)
-    assert sch[0] == ("pm_left", 0, 1) and sch[1] == ("trail", 0, 1)
-    assert sch[2] == ("lead", 1, 1) and sch[3] == ("leaf", 1, 1)
-    assert sch[4] == ("pm_right", 2, 4) and sch[5] == ("trail", 2, 4)
-    assert sch[-2] == ("lead", 4, 4) and sch[-1] == ("leaf", 4, 4)
+    assert sch[0] == [("pm_left", (0, 1), None), ("trail", (0, 0), (0, 1))]
+    assert sch[1] == [("lead", (1, 1), (0, 1))]
+    assert sch[2] == [("pm_right", (2, 4), None), ("trail", (2, 2), (2, 4))]
+    assert sch[3] == [("lead", (3, 4), (2, 4)), ("trail", (3, 3), (3, 4))]
+    assert sch[4] == [("lead", (4, 4), (3, 4))]
+    # peeling the last mode of {3,4,5}: {3,4} | {5}
+    sch = O.subtree_schedule(5, 2, peel=1 << (2 * 8 + 4))
+    assert sch[2] == [("pm_right", (2, 4), None), ("trail", (2, 3), (2, 4)), ("trail", (2, 2), (2, 3))]
+    assert sch[3] == [("lead", (3, 3), (2, 3))]
+    assert sch[4] == [("lead", (4, 4), (2, 4))]
+    # every mode's list ends with its leaf
+    for N in range(2, 7):
+        for s in range(1, N):
+            for peel in _peel_masks(N, s)[:16]:
+                for n, ops in enumerate(O.subtree_schedule(N, s, peel)):
+                    assert ops[-1][1] == (n, n)
+
+
+def test_subtree_schedule_visits_each_node_once_before_its_lowest_mode():
+    def nodes(a, b, peel):
+        if a == b:
+            return [(a, b)]
+        c = O.tree_split(a, b, peel)
+        return [(a, b)] + nodes(a, c, peel) + nodes(c + 1, b, peel)
+
+    for N in range(2, 7):
+        for s in range(1, N):
+            for peel in _peel_masks(N, s)[:16]:
+                sch = O.subtree_schedule(N, s, peel)
+                seen = [(n, op[1]) for n, ops in enumerate(sch) for op in ops]
+                tree = nodes(0, s - 1, peel) + nodes(s, N - 1, peel)
+                assert sorted(node for _, node in seen) == sorted(tree)      # each node exactly once
+                assert all(n == node[0] for n, node in seen)                 # just before its lowest mode
+
+
+def test_contractions_of_a_node_are_the_definition():
+    """contract_trailing / contract_leading against plain loops on a 3-mode node."""
+    rng = np.random.default_rng(5)
+    dims, R = (3, 4, 2), 2
+    T = rng.random(dims + (R,))
+    H = [rng.random((d, R)) for d in dims]
+    # keep mode 0, contract modes 1, 2
+    ref = np.zeros((3, R))
+    for i in range(3):
+        for j in range(4):
+            for k in range(2):
+                ref[i] += T[i, j, k] * H[1][j] * H[2][k]
+    np.testing.assert_allclose(O.contract_trailing(T, 1, H[1:]), ref, rtol=1e-13)
+    # keep modes 0, 1, contract mode 2
+    ref = np.einsum("ijkr,kr->ijr", T, H[2])
+    np.testing.assert_allclose(O.contract_trailing(T, 2, H[2:]), ref, rtol=1e-13)
+    # contract modes 0, 1, keep mode 2
+    ref = np.zeros((2, R))
+    for i in range(3):
+        for j in range(4):
+            ref += T[i, j] * H[0][i] * H[1][j]
+    np.testing.assert_allclose(O.contract_leading(T, H[:2]), ref, rtol=1e-13)
 
 
 def test_choose_split():
