@@ -298,6 +298,8 @@ def _serving_study(dev, n_pool, n_sat, n_jobs, load_fracs, iters, budget_gb, max
         wait = np.array([r["admit_s"] - r["submit_s"] for r in ok])
         dev_lat = np.array([r["done_s"] - r["start_s"] for r in ok])
         span = max(r["done_s"] for r in res) - min(r["submit_s"] for r in res)
+        if errors:
+            errors["last_hip_error"] = list(native.last_device_error())
         return dict(jobs=n, completed_ok=len(ok), errors=errors, jobs_per_s=len(ok) / span, span_s=span,
                     p50_s=pct(lat, 50), p99_s=pct(lat, 99), mean_s=float(lat.mean()) if len(lat) else None,
                     queue_wait_p50_s=pct(wait, 50), queue_wait_p99_s=pct(wait, 99),

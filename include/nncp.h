@@ -78,8 +78,20 @@ typedef struct nncp_options {
                          inner_sweeps every block update is solved exactly (to that tolerance), the
                          faithful block coordinate descent of Section II-B. 0: always inner_sweeps
                          sweeps. EINVAL if negative or not finite. */
-  unsigned long long reserved1;
+  unsigned long long tree_peel; /* shape of the dimension tree below the root split (Section IV-A allows
+                         any binary tree over contiguous mode ranges): an internal node {a..b} (0-based
+                         modes) splits as {a} | {a+1..b} (the paper's N = 5 example), or as
+                         {a..b-1} | {b} if bit a*8+b is set. Bits of nodes the tree does not contain are
+                         ignored. Every shape computes the same MTTKRPs; they differ in the sizes of
+                         the temporaries and the multi-TTVs. */
 } nncp_options;
+
+/* The most recent HIP runtime failure the library saw (in any thread): its
+ * hipError_t in *hip_error and a source location code in *where (for bug
+ * reports; either pointer may be NULL). Returns NNCP_EDEVICE if a failure was
+ * recorded since the library was loaded, NNCP_OK (both outputs 0) if none. Meant
+ * for diagnosing a call that returned NNCP_EDEVICE; the record is not cleared. */
+int nncp_last_device_error(int* hip_error, int* where);
 
 /* Human-readable text for a status code (static storage). */
 const char* nncp_strerror(int status);
@@ -167,6 +179,20 @@ int nncp_plan_set_stream(nncp_plan* plan, void* stream);
 int nncp_autotune_split(const void* X, int dtype, int N, const int64_t* dims, int R, float* const* H,
                         const nncp_options* opt, int reps, int* best_split, double* ms, void* stream);
 
+/* Tree-shape autotuning: times the dimension-tree MTTKRP sweep (as
+ * nncp_autotune_split does) for every tree of every root split, each internal
+ * node of three or more modes split either way (nncp_options.tree_peel), up to
+ * `cap` trees in the order: root split 1..N-1, then the left half's shapes,
+ * then the right half's. The paper's memory criterion (Section IV-C) picks the
+ * tree with the smallest temporaries; this measures time instead. Candidate k
+ * gets splits[k], peels[k] and ms[k] (host arrays of cap entries); *count
+ * receives the number timed and *best the index of the fastest. Trees whose
+ * workspace cannot be allocated are skipped (NNCP_ENOMEM if none fits). X and
+ * H (device) are only read. */
+int nncp_autotune_tree(const void* X, int dtype, int N, const int64_t* dims, int R, float* const* H,
+                       const nncp_options* opt, int reps, int cap, int* splits, unsigned long long* peels,
+                       double* ms, int* count, int* best, void* stream);
+
 /* Host copy of the fits recorded since the plan was created (or since the last
  * nncp_plan_run, which restarts the record): *count = outer iterations
  * completed; fit (host) receives min(*count, cap, 1024) values. */
@@ -188,7 +214,7 @@ int nncp_plan_fits(nncp_plan* plan, double* fit, int cap, int* count);
  * Fits are read per member with nncp_plan_fits. */
 typedef struct nncp_batch nncp_batch;
 int nncp_batch_create(nncp_batch** batch, void* stream);
-int nncp_batch_add(nncp_batch* batch, nncp_plan* plan);      /* EINVAL: rank > 64, no_tree, or already a member */
+int nncp_batch_add(nncp_batch* batch, nncp_plan* plan);      /* EINVAL: rank > 64, or already a member */
 int nncp_batch_remove(nncp_batch* batch, nncp_plan* plan);   /* ENOTFOUND: not a member */
 int nncp_batch_size(const nncp_batch* batch);
 /* Runs `ticks` outer iterations of every member; synchronises the stream. */

@@ -17,7 +17,9 @@
 // the normalised factors back.
 #include <algorithm>
 #include <cmath>
+#include <atomic>
 #include <cstring>
+#include <functional>
 #include <map>
 #include <new>
 #include <vector>
@@ -28,10 +30,13 @@ using namespace nncpk;
 
 namespace {
 
-#define HIPCHK(x)                          \
-  do {                                     \
-    hipError_t e_ = (x);                   \
-    if (e_ != hipSuccess) return NNCP_EDEVICE; \
+#define HIPCHK(x)                                 \
+  do {                                            \
+    hipError_t e_ = (x);                          \
+    if (e_ != hipSuccess) {                       \
+      nncpk::note_device_error((int)e_, __LINE__); \
+      return NNCP_EDEVICE;                        \
+    }                                             \
   } while (0)
 
 constexpr int kFitCap = 1024;
@@ -44,18 +49,32 @@ inline Sink sink_of(hipStream_t st) {
   return s;
 }
 
-struct Node {
+// A node {a..b} of the dimension tree (modes 0-based, inclusive) and how it is
+// computed: a root branch from the tensor, or from its parent by contracting
+// the parent's last modes (it is the parent's left child) or its first modes
+// (the right child).
+enum TreeKind : int { T_PM_LEFT = 0, T_PM_RIGHT = 1, T_TRAIL = 2, T_LEAD = 3 };
+struct TNode {
   int a = 0, b = 0;
-  float* buf = nullptr;
-  int64_t rows = 0;  // product of I_a..I_b
+  int parent = -1;
+  int kind = T_PM_LEFT;
+  int64_t rows = 0;     // product of I_a..I_b
+  int has_buf = 0;      // a temporary in the workspace (every node except the leaves below a root)
+  size_t off = 0;       // its offset
 };
 
 struct Layout {
   size_t off_zeros, off_alpha, off_iter, off_counters, off_lam, off_lammodel, off_lamin, off_G, off_S, off_fit,
-      off_finpart, off_pmpart, off_hpack, off_nspart, off_M, off_nodes, total;
+      off_finpart, off_pmpart, off_hpack, off_nspart, off_M, total;
   int ncounters;
-  int64_t node_bytes[kMaxModes];
   int node_f64;  // tree temporaries are FP64 for FP32 tensors, FP32 for 16-bit tensors
+  // the tree: nodes, and per mode the nodes computed just before its update
+  // (top-down; the last one is the leaf {n}, whose MTTKRP goes to M unless the
+  // leaf is a root branch itself)
+  int ntn;
+  TNode tn[2 * kMaxModes];
+  int nsched[kMaxModes];
+  int sched[kMaxModes][kMaxModes];
   PmLaunch pmL[2];
   // without the dimension tree (ablation): per mode, the side and split of the
   // partial MTTKRP that computes it from X, and two temporaries
@@ -68,6 +87,7 @@ struct Layout {
 struct Problem {
   int N = 0, R = 0, dtype = 0, s = 0, update = 0, wg_kib = 0, no_tree = 0, sweeps = 1;
   double inner_tol = 0.0;
+  uint64_t peel = 0;  // internal splits: bit a*8+b peels the last mode of node {a..b}
   int64_t dims[kMaxModes] = {};
   int64_t IL = 0, IR = 0, I = 0;
 };
@@ -129,9 +149,55 @@ int64_t prod_range(const Problem& p, int a, int b) {
   return r;
 }
 
-// subtree end for mode n
-inline int sub_end(const Problem& p, int n) { return n < p.s ? p.s - 1 : p.N - 1; }
-inline int sub_start(const Problem& p, int n) { return n < p.s ? 0 : p.s; }
+
+// Split point c of the internal node {a..b}: children {a..c} and {c+1..b}. The
+// paper allows any binary tree over contiguous mode ranges (Section IV-A); its
+// N = 5 example peels the first mode ({3,4,5} -> {3} | {4,5}), the default
+// here; bit a*8+b of `peel` peels the last mode instead ({a..b-1} | {b}).
+inline int tree_split(const Problem& p, int a, int b) { return ((p.peel >> (a * 8 + b)) & 1ull) ? b - 1 : a; }
+
+int add_tnode(const Problem& p, Layout& L, int a, int b, int parent) {
+  const int i = L.ntn++;
+  TNode& t = L.tn[i];
+  t.a = a;
+  t.b = b;
+  t.parent = parent;
+  if (parent < 0) t.kind = a == 0 ? T_PM_LEFT : T_PM_RIGHT;
+  else t.kind = a == L.tn[parent].a ? T_TRAIL : T_LEAD;
+  t.rows = prod_range(p, a, b);
+  t.has_buf = (a < b || parent < 0) ? 1 : 0;
+  if (a < b) {
+    const int c = tree_split(p, a, b);
+    add_tnode(p, L, a, c, i);
+    add_tnode(p, L, c + 1, b, i);
+  }
+  return i;
+}
+
+// The two root branches {0..s-1} and {s..N-1}, and each mode's schedule: the
+// nodes on the path from its root branch to its leaf whose lowest mode is n,
+// top-down. Such a node is computed just before mode n is updated, from its
+// parent (computed at that time or earlier): modes below it are then new and
+// modes above it old, which is what the direct MTTKRP of each of its leaves
+// sees, so the tree gives the direct MTTKRP exactly.
+void build_tree(const Problem& p, Layout& L) {
+  L.ntn = 0;
+  const int root[2] = {add_tnode(p, L, 0, p.s - 1, -1), add_tnode(p, L, p.s, p.N - 1, -1)};
+  for (int n = 0; n < p.N; ++n) {
+    L.nsched[n] = 0;
+    int i = root[n < p.s ? 0 : 1];
+    while (true) {
+      const TNode& t = L.tn[i];
+      if (t.a == n) L.sched[n][L.nsched[n]++] = i;
+      if (t.a == t.b) break;
+      // the child that holds n
+      int next = -1;
+      for (int k = 0; k < L.ntn; ++k)
+        if (L.tn[k].parent == i && L.tn[k].a <= n && n <= L.tn[k].b) next = k;
+      i = next;
+    }
+  }
+}
 
 Layout make_layout(const Problem& p) {
   Layout L{};
@@ -169,12 +235,9 @@ Layout make_layout(const Problem& p) {
   for (int k = 0; k < N; ++k) maxI = std::max(maxI, p.dims[k]);
   L.off_M = take(sizeof(double) * (size_t)maxI * R);
   L.node_f64 = p.dtype == NNCP_F32 ? 1 : 0;
-  L.off_nodes = o;
-  for (int n = 0; n < N; ++n) {
-    const int b = sub_end(p, n);
-    L.node_bytes[n] = prod_range(p, n, b) * R * (L.node_f64 ? 8 : 4);
-    take((size_t)L.node_bytes[n]);
-  }
+  build_tree(p, L);
+  for (int i = 0; i < L.ntn; ++i)
+    if (L.tn[i].has_buf) L.tn[i].off = take((size_t)L.tn[i].rows * R * (L.node_f64 ? 8 : 4));
   L.off_dtA = L.off_dtB = 0;
   if (p.no_tree) {
     // mode n from X directly: left with split n+1 (temporary over modes 1..n, then
@@ -254,11 +317,7 @@ struct nncp_plan {
   void* dtB() const { return (void*)(ws + L.off_dtB); }
   double* nspart() const { return at<double>(L.off_nspart); }
   double* Mbuf() const { return at<double>(L.off_M); }
-  void* node(int n) const {
-    size_t o = L.off_nodes;
-    for (int k = 0; k < n; ++k) o = align256(o + (size_t)L.node_bytes[k]);
-    return (void*)(ws + o);
-  }
+  void* tbuf(int i) const { return (void*)(ws + L.tn[i].off); }
 };
 
 namespace {
@@ -312,12 +371,15 @@ hipError_t run_pm(const nncp_plan* P, int side, void* T, int t_f64, const void* 
 
 // MTTKRP of mode n without the dimension tree: one partial MTTKRP from X, then
 // multi-TTVs down to M^(n). *M / *m_f64 say where it lives.
-hipError_t direct_mttkrp(const nncp_plan* P, int n, bool scaled, const Sink& st, const void** M, int* m_f64) {
+hipError_t direct_mttkrp(const nncp_plan* P, int n, bool scaled, const Sink& st0, const void** M, int* m_f64) {
   const Problem& p = P->p;
   const int side = P->L.dside[n], s = P->L.dsplit[n];
   const int f64 = P->L.node_f64;
   void* cur = P->dtA();
   void* nxt = P->dtB();
+  Sink st = st0;
+  st.mode = n;
+  st.step = 0;
   hipError_t e = run_pm_at(P, side, s, P->L.dpm[n], cur, f64, P->X, scaled, st);
   if (e != hipSuccess) return e;
   if (side == 0) {
@@ -332,6 +394,7 @@ hipError_t direct_mttkrp(const nncp_plan* P, int n, bool scaled, const Sink& st,
       a.krp = krp_for(P, k, k, scaled);
       a.out = nxt;
       a.out_f64 = f64;
+      st.step = k + 1;
       if ((e = mttv_lead_launch(a, st)) != hipSuccess) return e;
       std::swap(cur, nxt);
     }
@@ -356,50 +419,63 @@ hipError_t direct_mttkrp(const nncp_plan* P, int n, bool scaled, const Sink& st,
   a.out_f64 = 1;
   *M = P->Mbuf();
   *m_f64 = 1;
+  st.step = 1;
   return mttv_trail_launch(a, st);
 }
 
-// Node op for mode n: the root partial MTTKRP (n starts its half) or the leading
-// multi-TTV from node {n-1..b}.
-hipError_t node_op(const nncp_plan* P, int n, bool scaled, const Sink& st) {
+// Computes tree node i (see build_tree): a root partial MTTKRP, or a multi-TTV
+// from its parent. A leaf that is not a root branch goes to M (FP64). *M and
+// *m_f64 (optional) say where a leaf's MTTKRP lives.
+hipError_t tree_op(const nncp_plan* P, int i, bool scaled, const Sink& st, const void** M, int* m_f64) {
   const Problem& p = P->p;
-  const int b = sub_end(p, n), start = sub_start(p, n);
+  const TNode& t = P->L.tn[i];
   const int f64 = P->L.node_f64;
-  if (n == start) return run_pm(P, n == 0 ? 0 : 1, P->node(n), f64, P->X, scaled, st);
+  const bool leaf = t.a == t.b;
+  if (t.kind == T_PM_LEFT || t.kind == T_PM_RIGHT) {
+    if (leaf && M) {
+      *M = P->tbuf(i);
+      *m_f64 = f64;
+    }
+    return run_pm(P, t.kind == T_PM_LEFT ? 0 : 1, P->tbuf(i), f64, P->X, scaled, st);
+  }
+  const TNode& q = P->L.tn[t.parent];
   MttvArgs a{};
-  a.T = P->node(n - 1);
+  a.T = P->tbuf(t.parent);
   a.t_f64 = f64;
-  a.Ia = p.dims[n - 1];
-  a.J = prod_range(p, n, b);
   a.R = p.R;
-  a.krp = krp_for(P, n - 1, n - 1, scaled);
-  a.out = P->node(n);
-  a.out_f64 = f64;
-  return mttv_lead_launch(a, st);
+  if (t.kind == T_TRAIL) {  // keep modes a..b of the parent, contract b+1..q.b
+    a.Ia = t.rows;
+    a.J = prod_range(p, t.b + 1, q.b);
+    a.krp = krp_for(P, t.b + 1, q.b, scaled);
+  } else {  // contract modes q.a..a-1 of the parent, keep a..b
+    a.Ia = prod_range(p, q.a, t.a - 1);
+    a.J = t.rows;
+    a.krp = krp_for(P, q.a, t.a - 1, scaled);
+  }
+  if (leaf) {
+    a.out = P->Mbuf();
+    a.out_f64 = 1;
+    if (M) {
+      *M = P->Mbuf();
+      *m_f64 = 1;
+    }
+  } else {
+    a.out = P->tbuf(i);
+    a.out_f64 = f64;
+  }
+  return t.kind == T_TRAIL ? mttv_trail_launch(a, st) : mttv_lead_launch(a, st);
 }
 
-// Leaf op for mode n: M^(n) from node {n..b} by the trailing multi-TTV, or the
-// node itself when it is the leaf. *M and *m_f64 describe where M^(n) lives.
-hipError_t leaf_op(const nncp_plan* P, int n, bool scaled, const Sink& st, const void** M, int* m_f64) {
-  const Problem& p = P->p;
-  const int b = sub_end(p, n);
-  if (n == b) {
-    *M = P->node(n);
-    *m_f64 = P->L.node_f64;
-    return hipSuccess;
+// The tree ops of mode n (its schedule), numbered as the sink's steps.
+hipError_t tree_mode(const nncp_plan* P, int n, bool scaled, const Sink& st0, const void** M, int* m_f64) {
+  Sink st = st0;
+  st.mode = n;
+  for (int k = 0; k < P->L.nsched[n]; ++k) {
+    st.step = k;
+    hipError_t e = tree_op(P, P->L.sched[n][k], scaled, st, M, m_f64);
+    if (e != hipSuccess) return e;
   }
-  MttvArgs a{};
-  a.T = P->node(n);
-  a.t_f64 = P->L.node_f64;
-  a.Ia = p.dims[n];
-  a.J = prod_range(p, n + 1, b);
-  a.R = p.R;
-  a.krp = krp_for(P, n + 1, b, scaled);
-  a.out = P->Mbuf();
-  a.out_f64 = 1;
-  *M = P->Mbuf();
-  *m_f64 = 1;
-  return mttv_trail_launch(a, st);
+  return hipSuccess;
 }
 
 FinalizeArgs fin_args(const nncp_plan* P, int n, const void* M, int m_f64, int set_model, int next_mode,
@@ -445,7 +521,6 @@ hipError_t enqueue_iteration(nncp_plan* P, const Sink& st0, std::vector<std::pai
   };
   hipError_t e;
   for (int n = 0; n < p.N; ++n) {
-    const int start = sub_start(p, n);
     const void* M = nullptr;
     int m_f64 = 1;
     Sink st = st0;
@@ -454,11 +529,15 @@ hipError_t enqueue_iteration(nncp_plan* P, const Sink& st0, std::vector<std::pai
       if ((e = mark(PH_PM)) != hipSuccess) return e;
       if ((e = direct_mttkrp(P, n, true, st, &M, &m_f64)) != hipSuccess) return e;
     } else {
-      if ((e = mark(n == start ? PH_PM : PH_MTTV)) != hipSuccess) return e;
-      if ((e = node_op(P, n, true, st)) != hipSuccess) return e;
-      if ((e = mark(PH_MTTV)) != hipSuccess) return e;
-      if ((e = leaf_op(P, n, true, st, &M, &m_f64)) != hipSuccess) return e;
+      for (int k = 0; k < P->L.nsched[n]; ++k) {
+        const int i = P->L.sched[n][k];
+        const int kind = P->L.tn[i].kind;
+        if ((e = mark(kind == T_PM_LEFT || kind == T_PM_RIGHT ? PH_PM : PH_MTTV)) != hipSuccess) return e;
+        st.step = k;
+        if ((e = tree_op(P, i, true, st, &M, &m_f64)) != hipSuccess) return e;
+      }
     }
+    st.step = kStepUpdate;
     if ((e = mark(PH_NLS)) != hipSuccess) return e;
     UpdateArgs u{};
     u.M = M;
@@ -475,6 +554,7 @@ hipError_t enqueue_iteration(nncp_plan* P, const Sink& st0, std::vector<std::pai
     if ((e = update_launch(u, st)) != hipSuccess) return e;
     const bool last = (n == p.N - 1);
     if ((e = mark(last ? PH_ERR : PH_GRAM)) != hipSuccess) return e;
+    st.step = kStepFinal;
     if ((e = finalize_launch(fin_args(P, n, M, m_f64, 1, (n + 1) % p.N, last ? 1 : 0), st)) != hipSuccess) return e;
   }
   return mark(-1);
@@ -521,6 +601,13 @@ int build_graph(nncp_plan* P) {
 // ---------------------------------------------------------------------------
 extern "C" {
 
+int nncp_last_device_error(int* hip_error, int* where) {
+  const uint64_t v = nncpk::last_device_error();
+  if (hip_error) *hip_error = (int)(uint32_t)(v >> 32);
+  if (where) *where = (int)(uint32_t)v;
+  return v ? NNCP_EDEVICE : NNCP_OK;
+}
+
 const char* nncp_strerror(int s) {
   switch (s) {
     case NNCP_OK: return "ok";
@@ -541,6 +628,7 @@ size_t nncp_workspace_bytes(int N, const int64_t* dims, int R, int dtype, const 
   if (fill_problem(p, N, dims, R, dtype, NNCP_HALS, opt ? opt->split : 0) != NNCP_OK) return 0;
   p.wg_kib = opt ? opt->pm_wg_kib : 0;
   p.no_tree = opt ? (opt->no_tree != 0) : 0;
+  p.peel = opt ? opt->tree_peel : 0;
   return make_layout(p).total;
 }
 
@@ -558,6 +646,7 @@ int nncp_plan_create(nncp_plan** out, const void* X, int dtype, int N, const int
   if (p.sweeps > NNCP_MAX_SWEEPS) return NNCP_EINVAL;
   p.inner_tol = opt ? opt->inner_tol : 0.0;
   if (!(p.inner_tol >= 0.0) || !std::isfinite(p.inner_tol)) return NNCP_EINVAL;
+  p.peel = opt ? opt->tree_peel : 0;
   for (int k = 0; k < N; ++k)
     if (!H[k]) return NNCP_EINVAL;
   nncp_plan* P = new (std::nothrow) nncp_plan();
@@ -633,8 +722,10 @@ int nncp_plan_time_node(nncp_plan* P, int mode, int reps, double* ms_avg) {
   }
   int st = NNCP_OK;
   if (hipEventRecord(e0, s) != hipSuccess) st = NNCP_EDEVICE;
-  for (int i = 0; st == NNCP_OK && i < reps; ++i)
-    if (node_op(P, mode, true, s) != hipSuccess) st = NNCP_EDEVICE;
+  // the first tree op of the mode (a root partial MTTKRP for modes 1 and s+1)
+  const int node = P->L.nsched[mode] > 0 ? P->L.sched[mode][0] : -1;
+  for (int i = 0; st == NNCP_OK && node >= 0 && i < reps; ++i)
+    if (tree_op(P, node, true, s, nullptr, nullptr) != hipSuccess) st = NNCP_EDEVICE;
   float ms = 0.f;
   if (st == NNCP_OK && (hipEventRecord(e1, s) != hipSuccess || hipEventSynchronize(e1) != hipSuccess ||
                         hipEventElapsedTime(&ms, e0, e1) != hipSuccess))
@@ -662,7 +753,7 @@ int nncp_plan_time_mttkrp(nncp_plan* P, int reps, double* ms_avg) {
       int m_f64 = 1;
       if (P->p.no_tree) {
         if (direct_mttkrp(P, n, true, s, &M, &m_f64) != hipSuccess) st = NNCP_EDEVICE;
-      } else if (node_op(P, n, true, s) != hipSuccess || leaf_op(P, n, true, s, &M, &m_f64) != hipSuccess) {
+      } else if (tree_mode(P, n, true, s, &M, &m_f64) != hipSuccess) {
         st = NNCP_EDEVICE;
       }
     }
@@ -709,6 +800,67 @@ int nncp_autotune_split(const void* X, int dtype, int N, const int64_t* dims, in
   if (best == 0) return st_any;
   *best_split = best;
   return NNCP_OK;
+}
+
+int nncp_autotune_tree(const void* X, int dtype, int N, const int64_t* dims, int R, float* const* H,
+                       const nncp_options* opt, int reps, int cap, int* splits, unsigned long long* peels,
+                       double* ms, int* count, int* best, void* stream) {
+  if (!X || !H || !dims || !splits || !peels || !ms || !count || !best || reps < 1 || cap < 1 || N < 2 ||
+      N > kMaxModes)
+    return NNCP_EINVAL;
+  *count = 0;
+  *best = -1;
+  // every tree of every root split, in order: root split s, then the shapes of
+  // the left half and of the right half (peel-first before peel-last at each node)
+  std::vector<std::pair<int, uint64_t>> cand;
+  std::function<void(int, int, uint64_t, std::vector<uint64_t>&)> shapes = [&](int a, int b, uint64_t m,
+                                                                               std::vector<uint64_t>& out) {
+    if (b - a < 2) {
+      out.push_back(m);
+      return;
+    }
+    shapes(a + 1, b, m, out);                               // {a} | {a+1..b}
+    shapes(a, b - 1, m | (1ull << (a * 8 + b)), out);       // {a..b-1} | {b}
+  };
+  for (int s = 1; s < N; ++s) {
+    std::vector<uint64_t> left, right;
+    shapes(0, s - 1, 0, left);
+    shapes(s, N - 1, 0, right);
+    for (uint64_t l : left)
+      for (uint64_t r : right) cand.push_back({s, l | r});
+  }
+  nncp_options o{};
+  if (opt) o = *opt;
+  o.no_graph = 1;  // no iteration is run: nothing to capture
+  o.no_tree = 0;
+  int st_any = NNCP_ENOMEM;
+  double best_ms = 0.0;
+  for (size_t c = 0; c < cand.size() && *count < cap; ++c) {
+    o.split = cand[c].first;
+    o.tree_peel = cand[c].second;
+    nncp_plan* P = nullptr;
+    int st = nncp_plan_create(&P, X, dtype, N, dims, R, NNCP_HALS, H, nullptr, nullptr, 0, &o, stream);
+    if (st == NNCP_ENOMEM) {
+      (void)hipGetLastError();
+      continue;
+    }
+    if (st != NNCP_OK) return st;
+    double warm = 0.0, t = 0.0;
+    st = nncp_plan_time_mttkrp(P, 1, &warm);
+    if (st == NNCP_OK) st = nncp_plan_time_mttkrp(P, reps, &t);
+    nncp_plan_destroy(P);
+    if (st != NNCP_OK) return st;
+    st_any = NNCP_OK;
+    const int k = (*count)++;
+    splits[k] = cand[c].first;
+    peels[k] = cand[c].second;
+    ms[k] = t;
+    if (*best < 0 || t < best_ms) {
+      *best = k;
+      best_ms = t;
+    }
+  }
+  return *best < 0 ? st_any : NNCP_OK;
 }
 
 int nncp_plan_set_stream(nncp_plan* P, void* stream) {
@@ -936,13 +1088,13 @@ int nncp_mttkrp(const void* X, int dtype, int N, const int64_t* dims, int s, int
   if (st != NNCP_OK) return st;
   hipStream_t hs = (hipStream_t)stream;
   if (hipDeviceSynchronize() != hipSuccess) return NNCP_EDEVICE;
-  // walk n's subtree from its root branch: nodes {start..b}, {start+1..b}, ..., {n..b}
+  // the schedules of n's half from its first mode up to n: every node on the
+  // path to leaf n is computed (with the given factors) by the time n's runs
   const Problem& p = c.P.p;
-  for (int k = sub_start(p, n); k <= n; ++k)
-    if (node_op(&c.P, k, false, hs) != hipSuccess) return NNCP_EDEVICE;
   const void* Mp = nullptr;
   int m_f64 = 1;
-  if (leaf_op(&c.P, n, false, hs, &Mp, &m_f64) != hipSuccess) return NNCP_EDEVICE;
+  for (int k = n < p.s ? 0 : p.s; k <= n; ++k)
+    if (tree_mode(&c.P, k, false, hs, &Mp, &m_f64) != hipSuccess) return NNCP_EDEVICE;
   const int64_t cnt = p.dims[n] * R;
   if ((m_f64 ? copy_f64_launch(M, (const double*)Mp, cnt, hs) : widen_f32_launch(M, (const float*)Mp, cnt, hs)) !=
       hipSuccess)
@@ -1145,6 +1297,12 @@ int batch_build(nncp_batch* B) {
       have.emplace(kv.first, kv.second);
       recapture = true;
     }
+  // launches no member uses any more still run (with no items) every tick;
+  // once they outnumber the used ones, the graph is built for the used ones only
+  if (!recapture && have.size() > 2 * need.size() + 16) {
+    have = need;
+    recapture = true;
+  }
   // launch order: by stage, then by kernel (the map's key order)
   std::vector<nncp_batch::Launch> L;
   std::map<int64_t, int> slot;
@@ -1189,11 +1347,17 @@ int batch_build(nncp_batch* B) {
   B->dirty = false;
   if (!recapture) return NNCP_OK;
 
+  // The tick's graph is built node by node (no stream capture, so work that
+  // other threads enqueue meanwhile, such as a serving loader's uploads and
+  // allocations, cannot interfere with it): one kernel node per launch, each
+  // depending on the one before.
   batch_drop_graph(B);
   B->launches = L;
   const unsigned cus = (unsigned)device_cus();
-  HIPCHK(hipStreamBeginCapture(B->cap, hipStreamCaptureModeThreadLocal));
+  hipGraph_t gr = nullptr;
+  HIPCHK(hipGraphCreate(&gr, 0));
   hipError_t e = hipSuccess;
+  hipGraphNode_t prev = nullptr;
   for (size_t g = 0; g < L.size() && e == hipSuccess; ++g) {
     const BatchKernel bk = batch_kernel_for(L[g].kind, L[g].variant);
     if (!bk.fn) {
@@ -1204,17 +1368,26 @@ int batch_build(nncp_batch* B) {
     const int* gp = B->d_grp + 2 * g;
     const KOp* ops = B->d_ops;
     void* args[] = {(void*)&it, (void*)&gp, (void*)&ops};
-    e = hipLaunchKernel(bk.fn, dim3((unsigned)bk.per_cu * cus), dim3(bk.threads), args, bk.lds, B->cap);
+    hipKernelNodeParams kp{};
+    kp.func = const_cast<void*>(bk.fn);
+    kp.gridDim = dim3((unsigned)bk.per_cu * cus);
+    kp.blockDim = dim3(bk.threads);
+    kp.sharedMemBytes = (unsigned)bk.lds;
+    kp.kernelParams = args;
+    kp.extra = nullptr;
+    hipGraphNode_t node = nullptr;
+    e = hipGraphAddKernelNode(&node, gr, prev ? &prev : nullptr, prev ? 1 : 0, &kp);
+    prev = node;
   }
-  hipGraph_t gr = nullptr;
-  hipError_t e2 = hipStreamEndCapture(B->cap, &gr);
-  if (e != hipSuccess || e2 != hipSuccess) {
-    if (gr) hipGraphDestroy(gr);
+  if (e != hipSuccess) {
+    note_device_error((int)e, __LINE__);
+    hipGraphDestroy(gr);
     B->launches.clear();
     return NNCP_EDEVICE;
   }
   B->graph = gr;
-  if (hipGraphInstantiate(&B->gexec, gr, nullptr, nullptr, 0) != hipSuccess) {
+  if ((e = hipGraphInstantiate(&B->gexec, gr, nullptr, nullptr, 0)) != hipSuccess) {
+    note_device_error((int)e, __LINE__);
     batch_drop_graph(B);
     B->launches.clear();
     return NNCP_EDEVICE;
@@ -1226,6 +1399,16 @@ int batch_build(nncp_batch* B) {
 }  // namespace
 
 namespace nncpk {
+
+namespace {
+std::atomic<uint64_t> g_last_device_error{0};
+}
+
+void note_device_error(int hip_error, int where) {
+  g_last_device_error.store(((uint64_t)(uint32_t)hip_error << 32) | (uint32_t)where, std::memory_order_relaxed);
+}
+
+uint64_t last_device_error() { return g_last_device_error.load(std::memory_order_relaxed); }
 
 int batch_kernel_id(int kind, int variant) {
   switch (kind) {
@@ -1295,7 +1478,6 @@ int nncp_batch_create(nncp_batch** out, void* stream) {
 int nncp_batch_add(nncp_batch* B, nncp_plan* P) {
   if (!B || !P) return NNCP_EINVAL;
   if (P->p.R > kPmMaxCols) return NNCP_EINVAL;  // one column chunk per partial MTTKRP
-  if (P->p.no_tree) return NNCP_EINVAL;         // its chains of multi-TTVs share one stage slot
   for (nncp_plan* q : B->plans)
     if (q == P) return NNCP_EINVAL;
   try {

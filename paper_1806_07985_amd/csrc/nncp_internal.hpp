@@ -14,6 +14,9 @@ constexpr int kMaxRank = NNCP_MAX_RANK;
 // Rank handled by one partial-MTTKRP launch (four 16-wide MFMA column blocks);
 // larger ranks are processed in column chunks of this size.
 constexpr int kPmMaxCols = 64;
+// Dynamic LDS one partial-MTTKRP work-group may request: all of a CU's 160 KiB
+// (the kernels declare no static LDS).
+constexpr size_t kPmMaxLds = 160 * 1024;
 
 // Khatri-Rao operand description: rows are indexed by a mixed-radix index over
 // `nm` modes, the first listed mode fastest; row q of the operand is the
@@ -131,7 +134,7 @@ struct MttvArgs {
   int t_f64;            // T is double (else float)
   int64_t Ia, J;
   int R;
-  KrpDesc krp;          // trail: modes a+1..b (first fastest); lead: one mode (a)
+  KrpDesc krp;          // trail: the contracted last modes; lead: the contracted first modes (first fastest)
   void* out;
   int out_f64;          // out is double (else float)
 };
@@ -274,20 +277,23 @@ struct Sink {
   hipStream_t st = nullptr;
   void* rec = nullptr;  // std::vector<KOp>* when recording
   int mode = 0;         // mode whose steps are being recorded
+  int step = 0;         // position of the recorded op in the mode's sequence (see kslot)
   Sink() = default;
   Sink(hipStream_t s) : st(s) {}  // launch on s (implicit: a stream is a launching sink)
 };
-// Slot of a kernel kind among one mode's steps (pack, node op, split-K reduce,
-// leaf multi-TTV, update, Gram chunks, finalize).
+// Batching order of a recorded op: stage = 64 * mode + 4 * step + kslot(kind).
+// The driver numbers a mode's tree ops 0, 1, ... (a partial MTTKRP is its pack
+// (slot 0), the kernel (slot 1) and its split-K reduction (slot 2); a
+// multi-TTV is slot 1), the update is step kStepUpdate and the Gram/finalize
+// step kStepFinal (chunk partials slot 0, the finish slot 1).
+constexpr int kStepUpdate = 13, kStepFinal = 14;
 inline int kslot(int kind) {
   switch (kind) {
     case K_PACK16: return 0;
-    case K_PM_F32: case K_PM_16: case K_MTTV_LEAD: return 1;
+    case K_PM_F32: case K_PM_16: case K_MTTV_LEAD: case K_MTTV_TRAIL: case K_UPDATE: return 1;
     case K_PM_REDUCE: return 2;
-    case K_MTTV_TRAIL: return 3;
-    case K_UPDATE: return 4;
-    case K_GRAM_CHUNKS: case K_GRAM1K: return 5;
-    default: return 6;
+    case K_GRAM_CHUNKS: case K_GRAM1K: return 0;
+    default: return 1;
   }
 }
 // Append a record (host), stamping its stage; returns hipSuccess.
@@ -324,5 +330,11 @@ __device__ __forceinline__ double krp_colscale(const KrpDesc& k, int r) {
   }
   return s;
 }
+
+// Process-wide record of the most recent failed HIP runtime call (any thread):
+// its hipError_t and a source location (line in the driver; 200000 + line in
+// the serving loop). Read back through nncp_last_device_error.
+void note_device_error(int hip_error, int where);
+uint64_t last_device_error();
 
 }  // namespace nncpk

@@ -53,6 +53,7 @@ hipError_t pm_launch_16(const PmLaunch& L, const PmArgs& a, const Sink& sk) {
   if (!k || (wm != 1 && wm != 4) || (L.j1 && wm != 4)) return hipErrorInvalidValue;
   size_t lds = L.lds_bytes;
   if (pm_16_reduce_lds(L.side, L.nb, wm) > lds) lds = pm_16_reduce_lds(L.side, L.nb, wm);
+  if (lds > kPmMaxLds) return hipErrorInvalidValue;
   if (sk.rec) {
     KOp op{};
     op.kind = K_PACK16;

@@ -483,6 +483,7 @@ hipError_t pm_launch_f32(const PmLaunch& L, const PmArgs& a, const Sink& sk) {
   if (!k || (wm != 1 && wm != 4)) return hipErrorInvalidValue;
   size_t lds = L.lds_bytes;
   if (reduce_lds(L.side, L.nb, wm) > lds) lds = reduce_lds(L.side, L.nb, wm);
+  if (lds > kPmMaxLds) return hipErrorInvalidValue;
   if (sk.rec) {
     KOp op{};
     op.kind = K_PM_F32;

@@ -50,6 +50,15 @@ static size_t lds_for(int dtype, int RP, int i1blk, int jblk) {
   return (size_t)pm16_terms(dtype) * RP * (i1blk + 8) * sizeof(unsigned short) + (size_t)jblk * RP * sizeof(float);
 }
 
+// Most j values whose per-(j, column) scales fit in LDS beside an i1 block of
+// i1blk rows (at most 64): a group never asks for more than kPmMaxLds.
+static int jblk_cap(int dtype, int RP, int i1blk) {
+  const size_t base = lds_for(dtype, RP, i1blk, 0);
+  const size_t per = lds_for(dtype, RP, i1blk, 1) - base;
+  const int64_t cap = base >= kPmMaxLds ? 0 : (int64_t)((kPmMaxLds - base) / per);
+  return cap < 64 ? (int)cap : 64;
+}
+
 PmLaunch pm_plan(int side, int dtype, int64_t IL, int64_t IR, int I1, int R, int wg_kib) {
   PmLaunch L{};
   L.side = side;
@@ -103,7 +112,7 @@ PmLaunch pm_plan(int side, int dtype, int64_t IL, int64_t IR, int I1, int R, int
   const int64_t min_j = cdiv(8 * (4 / wm), steps_per_j);
   int64_t jblk = cdiv(L.J, n_jblk < 1 ? 1 : n_jblk);
   if (jblk < min_j) jblk = min_j;
-  if (jblk > 64) jblk = 64;
+  if (jblk > jblk_cap(dtype, RP, L.i1blk)) jblk = jblk_cap(dtype, RP, L.i1blk);
   if (jblk > L.J) jblk = L.J;
   if (jblk < 1) jblk = 1;
   L.jblk = (int)jblk;
@@ -151,7 +160,11 @@ size_t pm_variant_max_lds(int kind, int variant) {
   const int side = (variant / 1000) % 10, nb = (variant / 100) % 10;
   const int RP = 16 * nb;
   const int ks = f32 ? pm_f32_kstep(side) : pm_16_kstep(side);
-  size_t lds = lds_for(dtype, RP, lds_rows(dtype, RP, ks), 64);
+  size_t lds = 0;
+  for (int rows = ks; rows <= lds_rows(dtype, RP, ks); rows += ks) {
+    const size_t b = lds_for(dtype, RP, rows, jblk_cap(dtype, RP, rows));
+    if (b > lds) lds = b;
+  }
   const size_t red = f32 ? pm_f32_reduce_lds(side, nb, 1) : pm_16_reduce_lds(side, nb, 1);
   return lds > red ? lds : red;
 }

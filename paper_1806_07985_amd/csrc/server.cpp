@@ -31,6 +31,7 @@
 #include <vector>
 
 #include "nncp.h"
+#include "nncp_internal.hpp"
 
 namespace {
 
@@ -100,6 +101,12 @@ size_t job_footprint(const Job& j) {
   return b;
 }
 
+bool hip_failed(hipError_t e, int line) {
+  if (e == hipSuccess) return false;
+  nncpk::note_device_error((int)e, 200000 + line);
+  return true;
+}
+
 // Frees the job's device buffers in stream order on the loader's stream (no
 // device-wide synchronisation; the caller has finished using them).
 void release_device(nncp_server* S, Job* j) {
@@ -120,11 +127,11 @@ int load_device(nncp_server* S, Job* j) {
   hipStream_t s = S->up;
   const size_t xb = (size_t)j->I * elem_bytes(j->dtype);
   if (hipMallocAsync(&j->Xd, xb, s) != hipSuccess) return NNCP_ENOMEM;
-  if (hipMemcpyAsync(j->Xd, j->X, xb, hipMemcpyHostToDevice, s) != hipSuccess) return NNCP_EDEVICE;
+  if (hip_failed(hipMemcpyAsync(j->Xd, j->X, xb, hipMemcpyHostToDevice, s), __LINE__)) return NNCP_EDEVICE;
   for (int n = 0; n < j->N; ++n) {
     const size_t hb = (size_t)j->dims[n] * j->R * sizeof(float);
     if (hipMallocAsync((void**)&j->Hd[n], hb, s) != hipSuccess) return NNCP_ENOMEM;
-    if (hipMemcpyAsync(j->Hd[n], j->H0[n].data(), hb, hipMemcpyHostToDevice, s) != hipSuccess)
+    if (hip_failed(hipMemcpyAsync(j->Hd[n], j->H0[n].data(), hb, hipMemcpyHostToDevice, s), __LINE__))
       return NNCP_EDEVICE;
   }
   nncp_options o{};
@@ -156,11 +163,12 @@ int retire_device(nncp_server* S, Job* j) {
   j->H.resize(j->N);
   for (int n = 0; r == NNCP_OK && n < j->N; ++n) {
     j->H[n].resize((size_t)j->dims[n] * j->R);
-    if (hipMemcpyAsync(j->H[n].data(), j->Hd[n], j->H[n].size() * sizeof(float), hipMemcpyDeviceToHost, S->st) !=
-        hipSuccess)
+    if (hip_failed(hipMemcpyAsync(j->H[n].data(), j->Hd[n], j->H[n].size() * sizeof(float),
+                                  hipMemcpyDeviceToHost, S->st),
+                   __LINE__))
       r = NNCP_EDEVICE;
   }
-  if (hipStreamSynchronize(S->st) != hipSuccess && r == NNCP_OK) r = NNCP_EDEVICE;
+  if (hip_failed(hipStreamSynchronize(S->st), __LINE__) && r == NNCP_OK) r = NNCP_EDEVICE;
   release_device(S, j);
   return r;
 }

@@ -220,8 +220,10 @@ __global__ __launch_bounds__(NT) void mttv_trail_kernel(MttvArgs a) {
 }
 
 // --------------------------------------------------------------------------
-// Multi-TTV, leading mode: out(j, r) = sum_i T(i, j, r) H(i, r), one lane group
-// of GS lanes per output (contiguous dot product, shuffle reduction).
+// Multi-TTV, leading modes: out(j, r) = sum_i T(i, j, r) K(i, r), i over the
+// leading mode(s) of the node (K = their Khatri-Rao product, the first
+// fastest; one mode: K = H), one lane group of GS lanes per output
+// (contiguous dot product, shuffle reduction).
 // --------------------------------------------------------------------------
 template <int GS, typename TN>
 __device__ __forceinline__ void mttv_lead_body(const MttvArgs& a, int bx) {
@@ -235,8 +237,33 @@ __device__ __forceinline__ void mttv_lead_body(const MttvArgs& a, int bx) {
     r = (int)(o / a.J);
     const int64_t j = o - (int64_t)r * a.J;
     const TN* Tc = (const TN*)a.T + a.Ia * (j + a.J * (int64_t)r);
-    const float* Hc = a.krp.f[0] + a.Ia * (int64_t)r;
-    for (int64_t i = p; i < a.Ia; i += GS) acc += (double)Tc[i] * (double)Hc[i];
+    if (a.krp.nm == 1) {
+      const float* Hc = a.krp.f[0] + a.Ia * (int64_t)r;
+      for (int64_t i = p; i < a.Ia; i += GS) acc += (double)Tc[i] * (double)Hc[i];
+    } else {
+      const bool narrow = a.Ia <= (int64_t)UINT32_MAX;  // 32-bit index arithmetic suffices
+      for (int64_t i = p; i < a.Ia; i += GS) {
+        double k = 1.0;
+        if (narrow) {
+          uint32_t rem = (uint32_t)i;
+          for (int m = 0; m < a.krp.nm; ++m) {
+            const uint32_t d = (uint32_t)a.krp.dim[m];
+            const uint32_t q = rem / d;
+            k *= (double)a.krp.f[m][(int64_t)(rem - q * d) + (int64_t)d * r];
+            rem = q;
+          }
+        } else {
+          int64_t rem = i;
+          for (int m = 0; m < a.krp.nm; ++m) {
+            const int64_t d = a.krp.dim[m];
+            const int64_t q = rem / d;
+            k *= (double)a.krp.f[m][(rem - q * d) + d * r];
+            rem = q;
+          }
+        }
+        acc += (double)Tc[i] * k;
+      }
+    }
   }
 #pragma unroll
   for (int off = GS / 2; off > 0; off >>= 1) acc += __shfl_xor(acc, off, GS);
@@ -1261,7 +1288,7 @@ hipError_t sink_record(const Sink& s, const KOp& op) {
   if (!s.rec) return hipErrorInvalidValue;
   try {
     KOp o = op;
-    o.stage = 16 * s.mode + kslot(op.kind);
+    o.stage = 64 * s.mode + 4 * s.step + kslot(op.kind);
     static_cast<std::vector<KOp>*>(s.rec)->push_back(o);
   } catch (...) {
     return hipErrorOutOfMemory;

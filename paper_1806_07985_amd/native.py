@@ -39,7 +39,7 @@ class Options(ctypes.Structure):
                 ("inner_sweeps", ctypes.c_int),
                 ("reserved0", ctypes.c_int),
                 ("inner_tol", ctypes.c_double),
-                ("reserved1", ctypes.c_uint64)]
+                ("tree_peel", ctypes.c_uint64)]
 
 
 class JobRequest(ctypes.Structure):
@@ -65,8 +65,20 @@ class ServerStats(ctypes.Structure):
 class NNCPError(RuntimeError):
     def __init__(self, status: int, what: str):
         msg = _lib.nncp_strerror(status).decode() if _lib is not None else str(status)
+        if status == -3 and _lib is not None:
+            code, where = last_device_error()
+            msg += f" [last HIP error {code} at {where}]"
         super().__init__(f"{what}: {msg} ({status})")
         self.status = status
+
+
+def last_device_error():
+    """(hipError_t, source location) of the library's most recent failed HIP
+    call, or (0, 0) if none since it was loaded."""
+    L = lib()
+    code, where = ctypes.c_int(0), ctypes.c_int(0)
+    L.nncp_last_device_error(ctypes.byref(code), ctypes.byref(where))
+    return code.value, where.value
 
 
 _lib = None
@@ -76,6 +88,7 @@ def _declare(L):
     L.nncp_strerror.restype = ctypes.c_char_p
     L.nncp_strerror.argtypes = [ctypes.c_int]
     L.nncp_version.restype = ctypes.c_int
+    L.nncp_last_device_error.argtypes = [ctypes.POINTER(ctypes.c_int), ctypes.POINTER(ctypes.c_int)]
     L.nncp_workspace_bytes.restype = ctypes.c_size_t
     L.nncp_workspace_bytes.argtypes = [ctypes.c_int, c_i64p, ctypes.c_int, ctypes.c_int, ctypes.POINTER(Options)]
     L.nncp.restype = ctypes.c_int
@@ -103,6 +116,11 @@ def _declare(L):
     L.nncp_autotune_split.restype = ctypes.c_int
     L.nncp_autotune_split.argtypes = [c_vp, ctypes.c_int, ctypes.c_int, c_i64p, ctypes.c_int, ctypes.POINTER(c_vp),
                                       c_vp, ctypes.c_int, ctypes.POINTER(ctypes.c_int), c_dp, c_vp]
+    L.nncp_autotune_tree.restype = ctypes.c_int
+    L.nncp_autotune_tree.argtypes = [c_vp, ctypes.c_int, ctypes.c_int, c_i64p, ctypes.c_int, ctypes.POINTER(c_vp),
+                                     c_vp, ctypes.c_int, ctypes.c_int, ctypes.POINTER(ctypes.c_int),
+                                     ctypes.POINTER(ctypes.c_uint64), c_dp, ctypes.POINTER(ctypes.c_int),
+                                     ctypes.POINTER(ctypes.c_int), c_vp]
     L.nncp_quantize.restype = ctypes.c_int
     L.nncp_quantize.argtypes = [c_vp, c_vp, ctypes.c_int, ctypes.c_int64, c_vp]
     L.nncp_norm_sq.restype = ctypes.c_int
@@ -248,8 +266,8 @@ def version() -> int:
     return lib().nncp_version()
 
 
-def workspace_bytes(dims, R, dtype="f32", split=0, pm_wg_kib=0, no_tree=False) -> int:
-    o = Options(split=split, pm_wg_kib=pm_wg_kib, no_tree=1 if no_tree else 0)
+def workspace_bytes(dims, R, dtype="f32", split=0, pm_wg_kib=0, no_tree=False, peel=0) -> int:
+    o = Options(split=split, pm_wg_kib=pm_wg_kib, no_tree=1 if no_tree else 0, tree_peel=peel)
     return int(lib().nncp_workspace_bytes(len(dims), _dims(dims), R, _DTYPE[dtype], ctypes.byref(o)))
 
 
@@ -258,7 +276,8 @@ def _dtype_name(t) -> str:
 
 
 def nncp(X, dims, R, iters, H, lam=None, update="hals", split=0, graph=True, record_fit=True,
-         tol=0.0, workspace=None, stream=None, pm_wg_kib=0, no_tree=False, inner_sweeps=1, inner_tol=0.0):
+         tol=0.0, workspace=None, stream=None, pm_wg_kib=0, no_tree=False, inner_sweeps=1, inner_tol=0.0,
+         peel=0):
     """Run the full driver. H: list of device (R, I_n) float32 tensors, updated in place.
 
     Returns dict(fit=np.ndarray, lam=np.ndarray, iters_done=int).
@@ -274,7 +293,8 @@ def nncp(X, dims, R, iters, H, lam=None, update="hals", split=0, graph=True, rec
     fit = (ctypes.c_double * max(1, iters))()
     done = ctypes.c_int(0)
     o = Options(split=split, no_record_fit=0 if record_fit else 1, no_graph=0 if graph else 1, tol=tol,
-                pm_wg_kib=pm_wg_kib, no_tree=1 if no_tree else 0, inner_sweeps=inner_sweeps, inner_tol=inner_tol)
+                pm_wg_kib=pm_wg_kib, no_tree=1 if no_tree else 0, inner_sweeps=inner_sweeps, inner_tol=inner_tol,
+                tree_peel=peel)
     ws_ptr, ws_bytes = (None, 0)
     if workspace is not None:
         ws_ptr, ws_bytes = _ptr(workspace), workspace.numel() * workspace.element_size()
@@ -304,11 +324,32 @@ def autotune_split(X, dims, R, H, reps=3, pm_wg_kib=0, stream=None):
     return best.value, list(ms)
 
 
+def autotune_tree(X, dims, R, H, reps=3, cap=64, pm_wg_kib=0, stream=None):
+    """Every dimension tree (root split and internal splits) timed on the device
+    (nncp_autotune_tree). Returns (best_split, best_peel, [(split, peel, ms), ...])."""
+    import torch
+    N = len(dims)
+    _need(X, int(np.prod(dims)), name="X")
+    for n, h in enumerate(H):
+        _need(h, dims[n] * R, torch.float32, name=f"H[{n}]")
+    o = Options(pm_wg_kib=pm_wg_kib)
+    splits = (ctypes.c_int * cap)()
+    peels = (ctypes.c_uint64 * cap)()
+    ms = (ctypes.c_double * cap)()
+    count = ctypes.c_int(0)
+    best = ctypes.c_int(-1)
+    _check(lib().nncp_autotune_tree(_ptr(X), _dtype_code(X), N, _dims(dims), R, _ptr_array(H), ctypes.byref(o),
+                                    reps, cap, splits, peels, ms, ctypes.byref(count), ctypes.byref(best),
+                                    _stream(stream)), "nncp_autotune_tree")
+    rows = [(splits[k], int(peels[k]), ms[k]) for k in range(count.value)]
+    return rows[best.value][0], rows[best.value][1], rows
+
+
 class Plan:
     """Persistent driver state: create once, run repeatedly, finish to normalise."""
 
     def __init__(self, X, dims, R, H, lam=None, update="hals", split=0, graph=True, phase_timers=False,
-                 workspace=None, stream=None, pm_wg_kib=0, no_tree=False, inner_sweeps=1, inner_tol=0.0):
+                 workspace=None, stream=None, pm_wg_kib=0, no_tree=False, inner_sweeps=1, inner_tol=0.0, peel=0):
         import torch
         L = lib()
         self.dims, self.R, self.H, self.X = list(dims), R, list(H), X
@@ -321,10 +362,10 @@ class Plan:
             lam_arr = (ctypes.c_double * R)(*np.asarray(lam, dtype=np.float64))
         o = Options(split=split, no_graph=0 if graph else 1, phase_timers=1 if phase_timers else 0,
                     pm_wg_kib=pm_wg_kib, no_tree=1 if no_tree else 0, inner_sweeps=inner_sweeps,
-                    inner_tol=inner_tol)
+                    inner_tol=inner_tol, tree_peel=peel)
         self._ws = workspace
         if workspace is None:
-            nbytes = workspace_bytes(dims, R, _dtype_name(X), split, pm_wg_kib, no_tree)
+            nbytes = workspace_bytes(dims, R, _dtype_name(X), split, pm_wg_kib, no_tree, peel)
             self._ws = torch.empty(nbytes, dtype=torch.uint8, device=X.device)
         handle = c_vp()
         st = L.nncp_plan_create(ctypes.byref(handle), _ptr(X), _dtype_code(X), len(dims), _dims(dims), R,

@@ -124,3 +124,10 @@ def test_autotune_split_rejects_bad_arguments_without_a_device():
     assert L.nncp_autotune_split(ctypes.c_void_p(16), 0, 1, dims, 2, H, None, 3, ctypes.byref(best), None,
                                  None) == -1
     assert L.nncp_autotune_split(ctypes.c_void_p(16), 0, 3, dims, 2, H, None, 3, None, None, None) == -1
+
+
+def test_last_device_error_is_callable():
+    from paper_1806_07985_amd import native
+    code, where = native.last_device_error()
+    assert isinstance(code, int) and isinstance(where, int)
+    assert (code == 0) == (where == 0)

@@ -149,3 +149,42 @@ def test_quantized_fit_close_to_fp32_fit(gpu_lib):
     print(f"fit vs FP32 tensor: {fits}", flush=True)
     assert abs(fits["bf16"] - fits["f32"]) < 1e-4
     assert abs(fits["f16"] - fits["f32"]) < 1e-4
+
+
+def test_bf16_rank64_full_lds_block_alone_and_batched(gpu_lib):
+    """BF16 at rank 64 keeps three 64-column term rows per i1 in LDS; with a
+    full 384-row i1 block and a long j range (one work-group per column tile,
+    from a large per-group share of the tensor) the per-(j, column) scales are
+    what is left of the CU's 160 KiB, so the j block is cut below 64. The plan
+    still follows the oracle, and the same plan advanced in a batch (graph of
+    kernel nodes sized for the largest LDS the variant can ask for) gives
+    bitwise the same factors."""
+    import torch
+    from paper_1806_07985_amd import native
+    dims, R, split, iters = (384, 1400, 16), 64, 2, 3
+    print(f"case bf16 full lds block dims={dims} R={R}", flush=True)
+    X, _ = inputs.planted(dims, R, 0.01, seed=61, dtype=np.float32)
+    H0 = [h.astype(np.float32) for h in inputs.init_factors(dims, R, seed=62)]
+    Xd, Xq = _quantized(X, "bf16")
+    Ha = [native.factor_to_device(h) for h in H0]
+    out = native.nncp(Xd, list(dims), R, iters, Ha, split=split, pm_wg_kib=1 << 14)
+    ref = O.nncp(Xq, [h.astype(np.float64) for h in H0], iters)
+    errs = [np.linalg.norm(native.factor_to_host(h) - r) / np.linalg.norm(r) for h, r in zip(Ha, ref["H"])]
+    fit_err = float(np.max(np.abs(np.asarray(out["fit"]) - np.asarray(ref["fit"]))))
+    print(f"  factor errs {['%.1e' % e for e in errs]} fit {fit_err:.1e}", flush=True)
+    assert max(errs) < TRAJ_TOL["bf16"] and fit_err < TRAJ_TOL["bf16"]
+    # the same plan alone (graph) and advanced by a batch: the unnormalised factors
+    Hc = [native.factor_to_device(h) for h in H0]
+    alone = native.Plan(Xd, list(dims), R, Hc, split=split, pm_wg_kib=1 << 14)
+    alone.run(iters)
+    Hb = [native.factor_to_device(h) for h in H0]
+    plan = native.Plan(Xd, list(dims), R, Hb, split=split, pm_wg_kib=1 << 14, graph=False)
+    batch = native.Batch()
+    batch.add(plan)
+    batch.run(iters)
+    torch.cuda.synchronize()
+    assert all(torch.equal(a, b) for a, b in zip(Hc, Hb))
+    assert np.array_equal(alone.fits(), plan.fits())
+    batch.close()
+    plan.close()
+    alone.close()

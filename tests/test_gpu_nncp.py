@@ -219,7 +219,7 @@ def test_inner_sweeps_above_maximum_rejected(gpu_lib):
     X, _ = inputs.planted(dims, R, 0.02, seed=55, dtype=np.float32)
     Hd = [native.factor_to_device(h.astype(np.float32)) for h in inputs.init_factors(dims, R, seed=56)]
     with pytest.raises(Exception):
-        native.nncp(native.tensor_to_device(X), list(dims), R, 1, Hd, inner_sweeps=100000)
+        native.nncp(native.tensor_to_device(X), list(dims), R, 1, Hd, inner_sweeps=100001)
 
 
 @pytest.mark.parametrize("dims,R,dt", [((24, 20, 18, 16), 8, "f32"), ((40, 36, 30), 12, "bf16"),
