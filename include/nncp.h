@@ -294,6 +294,24 @@ int nncp_quantize(const float* src, void* dst, int dtype, int64_t n, void* strea
 int nncp_norm_sq(const void* X, int dtype, int64_t n, double* out_dev, void* stream);
 
 /*
+ * nncp_norm_sq without any device allocation, for callers that cannot allocate
+ * (code recorded under HIP graph capture, serving loops that must not touch the
+ * allocator). Same result as nncp_norm_sq, bit for bit: the same kernel, grid
+ * and summation order. It only enqueues work on `stream` (no synchronisation);
+ * out_dev is written when the stream reaches it.
+ * Scratch: the FP64 block partials and the arrival counter live in a static
+ * device array of 8.2 KB per GPU (1024 partials), held until the process ends;
+ * the grid never exceeds 1024 work-groups, so every n >= 1 fits, and a grid that
+ * would need more partials is rejected with NNCP_EINVAL. The counter is cleared
+ * by a kernel at the start of each call. All calls on one GPU share that array:
+ * calls that overlap on one GPU (concurrent streams or threads) race, so
+ * serialise them (one stream, or an event between calls).
+ * Errors: NNCP_EINVAL for a NULL pointer, n < 1 or an unknown dtype;
+ * NNCP_EDEVICE if the scratch address cannot be obtained or a launch fails.
+ */
+int nncp_norm_sq_noalloc(const void* X, int dtype, int64_t n, double* out_dev, void* stream);
+
+/*
  * Partial MTTKRP for a root branch of the dimension tree (Section IV-A, Fig. 2a):
  * with I_L = I_1*...*I_s and I_R = I_{s+1}*...*I_N, view X as the column-major
  * I_L x I_R matrix X_[L].

@@ -125,6 +125,8 @@ def _declare(L):
     L.nncp_quantize.argtypes = [c_vp, c_vp, ctypes.c_int, ctypes.c_int64, c_vp]
     L.nncp_norm_sq.restype = ctypes.c_int
     L.nncp_norm_sq.argtypes = [c_vp, ctypes.c_int, ctypes.c_int64, c_vp, c_vp]
+    L.nncp_norm_sq_noalloc.restype = ctypes.c_int
+    L.nncp_norm_sq_noalloc.argtypes = [c_vp, ctypes.c_int, ctypes.c_int64, c_vp, c_vp]
     L.nncp_partial_mttkrp.restype = ctypes.c_int
     L.nncp_partial_mttkrp.argtypes = [c_vp, ctypes.c_int, ctypes.c_int, c_i64p, ctypes.c_int, ctypes.c_int,
                                       ctypes.POINTER(c_vp), ctypes.c_int, c_vp, c_vp]
@@ -576,6 +578,16 @@ def norm_sq(X, stream=None) -> float:
     out = torch.zeros(1, dtype=torch.float64, device=X.device)
     _check(lib().nncp_norm_sq(_ptr(X), _dtype_code(X), X.numel(), _ptr(out), _stream(stream)), "nncp_norm_sq")
     return float(out.item())
+
+
+def norm_sq_noalloc(X, out, stream=None):
+    """||X||^2 into the device float64 tensor `out` (one element) through the entry
+    point that allocates nothing; enqueued on the stream, not synchronised."""
+    import torch
+    _need(out, 1, torch.float64, name="out")
+    _check(lib().nncp_norm_sq_noalloc(_ptr(X), _dtype_code(X), X.numel(), _ptr(out), _stream(stream)),
+           "nncp_norm_sq_noalloc")
+    return out
 
 
 def partial_mttkrp(X, dims, s, side, H, R, stream=None):
