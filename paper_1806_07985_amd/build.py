@@ -11,7 +11,8 @@ ROOT = os.path.dirname(PKG)
 CSRC = os.path.join(PKG, "csrc")
 LIB_DIR = os.path.join(PKG, "lib")
 LIB = os.path.join(LIB_DIR, "libnncp.so")
-SOURCES = ["pm_plan.hip", "pm_kernels.hip", "pm16_kernels.hip", "pm16_bf16.hip", "pm16_f16.hip", "small_kernels.hip",
+SOURCES = ["pm_plan.hip", "pm_kernels.hip", "pm16_kernels.hip", "pm16_bf16.hip", "pm16_f16.hip", "pm16_bf16_mt.hip",
+           "pm16_f16_mt.hip", "small_kernels.hip",
            "driver.hip", "server.cpp", "noalloc.hip"]
 
 HIPCC_FLAGS = [

@@ -1310,13 +1310,44 @@ int batch_build(nncp_batch* B) {
     slot[kv.first] = (int)L.size();
     L.push_back(kv.second);
   }
-  // items of each launch, contiguous
+  // Items of each launch, contiguous. A batch item of a small op runs `coarse`
+  // of its stand-alone work-groups in turn, so that an item carries enough work
+  // to amortise fetching its descriptor (the blocks of these ops are tiny) --
+  // but only while the launch still has several items per persistent group.
+  {
+    std::vector<double> blocks(L.size(), 0.0);
+    for (const KOp& o : all)
+      blocks[slot[key_of(o.stage, batch_kernel_id(o.kind, o.variant))]] += (double)o.gx * (double)o.gy;
+    const double cus = (double)device_cus();
+    for (KOp& o : all) {
+      o.coarse = 1;
+      const int kid = batch_kernel_id(o.kind, o.variant);
+      if (kid != 1) continue;
+      const double groups = (double)batch_kernel_for(o.kind, o.variant).per_cu * cus;
+      const double c = blocks[slot[key_of(o.stage, kid)]] / (4.0 * groups);
+      const unsigned want = c >= 8.0 ? 8u : (c >= 1.0 ? (unsigned)c : 1u);
+      o.coarse = want < o.gx ? want : (o.gx > 0 ? o.gx : 1u);
+    }
+  }
   std::vector<std::vector<BItem>> per(L.size());
   for (size_t i = 0; i < all.size(); ++i) {
     const KOp& o = all[i];
     auto& v = per[slot[key_of(o.stage, batch_kernel_id(o.kind, o.variant))]];
+    const unsigned nx = (o.gx + o.coarse - 1) / o.coarse;
     for (unsigned by = 0; by < o.gy; ++by)
-      for (unsigned bx = 0; bx < o.gx; ++bx) v.push_back(BItem{(int)i, (int)bx, (int)by});
+      for (unsigned bx = 0; bx < nx; ++bx) v.push_back(BItem{(int)i, (int)bx, (int)by});
+  }
+  // A persistent group takes items g, g + grid, g + 2 grid, ...: partial-MTTKRP
+  // items in order of decreasing share of the tensor, so the largest start first
+  // and the launch's tail is made of small ones.
+  for (size_t g = 0; g < L.size(); ++g) {
+    if (L[g].kind != K_PM_F32 && L[g].kind != K_PM_16) continue;
+    auto share = [&](const BItem& it) {
+      const KOp& o = all[it.op];
+      return (double)o.u.pm.IL * (double)o.u.pm.IR / ((double)o.gx * (double)o.gy);
+    };
+    std::stable_sort(per[g].begin(), per[g].end(),
+                     [&](const BItem& x, const BItem& y) { return share(x) > share(y); });
   }
   std::vector<BItem> items;
   std::vector<int> grp(2 * L.size());
@@ -1349,16 +1380,22 @@ int batch_build(nncp_batch* B) {
 
   // The tick's graph is built node by node (no stream capture, so work that
   // other threads enqueue meanwhile, such as a serving loader's uploads and
-  // allocations, cannot interfere with it): one kernel node per launch, each
-  // depending on the one before.
+  // allocations, cannot interfere with it): one kernel node per launch. The ops
+  // of one stage are independent (different members, or independent ops of one
+  // member), so a stage's launches depend only on all launches of the stage
+  // before and may overlap one another's tails.
   batch_drop_graph(B);
   B->launches = L;
   const unsigned cus = (unsigned)device_cus();
   hipGraph_t gr = nullptr;
   HIPCHK(hipGraphCreate(&gr, 0));
   hipError_t e = hipSuccess;
-  hipGraphNode_t prev = nullptr;
+  std::vector<hipGraphNode_t> before, cur;
   for (size_t g = 0; g < L.size() && e == hipSuccess; ++g) {
+    if (g == 0 || L[g].stage != L[g - 1].stage) {
+      if (!cur.empty()) before.swap(cur);
+      cur.clear();
+    }
     const BatchKernel bk = batch_kernel_for(L[g].kind, L[g].variant);
     if (!bk.fn) {
       e = hipErrorInvalidValue;
@@ -1376,8 +1413,8 @@ int batch_build(nncp_batch* B) {
     kp.kernelParams = args;
     kp.extra = nullptr;
     hipGraphNode_t node = nullptr;
-    e = hipGraphAddKernelNode(&node, gr, prev ? &prev : nullptr, prev ? 1 : 0, &kp);
-    prev = node;
+    e = hipGraphAddKernelNode(&node, gr, before.empty() ? nullptr : before.data(), before.size(), &kp);
+    if (e == hipSuccess) cur.push_back(node);
   }
   if (e != hipSuccess) {
     note_device_error((int)e, __LINE__);

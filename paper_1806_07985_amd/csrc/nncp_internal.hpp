@@ -59,6 +59,8 @@ struct PmArgs {
   unsigned* counters;    // one per M tile; zero on entry, left zero on exit
   int nsplit;            // (n_i1blk / istages) * n_jblk
   int wm;                // waves along M in a work-group (1 or 4); the other 4 / wm split K
+  int mtiles;            // M tiles of the output
+  int mper;              // M tiles one work-group streams in turn (> 1 only with wm == 4, istages == 1)
   // the number of i1 blocks one work-group walks in turn (restaging LDS between
   // them) instead of splitting K over work-groups
   int istages;
@@ -79,8 +81,10 @@ struct PmLaunch {
   int side;      // 0 left (m contiguous), 1 right (k contiguous)
   int dtype;
   int nb;        // 16-wide column blocks
-  int mtile;     // output rows per work-group
+  int mtile;     // output rows per M tile
   int mtiles;
+  int mper;      // M tiles per work-group
+  int mgroups;   // work-groups along M: ceil(mtiles / mper)
   int nsplit;
   int I1, I1pad, i1blk, n_i1blk, jblk, n_jblk, fold, istages;
   int j1;        // 16-bit right node with J == 1: the specialised kernel (column scale at the end)
@@ -101,7 +105,7 @@ hipError_t pm_launch(const PmLaunch& L, const PmArgs& a, hipStream_t st);
 struct Sink;
 struct ReduceArgs;
 hipError_t pm_launch(const PmLaunch& L, const PmArgs& a, const Sink& sk);
-// per-dtype kernels (pm_kernels.hip, pm16_kernels.hip + pm16_bf16.hip / pm16_f16.hip)
+// per-dtype kernels (pm_kernels.hip, pm16_kernels.hip + pm16_{bf16,f16}{,_mt}.hip)
 int pm_f32_wave_rows(int side, int nb);
 int pm_f32_kstep(int side);
 size_t pm_f32_reduce_lds(int side, int nb, int wm);
@@ -110,8 +114,8 @@ int pm_16_wave_rows(int side, int nb, int j1 = 0);
 int pm_16_kstep(int side);
 size_t pm_16_reduce_lds(int side, int nb, int wm);
 hipError_t pm_launch_16(const PmLaunch& L, const PmArgs& a, const Sink& sk);
-template <int DT>
-const void* pm16_kernel(int side, int nb, int j1, int fast, bool batch);
+template <int DT, bool MT>
+const void* pm16_kernel_form(int side, int nb, int j1, int fast, bool batch);
 // Every vector load of every k-step lies inside the tensor for this shape (no
 // padded i1, and on the left side no row group straddling a column end): the
 // kernels then skip the per-step check.
@@ -237,8 +241,8 @@ struct PackArgs {        // term pack of the first contracted factor (16-bit ten
 };
 
 enum KKind : int {
-  K_PM_F32 = 1,     // variant: side*1000 + nb*100 + wm*10 + fast
-  K_PM_16 = 2,      // variant: (dtype == BF16)*10000 + side*1000 + nb*100 + wm*10 + fast
+  K_PM_F32 = 1,     // variant: side*1000 + nb*100 + mt*10 + fast
+  K_PM_16 = 2,      // variant: j1*100000 + (dtype == BF16)*10000 + side*1000 + nb*100 + mt*10 + fast
   K_PACK16 = 3,     // variant: dtype == BF16
   K_PM_REDUCE = 4,  // variant: t_f64
   K_MTTV_TRAIL = 5, // variant: t_f64
@@ -254,9 +258,10 @@ enum KKind : int {
 struct KOp {
   int kind;
   int variant;
-  int stage;         // batching order: 16 * mode + slot of the kind within the mode's steps
+  int stage;         // batching order: 64 * mode + 4 * step + slot (see kslot)
   unsigned gx, gy;   // work-groups of the stand-alone launch (x, y)
   unsigned lds;      // dynamic LDS bytes
+  unsigned coarse;   // batched small ops: stand-alone work-groups (along x) one batch item runs in turn
   union {
     PmArgs pm;
     MttvArgs mt;
@@ -267,7 +272,8 @@ struct KOp {
   } u;
 };
 
-// One work-group's share of a recorded launch: op index and its (x, y) tile.
+// One work-group's share of a recorded launch: op index and its (x, y) tile
+// (for a small op, x counts runs of `coarse` stand-alone work-groups).
 struct BItem {
   int op;
   int bx, by;

@@ -3,6 +3,6 @@
 #include "pm16_body.hpp"
 
 namespace nncpk {
-template const void* pm16_kernel<NNCP_BF16>(int, int, int, int, bool);
+template const void* pm16_kernel_form<NNCP_BF16, false>(int, int, int, int, bool);
 template const void* pm16_pack_kernel<NNCP_BF16>(bool);
 }  // namespace nncpk

@@ -177,8 +177,8 @@ constexpr int right_pf16(int nb) { return 3; }
 // TR*li .. TR*li+TR-1 of the 8 columns i1 = base + 8*lq + e; MFMA tile tt takes
 // row TR*li + tt of those 8 loads as its 8-k operand.
 // ----------------------------------------------------------------------------
-template <int DT, int NB, bool FAST>
-__device__ __forceinline__ void left_body(const PmArgs& a, int bx, int by, int gx) {
+template <int DT, int NB, bool FAST, bool MT>
+__device__ __forceinline__ void left_body(const PmArgs& a, int bx, int by) {
   constexpr int RP = NB * 16;
   constexpr int TR = left_tr16(NB);
   constexpr int D = left_pf16(NB);
@@ -199,7 +199,10 @@ __device__ __forceinline__ void left_body(const PmArgs& a, int bx, int by, int g
   const int li = lane & 15, lq = lane >> 4;
   const int64_t Mtot = a.IL, Ktot = a.IR;
   const int mtile = WM * WROWS;
-  const int64_t mw = (int64_t)bx * mtile + wm * WROWS;
+  // the group's M tiles tile0 .. tile0 + ntile - 1 (ntile > 1 only with WK == 1),
+  // streamed as one sequence of k-steps per wave
+  const int tile0 = MT ? bx * a.mper : bx;
+  const int ntile = MT ? min(a.mper, a.mtiles - tile0) : 1;
   const int ib = by % a.n_i1blk, jb = by / a.n_i1blk;
   const int i1_0 = ib * a.i1blk;
   const int i1n = min(a.i1blk, a.I1pad - i1_0);
@@ -214,6 +217,7 @@ __device__ __forceinline__ void left_body(const PmArgs& a, int bx, int by, int g
   const int S1 = i1n / KS;
   int sb, se;
   wave_range(S1 * jn, wk, WK, &sb, &se);
+  se += (ntile - 1) * S1 * jn;
 
   float acc[NACC][4];
 #pragma unroll
@@ -221,8 +225,10 @@ __device__ __forceinline__ void left_body(const PmArgs& a, int bx, int by, int g
 #pragma unroll
     for (int e = 0; e < 4; ++e) acc[v][e] = 0.f;
 
-  const int64_t m = mw + TR * li;
-  const int64_t mload = m < Mtot ? m : 0;  // a row group wholly past the output reads row 0
+  // lane's first row in the tile being loaded; a row group wholly past the
+  // output reads row 0
+  int64_t m = (int64_t)tile0 * mtile + wm * WROWS + TR * li;
+  int64_t mload = m < Mtot ? m : 0;
   const int ilim = a.I1 - i1_0;
   const unsigned short* zeros = (const unsigned short*)a.zeros;
   // The vector loads of a step read elements up to Mtot * (colbase + KS) + TR - 2
@@ -231,7 +237,8 @@ __device__ __forceinline__ void left_body(const PmArgs& a, int bx, int by, int g
   const int64_t vec_lim = Mtot * Ktot - (TR - 1);
 
   const int jrot = (WK == 1 && jn > 1) ? (int)(((unsigned)bx * 5u) % (unsigned)jn) : 0;
-  int jl = sb / S1 + jrot, tl = sb - (sb / S1) * S1;
+  int jcntL = sb / S1, tileL = 0;
+  int jl = jcntL + jrot, tl = sb - jcntL * S1;
   if (jl >= jn) jl -= jn;
   auto load = [&](vT (&A)[8]) {
     const int64_t colbase = (int64_t)a.I1 * (j0 + jl) + i1_0 + KS * tl;
@@ -255,7 +262,27 @@ __device__ __forceinline__ void left_body(const PmArgs& a, int bx, int by, int g
     if (++tl == S1) {
       tl = 0;
       if (++jl == jn) jl = 0;
+      if (MT && ++jcntL == jn) {
+        jcntL = 0;
+        if (++tileL == ntile) tileL = 0;
+        m = (int64_t)(tile0 + tileL) * mtile + wm * WROWS + TR * li;
+        mload = m < Mtot ? m : 0;
+      }
     }
+  };
+
+  const bool direct = (a.nsplit == 1);
+  const int64_t Mpad = (int64_t)a.mtiles * mtile;
+  auto store_tile = [&](int64_t mw) {
+#pragma unroll
+    for (int nb = 0; nb < NB; ++nb)
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        double o[TR];
+#pragma unroll
+        for (int tt = 0; tt < TR; ++tt) o[tt] = (double)acc[tt * NB + nb][v];
+        pm_store_rows<TR>(a, direct, Mtot, Mpad, RP, by, 16 * nb + li, mw + TR * (4 * lq + v), o);
+      }
   };
 
   f4 c32[TR][NB];
@@ -263,7 +290,7 @@ __device__ __forceinline__ void left_body(const PmArgs& a, int bx, int by, int g
   for (int tt = 0; tt < TR; ++tt)
 #pragma unroll
     for (int nb = 0; nb < NB; ++nb) c32[tt][nb] = f4{0.f, 0.f, 0.f, 0.f};
-  int jc = jl, tc = tl, left = se - sb;
+  int jc = jl, tc = tl, jcntC = jcntL, tileC = 0, left = se - sb;
   auto compute = [&](const vT (&A)[8]) {
     const int kk = KS * tc + 8 * lq;
     u4 B[NTM][NB];
@@ -298,6 +325,17 @@ __device__ __forceinline__ void left_body(const PmArgs& a, int bx, int by, int g
     if (++tc == S1) {
       tc = 0;
       if (++jc == jn) jc = 0;
+      if (MT && ++jcntC == jn) {
+        jcntC = 0;
+        if (tileC + 1 < ntile) {  // a tile done (its last j scaled above): store it, start the next
+          store_tile((int64_t)(tile0 + tileC) * mtile + wm * WROWS);
+#pragma unroll
+          for (int v = 0; v < NACC; ++v)
+#pragma unroll
+            for (int e = 0; e < 4; ++e) acc[v][e] = 0.f;
+          ++tileC;
+        }
+      }
     }
   };
 
@@ -320,17 +358,7 @@ __device__ __forceinline__ void left_body(const PmArgs& a, int bx, int by, int g
 
   reduce_waves<NACC>(acc, lds_d, wk, wm, WK);
   if (wk != 0) return;
-  const bool direct = (a.nsplit == 1);
-  const int64_t Mpad = (int64_t)gx * mtile;
-#pragma unroll
-  for (int nb = 0; nb < NB; ++nb)
-#pragma unroll
-    for (int v = 0; v < 4; ++v) {
-      double o[TR];
-#pragma unroll
-      for (int tt = 0; tt < TR; ++tt) o[tt] = (double)acc[tt * NB + nb][v];
-      pm_store_rows<TR>(a, direct, Mtot, Mpad, RP, by, 16 * nb + li, mw + TR * (4 * lq + v), o);
-    }
+  store_tile((int64_t)(tile0 + ntile - 1) * mtile + wm * WROWS);
 }
 
 // ----------------------------------------------------------------------------
@@ -343,8 +371,8 @@ __device__ __forceinline__ void left_body(const PmArgs& a, int bx, int by, int g
 // factor per column: the MFMA sums run over all of K (FP32) and are scaled once
 // at the end, with no separate accumulators (every wave owns its columns).
 // ----------------------------------------------------------------------------
-template <int DT, int NB, bool J1, bool FAST>
-__device__ __forceinline__ void right_body(const PmArgs& a, int bx, int by, int gx) {
+template <int DT, int NB, bool J1, bool FAST, bool MT>
+__device__ __forceinline__ void right_body(const PmArgs& a, int bx, int by) {
   constexpr int RP = NB * 16;
   constexpr int MC = J1 ? right_mc16_j1(NB) : right_mc16(NB);
   constexpr int D = J1 ? right_pf16_j1(NB) : right_pf16(NB);
@@ -364,7 +392,10 @@ __device__ __forceinline__ void right_body(const PmArgs& a, int bx, int by, int 
   const int li = lane & 15, lq = lane >> 4;
   const int64_t Mtot = a.IR, Ktot = a.IL;
   const int mtile = WM * 16 * MC;
-  const int64_t cw = (int64_t)bx * mtile + wm * 16 * MC;
+  // the group's M tiles tile0 .. tile0 + ntile - 1 (ntile > 1 only with WK == 1
+  // and istages == 1), streamed as one sequence of k-steps per wave
+  const int tile0 = MT ? bx * a.mper : bx;
+  const int ntile = MT ? min(a.mper, a.mtiles - tile0) : 1;
   const int n_i1grp = a.n_i1blk / a.istages;
   const int ib0 = (by % n_i1grp) * a.istages, jb = by / n_i1grp;
   const int64_t j0 = (int64_t)jb * a.jblk;
@@ -382,6 +413,7 @@ __device__ __forceinline__ void right_body(const PmArgs& a, int bx, int by, int 
   for (int st = 0; st < a.istages; ++st) total += (stage_rows(st) / KS) * jn;
   int sb, se;
   wave_range(total, wk, WK, &sb, &se);  // istages > 1 implies WK == 1: the whole range
+  se += (ntile - 1) * total;
 
   float acc[NACC][4];
 #pragma unroll
@@ -389,24 +421,30 @@ __device__ __forceinline__ void right_body(const PmArgs& a, int bx, int by, int 
 #pragma unroll
     for (int e = 0; e < 4; ++e) acc[v][e] = 0.f;
 
-  const unsigned short* colp[MC];
-#pragma unroll
-  for (int g = 0; g < MC; ++g) {
-    const int64_t c = cw + 16 * g + li;
-    colp[g] = X + Ktot * (c < Mtot ? c : 0) + 8 * lq;  // columns past the output read column 0
-  }
+  // Columns of the tile being loaded (columns past the output read column 0).
   // The vector loads of a step read elements up to Ktot * cmax + lbase + KS - 1
   // (cmax: the wave's last column that is read, lane offsets up to KS - 1): all
   // of them lie inside the tensor while lbase <= vec_lim.
-  const int64_t cmax = min(cw + 16 * MC - 1, Mtot - 1);
-  const int64_t vec_lim = Mtot * Ktot - Ktot * cmax - KS;  // wave-uniform
+  const unsigned short* colp[MC];
+  int64_t vec_lim;
+  auto set_tile = [&](int t) {
+    const int64_t cw = (int64_t)(tile0 + t) * mtile + wm * 16 * MC;
+#pragma unroll
+    for (int g = 0; g < MC; ++g) {
+      const int64_t c = cw + 16 * g + li;
+      colp[g] = X + Ktot * (c < Mtot ? c : 0) + 8 * lq;
+    }
+    const int64_t cmax = min(cw + 16 * MC - 1, Mtot - 1);
+    vec_lim = Mtot * Ktot - Ktot * cmax - KS;  // wave-uniform
+  };
+  set_tile(0);
   const unsigned short* zeros = (const unsigned short*)a.zeros;
 
   // cursor (stage, j, t): t over the stage's k-steps, j over the block (rotated
   // start with one wave along K), stages in order. The load cursor runs D steps
   // ahead and wraps to the start after the last step, so it stays in bounds.
   const int jrot = (WK == 1 && jn > 1) ? (int)(((unsigned)bx * 5u) % (unsigned)jn) : 0;
-  int stL = 0, S1L = stage_rows(0) / KS;
+  int stL = 0, S1L = stage_rows(0) / KS, tileL = 0;
   int jcntL = sb / S1L;  // sb > 0 only when istages == 1
   int tl = sb - jcntL * S1L;
   int jl = jcntL + jrot;
@@ -441,7 +479,13 @@ __device__ __forceinline__ void right_body(const PmArgs& a, int bx, int by, int 
       if (++jl == jn) jl = 0;
       if (++jcntL == jn) {
         jcntL = 0;
-        if (++stL == a.istages) stL = 0;
+        if (++stL == a.istages) {
+          stL = 0;
+          if (MT) {
+            if (++tileL == ntile) tileL = 0;
+            set_tile(tileL);
+          }
+        }
         S1L = stage_rows(stL) / KS;
       }
     }
@@ -452,7 +496,32 @@ __device__ __forceinline__ void right_body(const PmArgs& a, int bx, int by, int 
   for (int g = 0; g < MC; ++g)
 #pragma unroll
     for (int nb = 0; nb < NB; ++nb) c32[g][nb] = f4{0.f, 0.f, 0.f, 0.f};
-  int stC = 0, S1C = S1L, jc = jl, tc = tl, jcntC = jcntL, left = se - sb;
+
+  // J1: the MFMA sums of the whole K range times the one Khatri-Rao scale per column
+  auto finish_j1 = [&]() {
+#pragma unroll
+    for (int nb = 0; nb < NB; ++nb) {
+      const float s = sc[16 * nb + li];
+#pragma unroll
+      for (int g = 0; g < MC; ++g)
+#pragma unroll
+        for (int e = 0; e < 4; ++e) acc[g * NB + nb][e] = c32[g][nb][e] * s;
+    }
+  };
+  const bool direct = (a.nsplit == 1);
+  const int64_t Mpad = (int64_t)a.mtiles * mtile;
+  auto store_tile = [&](int64_t cw) {
+#pragma unroll
+    for (int g = 0; g < MC; ++g)
+#pragma unroll
+      for (int nb = 0; nb < NB; ++nb) {
+        double o[4];
+#pragma unroll
+        for (int v = 0; v < 4; ++v) o[v] = (double)acc[g * NB + nb][v];
+        pm_store_rows<4>(a, direct, Mtot, Mpad, RP, by, 16 * nb + li, cw + 16 * g + 4 * lq, o);
+      }
+  };
+  int stC = 0, S1C = S1L, jc = jl, tc = tl, jcntC = jcntL, tileC = 0, left = se - sb;
   auto compute = [&](const vT (&A)[MC][2]) {
     const int kk = KS * tc + 8 * lq;
 #pragma unroll
@@ -494,6 +563,21 @@ __device__ __forceinline__ void right_body(const PmArgs& a, int bx, int by, int 
           stage<NTM>(a, hs, lp, RP, (ib0 + stC) * a.i1blk, stage_rows(stC));
           __syncthreads();
           S1C = stage_rows(stC) / KS;
+        } else if (MT && tileC + 1 < ntile) {  // a tile done (istages == 1): store it, start the next
+          stC = 0;
+          if (J1) {
+            finish_j1();
+#pragma unroll
+            for (int g = 0; g < MC; ++g)
+#pragma unroll
+              for (int nb = 0; nb < NB; ++nb) c32[g][nb] = f4{0.f, 0.f, 0.f, 0.f};
+          }
+          store_tile((int64_t)(tile0 + tileC) * mtile + wm * 16 * MC);
+#pragma unroll
+          for (int v = 0; v < NACC; ++v)
+#pragma unroll
+            for (int e = 0; e < 4; ++e) acc[v][e] = 0.f;
+          ++tileC;
         }
       }
     }
@@ -516,48 +600,28 @@ __device__ __forceinline__ void right_body(const PmArgs& a, int bx, int by, int 
   for (int d = 0; d < D - 1; ++d)
     if (s + d < se) compute(A[d]);
 
-  if (J1) {
-#pragma unroll
-    for (int nb = 0; nb < NB; ++nb) {
-      const float s = sc[16 * nb + li];
-#pragma unroll
-      for (int g = 0; g < MC; ++g)
-#pragma unroll
-        for (int e = 0; e < 4; ++e) acc[g * NB + nb][e] = c32[g][nb][e] * s;
-    }
-  } else {
-    reduce_waves<NACC>(acc, lds_d, wk, wm, WK);
-  }
+  if (J1) finish_j1();
+  else reduce_waves<NACC>(acc, lds_d, wk, wm, WK);
   if (wk != 0) return;
-  const bool direct = (a.nsplit == 1);
-  const int64_t Mpad = (int64_t)gx * mtile;
-#pragma unroll
-  for (int g = 0; g < MC; ++g)
-#pragma unroll
-    for (int nb = 0; nb < NB; ++nb) {
-      double o[4];
-#pragma unroll
-      for (int v = 0; v < 4; ++v) o[v] = (double)acc[g * NB + nb][v];
-      pm_store_rows<4>(a, direct, Mtot, Mpad, RP, by, 16 * nb + li, cw + 16 * g + 4 * lq, o);
-    }
+  store_tile((int64_t)(tile0 + ntile - 1) * mtile + wm * 16 * MC);
 }
 
 // FAST: the shape guarantees that every vector load of every step lies inside
 // the tensor (pm16_fast), so the loads need no per-step check.
-template <int DT, int SIDE, int NB, bool J1, bool FAST>
-__device__ __forceinline__ void body(const PmArgs& a, int bx, int by, int gx) {
-  if (SIDE == 0) left_body<DT, NB, FAST>(a, bx, by, gx);
-  else right_body<DT, NB, J1, FAST>(a, bx, by, gx);
+template <int DT, int SIDE, int NB, bool J1, bool FAST, bool MT>
+__device__ __forceinline__ void body(const PmArgs& a, int bx, int by) {
+  if (SIDE == 0) left_body<DT, NB, FAST, MT>(a, bx, by);
+  else right_body<DT, NB, J1, FAST, MT>(a, bx, by);
 }
 
 // Stand-alone kernels: one work-group per (M tile, split).
-template <int DT, int SIDE, int NB, bool J1, bool FAST>
+template <int DT, int SIDE, int NB, bool J1, bool FAST, bool MT>
 __global__ __launch_bounds__(NT, 1) void pm16_kernel_std(PmArgs a) {
-  body<DT, SIDE, NB, J1, FAST>(a, blockIdx.x, blockIdx.y, gridDim.x);
+  body<DT, SIDE, NB, J1, FAST, MT>(a, blockIdx.x, blockIdx.y);
 }
 // Persistent batched form: items grp[0] + b, grp[0] + b + gridDim.x, ... below
 // grp[0] + grp[1], each one (M tile, split) work-group of a recorded launch.
-template <int DT, int SIDE, int NB, bool J1, bool FAST>
+template <int DT, int SIDE, int NB, bool J1, bool FAST, bool MT>
 __global__ __launch_bounds__(NT, 1) void pm16_kernel_items(const BItem* __restrict__ items,
                                                            const int* __restrict__ grp,
                                                            const KOp* __restrict__ ops) {
@@ -565,7 +629,7 @@ __global__ __launch_bounds__(NT, 1) void pm16_kernel_items(const BItem* __restri
   for (int i = blockIdx.x; i < n; i += gridDim.x) {
     const BItem it = items[off + i];
     const KOp& op = ops[it.op];
-    body<DT, SIDE, NB, J1, FAST>(op.u.pm, it.bx, it.by, op.gx);
+    body<DT, SIDE, NB, J1, FAST, MT>(op.u.pm, it.bx, it.by);
     __syncthreads();  // LDS is reused by the next item
   }
 }
@@ -585,34 +649,40 @@ __global__ __launch_bounds__(256) void pack_kernel_items(const BItem* __restrict
   }
 }
 
-template <int DT, int SIDE, bool J1, bool FAST>
+template <int DT, int SIDE, bool J1, bool FAST, bool MT>
 const void* pick(int nb, bool batch) {
   switch (nb) {
     case 1:
-      return batch ? (const void*)pm16_kernel_items<DT, SIDE, 1, J1, FAST>
-                   : (const void*)pm16_kernel_std<DT, SIDE, 1, J1, FAST>;
+      return batch ? (const void*)pm16_kernel_items<DT, SIDE, 1, J1, FAST, MT>
+                   : (const void*)pm16_kernel_std<DT, SIDE, 1, J1, FAST, MT>;
     case 2:
-      return batch ? (const void*)pm16_kernel_items<DT, SIDE, 2, J1, FAST>
-                   : (const void*)pm16_kernel_std<DT, SIDE, 2, J1, FAST>;
+      return batch ? (const void*)pm16_kernel_items<DT, SIDE, 2, J1, FAST, MT>
+                   : (const void*)pm16_kernel_std<DT, SIDE, 2, J1, FAST, MT>;
     case 4:
-      return batch ? (const void*)pm16_kernel_items<DT, SIDE, 4, J1, FAST>
-                   : (const void*)pm16_kernel_std<DT, SIDE, 4, J1, FAST>;
+      return batch ? (const void*)pm16_kernel_items<DT, SIDE, 4, J1, FAST, MT>
+                   : (const void*)pm16_kernel_std<DT, SIDE, 4, J1, FAST, MT>;
     default: return nullptr;
   }
 }
 
-template <int DT, bool FAST>
+template <int DT, bool FAST, bool MT>
 const void* pick_side(int side, int nb, int j1, bool batch) {
-  if (j1) return side == 1 ? pick<DT, 1, true, FAST>(nb, batch) : nullptr;
-  return side == 0 ? pick<DT, 0, false, FAST>(nb, batch) : pick<DT, 1, false, FAST>(nb, batch);
+  if (j1) return side == 1 ? pick<DT, 1, true, FAST, MT>(nb, batch) : nullptr;
+  return side == 0 ? pick<DT, 0, false, FAST, MT>(nb, batch) : pick<DT, 1, false, FAST, MT>(nb, batch);
+}
+
+template <int DT, bool MT>
+const void* pick_fast(int side, int nb, int j1, int fast, bool batch) {
+  return fast ? pick_side<DT, true, MT>(side, nb, j1, batch) : pick_side<DT, false, MT>(side, nb, j1, batch);
 }
 
 }  // namespace pm16
 
-// Kernel of (side, column blocks, J == 1 form, unchecked loads), stand-alone or batched.
-template <int DT>
-const void* pm16_kernel(int side, int nb, int j1, int fast, bool batch) {
-  return fast ? pm16::pick_side<DT, true>(side, nb, j1, batch) : pm16::pick_side<DT, false>(side, nb, j1, batch);
+// Kernel of (side, column blocks, J == 1 form, unchecked loads), stand-alone or
+// batched, in the one-tile (MT false) or several-tile form.
+template <int DT, bool MT>
+const void* pm16_kernel_form(int side, int nb, int j1, int fast, bool batch) {
+  return pm16::pick_fast<DT, MT>(side, nb, j1, fast, batch);
 }
 template <int DT>
 const void* pm16_pack_kernel(bool batch) {

@@ -6,8 +6,10 @@
 
 namespace nncpk {
 
-extern template const void* pm16_kernel<NNCP_BF16>(int, int, int, int, bool);
-extern template const void* pm16_kernel<NNCP_F16>(int, int, int, int, bool);
+extern template const void* pm16_kernel_form<NNCP_BF16, false>(int, int, int, int, bool);
+extern template const void* pm16_kernel_form<NNCP_BF16, true>(int, int, int, int, bool);
+extern template const void* pm16_kernel_form<NNCP_F16, false>(int, int, int, int, bool);
+extern template const void* pm16_kernel_form<NNCP_F16, true>(int, int, int, int, bool);
 extern template const void* pm16_pack_kernel<NNCP_BF16>(bool);
 extern template const void* pm16_pack_kernel<NNCP_F16>(bool);
 
@@ -17,9 +19,12 @@ constexpr int left_tr16(int nb) { return nb >= 4 ? 4 : 8; }
 constexpr int right_mc16(int nb) { return 4; }
 constexpr int right_mc16_j1(int nb) { return 8; }
 
-const void* kernel16(int dtype, int side, int nb, int j1, int fast, bool batch) {
-  return dtype == NNCP_BF16 ? pm16_kernel<NNCP_BF16>(side, nb, j1, fast, batch)
-                            : pm16_kernel<NNCP_F16>(side, nb, j1, fast, batch);
+const void* kernel16(int dtype, int side, int nb, int j1, int fast, int mt, bool batch) {
+  if (dtype == NNCP_BF16)
+    return mt ? pm16_kernel_form<NNCP_BF16, true>(side, nb, j1, fast, batch)
+              : pm16_kernel_form<NNCP_BF16, false>(side, nb, j1, fast, batch);
+  return mt ? pm16_kernel_form<NNCP_F16, true>(side, nb, j1, fast, batch)
+            : pm16_kernel_form<NNCP_F16, false>(side, nb, j1, fast, batch);
 }
 
 void allow_big_lds(const void* k) { pm_allow_lds(k, 160 * 1024); }
@@ -47,9 +52,11 @@ hipError_t pm_launch_16(const PmLaunch& L, const PmArgs& a, const Sink& sk) {
   PackArgs pa{a.krp.f[0], a.I1, a.I1pad, a.R, a.col0, RP, a.hpack, a.hscale};
   const int wm = a.wm;
   const bool fast = pm16_fast(L.side, a.IL, a.I1, L.nb);
-  // variant = j1*100000 + bf16*10000 + side*1000 + nb*100 + fast
-  const int variant = (L.j1 ? 100000 : 0) + (bf ? 10000 : 0) + L.side * 1000 + L.nb * 100 + (fast ? 1 : 0);
-  const void* k = kernel16(L.dtype, L.side, L.nb, L.j1, fast, false);
+  const bool mt = L.mper > 1;
+  // variant = j1*100000 + bf16*10000 + side*1000 + nb*100 + mt*10 + fast
+  const int variant =
+      (L.j1 ? 100000 : 0) + (bf ? 10000 : 0) + L.side * 1000 + L.nb * 100 + (mt ? 10 : 0) + (fast ? 1 : 0);
+  const void* k = kernel16(L.dtype, L.side, L.nb, L.j1, fast, mt, false);
   if (!k || (wm != 1 && wm != 4) || (L.j1 && wm != 4)) return hipErrorInvalidValue;
   size_t lds = L.lds_bytes;
   if (pm_16_reduce_lds(L.side, L.nb, wm) > lds) lds = pm_16_reduce_lds(L.side, L.nb, wm);
@@ -66,7 +73,7 @@ hipError_t pm_launch_16(const PmLaunch& L, const PmArgs& a, const Sink& sk) {
     KOp pm{};
     pm.kind = K_PM_16;
     pm.variant = variant;
-    pm.gx = (unsigned)L.mtiles;
+    pm.gx = (unsigned)L.mgroups;
     pm.gy = (unsigned)L.nsplit;
     pm.lds = (unsigned)lds;
     pm.u.pm = a;
@@ -80,14 +87,14 @@ hipError_t pm_launch_16(const PmLaunch& L, const PmArgs& a, const Sink& sk) {
   }
   allow_big_lds(k);
   void* args[] = {(void*)&a};
-  return hipLaunchKernel(k, dim3(L.mtiles, L.nsplit), dim3(NT), args, lds, sk.st);
+  return hipLaunchKernel(k, dim3(L.mgroups, L.nsplit), dim3(NT), args, lds, sk.st);
 }
 
 const void* pm16_batch_kernel(int variant) {
   const int j1 = variant >= 100000 ? 1 : 0;
   const int dtype = ((variant / 10000) % 10) ? NNCP_BF16 : NNCP_F16;
   const int side = (variant / 1000) % 10, nb = (variant / 100) % 10;
-  const void* k = kernel16(dtype, side, nb, j1, variant % 10, true);
+  const void* k = kernel16(dtype, side, nb, j1, variant % 10, (variant / 10) % 10, true);
   if (k) allow_big_lds(k);
   return k;
 }

@@ -43,8 +43,8 @@ constexpr int right_pf(int nb) { return 3; }
 // (li, lq) loads rows TR*li .. TR*li+TR-1 of the columns i1 = base + 4*lq + u,
 // u = 0..3; MFMA chain tt uses row TR*li + tt of every load.
 // ----------------------------------------------------------------------------
-template <int NB, int D, bool FAST>
-__device__ __forceinline__ void pm_left_f32_body(const PmArgs& a, int bx, int by, int gx) {
+template <int NB, int D, bool FAST, bool MT>
+__device__ __forceinline__ void pm_left_f32_body(const PmArgs& a, int bx, int by) {
   constexpr int RP = NB * 16;
   constexpr int TR = left_tr(NB);
   constexpr int KS = 16;
@@ -63,7 +63,11 @@ __device__ __forceinline__ void pm_left_f32_body(const PmArgs& a, int bx, int by
   const int li = lane & 15, lq = lane >> 4;
   const int64_t Mtot = a.IL, Ktot = a.IR;
   const int mtile = WM * WROWS;
-  const int64_t mw = (int64_t)bx * mtile + wm * WROWS;
+  // the group's M tiles tile0 .. tile0 + ntile - 1 (ntile > 1 only with WK == 1):
+  // one continuous stream of k-steps per wave, the loads of a tile's first steps
+  // issued while the previous tile's last steps are computed
+  const int tile0 = MT ? bx * a.mper : bx;
+  const int ntile = MT ? min(a.mper, a.mtiles - tile0) : 1;
   const int ib = by % a.n_i1blk, jb = by / a.n_i1blk;
   const int i1_0 = ib * a.i1blk;
   const int i1n = min(a.i1blk, a.I1pad - i1_0);
@@ -77,6 +81,7 @@ __device__ __forceinline__ void pm_left_f32_body(const PmArgs& a, int bx, int by
   const int S1 = i1n / KS;
   int sb, se;
   wave_range(S1 * jn, wk, WK, &sb, &se);
+  se += (ntile - 1) * S1 * jn;
 
   double acc[NACC][4];
 #pragma unroll
@@ -84,8 +89,10 @@ __device__ __forceinline__ void pm_left_f32_body(const PmArgs& a, int bx, int by
 #pragma unroll
     for (int e = 0; e < 4; ++e) acc[v][e] = 0.0;
 
-  const int64_t m = mw + TR * li;
-  const int64_t mload = m < Mtot ? m : 0;  // a row group wholly past the output reads row 0
+  // lane's first row in the tile being loaded; a row group wholly past the
+  // output reads row 0
+  int64_t m = (int64_t)tile0 * mtile + wm * WROWS + TR * li;
+  int64_t mload = m < Mtot ? m : 0;
   const int ilim = a.I1 - i1_0;            // lane i1 offsets >= ilim are padding
   const float* zeros = (const float*)a.zeros;
   int64_t lane_col[4];                     // lane part of the address of column (colbase + 4*lq + u)
@@ -100,10 +107,11 @@ __device__ __forceinline__ void pm_left_f32_body(const PmArgs& a, int bx, int by
   // starts at a j rotated by its M tile, so groups that share a split do not all
   // request the same addresses modulo the column stride at the same time.
   const int jrot = (WK == 1 && jn > 1) ? (int)(((unsigned)bx * 5u) % (unsigned)jn) : 0;
-  int jl = sb / S1 + jrot, tl = sb - (sb / S1) * S1;
+  int jcntL = sb / S1, tileL = 0;
+  int jl = jcntL + jrot, tl = sb - jcntL * S1;
   if (jl >= jn) jl -= jn;  // an empty range (sb == S1 * jn) starts at the block's first j
-  // The cursor stays inside the group's j block (it wraps), so loads of steps
-  // past the wave's range read valid memory and are simply not used.
+  // The cursor stays inside the group's j block and tiles (it wraps), so loads
+  // of steps past the wave's range read valid memory and are simply not used.
   auto load = [&](vT (&A)[4]) {
     const int64_t colbase = (int64_t)a.I1 * (j0 + jl) + i1_0 + KS * tl;
     const float* base = X + Mtot * colbase;
@@ -126,7 +134,28 @@ __device__ __forceinline__ void pm_left_f32_body(const PmArgs& a, int bx, int by
     if (++tl == S1) {
       tl = 0;
       if (++jl == jn) jl = 0;
+      if (MT && ++jcntL == jn) {
+        jcntL = 0;
+        if (++tileL == ntile) tileL = 0;
+        m = (int64_t)(tile0 + tileL) * mtile + wm * WROWS + TR * li;
+        mload = m < Mtot ? m : 0;
+      }
     }
+  };
+
+  // acc[tt*NB+nb][v]: row mw + TR*(4*lq + v) + tt, rank column 16nb + li.
+  const bool direct = (a.nsplit == 1);
+  const int64_t Mpad = (int64_t)a.mtiles * mtile;
+  auto store_tile = [&](int64_t mw) {
+#pragma unroll
+    for (int nb = 0; nb < NB; ++nb)
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        double o[TR];
+#pragma unroll
+        for (int tt = 0; tt < TR; ++tt) o[tt] = acc[tt * NB + nb][v];
+        pm_store_rows<TR>(a, direct, Mtot, Mpad, RP, by, 16 * nb + li, mw + TR * (4 * lq + v), o);
+      }
   };
 
   // FP32 partial sums (one 16x16 block per (tt, nb)) live for `fold` k-steps and
@@ -136,7 +165,7 @@ __device__ __forceinline__ void pm_left_f32_body(const PmArgs& a, int bx, int by
   for (int tt = 0; tt < TR; ++tt)
 #pragma unroll
     for (int nb = 0; nb < NB; ++nb) c32[tt][nb] = f4{0.f, 0.f, 0.f, 0.f};
-  int jc = jl, tc = tl, fc = tl % a.fold, sc_left = se - sb;
+  int jc = jl, tc = tl, jcntC = jcntL, tileC = 0, fc = tl % a.fold, sc_left = se - sb;
   auto compute = [&](const vT (&A)[4]) {
     const int kk = KS * tc + 4 * lq;
     f4 B[NB];
@@ -169,6 +198,17 @@ __device__ __forceinline__ void pm_left_f32_body(const PmArgs& a, int bx, int by
     if (++tc == S1) {
       tc = 0;
       if (++jc == jn) jc = 0;
+      if (MT && ++jcntC == jn) {
+        jcntC = 0;
+        if (tileC + 1 < ntile) {  // a tile done (its last j folded above): store it, start the next
+          store_tile((int64_t)(tile0 + tileC) * mtile + wm * WROWS);
+#pragma unroll
+          for (int v = 0; v < NACC; ++v)
+#pragma unroll
+            for (int e = 0; e < 4; ++e) acc[v][e] = 0.0;
+          ++tileC;
+        }
+      }
     }
   };
 
@@ -196,19 +236,7 @@ __device__ __forceinline__ void pm_left_f32_body(const PmArgs& a, int bx, int by
   __syncthreads();  // LDS is reused by the cross-wave reduction
   wave_reduce_k<NACC>(acc, lds_d, wk, wm, WK);
   if (wk != 0) return;
-
-  // acc[tt*NB+nb][v]: row mw + TR*(4*lq + v) + tt, rank column 16nb + li.
-  const bool direct = (a.nsplit == 1);
-  const int64_t Mpad = (int64_t)gx * mtile;
-#pragma unroll
-  for (int nb = 0; nb < NB; ++nb)
-#pragma unroll
-    for (int v = 0; v < 4; ++v) {
-      double o[TR];
-#pragma unroll
-      for (int tt = 0; tt < TR; ++tt) o[tt] = acc[tt * NB + nb][v];
-      pm_store_rows<TR>(a, direct, Mtot, Mpad, RP, by, 16 * nb + li, mw + TR * (4 * lq + v), o);
-    }
+  store_tile((int64_t)(tile0 + ntile - 1) * mtile + wm * WROWS);
 }
 
 // ----------------------------------------------------------------------------
@@ -219,8 +247,8 @@ __device__ __forceinline__ void pm_left_f32_body(const PmArgs& a, int bx, int by
 // `istages` i1 blocks (j inside each), restaging LDS between them; istages > 1
 // only with every wave on its own columns (WM = 4).
 // ----------------------------------------------------------------------------
-template <int NB, int D, bool FAST>
-__device__ __forceinline__ void pm_right_f32_body(const PmArgs& a, int bx, int by, int gx) {
+template <int NB, int D, bool FAST, bool MT>
+__device__ __forceinline__ void pm_right_f32_body(const PmArgs& a, int bx, int by) {
   constexpr int RP = NB * 16;
   constexpr int MC = right_mc(NB);
   constexpr int KS = 32;
@@ -238,7 +266,10 @@ __device__ __forceinline__ void pm_right_f32_body(const PmArgs& a, int bx, int b
   const int li = lane & 15, lq = lane >> 4;
   const int64_t Mtot = a.IR, Ktot = a.IL;
   const int mtile = WM * 16 * MC;
-  const int64_t cw = (int64_t)bx * mtile + wm * 16 * MC;
+  // the group's M tiles tile0 .. tile0 + ntile - 1 (ntile > 1 only with WK == 1
+  // and istages == 1), streamed as one sequence of k-steps per wave
+  const int tile0 = MT ? bx * a.mper : bx;
+  const int ntile = MT ? min(a.mper, a.mtiles - tile0) : 1;
   const int n_i1grp = a.n_i1blk / a.istages;
   const int ib0 = (by % n_i1grp) * a.istages, jb = by / n_i1grp;
   const int64_t j0 = (int64_t)jb * a.jblk;
@@ -255,6 +286,7 @@ __device__ __forceinline__ void pm_right_f32_body(const PmArgs& a, int bx, int b
   for (int st = 0; st < a.istages; ++st) total += (stage_rows(st) / KS) * jn;
   int sb, se;
   wave_range(total, wk, WK, &sb, &se);  // istages > 1 implies WK == 1: the whole range
+  se += (ntile - 1) * total;
 
   double acc[NACC][4];
 #pragma unroll
@@ -262,25 +294,31 @@ __device__ __forceinline__ void pm_right_f32_body(const PmArgs& a, int bx, int b
 #pragma unroll
     for (int e = 0; e < 4; ++e) acc[v][e] = 0.0;
 
-  const float* colp[MC];
-#pragma unroll
-  for (int g = 0; g < MC; ++g) {
-    const int64_t c = cw + 16 * g + li;
-    colp[g] = X + Ktot * (c < Mtot ? c : 0) + 4 * lq;  // columns past the output read column 0
-  }
+  // Columns of the tile being loaded (columns past the output read column 0).
   // The vector loads of a step read elements up to Ktot * cmax + lbase + KS - 1
   // (cmax: the wave's last column that is read, lane offsets up to KS - 1): all
   // of them lie inside the tensor while lbase <= vec_lim. Only the steps that
   // run past the end of a column near the tensor's end fail this.
-  const int64_t cmax = min(cw + 16 * MC - 1, Mtot - 1);
-  const int64_t vec_lim = Mtot * Ktot - Ktot * cmax - KS;  // wave-uniform
+  const float* colp[MC];
+  int64_t vec_lim;
+  auto set_tile = [&](int t) {
+    const int64_t cw = (int64_t)(tile0 + t) * mtile + wm * 16 * MC;
+#pragma unroll
+    for (int g = 0; g < MC; ++g) {
+      const int64_t c = cw + 16 * g + li;
+      colp[g] = X + Ktot * (c < Mtot ? c : 0) + 4 * lq;
+    }
+    const int64_t cmax = min(cw + 16 * MC - 1, Mtot - 1);
+    vec_lim = Mtot * Ktot - Ktot * cmax - KS;  // wave-uniform
+  };
+  set_tile(0);
   const float* zeros = (const float*)a.zeros;
 
   // cursor (stage, j, t): t over the stage's k-steps, j over the block (rotated
   // start with one wave along K), stages in order. The load cursor runs D steps
   // ahead and wraps to the start after the last step, so it stays in bounds.
   const int jrot = (WK == 1 && jn > 1) ? (int)(((unsigned)bx * 5u) % (unsigned)jn) : 0;
-  int stL = 0, S1L = stage_rows(0) / KS;
+  int stL = 0, S1L = stage_rows(0) / KS, tileL = 0;
   int jcntL = sb / S1L;  // sb > 0 only when istages == 1
   int tl = sb - jcntL * S1L;
   int jl = jcntL + jrot;
@@ -315,10 +353,31 @@ __device__ __forceinline__ void pm_right_f32_body(const PmArgs& a, int bx, int b
       if (++jl == jn) jl = 0;
       if (++jcntL == jn) {
         jcntL = 0;
-        if (++stL == a.istages) stL = 0;
+        if (++stL == a.istages) {
+          stL = 0;
+          if (MT) {
+            if (++tileL == ntile) tileL = 0;
+            set_tile(tileL);
+          }
+        }
         S1L = stage_rows(stL) / KS;
       }
     }
+  };
+
+  // acc[g*NB+nb][v]: column c = cw + 16g + 4*lq + v, rank column 16nb + li.
+  const bool direct = (a.nsplit == 1);
+  const int64_t Mpad = (int64_t)a.mtiles * mtile;
+  auto store_tile = [&](int64_t cw) {
+#pragma unroll
+    for (int g = 0; g < MC; ++g)
+#pragma unroll
+      for (int nb = 0; nb < NB; ++nb) {
+        double o[4];
+#pragma unroll
+        for (int v = 0; v < 4; ++v) o[v] = acc[g * NB + nb][v];
+        pm_store_rows<4>(a, direct, Mtot, Mpad, RP, by, 16 * nb + li, cw + 16 * g + 4 * lq, o);
+      }
   };
 
   f4 c32[MC][NB];
@@ -326,7 +385,7 @@ __device__ __forceinline__ void pm_right_f32_body(const PmArgs& a, int bx, int b
   for (int g = 0; g < MC; ++g)
 #pragma unroll
     for (int nb = 0; nb < NB; ++nb) c32[g][nb] = f4{0.f, 0.f, 0.f, 0.f};
-  int stC = 0, S1C = S1L, jc = jl, tc = tl, jcntC = jcntL, fc = tl % a.fold, sc_left = se - sb;
+  int stC = 0, S1C = S1L, jc = jl, tc = tl, jcntC = jcntL, tileC = 0, fc = tl % a.fold, sc_left = se - sb;
   auto compute = [&](const vT (&A)[MC][2]) {
     const int kk = KS * tc + 4 * lq;
     f4 B[2][NB];
@@ -370,6 +429,14 @@ __device__ __forceinline__ void pm_right_f32_body(const PmArgs& a, int bx, int b
           pm_stage_h1(a, hs, hp, RP, (ib0 + stC) * a.i1blk, stage_rows(stC));
           __syncthreads();
           S1C = stage_rows(stC) / KS;
+        } else if (MT && tileC + 1 < ntile) {  // a tile done (istages == 1): store it, start the next
+          stC = 0;
+          store_tile((int64_t)(tile0 + tileC) * mtile + wm * 16 * MC);
+#pragma unroll
+          for (int v = 0; v < NACC; ++v)
+#pragma unroll
+            for (int e = 0; e < 4; ++e) acc[v][e] = 0.0;
+          ++tileC;
         }
       }
     }
@@ -395,63 +462,58 @@ __device__ __forceinline__ void pm_right_f32_body(const PmArgs& a, int bx, int b
   __syncthreads();
   wave_reduce_k<NACC>(acc, lds_d, wk, wm, WK);
   if (wk != 0) return;
-
-  // acc[g*NB+nb][v]: column c = cw + 16g + 4*lq + v, rank column 16nb + li.
-  const bool direct = (a.nsplit == 1);
-  const int64_t Mpad = (int64_t)gx * mtile;
-#pragma unroll
-  for (int g = 0; g < MC; ++g)
-#pragma unroll
-    for (int nb = 0; nb < NB; ++nb) {
-      double o[4];
-#pragma unroll
-      for (int v = 0; v < 4; ++v) o[v] = acc[g * NB + nb][v];
-      pm_store_rows<4>(a, direct, Mtot, Mpad, RP, by, 16 * nb + li, cw + 16 * g + 4 * lq, o);
-    }
+  store_tile((int64_t)(tile0 + ntile - 1) * mtile + wm * 16 * MC);
 }
 
 // FAST: the shape guarantees that every vector load of every step lies inside
-// the tensor (pm_f32_fast), so the loads need no per-step check.
-template <int NB, bool FAST>
-__device__ __forceinline__ void pm_f32_body(int side, const PmArgs& a, int bx, int by, int gx) {
-  if (side == 0) pm_left_f32_body<NB, left_pf(NB), FAST>(a, bx, by, gx);
-  else pm_right_f32_body<NB, right_pf(NB), FAST>(a, bx, by, gx);
+// the tensor (pm_f32_fast), so the loads need no per-step check. MT: a group
+// streams several M tiles (a separate form, so that the one-tile kernels keep
+// their register budget).
+template <int NB, bool FAST, bool MT>
+__device__ __forceinline__ void pm_f32_body(int side, const PmArgs& a, int bx, int by) {
+  if (side == 0) pm_left_f32_body<NB, left_pf(NB), FAST, MT>(a, bx, by);
+  else pm_right_f32_body<NB, right_pf(NB), FAST, MT>(a, bx, by);
 }
 
-// Stand-alone kernels: one work-group per (M tile, split).
-template <int SIDE, int NB, bool FAST>
+// Stand-alone kernels: one work-group per (M tile group, split).
+template <int SIDE, int NB, bool FAST, bool MT>
 __global__ __launch_bounds__(NT, 2) void pm_f32(PmArgs a) {
-  pm_f32_body<NB, FAST>(SIDE, a, blockIdx.x, blockIdx.y, gridDim.x);
+  pm_f32_body<NB, FAST, MT>(SIDE, a, blockIdx.x, blockIdx.y);
 }
 
 // Persistent batched form of the same kernel: work-group b takes the items
 // grp[0] + b, grp[0] + b + gridDim.x, ... below grp[0] + grp[1]; each item is one
-// (M tile, split) work-group of a recorded stand-alone launch of this variant.
-template <int SIDE, int NB, bool FAST>
+// (M tile group, split) work-group of a recorded stand-alone launch of this variant.
+template <int SIDE, int NB, bool FAST, bool MT>
 __global__ __launch_bounds__(NT, 2) void pm_f32_items(const BItem* __restrict__ items, const int* __restrict__ grp,
                                                       const KOp* __restrict__ ops) {
   const int off = grp[0], n = grp[1];
   for (int i = blockIdx.x; i < n; i += gridDim.x) {
     const BItem it = items[off + i];
     const KOp& op = ops[it.op];
-    pm_f32_body<NB, FAST>(SIDE, op.u.pm, it.bx, it.by, op.gx);
+    pm_f32_body<NB, FAST, MT>(SIDE, op.u.pm, it.bx, it.by);
     __syncthreads();  // LDS is reused by the next item
   }
 }
 
-template <int SIDE, bool FAST>
+template <int SIDE, bool FAST, bool MT>
 const void* pick(int nb, bool batch) {
   switch (nb) {
-    case 1: return batch ? (const void*)pm_f32_items<SIDE, 1, FAST> : (const void*)pm_f32<SIDE, 1, FAST>;
-    case 2: return batch ? (const void*)pm_f32_items<SIDE, 2, FAST> : (const void*)pm_f32<SIDE, 2, FAST>;
-    case 4: return batch ? (const void*)pm_f32_items<SIDE, 4, FAST> : (const void*)pm_f32<SIDE, 4, FAST>;
+    case 1: return batch ? (const void*)pm_f32_items<SIDE, 1, FAST, MT> : (const void*)pm_f32<SIDE, 1, FAST, MT>;
+    case 2: return batch ? (const void*)pm_f32_items<SIDE, 2, FAST, MT> : (const void*)pm_f32<SIDE, 2, FAST, MT>;
+    case 4: return batch ? (const void*)pm_f32_items<SIDE, 4, FAST, MT> : (const void*)pm_f32<SIDE, 4, FAST, MT>;
     default: return nullptr;
   }
 }
 
-const void* kernel_for(int side, int nb, bool fast, bool batch) {
-  if (side == 0) return fast ? pick<0, true>(nb, batch) : pick<0, false>(nb, batch);
-  return fast ? pick<1, true>(nb, batch) : pick<1, false>(nb, batch);
+template <int SIDE, bool MT>
+const void* pick_fast(int nb, bool fast, bool batch) {
+  return fast ? pick<SIDE, true, MT>(nb, batch) : pick<SIDE, false, MT>(nb, batch);
+}
+
+const void* kernel_for(int side, int nb, bool fast, bool mt, bool batch) {
+  if (side == 0) return mt ? pick_fast<0, true>(nb, fast, batch) : pick_fast<0, false>(nb, fast, batch);
+  return mt ? pick_fast<1, true>(nb, fast, batch) : pick_fast<1, false>(nb, fast, batch);
 }
 
 size_t reduce_lds(int side, int nb, int wm) {
@@ -477,9 +539,10 @@ bool pm_f32_fast(int side, int64_t IL, int I1, int nb) {
 hipError_t pm_launch_f32(const PmLaunch& L, const PmArgs& a, const Sink& sk) {
   const int wm = a.wm;
   const bool fast = pm_f32_fast(L.side, a.IL, a.I1, L.nb);
-  // variant = side*1000 + nb*100 + fast
-  const int variant = L.side * 1000 + L.nb * 100 + (fast ? 1 : 0);
-  const void* k = kernel_for(L.side, L.nb, fast, false);
+  const bool mt = L.mper > 1;
+  // variant = side*1000 + nb*100 + mt*10 + fast
+  const int variant = L.side * 1000 + L.nb * 100 + (mt ? 10 : 0) + (fast ? 1 : 0);
+  const void* k = kernel_for(L.side, L.nb, fast, mt, false);
   if (!k || (wm != 1 && wm != 4)) return hipErrorInvalidValue;
   size_t lds = L.lds_bytes;
   if (reduce_lds(L.side, L.nb, wm) > lds) lds = reduce_lds(L.side, L.nb, wm);
@@ -488,7 +551,7 @@ hipError_t pm_launch_f32(const PmLaunch& L, const PmArgs& a, const Sink& sk) {
     KOp op{};
     op.kind = K_PM_F32;
     op.variant = variant;
-    op.gx = (unsigned)L.mtiles;
+    op.gx = (unsigned)L.mgroups;
     op.gy = (unsigned)L.nsplit;
     op.lds = (unsigned)lds;
     op.u.pm = a;
@@ -496,12 +559,12 @@ hipError_t pm_launch_f32(const PmLaunch& L, const PmArgs& a, const Sink& sk) {
   }
   if (lds > 64 * 1024) pm_allow_lds(k, 160 * 1024);
   void* args[] = {(void*)&a};
-  return hipLaunchKernel(k, dim3(L.mtiles, L.nsplit), dim3(NT), args, lds, sk.st);
+  return hipLaunchKernel(k, dim3(L.mgroups, L.nsplit), dim3(NT), args, lds, sk.st);
 }
 
 const void* pm_f32_batch_kernel(int variant) {
   const int side = variant / 1000, nb = (variant / 100) % 10;
-  const void* k = kernel_for(side, nb, variant % 10 != 0, true);
+  const void* k = kernel_for(side, nb, variant % 10 != 0, (variant / 10) % 10 != 0, true);
   if (k) pm_allow_lds(k, 160 * 1024);
   return k;
 }

@@ -51,12 +51,14 @@ static size_t lds_for(int dtype, int RP, int i1blk, int jblk) {
 }
 
 // Most j values whose per-(j, column) scales fit in LDS beside an i1 block of
-// i1blk rows (at most 64): a group never asks for more than kPmMaxLds.
-static int jblk_cap(int dtype, int RP, int i1blk) {
+// i1blk rows, at most `lim`: a 16-bit group never asks for more than kPmMaxLds,
+// an FP32 group for more than half of it (two FP32 groups share a CU).
+static int jblk_cap(int dtype, int RP, int i1blk, int lim = 64) {
+  const size_t maxl = dtype == NNCP_F32 ? kPmMaxLds / 2 : kPmMaxLds;
   const size_t base = lds_for(dtype, RP, i1blk, 0);
   const size_t per = lds_for(dtype, RP, i1blk, 1) - base;
-  const int64_t cap = base >= kPmMaxLds ? 0 : (int64_t)((kPmMaxLds - base) / per);
-  return cap < 64 ? (int)cap : 64;
+  const int64_t cap = base >= maxl ? 0 : (int64_t)((maxl - base) / per);
+  return cap < lim ? (int)cap : lim;
 }
 
 PmLaunch pm_plan(int side, int dtype, int64_t IL, int64_t IR, int I1, int R, int wg_kib) {
@@ -101,8 +103,30 @@ PmLaunch pm_plan(int side, int dtype, int64_t IL, int64_t IR, int I1, int R, int
   if (side == 1 && wm == 4 && L.n_i1blk > 1 && L.mtiles >= target) L.istages = L.n_i1blk;
   const int n_i1grp = L.n_i1blk / L.istages;
 
+  // Many short tiles (one i1 block, at least as many four-wave tiles as the
+  // target group count): four waves along M, and each group streams several
+  // consecutive tiles, so a wave keeps its loads in flight across tile
+  // boundaries and the group stages H_1 and the scales once for all of them,
+  // instead of a group per tile whose few k-steps per wave are mostly load
+  // latency.
+  L.mper = 1;
+  {
+    const int64_t t4 = cdiv(Mtot, 4 * wave_rows);
+    if (!L.j1 && L.n_i1blk == 1 && t4 >= target) {
+      wm = 4;
+      L.mtile = 4 * wave_rows;
+      L.mtiles = (int)t4;
+      L.mper = (int)cdiv(t4, target);
+    } else if (L.j1 && L.istages == 1 && L.mtiles >= target && L.nb < 4) {
+      // (the J == 1 kernel at four column blocks has no registers to spare for it)
+      L.mper = (int)cdiv(L.mtiles, target);
+    }
+  }
+  L.wm = wm;
+  L.mgroups = (int)cdiv(L.mtiles, L.mper);
+
   const int64_t steps_per_j = L.i1blk / ks;
-  int64_t want_splits = target / L.mtiles;
+  int64_t want_splits = target / L.mgroups;
   if (want_splits < 1) want_splits = 1;
   // never more groups than the target: a second partial round of groups (one
   // group fills a CU's LDS) would double the kernel's time for a few groups
@@ -112,7 +136,18 @@ PmLaunch pm_plan(int side, int dtype, int64_t IL, int64_t IR, int I1, int R, int
   const int64_t min_j = cdiv(8 * (4 / wm), steps_per_j);
   int64_t jblk = cdiv(L.J, n_jblk < 1 ? 1 : n_jblk);
   if (jblk < min_j) jblk = min_j;
-  if (jblk > jblk_cap(dtype, RP, L.i1blk)) jblk = jblk_cap(dtype, RP, L.i1blk);
+  if (jblk > jblk_cap(dtype, RP, L.i1blk)) {
+    // at most 64 j per group (the scales are a prologue of jblk * RP products),
+    // unless that leaves a few groups beyond the target -- a second, mostly
+    // idle round for a 16-bit kernel (one group per CU): then up to 128
+    const int64_t over = L.mgroups * n_i1grp * cdiv(L.J, jblk_cap(dtype, RP, L.i1blk));
+    const int64_t room = target / (L.mgroups * n_i1grp);
+    if (dtype != NNCP_F32 && over > target && over < 2 * target && room >= 1 &&
+        cdiv(L.J, room) <= jblk_cap(dtype, RP, L.i1blk, 128))
+      jblk = cdiv(L.J, room);
+    else
+      jblk = jblk_cap(dtype, RP, L.i1blk);
+  }
   if (jblk > L.J) jblk = L.J;
   if (jblk < 1) jblk = 1;
   L.jblk = (int)jblk;
@@ -152,6 +187,8 @@ void pm_fill_args(const PmLaunch& L, PmArgs& a) {
   a.nsplit = L.nsplit;
   a.istages = L.istages;
   a.wm = L.wm;
+  a.mtiles = L.mtiles;
+  a.mper = L.mper;
 }
 
 size_t pm_variant_max_lds(int kind, int variant) {
@@ -162,7 +199,7 @@ size_t pm_variant_max_lds(int kind, int variant) {
   const int ks = f32 ? pm_f32_kstep(side) : pm_16_kstep(side);
   size_t lds = 0;
   for (int rows = ks; rows <= lds_rows(dtype, RP, ks); rows += ks) {
-    const size_t b = lds_for(dtype, RP, rows, jblk_cap(dtype, RP, rows));
+    const size_t b = lds_for(dtype, RP, rows, jblk_cap(dtype, RP, rows, f32 ? 64 : 128));
     if (b > lds) lds = b;
   }
   const size_t red = f32 ? pm_f32_reduce_lds(side, nb, 1) : pm_16_reduce_lds(side, nb, 1);

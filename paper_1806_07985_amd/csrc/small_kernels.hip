@@ -1108,8 +1108,12 @@ __global__ __launch_bounds__(NT) void small_batch_kernel(const BItem* __restrict
   const int off = grp[0], n = grp[1];
   for (int i = blockIdx.x; i < n; i += gridDim.x) {
     const BItem it = items[off + i];
-    small_op(ops[it.op], it.bx, it.by);
-    __syncthreads();
+    const KOp& op = ops[it.op];
+    const unsigned b0 = (unsigned)it.bx * op.coarse, b1 = min(b0 + op.coarse, op.gx);
+    for (unsigned b = b0; b < b1; ++b) {
+      small_op(op, (int)b, it.by);
+      __syncthreads();  // static LDS is reused by the next work-group's share
+    }
   }
 }
 
@@ -1227,8 +1231,11 @@ hipError_t mttv_trail_launch(const MttvArgs& a, const Sink& sk) {
 hipError_t mttv_lead_launch(const MttvArgs& a, const Sink& sk) {
   const int64_t outputs = a.J * a.R;
   if (outputs <= 0) return hipSuccess;
+  // lanes per output: about 8 elements of the contracted range per lane (at
+  // least 4 lanes, at most a wave), so that short ranges still give each
+  // work-group many outputs and each lane several independent loads
   int gs = 4;
-  while (gs < 64 && gs < a.Ia) gs <<= 1;
+  while (gs < 64 && gs * 8 < a.Ia) gs <<= 1;
   const unsigned blocks = (unsigned)((outputs * gs + NT - 1) / NT);
   const void* k = nullptr;
 #define NNCP_LEAD(GSV) \

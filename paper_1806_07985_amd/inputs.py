@@ -1,9 +1,12 @@
 """Seeded synthetic workloads for NNCP.
 
 This module only draws random numbers and assembles test tensors. It holds
-none of the decomposition's arithmetic (no MTTKRP, no Gram matrices, no
-factor updates, no fit), so both the FP64 oracle and the GPU path can take
-their inputs from it without sharing any of the method.
+none of the decomposition's arithmetic (no MTTKRP, no factor updates, no
+fit), so both the FP64 oracle and the GPU path can take their inputs from it
+without sharing any of the method. The one norm it computes is the noise
+scale of a generated tensor (the clean part's Frobenius norm; for the
+slab-wise generator by its closed form over the factors' Gram matrices), a
+property of the input, not a step either side takes from here.
 
 Conventions used throughout the package:
 

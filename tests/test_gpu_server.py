@@ -36,6 +36,13 @@ def test_served_jobs_equal_alone_and_oracle(gpu_lib):
     import torch
     from paper_1806_07985_amd import native
     srv = native.Server(8 << 30, max_active=4)
+    # a long job admitted first keeps the batch running while the others arrive,
+    # so jobs share ticks whatever the speed of the tick (it is checked against
+    # the same job alone only)
+    anchor_dims, anchor_R, anchor_iters = (32, 30, 28), 8, 3000
+    Xa, _ = _host_tensor(anchor_dims, anchor_R, "f32", 699)
+    Ha0 = [h.astype(np.float32) for h in inputs.init_factors(anchor_dims, anchor_R, seed=799)]
+    anchor = srv.submit(Xa, anchor_dims, anchor_R, Ha0, anchor_iters)
     specs, ids = [], []
     for k, (dims, R, dt, upd, iters) in enumerate(JOBS):
         Xh, X64 = _host_tensor(dims, R, dt, 700 + k)
@@ -44,16 +51,27 @@ def test_served_jobs_equal_alone_and_oracle(gpu_lib):
         ids.append(srv.submit(Xh, dims, R, H0, iters, update=upd))
         print(f"case served submit {dims} R={R} {dt} {upd} iters={iters}", flush=True)
         time.sleep(0.002 * k)                   # staggered arrivals
-    for i in ids:
+    for i in ids + [anchor]:
         assert srv.wait(i, 60)
     res = [srv.poll(i) for i in ids]
+    ra = srv.poll(anchor)
     st = srv.stats()
     print(f"server stats {st}", flush=True)
     # jobs ran together (continuous batching), within the slot limit
-    assert 2 <= st["peak_active"] <= 4 and st["completed"] == len(JOBS)
+    assert 2 <= st["peak_active"] <= 4 and st["completed"] == len(JOBS) + 1
     assert all(r["submit_s"] <= r["admit_s"] <= r["start_s"] <= r["done_s"] for r in res)
+    assert sum(1 for r in res if r["start_s"] < ra["done_s"]) >= 1   # someone joined the running anchor
     outs = [srv.fetch(i) for i in ids]
+    out_a = srv.fetch(anchor)
     srv.close()
+    Hd = [native.factor_to_device(h) for h in Ha0]
+    plan = native.Plan(Xa.cuda(), list(anchor_dims), anchor_R, Hd)
+    plan.run(anchor_iters)
+    lam_a = plan.finish()
+    plan.close()
+    assert ra["status"] == 0 and ra["iters_done"] == anchor_iters
+    assert all(np.array_equal(native.factor_to_host(h), hs) for h, hs in zip(Hd, out_a["H"]))
+    assert np.array_equal(lam_a, out_a["lam"])
     for k, ((dims, R, dt, upd, iters), (Xh, X64, H0), r, out) in enumerate(zip(JOBS, specs, res, outs)):
         assert r["status"] == 0 and r["iters_done"] == iters
         # the same job alone
