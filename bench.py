@@ -174,7 +174,7 @@ def _lowprec_study(dev, iters, seconds_note=None):
     return out
 
 
-def _batch_study(dev, n_jobs, iters):
+def _batch_study(dev, n_jobs, iters, wg_kib=0):
     """The batch workload: n_jobs 3-way FP32 tensors, each dim U[32, 256], planted
     rank R in {8, 16, 32} + 1% noise, NNCP at that R, HALS, `iters` outer
     iterations. All jobs advance together (one persistent work-list launch per
@@ -196,7 +196,7 @@ def _batch_study(dev, n_jobs, iters):
         out = []
         for j in jobs:
             H = [native.factor_to_device(h, device=dev) for h in j["H0"]]
-            out.append((native.Plan(j["X"], list(j["dims"]), j["R"], H, graph=graph), H))
+            out.append((native.Plan(j["X"], list(j["dims"]), j["R"], H, graph=graph, pm_wg_kib=wg_kib), H))
         return out
 
     mixed = plans(graph=False)
@@ -410,6 +410,8 @@ def main(argv=None):
     ap.add_argument("--no-workloads", action="store_true", help="skip the 1024^3 and 64^5 workloads")
     ap.add_argument("--batch-jobs", type=int, default=256)
     ap.add_argument("--batch-iters", type=int, default=30)
+    ap.add_argument("--batch-wg-kib", type=int, default=0,
+                    help="partial-MTTKRP tensor KiB per work-group of the batch jobs' plans (0: the library default)")
     ap.add_argument("--no-serve", action="store_true", help="skip the serving-stream study")
     ap.add_argument("--serve-pool", type=int, default=16)
     ap.add_argument("--serve-sat-jobs", type=int, default=200)
@@ -573,7 +575,7 @@ def main(argv=None):
         out["workloads"] = _workloads_study(dev, 20)
         note("workloads study")
     if not args.no_batch:
-        out["batch"] = _batch_study(dev, args.batch_jobs, args.batch_iters)
+        out["batch"] = _batch_study(dev, args.batch_jobs, args.batch_iters, args.batch_wg_kib)
         note("batch study")
     if not args.no_serve:
         loads = [float(x) for x in args.serve_loads.split(",") if x]
