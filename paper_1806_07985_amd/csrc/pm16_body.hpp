@@ -249,12 +249,18 @@ __device__ __forceinline__ void left_body(const PmArgs& a, int bx, int by) {
     } else {
 #pragma unroll
       for (int e = 0; e < 8; ++e) {
+        // per lane: the whole row group of a real column in one vector load,
+        // else element by element (rows past the output, padded i1: zero)
         const bool kv = (KS * tl + 8 * lq + e) < ilim;
         vT v;
+        if (kv && m + TR <= Mtot) {
+          v = *(const vT*)(base + Mtot * e + m);
+        } else {
 #pragma unroll
-        for (int t = 0; t < TR; ++t) {
-          const unsigned short* p = (kv && m + t < Mtot) ? base + Mtot * e + m + t : zeros;
-          v[t] = *p;
+          for (int t = 0; t < TR; ++t) {
+            const unsigned short* p = (kv && m + t < Mtot) ? base + Mtot * e + m + t : zeros;
+            v[t] = *p;
+          }
         }
         A[e] = v;
       }
@@ -464,11 +470,17 @@ __device__ __forceinline__ void right_body(const PmArgs& a, int bx, int by) {
         const int off = KS * tl + 32 * h + 8 * lq;
 #pragma unroll
         for (int g = 0; g < MC; ++g) {
+          // per lane: eight real k in one vector load, else element by element
+          // (padded i1 reads zero)
           vT v;
+          if (off + 8 <= ilimL) {
+            v = *(const vT*)(colp[g] + lbase + 32 * h);
+          } else {
 #pragma unroll
-          for (int e = 0; e < 8; ++e) {
-            const unsigned short* p = (off + e < ilimL) ? colp[g] + lbase + 32 * h + e : zeros;
-            v[e] = *p;
+            for (int e = 0; e < 8; ++e) {
+              const unsigned short* p = (off + e < ilimL) ? colp[g] + lbase + 32 * h + e : zeros;
+              v[e] = *p;
+            }
           }
           A[g][h] = v;
         }
@@ -659,8 +671,12 @@ const void* pick(int nb, bool batch) {
       return batch ? (const void*)pm16_kernel_items<DT, SIDE, 2, J1, FAST, MT>
                    : (const void*)pm16_kernel_std<DT, SIDE, 2, J1, FAST, MT>;
     case 4:
-      return batch ? (const void*)pm16_kernel_items<DT, SIDE, 4, J1, FAST, MT>
-                   : (const void*)pm16_kernel_std<DT, SIDE, 4, J1, FAST, MT>;
+      if constexpr (J1 && MT) {
+        return nullptr;  // not planned: the J == 1 kernel at four column blocks has no registers to spare
+      } else {
+        return batch ? (const void*)pm16_kernel_items<DT, SIDE, 4, J1, FAST, MT>
+                     : (const void*)pm16_kernel_std<DT, SIDE, 4, J1, FAST, MT>;
+      }
     default: return nullptr;
   }
 }

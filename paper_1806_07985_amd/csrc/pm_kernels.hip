@@ -121,12 +121,18 @@ __device__ __forceinline__ void pm_left_f32_body(const PmArgs& a, int bx, int by
     } else {
 #pragma unroll
       for (int u = 0; u < 4; ++u) {
+        // per lane: the whole row group of a real column in one vector load,
+        // else element by element (rows past the output, padded i1: zero)
         const bool kv = (KS * tl + 4 * lq + u) < ilim;
         vT v;
+        if (kv && m + TR <= Mtot) {
+          v = *(const vT*)(base + lane_col[u] + m);
+        } else {
 #pragma unroll
-        for (int e = 0; e < TR; ++e) {
-          const float* p = (kv && m + e < Mtot) ? base + lane_col[u] + m + e : zeros;
-          v[e] = *p;
+          for (int e = 0; e < TR; ++e) {
+            const float* p = (kv && m + e < Mtot) ? base + lane_col[u] + m + e : zeros;
+            v[e] = *p;
+          }
         }
         A[u] = v;
       }
@@ -338,11 +344,17 @@ __device__ __forceinline__ void pm_right_f32_body(const PmArgs& a, int bx, int b
         const int off = KS * tl + 16 * h + 4 * lq;
 #pragma unroll
         for (int g = 0; g < MC; ++g) {
+          // per lane: four real k in one vector load, else element by element
+          // (padded i1 reads zero)
           vT v;
+          if (off + 4 <= ilimL) {
+            v = *(const vT*)(colp[g] + lbase + 16 * h);
+          } else {
 #pragma unroll
-          for (int e = 0; e < 4; ++e) {
-            const float* p = (off + e < ilimL) ? colp[g] + lbase + 16 * h + e : zeros;
-            v[e] = *p;
+            for (int e = 0; e < 4; ++e) {
+              const float* p = (off + e < ilimL) ? colp[g] + lbase + 16 * h + e : zeros;
+              v[e] = *p;
+            }
           }
           A[g][h] = v;
         }
