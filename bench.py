@@ -81,23 +81,62 @@ def _algorithmic_bytes(dims, s, R, sx, node_bytes):
     return pm_left, pm_right, mttv
 
 
-def _cpu_baseline(X, H0, iters, seconds_cap=40.0):
+def _time_oracle_iters(X64, H0, iters, seconds_cap, **kw):
+    """Outer iterations of the FP64 oracle per second (stops early at the cap)."""
     import oracle as O
-    X64 = X.astype(np.float64)
     alpha = float(np.sum(X64 * X64))
     t0 = time.perf_counter()
     done = 0
     while done < iters:
-        O.nncp(X64, H0, 1, alpha=alpha)
+        O.nncp(X64, H0, 1, alpha=alpha, **kw)
         done += 1
         if time.perf_counter() - t0 > seconds_cap:
             break
-    dt = time.perf_counter() - t0
+    return done, time.perf_counter() - t0
+
+
+def _cpu_baseline(X, H0, iters, split, seconds_cap=40.0, legs=True):
+    """The FP64 NumPy oracle on the host's cores, as it stands: the headline leg
+    (direct MTTKRP from an explicit Khatri-Rao product) on the benchmark tensor,
+    and, as context, the oracle's dimension-tree MTTKRP on the same tensor, one
+    iteration at the hyperspectral shape and a sample of the 256-job batch."""
+    from paper_1806_07985_amd import inputs
+    X64 = X.astype(np.float64)
+    done, dt = _time_oracle_iters(X64, H0, iters, seconds_cap)
     cores = len(os.sched_getaffinity(0))
-    return dict(value=done / dt, unit="iters/s", cores=cores, kind="oracle",
-                sample=f"{done} outer iteration(s) of the FP64 NumPy oracle (direct MTTKRP from an explicit "
-                       f"Khatri-Rao product, HALS) on the full {'x'.join(map(str, X.shape))} tensor, "
-                       f"BLAS threads = {os.environ.get('OPENBLAS_NUM_THREADS', cores)}")
+    out = dict(value=done / dt, unit="iters/s", cores=cores, kind="oracle",
+               sample=f"{done} outer iteration(s) of the FP64 NumPy oracle (direct MTTKRP from an explicit "
+                      f"Khatri-Rao product, HALS) on the full {'x'.join(map(str, X.shape))} tensor, "
+                      f"BLAS threads = {os.environ.get('OPENBLAS_NUM_THREADS', cores)}")
+    if not legs:
+        return out
+    extra = {}
+    d, t = _time_oracle_iters(X64, H0, 1, seconds_cap, mttkrp="tree", split=split)
+    extra["tree_same_tensor"] = dict(iters_per_s=d / t, sample=f"{d} iteration(s), dimension-tree MTTKRP, "
+                                                                 f"split {split}")
+    del X64
+    dims = (1024, 1344, 33, 9)
+    # the tensor is assembled on the device (the host recipe takes about a minute)
+    # and handed to the oracle as FP64 values
+    Xh = inputs.hsi_like_device(dims, 50, 0.02, seed=21).cpu().numpy().astype(np.float64)
+    Xh = Xh.reshape(dims, order="F")
+    Hh = inputs.init_factors(dims, 50, seed=22)
+    d, t = _time_oracle_iters(Xh, Hh, 1, seconds_cap, split=1)
+    extra["hyperspectral_1024x1344x33x9_r50"] = dict(s_per_iter=t / d, sample=f"{d} iteration(s), direct MTTKRP")
+    del Xh
+    shapes = inputs.batch_shapes(256, seed=9)
+    pick = shapes[::32]                      # 8 of the 256 jobs, 2 iterations each
+    t_jobs = 0.0
+    for j, (dj, Rj) in enumerate(pick):
+        Xj, _ = inputs.planted(dj, Rj, 0.01, seed=1000 + 32 * j)
+        Hj = inputs.init_factors(dj, Rj, seed=5000 + 32 * j)
+        d, t = _time_oracle_iters(Xj, Hj, 2, seconds_cap)
+        t_jobs += t / d
+    extra["batch_256_jobs"] = dict(s_per_iter_all_jobs=t_jobs / len(pick) * len(shapes),
+                                   sample=f"{len(pick)} of the 256 jobs (every 32nd), 2 iterations each, "
+                                          f"scaled to all jobs")
+    out["legs"] = extra
+    return out
 
 
 def _fit_against(Xd, dims, s, Hd, lam):
@@ -402,6 +441,8 @@ def main(argv=None):
     ap.add_argument("--dtype", default="f32", choices=["f32", "bf16", "f16"], help="tensor storage of the main run")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-iters", type=int, default=3)
+    ap.add_argument("--no-cpu-legs", action="store_true",
+                    help="time only the headline oracle leg (not the tree, hyperspectral and batch legs)")
     ap.add_argument("--no-lowprec", action="store_true",
                     help="skip the FP32 / BF16 / FP16 study on the 1024x1344x33x9 tensor")
     ap.add_argument("--lowprec-iters", type=int, default=100)
@@ -584,7 +625,8 @@ def main(argv=None):
                                         max_active=args.serve_max_active)
         note("serving study")
     if not args.no_cpu_baseline and X is not None:
-        out["cpu_baseline"] = _cpu_baseline(X, [h.astype(np.float64) for h in H0], args.cpu_iters)
+        out["cpu_baseline"] = _cpu_baseline(X, [h.astype(np.float64) for h in H0], args.cpu_iters, s,
+                                            legs=not args.no_cpu_legs)
         note("CPU baseline")
     print(json.dumps(out), flush=True)
     return 0
