@@ -43,8 +43,9 @@ def _pm_sources_digest(dtype: str = "f32") -> str:
 
 
 def _traffic_from_profile(workload: str, launch_bytes: float, dtype: str = "f32", key: str = "hbm_bytes_per_launch"):
-    """A figure of one PM launch (HBM bytes by default) from the committed
-    rocprofv3 counter summary, if it was taken on the current kernel sources
+    """A figure of one PM launch from the committed rocprofv3 counter summary
+    (HBM bytes from FETCH_SIZE + WRITE_SIZE scaled by a plain copy's reading,
+    or the MfmaUtil percentage), if it was taken on the current kernel sources
     (else None)."""
     p = os.path.join(ROOT, "profiles", f"pm_traffic_{workload}.json")
     if not os.path.exists(p):
@@ -577,7 +578,8 @@ def main(argv=None):
                    "dims": dims, "R": R, "split": s, "update": args.update, "tensor_dtype": args.dtype},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS,
-                     "traffic": _traffic_from_profile(workload, bytes_dom) if args.dtype == "f32" else None,
+                     "traffic": _traffic_from_profile(workload, bytes_dom, args.dtype, f"hbm_bytes_per_launch_{dom}"),
+                     "mfma_util_counter": _traffic_from_profile(workload, bytes_dom, args.dtype, f"mfma_util_{dom}"),
                      "kernel": f"partial MTTKRP ({dom} root node)",
                      "bytes_per_launch": bytes_dom, "ms_per_launch": ms_dom,
                      "mfma_tflops": flops_pm / (ms_dom * 1e-3) / 1e12,
@@ -608,7 +610,10 @@ def main(argv=None):
         ach16 = lp[f"pm_{dom16}_GBs"]
         out["roofline_bf16"] = {
             "bound": "hbm", "achieved": ach16, "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": ach16 / HBM_PEAK_GBS,
-            "traffic": _traffic_from_profile(f"1024x1344x33x9_r50_bf16_{dom16}", lp[f"pm_{dom16}_bytes"], "bf16"),
+            "traffic": _traffic_from_profile("1024x1344x33x9_r50_bf16", lp[f"pm_{dom16}_bytes"], "bf16",
+                                             f"hbm_bytes_per_launch_{dom16}"),
+            "mfma_util_counter": _traffic_from_profile("1024x1344x33x9_r50_bf16", lp[f"pm_{dom16}_bytes"], "bf16",
+                                                       f"mfma_util_{dom16}"),
             "kernel": f"BF16 partial MTTKRP ({dom16} root node), 1024x1344x33x9 R=50",
             "bytes_per_launch": lp[f"pm_{dom16}_bytes"], "ms_per_launch": lp[f"pm_{dom16}_ms"]}
         note("low-precision study")
