@@ -21,6 +21,7 @@
 #include <cstring>
 #include <functional>
 #include <map>
+#include <mutex>
 #include <new>
 #include <vector>
 
@@ -1322,7 +1323,7 @@ int batch_build(nncp_batch* B) {
     for (KOp& o : all) {
       o.coarse = 1;
       const int kid = batch_kernel_id(o.kind, o.variant);
-      if (kid != 1) continue;
+      if (kid < 100 || kid >= 1000) continue;  // small ops only
       const double groups = (double)batch_kernel_for(o.kind, o.variant).per_cu * cus;
       const double c = blocks[slot[key_of(o.stage, kid)]] / (4.0 * groups);
       const unsigned want = c >= 8.0 ? 8u : (c >= 1.0 ? (unsigned)c : 1u);
@@ -1453,9 +1454,30 @@ int batch_kernel_id(int kind, int variant) {
     case K_PM_16: return 2000000 + variant;
     case K_PACK16: return 3000000 + variant;
     case K_FIN1K: case K_GRAM1K: case K_TAIL1K: return 2;
-    default: return 1;
+    case K_UPDATE: return 200 + variant;  // one kernel per register variant
+    default: return 100 + kind;           // small ops: one kernel per kind
   }
 }
+
+namespace {
+// Work-groups of a persistent launch per CU: as many as fit at once (at most
+// cap); looked up once per kernel.
+int groups_per_cu(const void* fn, int threads, size_t lds, int cap) {
+  static std::mutex mu;
+  static std::map<const void*, int> known;
+  std::lock_guard<std::mutex> lk(mu);
+  auto it = known.find(fn);
+  if (it != known.end()) return it->second;
+  int n = 0;
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, fn, threads, lds) != hipSuccess || n < 1) {
+    (void)hipGetLastError();
+    n = 1;
+  }
+  if (n > cap) n = cap;
+  known.emplace(fn, n);
+  return n;
+}
+}  // namespace
 
 BatchKernel batch_kernel_for(int kind, int variant) {
   BatchKernel k;
@@ -1484,9 +1506,12 @@ BatchKernel batch_kernel_for(int kind, int variant) {
       k.per_cu = 1;
       break;
     default:
-      k.fn = small_batch_kernel_ptr();
+      // (the R > 64 forms, which need dynamic LDS, never run in a batch)
+      if ((kind == K_UPDATE && variant <= 2) || kind == K_FIN_FUSED || kind == K_GRAM_CHUNKS || kind == K_FIN_TAIL)
+        break;
+      k.fn = small_batch_kernel_ptr(kind, variant);
       k.threads = 256;
-      k.per_cu = 8;
+      k.per_cu = k.fn ? groups_per_cu(k.fn, 256, 0, 8) : 1;
       break;
   }
   return k;

@@ -321,7 +321,8 @@ struct BatchKernel {
 // Ops of equal id run in the same launch of one stage.
 int batch_kernel_id(int kind, int variant);
 BatchKernel batch_kernel_for(int kind, int variant);
-const void* small_batch_kernel_ptr();
+// Batched form of a small op's kernel (nullptr for a kind without one).
+const void* small_batch_kernel_ptr(int kind, int variant);
 const void* fin_batch_kernel_ptr();
 size_t fin_batch_max_lds();
 

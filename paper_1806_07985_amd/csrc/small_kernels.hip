@@ -1061,49 +1061,44 @@ __global__ __launch_bounds__(NT) void pm_reduce_kernel(ReduceArgs ra) {
   pm_reduce_body<TO>(ra, blockIdx.x);
 }
 
-// Persistent batched form of the small kernels of the iteration.
+// Persistent batched forms of the small kernels of the iteration: one kernel
+// per kind (and per register variant of the update), so that each runs at its
+// own occupancy rather than at that of the most register-hungry one.
+template <int KIND, int VAR>
 __device__ __forceinline__ void small_op(const KOp& op, int bx, int by) {
-  switch (op.kind) {
-    case K_PM_REDUCE:
-      if (op.variant) pm_reduce_body<double>(op.u.red, bx);
-      else pm_reduce_body<float>(op.u.red, bx);
-      break;
-    case K_MTTV_TRAIL:
-      if (op.variant) mttv_trail_body<double>(op.u.mt, bx, by);
-      else mttv_trail_body<float>(op.u.mt, bx, by);
-      break;
-    case K_MTTV_LEAD:
-      switch (op.variant) {
-        case 41: mttv_lead_body<4, double>(op.u.mt, bx); break;
-        case 40: mttv_lead_body<4, float>(op.u.mt, bx); break;
-        case 81: mttv_lead_body<8, double>(op.u.mt, bx); break;
-        case 80: mttv_lead_body<8, float>(op.u.mt, bx); break;
-        case 161: mttv_lead_body<16, double>(op.u.mt, bx); break;
-        case 160: mttv_lead_body<16, float>(op.u.mt, bx); break;
-        case 321: mttv_lead_body<32, double>(op.u.mt, bx); break;
-        case 320: mttv_lead_body<32, float>(op.u.mt, bx); break;
-        case 641: mttv_lead_body<64, double>(op.u.mt, bx); break;
-        default: mttv_lead_body<64, float>(op.u.mt, bx); break;
-      }
-      break;
-    case K_UPDATE:
-      switch (op.variant) {
-        case 1: update_body<1>(op.u.up, bx); break;
-        case 2: update_body<2>(op.u.up, bx); break;
-        case 16: update_reg_body<16>(op.u.up, bx); break;
-        case 32: update_reg_body<32>(op.u.up, bx); break;
-        default: update_reg_body<64>(op.u.up, bx); break;
-      }
-      break;
-    case K_FIN_FUSED: finalize_fused_body(op.u.fin); break;
-    case K_GRAM_CHUNKS: gram_chunks_body(op.u.fin, bx); break;
-    case K_FIN_TAIL: finalize_tail_body(op.u.fin); break;
-    default: break;
+  if constexpr (KIND == K_PM_REDUCE) {
+    if (op.variant) pm_reduce_body<double>(op.u.red, bx);
+    else pm_reduce_body<float>(op.u.red, bx);
+  } else if constexpr (KIND == K_MTTV_TRAIL) {
+    if (op.variant) mttv_trail_body<double>(op.u.mt, bx, by);
+    else mttv_trail_body<float>(op.u.mt, bx, by);
+  } else if constexpr (KIND == K_MTTV_LEAD) {
+    switch (op.variant) {
+      case 41: mttv_lead_body<4, double>(op.u.mt, bx); break;
+      case 40: mttv_lead_body<4, float>(op.u.mt, bx); break;
+      case 81: mttv_lead_body<8, double>(op.u.mt, bx); break;
+      case 80: mttv_lead_body<8, float>(op.u.mt, bx); break;
+      case 161: mttv_lead_body<16, double>(op.u.mt, bx); break;
+      case 160: mttv_lead_body<16, float>(op.u.mt, bx); break;
+      case 321: mttv_lead_body<32, double>(op.u.mt, bx); break;
+      case 320: mttv_lead_body<32, float>(op.u.mt, bx); break;
+      case 641: mttv_lead_body<64, double>(op.u.mt, bx); break;
+      default: mttv_lead_body<64, float>(op.u.mt, bx); break;
+    }
+  } else if constexpr (KIND == K_UPDATE) {
+    if constexpr (VAR <= 2) update_body<VAR>(op.u.up, bx);
+    else update_reg_body<VAR>(op.u.up, bx);
+  } else if constexpr (KIND == K_FIN_FUSED) {
+    finalize_fused_body(op.u.fin);
+  } else if constexpr (KIND == K_GRAM_CHUNKS) {
+    gram_chunks_body(op.u.fin, bx);
+  } else if constexpr (KIND == K_FIN_TAIL) {
+    finalize_tail_body(op.u.fin);
   }
 }
 
-__global__ __launch_bounds__(NT) void small_batch_kernel(const BItem* __restrict__ items,
-                                                         const int* __restrict__ grp,
+template <int KIND, int VAR>
+__global__ __launch_bounds__(NT) void small_items_kernel(const BItem* __restrict__ items, const int* __restrict__ grp,
                                                          const KOp* __restrict__ ops) {
   const int off = grp[0], n = grp[1];
   for (int i = blockIdx.x; i < n; i += gridDim.x) {
@@ -1111,8 +1106,8 @@ __global__ __launch_bounds__(NT) void small_batch_kernel(const BItem* __restrict
     const KOp& op = ops[it.op];
     const unsigned b0 = (unsigned)it.bx * op.coarse, b1 = min(b0 + op.coarse, op.gx);
     for (unsigned b = b0; b < b1; ++b) {
-      small_op(op, (int)b, it.by);
-      __syncthreads();  // static LDS is reused by the next work-group's share
+      small_op<KIND, VAR>(op, (int)b, it.by);
+      __syncthreads();  // LDS is reused by the next work-group's share
     }
   }
 }
@@ -1303,7 +1298,26 @@ hipError_t sink_record(const Sink& s, const KOp& op) {
   return hipSuccess;
 }
 
-const void* small_batch_kernel_ptr() { return (const void*)small_batch_kernel; }
+const void* small_batch_kernel_ptr(int kind, int variant) {
+  switch (kind) {
+    case K_PM_REDUCE: return (const void*)small_items_kernel<K_PM_REDUCE, 0>;
+    case K_MTTV_TRAIL: return (const void*)small_items_kernel<K_MTTV_TRAIL, 0>;
+    case K_MTTV_LEAD: return (const void*)small_items_kernel<K_MTTV_LEAD, 0>;
+    case K_UPDATE:
+      switch (variant) {
+        case 1: return (const void*)small_items_kernel<K_UPDATE, 1>;
+        case 2: return (const void*)small_items_kernel<K_UPDATE, 2>;
+        case 16: return (const void*)small_items_kernel<K_UPDATE, 16>;
+        case 32: return (const void*)small_items_kernel<K_UPDATE, 32>;
+        case 64: return (const void*)small_items_kernel<K_UPDATE, 64>;
+        default: return nullptr;
+      }
+    case K_FIN_FUSED: return (const void*)small_items_kernel<K_FIN_FUSED, 0>;
+    case K_GRAM_CHUNKS: return (const void*)small_items_kernel<K_GRAM_CHUNKS, 0>;
+    case K_FIN_TAIL: return (const void*)small_items_kernel<K_FIN_TAIL, 0>;
+    default: return nullptr;
+  }
+}
 const void* fin_batch_kernel_ptr() {
   static bool attr = [] {
     (void)hipFuncSetAttribute((const void*)fin_batch_kernel, hipFuncAttributeMaxDynamicSharedMemorySize,
