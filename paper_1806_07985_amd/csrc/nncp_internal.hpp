@@ -89,6 +89,7 @@ struct PmLaunch {
   int I1, I1pad, i1blk, n_i1blk, jblk, n_jblk, fold, istages;
   int j1;        // 16-bit right node with J == 1: the specialised kernel (column scale at the end)
   int wm;        // waves along M per work-group (1 or 4)
+  int wide;      // FP32 only: the group takes a whole CU's LDS (one i1 block of a long first mode)
   int64_t J;
   size_t lds_bytes;
   size_t partial_doubles;
@@ -241,7 +242,7 @@ struct PackArgs {        // term pack of the first contracted factor (16-bit ten
 };
 
 enum KKind : int {
-  K_PM_F32 = 1,     // variant: side*1000 + nb*100 + mt*10 + fast
+  K_PM_F32 = 1,     // variant: wide*10000 + side*1000 + nb*100 + mt*10 + fast
   K_PM_16 = 2,      // variant: j1*100000 + (dtype == BF16)*10000 + side*1000 + nb*100 + mt*10 + fast
   K_PACK16 = 3,     // variant: dtype == BF16
   K_PM_REDUCE = 4,  // variant: t_f64

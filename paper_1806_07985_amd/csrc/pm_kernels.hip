@@ -552,8 +552,8 @@ hipError_t pm_launch_f32(const PmLaunch& L, const PmArgs& a, const Sink& sk) {
   const int wm = a.wm;
   const bool fast = pm_f32_fast(L.side, a.IL, a.I1, L.nb);
   const bool mt = L.mper > 1;
-  // variant = side*1000 + nb*100 + mt*10 + fast
-  const int variant = L.side * 1000 + L.nb * 100 + (mt ? 10 : 0) + (fast ? 1 : 0);
+  // variant = wide*10000 + side*1000 + nb*100 + mt*10 + fast (wide: launched with more LDS)
+  const int variant = (L.wide ? 10000 : 0) + L.side * 1000 + L.nb * 100 + (mt ? 10 : 0) + (fast ? 1 : 0);
   const void* k = kernel_for(L.side, L.nb, fast, mt, false);
   if (!k || (wm != 1 && wm != 4)) return hipErrorInvalidValue;
   size_t lds = L.lds_bytes;
@@ -575,7 +575,7 @@ hipError_t pm_launch_f32(const PmLaunch& L, const PmArgs& a, const Sink& sk) {
 }
 
 const void* pm_f32_batch_kernel(int variant) {
-  const int side = variant / 1000, nb = (variant / 100) % 10;
+  const int side = (variant / 1000) % 10, nb = (variant / 100) % 10;
   const void* k = kernel_for(side, nb, variant % 10 != 0, (variant / 10) % 10 != 0, true);
   if (k) pm_allow_lds(k, 160 * 1024);
   return k;

@@ -35,12 +35,12 @@ static int64_t target_wgs(int64_t x_bytes, int wg_kib) {
 }
 
 // LDS budget of the i1 block of H_1: FP32 rows in ~48 KB (two groups may share a
-// CU), or the 16-bit term rows in up to 128 KB (two terms) or 150 KB (three
-// terms; one group per CU).
-static int lds_rows(int dtype, int RP, int ks) {
+// CU; `wide`: 140 KB, one group per CU), or the 16-bit term rows in up to 128 KB
+// (two terms) or 150 KB (three terms; one group per CU).
+static int lds_rows(int dtype, int RP, int ks, bool wide = false) {
   const bool f32 = dtype == NNCP_F32;
   const int row_bytes = f32 ? RP * 4 : RP * 2 * pm16_terms(dtype);
-  const int budget = f32 ? 48 * 1024 : (pm16_terms(dtype) == 2 ? 128 * 1024 : 150 * 1024);
+  const int budget = f32 ? (wide ? 140 * 1024 : 48 * 1024) : (pm16_terms(dtype) == 2 ? 128 * 1024 : 150 * 1024);
   int maxrows = budget / row_bytes / ks * ks;
   return maxrows < ks ? ks : maxrows;
 }
@@ -51,10 +51,11 @@ static size_t lds_for(int dtype, int RP, int i1blk, int jblk) {
 }
 
 // Most j values whose per-(j, column) scales fit in LDS beside an i1 block of
-// i1blk rows, at most `lim`: a 16-bit group never asks for more than kPmMaxLds,
-// an FP32 group for more than half of it (two FP32 groups share a CU).
-static int jblk_cap(int dtype, int RP, int i1blk, int lim = 64) {
-  const size_t maxl = dtype == NNCP_F32 ? kPmMaxLds / 2 : kPmMaxLds;
+// i1blk rows, at most `lim`: a 16-bit or wide FP32 group never asks for more
+// than kPmMaxLds, another FP32 group for more than half of it (two FP32 groups
+// share a CU).
+static int jblk_cap(int dtype, int RP, int i1blk, int lim = 64, bool wide = false) {
+  const size_t maxl = (dtype == NNCP_F32 && !wide) ? kPmMaxLds / 2 : kPmMaxLds;
   const size_t base = lds_for(dtype, RP, i1blk, 0);
   const size_t per = lds_for(dtype, RP, i1blk, 1) - base;
   const int64_t cap = base >= maxl ? 0 : (int64_t)((maxl - base) / per);
@@ -80,7 +81,16 @@ PmLaunch pm_plan(int side, int dtype, int64_t IL, int64_t IR, int I1, int R, int
   L.I1 = I1;
   L.J = Ktot / I1;
   L.I1pad = (int)cdiv(I1, ks) * ks;
-  const int maxrows = lds_rows(dtype, RP, ks);
+  int maxrows = lds_rows(dtype, RP, ks);
+  // An FP32 right node whose whole first contracted mode fits one CU's LDS but
+  // not half of it takes the CU alone (wide): one i1 block, so no restaging
+  // of LDS and no split K across i1 blocks (1024^3: the right node 1.18 ->
+  // 1.06 ms). Where two blocks or more remain, two groups per CU are faster.
+  L.wide = 0;
+  if (f32 && side == 1 && (int)cdiv(I1, ks) * ks > maxrows && (int)cdiv(I1, ks) * ks <= lds_rows(dtype, RP, ks, true)) {
+    L.wide = 1;
+    maxrows = lds_rows(dtype, RP, ks, true);
+  }
   L.n_i1blk = (int)cdiv(L.I1pad, maxrows);
   L.i1blk = (int)cdiv(cdiv(L.I1pad, L.n_i1blk), ks) * ks;
   L.n_i1blk = (int)cdiv(L.I1pad, L.i1blk);
@@ -136,17 +146,17 @@ PmLaunch pm_plan(int side, int dtype, int64_t IL, int64_t IR, int I1, int R, int
   const int64_t min_j = cdiv(8 * (4 / wm), steps_per_j);
   int64_t jblk = cdiv(L.J, n_jblk < 1 ? 1 : n_jblk);
   if (jblk < min_j) jblk = min_j;
-  if (jblk > jblk_cap(dtype, RP, L.i1blk)) {
+  if (jblk > jblk_cap(dtype, RP, L.i1blk, 64, L.wide)) {
     // at most 64 j per group (the scales are a prologue of jblk * RP products),
     // unless that leaves a few groups beyond the target -- a second, mostly
     // idle round for a 16-bit kernel (one group per CU): then up to 128
-    const int64_t over = L.mgroups * n_i1grp * cdiv(L.J, jblk_cap(dtype, RP, L.i1blk));
+    const int64_t over = L.mgroups * n_i1grp * cdiv(L.J, jblk_cap(dtype, RP, L.i1blk, 64, L.wide));
     const int64_t room = target / (L.mgroups * n_i1grp);
     if (dtype != NNCP_F32 && over > target && over < 2 * target && room >= 1 &&
-        cdiv(L.J, room) <= jblk_cap(dtype, RP, L.i1blk, 128))
+        cdiv(L.J, room) <= jblk_cap(dtype, RP, L.i1blk, 128, L.wide))
       jblk = cdiv(L.J, room);
     else
-      jblk = jblk_cap(dtype, RP, L.i1blk);
+      jblk = jblk_cap(dtype, RP, L.i1blk, 64, L.wide);
   }
   if (jblk > L.J) jblk = L.J;
   if (jblk < 1) jblk = 1;
@@ -195,11 +205,12 @@ size_t pm_variant_max_lds(int kind, int variant) {
   const bool f32 = kind == K_PM_F32;
   const int dtype = f32 ? NNCP_F32 : (((variant / 10000) % 10) ? NNCP_BF16 : NNCP_F16);
   const int side = (variant / 1000) % 10, nb = (variant / 100) % 10;
+  const bool wide = f32 && (variant / 10000) % 10;
   const int RP = 16 * nb;
   const int ks = f32 ? pm_f32_kstep(side) : pm_16_kstep(side);
   size_t lds = 0;
-  for (int rows = ks; rows <= lds_rows(dtype, RP, ks); rows += ks) {
-    const size_t b = lds_for(dtype, RP, rows, jblk_cap(dtype, RP, rows, f32 ? 64 : 128));
+  for (int rows = ks; rows <= lds_rows(dtype, RP, ks, wide); rows += ks) {
+    const size_t b = lds_for(dtype, RP, rows, jblk_cap(dtype, RP, rows, f32 ? 64 : 128, wide));
     if (b > lds) lds = b;
   }
   const size_t red = f32 ? pm_f32_reduce_lds(side, nb, 1) : pm_16_reduce_lds(side, nb, 1);

@@ -100,6 +100,10 @@ def test_membership_changes_rewrite_lists_without_capturing(gpu_lib):
     dims, R = (48, 40, 36), 16
     iters = [5, 40, 12, 30, 8, 25, 50, 15, 20, 35]
     srv = native.Server(8 << 30, max_active=4)
+    # a long job of the same kind keeps the batch running while the others
+    # arrive, join and leave, whatever the speed of a tick
+    Xa, _ = _host_tensor(dims, R, "f32", 899)
+    anchor = srv.submit(Xa, dims, R, [h.astype(np.float32) for h in inputs.init_factors(dims, R, seed=949)], 2000)
     ids, specs = [], []
     for k, it in enumerate(iters):
         Xh, _ = _host_tensor(dims, R, "f32", 900 + k)
@@ -107,12 +111,13 @@ def test_membership_changes_rewrite_lists_without_capturing(gpu_lib):
         specs.append((Xh, H0, it))
         ids.append(srv.submit(Xh, dims, R, H0, it))
     print(f"case membership: {len(ids)} jobs submitted", flush=True)
-    for i in ids:
+    for i in ids + [anchor]:
         assert srv.wait(i, 60)
     st = srv.stats()
     print(f"server stats {st}", flush=True)
     res = [srv.poll(i) for i in ids]
     outs = [srv.fetch(i) for i in ids]
+    assert srv.poll(anchor)["status"] == 0
     srv.close()
     assert all(r["status"] == 0 for r in res)
     assert st["peak_active"] >= 2
