@@ -83,35 +83,39 @@ __device__ __forceinline__ void pm_fill_scales(const PmArgs& a, T* sc, int RP, i
 }
 
 // The FP32 kernels' LDS copy of an i1 block of the first contracted factor:
-// hs[r * hp + i] = H_1(i1_0 + i, col0 + r), zero for i1 >= I1 and r >= R. Eight
-// entries per thread per round trip, loads unconditional from valid addresses.
+// hs[r * hp + i] = H_1(i1_0 + i, col0 + r), zero for i1 >= I1 and r >= R. A work
+// item is four consecutive rows of one column (one element-aligned 16-byte
+// load, element loads where the four straddle I1; hp, i1n and i1_0 are
+// multiples of four, so the LDS store is one aligned 16-byte write); eight
+// items per thread per round trip, all loads issued before any is stored.
 __device__ __forceinline__ void pm_stage_h1(const PmArgs& a, float* hs, int hp, int RP, int i1_0, int i1n) {
   const float* f0 = a.krp.f[0];
-  const int total = RP * i1n;
+  const int q = i1n >> 2;  // items per column
+  const int total = RP * q;
   constexpr int CH = 8;
-  const int dr = NT / i1n, di = NT - dr * i1n;
-  int r = threadIdx.x / i1n, i = threadIdx.x - r * i1n;
   for (int e0 = threadIdx.x; e0 < total; e0 += NT * CH) {
-    float v[CH];
+    f4 v[CH];
     int dst[CH];
 #pragma unroll
     for (int c = 0; c < CH; ++c) {
       const int e = e0 + NT * c;
+      const int r = e / q, i = 4 * (e - r * q);
       const int i1 = i1_0 + i;
-      const bool ok = e < total && r < a.R && i1 < a.I1;
-      const float x = f0[ok ? (int64_t)i1 + (int64_t)a.I1 * (a.col0 + r) : 0];
-      v[c] = ok ? x : 0.f;
-      dst[c] = e < total ? r * hp + i : -1;
-      r += dr;
-      i += di;
-      if (i >= i1n) {
-        i -= i1n;
-        ++r;
+      const bool colok = e < total && r < a.R;
+      const float* src = f0 + (int64_t)a.I1 * (a.col0 + (colok ? r : 0));
+      f4 x = {0.f, 0.f, 0.f, 0.f};
+      if (colok && i1 + 4 <= a.I1) {
+        x = *(const f32v<4>*)(src + i1);
+      } else if (colok) {
+#pragma unroll
+        for (int u = 0; u < 4; ++u) x[u] = (i1 + u < a.I1) ? src[i1 + u] : 0.f;
       }
+      v[c] = x;
+      dst[c] = e < total ? r * hp + i : -1;
     }
 #pragma unroll
     for (int c = 0; c < CH; ++c)
-      if (dst[c] >= 0) hs[dst[c]] = v[c];
+      if (dst[c] >= 0) *(f4*)&hs[dst[c]] = v[c];
   }
 }
 
