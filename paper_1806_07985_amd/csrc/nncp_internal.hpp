@@ -90,6 +90,7 @@ struct PmLaunch {
   int j1;        // 16-bit right node with J == 1: the specialised kernel (column scale at the end)
   int wm;        // waves along M per work-group (1 or 4)
   int wide;      // FP32 only: the group takes a whole CU's LDS (one i1 block of a long first mode)
+  int xs;        // FP32 right node only: X staged through LDS in 256-byte column runs
   int64_t J;
   size_t lds_bytes;
   size_t partial_doubles;
@@ -107,8 +108,11 @@ struct Sink;
 struct ReduceArgs;
 hipError_t pm_launch(const PmLaunch& L, const PmArgs& a, const Sink& sk);
 // per-dtype kernels (pm_kernels.hip, pm16_kernels.hip + pm16_{bf16,f16}{,_mt}.hip)
-int pm_f32_wave_rows(int side, int nb);
-int pm_f32_kstep(int side);
+int pm_f32_wave_rows(int side, int nb, bool xs = false);
+int pm_f32_kstep(int side, bool xs = false);
+// LDS of the four waves' staging tiles of the xs form
+size_t pm_f32_xs_tile_lds(int nb);
+bool pm_f32_xs_ok(int64_t Ktot, int nb);
 size_t pm_f32_reduce_lds(int side, int nb, int wm);
 hipError_t pm_launch_f32(const PmLaunch& L, const PmArgs& a, const Sink& sk);
 int pm_16_wave_rows(int side, int nb, int j1 = 0);
@@ -120,7 +124,7 @@ const void* pm16_kernel_form(int side, int nb, int j1, int fast, bool batch);
 // Every vector load of every k-step lies inside the tensor for this shape (no
 // padded i1, and on the left side no row group straddling a column end): the
 // kernels then skip the per-step check.
-bool pm_f32_fast(int side, int64_t IL, int I1, int nb);
+bool pm_f32_fast(int side, int64_t IL, int I1, int nb, bool xs = false);
 bool pm16_fast(int side, int64_t IL, int I1, int nb);
 template <int DT>
 const void* pm16_pack_kernel(bool batch);
@@ -242,7 +246,7 @@ struct PackArgs {        // term pack of the first contracted factor (16-bit ten
 };
 
 enum KKind : int {
-  K_PM_F32 = 1,     // variant: wide*10000 + side*1000 + nb*100 + mt*10 + fast
+  K_PM_F32 = 1,     // variant: xs*100000 + wide*10000 + side*1000 + nb*100 + mt*10 + fast
   K_PM_16 = 2,      // variant: j1*100000 + (dtype == BF16)*10000 + side*1000 + nb*100 + mt*10 + fast
   K_PACK16 = 3,     // variant: dtype == BF16
   K_PM_REDUCE = 4,  // variant: t_f64

@@ -477,6 +477,287 @@ __device__ __forceinline__ void pm_right_f32_body(const PmArgs& a, int bx, int b
   store_tile((int64_t)(tile0 + ntile - 1) * mtile + wm * 16 * MC);
 }
 
+// ----------------------------------------------------------------------------
+// Right side with X staged through LDS (the "xs" form). The direct loads above
+// give each lane's 16-byte load its own column (the MFMA row index), so one
+// load instruction reads sixteen columns, 64 bytes from each; measured on this
+// chip, HBM serves that pattern at ~6.0 TB/s against ~6.8 TB/s for four columns
+// of 256 bytes. Here load instruction i of a step reads columns 4i .. 4i+3 of
+// the wave, 64 consecutive k (256 bytes) each (lane (li, lq): column 4i + lq,
+// k 4li .. 4li+3); the wave writes every lane's 16 bytes into its own padded
+// [column][k] tile in LDS and reads them back in the MFMA layout (lane (li, lq):
+// column li, k 16h + 4lq .. +3). A tile is written and read by one wave only,
+// and a wave's LDS operations execute in order, so there is no barrier and one
+// tile per wave is enough. Shapes: I1 a multiple of 64 (each step is 64 real
+// i1 of one j, so every load lies inside the tensor), four waves along M and
+// one i1 block per group (the plan falls back to the direct form otherwise).
+// ----------------------------------------------------------------------------
+constexpr int kXsKs = 64;            // k per step
+constexpr int kBufWord3 = 0x00020000;  // buffer resource word 3: raw 32-bit data
+constexpr int kBufNt = 2;              // buffer load cache policy: nontemporal
+constexpr int kXsRow = kXsKs + 4;    // floats per staged column in LDS (padded)
+constexpr int xs_mc(int nb) { return nb >= 4 ? 1 : 2; }
+constexpr int xs_pf(int nb) { return 3; }
+
+template <int NB, int D, bool MT>
+__device__ __forceinline__ void pm_right_f32_xs_body(const PmArgs& a, int bx, int by) {
+  constexpr int RP = NB * 16;
+  constexpr int MC = xs_mc(NB);
+  constexpr int KS = kXsKs;
+  constexpr int NI = 4 * MC;  // load instructions per step
+  constexpr int NACC = MC * NB;
+  extern __shared__ double lds_d[];
+  const int hp = a.i1blk + 4;
+  float* hs = (float*)lds_d;
+  double* sc = lds_d + (RP * hp + 1) / 2;
+  const int lane = threadIdx.x & 63;
+  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  const int li = lane & 15, lq = lane >> 4;
+  // the wave's staging tile, after the scales (16-byte aligned: RP * hp and
+  // jblk * RP are multiples of 64 floats)
+  float* xt = (float*)(sc + (size_t)a.jblk * RP) + wave * (16 * MC * kXsRow);
+  const int64_t Mtot = a.IR, Ktot = a.IL;
+  const int mtile = 4 * 16 * MC;
+  const int tile0 = MT ? bx * a.mper : bx;
+  const int ntile = MT ? min(a.mper, a.mtiles - tile0) : 1;
+  const int ib = by % a.n_i1blk, jb = by / a.n_i1blk;
+  const int i1_0 = ib * a.i1blk;
+  const int i1n = min(a.i1blk, a.I1pad - i1_0);
+  const int64_t j0 = (int64_t)jb * a.jblk;
+  const int jn = (int)min((int64_t)a.jblk, a.J - j0);
+  const float* X = (const float*)a.X;
+
+  pm_prologue(a, hs, hp, sc, RP, i1_0, i1n, j0, jn);
+  __syncthreads();
+
+  const int S1 = i1n / KS;
+  const int se = ntile * S1 * jn;  // every wave walks all steps of its columns
+
+  double acc[NACC][4];
+#pragma unroll
+  for (int v = 0; v < NACC; ++v)
+#pragma unroll
+    for (int e = 0; e < 4; ++e) acc[v][e] = 0.0;
+
+  // Loads are buffer loads: the wave-uniform resource starts at the step's
+  // first element of the wave's first column and ends at the tensor's end, so
+  // lanes of columns past the output read zeros (the buffer range check) and
+  // the per-lane byte offsets, column 4i + lq and k 4li, are fixed.
+  const int64_t IX = Mtot * Ktot;
+  uint32_t voff[NI];
+#pragma unroll
+  for (int i = 0; i < NI; ++i) voff[i] = (uint32_t)((((int64_t)(4 * i + lq)) * Ktot + 4 * li) * 4);
+  int64_t cwk = 0;  // first element of the wave's columns in the tile being loaded
+  auto set_tile = [&](int t) { cwk = ((int64_t)(tile0 + t) * mtile + wave * 16 * MC) * Ktot; };
+  set_tile(0);
+
+  // cursor (tile, j, t); j starts rotated by the group, the load cursor runs D
+  // steps ahead and wraps inside the group's tiles and j block
+  const int jrot = jn > 1 ? (int)(((unsigned)bx * 5u) % (unsigned)jn) : 0;
+  int tileL = 0, jcntL = 0, tl = 0, jl = jrot;
+  auto load = [&](f4 (&A)[NI]) {
+    const int64_t e0 = cwk + (int64_t)a.I1 * (j0 + jl) + i1_0 + KS * tl;
+    const int64_t rem = IX - e0;
+    const int nrec = rem <= 0 ? 0 : (rem >= (int64_t)0x3fffffff ? (int)0xfffffffc : (int)(rem * 4));
+    const __amdgpu_buffer_rsrc_t rs = __builtin_amdgcn_make_buffer_rsrc((void*)(X + e0), (short)0, nrec, kBufWord3);
+#pragma unroll
+    for (int i = 0; i < NI; ++i) A[i] = __builtin_bit_cast(f4, __builtin_amdgcn_raw_buffer_load_b128(rs, (int)voff[i], 0, kBufNt));
+    if (++tl == S1) {
+      tl = 0;
+      if (++jl == jn) jl = 0;
+      if (MT && ++jcntL == jn) {
+        jcntL = 0;
+        if (++tileL == ntile) tileL = 0;
+        set_tile(tileL);
+      }
+    }
+  };
+  auto stage = [&](const f4 (&A)[NI]) {
+#pragma unroll
+    for (int i = 0; i < NI; ++i) *(f4*)&xt[(4 * i + lq) * kXsRow + 4 * li] = A[i];
+  };
+
+  // acc[g*NB+nb][v]: column c = cw + 16g + 4*lq + v, rank column 16nb + li.
+  const bool direct = (a.nsplit == 1);
+  const int64_t Mpad = (int64_t)a.mtiles * mtile;
+  auto store_tile = [&](int64_t cw) {
+#pragma unroll
+    for (int g = 0; g < MC; ++g)
+#pragma unroll
+      for (int nb = 0; nb < NB; ++nb) {
+        double o[4];
+#pragma unroll
+        for (int v = 0; v < 4; ++v) o[v] = acc[g * NB + nb][v];
+        pm_store_rows<4>(a, direct, Mtot, Mpad, RP, by, 16 * nb + li, cw + 16 * g + 4 * lq, o);
+      }
+  };
+
+  // MFMA operands of one h (16 k) of a step: the tile's four k of each column
+  // group and the H_1 values of the same k for each column block
+  struct Ops {
+    f4 x[MC], b[NB];
+  };
+  auto read_ops = [&](int t, int h, Ops& o) {
+#pragma unroll
+    for (int g = 0; g < MC; ++g) o.x[g] = *(const f4*)&xt[(16 * g + li) * kXsRow + 16 * h + 4 * lq];
+#pragma unroll
+    for (int nb = 0; nb < NB; ++nb) o.b[nb] = *(const f4*)&hs[(16 * nb + li) * hp + KS * t + 4 * lq + 16 * h];
+  };
+  using Acc32 = f4[MC][NB];
+  // `first`: the step's first products, which start the sums (zero input)
+  auto mma = [&](const Ops& o, Acc32& c, bool first) {
+#pragma unroll
+    for (int u = 0; u < 4; ++u)
+#pragma unroll
+      for (int g = 0; g < MC; ++g)
+#pragma unroll
+        for (int nb = 0; nb < NB; ++nb)
+          c[g][nb] = mfma4(o.x[g][u], o.b[nb][u], (first && u == 0) ? f4{0.f, 0.f, 0.f, 0.f} : c[g][nb]);
+  };
+  // FP32 sums of one step (64 products per output) into FP64 with the step's
+  // per-(j, column) scale
+  auto fold = [&](const Acc32& c, const double (&scl)[NB]) {
+#pragma unroll
+    for (int nb = 0; nb < NB; ++nb)
+#pragma unroll
+      for (int g = 0; g < MC; ++g)
+#pragma unroll
+        for (int e = 0; e < 4; ++e) acc[g * NB + nb][e] = __builtin_fma((double)c[g][nb][e], scl[nb], acc[g * NB + nb][e]);
+  };
+  auto read_scales = [&](int j, double (&scl)[NB]) {
+#pragma unroll
+    for (int nb = 0; nb < NB; ++nb) scl[nb] = sc[j * RP + 16 * nb + li];
+  };
+
+  // Each step sums into its own FP32 set (two sets, alternating with the step's
+  // parity) and is folded into FP64 during the next step, after that step's
+  // first MFMAs: the fold's reads of the MFMA results then find them complete.
+  // A set that holds nothing to fold is zero (so the fold is unconditional).
+  Acc32 c32[2];
+#pragma unroll
+  for (int q = 0; q < 2; ++q)
+#pragma unroll
+    for (int g = 0; g < MC; ++g)
+#pragma unroll
+      for (int nb = 0; nb < NB; ++nb) c32[q][g][nb] = f4{0.f, 0.f, 0.f, 0.f};
+  int jc = jl, tc = 0, jcntC = 0, tileC = 0, jprev = 0;
+  // One step, in four scheduling regions, one per h (16 k). On entry the tile
+  // holds the step and p0 its h = 0 operands. The LDS reads of h + 1 go out
+  // before the MFMAs of h; with `next`, the following step (registers An,
+  // loaded D steps ago) is written to the tile and the loads D steps ahead go
+  // out into An during the MFMAs of h = 2, and its h = 0 operands are read
+  // before the MFMAs of h = 3 (a wave's LDS operations run in order, so the
+  // tile is rewritten only after this step's reads). sched_group_barrier
+  // spreads the LDS and memory instructions between the MFMAs, so that the
+  // matrix pipe keeps busy while the LDS takes the writes.
+  constexpr int NR = MC + NB;  // LDS reads of one h
+  Ops p0, p1;
+  auto step = [&](f4 (&An)[NI], bool next, Acc32& cc, Acc32& cp) {
+    double sp[NB];
+    read_scales(jprev, sp);
+    read_ops(tc, 1, p1);
+    mma(p0, cc, true);
+    fold(cp, sp);
+#pragma unroll
+    for (int i = 0; i < NR + NB; ++i) {
+      __builtin_amdgcn_sched_group_barrier(0x100, 1, 0);  // LDS read
+      __builtin_amdgcn_sched_group_barrier(0x008, 1, 0);  // MFMA
+    }
+#pragma unroll
+    for (int i = 0; i < 4 * MC * NB - NR - NB; ++i) {
+      __builtin_amdgcn_sched_group_barrier(0x002, 3, 0);  // VALU
+      __builtin_amdgcn_sched_group_barrier(0x008, 1, 0);
+    }
+    __builtin_amdgcn_sched_barrier(0);
+    read_ops(tc, 2, p0);
+    mma(p1, cc, false);
+#pragma unroll
+    for (int i = 0; i < NR; ++i) {
+      __builtin_amdgcn_sched_group_barrier(0x100, 1, 1);
+      __builtin_amdgcn_sched_group_barrier(0x008, 1, 1);
+    }
+    __builtin_amdgcn_sched_barrier(0);
+    read_ops(tc, 3, p1);
+    mma(p0, cc, false);
+    if (next) {
+      stage(An);
+      load(An);
+    }
+#pragma unroll
+    for (int i = 0; i < NR; ++i) {
+      __builtin_amdgcn_sched_group_barrier(0x100, 1, 2);
+      __builtin_amdgcn_sched_group_barrier(0x008, 1, 2);
+    }
+#pragma unroll
+    for (int i = 0; i < NI; ++i) {
+      __builtin_amdgcn_sched_group_barrier(0x200, 1, 2);  // LDS write
+      __builtin_amdgcn_sched_group_barrier(0x020, 1, 2);  // memory read
+      __builtin_amdgcn_sched_group_barrier(0x008, 1, 2);
+    }
+    __builtin_amdgcn_sched_barrier(0);
+    if (next) read_ops(tc + 1 == S1 ? 0 : tc + 1, 0, p0);
+    mma(p1, cc, false);
+#pragma unroll
+    for (int i = 0; i < NR; ++i) {
+      __builtin_amdgcn_sched_group_barrier(0x100, 1, 3);
+      __builtin_amdgcn_sched_group_barrier(0x008, 1, 3);
+    }
+    __builtin_amdgcn_sched_barrier(0);
+    jprev = jc;
+    if (++tc == S1) {
+      tc = 0;
+      if (++jc == jn) jc = 0;
+      if (MT && ++jcntC == jn) {
+        jcntC = 0;
+        if (tileC + 1 < ntile) {  // a tile done: fold its last step now, store it, start the next
+          double sl[NB];
+          read_scales(jprev, sl);
+          fold(cc, sl);
+#pragma unroll
+          for (int g = 0; g < MC; ++g)
+#pragma unroll
+            for (int nb = 0; nb < NB; ++nb) cc[g][nb] = f4{0.f, 0.f, 0.f, 0.f};
+          store_tile((int64_t)(tile0 + tileC) * mtile + wave * 16 * MC);
+#pragma unroll
+          for (int v = 0; v < NACC; ++v)
+#pragma unroll
+            for (int e = 0; e < 4; ++e) acc[v][e] = 0.0;
+          ++tileC;
+        }
+      }
+    }
+  };
+
+  // D steps of X in flight in registers: step s + 1 is staged from ring slot
+  // (s + 1) % D while step s is computed, and that slot then loads step s + 1 + D
+  // (the cursor wraps inside the group's tiles and j block, so loads past the
+  // end read valid memory that is never used). The loop body covers 2D steps so
+  // that ring slots and FP32 sets are both fixed per unrolled step.
+  f4 A[D][NI];
+#pragma unroll
+  for (int d = 0; d < D; ++d) load(A[d]);
+  stage(A[0]);
+  __builtin_amdgcn_sched_barrier(0);
+  load(A[0]);
+  __builtin_amdgcn_sched_barrier(0);
+  read_ops(0, 0, p0);
+  int s = 0;
+  for (; s + 2 * D < se; s += 2 * D) {
+#pragma unroll
+    for (int d = 0; d < 2 * D; ++d) step(A[(d + 1) % D], true, c32[d % 2], c32[(d + 1) % 2]);
+  }
+#pragma unroll
+  for (int d = 0; d < 2 * D; ++d)
+    if (s + d < se) step(A[(d + 1) % D], s + d + 1 < se, c32[d % 2], c32[(d + 1) % 2]);
+  {  // the last step (its set: parity of se - 1)
+    double sl[NB];
+    read_scales(jprev, sl);
+    if ((se - 1) % 2 == 0) fold(c32[0], sl);
+    else fold(c32[1], sl);
+  }
+  store_tile((int64_t)(tile0 + ntile - 1) * mtile + wave * 16 * MC);
+}
+
 // FAST: the shape guarantees that every vector load of every step lies inside
 // the tensor (pm_f32_fast), so the loads need no per-step check. MT: a group
 // streams several M tiles (a separate form, so that the one-tile kernels keep
@@ -508,6 +789,33 @@ __global__ __launch_bounds__(NT, 2) void pm_f32_items(const BItem* __restrict__ 
   }
 }
 
+// The xs form (right side only; FAST shapes by construction).
+template <int NB, bool MT>
+__global__ __launch_bounds__(NT, 2) void pm_f32_xs(PmArgs a) {
+  pm_right_f32_xs_body<NB, xs_pf(NB), MT>(a, blockIdx.x, blockIdx.y);
+}
+template <int NB, bool MT>
+__global__ __launch_bounds__(NT, 2) void pm_f32_xs_items(const BItem* __restrict__ items, const int* __restrict__ grp,
+                                                         const KOp* __restrict__ ops) {
+  const int off = grp[0], n = grp[1];
+  for (int i = blockIdx.x; i < n; i += gridDim.x) {
+    const BItem it = items[off + i];
+    const KOp& op = ops[it.op];
+    pm_right_f32_xs_body<NB, xs_pf(NB), MT>(op.u.pm, it.bx, it.by);
+    __syncthreads();  // LDS is reused by the next item
+  }
+}
+
+template <bool MT>
+const void* pick_xs(int nb, bool batch) {
+  switch (nb) {
+    case 1: return batch ? (const void*)pm_f32_xs_items<1, MT> : (const void*)pm_f32_xs<1, MT>;
+    case 2: return batch ? (const void*)pm_f32_xs_items<2, MT> : (const void*)pm_f32_xs<2, MT>;
+    case 4: return batch ? (const void*)pm_f32_xs_items<4, MT> : (const void*)pm_f32_xs<4, MT>;
+    default: return nullptr;
+  }
+}
+
 template <int SIDE, bool FAST, bool MT>
 const void* pick(int nb, bool batch) {
   switch (nb) {
@@ -523,7 +831,8 @@ const void* pick_fast(int nb, bool fast, bool batch) {
   return fast ? pick<SIDE, true, MT>(nb, batch) : pick<SIDE, false, MT>(nb, batch);
 }
 
-const void* kernel_for(int side, int nb, bool fast, bool mt, bool batch) {
+const void* kernel_for(int side, int nb, bool fast, bool mt, bool xs, bool batch) {
+  if (xs) return side == 1 && fast ? (mt ? pick_xs<true>(nb, batch) : pick_xs<false>(nb, batch)) : nullptr;
   if (side == 0) return mt ? pick_fast<0, true>(nb, fast, batch) : pick_fast<0, false>(nb, fast, batch);
   return mt ? pick_fast<1, true>(nb, fast, batch) : pick_fast<1, false>(nb, fast, batch);
 }
@@ -536,26 +845,34 @@ size_t reduce_lds(int side, int nb, int wm) {
 
 }  // namespace
 
-int pm_f32_wave_rows(int side, int nb) { return side == 0 ? 16 * left_tr(nb) : 16 * right_mc(nb); }
-int pm_f32_kstep(int side) { return side == 0 ? 16 : 32; }
+int pm_f32_wave_rows(int side, int nb, bool xs) {
+  if (xs) return 16 * xs_mc(nb);
+  return side == 0 ? 16 * left_tr(nb) : 16 * right_mc(nb);
+}
+int pm_f32_kstep(int side, bool xs) { return xs ? kXsKs : (side == 0 ? 16 : 32); }
+size_t pm_f32_xs_tile_lds(int nb) { return (size_t)4 * 16 * xs_mc(nb) * kXsRow * sizeof(float); }
+// the per-lane buffer offsets (up to 16 MC columns of Ktot elements) fit 31 bits
+bool pm_f32_xs_ok(int64_t Ktot, int nb) { return (int64_t)16 * xs_mc(nb) * Ktot * 4 + 256 < ((int64_t)1 << 31); }
 size_t pm_f32_reduce_lds(int side, int nb, int wm) { return reduce_lds(side, nb, wm); }
 
 // Every vector load of every step lies inside the tensor when the k-steps
 // tile I1 exactly (no padded i1) and, on the left side, the row groups tile
 // I_L exactly (no group straddles a column end).
-bool pm_f32_fast(int side, int64_t IL, int I1, int nb) {
-  if (I1 % pm_f32_kstep(side) != 0) return false;
+bool pm_f32_fast(int side, int64_t IL, int I1, int nb, bool xs) {
+  if (I1 % pm_f32_kstep(side, xs) != 0) return false;
   return side == 1 || IL % left_tr(nb) == 0;
 }
 
 hipError_t pm_launch_f32(const PmLaunch& L, const PmArgs& a, const Sink& sk) {
   const int wm = a.wm;
-  const bool fast = pm_f32_fast(L.side, a.IL, a.I1, L.nb);
+  const bool fast = pm_f32_fast(L.side, a.IL, a.I1, L.nb, L.xs);
   const bool mt = L.mper > 1;
-  // variant = wide*10000 + side*1000 + nb*100 + mt*10 + fast (wide: launched with more LDS)
-  const int variant = (L.wide ? 10000 : 0) + L.side * 1000 + L.nb * 100 + (mt ? 10 : 0) + (fast ? 1 : 0);
-  const void* k = kernel_for(L.side, L.nb, fast, mt, false);
+  // variant = xs*100000 + wide*10000 + side*1000 + nb*100 + mt*10 + fast (wide: launched with more LDS)
+  const int variant =
+      (L.xs ? 100000 : 0) + (L.wide ? 10000 : 0) + L.side * 1000 + L.nb * 100 + (mt ? 10 : 0) + (fast ? 1 : 0);
+  const void* k = kernel_for(L.side, L.nb, fast, mt, L.xs, false);
   if (!k || (wm != 1 && wm != 4)) return hipErrorInvalidValue;
+  if (L.xs && (wm != 4 || a.istages != 1)) return hipErrorInvalidValue;
   size_t lds = L.lds_bytes;
   if (reduce_lds(L.side, L.nb, wm) > lds) lds = reduce_lds(L.side, L.nb, wm);
   if (lds > kPmMaxLds) return hipErrorInvalidValue;
@@ -576,7 +893,7 @@ hipError_t pm_launch_f32(const PmLaunch& L, const PmArgs& a, const Sink& sk) {
 
 const void* pm_f32_batch_kernel(int variant) {
   const int side = (variant / 1000) % 10, nb = (variant / 100) % 10;
-  const void* k = kernel_for(side, nb, variant % 10 != 0, (variant / 10) % 10 != 0, true);
+  const void* k = kernel_for(side, nb, variant % 10 != 0, (variant / 10) % 10 != 0, (variant / 100000) % 10 != 0, true);
   if (k) pm_allow_lds(k, 160 * 1024);
   return k;
 }

@@ -35,12 +35,14 @@ static int64_t target_wgs(int64_t x_bytes, int wg_kib) {
 }
 
 // LDS budget of the i1 block of H_1: FP32 rows in ~48 KB (two groups may share a
-// CU; `wide`: 140 KB, one group per CU), or the 16-bit term rows in up to 128 KB
-// (two terms) or 150 KB (three terms; one group per CU).
-static int lds_rows(int dtype, int RP, int ks, bool wide = false) {
+// CU; `wide`: 140 KB, one group per CU; `xs`: 96 KB beside the X staging tiles),
+// or the 16-bit term rows in up to 128 KB (two terms) or 150 KB (three terms;
+// one group per CU).
+static int lds_rows(int dtype, int RP, int ks, bool wide = false, bool xs = false) {
   const bool f32 = dtype == NNCP_F32;
   const int row_bytes = f32 ? RP * 4 : RP * 2 * pm16_terms(dtype);
-  const int budget = f32 ? (wide ? 140 * 1024 : 48 * 1024) : (pm16_terms(dtype) == 2 ? 128 * 1024 : 150 * 1024);
+  const int budget = f32 ? (xs ? 96 * 1024 : (wide ? 140 * 1024 : 48 * 1024))
+                         : (pm16_terms(dtype) == 2 ? 128 * 1024 : 150 * 1024);
   int maxrows = budget / row_bytes / ks * ks;
   return maxrows < ks ? ks : maxrows;
 }
@@ -52,17 +54,20 @@ static size_t lds_for(int dtype, int RP, int i1blk, int jblk) {
 
 // Most j values whose per-(j, column) scales fit in LDS beside an i1 block of
 // i1blk rows, at most `lim`: a 16-bit or wide FP32 group never asks for more
-// than kPmMaxLds, another FP32 group for more than half of it (two FP32 groups
-// share a CU).
-static int jblk_cap(int dtype, int RP, int i1blk, int lim = 64, bool wide = false) {
-  const size_t maxl = (dtype == NNCP_F32 && !wide) ? kPmMaxLds / 2 : kPmMaxLds;
+// than kPmMaxLds, an xs group for more than kPmMaxLds less its staging tiles
+// (xs_tiles bytes), another FP32 group for more than half of it (two FP32
+// groups share a CU).
+static int jblk_cap(int dtype, int RP, int i1blk, int lim = 64, bool wide = false, size_t xs_tiles = 0) {
+  const size_t maxl = xs_tiles ? kPmMaxLds - xs_tiles : ((dtype == NNCP_F32 && !wide) ? kPmMaxLds / 2 : kPmMaxLds);
   const size_t base = lds_for(dtype, RP, i1blk, 0);
   const size_t per = lds_for(dtype, RP, i1blk, 1) - base;
   const int64_t cap = base >= maxl ? 0 : (int64_t)((maxl - base) / per);
   return cap < lim ? (int)cap : lim;
 }
 
-PmLaunch pm_plan(int side, int dtype, int64_t IL, int64_t IR, int I1, int R, int wg_kib) {
+// xs: plan the FP32 right node's LDS-staged form; the result has xs == 0 when
+// the shape does not suit it (the caller then plans the direct form).
+static PmLaunch plan_impl(int side, int dtype, int64_t IL, int64_t IR, int I1, int R, int wg_kib, bool xs) {
   PmLaunch L{};
   L.side = side;
   L.dtype = dtype;
@@ -70,24 +75,28 @@ PmLaunch pm_plan(int side, int dtype, int64_t IL, int64_t IR, int I1, int R, int
   L.nb = Rc <= 16 ? 1 : (Rc <= 32 ? 2 : 4);
   const int RP = 16 * L.nb;
   const bool f32 = dtype == NNCP_F32;
+  xs = xs && f32 && side == 1 && I1 % pm_f32_kstep(1, true) == 0 && pm_f32_xs_ok(IL, L.nb);
+  L.xs = xs ? 1 : 0;
+  const size_t xs_tiles = xs ? pm_f32_xs_tile_lds(L.nb) : 0;
   const int64_t Mtot = side == 0 ? IL : IR;
   const int64_t Ktot = side == 0 ? IR : IL;
-  const int ks = f32 ? pm_f32_kstep(side) : pm_16_kstep(side);
+  const int ks = f32 ? pm_f32_kstep(side, xs) : pm_16_kstep(side);
   // a tall 16-bit right node with J == 1 uses the specialised kernel (wider waves)
   L.j1 = (!f32 && side == 1 && Ktot / I1 == 1 && cdiv(Mtot, 4 * pm_16_wave_rows(1, L.nb, 1)) >= 64) ? 1 : 0;
-  const int wave_rows = f32 ? pm_f32_wave_rows(side, L.nb) : pm_16_wave_rows(side, L.nb, L.j1);
+  const int wave_rows = f32 ? pm_f32_wave_rows(side, L.nb, xs) : pm_16_wave_rows(side, L.nb, L.j1);
   const int64_t target = target_wgs(IL * IR * (f32 ? 4 : 2), wg_kib);
 
   L.I1 = I1;
   L.J = Ktot / I1;
   L.I1pad = (int)cdiv(I1, ks) * ks;
-  int maxrows = lds_rows(dtype, RP, ks);
+  int maxrows = lds_rows(dtype, RP, ks, false, xs);
   // An FP32 right node whose whole first contracted mode fits one CU's LDS but
   // not half of it takes the CU alone (wide): one i1 block, so no restaging
   // of LDS and no split K across i1 blocks (1024^3: the right node 1.18 ->
   // 1.06 ms). Where two blocks or more remain, two groups per CU are faster.
   L.wide = 0;
-  if (f32 && side == 1 && (int)cdiv(I1, ks) * ks > maxrows && (int)cdiv(I1, ks) * ks <= lds_rows(dtype, RP, ks, true)) {
+  if (!xs && f32 && side == 1 && (int)cdiv(I1, ks) * ks > maxrows &&
+      (int)cdiv(I1, ks) * ks <= lds_rows(dtype, RP, ks, true)) {
     L.wide = 1;
     maxrows = lds_rows(dtype, RP, ks, true);
   }
@@ -111,6 +120,11 @@ PmLaunch pm_plan(int side, int dtype, int64_t IL, int64_t IR, int I1, int R, int
   // partials of a tall output would cost more HBM traffic than X.
   L.istages = 1;
   if (side == 1 && wm == 4 && L.n_i1blk > 1 && L.mtiles >= target) L.istages = L.n_i1blk;
+  // the xs form has four waves along M and one i1 block per group
+  if (xs && (wm != 4 || L.istages != 1)) {
+    L.xs = 0;
+    return L;
+  }
   const int n_i1grp = L.n_i1blk / L.istages;
 
   // Many short tiles (one i1 block, at least as many four-wave tiles as the
@@ -146,17 +160,17 @@ PmLaunch pm_plan(int side, int dtype, int64_t IL, int64_t IR, int I1, int R, int
   const int64_t min_j = cdiv(8 * (4 / wm), steps_per_j);
   int64_t jblk = cdiv(L.J, n_jblk < 1 ? 1 : n_jblk);
   if (jblk < min_j) jblk = min_j;
-  if (jblk > jblk_cap(dtype, RP, L.i1blk, 64, L.wide)) {
+  if (jblk > jblk_cap(dtype, RP, L.i1blk, 64, L.wide, xs_tiles)) {
     // at most 64 j per group (the scales are a prologue of jblk * RP products),
     // unless that leaves a few groups beyond the target -- a second, mostly
     // idle round for a 16-bit kernel (one group per CU): then up to 128
-    const int64_t over = L.mgroups * n_i1grp * cdiv(L.J, jblk_cap(dtype, RP, L.i1blk, 64, L.wide));
+    const int64_t over = L.mgroups * n_i1grp * cdiv(L.J, jblk_cap(dtype, RP, L.i1blk, 64, L.wide, xs_tiles));
     const int64_t room = target / (L.mgroups * n_i1grp);
     if (dtype != NNCP_F32 && over > target && over < 2 * target && room >= 1 &&
-        cdiv(L.J, room) <= jblk_cap(dtype, RP, L.i1blk, 128, L.wide))
+        cdiv(L.J, room) <= jblk_cap(dtype, RP, L.i1blk, 128, L.wide, xs_tiles))
       jblk = cdiv(L.J, room);
     else
-      jblk = jblk_cap(dtype, RP, L.i1blk, 64, L.wide);
+      jblk = jblk_cap(dtype, RP, L.i1blk, 64, L.wide, xs_tiles);
   }
   if (jblk > L.J) jblk = L.J;
   if (jblk < 1) jblk = 1;
@@ -177,12 +191,20 @@ PmLaunch pm_plan(int side, int dtype, int64_t IL, int64_t IR, int I1, int R, int
   }
   L.n_jblk = (int)cdiv(L.J, jblk);
   L.nsplit = n_i1grp * L.n_jblk;
-  L.lds_bytes = lds_for(dtype, RP, L.i1blk, L.jblk);
+  L.lds_bytes = lds_for(dtype, RP, L.i1blk, L.jblk) + xs_tiles;
   L.pack_bytes =
       f32 ? 0 : (size_t)pm16_terms(dtype) * RP * L.I1pad * sizeof(unsigned short) + 256 + (size_t)RP * sizeof(float);
   L.partial_doubles = L.nsplit > 1 ? (size_t)L.nsplit * RP * (size_t)L.mtiles * L.mtile : 0;
   L.ncounters = L.mtiles;
   return L;
+}
+
+PmLaunch pm_plan(int side, int dtype, int64_t IL, int64_t IR, int I1, int R, int wg_kib) {
+  if (dtype == NNCP_F32 && side == 1) {
+    const PmLaunch L = plan_impl(side, dtype, IL, IR, I1, R, wg_kib, true);
+    if (L.xs) return L;
+  }
+  return plan_impl(side, dtype, IL, IR, I1, R, wg_kib, false);
 }
 
 void pm_fill_args(const PmLaunch& L, PmArgs& a) {
@@ -206,11 +228,13 @@ size_t pm_variant_max_lds(int kind, int variant) {
   const int dtype = f32 ? NNCP_F32 : (((variant / 10000) % 10) ? NNCP_BF16 : NNCP_F16);
   const int side = (variant / 1000) % 10, nb = (variant / 100) % 10;
   const bool wide = f32 && (variant / 10000) % 10;
+  const bool xs = f32 && (variant / 100000) % 10;
+  const size_t xs_tiles = xs ? pm_f32_xs_tile_lds(nb) : 0;
   const int RP = 16 * nb;
-  const int ks = f32 ? pm_f32_kstep(side) : pm_16_kstep(side);
+  const int ks = f32 ? pm_f32_kstep(side, xs) : pm_16_kstep(side);
   size_t lds = 0;
-  for (int rows = ks; rows <= lds_rows(dtype, RP, ks, wide); rows += ks) {
-    const size_t b = lds_for(dtype, RP, rows, jblk_cap(dtype, RP, rows, f32 ? 64 : 128, wide));
+  for (int rows = ks; rows <= lds_rows(dtype, RP, ks, wide, xs); rows += ks) {
+    const size_t b = lds_for(dtype, RP, rows, jblk_cap(dtype, RP, rows, f32 ? 64 : 128, wide, xs_tiles)) + xs_tiles;
     if (b > lds) lds = b;
   }
   const size_t red = f32 ? pm_f32_reduce_lds(side, nb, 1) : pm_16_reduce_lds(side, nb, 1);

@@ -174,6 +174,82 @@ static void emu_right(const PmLaunch& L, int64_t IL, int64_t IR, bool f32, bool 
       }
 }
 
+// The FP32 right node's LDS-staged (xs) form: load instruction i of a step reads
+// column cw + 4i + lq at k offset 4li, 64 k per step; each wave writes its tile
+// [16 MC columns][kXsRow] after the H_1 block and the scales, and reads it back
+// at column 16g + li, k 16h + 4lq. B operands: H_1 rows of the step's k.
+static void emu_right_xs(const PmLaunch& L, int64_t IL, int64_t IR) {
+  const int nb = L.nb, RP = 16 * nb;
+  const int MC = pm_f32_wave_rows(1, nb, true) / 16;
+  const int KS = pm_f32_kstep(1, true), ROW = KS + 4, D = 3, NI = 4 * MC;
+  const int64_t Mtot = IR, Ktot = IL, I = IL * IR;
+  if (L.wm != 4 || L.istages != 1 || L.I1 % KS != 0 || L.mtile != 4 * 16 * MC) { printf("  bad xs geometry\n"); ++bad; return; }
+  // LDS: H_1 block, scales, four tiles
+  const int hp = L.i1blk + 4;
+  const int64_t xt0 = (int64_t)RP * hp * 4 + (int64_t)L.jblk * RP * 8;  // bytes
+  const int64_t tile_bytes = (int64_t)16 * MC * ROW * 4;
+  chk(xt0 + 4 * tile_bytes - 1, (int64_t)L.lds_bytes, "xs lds");
+  chk((int64_t)L.lds_bytes - 1, (int64_t)kPmMaxLds, "xs lds max");
+  if (xt0 % 16) { printf("  xs tile misaligned\n"); ++bad; }
+  for (int lane = 0; lane < 64; ++lane) {
+    const int li = lane & 15, lq = lane >> 4;
+    for (int i = 0; i < NI; ++i) {
+      chk((4 * i + lq) * ROW + 4 * li, 16 * MC * ROW, "xs stage lo");
+      chk((4 * i + lq) * ROW + 4 * li + 3, 16 * MC * ROW, "xs stage hi");
+    }
+    for (int g = 0; g < MC; ++g)
+      for (int h = 0; h < 4; ++h) chk((16 * g + li) * ROW + 16 * h + 4 * lq + 3, 16 * MC * ROW, "xs read");
+  }
+  const int64_t Mpad = (int64_t)L.mtiles * L.mtile;
+  for (int by = 0; by < L.nsplit; ++by)
+    for (int bx = 0; bx < L.mgroups; ++bx)
+      for (int wave = 0; wave < 4; ++wave) {
+        const int tile0 = bx * L.mper, ntile = std::min(L.mper, L.mtiles - tile0);
+        if (ntile < 1) { printf("  empty group\n"); ++bad; continue; }
+        const int ib = by % L.n_i1blk, jb = by / L.n_i1blk;
+        const int i1_0 = ib * L.i1blk;
+        const int i1n = std::min(L.i1blk, L.I1pad - i1_0);
+        const int64_t j0 = (int64_t)jb * L.jblk;
+        const int jn = (int)std::min((int64_t)L.jblk, L.J - j0);
+        if (jn <= 0 || i1n % KS) { printf("  bad xs block\n"); ++bad; continue; }
+        const int S1 = i1n / KS;
+        const int se = ntile * S1 * jn;
+        for (int t = 0; t < ntile; ++t)
+          for (int lane = 0; lane < 64; ++lane) {
+            const int lq = lane >> 4;
+            for (int g = 0; g < MC; ++g)
+              chk((int64_t)(tile0 + t) * L.mtile + wave * 16 * MC + 16 * g + 4 * lq + 3, Mpad, "xs store");
+          }
+        const int jrot = jn > 1 ? (int)(((unsigned)bx * 5u) % (unsigned)jn) : 0;
+        int tileL = 0, jcntL = 0, tl = 0, jl = jrot;
+        int64_t cw = (int64_t)tile0 * L.mtile + wave * 16 * MC;
+        // D loads, one more for step D, then one for each step that has a successor
+        const int nloads = D + se;
+        for (int q = 0; q < nloads; ++q) {
+          // buffer loads: base e0 (the step's first element of the wave's first
+          // column), range min(I - e0, 2^30 - 1) elements, lane offset
+          // (4i + lq) Ktot + 4li; reads at or past the range return zeros
+          const int64_t e0 = Ktot * cw + (int64_t)L.I1 * (j0 + jl) + i1_0 + KS * tl;
+          const int64_t rem = I - e0;
+          const int64_t nrec = rem <= 0 ? 0 : std::min<int64_t>(rem, 0x3fffffff);
+          for (int lane = 0; lane < 64; ++lane) {
+            const int li = lane & 15, lq = lane >> 4;
+            for (int i = 0; i < NI; ++i) {
+              const int64_t c = cw + 4 * i + lq;
+              const int64_t off = (int64_t)(4 * i + lq) * Ktot + 4 * li;
+              chk(off * 4 + 15, (int64_t)1 << 31, "xs voffset");
+              if (off + 3 < nrec) { chk(e0 + off, I, "xs vec lo"); chk(e0 + off + 3, I, "xs vec hi"); }
+              else if (off < nrec) { printf("  xs load straddles the range\n"); ++bad; }
+              if (c < Mtot && !(off + 3 < nrec)) { printf("  xs load of a real column suppressed\n"); ++bad; }
+            }
+          }
+          if (++tl == S1) { tl = 0; if (++jl == jn) jl = 0;
+            if (ntile > 1 && ++jcntL == jn) { jcntL = 0; if (++tileL == ntile) tileL = 0;
+              cw = (int64_t)(tile0 + tileL) * L.mtile + wave * 16 * MC; } }
+        }
+      }
+}
+
 static int run_case(int dt, int64_t IL, int64_t IR, int I1l, int I1r, int R) {
   const bool f32 = dt == 0;
   const long long bad0 = bad;
@@ -182,8 +258,9 @@ static int run_case(int dt, int64_t IL, int64_t IR, int I1l, int I1r, int R) {
     PmLaunch L = pm_plan(side, dt, IL, IR, side == 0 ? I1l : I1r, Rc, 0);
     if ((int64_t)L.mgroups * L.nsplit * 64 * 4 > 400000000LL) continue;  // too large to walk here
     const int I1 = side == 0 ? I1l : I1r;
-    const bool fast = f32 ? pm_f32_fast(side, IL, I1, L.nb) : pm16_fast(side, IL, I1, L.nb);
+    const bool fast = f32 ? pm_f32_fast(side, IL, I1, L.nb, L.xs) : pm16_fast(side, IL, I1, L.nb);
     if (side == 0) emu_left(L, IL, IR, f32, fast);
+    else if (L.xs) emu_right_xs(L, IL, IR);
     else emu_right(L, IL, IR, f32, fast);
   }
   return bad == bad0 ? 0 : 1;

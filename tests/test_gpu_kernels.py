@@ -57,6 +57,11 @@ PM_CASES = [
     ((1024, 300), 24, 1),        # long reduction, many splits
     ((64, 1040, 8), 32, 1),      # left: three i1 blocks (352, 352, 336 rows) with FP32 chains of 2 steps;
                                  # the short last block has an odd step count (chains must end with each j)
+    # FP32 right node staged through LDS (first mode a multiple of 64, long output):
+    ((64, 5, 8200), 20, 2),      # two M tiles per group, ragged last tile, j rotation
+    ((128, 3, 4500), 50, 2),     # four column blocks (one 16-column group per wave), three tiles per group
+    ((64, 64, 9000), 32, 2),     # split K over three j blocks (FP64 partials)
+    ((128, 2, 8300), 12, 1),     # one column block, J = 1, five tiles per group
 ]
 
 

@@ -25,7 +25,8 @@ SHAPES = [(60, 50, 40), (33, 47, 29), (64, 40, 24, 10), (40, 36, 30), (20, 18, 2
           (3012, 12, 10), (300, 20, 10), (60, 200, 200), (36, 300, 120), (9, 8, 16), (7, 11, 13), (1, 1, 1), (1, 5, 1),
           (2, 3), (5, 1), (1, 7), (3, 1, 2), (12, 10, 9, 8, 7), (1152, 70000), (1030, 66000), (37, 29, 23),
           (200000, 40), (40, 200000), (199999, 37), (37, 199999), (4096, 64, 64), (64, 64, 4096), (1000, 100, 100),
-          (333, 333, 333), (48, 2000, 33), (384, 1400, 16)]
+          (333, 333, 333), (48, 2000, 33), (384, 1400, 16), (128, 128, 128, 128), (64, 64, 64, 200), (640, 30, 500),
+          (64, 5, 8200), (128, 3, 4500), (64, 64, 9000), (128, 2, 8300)]
 
 
 def _cases():
