@@ -66,7 +66,7 @@ struct TNode {
 
 struct Layout {
   size_t off_zeros, off_alpha, off_iter, off_counters, off_lam, off_lammodel, off_lamin, off_G, off_S, off_fit,
-      off_finpart, off_pmpart, off_hpack, off_nspart, off_M, total;
+      off_finpart, off_pmpart, off_hpack, off_sctab, off_nspart, off_M, total;
   int ncounters;
   int node_f64;  // tree temporaries are FP64 for FP32 tensors, FP32 for 16-bit tensors
   // the tree: nodes, and per mode the nodes computed just before its update
@@ -231,6 +231,10 @@ Layout make_layout(const Problem& p) {
   L.off_finpart = take(sizeof(double) * (size_t)maxchunks * (RR + 1));
   L.off_pmpart = take(sizeof(double) * std::max(L.pmL[0].partial_doubles, L.pmL[1].partial_doubles));
   L.off_hpack = take(std::max(L.pmL[0].pack_bytes, L.pmL[1].pack_bytes));
+  // FP32 tensors: the scale table of a partial MTTKRP (the largest root launch)
+  const bool f32 = p.dtype == NNCP_F32;
+  size_t tab = f32 ? std::max(pm_f32_sctab_doubles(L.pmL[0]), pm_f32_sctab_doubles(L.pmL[1])) : 0;
+  L.off_sctab = take(sizeof(double) * tab);
   L.off_nspart = take(sizeof(double) * L.ns_blocks);
   int64_t maxI = 0;
   for (int k = 0; k < N; ++k) maxI = std::max(maxI, p.dims[k]);
@@ -258,6 +262,10 @@ Layout make_layout(const Problem& p) {
       tmax = std::max(tmax, side == 0 ? tl : tr);
       part = std::max(part, L.dpm[n].partial_doubles);
       pack = std::max(pack, L.dpm[n].pack_bytes);
+      if (f32 && pm_f32_sctab_doubles(L.dpm[n]) > tab) {
+        tab = pm_f32_sctab_doubles(L.dpm[n]);
+        L.off_sctab = take(sizeof(double) * tab);  // relocated to fit the no-tree launches too
+      }
     }
     const size_t tb = (size_t)tmax * R * (L.node_f64 ? 8 : 4);
     L.off_dtA = take(tb);
@@ -314,6 +322,7 @@ struct nncp_plan {
   // 16-bit tensors: 64 column scales, then the packed hi/lo first factor
   float* hscale() const { return at<float>(L.off_hpack); }
   unsigned short* hpack() const { return at<unsigned short>(L.off_hpack + 256); }
+  double* sctab() const { return at<double>(L.off_sctab); }
   void* dtA() const { return (void*)(ws + L.off_dtA); }
   void* dtB() const { return (void*)(ws + L.off_dtB); }
   double* nspart() const { return at<double>(L.off_nspart); }
@@ -356,6 +365,7 @@ hipError_t run_pm_at(const nncp_plan* P, int side, int s, const PmLaunch& lp, vo
     a.partial = P->pmpart();
     a.hpack = P->hpack();
     a.hscale = P->hscale();
+    a.sctab = p.dtype == NNCP_F32 ? P->sctab() : nullptr;
     a.zeros = P->zeros();
     a.counters = P->counters();
     const PmLaunch l = (a.R == std::min(kPmMaxCols, p.R)) ? lp : pm_plan(side, p.dtype, IL, IR, I1, a.R, p.wg_kib);

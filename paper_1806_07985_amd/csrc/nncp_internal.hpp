@@ -69,6 +69,11 @@ struct PmArgs {
   // holds the inverse), laid out [term 0 rows RP][term 1 rows RP]... x I1pad
   unsigned short* hpack;
   float* hscale;
+  // FP32 tensors, optional: the per-(j, column) scales of the whole launch,
+  // sctab[j * RP + r] (RP = 16 * nb), written by a pre-kernel before the partial
+  // MTTKRP (pm_launch_f32 launches it); the work-groups then copy their j block
+  // instead of each computing it. nullptr: every group computes its own block.
+  double* sctab;
 };
 
 // 16-bit tensors: the first contracted factor enters the MFMA as a sum of this
@@ -112,6 +117,8 @@ int pm_f32_wave_rows(int side, int nb, bool xs = false);
 int pm_f32_kstep(int side, bool xs = false);
 // LDS of the four waves' staging tiles of the xs form
 size_t pm_f32_xs_tile_lds(int nb);
+// doubles of the scale table of an FP32 launch plan (J x 16 nb)
+size_t pm_f32_sctab_doubles(const PmLaunch& L);
 bool pm_f32_xs_ok(int64_t Ktot, int nb);
 size_t pm_f32_reduce_lds(int side, int nb, int wm);
 hipError_t pm_launch_f32(const PmLaunch& L, const PmArgs& a, const Sink& sk);

@@ -120,11 +120,29 @@ __device__ __forceinline__ void pm_stage_h1(const PmArgs& a, float* hs, int hp, 
 }
 
 // LDS prologue of the FP32 kernels: the first i1 block of H_1 and the
-// per-(j, column) Khatri-Rao scales sc[jj * RP + r] of the group's j block.
+// per-(j, column) Khatri-Rao scales sc[jj * RP + r] of the group's j block,
+// copied from the launch's scale table when there is one (a contiguous run of
+// jn * RP doubles; 16-byte loads, all issued before any is stored), else
+// computed here.
 __device__ __forceinline__ void pm_prologue(const PmArgs& a, float* hs, int hp, double* sc, int RP, int i1_0,
                                             int i1n, int64_t j0, int jn) {
   pm_stage_h1(a, hs, hp, RP, i1_0, i1n);
-  pm_fill_scales<double>(a, sc, RP, j0, jn, nullptr);
+  if (a.sctab) {
+    typedef double d2 __attribute__((ext_vector_type(2)));
+    const d2* src = (const d2*)(a.sctab + j0 * RP);
+    const int total = jn * RP / 2;  // RP is a multiple of 16
+    constexpr int CH = 4;
+    for (int e0 = threadIdx.x; e0 < total; e0 += NT * CH) {
+      d2 v[CH];
+#pragma unroll
+      for (int c = 0; c < CH; ++c) v[c] = src[e0 + NT * c < total ? e0 + NT * c : 0];
+#pragma unroll
+      for (int c = 0; c < CH; ++c)
+        if (e0 + NT * c < total) ((d2*)sc)[e0 + NT * c] = v[c];
+    }
+  } else {
+    pm_fill_scales<double>(a, sc, RP, j0, jn, nullptr);
+  }
 }
 
 // Sum the FP64 accumulators of the WK waves that share an M range through LDS;

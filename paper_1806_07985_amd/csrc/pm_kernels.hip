@@ -806,6 +806,17 @@ __global__ __launch_bounds__(NT, 2) void pm_f32_xs_items(const BItem* __restrict
   }
 }
 
+// The scale table of a launch: sctab[j * RP + r] = Krest(j, col0 + r) times
+// the column's 1/lambda product (0 for r >= R), j < J. The same function of
+// (j, column) the work-groups otherwise evaluate themselves.
+__global__ __launch_bounds__(NT) void pm_scale_table_kernel(PmArgs a, int RP, int64_t n) {
+  const int64_t e = (int64_t)blockIdx.x * NT + threadIdx.x;
+  if (e >= n) return;
+  const int64_t j = e / RP;
+  const int r = (int)(e - j * RP);
+  a.sctab[e] = r < a.R ? krp_scale_entry(a.krp, (uint32_t)j, a.col0 + r) : 0.0;
+}
+
 template <bool MT>
 const void* pick_xs(int nb, bool batch) {
   switch (nb) {
@@ -884,12 +895,23 @@ hipError_t pm_launch_f32(const PmLaunch& L, const PmArgs& a, const Sink& sk) {
     op.gy = (unsigned)L.nsplit;
     op.lds = (unsigned)lds;
     op.u.pm = a;
+    op.u.pm.sctab = nullptr;  // batched groups compute their own scales
     return sink_record(sk, op);
+  }
+  if (a.sctab) {
+    const int RP = 16 * L.nb;
+    int64_t n = L.J * RP;
+    void* targs[] = {(void*)&a, (void*)&RP, (void*)&n};
+    hipError_t e = hipLaunchKernel((const void*)pm_scale_table_kernel, dim3((unsigned)((n + NT - 1) / NT)), dim3(NT),
+                                   targs, 0, sk.st);
+    if (e != hipSuccess) return e;
   }
   if (lds > 64 * 1024) pm_allow_lds(k, 160 * 1024);
   void* args[] = {(void*)&a};
   return hipLaunchKernel(k, dim3(L.mgroups, L.nsplit), dim3(NT), args, lds, sk.st);
 }
+
+size_t pm_f32_sctab_doubles(const PmLaunch& L) { return (size_t)L.J * 16 * L.nb; }
 
 const void* pm_f32_batch_kernel(int variant) {
   const int side = (variant / 1000) % 10, nb = (variant / 100) % 10;
