@@ -231,9 +231,8 @@ Layout make_layout(const Problem& p) {
   L.off_finpart = take(sizeof(double) * (size_t)maxchunks * (RR + 1));
   L.off_pmpart = take(sizeof(double) * std::max(L.pmL[0].partial_doubles, L.pmL[1].partial_doubles));
   L.off_hpack = take(std::max(L.pmL[0].pack_bytes, L.pmL[1].pack_bytes));
-  // FP32 tensors: the scale table of a partial MTTKRP (the largest root launch)
-  const bool f32 = p.dtype == NNCP_F32;
-  size_t tab = f32 ? std::max(pm_f32_sctab_doubles(L.pmL[0]), pm_f32_sctab_doubles(L.pmL[1])) : 0;
+  // the scale table of a partial MTTKRP (the largest root launch)
+  size_t tab = std::max(pm_sctab_doubles(L.pmL[0]), pm_sctab_doubles(L.pmL[1]));
   L.off_sctab = take(sizeof(double) * tab);
   L.off_nspart = take(sizeof(double) * L.ns_blocks);
   int64_t maxI = 0;
@@ -262,8 +261,8 @@ Layout make_layout(const Problem& p) {
       tmax = std::max(tmax, side == 0 ? tl : tr);
       part = std::max(part, L.dpm[n].partial_doubles);
       pack = std::max(pack, L.dpm[n].pack_bytes);
-      if (f32 && pm_f32_sctab_doubles(L.dpm[n]) > tab) {
-        tab = pm_f32_sctab_doubles(L.dpm[n]);
+      if (pm_sctab_doubles(L.dpm[n]) > tab) {
+        tab = pm_sctab_doubles(L.dpm[n]);
         L.off_sctab = take(sizeof(double) * tab);  // relocated to fit the no-tree launches too
       }
     }
@@ -365,7 +364,7 @@ hipError_t run_pm_at(const nncp_plan* P, int side, int s, const PmLaunch& lp, vo
     a.partial = P->pmpart();
     a.hpack = P->hpack();
     a.hscale = P->hscale();
-    a.sctab = p.dtype == NNCP_F32 ? P->sctab() : nullptr;
+    a.sctab = P->sctab();
     a.zeros = P->zeros();
     a.counters = P->counters();
     const PmLaunch l = (a.R == std::min(kPmMaxCols, p.R)) ? lp : pm_plan(side, p.dtype, IL, IR, I1, a.R, p.wg_kib);

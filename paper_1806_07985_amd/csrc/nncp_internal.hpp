@@ -69,9 +69,9 @@ struct PmArgs {
   // holds the inverse), laid out [term 0 rows RP][term 1 rows RP]... x I1pad
   unsigned short* hpack;
   float* hscale;
-  // FP32 tensors, optional: the per-(j, column) scales of the whole launch,
+  // Optional: the per-(j, column) Khatri-Rao scales of the whole launch in FP64,
   // sctab[j * RP + r] (RP = 16 * nb), written by a pre-kernel before the partial
-  // MTTKRP (pm_launch_f32 launches it); the work-groups then copy their j block
+  // MTTKRP (the launchers run it); the work-groups then copy their j block
   // instead of each computing it. nullptr: every group computes its own block.
   double* sctab;
 };
@@ -117,8 +117,10 @@ int pm_f32_wave_rows(int side, int nb, bool xs = false);
 int pm_f32_kstep(int side, bool xs = false);
 // LDS of the four waves' staging tiles of the xs form
 size_t pm_f32_xs_tile_lds(int nb);
-// doubles of the scale table of an FP32 launch plan (J x 16 nb)
-size_t pm_f32_sctab_doubles(const PmLaunch& L);
+// doubles of the scale table of a launch plan (J x 16 nb), and the pre-kernel
+// that writes it (a.sctab, a.krp, a.R, a.col0)
+size_t pm_sctab_doubles(const PmLaunch& L);
+hipError_t pm_scale_table_launch(const PmLaunch& L, const PmArgs& a, hipStream_t st);
 bool pm_f32_xs_ok(int64_t Ktot, int nb);
 size_t pm_f32_reduce_lds(int side, int nb, int wm);
 hipError_t pm_launch_f32(const PmLaunch& L, const PmArgs& a, const Sink& sk);

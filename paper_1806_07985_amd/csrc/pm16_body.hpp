@@ -111,9 +111,38 @@ __device__ __forceinline__ void pack_body(const PackArgs& pa, int r) {
 }
 
 // Per-(j, column) factors of a work-group's j block: Krest(j0 + jj, col0 + r)
-// times the column's 1/lambda product times the pack scale, in FP32.
+// times the column's 1/lambda product times the pack scale, in FP32: from the
+// launch's FP64 scale table when there is one (the product and the rounding to
+// FP32 are then done here, as pm_fill_scales does them), else computed here.
 __device__ __forceinline__ void scales(const PmArgs& a, float* sc, int RP, int64_t j0, int jn) {
-  pm_fill_scales<float>(a, sc, RP, j0, jn, a.hscale);
+  if (!a.sctab) {
+    pm_fill_scales<float>(a, sc, RP, j0, jn, a.hscale);
+    return;
+  }
+  typedef double d2 __attribute__((ext_vector_type(2)));
+  const d2* src = (const d2*)(a.sctab + j0 * RP);
+  const int total = jn * RP / 2;  // RP is a multiple of 16
+  constexpr int CH = 4;
+  for (int e0 = threadIdx.x; e0 < total; e0 += NT * CH) {
+    d2 v[CH];
+    float hs[CH][2];
+#pragma unroll
+    for (int c = 0; c < CH; ++c) {
+      const int e = e0 + NT * c < total ? e0 + NT * c : 0;
+      v[c] = src[e];
+      const int r = (2 * e) % RP;  // even: r and r + 1 lie in one row
+      hs[c][0] = a.hscale[r < a.R ? r : 0];
+      hs[c][1] = a.hscale[r + 1 < a.R ? r + 1 : 0];
+    }
+#pragma unroll
+    for (int c = 0; c < CH; ++c)
+      if (e0 + NT * c < total) {
+        const int e = e0 + NT * c;
+        const int r = (2 * e) % RP;
+        sc[2 * e] = r < a.R ? (float)(v[c][0] * (double)hs[c][0]) : 0.f;
+        sc[2 * e + 1] = r + 1 < a.R ? (float)(v[c][1] * (double)hs[c][1]) : 0.f;
+      }
+  }
 }
 
 // Copy rows [i1_0, i1_0 + i1n) of the NTM packed factor terms into LDS (pitch

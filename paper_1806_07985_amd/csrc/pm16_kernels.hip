@@ -77,7 +77,12 @@ hipError_t pm_launch_16(const PmLaunch& L, const PmArgs& a, const Sink& sk) {
     pm.gy = (unsigned)L.nsplit;
     pm.lds = (unsigned)lds;
     pm.u.pm = a;
+    pm.u.pm.sctab = nullptr;  // batched groups compute their own scales
     return sink_record(sk, pm);
+  }
+  if (a.sctab) {
+    hipError_t e = pm_scale_table_launch(L, a, sk.st);
+    if (e != hipSuccess) return e;
   }
   {
     void* pargs[] = {(void*)&pa};

@@ -899,11 +899,7 @@ hipError_t pm_launch_f32(const PmLaunch& L, const PmArgs& a, const Sink& sk) {
     return sink_record(sk, op);
   }
   if (a.sctab) {
-    const int RP = 16 * L.nb;
-    int64_t n = L.J * RP;
-    void* targs[] = {(void*)&a, (void*)&RP, (void*)&n};
-    hipError_t e = hipLaunchKernel((const void*)pm_scale_table_kernel, dim3((unsigned)((n + NT - 1) / NT)), dim3(NT),
-                                   targs, 0, sk.st);
+    hipError_t e = pm_scale_table_launch(L, a, sk.st);
     if (e != hipSuccess) return e;
   }
   if (lds > 64 * 1024) pm_allow_lds(k, 160 * 1024);
@@ -911,7 +907,16 @@ hipError_t pm_launch_f32(const PmLaunch& L, const PmArgs& a, const Sink& sk) {
   return hipLaunchKernel(k, dim3(L.mgroups, L.nsplit), dim3(NT), args, lds, sk.st);
 }
 
-size_t pm_f32_sctab_doubles(const PmLaunch& L) { return (size_t)L.J * 16 * L.nb; }
+size_t pm_sctab_doubles(const PmLaunch& L) { return (size_t)L.J * 16 * L.nb; }
+
+hipError_t pm_scale_table_launch(const PmLaunch& L, const PmArgs& a, hipStream_t st) {
+  int RP = 16 * L.nb;
+  int64_t n = L.J * RP;
+  PmArgs b = a;
+  void* targs[] = {(void*)&b, (void*)&RP, (void*)&n};
+  return hipLaunchKernel((const void*)pm_scale_table_kernel, dim3((unsigned)((n + NT - 1) / NT)), dim3(NT), targs, 0,
+                         st);
+}
 
 const void* pm_f32_batch_kernel(int variant) {
   const int side = (variant / 1000) % 10, nb = (variant / 100) % 10;
