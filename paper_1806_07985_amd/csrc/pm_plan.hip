@@ -160,17 +160,24 @@ static PmLaunch plan_impl(int side, int dtype, int64_t IL, int64_t IR, int I1, i
   const int64_t min_j = cdiv(8 * (4 / wm), steps_per_j);
   int64_t jblk = cdiv(L.J, n_jblk < 1 ? 1 : n_jblk);
   if (jblk < min_j) jblk = min_j;
-  if (jblk > jblk_cap(dtype, RP, L.i1blk, 64, L.wide, xs_tiles)) {
-    // at most 64 j per group (the scales are a prologue of jblk * RP products),
-    // unless that leaves a few groups beyond the target -- a second, mostly
-    // idle round for a 16-bit kernel (one group per CU): then up to 128
-    const int64_t over = L.mgroups * n_i1grp * cdiv(L.J, jblk_cap(dtype, RP, L.i1blk, 64, L.wide, xs_tiles));
+  // at most 64 j per group (a group's scales are a prologue of jblk * RP
+  // values: copied from the launch's table, or computed where there is none),
+  // or 128 for an FP32 launch that still has two rounds of groups or more with
+  // it (the 64^5 left node: 4096 -> 2048 groups, 0.85 -> 0.76 ms; fewer groups
+  // than that would leave CUs unevenly loaded), unless that leaves a few groups
+  // beyond the target -- a second, mostly idle round for a 16-bit kernel (one
+  // group per CU): then up to 128
+  int jlim = 64;
+  if (f32 && L.mgroups * n_i1grp * cdiv(L.J, jblk_cap(dtype, RP, L.i1blk, 128, L.wide, xs_tiles)) >= 2 * 2 * target)
+    jlim = 128;
+  if (jblk > jblk_cap(dtype, RP, L.i1blk, jlim, L.wide, xs_tiles)) {
+    const int64_t over = L.mgroups * n_i1grp * cdiv(L.J, jblk_cap(dtype, RP, L.i1blk, jlim, L.wide, xs_tiles));
     const int64_t room = target / (L.mgroups * n_i1grp);
     if (dtype != NNCP_F32 && over > target && over < 2 * target && room >= 1 &&
         cdiv(L.J, room) <= jblk_cap(dtype, RP, L.i1blk, 128, L.wide, xs_tiles))
       jblk = cdiv(L.J, room);
     else
-      jblk = jblk_cap(dtype, RP, L.i1blk, 64, L.wide, xs_tiles);
+      jblk = jblk_cap(dtype, RP, L.i1blk, jlim, L.wide, xs_tiles);
   }
   if (jblk > L.J) jblk = L.J;
   if (jblk < 1) jblk = 1;
@@ -234,7 +241,7 @@ size_t pm_variant_max_lds(int kind, int variant) {
   const int ks = f32 ? pm_f32_kstep(side, xs) : pm_16_kstep(side);
   size_t lds = 0;
   for (int rows = ks; rows <= lds_rows(dtype, RP, ks, wide, xs); rows += ks) {
-    const size_t b = lds_for(dtype, RP, rows, jblk_cap(dtype, RP, rows, f32 ? 64 : 128, wide, xs_tiles)) + xs_tiles;
+    const size_t b = lds_for(dtype, RP, rows, jblk_cap(dtype, RP, rows, 128, wide, xs_tiles)) + xs_tiles;
     if (b > lds) lds = b;
   }
   const size_t red = f32 ? pm_f32_reduce_lds(side, nb, 1) : pm_16_reduce_lds(side, nb, 1);
