@@ -196,7 +196,7 @@ __device__ __forceinline__ void reduce_waves(float (&accf)[NACC][4], double* lds
 // Rows per left wave = 16 * TR, columns per right wave = 16 * MC.
 constexpr int left_tr16(int nb) { return nb >= 4 ? 4 : 8; }
 constexpr int right_mc16(int nb) { return 4; }
-constexpr int right_mc16_j1(int nb) { return 8; }
+constexpr int right_mc16_j1(int nb) { return nb >= 4 ? 9 : 8; }
 constexpr int right_pf16_j1(int nb) { return nb >= 4 ? 2 : 3; }
 constexpr int left_pf16(int nb) { return 3; }
 constexpr int right_pf16(int nb) { return 3; }

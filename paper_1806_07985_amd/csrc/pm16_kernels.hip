@@ -17,7 +17,7 @@ namespace {
 
 constexpr int left_tr16(int nb) { return nb >= 4 ? 4 : 8; }
 constexpr int right_mc16(int nb) { return 4; }
-constexpr int right_mc16_j1(int nb) { return 8; }
+constexpr int right_mc16_j1(int nb) { return nb >= 4 ? 9 : 8; }
 
 const void* kernel16(int dtype, int side, int nb, int j1, int fast, int mt, bool batch) {
   if (dtype == NNCP_BF16)
