@@ -262,6 +262,15 @@ static int run_case(int dt, int64_t IL, int64_t IR, int I1l, int I1r, int R) {
     if (side == 0) emu_left(L, IL, IR, f32, fast);
     else if (L.xs) emu_right_xs(L, IL, IR);
     else emu_right(L, IL, IR, f32, fast);
+    if (!f32 && side == 1) {
+      // 16-bit right node: the staged factor terms (RP columns each, pitch
+      // i1blk + 8) and the j block's scales, as the kernel lays them out, fit
+      // the launch's LDS
+      const int RP = 16 * L.nb;
+      const int64_t need = (int64_t)pm16_terms(dt) * RP * (L.i1blk + 8) * 2 + (int64_t)L.jblk * RP * 4;
+      chk(need - 1, (int64_t)L.lds_bytes, "16-bit right lds");
+      chk((int64_t)L.lds_bytes - 1, (int64_t)kPmMaxLds, "lds max");
+    }
   }
   return bad == bad0 ? 0 : 1;
 }
