@@ -1508,6 +1508,11 @@ BatchKernel batch_kernel_for(int kind, int variant) {
       k.threads = 256;
       k.per_cu = 4;
       break;
+    case K_SCTAB:
+      k.fn = pm_sctab_batch_kernel();
+      k.threads = 256;
+      k.per_cu = groups_per_cu(k.fn, 256, 0, 8);
+      break;
     case K_FIN1K: case K_GRAM1K: case K_TAIL1K:
       k.fn = fin_batch_kernel_ptr();
       k.threads = 1024;

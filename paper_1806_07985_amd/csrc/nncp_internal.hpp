@@ -121,6 +121,9 @@ size_t pm_f32_xs_tile_lds(int nb);
 // that writes it (a.sctab, a.krp, a.R, a.col0)
 size_t pm_sctab_doubles(const PmLaunch& L);
 hipError_t pm_scale_table_launch(const PmLaunch& L, const PmArgs& a, hipStream_t st);
+// the same pre-kernel recorded into a batch (slot 0, before the partial MTTKRP)
+hipError_t pm_scale_table_record(const PmLaunch& L, const PmArgs& a, const Sink& sk);
+const void* pm_sctab_batch_kernel();
 bool pm_f32_xs_ok(int64_t Ktot, int nb);
 size_t pm_f32_reduce_lds(int side, int nb, int wm);
 hipError_t pm_launch_f32(const PmLaunch& L, const PmArgs& a, const Sink& sk);
@@ -267,7 +270,8 @@ enum KKind : int {
   K_FIN_TAIL = 11,
   K_FIN1K = 12,     // R <= 64, one row chunk, 1024 threads; variant: R x R entries per thread
   K_GRAM1K = 13,    // R <= 64, one row chunk's Gram partial, 1024 threads; variant as K_FIN1K
-  K_TAIL1K = 14     // R <= 64, sum of the chunk partials and the finish, 1024 threads
+  K_TAIL1K = 14,    // R <= 64, sum of the chunk partials and the finish, 1024 threads
+  K_SCTAB = 15      // a partial MTTKRP's scale table (u.pm); variant: 16 * column blocks
 };
 struct KOp {
   int kind;
@@ -309,7 +313,7 @@ struct Sink {
 constexpr int kStepUpdate = 13, kStepFinal = 14;
 inline int kslot(int kind) {
   switch (kind) {
-    case K_PACK16: return 0;
+    case K_PACK16: case K_SCTAB: return 0;
     case K_PM_F32: case K_PM_16: case K_MTTV_LEAD: case K_MTTV_TRAIL: case K_UPDATE: return 1;
     case K_PM_REDUCE: return 2;
     case K_GRAM_CHUNKS: case K_GRAM1K: return 0;

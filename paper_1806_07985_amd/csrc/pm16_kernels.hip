@@ -77,7 +77,10 @@ hipError_t pm_launch_16(const PmLaunch& L, const PmArgs& a, const Sink& sk) {
     pm.gy = (unsigned)L.nsplit;
     pm.lds = (unsigned)lds;
     pm.u.pm = a;
-    pm.u.pm.sctab = nullptr;  // batched groups compute their own scales
+    if (a.sctab) {
+      e = pm_scale_table_record(L, a, sk);
+      if (e != hipSuccess) return e;
+    }
     return sink_record(sk, pm);
   }
   if (a.sctab) {

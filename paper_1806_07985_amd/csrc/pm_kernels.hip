@@ -809,12 +809,31 @@ __global__ __launch_bounds__(NT, 2) void pm_f32_xs_items(const BItem* __restrict
 // The scale table of a launch: sctab[j * RP + r] = Krest(j, col0 + r) times
 // the column's 1/lambda product (0 for r >= R), j < J. The same function of
 // (j, column) the work-groups otherwise evaluate themselves.
-__global__ __launch_bounds__(NT) void pm_scale_table_kernel(PmArgs a, int RP, int64_t n) {
-  const int64_t e = (int64_t)blockIdx.x * NT + threadIdx.x;
+__device__ __forceinline__ void scale_table_block(const PmArgs& a, int RP, int64_t n, int64_t blk) {
+  const int64_t e = blk * NT + threadIdx.x;
   if (e >= n) return;
   const int64_t j = e / RP;
   const int r = (int)(e - j * RP);
   a.sctab[e] = r < a.R ? krp_scale_entry(a.krp, (uint32_t)j, a.col0 + r) : 0.0;
+}
+__global__ __launch_bounds__(NT) void pm_scale_table_kernel(PmArgs a, int RP, int64_t n) {
+  scale_table_block(a, RP, n, blockIdx.x);
+}
+// Batched form: an item runs `coarse` consecutive blocks of one recorded table.
+__global__ __launch_bounds__(NT) void pm_scale_table_items(const BItem* __restrict__ items,
+                                                           const int* __restrict__ grp,
+                                                           const KOp* __restrict__ ops) {
+  const int off = grp[0], n = grp[1];
+  for (int i = blockIdx.x; i < n; i += gridDim.x) {
+    const BItem it = items[off + i];
+    const KOp& op = ops[it.op];
+    const int RP = op.variant;
+    const int64_t tot = op.u.pm.J * RP;
+    for (unsigned c = 0; c < op.coarse; ++c) {
+      const int64_t b = (int64_t)it.bx * op.coarse + c;
+      if (b < (int64_t)op.gx) scale_table_block(op.u.pm, RP, tot, b);
+    }
+  }
 }
 
 template <bool MT>
@@ -895,7 +914,10 @@ hipError_t pm_launch_f32(const PmLaunch& L, const PmArgs& a, const Sink& sk) {
     op.gy = (unsigned)L.nsplit;
     op.lds = (unsigned)lds;
     op.u.pm = a;
-    op.u.pm.sctab = nullptr;  // batched groups compute their own scales
+    if (a.sctab) {
+      hipError_t e = pm_scale_table_record(L, a, sk);
+      if (e != hipSuccess) return e;
+    }
     return sink_record(sk, op);
   }
   if (a.sctab) {
@@ -908,6 +930,20 @@ hipError_t pm_launch_f32(const PmLaunch& L, const PmArgs& a, const Sink& sk) {
 }
 
 size_t pm_sctab_doubles(const PmLaunch& L) { return (size_t)L.J * 16 * L.nb; }
+
+hipError_t pm_scale_table_record(const PmLaunch& L, const PmArgs& a, const Sink& sk) {
+  const int RP = 16 * L.nb;
+  const int64_t n = L.J * RP;
+  KOp op{};
+  op.kind = K_SCTAB;
+  op.variant = RP;
+  op.gx = (unsigned)((n + NT - 1) / NT);
+  op.gy = 1;
+  op.u.pm = a;
+  return sink_record(sk, op);
+}
+
+const void* pm_sctab_batch_kernel() { return (const void*)pm_scale_table_items; }
 
 hipError_t pm_scale_table_launch(const PmLaunch& L, const PmArgs& a, hipStream_t st) {
   int RP = 16 * L.nb;
