@@ -38,10 +38,10 @@ static int64_t target_wgs(int64_t x_bytes, int wg_kib) {
 // CU; `wide`: 140 KB, one group per CU; `xs`: 96 KB beside the X staging tiles),
 // or the 16-bit term rows in up to 128 KB (two terms) or 150 KB (three terms;
 // one group per CU).
-static int lds_rows(int dtype, int RP, int ks, bool wide = false, bool xs = false) {
+static int lds_rows(int dtype, int RP, int ks, bool wide = false, bool xs = false, bool jone = false) {
   const bool f32 = dtype == NNCP_F32;
   const int row_bytes = f32 ? RP * 4 : RP * 2 * pm16_terms(dtype);
-  const int budget = f32 ? (xs ? 96 * 1024 : (wide ? 140 * 1024 : 48 * 1024))
+  const int budget = f32 ? (xs ? 96 * 1024 : (wide ? 140 * 1024 : (jone ? 72 * 1024 : 48 * 1024)))
                          : (pm16_terms(dtype) == 2 ? 128 * 1024 : 150 * 1024);
   int maxrows = budget / row_bytes / ks * ks;
   return maxrows < ks ? ks : maxrows;
@@ -89,7 +89,8 @@ static PmLaunch plan_impl(int side, int dtype, int64_t IL, int64_t IR, int I1, i
   L.I1 = I1;
   L.J = Ktot / I1;
   L.I1pad = (int)cdiv(I1, ks) * ks;
-  int maxrows = lds_rows(dtype, RP, ks, false, xs);
+  // (an FP32 launch with J == 1 keeps one j of scales: its H_1 block may take 72 KB)
+  int maxrows = lds_rows(dtype, RP, ks, false, xs, L.J == 1);
   // An FP32 right node whose whole first contracted mode fits one CU's LDS but
   // not half of it takes the CU alone (wide): one i1 block, so no restaging
   // of LDS and no split K across i1 blocks (1024^3: the right node 1.18 ->
@@ -242,6 +243,11 @@ size_t pm_variant_max_lds(int kind, int variant) {
   size_t lds = 0;
   for (int rows = ks; rows <= lds_rows(dtype, RP, ks, wide, xs); rows += ks) {
     const size_t b = lds_for(dtype, RP, rows, jblk_cap(dtype, RP, rows, 128, wide, xs_tiles)) + xs_tiles;
+    if (b > lds) lds = b;
+  }
+  // launches with J == 1: one j of scales beside a possibly larger H_1 block
+  for (int rows = ks; rows <= lds_rows(dtype, RP, ks, wide, xs, true); rows += ks) {
+    const size_t b = lds_for(dtype, RP, rows, 1) + xs_tiles;
     if (b > lds) lds = b;
   }
   const size_t red = f32 ? pm_f32_reduce_lds(side, nb, 1) : pm_16_reduce_lds(side, nb, 1);

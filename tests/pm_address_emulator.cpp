@@ -262,6 +262,14 @@ static int run_case(int dt, int64_t IL, int64_t IR, int I1l, int I1r, int R) {
     if (side == 0) emu_left(L, IL, IR, f32, fast);
     else if (L.xs) emu_right_xs(L, IL, IR);
     else emu_right(L, IL, IR, f32, fast);
+    {
+      // a batched launch of this plan's kernel variant reserves at least the
+      // plan's LDS (the variant's maximum over every plan it can run)
+      const int kind = f32 ? K_PM_F32 : K_PM_16;
+      const int var = f32 ? (L.xs ? 100000 : 0) + (L.wide ? 10000 : 0) + side * 1000 + L.nb * 100
+                          : (L.j1 ? 100000 : 0) + (dt == NNCP_BF16 ? 10000 : 0) + side * 1000 + L.nb * 100;
+      chk((int64_t)L.lds_bytes - 1, (int64_t)pm_variant_max_lds(kind, var), "batch variant lds");
+    }
     if (!f32 && side == 1) {
       // 16-bit right node: the staged factor terms (RP columns each, pitch
       // i1blk + 8) and the j block's scales, as the kernel lays them out, fit
