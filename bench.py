@@ -347,7 +347,9 @@ def _serving_study(dev, n_pool, n_sat, n_jobs, load_fracs, iters, budget_gb, max
                     p50_device_s=pct(dev_lat, 50), p99_device_s=pct(dev_lat, 99),
                     peak_active=st["peak_active"], ticks=st["ticks"],
                     busy_frac=st["busy_s"] / max(span, 1e-9), peak_GB=st["peak_bytes"] / 1e9,
-                    graph_captures=st["graph_captures"], list_updates=st["list_updates"])
+                    graph_captures=st["graph_captures"], list_updates=st["list_updates"],
+                    rebuild_s=st["rebuild_s"], graph_build_s=st["graph_s"],
+                    rebuild_frac_of_busy=st["rebuild_s"] / max(st["busy_s"], 1e-9))
 
     entries_mean = float(np.mean([p_["entries"] for p_ in pool]))
     sat = run(n_sat, None)

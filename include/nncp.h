@@ -227,6 +227,11 @@ int nncp_batch_stats(const nncp_batch* batch, int* launches, int64_t* items);
  * launch (a step of its iteration on a kernel variant) that the captured graph
  * does not have, or a list outgrows its device buffer. Either output may be NULL. */
 int nncp_batch_captures(const nncp_batch* batch, int64_t* captures, int64_t* list_updates);
+/* Host seconds spent between ticks since the batch was created: rewriting the
+ * work lists after membership changes (re-recording every member's iteration
+ * and uploading the lists; the graph builds included) and building the tick's
+ * graph. Either output may be NULL. */
+int nncp_batch_build_time(const nncp_batch* batch, double* rebuild_s, double* graph_s);
 int nncp_batch_destroy(nncp_batch* batch);   /* does not destroy the member plans */
 
 /* ---- Serving: continuous batching of jobs that arrive over time ----
@@ -267,6 +272,7 @@ typedef struct nncp_server_stats {
   double busy_s, now_s;     /* time spent in ticks; server clock now */
   int64_t graph_captures;   /* captures of the batch's tick graph (see nncp_batch_captures) */
   int64_t list_updates;     /* rewrites of its device work lists (membership changes) */
+  double rebuild_s, graph_s; /* host time in those rewrites and graph builds (nncp_batch_build_time) */
 } nncp_server_stats;
 int nncp_server_create(nncp_server** server, size_t hbm_budget_bytes, int max_active, int flags);
 int nncp_server_submit(nncp_server* server, const nncp_job_request* req, uint64_t* id);

@@ -18,6 +18,7 @@
 #include <algorithm>
 #include <cmath>
 #include <atomic>
+#include <chrono>
 #include <cstring>
 #include <functional>
 #include <map>
@@ -1241,6 +1242,7 @@ struct nncp_batch {
   hipGraphExec_t gexec = nullptr;
   size_t n_items = 0;
   int64_t captures = 0, list_updates = 0;
+  double rebuild_s = 0.0, graph_s = 0.0;  // host time: list rewrites (graph builds included), graph builds
 };
 
 namespace {
@@ -1394,6 +1396,7 @@ int batch_build(nncp_batch* B) {
   // of one stage are independent (different members, or independent ops of one
   // member), so a stage's launches depend only on all launches of the stage
   // before and may overlap one another's tails.
+  const auto tg = std::chrono::steady_clock::now();
   batch_drop_graph(B);
   B->launches = L;
   const unsigned cus = (unsigned)device_cus();
@@ -1440,6 +1443,7 @@ int batch_build(nncp_batch* B) {
     return NNCP_EDEVICE;
   }
   ++B->captures;
+  B->graph_s += std::chrono::duration<double>(std::chrono::steady_clock::now() - tg).count();
   return NNCP_OK;
 }
 
@@ -1582,7 +1586,9 @@ int nncp_batch_run(nncp_batch* B, int ticks) {
   if (B->dirty) {
     // members may have been set up on the caller's stream
     HIPCHK(hipStreamSynchronize(B->st));
+    const auto t0 = std::chrono::steady_clock::now();
     int r = batch_build(B);
+    B->rebuild_s += std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
     if (r != NNCP_OK) return r;
   }
   HIPCHK(hipEventRecord(B->ev[0], B->st));
@@ -1605,6 +1611,13 @@ int nncp_batch_captures(const nncp_batch* B, int64_t* captures, int64_t* list_up
   if (!B) return NNCP_EINVAL;
   if (captures) *captures = B->captures;
   if (list_updates) *list_updates = B->list_updates;
+  return NNCP_OK;
+}
+
+int nncp_batch_build_time(const nncp_batch* B, double* rebuild_s, double* graph_s) {
+  if (!B) return NNCP_EINVAL;
+  if (rebuild_s) *rebuild_s = B->rebuild_s;
+  if (graph_s) *graph_s = B->graph_s;
   return NNCP_OK;
 }
 

@@ -465,11 +465,14 @@ int nncp_server_get_stats(nncp_server* S, nncp_server_stats* out) {
   out->now_s = S->now();
   out->graph_captures = 0;
   out->list_updates = 0;
+  out->rebuild_s = 0.0;
+  out->graph_s = 0.0;
   if (S->batch) {
     int64_t c = 0, u = 0;
     nncp_batch_captures(S->batch, &c, &u);
     out->graph_captures = c;
     out->list_updates = u;
+    nncp_batch_build_time(S->batch, &out->rebuild_s, &out->graph_s);
   }
   return NNCP_OK;
 }

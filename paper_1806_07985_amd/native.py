@@ -59,7 +59,7 @@ class ServerStats(ctypes.Structure):
                 ("ticks", ctypes.c_int64), ("completed", ctypes.c_int64), ("rejected", ctypes.c_int64),
                 ("bytes_in_use", ctypes.c_size_t), ("peak_bytes", ctypes.c_size_t), ("budget_bytes", ctypes.c_size_t),
                 ("busy_s", ctypes.c_double), ("now_s", ctypes.c_double), ("graph_captures", ctypes.c_int64),
-                ("list_updates", ctypes.c_int64)]
+                ("list_updates", ctypes.c_int64), ("rebuild_s", ctypes.c_double), ("graph_s", ctypes.c_double)]
 
 
 class NNCPError(RuntimeError):
@@ -159,6 +159,8 @@ def _declare(L):
     L.nncp_batch_stats.argtypes = [c_vp, ctypes.POINTER(ctypes.c_int), ctypes.POINTER(ctypes.c_int64)]
     L.nncp_batch_captures.restype = ctypes.c_int
     L.nncp_batch_captures.argtypes = [c_vp, ctypes.POINTER(ctypes.c_int64), ctypes.POINTER(ctypes.c_int64)]
+    L.nncp_batch_build_time.restype = ctypes.c_int
+    L.nncp_batch_build_time.argtypes = [c_vp, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_double)]
     L.nncp_batch_destroy.restype = ctypes.c_int
     L.nncp_batch_destroy.argtypes = [c_vp]
     L.nncp_server_create.restype = ctypes.c_int
@@ -457,8 +459,11 @@ class Batch:
         cap = ctypes.c_int64(0)
         upd = ctypes.c_int64(0)
         _check(lib().nncp_batch_captures(self._h, ctypes.byref(cap), ctypes.byref(upd)), "nncp_batch_captures")
+        rb = ctypes.c_double(0.0)
+        gs = ctypes.c_double(0.0)
+        _check(lib().nncp_batch_build_time(self._h, ctypes.byref(rb), ctypes.byref(gs)), "nncp_batch_build_time")
         return dict(launches_per_tick=n.value, items_per_tick=it.value, graph_captures=cap.value,
-                    list_updates=upd.value)
+                    list_updates=upd.value, rebuild_s=rb.value, graph_s=gs.value)
 
     def close(self):
         if getattr(self, "_h", None):

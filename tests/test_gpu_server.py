@@ -127,6 +127,8 @@ def test_membership_changes_rewrite_lists_without_capturing(gpu_lib):
     assert st["peak_active"] >= 2
     assert st["graph_captures"] == 1
     assert st["list_updates"] >= 4
+    # host time between ticks: list rewrites, the one graph build among them
+    assert 0.0 < st["graph_s"] <= st["rebuild_s"]
     for k in (0, 6):
         Xh, H0, it = specs[k]
         Hd = [native.factor_to_device(h) for h in H0]
