@@ -64,20 +64,20 @@ def test_c2_trajectory_50(c2_data, update):
     _compare(g, o, 1e-5)
 
 
-def _row_mttkrp(sl, hs):
-    """sum over the slice's modes of sl * prod_k hs[k][i_k, r], for every r (FP64):
-    contract the last mode with its factor, then the others diagonally in r."""
-    T = np.tensordot(sl, hs[-1], axes=([sl.ndim - 1], [0]))
-    for h in reversed(hs[:-1]):
-        T = np.einsum("...kr,kr->...r", T, h)
-    return T
+def _row_mttkrp(sl, n, H64):
+    """Row i of mode n's MTTKRP from slice i of the tensor (all modes but n), by
+    the oracle's direct MTTKRP of that slice kept as a tensor whose mode n has
+    extent 1: row i of M^(n) depends on slice i and the other factors only."""
+    Xs = np.expand_dims(sl, n)
+    Hs = [h if k != n else np.zeros((1, h.shape[1])) for k, h in enumerate(H64)]
+    return O.mttkrp_direct(Xs, Hs, n)[0]
 
 
 @pytest.mark.parametrize("dims", [(1024, 1024, 1024), (64, 64, 64, 64, 64)])
 def test_large_workload_sampled_mttkrp_rows(gpu_lib, dims):
     """The paper's 1024^3 and 64^5 workloads at full size: sampled rows of every
-    mode's tree MTTKRP against FP64 sums on the host (the whole oracle MTTKRP
-    would take minutes per mode at this size)."""
+    mode's tree MTTKRP against the FP64 oracle's direct MTTKRP of the row's
+    slice (the whole oracle MTTKRP would take minutes per mode at this size)."""
     import torch
     from paper_1806_07985_amd import native
     R = 32
@@ -92,12 +92,11 @@ def test_large_workload_sampled_mttkrp_rows(gpu_lib, dims):
     rng = np.random.default_rng(5)
     for n in range(N):
         M = native.mttkrp(X, list(dims), s, n, Hd, R).cpu().numpy().T     # I_n x R
-        others = [H64[k] for k in range(N) if k != n]
         print(f"  mode {n}", flush=True)
         for i in rng.choice(dims[n], size=3, replace=False):
             sl = Xh[(slice(None),) * n + (int(i),)].astype(np.float64)   # a strided view, then one copy
-            ref = _row_mttkrp(sl, others)
-            bound = _row_mttkrp(np.abs(sl), others)
+            ref = _row_mttkrp(sl, n, H64)
+            bound = _row_mttkrp(np.abs(sl), n, H64)      # (the factors are nonnegative)
             err = np.abs(M[i] - ref)
             assert np.all(err <= 1e-6 * bound), (n, int(i), float(np.max(err / bound)))
     del X
@@ -106,8 +105,8 @@ def test_large_workload_sampled_mttkrp_rows(gpu_lib, dims):
 
 def test_fmri_shaped_bf16_sampled_mttkrp_rows(gpu_lib):
     """The paper's 30012 x 1200 x 500 fMRI tensor shape at full size, stored in
-    BF16 (36 GB), rank 10: sampled rows of every mode's tree MTTKRP against FP64
-    sums over the same BF16 values on the host. Slices are cut on the device
+    BF16 (36 GB), rank 10: sampled rows of every mode's tree MTTKRP against the
+    FP64 oracle's direct MTTKRP of the row's slice (the same BF16 values). Slices are cut on the device
     (the whole tensor is never copied to the host). Bound: the 16-bit path's
     2e-5 of sum |x||k| (FP32 MFMA accumulation)."""
     import torch
@@ -124,7 +123,6 @@ def test_fmri_shaped_bf16_sampled_mttkrp_rows(gpu_lib):
     worst = 0.0
     for n in range(3):
         M = native.mttkrp(X, list(dims), s, n, Hd, R).cpu().numpy().T     # I_n x R
-        others = [H64[k] for k in range(3) if k != n]
         for i in rng.choice(dims[n], size=2, replace=False):
             i = int(i)
             if n == 0:
@@ -133,8 +131,8 @@ def test_fmri_shaped_bf16_sampled_mttkrp_rows(gpu_lib):
                 sl = X3[:, i, :].double().cpu().numpy().T     # (i, k)
             else:
                 sl = X3[i].double().cpu().numpy().T           # (i, j)
-            ref = _row_mttkrp(sl, others)
-            bound = _row_mttkrp(np.abs(sl), others)
+            ref = _row_mttkrp(sl, n, H64)
+            bound = _row_mttkrp(np.abs(sl), n, H64)
             ratio = float(np.max(np.abs(M[i] - ref) / bound))
             worst = max(worst, ratio)
             print(f"  mode {n} row {i}: err / sum|x||k| = {ratio:.2e}", flush=True)
