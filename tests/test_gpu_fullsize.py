@@ -140,3 +140,29 @@ def test_fmri_shaped_bf16_sampled_mttkrp_rows(gpu_lib):
     print(f"  worst {worst:.2e}", flush=True)
     del X, X3
     torch.cuda.empty_cache()
+
+
+@pytest.mark.parametrize("dims,split", [((1024, 1024, 1024), 1), ((64, 64, 64, 64, 64), 2)])
+def test_large_workload_trajectory(gpu_lib, dims, split):
+    """Ten HALS iterations of the 1024^3 and 64^5 workloads at full size, as
+    bench.py runs them (plan, HIP graph, the default root split), against the
+    FP64 oracle's dimension-tree NNCP on the same stored values (the oracle's
+    tree equals its direct MTTKRP to 1e-11, pinned on the CPU)."""
+    import torch
+    from paper_1806_07985_amd import native
+    R, iters = 32, 10
+    print(f"case large trajectory dims={dims}", flush=True)
+    X = inputs.planted_device(dims, R, 0.01, seed=41, device="cuda")
+    H0 = [h.astype(np.float32) for h in inputs.init_factors(dims, R, seed=43)]
+    Hd = [native.factor_to_device(h) for h in H0]
+    plan = native.Plan(X, list(dims), R, Hd, split=split)
+    fit = plan.run(iters)
+    lam = plan.finish()
+    plan.close()
+    g = dict(H=[native.factor_to_host(h) for h in Hd], lam=lam, fit=fit)
+    Xh = X.cpu().numpy().astype(np.float64).reshape(dims, order="F")
+    del X
+    torch.cuda.empty_cache()
+    print("  oracle", flush=True)
+    o = O.nncp(Xh, [h.astype(np.float64) for h in H0], iters, mttkrp="tree", split=split)
+    _compare(g, o, 1e-5)
