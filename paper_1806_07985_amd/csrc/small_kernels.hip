@@ -192,19 +192,20 @@ __device__ __forceinline__ void mttv_trail_body(const MttvArgs& a, int bx, int r
       kv[e] = p;
     }
     __syncthreads();
-    // eight rows j of this phase in flight per step; rows past the chunk (or
-    // past I_a) read a valid element and are weighted by zero
+    // sixteen rows j of this phase in flight per step (each thread still adds
+    // its rows j = ph, ph + 4, ... in increasing order); rows past the chunk
+    // (or past I_a) read a valid element and are weighted by zero
     const int64_t ic = i < a.Ia ? i : 0;
     const TN* base = Tr + ic + a.Ia * j0;
-    for (int e = ph; e < cnt; e += 32) {
-      TN t[8];
+    for (int e = ph; e < cnt; e += 64) {
+      TN t[16];
 #pragma unroll
-      for (int u = 0; u < 8; ++u) {
+      for (int u = 0; u < 16; ++u) {
         const int ej = e + 4 * u;
         t[u] = base[a.Ia * (int64_t)(ej < cnt ? ej : e)];
       }
 #pragma unroll
-      for (int u = 0; u < 8; ++u) {
+      for (int u = 0; u < 16; ++u) {
         const int ej = e + 4 * u;
         if (ej < cnt) acc += (double)t[u] * kv[ej];
       }
@@ -241,8 +242,21 @@ __device__ __forceinline__ void mttv_lead_body(const MttvArgs& a, int bx) {
     const int64_t j = o - (int64_t)r * a.J;
     const TN* Tc = (const TN*)a.T + a.Ia * (j + a.J * (int64_t)r);
     if (a.krp.nm == 1) {
+      // eight products of the lane in flight, added in increasing i
       const float* Hc = a.krp.f[0] + a.Ia * (int64_t)r;
-      for (int64_t i = p; i < a.Ia; i += GS) acc += (double)Tc[i] * (double)Hc[i];
+      int64_t i = p;
+      for (; i + 7 * GS < a.Ia; i += 8 * GS) {
+        TN t[8];
+        float h[8];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) {
+          t[u] = Tc[i + u * GS];
+          h[u] = Hc[i + u * GS];
+        }
+#pragma unroll
+        for (int u = 0; u < 8; ++u) acc += (double)t[u] * (double)h[u];
+      }
+      for (; i < a.Ia; i += GS) acc += (double)Tc[i] * (double)Hc[i];
     } else {
       const bool narrow = a.Ia <= (int64_t)UINT32_MAX;  // 32-bit index arithmetic suffices
       for (int64_t i = p; i < a.Ia; i += GS) {
