@@ -207,7 +207,7 @@ constexpr int right_pf16(int nb) { return 3; }
 // TR*li .. TR*li+TR-1 of the 8 columns i1 = base + 8*lq + e; MFMA tile tt takes
 // row TR*li + tt of those 8 loads as its 8-k operand.
 // ----------------------------------------------------------------------------
-template <int DT, int NB, bool FAST, bool MT>
+template <int DT, int NB, bool FAST, bool MT, bool NTL>
 __device__ __forceinline__ void left_body(const PmArgs& a, int bx, int by) {
   constexpr int RP = NB * 16;
   constexpr int TR = left_tr16(NB);
@@ -275,7 +275,7 @@ __device__ __forceinline__ void left_body(const PmArgs& a, int bx, int by) {
     const unsigned short* base = X + Mtot * (colbase + 8 * lq);
     if (FAST || Mtot * (colbase + KS) <= vec_lim) {  // uniform
 #pragma unroll
-      for (int e = 0; e < 8; ++e) A[e] = __builtin_nontemporal_load((const vT*)(base + Mtot * e + mload));
+      for (int e = 0; e < 8; ++e) A[e] = tload<NTL>((const vT*)(base + Mtot * e + mload));
     } else {
 #pragma unroll
       for (int e = 0; e < 8; ++e) {
@@ -407,7 +407,7 @@ __device__ __forceinline__ void left_body(const PmArgs& a, int bx, int by) {
 // factor per column: the MFMA sums run over all of K (FP32) and are scaled once
 // at the end, with no separate accumulators (every wave owns its columns).
 // ----------------------------------------------------------------------------
-template <int DT, int NB, bool J1, bool FAST, bool MT>
+template <int DT, int NB, bool J1, bool FAST, bool MT, bool NTL>
 __device__ __forceinline__ void right_body(const PmArgs& a, int bx, int by) {
   constexpr int RP = NB * 16;
   constexpr int MC = J1 ? right_mc16_j1(NB) : right_mc16(NB);
@@ -492,7 +492,7 @@ __device__ __forceinline__ void right_body(const PmArgs& a, int bx, int by) {
 #pragma unroll
       for (int h = 0; h < 2; ++h)
 #pragma unroll
-        for (int g = 0; g < MC; ++g) A[g][h] = __builtin_nontemporal_load((const vT*)(colp[g] + lbase + 32 * h));
+        for (int g = 0; g < MC; ++g) A[g][h] = tload<NTL>((const vT*)(colp[g] + lbase + 32 * h));
     } else {
       const int ilimL = a.I1 - i1s;
 #pragma unroll
@@ -649,17 +649,18 @@ __device__ __forceinline__ void right_body(const PmArgs& a, int bx, int by) {
 }
 
 // FAST: the shape guarantees that every vector load of every step lies inside
-// the tensor (pm16_fast), so the loads need no per-step check.
-template <int DT, int SIDE, int NB, bool J1, bool FAST, bool MT>
+// the tensor (pm16_fast), so the loads need no per-step check. NTL: tensor loads
+// with the streaming hint (stand-alone launches; see pm_f32_body).
+template <int DT, int SIDE, int NB, bool J1, bool FAST, bool MT, bool NTL>
 __device__ __forceinline__ void body(const PmArgs& a, int bx, int by) {
-  if (SIDE == 0) left_body<DT, NB, FAST, MT>(a, bx, by);
-  else right_body<DT, NB, J1, FAST, MT>(a, bx, by);
+  if (SIDE == 0) left_body<DT, NB, FAST, MT, NTL>(a, bx, by);
+  else right_body<DT, NB, J1, FAST, MT, NTL>(a, bx, by);
 }
 
 // Stand-alone kernels: one work-group per (M tile, split).
 template <int DT, int SIDE, int NB, bool J1, bool FAST, bool MT>
 __global__ __launch_bounds__(NT, 1) void pm16_kernel_std(PmArgs a) {
-  body<DT, SIDE, NB, J1, FAST, MT>(a, blockIdx.x, blockIdx.y);
+  body<DT, SIDE, NB, J1, FAST, MT, true>(a, blockIdx.x, blockIdx.y);
 }
 // Persistent batched form: items grp[0] + b, grp[0] + b + gridDim.x, ... below
 // grp[0] + grp[1], each one (M tile, split) work-group of a recorded launch.
@@ -671,7 +672,7 @@ __global__ __launch_bounds__(NT, 1) void pm16_kernel_items(const BItem* __restri
   for (int i = blockIdx.x; i < n; i += gridDim.x) {
     const BItem it = items[off + i];
     const KOp& op = ops[it.op];
-    body<DT, SIDE, NB, J1, FAST, MT>(op.u.pm, it.bx, it.by);
+    body<DT, SIDE, NB, J1, FAST, MT, false>(op.u.pm, it.bx, it.by);
     __syncthreads();  // LDS is reused by the next item
   }
 }

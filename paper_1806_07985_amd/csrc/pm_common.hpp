@@ -19,6 +19,13 @@ using f32v = float __attribute__((ext_vector_type(L), aligned(4)));
 template <int L>
 using u16v = unsigned short __attribute__((ext_vector_type(L), aligned(2)));
 
+// A tensor load, with the nontemporal (streaming) hint when NT.
+template <bool NT, typename V>
+__device__ __forceinline__ V tload(const V* p) {
+  if constexpr (NT) return __builtin_nontemporal_load(p);
+  else return *p;
+}
+
 __device__ __forceinline__ f4 mfma4(float a, float b, f4 c) {
   return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
 }
